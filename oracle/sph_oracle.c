@@ -1,0 +1,545 @@
+/*
+ * Brute-force FP64 reference ("oracle") for the grad-h SPH density and force
+ * loops and the kick-drift-kick leapfrog step of the GANDALF paper
+ * (Hubber, Rosotti & Booth 2017, arXiv:1709.04488, section 2.1).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file.  It exists so that tests, the smoke check and the
+ * benchmark's CPU baseline can compare the HIP path against a plain, slow,
+ * obviously correct computation.  It shares no code, header, table or
+ * constant generator with the HIP path.
+ *
+ * Every sum runs over all particles j = 1..N in index order, with no cells,
+ * no trees and no reordering.  The only shortcut is exact: once a bracket
+ * [h_lo, h_hi] on the smoothing length is known, particles with
+ * r_ij >= 2 h_hi are dropped from the list used by the bisection, because the
+ * M4 kernel vanishes identically beyond 2h (compact support R h with R = 2,
+ * section 2); adding those zero terms would not change a single bit.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no FMA
+ * contraction, so every product and sum is rounded as written).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+#define ORC_ENOROOT -4   /* no smoothing length satisfies the h-rho relation */
+#define ORC_EBOX -5      /* periodic: the root needs 2h >= L/2 */
+#define ORC_ECAP -8      /* neighbour export: caller's capacity too small */
+
+typedef struct {
+    double eta;      /* h = eta (m/rho)^(1/3), eq. EQN:HRHO */
+    double gamma;    /* ideal-gas ratio of specific heats, P = (gamma-1) rho u */
+    double alpha;    /* alpha_AV, eq. EQN:MON97ARTVISC */
+    double beta;     /* beta_AV (= 2 alpha_AV in the paper) */
+    double ccfl;     /* C_CFL, eq. EQN:SPH_DT */
+    int32_t periodic;
+    int32_t pad_;
+    double lo[3], hi[3];
+} orc_params;
+
+/* ---------------------------------------------------------------------------
+ * M4 cubic spline (Monaghan & Lattanzio 1985), compact support 2h, 3D
+ * normalisation sigma = 1/pi.  The paper names this kernel with R = 2
+ * (section 2) and defers the formula to Hubber et al. 2011, appendix A.
+ *   f(q) = 1 - 3/2 q^2 + 3/4 q^3     0 <= q < 1
+ *        = 1/4 (2 - q)^3             1 <= q < 2
+ *        = 0                          q >= 2
+ *   W(r,h) = sigma h^-3 f(r/h)
+ * ------------------------------------------------------------------------- */
+static const double ORC_SIGMA = 0.31830988618379067154; /* 1/pi */
+
+double orc_f(double q)
+{
+    if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+    if (q < 2.0) { double t = 2.0 - q; return 0.25 * t * t * t; }
+    return 0.0;
+}
+
+/* df/dq */
+double orc_df(double q)
+{
+    if (q < 1.0) return -3.0 * q + 2.25 * q * q;
+    if (q < 2.0) { double t = 2.0 - q; return -0.75 * t * t; }
+    return 0.0;
+}
+
+double orc_W(double r, double h)
+{
+    return ORC_SIGMA / (h * h * h) * orc_f(r / h);
+}
+
+/* dW/dr: the kernel gradient is grad_i W(r_ij, h) = orc_dWdr(r, h) * rhat_ij */
+double orc_dWdr(double r, double h)
+{
+    return ORC_SIGMA / (h * h * h * h) * orc_df(r / h);
+}
+
+/* dW/dh = -sigma h^-4 (3 f(q) + q f'(q)) */
+double orc_dWdh(double r, double h)
+{
+    double q = r / h;
+    return -ORC_SIGMA / (h * h * h * h) * (3.0 * orc_f(q) + q * orc_df(q));
+}
+
+/* ---------------------------------------------------------------------------
+ * Pair separation r_i - r_j.  Periodic boxes use the minimum image, one axis
+ * at a time: shift by one box length when the separation exceeds half of it.
+ * This is equivalent to the paper's periodic ghost copies (section 4.3) as
+ * long as 2h < L/2, which the density solve enforces.
+ * ------------------------------------------------------------------------- */
+static inline double sep(double a, double b, int periodic, double L)
+{
+    double d = a - b;
+    if (periodic) {
+        if (d > 0.5 * L) d -= L;
+        else if (d < -0.5 * L) d += L;
+    }
+    return d;
+}
+
+static inline double pair_r2(const orc_params *p, const double *x, const double *y,
+                             const double *z, int64_t i, int64_t j,
+                             double *dx, double *dy, double *dz)
+{
+    double Lx = p->hi[0] - p->lo[0], Ly = p->hi[1] - p->lo[1], Lz = p->hi[2] - p->lo[2];
+    *dx = sep(x[i], x[j], p->periodic, Lx);
+    *dy = sep(y[i], y[j], p->periodic, Ly);
+    *dz = sep(z[i], z[j], p->periodic, Lz);
+    return (*dx * *dx + *dy * *dy) + *dz * *dz;
+}
+
+static double min_box_len(const orc_params *p)
+{
+    double L = p->hi[0] - p->lo[0];
+    for (int k = 1; k < 3; k++) if (p->hi[k] - p->lo[k] < L) L = p->hi[k] - p->lo[k];
+    return L;
+}
+
+/* ---------------------------------------------------------------------------
+ * Density and smoothing length (eqs. EQN:SPHRHO, EQN:HRHO, EQN:OMEGA).
+ *
+ * rho_i(h) = sum_j m_j W(r_ij, h) (self term included: the sum runs over
+ * j = 1..N).  The h-rho relation h^3 rho_i(h) = eta^3 m_i is solved as the
+ * root of   g(h) = sigma sum_j m_j f(r_ij/h) - eta^3 m_i,
+ * which equals h^3 rho_i(h) - eta^3 m_i.  g is non-decreasing in h (f is
+ * non-increasing in q) and g(0+) = (sigma - eta^3) m_i < 0, so the root is
+ * unique whenever it exists.  It is found by bracketing (doubling/halving
+ * the guess) and plain bisection down to a few ulp.  This is deliberately a
+ * different root finder from the Newton-Raphson iteration of the HIP path:
+ * the answer is defined by the relation, not by the iteration.
+ *
+ * Omega_i = 1 - (dh/drho) sum_j m_j dW/dh with dh/drho = -h/(3 rho) from
+ * EQN:HRHO, i.e. Omega_i = 1 + h rho'_i / (3 rho_i).
+ * ------------------------------------------------------------------------- */
+typedef struct { double r; double m; } orc_nb;
+
+static double g_full(const orc_params *p, int64_t n, const double *x, const double *y,
+                     const double *z, const double *m, int64_t i, double h)
+{
+    double s = 0.0, h2x4 = (2.0 * h) * (2.0 * h);
+    for (int64_t j = 0; j < n; j++) {
+        double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
+        if (r2 < h2x4) s += m[j] * orc_f(sqrt(r2) / h);
+    }
+    return ORC_SIGMA * s - p->eta * p->eta * p->eta * m[i];
+}
+
+static double g_list(const orc_params *p, const orc_nb *nb, int64_t k, double mi, double h)
+{
+    double s = 0.0;
+    for (int64_t a = 0; a < k; a++) s += nb[a].m * orc_f(nb[a].r / h);
+    return ORC_SIGMA * s - p->eta * p->eta * p->eta * mi;
+}
+
+/* Solve for one particle; fills h, rho, rho' (= sum m dW/dh), omega, nngb. */
+static int solve_one(const orc_params *p, int64_t n, const double *x, const double *y,
+                     const double *z, const double *m, int64_t i, double hguess,
+                     orc_nb *nb, double *h_out, double *rho_out, double *drho_out,
+                     double *omega_out, int32_t *nngb_out)
+{
+    if (!(hguess > 0.0) || !isfinite(hguess)) return ORC_EINVAL;
+    double lo, hi;
+    double gh = g_full(p, n, x, y, z, m, i, hguess);
+    if (gh < 0.0) {
+        lo = hguess; hi = 2.0 * hguess;
+        int it = 0;
+        while (g_full(p, n, x, y, z, m, i, hi) < 0.0) {
+            lo = hi; hi *= 2.0;
+            if (++it > 80) return ORC_ENOROOT;
+            if (p->periodic && 4.0 * lo >= min_box_len(p)) return ORC_EBOX;
+        }
+    } else {
+        hi = hguess; lo = 0.5 * hguess;
+        int it = 0;
+        while (g_full(p, n, x, y, z, m, i, lo) >= 0.0) {
+            hi = lo; lo *= 0.5;
+            if (++it > 1100) return ORC_ENOROOT;
+        }
+    }
+    /* Exact pruning: only j with r_ij < 2 hi can contribute for h <= hi. */
+    int64_t k = 0;
+    double lim = (2.0 * hi) * (2.0 * hi);
+    for (int64_t j = 0; j < n; j++) {
+        double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
+        if (r2 < lim) { nb[k].r = sqrt(r2); nb[k].m = m[j]; k++; }
+    }
+    for (int it = 0; it < 400; it++) {
+        double mid = lo + 0.5 * (hi - lo);
+        if (mid <= lo || mid >= hi) break;
+        if (hi - lo <= 4.0 * (nextafter(hi, INFINITY) - hi)) break;
+        if (g_list(p, nb, k, m[i], mid) < 0.0) lo = mid; else hi = mid;
+    }
+    double h = lo + 0.5 * (hi - lo);
+    if (p->periodic && 4.0 * h >= min_box_len(p)) return ORC_EBOX;
+
+    double rho = 0.0, drho = 0.0;
+    int32_t cnt = 0;
+    double h2x4 = (2.0 * h) * (2.0 * h);
+    for (int64_t j = 0; j < n; j++) {
+        double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
+        if (r2 < h2x4) {
+            double r = sqrt(r2);
+            rho += m[j] * orc_W(r, h);
+            drho += m[j] * orc_dWdh(r, h);
+            if (j != i) cnt++;
+        }
+    }
+    *h_out = h;
+    *rho_out = rho;
+    *drho_out = drho;
+    *omega_out = 1.0 + h * drho / (3.0 * rho);
+    *nngb_out = cnt;
+    return ORC_OK;
+}
+
+/*
+ * Density loop for the selected particles (sel == NULL: all n).  Output k
+ * belongs to particle sel[k].  h_guess is indexed by particle.
+ */
+int orc_density(const orc_params *p, int64_t n, const double *x, const double *y,
+                const double *z, const double *m, const double *h_guess,
+                int64_t nsel, const int64_t *sel, double *h, double *rho,
+                double *drhodh, double *omega, int32_t *nngb)
+{
+    if (n < 0 || nsel < 0) return ORC_EINVAL;
+    if (sel == NULL) nsel = n;
+    int status = ORC_OK;
+#pragma omp parallel
+    {
+        orc_nb *nb = (orc_nb *)malloc(sizeof(orc_nb) * (size_t)(n > 0 ? n : 1));
+        if (!nb) {
+#pragma omp atomic write
+            status = ORC_ENOMEM;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t k = 0; k < nsel; k++) {
+            if (!nb) continue;
+            int64_t i = sel ? sel[k] : k;
+            int rc = solve_one(p, n, x, y, z, m, i, h_guess[i], nb, &h[k], &rho[k],
+                               &drhodh[k], &omega[k], &nngb[k]);
+            if (rc != ORC_OK) {
+#pragma omp critical
+                { if (status == ORC_OK) status = rc; }
+            }
+        }
+        free(nb);
+    }
+    return status;
+}
+
+/* rho_i and rho'_i = sum_j m_j dW/dh at a given h_i (no h-rho solve), and
+ * the density-neighbour count.  Used to check the solve from outside. */
+int orc_rho_at(const orc_params *p, int64_t n, const double *x, const double *y,
+               const double *z, const double *m, int64_t nsel, const int64_t *sel,
+               const double *hsel, double *rho, double *drhodh, int32_t *nngb)
+{
+    if (n < 0 || nsel < 0) return ORC_EINVAL;
+    if (sel == NULL) nsel = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nsel; k++) {
+        int64_t i = sel ? sel[k] : k;
+        double h = hsel[k], r0 = 0.0, r1 = 0.0;
+        int32_t cnt = 0;
+        double h2x4 = (2.0 * h) * (2.0 * h);
+        for (int64_t j = 0; j < n; j++) {
+            double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
+            if (r2 < h2x4) {
+                double r = sqrt(r2);
+                r0 += m[j] * orc_W(r, h);
+                r1 += m[j] * orc_dWdh(r, h);
+                if (j != i) cnt++;
+            }
+        }
+        rho[k] = r0;
+        drhodh[k] = r1;
+        nngb[k] = cnt;
+    }
+    return ORC_OK;
+}
+
+/* Ideal-gas equation of state: P = (gamma-1) rho u (section 2.1.1) and the
+ * adiabatic sound speed c = sqrt(gamma P / rho). */
+void orc_eos(int64_t n, double gamma, const double *rho, const double *u,
+             double *P, double *c)
+{
+    for (int64_t i = 0; i < n; i++) {
+        P[i] = (gamma - 1.0) * rho[i] * u[i];
+        c[i] = sqrt(gamma * P[i] / rho[i]);
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Force loop (eqs. EQN:GRADHMOMEQN, EQN:GRADHENEQN, EQN:MON97ARTVISC,
+ * EQN:MON97ENERGYDISS with alpha_AC = 0) and the signal speed / CFL step
+ * (eq. EQN:SPH_DT and the v_sig definition beside it).
+ *
+ * For every j != i with r_ij < 2 max(h_i, h_j) (both W(h_i) and W(h_j)
+ * appear in the momentum equation):
+ *   G_i = dW/dr(r_ij, h_i) rhat_ij,  G_j = dW/dr(r_ij, h_j) rhat_ij
+ *   A_i = P_i / (Omega_i rho_i^2)
+ *   a_i    += -m_j (A_i G_i + A_j G_j)
+ *   du_i   +=  A_i m_j v_ij . G_i
+ *   w       =  v_ij . rhat_ij
+ *   vs      =  c_i + c_j - beta min(0, w)
+ *   vsig_i  =  max(vsig_i, vs)
+ *   if w < 0 (mu_ij = w):
+ *     rhobar = (rho_i + rho_j)/2,  Gbar = (G_i + G_j)/2
+ *     a_i  +=  (m_j / rhobar) alpha vs w Gbar
+ *     du_i += -(m_j / rhobar) alpha vs w^2/2 rhat_ij . Gbar
+ * Coincident pairs (r_ij = 0) add nothing to a or du and enter vsig with
+ * w = 0.  With no neighbour at all vsig_i = 2 c_i (the self-pair value).
+ * dt_i = C_CFL h_i / vsig_i.
+ * scale_a[i] = sum_j |pair term of a_i|, scale_u[i] = sum_j |pair term of du_i|
+ * (used to judge a_i ~ 0 results that arise by cancellation).
+ * ------------------------------------------------------------------------- */
+int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
+               const double *z, const double *vx, const double *vy, const double *vz,
+               const double *m, const double *u, const double *h, const double *rho,
+               const double *omega, int64_t nsel, const int64_t *sel,
+               double *ax, double *ay, double *az, double *dudt, double *vsig,
+               double *dt, double *scale_a, double *scale_u, int32_t *nforce)
+{
+    if (n < 0 || nsel < 0) return ORC_EINVAL;
+    if (sel == NULL) nsel = n;
+    const double gam = p->gamma;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nsel; k++) {
+        int64_t i = sel ? sel[k] : k;
+        double Pi = (gam - 1.0) * rho[i] * u[i];
+        double ci = sqrt(gam * Pi / rho[i]);
+        double Ai = Pi / (omega[i] * rho[i] * rho[i]);
+        double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+        double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, sa = 0.0, su = 0.0;
+        double vs_max = 2.0 * ci;
+        int have_ngb = 0;
+        int32_t cnt = 0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
+            double hj2x4 = (2.0 * h[j]) * (2.0 * h[j]);
+            if (!(r2 < hi2x4 || r2 < hj2x4)) continue;
+            cnt++;
+            double Pj = (gam - 1.0) * rho[j] * u[j];
+            double cj = sqrt(gam * Pj / rho[j]);
+            if (r2 == 0.0) {
+                double vs0 = ci + cj;
+                if (!have_ngb || vs0 > vs_max) vs_max = vs0;
+                have_ngb = 1;
+                continue;
+            }
+            double Aj = Pj / (omega[j] * rho[j] * rho[j]);
+            double r = sqrt(r2);
+            double ex = dx / r, ey = dy / r, ez = dz / r;
+            double gi = orc_dWdr(r, h[i]);
+            double gj = orc_dWdr(r, h[j]);
+            double vxij = vx[i] - vx[j], vyij = vy[i] - vy[j], vzij = vz[i] - vz[j];
+            double w = (vxij * ex + vyij * ey) + vzij * ez;
+            /* pressure term: vector coefficient along rhat */
+            double cvec = -m[j] * (Ai * gi + Aj * gj);
+            double cdu = Ai * m[j] * gi * w;
+            double vs = ci + cj - p->beta * (w < 0.0 ? w : 0.0);
+            if (!have_ngb || vs > vs_max) vs_max = vs;
+            have_ngb = 1;
+            if (w < 0.0) {
+                double rhobar = 0.5 * (rho[i] + rho[j]);
+                double gbar = 0.5 * (gi + gj);
+                cvec += (m[j] / rhobar) * p->alpha * vs * w * gbar;
+                cdu += -(m[j] / rhobar) * p->alpha * vs * 0.5 * w * w * gbar;
+            }
+            axi += cvec * ex;
+            ayi += cvec * ey;
+            azi += cvec * ez;
+            dui += cdu;
+            sa += fabs(cvec);
+            su += fabs(cdu);
+        }
+        ax[k] = axi;
+        ay[k] = ayi;
+        az[k] = azi;
+        dudt[k] = dui;
+        vsig[k] = vs_max;
+        dt[k] = p->ccfl * h[i] / vs_max;
+        scale_a[k] = sa;
+        scale_u[k] = su;
+        nforce[k] = cnt;
+    }
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * Neighbour lists, ascending j, for the selected particles.
+ *   mode 0: density neighbours  j != i with r_ij^2 < (2 h_i)^2
+ *   mode 1: force neighbours    j != i with r_ij^2 < (2 h_i)^2 or < (2 h_j)^2
+ * counts[k] is always filled.  If idx != NULL, the lists are written back to
+ * back (offsets = exclusive prefix sum of counts); ORC_ECAP if they exceed cap.
+ * ------------------------------------------------------------------------- */
+int orc_neighbours(const orc_params *p, int64_t n, const double *x, const double *y,
+                   const double *z, const double *h, int32_t mode, int64_t nsel,
+                   const int64_t *sel, int64_t *counts, int32_t *idx, int64_t cap)
+{
+    if (n < 0 || nsel < 0 || (mode != 0 && mode != 1)) return ORC_EINVAL;
+    if (sel == NULL) nsel = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nsel; k++) {
+        int64_t i = sel ? sel[k] : k;
+        double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
+            int in = r2 < hi2x4;
+            if (mode == 1) in = in || r2 < (2.0 * h[j]) * (2.0 * h[j]);
+            if (in) c++;
+        }
+        counts[k] = c;
+    }
+    if (!idx) return ORC_OK;
+    int64_t total = 0;
+    for (int64_t k = 0; k < nsel; k++) total += counts[k];
+    if (total > cap) return ORC_ECAP;
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nsel + 1));
+    if (!off) return ORC_ENOMEM;
+    off[0] = 0;
+    for (int64_t k = 0; k < nsel; k++) off[k + 1] = off[k] + counts[k];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nsel; k++) {
+        int64_t i = sel ? sel[k] : k;
+        double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+        int64_t c = off[k];
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
+            int in = r2 < hi2x4;
+            if (mode == 1) in = in || r2 < (2.0 * h[j]) * (2.0 * h[j]);
+            if (in) idx[c++] = (int32_t)j;
+        }
+    }
+    free(off);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * Kick-drift-kick leapfrog (eqs. EQN:LFKDK1, EQN:LFKDK2) with the SPH main
+ * loop order of section 5.1: integrate, neighbours, h + forces, time-step,
+ * closing kick.  The accelerations at step n+1 need velocities and internal
+ * energies at n+1, so they are evaluated at the predicted values
+ * v* = v^n + a^n dt and u* = u^n + du^n dt (the paper leaves this open).
+ * u is integrated with the same kick-drift-kick pattern as v.
+ *
+ * On entry h holds a guess; a, du, dt_i are computed first.  dt_fixed > 0
+ * fixes the step; otherwise each step uses min_i dt_i of the latest forces.
+ * energy[s] = sum 1/2 m v^2 + sum m u after s steps (s = 0..nsteps),
+ * dt_used[s] the step taken by step s+1.
+ * ------------------------------------------------------------------------- */
+static double total_energy(int64_t n, const double *m, const double *vx, const double *vy,
+                           const double *vz, const double *u)
+{
+    double e = 0.0;
+    for (int64_t i = 0; i < n; i++)
+        e += 0.5 * m[i] * ((vx[i] * vx[i] + vy[i] * vy[i]) + vz[i] * vz[i]) + m[i] * u[i];
+    return e;
+}
+
+static int eval_all(const orc_params *p, int64_t n, const double *x, const double *y,
+                    const double *z, const double *vx, const double *vy, const double *vz,
+                    const double *m, const double *u, double *h, double *rho,
+                    double *omega, double *ax, double *ay, double *az, double *du,
+                    double *dt, double *work)
+{
+    double *hn = work, *drho = work + n, *vsig = work + 2 * n, *sa = work + 3 * n,
+           *su = work + 4 * n;
+    int32_t *cnt = (int32_t *)(work + 5 * n);
+    int rc = orc_density(p, n, x, y, z, m, h, n, NULL, hn, rho, drho, omega, cnt);
+    if (rc != ORC_OK) return rc;
+    memcpy(h, hn, sizeof(double) * (size_t)n);
+    return orc_forces(p, n, x, y, z, vx, vy, vz, m, u, h, rho, omega, n, NULL, ax, ay, az,
+                      du, vsig, dt, sa, su, cnt);
+}
+
+int orc_kdk(const orc_params *p, int64_t n, double *x, double *y, double *z, double *vx,
+            double *vy, double *vz, const double *m, double *u, double *h,
+            int32_t nsteps, double dt_fixed, double *energy, double *dt_used)
+{
+    if (n <= 0 || nsteps < 0) return ORC_EINVAL;
+    size_t N = (size_t)n;
+    double *buf = (double *)malloc(sizeof(double) * N * 21);
+    if (!buf) return ORC_ENOMEM;
+    double *rho = buf, *omega = buf + N, *ax = buf + 2 * N, *ay = buf + 3 * N,
+           *az = buf + 4 * N, *du = buf + 5 * N, *dt = buf + 6 * N, *vxh = buf + 7 * N,
+           *vyh = buf + 8 * N, *vzh = buf + 9 * N, *uh = buf + 10 * N, *vxp = buf + 11 * N,
+           *vyp = buf + 12 * N, *vzp = buf + 13 * N, *up = buf + 14 * N, *work = buf + 15 * N;
+    /* work: 5N doubles + N int32 (eval_all scratch) */
+    int rc = eval_all(p, n, x, y, z, vx, vy, vz, m, u, h, rho, omega, ax, ay, az, du, dt, work);
+    if (rc != ORC_OK) { free(buf); return rc; }
+    if (energy) energy[0] = total_energy(n, m, vx, vy, vz, u);
+    double L[3];
+    for (int k = 0; k < 3; k++) L[k] = p->hi[k] - p->lo[k];
+    for (int32_t s = 0; s < nsteps; s++) {
+        double d = dt_fixed;
+        if (!(d > 0.0)) {
+            d = dt[0];
+            for (int64_t i = 1; i < n; i++) if (dt[i] < d) d = dt[i];
+        }
+        if (dt_used) dt_used[s] = d;
+        for (int64_t i = 0; i < n; i++) {
+            vxh[i] = vx[i] + 0.5 * d * ax[i];
+            vyh[i] = vy[i] + 0.5 * d * ay[i];
+            vzh[i] = vz[i] + 0.5 * d * az[i];
+            uh[i] = u[i] + 0.5 * d * du[i];
+            double *pos[3] = {&x[i], &y[i], &z[i]};
+            double vel[3] = {vxh[i], vyh[i], vzh[i]};
+            for (int k = 0; k < 3; k++) {
+                double q = *pos[k] + d * vel[k];
+                if (p->periodic) {
+                    if (q >= p->hi[k]) q -= L[k];
+                    else if (q < p->lo[k]) q += L[k];
+                }
+                *pos[k] = q;
+            }
+            vxp[i] = vxh[i] + 0.5 * d * ax[i];
+            vyp[i] = vyh[i] + 0.5 * d * ay[i];
+            vzp[i] = vzh[i] + 0.5 * d * az[i];
+            up[i] = uh[i] + 0.5 * d * du[i];
+        }
+        rc = eval_all(p, n, x, y, z, vxp, vyp, vzp, m, up, h, rho, omega, ax, ay, az, du, dt,
+                      work);
+        if (rc != ORC_OK) { free(buf); return rc; }
+        for (int64_t i = 0; i < n; i++) {
+            vx[i] = vxh[i] + 0.5 * d * ax[i];
+            vy[i] = vyh[i] + 0.5 * d * ay[i];
+            vz[i] = vzh[i] + 0.5 * d * az[i];
+            u[i] = uh[i] + 0.5 * d * du[i];
+        }
+        if (energy) energy[s + 1] = total_energy(n, m, vx, vy, vz, u);
+    }
+    free(buf);
+    return ORC_OK;
+}
+
+int orc_num_threads(void) { return omp_get_max_threads(); }
