@@ -1,0 +1,261 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) grad-h SPH hot path.
+ *
+ * The library evaluates, for one set of N particles in 3D, the steps of the
+ * SPH main loop described in the GANDALF paper (Hubber, Rosotti & Booth 2017,
+ * arXiv:1709.04488, sections 2.1 and 5.1):
+ *
+ *   neighbour search  -- a Morton-key radix sort and a leaf/box tree over the
+ *                        sorted particles (the paper's KD-tree with N_LEAF
+ *                        particles per leaf and smoothing-sphere extent boxes,
+ *                        section 4.2, rebuilt for the GPU)
+ *   density loop      -- rho_i = sum_j m_j W(r_ij, h_i) (eq. EQN:SPHRHO) with
+ *                        h_i = eta (m_i/rho_i)^(1/3) (eq. EQN:HRHO) solved by
+ *                        Newton-Raphson, Omega_i (eq. EQN:OMEGA), the ideal-gas
+ *                        pressure P = (gamma-1) rho u and sound speed
+ *   force loop        -- grad-h momentum and energy equations (eqs.
+ *                        EQN:GRADHMOMEQN, EQN:GRADHENEQN) with Monaghan
+ *                        artificial viscosity (eqs. EQN:MON97ARTVISC,
+ *                        EQN:MON97ENERGYDISS, alpha_AC = 0), the signal speed
+ *                        and the CFL time-step (eq. EQN:SPH_DT)
+ *   time integration  -- kick-drift-kick leapfrog (eqs. EQN:LFKDK1/EQN:LFKDK2)
+ *
+ * Kernel: M4 cubic spline, support 2h (section 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   Particle arrays are structure-of-arrays, one value per particle,
+ *           in the caller's index order, and live in DEVICE memory on the
+ *           device that was current when the context was created.  The caller
+ *           owns them; the library never frees or keeps them past the call
+ *           except where stated.  The library owns its context and all scratch
+ *           memory (sort buffers, sorted copies, tree, status word), allocated
+ *           at most up to the HBM budget given to sph_create.
+ * Streams.  Every call enqueues work on the context's HIP stream and returns
+ *           without waiting, unless stated otherwise.  Results are valid after
+ *           the stream has drained (sph_sync, or any later stream-ordered use).
+ * Errors.   Argument errors are returned at once (SPH_EINVAL).  Conditions the
+ *           device detects (non-finite values, an h solve that did not
+ *           converge, a smoothing length too large for the periodic box) are
+ *           recorded in a sticky status word and returned by sph_sync.  The
+ *           library never aborts and throws nothing across the ABI.
+ *           sph_last_error gives a readable description of the last error.
+ * Threads.  A context is not thread-safe; distinct contexts are independent.
+ * Units.    Any consistent set; the parameters are dimensionless.
+ */
+#ifndef SPH_MI355X_H
+#define SPH_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_EINVAL = -1,        /* bad argument (NULL array, n < 0, bad parameter) */
+    SPH_ENOMEM = -2,        /* device allocation failed */
+    SPH_EDEVICE = -3,       /* a HIP runtime call failed */
+    SPH_ENOTCONVERGED = -4, /* some h_i did not reach h_rtol in h_max_iter steps */
+    SPH_ESTENCIL = -5,      /* periodic box: some 2 h_i >= L/2 (minimum image ambiguous) */
+    SPH_ENONFINITE = -6,    /* a NaN or Inf input or result */
+    SPH_EBUDGET = -7,       /* the working set would exceed the HBM budget */
+    SPH_ECAP = -8,          /* an output capacity given by the caller is too small */
+    SPH_ESTATE = -9         /* call out of order (e.g. sph_step before upload) */
+} sph_status;
+
+enum { SPH_FP64 = 0, SPH_FP32_PAIR = 1 };
+
+/*
+ * Method parameters.  Defaults (sph_default_params): eta = 1.2 (section
+ * 2.1.1), gamma = 5/3, alpha_av = 1, beta_av = 2 alpha_av (section 2.1.1),
+ * c_cfl = 0.2 (section 2.1.4), h_rtol = 1e-12, h_max_iter = 50, periodic
+ * unit box, FP64, leaf_size 16.
+ *
+ * precision = SPH_FP64: every pair term in double precision.
+ * precision = SPH_FP32_PAIR: pair separations are formed in single precision
+ *   from offsets to each leaf's centre, so their error does not grow with the
+ *   distance from the origin; pair arithmetic is single precision; positions,
+ *   per-particle accumulators (density sums, h residual, accelerations,
+ *   du/dt) and time integration stay double precision.  The single-precision
+ *   pair terms leave ~1e-7 relative noise in the h residual, so in this mode
+ *   the Newton-Raphson stop tolerance is max(h_rtol, 2e-6).
+ */
+typedef struct {
+    double eta;        /* h = eta (m/rho)^(1/3) */
+    double gamma;      /* ratio of specific heats, > 1 */
+    double alpha_av;   /* artificial viscosity strength (0 disables it) */
+    double beta_av;    /* signal-speed coefficient */
+    double c_cfl;      /* CFL multiplier */
+    double h_rtol;     /* Newton-Raphson stop: |h_new - h| <= h_rtol h */
+    int32_t h_max_iter;/* Newton-Raphson iteration cap (>= 1) */
+    int32_t periodic;  /* 1: periodic box [box_lo, box_hi); 0: isolated */
+    double box_lo[3];
+    double box_hi[3];
+    int32_t precision; /* SPH_FP64 or SPH_FP32_PAIR */
+    int32_t leaf_size; /* particles per tree leaf: 8, 16 or 32 */
+} sph_params;
+
+/*
+ * One particle set, device pointers, caller index order.  Which arrays each
+ * call reads (R) or writes (W):
+ *
+ *                   x,y,z  m   h    u  vx,vy,vz  rho,omega  pressure,cs  ax..dt  nngb nforce
+ *   sph_build_cells   R        R
+ *   sph_density       R    R   RW                W          W(opt)             W(opt)
+ *   sph_forces        R    R   R    R  R         R          W(opt)       W            W(opt)
+ *   sph_upload_state  R    R   R    R  R
+ *   sph_download_state W       W    W  W         W          W(opt)       W(opt)
+ *
+ * h on entry to sph_density is the initial guess of each smoothing length
+ * (> 0); on return it holds the converged value.  dt is the per-particle
+ * CFL step C_CFL h_i / v_sig,i.  (opt) arrays may be NULL.
+ */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z;
+    const double *vx, *vy, *vz;
+    const double *m;
+    const double *u;      /* specific internal energy */
+    double *h;            /* smoothing length */
+    double *rho, *omega;  /* density, grad-h correction */
+    double *pressure, *cs;
+    double *ax, *ay, *az; /* dv/dt */
+    double *dudt;         /* du/dt */
+    double *vsig;         /* max signal speed over force neighbours */
+    double *dt;           /* per-particle CFL step */
+    int32_t *nngb;        /* density neighbours j != i with r_ij < 2 h_i */
+    int32_t *nforce;      /* force neighbours j != i with r_ij < 2 max(h_i, h_j) */
+} sph_particles;
+
+/* Diagnostics of the resident state, valid after sph_sync. */
+typedef struct {
+    double time;          /* sum of the steps taken */
+    double dt_last;       /* step taken by the last sph_step */
+    double dt_next;       /* min_i dt_i of the latest forces (next Courant step) */
+    double kinetic;       /* sum 1/2 m v^2 */
+    double thermal;       /* sum m u */
+    double momentum[3];   /* sum m v */
+    int64_t steps;
+    int64_t n_dens_pairs; /* density interactions of the last evaluation */
+    int64_t n_force_pairs;/* force interactions of the last evaluation */
+    int32_t nr_iter_max;  /* Newton-Raphson iterations of the last density pass */
+    int32_t pad_;
+} sph_state_stats;
+
+typedef struct sph_ctx sph_ctx;
+
+/* Default parameters (see sph_params). */
+void sph_default_params(sph_params *p);
+
+/*
+ * Create a context bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  hbm_budget_bytes caps the
+ * library's own device allocations (0 = no cap).  *ctx is NULL on error.
+ */
+sph_status sph_create(sph_ctx **ctx, const sph_params *p, void *hip_stream,
+                      size_t hbm_budget_bytes);
+
+/* Free everything the context owns.  Waits for its stream.  NULL is a no-op. */
+sph_status sph_destroy(sph_ctx *ctx);
+
+/* Rebind the context to another stream (subsequent calls enqueue there). */
+sph_status sph_set_stream(sph_ctx *ctx, void *hip_stream);
+
+/* Replace the method parameters (same validation as sph_create). */
+sph_status sph_set_params(sph_ctx *ctx, const sph_params *p);
+
+/*
+ * Neighbour-search structure for ps (reads x, y, z, h): bounding box, Morton
+ * keys, device radix sort, sorted copies of the particle data, leaves of
+ * leaf_size consecutive particles with their bounding boxes and largest h, and
+ * the tree of boxes above them.  sph_density builds it itself; this entry
+ * point exists to time or test the build on its own.
+ */
+sph_status sph_build_cells(sph_ctx *ctx, const sph_particles *ps);
+
+/*
+ * Density loop and h solve (eqs. EQN:SPHRHO, EQN:HRHO, EQN:OMEGA): for each i
+ * the h_i with h_i^3 rho_i(h_i) = eta^3 m_i, found by safeguarded
+ * Newton-Raphson from the guess in ps->h to |dh| <= h_rtol h (the self term
+ * j = i is part of rho_i).  Writes h, rho, omega, and if non-NULL pressure
+ * (gamma-1) rho u (reads u then), cs = sqrt(gamma P / rho), nngb.
+ * Rebuilds the neighbour structure for the current positions first.
+ */
+sph_status sph_density(sph_ctx *ctx, sph_particles *ps);
+
+/*
+ * Force loop (eqs. EQN:GRADHMOMEQN, EQN:GRADHENEQN, EQN:MON97ARTVISC,
+ * EQN:MON97ENERGYDISS with alpha_AC = 0; signal speed and eq. EQN:SPH_DT).
+ * Reads x, y, z, v, m, u, h, rho, omega; writes ax, ay, az, dudt, vsig, dt
+ * and, if non-NULL, nforce.  Pairs with r_ij = 0 add nothing to a or du/dt.
+ * Reuses the neighbour structure of the last sph_density / sph_build_cells
+ * call on the same arrays (same x, y, z pointers and n); otherwise rebuilds.
+ */
+sph_status sph_forces(sph_ctx *ctx, sph_particles *ps);
+
+/*
+ * Copy a particle set (x, y, z, v, m, u, h) into context-owned device memory
+ * for time integration with sph_step.  Evaluates density and forces of the
+ * initial state.  Keeps nothing that points into ps.
+ */
+sph_status sph_upload_state(sph_ctx *ctx, const sph_particles *ps);
+
+/*
+ * One kick-drift-kick leapfrog step of the resident state (eqs. EQN:LFKDK1,
+ * EQN:LFKDK2; loop order of section 5.1): half kick of v and u, drift of x
+ * (wrapped into a periodic box), neighbour search, density, forces at the
+ * predicted v* = v + a dt and u* = u + du dt, closing half kick, new CFL
+ * step min_i dt_i.  dt > 0 fixes the step; dt <= 0 takes the CFL step of the
+ * latest forces (read on the device; no host round trip).  If dt_used is not
+ * NULL it receives the step actually taken when sph_sync next returns.
+ */
+sph_status sph_step(sph_ctx *ctx, double dt, double *dt_used);
+
+/* Write the resident state back in the caller's original index order:
+ * x, y, z, v, u, h and, where non-NULL, rho, omega, pressure, cs, a, dudt,
+ * vsig, dt, nngb, nforce (m is constant and not written). */
+sph_status sph_download_state(sph_ctx *ctx, sph_particles *ps);
+
+/* Diagnostics of the resident state (waits for the stream). */
+sph_status sph_state_info(sph_ctx *ctx, sph_state_stats *info);
+
+/*
+ * Neighbour lists, for tests and export, at the given h (no h solve):
+ *   mode 0: j != i with r_ij^2 < (2 h_i)^2        (density neighbours)
+ *   mode 1: j != i with r_ij^2 < (2 h_i)^2 or r_ij^2 < (2 h_j)^2  (force)
+ * r_ij^2 is formed exactly as (dx*dx + dy*dy) + dz*dz with the minimum image
+ * per axis and no fused multiply-add.  offsets: device int64[n+1], idx:
+ * device int32[cap]; the lists of particle i are idx[offsets[i] ..
+ * offsets[i+1]) in ascending order of j.  SPH_ECAP if they exceed cap
+ * (offsets is still complete).  Waits for the stream.
+ */
+sph_status sph_neighbours(sph_ctx *ctx, const sph_particles *ps, int32_t mode,
+                          int64_t *offsets, int32_t *idx, int64_t cap);
+
+/* Wait for the context's stream; return and clear the sticky device status. */
+sph_status sph_sync(sph_ctx *ctx);
+
+/* Readable description of the last error on this context ("" if none). */
+const char *sph_last_error(const sph_ctx *ctx);
+
+/* Bytes of device memory the context currently holds. */
+size_t sph_device_bytes(const sph_ctx *ctx);
+
+/*
+ * Timing of individual kernels with HIP events on the context's stream.
+ * When enabled, the density-loop and force-loop kernels are bracketed by
+ * events; sph_kernel_times (waits for the stream) returns the summed
+ * milliseconds and launch counts since the last reset.  which: 0 density
+ * loop, 1 force loop, 2 neighbour build (keys, sort, gather, tree).
+ */
+sph_status sph_enable_kernel_timing(sph_ctx *ctx, int32_t enable);
+sph_status sph_kernel_times(sph_ctx *ctx, int32_t which, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_MI355X_H */

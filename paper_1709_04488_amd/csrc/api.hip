@@ -1,0 +1,647 @@
+// C ABI of libsph: context lifetime, memory plan, argument checks and the
+// order in which each entry point enqueues the kernels.
+#include "sph_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+namespace sph {
+
+sph_status fail(sph_ctx *c, sph_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+sph_status hip_check(sph_ctx *c, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return SPH_OK;
+    return fail(c, SPH_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+constexpr int kRsTile = 4096;
+
+// per-particle device bytes of everything sized by the capacity
+int64_t bytes_per_particle(const sph_params &p)
+{
+    int64_t b = 0;
+    b += 2 * 8 + 2 * 4;        // sort keys / values, ping-pong
+    b += 20 * 8 + 2 * 4 + 4;   // s: doubles, nngb/nforce, id
+    b += 4 * 8;                // s: predictor arrays
+    b += 3 * 4;                // s: fp32 offsets
+    b += 13 * 8 + 4;           // t: re-sort buffers
+    (void)p;
+    return b;
+}
+
+sph_status check_params(sph_ctx *c, const sph_params *p)
+{
+    if (!p) return fail(c, SPH_EINVAL, "params is NULL");
+    if (!(p->eta > 0.0) || !(p->gamma > 1.0) || !(p->alpha_av >= 0.0) || !(p->beta_av >= 0.0) ||
+        !(p->c_cfl > 0.0) || !(p->h_rtol > 0.0) || p->h_max_iter < 1)
+        return fail(c, SPH_EINVAL, "invalid method parameter");
+    if (p->precision != SPH_FP64 && p->precision != SPH_FP32_PAIR)
+        return fail(c, SPH_EINVAL, "precision must be SPH_FP64 or SPH_FP32_PAIR");
+    if (p->leaf_size != 8 && p->leaf_size != 16 && p->leaf_size != 32)
+        return fail(c, SPH_EINVAL, "leaf_size must be 8, 16 or 32");
+    if (p->periodic)
+        for (int a = 0; a < 3; a++)
+            if (!(p->box_hi[a] > p->box_lo[a]) || !std::isfinite(p->box_hi[a] - p->box_lo[a]))
+                return fail(c, SPH_EINVAL, "periodic box must have box_hi > box_lo");
+    return SPH_OK;
+}
+
+void set_box(sph_ctx *c)
+{
+    Box &b = c->box;
+    b.periodic = c->p.periodic ? 1 : 0;
+    for (int a = 0; a < 3; a++) {
+        b.lo[a] = c->p.box_lo[a];
+        b.len[a] = c->p.box_hi[a] - c->p.box_lo[a];
+        b.half[a] = 0.5 * b.len[a];
+    }
+}
+
+void free_all(sph_ctx *c)
+{
+    for (void *ptr : c->allocs) (void)hipFree(ptr);
+    c->allocs.clear();
+    if (c->nodes) (void)hipFree(c->nodes);
+    if (c->hist) (void)hipFree(c->hist);
+    c->nodes = nullptr;
+    c->hist = nullptr;
+    c->ncap = 0;
+    c->node_cap = 0;
+    c->hist_cap = 0;
+    c->s = Sorted{};
+    c->t = Sorted{};
+    c->keys[0] = c->keys[1] = nullptr;
+    c->vals[0] = c->vals[1] = nullptr;
+    c->perm = nullptr;
+    c->bytes = 4096;   // fixed buffers (status, scalars, box, partials)
+    c->built = false;
+    c->resident = false;
+}
+
+template <class T>
+sph_status alloc(sph_ctx *c, T **ptr, int64_t count)
+{
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)std::max<int64_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, SPH_ENOMEM, "hipMalloc failed");
+    }
+    c->allocs.push_back(p);
+    c->bytes += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    *ptr = (T *)p;
+    return SPH_OK;
+}
+
+int64_t node_count(int64_t n, int G)
+{
+    int64_t cnt = ceil_div(std::max<int64_t>(n, 1), G), tot = 0;
+    while (true) {
+        tot += cnt;
+        if (cnt == 1) break;
+        cnt = ceil_div(cnt, 8);
+    }
+    return tot;
+}
+
+} // namespace
+
+sph_status ensure_capacity(sph_ctx *c, int64_t n)
+{
+    if (n > (int64_t)0xFFFFFFF0ll) return fail(c, SPH_EINVAL, "n exceeds 2^32 - 16");
+    int64_t nodes_needed = node_count(n, c->p.leaf_size);
+    if (n <= c->ncap && nodes_needed <= c->node_cap) return SPH_OK;
+    int64_t cap = std::max<int64_t>(n, 1024);
+    int64_t need = bytes_per_particle(c->p) * cap + node_count(cap, 8) * (int64_t)sizeof(Node) +
+                   256 * 4 * ceil_div(cap, kRsTile) + 4096;
+    if (c->budget && (size_t)need > c->budget)
+        return fail(c, SPH_EBUDGET, "working set of " + std::to_string(need) +
+                                        " bytes exceeds the HBM budget of " +
+                                        std::to_string(c->budget));
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
+    bool was_resident = c->resident;
+    free_all(c);
+    if (was_resident) return fail(c, SPH_ESTATE, "resident state lost on reallocation");
+    sph_status s = SPH_OK;
+    Sorted &S = c->s, &T = c->t;
+#define A_(ptr, cnt) if (s == SPH_OK) s = alloc(c, &(ptr), (cnt))
+    A_(c->keys[0], cap); A_(c->keys[1], cap);
+    A_(c->vals[0], cap); A_(c->vals[1], cap);
+    double **sd[] = {&S.x, &S.y, &S.z, &S.vx, &S.vy, &S.vz, &S.m, &S.u, &S.h, &S.rho, &S.omega,
+                     &S.A, &S.c, &S.hinv, &S.ax, &S.ay, &S.az, &S.du, &S.vsig, &S.dt,
+                     &S.vpx, &S.vpy, &S.vpz, &S.up,
+                     &T.x, &T.y, &T.z, &T.vx, &T.vy, &T.vz, &T.m, &T.u, &T.h,
+                     &T.vpx, &T.vpy, &T.vpz, &T.up};
+    for (double **pp : sd) A_(*pp, cap);
+    A_(S.nngb, cap); A_(S.nforce, cap);
+    A_(S.id, cap); A_(T.id, cap);
+    A_(S.fx, cap); A_(S.fy, cap); A_(S.fz, cap);
+#undef A_
+    if (s != SPH_OK) { free_all(c); return s; }
+    int64_t ncap_nodes = node_count(cap, 8);
+    hipError_t e1 = hipMalloc((void **)&c->nodes, sizeof(Node) * (size_t)ncap_nodes);
+    int64_t hcap = 256 * ceil_div(cap, kRsTile);
+    hipError_t e2 = hipMalloc((void **)&c->hist, sizeof(uint32_t) * (size_t)hcap);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        free_all(c);
+        return fail(c, SPH_ENOMEM, "hipMalloc failed (tree)");
+    }
+    c->bytes += sizeof(Node) * (size_t)ncap_nodes + sizeof(uint32_t) * (size_t)hcap;
+    c->node_cap = ncap_nodes;
+    c->hist_cap = hcap;
+    c->ncap = cap;
+    return SPH_OK;
+}
+
+void timer_begin(sph_ctx *c, int which, hipEvent_t *b, hipEvent_t *e)
+{
+    *b = *e = nullptr;
+    if (!c->timer.on) return;
+    auto &pool = c->timer.pool;
+    if (pool.empty()) {
+        hipEvent_t x, y;
+        if (hipEventCreate(&x) != hipSuccess) return;
+        if (hipEventCreate(&y) != hipSuccess) { (void)hipEventDestroy(x); return; }
+        pool.push_back({x, y});
+    }
+    auto pr = pool.back();
+    pool.pop_back();
+    *b = pr.first;
+    *e = pr.second;
+    (void)which;
+    (void)hipEventRecord(*b, c->stream);
+}
+
+void timer_end(sph_ctx *c, int which, hipEvent_t b, hipEvent_t e)
+{
+    if (!b) return;
+    (void)hipEventRecord(e, c->stream);
+    c->timer.pending[which].push_back({b, e});
+}
+
+} // namespace sph
+
+using namespace sph;
+
+namespace {
+
+sph_status check_ps(sph_ctx *c, const sph_particles *ps)
+{
+    if (!c) return SPH_EINVAL;
+    if (!ps) return fail(c, SPH_EINVAL, "particles is NULL");
+    if (ps->n < 0) return fail(c, SPH_EINVAL, "n < 0");
+    return SPH_OK;
+}
+
+#define REQ(ptr, name)                                                          \
+    do {                                                                        \
+        if (ps->n > 0 && !(ptr)) return fail(c, SPH_EINVAL, name " is NULL");  \
+    } while (0)
+
+#define TRY(expr)                        \
+    do {                                 \
+        sph_status st_ = (expr);         \
+        if (st_ != SPH_OK) return st_;   \
+    } while (0)
+
+sph_status build_from(sph_ctx *c, const sph_particles *ps, bool with_m)
+{
+    const int64_t n = ps->n;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_begin(c, 2, &e0, &e1);
+    TRY(build_order(c, n, ps->x, ps->y, ps->z));
+    GatherList g{};
+    const void *src[] = {ps->x, ps->y, ps->z, ps->h, ps->m};
+    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.h, c->s.m};
+    g.count = with_m ? 5 : 4;
+    for (int a = 0; a < g.count; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
+    TRY(gather(c, n, g, false));
+    TRY(build_tree(c, n));
+    timer_end(c, 2, e0, e1);
+    c->built = true;
+    c->built_x = ps->x;
+    c->built_n = n;
+    return SPH_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+void sph_default_params(sph_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->eta = 1.2;
+    p->gamma = 5.0 / 3.0;
+    p->alpha_av = 1.0;
+    p->beta_av = 2.0;
+    p->c_cfl = 0.2;
+    p->h_rtol = 1e-12;
+    p->h_max_iter = 50;
+    p->periodic = 1;
+    for (int a = 0; a < 3; a++) { p->box_lo[a] = 0.0; p->box_hi[a] = 1.0; }
+    p->precision = SPH_FP64;
+    p->leaf_size = 16;
+}
+
+sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size_t budget)
+{
+    if (!out) return SPH_EINVAL;
+    *out = nullptr;
+    sph_ctx *c = new (std::nothrow) sph_ctx();
+    if (!c) return SPH_ENOMEM;
+    sph_status s = check_params(c, p);
+    if (s != SPH_OK) { delete c; return s; }
+    c->p = *p;
+    set_box(c);
+    c->stream = (hipStream_t)hip_stream;
+    c->budget = budget;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return SPH_EDEVICE; }
+    bool ok = hipMalloc((void **)&c->d_status, sizeof(int32_t) * kStatusWords) == hipSuccess &&
+              hipMalloc((void **)&c->d_scal, sizeof(double) * 16) == hipSuccess &&
+              hipMalloc((void **)&c->d_counts, sizeof(int64_t) * 4) == hipSuccess &&
+              hipMalloc((void **)&c->d_box, sizeof(double) * 8) == hipSuccess &&
+              hipMalloc((void **)&c->d_part, sizeof(double) * 1024 * 8) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_status, sizeof(int32_t) * kStatusWords) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_scal, sizeof(double) * 16) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        sph_destroy(c);
+        return SPH_ENOMEM;
+    }
+    c->bytes = 4096;
+    ok = hipMemset(c->d_status, 0, sizeof(int32_t) * kStatusWords) == hipSuccess &&
+         hipMemset(c->d_scal, 0, sizeof(double) * 16) == hipSuccess &&
+         hipMemset(c->d_counts, 0, sizeof(int64_t) * 4) == hipSuccess;
+    if (!ok) { sph_destroy(c); return SPH_EDEVICE; }
+    *out = c;
+    return SPH_OK;
+}
+
+sph_status sph_destroy(sph_ctx *c)
+{
+    if (!c) return SPH_OK;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    for (int w = 0; w < 3; w++)
+        for (auto &pr : c->timer.pending[w]) c->timer.pool.push_back(pr);
+    for (auto &pr : c->timer.pool) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    if (c->d_status) (void)hipFree(c->d_status);
+    if (c->d_scal) (void)hipFree(c->d_scal);
+    if (c->d_counts) (void)hipFree(c->d_counts);
+    if (c->d_box) (void)hipFree(c->d_box);
+    if (c->d_part) (void)hipFree(c->d_part);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    delete c;
+    return SPH_OK;
+}
+
+sph_status sph_set_stream(sph_ctx *c, void *hip_stream)
+{
+    if (!c) return SPH_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return SPH_OK;
+}
+
+sph_status sph_set_params(sph_ctx *c, const sph_params *p)
+{
+    if (!c) return SPH_EINVAL;
+    TRY(check_params(c, p));
+    bool regrow = p->leaf_size < c->p.leaf_size;
+    c->p = *p;
+    set_box(c);
+    c->built = false;
+    if (regrow) c->node_cap = 0;   // force a re-plan of the tree storage on next use
+    return SPH_OK;
+}
+
+sph_status sph_build_cells(sph_ctx *c, const sph_particles *ps)
+{
+    TRY(check_ps(c, ps));
+    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z"); REQ(ps->h, "h");
+    c->resident = false;
+    TRY(ensure_capacity(c, ps->n));
+    c->n = ps->n;
+    return build_from(c, ps, ps->m != nullptr);
+}
+
+sph_status sph_density(sph_ctx *c, sph_particles *ps)
+{
+    TRY(check_ps(c, ps));
+    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z"); REQ(ps->m, "m"); REQ(ps->h, "h");
+    REQ(ps->rho, "rho"); REQ(ps->omega, "omega");
+    if ((ps->pressure || ps->cs)) REQ(ps->u, "u");
+    c->resident = false;
+    const int64_t n = ps->n;
+    TRY(ensure_capacity(c, n));
+    c->n = n;
+    if (n == 0) return SPH_OK;
+    TRY(build_from(c, ps, true));
+    TRY(run_density(c, n));
+    ScatterList sl{};
+    const void *src[] = {c->s.h, c->s.rho, c->s.omega, c->s.nngb};
+    void *dst[] = {ps->h, ps->rho, ps->omega, ps->nngb};
+    int kinds[] = {0, 0, 0, 1};
+    for (int a = 0; a < 4; a++) {
+        if (!dst[a]) continue;
+        sl.kind[sl.count] = kinds[a];
+        sl.src[sl.count] = src[a];
+        sl.dst[sl.count] = dst[a];
+        sl.count++;
+    }
+    TRY(scatter(c, n, sl, c->perm));
+    TRY(eos_scatter(c, n, c->perm, ps->u, ps->pressure, ps->cs));
+    return SPH_OK;
+}
+
+sph_status sph_forces(sph_ctx *c, sph_particles *ps)
+{
+    TRY(check_ps(c, ps));
+    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z");
+    REQ(ps->vx, "vx"); REQ(ps->vy, "vy"); REQ(ps->vz, "vz");
+    REQ(ps->m, "m"); REQ(ps->u, "u"); REQ(ps->h, "h"); REQ(ps->rho, "rho"); REQ(ps->omega, "omega");
+    REQ(ps->ax, "ax"); REQ(ps->ay, "ay"); REQ(ps->az, "az"); REQ(ps->dudt, "dudt");
+    REQ(ps->vsig, "vsig"); REQ(ps->dt, "dt");
+    const int64_t n = ps->n;
+    bool reuse = c->built && !c->resident && c->built_x == ps->x && c->built_n == n;
+    c->resident = false;
+    TRY(ensure_capacity(c, n));
+    c->n = n;
+    if (n == 0) return SPH_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!reuse) {
+        TRY(build_order(c, n, ps->x, ps->y, ps->z));
+        c->built = true;
+        c->built_x = ps->x;
+        c->built_n = n;
+    }
+    timer_begin(c, 2, &e0, &e1);
+    GatherList g{};
+    const void *src[] = {ps->x, ps->y, ps->z, ps->m, ps->h, ps->rho, ps->omega, ps->u,
+                         ps->vx, ps->vy, ps->vz};
+    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.m, c->s.h, c->s.rho, c->s.omega, c->s.u,
+                   c->s.vx, c->s.vy, c->s.vz};
+    g.count = 11;
+    for (int a = 0; a < g.count; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
+    TRY(gather(c, n, g, false));
+    TRY(build_tree(c, n));
+    timer_end(c, 2, e0, e1);
+    TRY(force_prep(c, n, c->s.u));
+    TRY(run_forces(c, n, c->s.vx, c->s.vy, c->s.vz));
+    ScatterList sl{};
+    const void *ss[] = {c->s.ax, c->s.ay, c->s.az, c->s.du, c->s.vsig, c->s.dt, c->s.nforce};
+    void *sd[] = {ps->ax, ps->ay, ps->az, ps->dudt, ps->vsig, ps->dt, ps->nforce};
+    int kinds[] = {0, 0, 0, 0, 0, 0, 1};
+    for (int a = 0; a < 7; a++) {
+        if (!sd[a]) continue;
+        sl.kind[sl.count] = kinds[a];
+        sl.src[sl.count] = ss[a];
+        sl.dst[sl.count] = sd[a];
+        sl.count++;
+    }
+    TRY(scatter(c, n, sl, c->perm));
+    return SPH_OK;
+}
+
+sph_status sph_upload_state(sph_ctx *c, const sph_particles *ps)
+{
+    TRY(check_ps(c, ps));
+    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z");
+    REQ(ps->vx, "vx"); REQ(ps->vy, "vy"); REQ(ps->vz, "vz");
+    REQ(ps->m, "m"); REQ(ps->u, "u"); REQ(ps->h, "h");
+    const int64_t n = ps->n;
+    c->resident = false;
+    TRY(ensure_capacity(c, n));
+    c->n = n;
+    if (n == 0) return fail(c, SPH_EINVAL, "resident state needs n > 0");
+    TRY(build_order(c, n, ps->x, ps->y, ps->z));
+    GatherList g{};
+    const void *src[] = {ps->x, ps->y, ps->z, ps->vx, ps->vy, ps->vz, ps->m, ps->u, ps->h};
+    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.vx, c->s.vy, c->s.vz, c->s.m, c->s.u, c->s.h};
+    g.count = 9;
+    for (int a = 0; a < g.count; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
+    TRY(gather(c, n, g, false));
+    TRY(hip_check(c, hipMemcpyAsync(c->s.id, c->perm, sizeof(uint32_t) * (size_t)n,
+                                    hipMemcpyDeviceToDevice, c->stream), "copy ids"));
+    TRY(build_tree(c, n));
+    TRY(run_density(c, n));
+    TRY(force_prep(c, n, c->s.u));
+    TRY(run_forces(c, n, c->s.vx, c->s.vy, c->s.vz));
+    TRY(reduce_dt(c, n));
+    TRY(hip_check(c, hipMemsetAsync(c->d_scal + 1, 0, sizeof(double) * 2, c->stream), "reset time"));
+    TRY(reduce_diag(c, n));
+    c->built = false;
+    c->resident = true;
+    c->steps = 0;
+    return SPH_OK;
+}
+
+sph_status sph_step(sph_ctx *c, double dt, double *dt_used)
+{
+    if (!c) return SPH_EINVAL;
+    if (!c->resident) return fail(c, SPH_ESTATE, "sph_step needs sph_upload_state first");
+    if (!std::isfinite(dt)) return fail(c, SPH_EINVAL, "dt is not finite");
+    const int64_t n = c->n;
+    TRY(kick_drift(c, n, dt));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_begin(c, 2, &e0, &e1);
+    TRY(build_order(c, n, c->s.x, c->s.y, c->s.z));
+    GatherList g{};
+    Sorted &S = c->s, &T = c->t;
+    double **sa[] = {&S.x, &S.y, &S.z, &S.vx, &S.vy, &S.vz, &S.m, &S.u, &S.h,
+                     &S.vpx, &S.vpy, &S.vpz, &S.up};
+    double **ta[] = {&T.x, &T.y, &T.z, &T.vx, &T.vy, &T.vz, &T.m, &T.u, &T.h,
+                     &T.vpx, &T.vpy, &T.vpz, &T.up};
+    const int nd = 13;
+    for (int a = 0; a < nd; a++) { g.kind[a] = 0; g.src[a] = *sa[a]; g.dst[a] = *ta[a]; }
+    g.kind[nd] = 1; g.src[nd] = S.id; g.dst[nd] = T.id;
+    g.count = nd + 1;
+    TRY(gather(c, n, g, false));
+    for (int a = 0; a < nd; a++) std::swap(*sa[a], *ta[a]);
+    std::swap(S.id, T.id);
+    TRY(build_tree(c, n));
+    timer_end(c, 2, e0, e1);
+    TRY(run_density(c, n));
+    TRY(force_prep(c, n, S.up));
+    TRY(run_forces(c, n, S.vpx, S.vpy, S.vpz));
+    TRY(closing_kick(c, n, dt));
+    TRY(reduce_dt(c, n));
+    TRY(reduce_diag(c, n));
+    c->steps++;
+    c->dt_used_out = dt_used;
+    return SPH_OK;
+}
+
+sph_status sph_download_state(sph_ctx *c, sph_particles *ps)
+{
+    TRY(check_ps(c, ps));
+    if (!c->resident) return fail(c, SPH_ESTATE, "no resident state");
+    if (ps->n != c->n) return fail(c, SPH_EINVAL, "n differs from the resident state");
+    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z");
+    REQ(ps->vx, "vx"); REQ(ps->vy, "vy"); REQ(ps->vz, "vz"); REQ(ps->u, "u"); REQ(ps->h, "h");
+    const int64_t n = c->n;
+    ScatterList sl{};
+    const void *src[] = {c->s.x, c->s.y, c->s.z, c->s.vx, c->s.vy, c->s.vz, c->s.u, c->s.h,
+                         c->s.rho, c->s.omega, c->s.ax, c->s.ay, c->s.az, c->s.du, c->s.vsig,
+                         c->s.dt, c->s.nngb, c->s.nforce};
+    void *dst[] = {(void *)ps->x, (void *)ps->y, (void *)ps->z, (void *)ps->vx, (void *)ps->vy,
+                   (void *)ps->vz, (void *)ps->u, ps->h, ps->rho, ps->omega, ps->ax, ps->ay,
+                   ps->az, ps->dudt, ps->vsig, ps->dt, ps->nngb, ps->nforce};
+    for (int a = 0; a < 18; a++) {
+        if (!dst[a]) continue;
+        sl.kind[sl.count] = a >= 16 ? 1 : 0;
+        sl.src[sl.count] = src[a];
+        sl.dst[sl.count] = dst[a];
+        sl.count++;
+    }
+    TRY(scatter(c, n, sl, c->s.id));
+    TRY(eos_scatter(c, n, c->s.id, ps->u, ps->pressure, ps->cs));
+    return SPH_OK;
+}
+
+sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
+{
+    if (!c || !info) return SPH_EINVAL;
+    if (!c->resident) return fail(c, SPH_ESTATE, "no resident state");
+    int64_t counts[2] = {0, 0};
+    TRY(hip_check(c, hipMemcpyAsync(c->h_scal, c->d_scal, sizeof(double) * 8,
+                                    hipMemcpyDeviceToHost, c->stream), "copy scalars"));
+    TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    TRY(hip_check(c, hipMemcpy(counts, c->d_counts, sizeof(counts), hipMemcpyDeviceToHost),
+                  "copy counts"));
+    int32_t st[kStatusWords];
+    TRY(hip_check(c, hipMemcpy(st, c->d_status, sizeof(st), hipMemcpyDeviceToHost), "status"));
+    std::memset(info, 0, sizeof(*info));
+    info->dt_next = c->h_scal[0];
+    info->dt_last = c->h_scal[1];
+    info->time = c->h_scal[2];
+    info->kinetic = c->h_scal[3];
+    info->thermal = c->h_scal[4];
+    for (int a = 0; a < 3; a++) info->momentum[a] = c->h_scal[5 + a];
+    info->steps = c->steps;
+    info->n_dens_pairs = counts[0];
+    info->n_force_pairs = counts[1];
+    info->nr_iter_max = st[5];
+    return SPH_OK;
+}
+
+sph_status sph_neighbours(sph_ctx *c, const sph_particles *ps, int32_t mode, int64_t *offsets,
+                          int32_t *idx, int64_t cap)
+{
+    TRY(check_ps(c, ps));
+    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z"); REQ(ps->h, "h");
+    if (!offsets) return fail(c, SPH_EINVAL, "offsets is NULL");
+    if (mode != 0 && mode != 1) return fail(c, SPH_EINVAL, "mode must be 0 or 1");
+    if (cap < 0 || (cap > 0 && !idx)) return fail(c, SPH_EINVAL, "bad idx / cap");
+    const int64_t n = ps->n;
+    c->resident = false;
+    TRY(ensure_capacity(c, n));
+    c->n = n;
+    if (n == 0) {
+        TRY(hip_check(c, hipMemsetAsync(offsets, 0, sizeof(int64_t), c->stream), "offsets"));
+        return hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    }
+    TRY(build_from(c, ps, false));
+    TRY(hip_check(c, hipMemcpyAsync(c->s.id, c->perm, sizeof(uint32_t) * (size_t)n,
+                                    hipMemcpyDeviceToDevice, c->stream), "copy ids"));
+    int64_t *counts_sorted = (int64_t *)c->s.ax;   // scratch
+    TRY(run_neighbours(c, n, mode, counts_sorted, nullptr, nullptr, 0));
+    ScatterList sl{};
+    sl.count = 1;
+    sl.kind[0] = 0;   // 8-byte copy
+    sl.src[0] = counts_sorted;
+    sl.dst[0] = offsets;
+    TRY(scatter(c, n, sl, c->perm));
+    TRY(scan_offsets(c, n, offsets));
+    int64_t total = 0;
+    TRY(hip_check(c, hipStreamSynchronize(c->stream), "sync"));
+    TRY(hip_check(c, hipMemcpy(&total, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost),
+                  "copy total"));
+    if (total > cap) return fail(c, SPH_ECAP, "neighbour lists need " + std::to_string(total) +
+                                                  " entries, cap is " + std::to_string(cap));
+    TRY(run_neighbours(c, n, mode, counts_sorted, offsets, idx, cap));
+    return hip_check(c, hipStreamSynchronize(c->stream), "sync");
+}
+
+sph_status sph_sync(sph_ctx *c)
+{
+    if (!c) return SPH_EINVAL;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
+    e = hipMemcpy(c->h_status, c->d_status, sizeof(int32_t) * kStatusWords, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_check(c, e, "read status");
+    if (c->dt_used_out && c->resident) {
+        double v = 0.0;
+        if (hipMemcpy(&v, c->d_scal + 1, sizeof(double), hipMemcpyDeviceToHost) == hipSuccess)
+            *c->dt_used_out = v;
+        c->dt_used_out = nullptr;
+    }
+    int32_t st[kStatusWords];
+    std::memcpy(st, c->h_status, sizeof(st));
+    if (st[0] != 0 || st[4] != 0 || st[5] != 0) {
+        e = hipMemset(c->d_status, 0, sizeof(int32_t) * kStatusWords);
+        if (e != hipSuccess) return hip_check(c, e, "clear status");
+    }
+    if (st[0] & kFlagNonFinite)
+        return fail(c, SPH_ENONFINITE, std::to_string(st[2]) + " particles with non-finite results");
+    if (st[0] & kFlagStencil)
+        return fail(c, SPH_ESTENCIL, std::to_string(st[3]) +
+                                         " particles with 2h >= L/2 in the periodic box");
+    if (st[0] & kFlagNotConverged)
+        return fail(c, SPH_ENOTCONVERGED, std::to_string(st[1]) +
+                                              " smoothing lengths did not converge");
+    c->err.clear();
+    return SPH_OK;
+}
+
+const char *sph_last_error(const sph_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+size_t sph_device_bytes(const sph_ctx *c) { return c ? c->bytes : 0; }
+
+sph_status sph_enable_kernel_timing(sph_ctx *c, int32_t enable)
+{
+    if (!c) return SPH_EINVAL;
+    c->timer.on = enable != 0;
+    return SPH_OK;
+}
+
+sph_status sph_kernel_times(sph_ctx *c, int32_t which, double *ms, int64_t *launches)
+{
+    if (!c || which < 0 || which > 2) return SPH_EINVAL;
+    TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    for (int w = 0; w < 3; w++) {
+        for (auto &pr : c->timer.pending[w]) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) {
+                c->timer.ms[w] += t;
+                c->timer.launches[w]++;
+            }
+            c->timer.pool.push_back(pr);
+        }
+        c->timer.pending[w].clear();
+    }
+    if (ms) *ms = c->timer.ms[which];
+    if (launches) *launches = c->timer.launches[which];
+    if (!ms && !launches) { c->timer.ms[which] = 0; c->timer.launches[which] = 0; }
+    return SPH_OK;
+}
+
+} // extern "C"

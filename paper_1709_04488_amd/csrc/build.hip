@@ -1,0 +1,412 @@
+// Neighbour-search structure: bounding box, Morton keys, LSD radix sort,
+// gathers into sorted order, leaf boxes and the 8-ary box tree above them.
+//
+// The paper builds a balanced KD-tree by median splits with N_LEAF particles
+// per leaf and propagates each cell's smoothing-sphere extent box upwards
+// (section 4.2).  On the GPU the same role is played by a Morton-order sort
+// (one radix sort instead of a recursive median selection, which the paper
+// names as its tree-build scaling bottleneck, section 5.2.1) followed by
+// leaves of leaf_size consecutive sorted particles; every leaf and node keeps
+// the bounding box of its particles and their largest h.
+#include "sph_internal.hpp"
+
+namespace sph {
+
+namespace {
+
+constexpr int kBoxThreads = 256;
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;   // 4096 keys per tile
+constexpr int kMortonBits = 16;                  // per axis: 48-bit keys, 6 passes
+
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void k_box_fixed(double *box, double l0, double l1, double l2, double h0, double h1,
+                            double h2)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        box[0] = l0; box[1] = l1; box[2] = l2;
+        box[3] = h0; box[4] = h1; box[5] = h2;
+    }
+}
+
+__global__ __launch_bounds__(kBoxThreads) void k_box_partial(int64_t n, const double *__restrict__ x,
+                                                             const double *__restrict__ y,
+                                                             const double *__restrict__ z,
+                                                             double *__restrict__ part)
+{
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        double v[3] = {x[k], y[k], z[k]};
+        for (int a = 0; a < 3; a++) { mn[a] = fmin(mn[a], v[a]); mx[a] = fmax(mx[a], v[a]); }
+    }
+    __shared__ double sh[6][kBoxThreads];
+    for (int a = 0; a < 3; a++) { sh[a][threadIdx.x] = mn[a]; sh[3 + a][threadIdx.x] = mx[a]; }
+    __syncthreads();
+    for (int s = kBoxThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int a = 0; a < 3; a++) {
+                sh[a][threadIdx.x] = fmin(sh[a][threadIdx.x], sh[a][threadIdx.x + s]);
+                sh[3 + a][threadIdx.x] = fmax(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + s]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void k_box_final(int nb, const double *__restrict__ part,
+                                                  double *__restrict__ box)
+{
+    if (threadIdx.x != 0) return;
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nb; b++)
+        for (int a = 0; a < 3; a++) {
+            mn[a] = fmin(mn[a], part[b * 6 + a]);
+            mx[a] = fmax(mx[a], part[b * 6 + 3 + a]);
+        }
+    for (int a = 0; a < 3; a++) { box[a] = mn[a]; box[3 + a] = mx[a]; }
+}
+
+__device__ inline uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_keys(int64_t n, const double *__restrict__ x,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ z,
+                                              const double *__restrict__ box, int bits,
+                                              uint64_t *__restrict__ keys,
+                                              uint32_t *__restrict__ vals)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double ext = fmax(fmax(box[3] - box[0], box[4] - box[1]), box[5] - box[2]);
+    double cells = (double)(1u << bits);
+    double scale = ext > 0.0 ? cells / ext : 0.0;
+    double top = cells - 1.0;
+    double q[3] = {(x[k] - box[0]) * scale, (y[k] - box[1]) * scale, (z[k] - box[2]) * scale};
+    uint64_t key = 0;
+    for (int a = 0; a < 3; a++) {
+        double c = floor(q[a]);
+        c = c < 0.0 ? 0.0 : (c > top ? top : c);
+        if (c != c) c = 0.0;   // NaN position: any key; flagged by the density loop
+        key |= spread3((uint64_t)c) << a;
+    }
+    keys[k] = key;
+    vals[k] = (uint32_t)k;
+}
+
+// ---- LSD radix sort, 8-bit digits ------------------------------------------
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(int64_t n, const uint64_t *__restrict__ keys,
+                                                        int shift, uint32_t *__restrict__ hist,
+                                                        int64_t ntiles)
+{
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = blockIdx.x * (int64_t)kRsTile;
+    for (int it = 0; it < kRsItems; it++) {
+        int64_t k = base + it * kRsThreads + threadIdx.x;
+        if (k < n) atomicAdd(&cnt[(keys[k] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of `total` counts in place by one block.
+__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *__restrict__ a, int64_t total)
+{
+    __shared__ uint32_t sums[1024];
+    int t = threadIdx.x;
+    int64_t chunk = (total + 1023) / 1024;
+    int64_t s0 = t * chunk, s1 = s0 + chunk < total ? s0 + chunk : total;
+    uint32_t s = 0;
+    for (int64_t k = s0; k < s1; k++) s += a[k];
+    sums[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        uint32_t v = t >= d ? sums[t - d] : 0u;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = sums[t] - s;
+    for (int64_t k = s0; k < s1; k++) {
+        uint32_t v = a[k];
+        a[k] = run;
+        run += v;
+    }
+}
+
+// Stable scatter.  Wave w of the block owns keys [tile + w*1024, +1024) and
+// walks them in 16 rounds of 64 in index order; equal digits within a round
+// are ranked with 8 ballots, across rounds with per-wave LDS counters, and
+// across waves by an exclusive prefix of those counters.
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint64_t *__restrict__ kin,
+                                                           const uint32_t *__restrict__ vin,
+                                                           uint64_t *__restrict__ kout,
+                                                           uint32_t *__restrict__ vout, int shift,
+                                                           const uint32_t *__restrict__ offs,
+                                                           int64_t ntiles)
+{
+    __shared__ uint32_t wcnt[kRsThreads / kWave][256];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    for (int k = threadIdx.x; k < (kRsThreads / kWave) * 256; k += kRsThreads)
+        (&wcnt[0][0])[k] = 0;
+    __syncthreads();
+    const uint64_t lt = __lanemask_lt();
+    const int64_t base = blockIdx.x * (int64_t)kRsTile + w * (kRsItems * kWave);
+    uint64_t key[kRsItems];
+    uint32_t val[kRsItems];
+    uint32_t rank[kRsItems];
+    for (int r = 0; r < kRsItems; r++) {
+        int64_t k = base + r * kWave + lane;
+        bool valid = k < n;
+        key[r] = valid ? kin[k] : 0ull;
+        val[r] = valid ? vin[k] : 0u;
+        uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+        uint64_t mask = __ballot(valid);
+        for (int b = 0; b < 8; b++) {
+            uint64_t bb = __ballot((d >> b) & 1u);
+            mask &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        uint32_t before = valid ? wcnt[w][d] : 0u;
+        uint32_t prior = (uint32_t)__popcll(mask & lt);
+        rank[r] = before + prior;
+        wave_lds_sync();
+        bool leader = valid && prior == 0;
+        if (leader) wcnt[w][d] = before + (uint32_t)__popcll(mask);
+        wave_lds_sync();
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        uint32_t run = 0;
+        for (int ww = 0; ww < kRsThreads / kWave; ww++) {
+            uint32_t v = wcnt[ww][threadIdx.x];
+            wcnt[ww][threadIdx.x] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < kRsItems; r++) {
+        int64_t k = base + r * kWave + lane;
+        if (k < n) {
+            uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+            uint32_t pos = offs[d * ntiles + blockIdx.x] + wcnt[w][d] + rank[r];
+            kout[pos] = key[r];
+            vout[pos] = val[r];
+        }
+    }
+}
+
+// ---- gathers ------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t *__restrict__ perm,
+                                                GatherList g, int identity)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int64_t src = identity ? k : (int64_t)perm[k];
+    for (int a = 0; a < g.count; a++) {
+        switch (g.kind[a]) {
+        case 0: ((double *)g.dst[a])[k] = ((const double *)g.src[a])[src]; break;
+        case 1: ((uint32_t *)g.dst[a])[k] = ((const uint32_t *)g.src[a])[src]; break;
+        default: ((float *)g.dst[a])[k] = ((const float *)g.src[a])[src]; break;
+        }
+    }
+}
+
+__global__ void k_iota(int64_t n, uint32_t *__restrict__ v)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) v[k] = (uint32_t)k;
+}
+
+// ---- leaves and tree -------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_leaves(int64_t n, int G, const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ z,
+                                                const double *__restrict__ h,
+                                                Node *__restrict__ leaves, int64_t L)
+{
+    int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    Node nd;
+    for (int a = 0; a < 3; a++) { nd.lo[a] = INFINITY; nd.hi[a] = -INFINITY; }
+    nd.hmax = 0.0;
+    nd.pad = 0.0;
+    int64_t k1 = (l + 1) * G < n ? (l + 1) * G : n;
+    for (int64_t k = l * G; k < k1; k++) {
+        double v[3] = {x[k], y[k], z[k]};
+        for (int a = 0; a < 3; a++) { nd.lo[a] = fmin(nd.lo[a], v[a]); nd.hi[a] = fmax(nd.hi[a], v[a]); }
+        nd.hmax = fmax(nd.hmax, h[k]);
+    }
+    leaves[l] = nd;
+}
+
+__global__ __launch_bounds__(256) void k_tree_level(const Node *__restrict__ child, int64_t nchild,
+                                                    Node *__restrict__ parent, int64_t npar)
+{
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= npar) return;
+    Node nd;
+    for (int a = 0; a < 3; a++) { nd.lo[a] = INFINITY; nd.hi[a] = -INFINITY; }
+    nd.hmax = 0.0;
+    nd.pad = 0.0;
+    int64_t c1 = 8 * p + 8 < nchild ? 8 * p + 8 : nchild;
+    for (int64_t c = 8 * p; c < c1; c++) {
+        Node ch = child[c];
+        for (int a = 0; a < 3; a++) { nd.lo[a] = fmin(nd.lo[a], ch.lo[a]); nd.hi[a] = fmax(nd.hi[a], ch.hi[a]); }
+        nd.hmax = fmax(nd.hmax, ch.hmax);
+    }
+    parent[p] = nd;
+}
+
+// FP32-pair mode: single-precision offsets of each particle from the centre of
+// its leaf box.
+__global__ __launch_bounds__(256) void k_offsets(int64_t n, int G, const double *__restrict__ x,
+                                                 const double *__restrict__ y,
+                                                 const double *__restrict__ z,
+                                                 const Node *__restrict__ leaves,
+                                                 float *__restrict__ fx, float *__restrict__ fy,
+                                                 float *__restrict__ fz)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const Node &nd = leaves[k / G];
+    fx[k] = (float)(x[k] - 0.5 * (nd.lo[0] + nd.hi[0]));
+    fy[k] = (float)(y[k] - 0.5 * (nd.lo[1] + nd.hi[1]));
+    fz[k] = (float)(z[k] - 0.5 * (nd.lo[2] + nd.hi[2]));
+}
+
+// A_i = P_i / (Omega_i rho_i^2), c_i = sqrt(gamma P_i / rho_i), 1/h_i with
+// P_i = (gamma - 1) rho_i u_i.
+__global__ __launch_bounds__(256) void k_force_prep(int64_t n, double gamma,
+                                                    const double *__restrict__ rho,
+                                                    const double *__restrict__ omega,
+                                                    const double *__restrict__ u,
+                                                    const double *__restrict__ h,
+                                                    double *__restrict__ A, double *__restrict__ c,
+                                                    double *__restrict__ hinv)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double P = (gamma - 1.0) * rho[k] * u[k];
+    A[k] = P / (omega[k] * rho[k] * rho[k]);
+    c[k] = sqrt(gamma * P / rho[k]);
+    hinv[k] = 1.0 / h[k];
+}
+
+} // namespace
+
+static inline unsigned grid_for(int64_t n, int threads)
+{
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y, const double *z)
+{
+    if (n == 0) return SPH_OK;
+    const sph_params &p = c->p;
+    if (p.periodic) {
+        hipLaunchKernelGGL(k_box_fixed, dim3(1), dim3(64), 0, c->stream, c->d_box, p.box_lo[0],
+                           p.box_lo[1], p.box_lo[2], p.box_hi[0], p.box_hi[1], p.box_hi[2]);
+    } else {
+        int nb = (int)std::min<int64_t>(1024, ceil_div(n, kBoxThreads));
+        hipLaunchKernelGGL(k_box_partial, dim3(nb), dim3(kBoxThreads), 0, c->stream, n, x, y, z,
+                           c->d_part);
+        hipLaunchKernelGGL(k_box_final, dim3(1), dim3(64), 0, c->stream, nb, c->d_part, c->d_box);
+    }
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, x, y, z,
+                       c->d_box, kMortonBits, c->keys[0], c->vals[0]);
+    int64_t ntiles = ceil_div(n, kRsTile);
+    int passes = (3 * kMortonBits + 7) / 8;
+    int cur = 0;
+    for (int ps = 0; ps < passes; ps++) {
+        int shift = 8 * ps;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(kRsThreads), 0, c->stream, n,
+                           c->keys[cur], shift, c->hist, ntiles);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, c->stream, c->hist, 256 * ntiles);
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(kRsThreads), 0, c->stream, n,
+                           c->keys[cur], c->vals[cur], c->keys[cur ^ 1], c->vals[cur ^ 1], shift,
+                           c->hist, ntiles);
+        cur ^= 1;
+    }
+    c->perm = c->vals[cur];
+    return hip_check(c, hipGetLastError(), "build_order");
+}
+
+sph_status gather(sph_ctx *c, int64_t n, const GatherList &g, bool identity_src_index)
+{
+    if (n == 0 || g.count == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, c->perm, g,
+                       identity_src_index ? 1 : 0);
+    return hip_check(c, hipGetLastError(), "gather");
+}
+
+sph_status build_tree(sph_ctx *c, int64_t n)
+{
+    TreeInfo &T = c->tree;
+    const int G = c->p.leaf_size;
+    T.leaf_size = G;
+    T.n = n;
+    if (n == 0) { T.nlev = 0; return SPH_OK; }
+    int64_t cnt = ceil_div(n, G), off = 0;
+    int lev = 0;
+    while (true) {
+        T.off[lev] = off;
+        T.cnt[lev] = cnt;
+        off += cnt;
+        lev++;
+        if (cnt == 1) break;
+        cnt = ceil_div(cnt, 8);
+        if (lev >= kMaxLevels) return fail(c, SPH_EINVAL, "tree too deep");
+    }
+    T.nlev = lev;
+    if (off > c->node_cap) return fail(c, SPH_ENOMEM, "node capacity");
+    hipLaunchKernelGGL(k_leaves, dim3(grid_for(T.cnt[0], 256)), dim3(256), 0, c->stream, n, G,
+                       c->s.x, c->s.y, c->s.z, c->s.h, c->nodes, T.cnt[0]);
+    for (int l = 1; l < T.nlev; l++)
+        hipLaunchKernelGGL(k_tree_level, dim3(grid_for(T.cnt[l], 256)), dim3(256), 0, c->stream,
+                           c->nodes + T.off[l - 1], T.cnt[l - 1], c->nodes + T.off[l], T.cnt[l]);
+    if (c->p.precision == SPH_FP32_PAIR)
+        hipLaunchKernelGGL(k_offsets, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, G, c->s.x,
+                           c->s.y, c->s.z, c->nodes, c->s.fx, c->s.fy, c->s.fz);
+    return hip_check(c, hipGetLastError(), "build_tree");
+}
+
+sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted)
+{
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_force_prep, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n,
+                       c->p.gamma, c->s.rho, c->s.omega, u_sorted, c->s.h, c->s.A, c->s.c,
+                       c->s.hinv);
+    return hip_check(c, hipGetLastError(), "force_prep");
+}
+
+sph_status iota(sph_ctx *c, int64_t n, uint32_t *v)
+{
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, v);
+    return hip_check(c, hipGetLastError(), "iota");
+}
+
+} // namespace sph

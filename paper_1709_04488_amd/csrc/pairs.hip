@@ -1,0 +1,822 @@
+// Pair loops: density + Newton-Raphson h solve, hydro forces, neighbour export.
+//
+// Work decomposition (the GPU analogue of the paper's per-leaf-cell
+// neighbour gathering, section 4.2, with one leaf as the unit of work as in
+// its OpenMP loop, section 5.2.1): one wavefront per home leaf of G sorted
+// particles, 64/G lanes per particle.  The wave walks the box tree to collect
+// the leaves that can hold neighbours of any of its particles into an LDS
+// list, then every lane sweeps its share of the particles of those leaves.
+// Each output is written by exactly one lane and summed in a fixed order, so
+// results are deterministic and need no atomics.
+#include "sph_internal.hpp"
+
+#include <algorithm>
+
+namespace sph {
+namespace {
+
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Blocks are dispatched round-robin over the XCDs; give each XCD a
+// contiguous run of leaves so that neighbouring leaves share an L2.
+__device__ inline int64_t xcd_leaf(int64_t b, int64_t nb)
+{
+    int64_t per = (nb + kXcds - 1) / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+// Squared gap between box [lo, hi] and node box (0 if they overlap), with the
+// periodic images of the node when the box is periodic.
+__device__ inline double box_gap2(const double lo[3], const double hi[3], const Node &nd,
+                                  const Box &bx)
+{
+    double s = 0.0;
+    for (int a = 0; a < 3; a++) {
+        double g = fmax(fmax(nd.lo[a] - hi[a], lo[a] - nd.hi[a]), 0.0);
+        if (bx.periodic) {
+            double L = bx.len[a];
+            double g1 = fmax(fmax(nd.lo[a] + L - hi[a], lo[a] - (nd.hi[a] + L)), 0.0);
+            double g2 = fmax(fmax(nd.lo[a] - L - hi[a], lo[a] - (nd.hi[a] - L)), 0.0);
+            g = fmin(g, fmin(g1, g2));
+        }
+        s += g * g;
+    }
+    return s;
+}
+
+// r_ij^2 exactly as (dx*dx + dy*dy) + dz*dz, each operation rounded on its
+// own, so neighbour predicates agree bit for bit with any other evaluation
+// written the same way.
+__device__ inline double exact_r2(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    double a = dx * dx;
+    double b = dy * dy;
+    double c = dz * dz;
+    return (a + b) + c;
+}
+
+// a*b + c*d with both products rounded before the sum and no fused
+// multiply-add, so swapping (a, b) with (c, d) gives the same bits: keeps the
+// pair force of (i, j) the exact negative of that of (j, i).
+template <class T>
+__device__ inline T sym_dot2(T a, T b, T c, T d)
+{
+#pragma clang fp contract(off)
+    T p = a * b;
+    T q = c * d;
+    return p + q;
+}
+
+__device__ inline double min_image(double d, double L, double half)
+{
+    if (d > half) d -= L;
+    else if (d < -half) d += L;
+    return d;
+}
+
+__device__ inline float min_image_f(float d, float L, float half)
+{
+    if (d > half) d -= L;
+    else if (d < -half) d += L;
+    return d;
+}
+
+struct WalkBuf {
+    uint32_t a[kFront];
+    uint32_t b[kFront];
+};
+
+// Breadth-first walk of the 8-ary tree, 64 child tests per step.  Returns the
+// number of candidate leaves (list in *out), or -1 if a frontier overflowed
+// the LDS capacity (then the caller scans every leaf).
+template <class Test>
+__device__ int walk(const TreeInfo &T, const Node *nodes, Test test, WalkBuf &wb,
+                    const uint32_t **out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t lt = __lanemask_lt();
+    uint32_t *cur = wb.a, *nxt = wb.b;
+    int top = T.nlev - 1;
+    if (top == 0) {
+        bool pass = lane == 0 && test(nodes[0]);
+        if (lane == 0) cur[0] = 0;
+        wave_lds_sync();
+        *out = cur;
+        return __ballot(pass) ? 1 : 0;
+    }
+    if (lane == 0) cur[0] = 0;
+    wave_lds_sync();
+    int ncur = 1;
+    for (int lev = top; lev > 0; lev--) {
+        const Node *cl = nodes + T.off[lev - 1];
+        const int64_t nchild = T.cnt[lev - 1];
+        const int total = ncur * 8;
+        int nout = 0;
+        for (int b = 0; b < total; b += kWave) {
+            int t = b + lane;
+            bool valid = t < total;
+            int64_t node = valid ? (int64_t)cur[t >> 3] * 8 + (t & 7) : 0;
+            valid = valid && node < nchild;
+            bool pass = valid && test(cl[node]);
+            uint64_t mask = __ballot(pass);
+            int pos = nout + (int)__popcll(mask & lt);
+            if (pass && pos < kFront) nxt[pos] = (uint32_t)node;
+            nout += (int)__popcll(mask);
+        }
+        wave_lds_sync();
+        if (nout > kFront) return -1;
+        uint32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        ncur = nout;
+        if (ncur == 0) break;
+    }
+    *out = cur;
+    return ncur;
+}
+
+// Visit every candidate leaf: from the LDS list, or (after an overflow) by
+// testing all leaves 64 at a time.  fn(c) is called wave-uniformly.
+template <class Test, class Fn>
+__device__ void for_each_leaf(const TreeInfo &T, const Node *nodes, int ncand,
+                              const uint32_t *list, Test test, Fn fn)
+{
+    if (ncand >= 0) {
+        for (int t = 0; t < ncand; t++) fn((int64_t)list[t]);
+        return;
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t L = T.cnt[0];
+    for (int64_t b = 0; b < L; b += kWave) {
+        int64_t c = b + lane;
+        uint64_t mask = __ballot(c < L && test(nodes[c]));
+        while (mask) {
+            int k = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            fn(b + k);
+        }
+    }
+}
+
+// Per candidate leaf: the periodic shift that the minimum image gives every
+// pair (i in home, j in c) closer than 2 hcov, when that shift is unique;
+// otherwise the pair loop applies the minimum image pair by pair.
+struct Shift {
+    double s[3];
+    bool per_pair;
+};
+
+__device__ inline Shift leaf_shift(const Node &home, const Node &cand, const Box &bx, double hcov)
+{
+    Shift sh{{0.0, 0.0, 0.0}, false};
+    if (!bx.periodic) return sh;
+    for (int a = 0; a < 3; a++) {
+        double dc = 0.5 * (home.lo[a] + home.hi[a]) - 0.5 * (cand.lo[a] + cand.hi[a]);
+        sh.s[a] = dc > bx.half[a] ? -bx.len[a] : (dc < -bx.half[a] ? bx.len[a] : 0.0);
+        double reach = 2.0 * hcov + 0.5 * ((home.hi[a] - home.lo[a]) + (cand.hi[a] - cand.lo[a]));
+        if (!(reach < 0.49 * bx.len[a])) sh.per_pair = true;
+    }
+    return sh;
+}
+
+// ---------------------------------------------------------------------------
+// Density loop + h solve
+// ---------------------------------------------------------------------------
+struct DensArgs {
+    int64_t n;
+    TreeInfo T;
+    Box box;
+    const Node *nodes;
+    const double *x, *y, *z, *m;
+    const float *fx, *fy, *fz;
+    double *h, *rho, *omega;
+    int32_t *nngb;
+    int32_t *status;
+    double eta3;
+    double h_rtol;
+    int32_t max_iter;
+};
+
+// M4: f(q) = a^3/4 - b^3, f'(q) = 3 b^2 - 3/4 a^2 with a = (2-q)_+, b = (1-q)_+
+template <class T>
+__device__ inline void m4(T qq, T &f, T &df)
+{
+    T a = qq < T(2) ? T(2) - qq : T(0);
+    T b = qq < T(1) ? T(1) - qq : T(0);
+    T a2 = a * a, b2 = b * b;
+    f = T(0.25) * a2 * a - b2 * b;
+    df = T(3) * b2 - T(0.75) * a2;
+}
+
+template <int G, int PREC>
+__global__ __launch_bounds__(kWave) void k_density(DensArgs A)
+{
+    constexpr int LPP = kWave / G;
+    constexpr int PER = G / LPP;
+    __shared__ WalkBuf wb;
+    const int lane = threadIdx.x;
+    const int64_t L = A.T.cnt[0];
+    const int64_t leaf = xcd_leaf(blockIdx.x, gridDim.x);
+    if (leaf >= L) return;
+    const int p = lane / LPP, q = lane % LPP;
+    const int64_t i = leaf * G + p;
+    const bool active = i < A.n;
+    const int64_t ii = active ? i : leaf * G;
+    const double xi = A.x[ii], yi = A.y[ii], zi = A.z[ii], mi = A.m[ii];
+    float fxi = 0.f, fyi = 0.f, fzi = 0.f;
+    if (PREC == SPH_FP32_PAIR) { fxi = A.fx[ii]; fyi = A.fy[ii]; fzi = A.fz[ii]; }
+    const Node home = A.nodes[leaf];
+    const Box &bx = A.box;
+    double h = A.h[ii];
+    double lo_b = 0.0, hi_b = INFINITY;
+    bool conv = !active;
+    double h_out = h, rho_out = 0.0, om_out = 1.0;
+    int n_out = 0;
+
+    double hcov = 1.25 * wave_max(active ? h : 0.0);
+    auto make_test = [&](double hc) {
+        double R = 2.0 * hc * (1.0 + 1e-10);
+        double R2 = R * R;
+        return [&bx, &home, R2](const Node &nd) { return box_gap2(home.lo, home.hi, nd, bx) < R2; };
+    };
+    const uint32_t *list = nullptr;
+    int ncand = walk(A.T, A.nodes, make_test(hcov), wb, &list);
+    int iter = 0;
+    for (;;) {
+        double s0 = 0.0, s2 = 0.0;
+        int cnt = 0;
+        const double hinv = 1.0 / h;
+        const double h2x4 = (2.0 * h) * (2.0 * h);
+        const float hinvf = (float)hinv, h2x4f = (float)h2x4;
+        auto body = [&](int64_t c) {
+            const Node cand = A.nodes[c];
+            const Shift sh = leaf_shift(home, cand, bx, hcov);
+            const int64_t j0 = c * G;
+            const int jn = (int)(A.n - j0 < G ? A.n - j0 : G);
+            if (PREC == SPH_FP64) {
+#pragma unroll
+                for (int t = 0; t < PER; t++) {
+                    const int jj = q + LPP * t;
+                    if (jj < jn) {
+                        const int64_t j = j0 + jj;
+                        double dx = xi - A.x[j], dy = yi - A.y[j], dz = zi - A.z[j];
+                        if (sh.per_pair) {
+                            dx = min_image(dx, bx.len[0], bx.half[0]);
+                            dy = min_image(dy, bx.len[1], bx.half[1]);
+                            dz = min_image(dz, bx.len[2], bx.half[2]);
+                        } else {
+                            dx += sh.s[0];
+                            dy += sh.s[1];
+                            dz += sh.s[2];
+                        }
+                        const double r2 = exact_r2(dx, dy, dz);
+                        if (r2 < h2x4) {
+                            const double mj = A.m[j];
+                            double f, df;
+                            const double qq = sqrt(r2) * hinv;
+                            m4(qq, f, df);
+                            s0 += mj * f;
+                            s2 += mj * (qq * df);
+                            cnt += (j != i);
+                        }
+                    }
+                }
+            } else {
+                const float ox = (float)((0.5 * (home.lo[0] + home.hi[0]) -
+                                          0.5 * (cand.lo[0] + cand.hi[0])) + (sh.per_pair ? 0.0 : sh.s[0]));
+                const float oy = (float)((0.5 * (home.lo[1] + home.hi[1]) -
+                                          0.5 * (cand.lo[1] + cand.hi[1])) + (sh.per_pair ? 0.0 : sh.s[1]));
+                const float oz = (float)((0.5 * (home.lo[2] + home.hi[2]) -
+                                          0.5 * (cand.lo[2] + cand.hi[2])) + (sh.per_pair ? 0.0 : sh.s[2]));
+#pragma unroll
+                for (int t = 0; t < PER; t++) {
+                    const int jj = q + LPP * t;
+                    if (jj < jn) {
+                        const int64_t j = j0 + jj;
+                        float dx = (fxi - A.fx[j]) + ox, dy = (fyi - A.fy[j]) + oy,
+                              dz = (fzi - A.fz[j]) + oz;
+                        if (sh.per_pair) {
+                            dx = min_image_f(dx, (float)bx.len[0], (float)bx.half[0]);
+                            dy = min_image_f(dy, (float)bx.len[1], (float)bx.half[1]);
+                            dz = min_image_f(dz, (float)bx.len[2], (float)bx.half[2]);
+                        }
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 < h2x4f) {
+                            const double mj = A.m[j];
+                            float f, df;
+                            const float qq = sqrtf(r2) * hinvf;
+                            m4(qq, f, df);
+                            s0 += mj * (double)f;
+                            s2 += mj * (double)(qq * df);
+                            cnt += (j != i);
+                        }
+                    }
+                }
+            }
+        };
+        for_each_leaf(A.T, A.nodes, ncand, list, make_test(hcov), body);
+#pragma unroll
+        for (int o = 1; o < LPP; o <<= 1) {
+            s0 += __shfl_xor(s0, o);
+            s2 += __shfl_xor(s2, o);
+            cnt += __shfl_xor(cnt, o);
+        }
+        if (!conv) {
+            // g(h) = h^3 rho(h) - eta^3 m = sigma sum m f - eta^3 m, non-decreasing;
+            // g'(h) = -(sigma/h) sum m q f'(q) >= 0
+            const double g = kSigma * s0 - A.eta3 * mi;
+            const double gp = -kSigma * s2 * hinv;
+            if (g < 0.0) lo_b = fmax(lo_b, h); else hi_b = fmin(hi_b, h);
+            double hn;
+            if (g == 0.0) {
+                hn = h;
+            } else {
+                hn = gp > 0.0 ? h - g / gp : (g < 0.0 ? 2.0 * h : 0.5 * h);
+                hn = fmin(fmax(hn, 0.5 * h), 2.0 * h);
+                if (!(hn > lo_b && hn < hi_b)) hn = hi_b < INFINITY ? 0.5 * (lo_b + hi_b) : 2.0 * h;
+            }
+            h_out = h;
+            rho_out = kSigma * s0 * hinv * hinv * hinv;
+            om_out = -s2 / (3.0 * s0);
+            n_out = cnt;
+            if (fabs(hn - h) <= A.h_rtol * h || !(hn == hn)) conv = true;
+            else h = hn;
+        }
+        iter++;
+        if (__ballot(!conv) == 0ull || iter >= A.max_iter) break;
+        const double hm = wave_max(conv ? 0.0 : h);
+        if (hm > hcov) {
+            hcov = 1.25 * hm;
+            ncand = walk(A.T, A.nodes, make_test(hcov), wb, &list);
+        }
+    }
+    if (active && q == 0) {
+        A.h[i] = h_out;
+        A.rho[i] = rho_out;
+        A.omega[i] = om_out;
+        A.nngb[i] = n_out;
+        bool bad = !isfinite(h_out) || !isfinite(rho_out) || !isfinite(om_out) || !(rho_out > 0.0);
+        if (bad) {
+            atomicOr(&A.status[0], kFlagNonFinite);
+            atomicAdd(&A.status[2], 1);
+        } else if (!conv) {
+            atomicOr(&A.status[0], kFlagNotConverged);
+            atomicAdd(&A.status[1], 1);
+        }
+        if (bx.periodic) {
+            double Lmin = fmin(fmin(bx.len[0], bx.len[1]), bx.len[2]);
+            if (!(4.0 * h_out < Lmin)) {
+                atomicOr(&A.status[0], kFlagStencil);
+                atomicAdd(&A.status[3], 1);
+            }
+        }
+    }
+    if (lane == 0) {
+        atomicMax(&A.status[5], iter);
+        if (ncand < 0) atomicAdd(&A.status[4], 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Force loop
+// ---------------------------------------------------------------------------
+struct ForceArgs {
+    int64_t n;
+    TreeInfo T;
+    Box box;
+    const Node *nodes;
+    const double *x, *y, *z, *vx, *vy, *vz, *m, *h, *hinv, *rho, *A, *c;
+    const float *fx, *fy, *fz;
+    double *ax, *ay, *az, *du, *vsig, *dt;
+    int32_t *nforce;
+    int32_t *status;
+    double alpha, beta, ccfl;
+};
+
+template <int G, int PREC>
+__global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
+{
+    constexpr int LPP = kWave / G;
+    constexpr int PER = G / LPP;
+    __shared__ WalkBuf wb;
+    const int lane = threadIdx.x;
+    const int64_t L = F.T.cnt[0];
+    const int64_t leaf = xcd_leaf(blockIdx.x, gridDim.x);
+    if (leaf >= L) return;
+    const int p = lane / LPP, q = lane % LPP;
+    const int64_t i = leaf * G + p;
+    const bool active = i < F.n;
+    const int64_t ii = active ? i : leaf * G;
+    const double xi = F.x[ii], yi = F.y[ii], zi = F.z[ii];
+    const double vxi = F.vx[ii], vyi = F.vy[ii], vzi = F.vz[ii];
+    const double hi = F.h[ii], hinvi = F.hinv[ii], rhoi = F.rho[ii], Ai = F.A[ii], ci = F.c[ii];
+    const double hi2x4 = (2.0 * hi) * (2.0 * hi);
+    const double gfi = kSigma * (hinvi * hinvi) * (hinvi * hinvi);
+    float fxi = 0.f, fyi = 0.f, fzi = 0.f;
+    if (PREC == SPH_FP32_PAIR) { fxi = F.fx[ii]; fyi = F.fy[ii]; fzi = F.fz[ii]; }
+    const Node home = F.nodes[leaf];
+    const Box &bx = F.box;
+    // symmetric criterion: a node can hold force neighbours of the home leaf
+    // if its box is closer than 2 max(h over home, h over node)
+    auto test = [&bx, &home](const Node &nd) {
+        double R = 2.0 * fmax(home.hmax, nd.hmax) * (1.0 + 1e-10);
+        return box_gap2(home.lo, home.hi, nd, bx) < R * R;
+    };
+    const uint32_t *list = nullptr;
+    int ncand = walk(F.T, F.nodes, test, wb, &list);
+
+    double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
+    int cnt = 0;
+    const double alpha = F.alpha, beta = F.beta;
+    auto body = [&](int64_t c) {
+        const Node cand = F.nodes[c];
+        const Shift sh = leaf_shift(home, cand, bx, fmax(home.hmax, cand.hmax));
+        const int64_t j0 = c * G;
+        const int jn = (int)(F.n - j0 < G ? F.n - j0 : G);
+        float ox = 0.f, oy = 0.f, oz = 0.f;
+        if (PREC == SPH_FP32_PAIR) {
+            ox = (float)((0.5 * (home.lo[0] + home.hi[0]) - 0.5 * (cand.lo[0] + cand.hi[0])) +
+                         (sh.per_pair ? 0.0 : sh.s[0]));
+            oy = (float)((0.5 * (home.lo[1] + home.hi[1]) - 0.5 * (cand.lo[1] + cand.hi[1])) +
+                         (sh.per_pair ? 0.0 : sh.s[1]));
+            oz = (float)((0.5 * (home.lo[2] + home.hi[2]) - 0.5 * (cand.lo[2] + cand.hi[2])) +
+                         (sh.per_pair ? 0.0 : sh.s[2]));
+        }
+#pragma unroll
+        for (int t = 0; t < PER; t++) {
+            const int jj = q + LPP * t;
+            if (jj >= jn) continue;
+            const int64_t j = j0 + jj;
+            const double hj = F.h[j];
+            const double hj2x4 = (2.0 * hj) * (2.0 * hj);
+            if (PREC == SPH_FP64) {
+                double dx = xi - F.x[j], dy = yi - F.y[j], dz = zi - F.z[j];
+                if (sh.per_pair) {
+                    dx = min_image(dx, bx.len[0], bx.half[0]);
+                    dy = min_image(dy, bx.len[1], bx.half[1]);
+                    dz = min_image(dz, bx.len[2], bx.half[2]);
+                } else {
+                    dx += sh.s[0];
+                    dy += sh.s[1];
+                    dz += sh.s[2];
+                }
+                const double r2 = exact_r2(dx, dy, dz);
+                if (!((r2 < hi2x4 || r2 < hj2x4) && j != i)) continue;
+                cnt++;
+                const double cj = F.c[j];
+                if (r2 == 0.0) {
+                    vs_max = fmax(vs_max, ci + cj);
+                    continue;
+                }
+                const double r = sqrt(r2);
+                const double rinv = 1.0 / r;
+                const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+                const double hinvj = F.hinv[j];
+                const double gfj = kSigma * (hinvj * hinvj) * (hinvj * hinvj);
+                double fi, dfi, fj, dfj;
+                m4(r * hinvi, fi, dfi);
+                m4(r * hinvj, fj, dfj);
+                const double gi = gfi * dfi, gj = gfj * dfj;
+                const double w = ((vxi - F.vx[j]) * ex + (vyi - F.vy[j]) * ey) + (vzi - F.vz[j]) * ez;
+                const double mj = F.m[j];
+                double cvec = -mj * sym_dot2(Ai, gi, F.A[j], gj);
+                double cdu = Ai * mj * gi * w;
+                const double wneg = fmin(w, 0.0);
+                const double vs = (ci + cj) - beta * wneg;
+                vs_max = fmax(vs_max, vs);
+                const double visc = (mj / (0.5 * (rhoi + F.rho[j]))) * alpha * vs * wneg;
+                const double gbar = 0.5 * (gi + gj);
+                cvec += visc * gbar;
+                cdu -= visc * 0.5 * wneg * gbar;
+                axi += cvec * ex;
+                ayi += cvec * ey;
+                azi += cvec * ez;
+                dui += cdu;
+            } else {
+                float dx = (fxi - F.fx[j]) + ox, dy = (fyi - F.fy[j]) + oy, dz = (fzi - F.fz[j]) + oz;
+                if (sh.per_pair) {
+                    dx = min_image_f(dx, (float)bx.len[0], (float)bx.half[0]);
+                    dy = min_image_f(dy, (float)bx.len[1], (float)bx.half[1]);
+                    dz = min_image_f(dz, (float)bx.len[2], (float)bx.half[2]);
+                }
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (!((r2 < (float)hi2x4 || r2 < (float)hj2x4) && j != i)) continue;
+                cnt++;
+                const float cj = (float)F.c[j];
+                const float cif = (float)ci;
+                if (r2 == 0.0f) {
+                    vs_max = fmax(vs_max, (double)(cif + cj));
+                    continue;
+                }
+                const float r = sqrtf(r2);
+                const float rinv = 1.0f / r;
+                const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+                const float hinvj = (float)F.hinv[j];
+                const float hinvif = (float)hinvi;
+                // own and other kernel factors formed by the same float expression,
+                // so the (j, i) pair sees exactly the values of the (i, j) pair
+                const float gfif = (float)kSigma * (hinvif * hinvif) * (hinvif * hinvif);
+                const float gfjf = (float)kSigma * (hinvj * hinvj) * (hinvj * hinvj);
+                float fi, dfi, fj, dfj;
+                m4(r * hinvif, fi, dfi);
+                m4(r * hinvj, fj, dfj);
+                const float gi = gfif * dfi, gj = gfjf * dfj;
+                const float w = ((float)(vxi - F.vx[j]) * ex + (float)(vyi - F.vy[j]) * ey) +
+                                (float)(vzi - F.vz[j]) * ez;
+                const float mj = (float)F.m[j];
+                const float Aif = (float)Ai;
+                float cvec = -mj * sym_dot2(Aif, gi, (float)F.A[j], gj);
+                float cdu = Aif * mj * gi * w;
+                const float wneg = fminf(w, 0.0f);
+                const float vs = (cif + cj) - (float)beta * wneg;
+                vs_max = fmax(vs_max, (double)vs);
+                const float visc = (mj / (0.5f * ((float)rhoi + (float)F.rho[j]))) * (float)alpha * vs * wneg;
+                const float gbar = 0.5f * (gi + gj);
+                cvec += visc * gbar;
+                cdu -= visc * 0.5f * wneg * gbar;
+                axi += (double)(cvec * ex);
+                ayi += (double)(cvec * ey);
+                azi += (double)(cvec * ez);
+                dui += (double)cdu;
+            }
+        }
+    };
+    for_each_leaf(F.T, F.nodes, ncand, list, test, body);
+#pragma unroll
+    for (int o = 1; o < LPP; o <<= 1) {
+        axi += __shfl_xor(axi, o);
+        ayi += __shfl_xor(ayi, o);
+        azi += __shfl_xor(azi, o);
+        dui += __shfl_xor(dui, o);
+        vs_max = fmax(vs_max, __shfl_xor(vs_max, o));
+        cnt += __shfl_xor(cnt, o);
+    }
+    if (active && q == 0) {
+        const double vsig = cnt > 0 ? vs_max : 2.0 * ci;
+        F.ax[i] = axi;
+        F.ay[i] = ayi;
+        F.az[i] = azi;
+        F.du[i] = dui;
+        F.vsig[i] = vsig;
+        F.dt[i] = F.ccfl * hi / vsig;
+        F.nforce[i] = cnt;
+        if (!isfinite(axi) || !isfinite(ayi) || !isfinite(azi) || !isfinite(dui) ||
+            !isfinite(vsig)) {
+            atomicOr(&F.status[0], kFlagNonFinite);
+            atomicAdd(&F.status[2], 1);
+        }
+    }
+    if (lane == 0 && ncand < 0) atomicAdd(&F.status[4], 1);
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour export (tests): counts, then lists in original indices
+// ---------------------------------------------------------------------------
+struct NgbArgs {
+    int64_t n;
+    TreeInfo T;
+    Box box;
+    const Node *nodes;
+    const double *x, *y, *z, *h;
+    const uint32_t *id;        // sorted -> caller index
+    int32_t mode;
+    int64_t *counts;           // sorted order (pass 1)
+    const int64_t *offsets;    // caller order (pass 2)
+    int32_t *idx;
+    int64_t cap;
+    int32_t *status;
+};
+
+template <int G>
+__global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
+{
+    constexpr int LPP = kWave / G;
+    constexpr int PER = G / LPP;
+    __shared__ WalkBuf wb;
+    const int lane = threadIdx.x;
+    const int64_t L = N.T.cnt[0];
+    const int64_t leaf = xcd_leaf(blockIdx.x, gridDim.x);
+    if (leaf >= L) return;
+    const int p = lane / LPP, q = lane % LPP;
+    const int64_t i = leaf * G + p;
+    const bool active = i < N.n;
+    const int64_t ii = active ? i : leaf * G;
+    const double xi = N.x[ii], yi = N.y[ii], zi = N.z[ii], hi = N.h[ii];
+    const double hi2x4 = (2.0 * hi) * (2.0 * hi);
+    const Node home = N.nodes[leaf];
+    const Box &bx = N.box;
+    const int32_t mode = N.mode;
+    auto test = [&bx, &home, mode](const Node &nd) {
+        double hh = mode == 0 ? home.hmax : fmax(home.hmax, nd.hmax);
+        double R = 2.0 * hh * (1.0 + 1e-10);
+        return box_gap2(home.lo, home.hi, nd, bx) < R * R;
+    };
+    const uint32_t *list = nullptr;
+    int ncand = walk(N.T, N.nodes, test, wb, &list);
+    // two sweeps in pass 2: count this lane's hits, then write them
+    int64_t mine = 0;
+    int64_t base = 0;
+    for (int sweep = 0; sweep < (pass == 1 ? 1 : 2); sweep++) {
+        int64_t k = 0;
+        auto body = [&](int64_t c) {
+            const Node cand = N.nodes[c];
+            const Shift sh = leaf_shift(home, cand, bx, mode == 0 ? home.hmax : fmax(home.hmax, cand.hmax));
+            const int64_t j0 = c * G;
+            const int jn = (int)(N.n - j0 < G ? N.n - j0 : G);
+#pragma unroll
+            for (int t = 0; t < PER; t++) {
+                const int jj = q + LPP * t;
+                if (jj >= jn) continue;
+                const int64_t j = j0 + jj;
+                double dx = xi - N.x[j], dy = yi - N.y[j], dz = zi - N.z[j];
+                if (sh.per_pair) {
+                    dx = min_image(dx, bx.len[0], bx.half[0]);
+                    dy = min_image(dy, bx.len[1], bx.half[1]);
+                    dz = min_image(dz, bx.len[2], bx.half[2]);
+                } else {
+                    dx += sh.s[0];
+                    dy += sh.s[1];
+                    dz += sh.s[2];
+                }
+                const double r2 = exact_r2(dx, dy, dz);
+                bool in = r2 < hi2x4;
+                if (mode == 1) {
+                    const double hj = N.h[j];
+                    in = in || r2 < (2.0 * hj) * (2.0 * hj);
+                }
+                if (in && j != i && active) {
+                    if (sweep == 1) {
+                        int64_t pos = base + k;
+                        if (pos < N.cap) N.idx[pos] = (int32_t)N.id[j];
+                    }
+                    k++;
+                }
+            }
+        };
+        for_each_leaf(N.T, N.nodes, ncand, list, test, body);
+        if (sweep == 0) {
+            mine = k;
+            // exclusive prefix over the LPP lanes of this particle
+            int64_t incl = mine;
+#pragma unroll
+            for (int o = 1; o < LPP; o <<= 1) {
+                int64_t v = (int64_t)__shfl_up((long long)incl, o, LPP);
+                if (q >= o) incl += v;
+            }
+            int64_t total = (int64_t)__shfl((long long)incl, (p * LPP) + LPP - 1);
+            if (pass == 1) {
+                if (active && q == 0) N.counts[i] = total;
+            } else {
+                base = active ? N.offsets[N.id[i]] + (incl - mine) : 0;
+            }
+        }
+    }
+    if (lane == 0 && ncand < 0) atomicAdd(&N.status[4], 1);
+}
+
+// ascending order within each list (insertion sort; lists are ~60 long)
+__global__ __launch_bounds__(256) void k_sort_lists(int64_t n, const int64_t *__restrict__ off,
+                                                    int32_t *__restrict__ idx, int64_t cap)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t a = off[i], b = off[i + 1];
+    if (b > cap) return;
+    for (int64_t k = a + 1; k < b; k++) {
+        int32_t v = idx[k];
+        int64_t m = k - 1;
+        while (m >= a && idx[m] > v) { idx[m + 1] = idx[m]; m--; }
+        idx[m + 1] = v;
+    }
+}
+
+template <class Args>
+inline void fill_common(sph_ctx *c, int64_t n, Args &a)
+{
+    a.n = n;
+    a.T = c->tree;
+    a.box = c->box;
+    a.nodes = c->nodes;
+}
+
+inline unsigned leaf_grid(int64_t L)
+{
+    // a multiple of the XCD count so every XCD gets the same number of blocks
+    int64_t per = (L + kXcds - 1) / kXcds;
+    return (unsigned)(per * kXcds);
+}
+
+} // namespace
+
+sph_status run_density(sph_ctx *c, int64_t n)
+{
+    if (n == 0) return SPH_OK;
+    DensArgs a{};
+    fill_common(c, n, a);
+    a.x = c->s.x; a.y = c->s.y; a.z = c->s.z; a.m = c->s.m;
+    a.fx = c->s.fx; a.fy = c->s.fy; a.fz = c->s.fz;
+    a.h = c->s.h; a.rho = c->s.rho; a.omega = c->s.omega; a.nngb = c->s.nngb;
+    a.status = c->d_status;
+    a.eta3 = c->p.eta * c->p.eta * c->p.eta;
+    // FP32-pair mode: the density sum carries single-precision pair terms
+    // (relative noise ~1e-7), so the Newton step cannot settle below a few
+    // 1e-7; its stop tolerance is floored at 2e-6.
+    a.h_rtol = c->p.precision == SPH_FP32_PAIR ? std::max(c->p.h_rtol, 2e-6) : c->p.h_rtol;
+    a.max_iter = c->p.h_max_iter;
+    const unsigned grid = leaf_grid(c->tree.cnt[0]);
+    const bool f32 = c->p.precision == SPH_FP32_PAIR;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_begin(c, 0, &e0, &e1);
+    switch (c->p.leaf_size) {
+    case 8:
+        if (f32) hipLaunchKernelGGL((k_density<8, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_density<8, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        break;
+    case 32:
+        if (f32) hipLaunchKernelGGL((k_density<32, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_density<32, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        break;
+    default:
+        if (f32) hipLaunchKernelGGL((k_density<16, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_density<16, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        break;
+    }
+    timer_end(c, 0, e0, e1);
+    return hip_check(c, hipGetLastError(), "density kernel");
+}
+
+sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy, const double *vz)
+{
+    if (n == 0) return SPH_OK;
+    ForceArgs a{};
+    fill_common(c, n, a);
+    a.x = c->s.x; a.y = c->s.y; a.z = c->s.z;
+    a.vx = vx; a.vy = vy; a.vz = vz;
+    a.m = c->s.m; a.h = c->s.h; a.hinv = c->s.hinv; a.rho = c->s.rho; a.A = c->s.A; a.c = c->s.c;
+    a.fx = c->s.fx; a.fy = c->s.fy; a.fz = c->s.fz;
+    a.ax = c->s.ax; a.ay = c->s.ay; a.az = c->s.az; a.du = c->s.du;
+    a.vsig = c->s.vsig; a.dt = c->s.dt; a.nforce = c->s.nforce;
+    a.status = c->d_status;
+    a.alpha = c->p.alpha_av; a.beta = c->p.beta_av; a.ccfl = c->p.c_cfl;
+    const unsigned grid = leaf_grid(c->tree.cnt[0]);
+    const bool f32 = c->p.precision == SPH_FP32_PAIR;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_begin(c, 1, &e0, &e1);
+    switch (c->p.leaf_size) {
+    case 8:
+        if (f32) hipLaunchKernelGGL((k_forces<8, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_forces<8, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        break;
+    case 32:
+        if (f32) hipLaunchKernelGGL((k_forces<32, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_forces<32, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        break;
+    default:
+        if (f32) hipLaunchKernelGGL((k_forces<16, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_forces<16, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        break;
+    }
+    timer_end(c, 1, e0, e1);
+    return hip_check(c, hipGetLastError(), "force kernel");
+}
+
+sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_sorted,
+                          const int64_t *offsets, int32_t *idx, int64_t cap)
+{
+    if (n == 0) return SPH_OK;
+    NgbArgs a{};
+    fill_common(c, n, a);
+    a.x = c->s.x; a.y = c->s.y; a.z = c->s.z; a.h = c->s.h;
+    a.id = c->s.id;
+    a.mode = mode;
+    a.counts = counts_sorted;
+    a.offsets = offsets;
+    a.idx = idx;
+    a.cap = cap;
+    a.status = c->d_status;
+    const unsigned grid = leaf_grid(c->tree.cnt[0]);
+    const int pass = offsets ? 2 : 1;
+    switch (c->p.leaf_size) {
+    case 8: hipLaunchKernelGGL((k_neighbours<8>), dim3(grid), dim3(kWave), 0, c->stream, a, pass); break;
+    case 32: hipLaunchKernelGGL((k_neighbours<32>), dim3(grid), dim3(kWave), 0, c->stream, a, pass); break;
+    default: hipLaunchKernelGGL((k_neighbours<16>), dim3(grid), dim3(kWave), 0, c->stream, a, pass); break;
+    }
+    if (pass == 2)
+        hipLaunchKernelGGL(k_sort_lists, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c->stream,
+                           n, offsets, idx, cap);
+    return hip_check(c, hipGetLastError(), "neighbour kernel");
+}
+
+} // namespace sph

@@ -1,0 +1,190 @@
+// Internal definitions shared by the HIP translation units of libsph.
+// Device code targets gfx950 (CDNA4, wave64) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/sph.h"
+
+namespace sph {
+
+// M4 cubic spline in B-spline form: f(q) = (2-q)_+^3 / 4 - (1-q)_+^3, which
+// equals 1 - 3/2 q^2 + 3/4 q^3 on [0,1) and (2-q)^3/4 on [1,2); 3D
+// normalisation 1/pi.
+constexpr double kSigma = 0.31830988618379067154;
+
+constexpr int kWave = 64;
+constexpr int kMaxLevels = 16;   // tree levels above the leaves (8-ary)
+constexpr int kFront = 512;      // per-wave LDS capacity of a walk frontier / candidate list
+constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks dispatched round-robin
+
+// Tree node: bounding box of the particles below it and their largest h.
+// 64 bytes, so one node is half a 128-byte cache line.
+struct alignas(64) Node {
+    double lo[3];
+    double hmax;
+    double hi[3];
+    double pad;
+};
+
+struct TreeInfo {
+    int32_t nlev;                  // levels including the leaf level (level 0)
+    int32_t leaf_size;
+    int64_t n;                     // particles
+    int64_t off[kMaxLevels];       // first node of each level in the node array
+    int64_t cnt[kMaxLevels];       // nodes per level
+};
+
+struct Box {
+    int32_t periodic;
+    double lo[3];
+    double len[3];                 // periodic box lengths
+    double half[3];                // len / 2
+};
+
+// Device status word: [0] flags, [1] h solves not converged, [2] non-finite
+// results, [3] periodic 2h >= L/2, [4] walk overflows (slow path taken),
+// [5] max Newton-Raphson iterations, [6..7] spare.
+enum : int32_t {
+    kFlagNotConverged = 1,
+    kFlagNonFinite = 2,
+    kFlagStencil = 4,
+};
+constexpr int kStatusWords = 8;
+
+// Arrays in sorted (Morton) order.  FP32-pair mode adds float offsets from the
+// centre of each particle's leaf.
+struct Sorted {
+    double *x = nullptr, *y = nullptr, *z = nullptr;
+    double *vx = nullptr, *vy = nullptr, *vz = nullptr;
+    double *m = nullptr, *u = nullptr, *h = nullptr;
+    double *rho = nullptr, *omega = nullptr;
+    double *A = nullptr, *c = nullptr, *hinv = nullptr;   // force record
+    double *ax = nullptr, *ay = nullptr, *az = nullptr, *du = nullptr;
+    double *vsig = nullptr, *dt = nullptr;
+    int32_t *nngb = nullptr, *nforce = nullptr;
+    uint32_t *id = nullptr;                    // original (caller) index
+    // resident-state integration arrays
+    double *vpx = nullptr, *vpy = nullptr, *vpz = nullptr, *up = nullptr;
+    // FP32-pair mode
+    float *fx = nullptr, *fy = nullptr, *fz = nullptr;
+};
+
+struct Timer {
+    bool on = false;
+    double ms[3] = {0, 0, 0};
+    int64_t launches[3] = {0, 0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[3];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+};
+
+} // namespace sph
+
+struct sph_ctx {
+    sph_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t budget = 0;
+    size_t bytes = 0;
+    std::string err;
+
+    // capacity of the per-particle buffers
+    int64_t ncap = 0;
+    int64_t n = 0;
+    std::vector<void *> allocs;          // everything sized by ncap
+
+    // build
+    uint64_t *keys[2] = {nullptr, nullptr};
+    uint32_t *vals[2] = {nullptr, nullptr};
+    uint32_t *hist = nullptr;
+    int64_t hist_cap = 0;
+    uint32_t *perm = nullptr;            // sorted position -> source index
+    double *d_box = nullptr;             // [lo0..2, hi0..2] on device
+    double *d_part = nullptr;            // reduction partials
+    sph::Node *nodes = nullptr;
+    int64_t node_cap = 0;
+    sph::TreeInfo tree{};
+    sph::Box box{};
+
+    sph::Sorted s;       // working / resident arrays
+    sph::Sorted t;       // alternate buffers for re-sorting the resident state
+
+    // identity of the arrays the current structure was built from
+    const double *built_x = nullptr;
+    int64_t built_n = -1;
+    bool built = false;
+
+    // resident state
+    bool resident = false;
+    double *d_scal = nullptr;   // [0] dt_next [1] dt_last [2] time [3] KE [4] TE [5..7] P
+    int64_t *d_counts = nullptr;// [0] density pairs [1] force pairs
+    double *h_scal = nullptr;   // pinned mirror
+    double *dt_used_out = nullptr;
+    int64_t steps = 0;
+
+    int32_t *d_status = nullptr;
+    int32_t *h_status = nullptr;   // pinned mirror
+
+    sph::Timer timer;
+};
+
+namespace sph {
+
+// ---- host helpers (api.hip) --------------------------------------------------
+sph_status fail(sph_ctx *c, sph_status s, const std::string &msg);
+sph_status hip_check(sph_ctx *c, hipError_t e, const char *what);
+sph_status ensure_capacity(sph_ctx *c, int64_t n);
+
+// ---- build.hip ---------------------------------------------------------------
+// Bounding box, keys, sort: fills c->perm (sorted -> source) for n positions.
+sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y,
+                       const double *z);
+// Gather `count` arrays through c->perm: dst[k] = src[perm[k]].
+struct GatherList {
+    int32_t count;
+    int32_t kind[24];        // 0: double, 1: uint32, 2: float
+    const void *src[24];
+    void *dst[24];
+};
+sph_status gather(sph_ctx *c, int64_t n, const GatherList &g, bool identity_src_index);
+// Leaf boxes and tree over c->s.{x,y,z,h}; FP32 offsets when requested.
+sph_status build_tree(sph_ctx *c, int64_t n);
+// Per-particle force record (A, c, hinv) from rho, omega, u.
+sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted);
+sph_status iota(sph_ctx *c, int64_t n, uint32_t *v);
+
+// ---- pairs.hip ---------------------------------------------------------------
+sph_status run_density(sph_ctx *c, int64_t n);
+sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy,
+                      const double *vz);
+sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_sorted,
+                          const int64_t *offsets_sorted, int32_t *idx, int64_t cap);
+
+// ---- step.hip ----------------------------------------------------------------
+// scatter sorted arrays back to caller order through c->perm
+struct ScatterList {
+    int32_t count;
+    int32_t kind[24];
+    const void *src[24];
+    void *dst[24];
+};
+sph_status scatter(sph_ctx *c, int64_t n, const ScatterList &s, const uint32_t *index);
+sph_status eos_scatter(sph_ctx *c, int64_t n, const uint32_t *index, const double *u_caller,
+                       double *P, double *cs);
+sph_status kick_drift(sph_ctx *c, int64_t n, double dt_host);
+sph_status closing_kick(sph_ctx *c, int64_t n, double dt_host);
+sph_status reduce_dt(sph_ctx *c, int64_t n);
+sph_status reduce_diag(sph_ctx *c, int64_t n);
+// exclusive prefix sum in place over a[0..n], treating a[n] as 0 on input
+sph_status scan_offsets(sph_ctx *c, int64_t n, int64_t *a);
+
+// timing
+void timer_begin(sph_ctx *c, int which, hipEvent_t *b, hipEvent_t *e);
+void timer_end(sph_ctx *c, int which, hipEvent_t b, hipEvent_t e);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+} // namespace sph

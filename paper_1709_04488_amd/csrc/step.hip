@@ -1,0 +1,281 @@
+// Elementwise and reduction kernels: scatter back to caller order, equation
+// of state on output, kick-drift-kick leapfrog (eqs. EQN:LFKDK1, EQN:LFKDK2),
+// global CFL step min_i dt_i (eq. EQN:SPH_DT) and conserved-quantity sums.
+// All are HBM-bound streams over SoA arrays.
+#include "sph_internal.hpp"
+
+namespace sph {
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 1024;
+constexpr int kRedVals = 8;
+
+__global__ __launch_bounds__(256) void k_scatter(int64_t n, const uint32_t *__restrict__ index,
+                                                 ScatterList s)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int64_t dst = index[k];
+    for (int a = 0; a < s.count; a++) {
+        switch (s.kind[a]) {
+        case 0: ((double *)s.dst[a])[dst] = ((const double *)s.src[a])[k]; break;
+        case 1: ((uint32_t *)s.dst[a])[dst] = ((const uint32_t *)s.src[a])[k]; break;
+        default: ((float *)s.dst[a])[dst] = ((const float *)s.src[a])[k]; break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_eos_scatter(int64_t n, double gamma,
+                                                     const uint32_t *__restrict__ index,
+                                                     const double *__restrict__ rho,
+                                                     const double *__restrict__ u_caller,
+                                                     double *__restrict__ P, double *__restrict__ cs)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int64_t d = index[k];
+    double Pk = (gamma - 1.0) * rho[k] * u_caller[d];
+    if (P) P[d] = Pk;
+    if (cs) cs[d] = sqrt(gamma * Pk / rho[k]);
+}
+
+struct KdkArgs {
+    int64_t n;
+    Box box;
+    double dt_host;
+    double *scal;   // [0] dt_next, [1] dt_last, [2] time
+    double *x, *y, *z, *vx, *vy, *vz, *u;
+    const double *ax, *ay, *az, *du;
+    double *vpx, *vpy, *vpz, *up;
+};
+
+__device__ inline double wrap(double q, double lo, double L)
+{
+    if (q >= lo + L) q -= L;
+    else if (q < lo) q += L;
+    return q;
+}
+
+// v_1/2 = v + a dt/2, u_1/2 = u + du dt/2, x += v_1/2 dt (wrapped),
+// predictor v* = v_1/2 + a dt/2, u* = u_1/2 + du dt/2.
+__global__ __launch_bounds__(256) void k_kick_drift(KdkArgs K)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const double dt = K.dt_host > 0.0 ? K.dt_host : K.scal[0];
+    if (k == 0) {
+        K.scal[1] = dt;
+        K.scal[2] += dt;
+    }
+    if (k >= K.n) return;
+    const double hd = 0.5 * dt;
+    double vh[3] = {K.vx[k] + hd * K.ax[k], K.vy[k] + hd * K.ay[k], K.vz[k] + hd * K.az[k]};
+    double uh = K.u[k] + hd * K.du[k];
+    double *pos[3] = {K.x, K.y, K.z};
+    for (int a = 0; a < 3; a++) {
+        double q = pos[a][k] + dt * vh[a];
+        if (K.box.periodic) q = wrap(q, K.box.lo[a], K.box.len[a]);
+        pos[a][k] = q;
+    }
+    K.vx[k] = vh[0]; K.vy[k] = vh[1]; K.vz[k] = vh[2];
+    K.u[k] = uh;
+    K.vpx[k] = vh[0] + hd * K.ax[k];
+    K.vpy[k] = vh[1] + hd * K.ay[k];
+    K.vpz[k] = vh[2] + hd * K.az[k];
+    K.up[k] = uh + hd * K.du[k];
+}
+
+// v = v_1/2 + a' dt/2, u = u_1/2 + du' dt/2 with the dt of the opening kick.
+__global__ __launch_bounds__(256) void k_closing_kick(KdkArgs K)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= K.n) return;
+    const double hd = 0.5 * K.scal[1];
+    K.vx[k] += hd * K.ax[k];
+    K.vy[k] += hd * K.ay[k];
+    K.vz[k] += hd * K.az[k];
+    K.u[k] += hd * K.du[k];
+}
+
+// min over dt_i -> scal[0]
+__global__ __launch_bounds__(kRedThreads) void k_min_partial(int64_t n, const double *__restrict__ v,
+                                                             double *__restrict__ part)
+{
+    double mn = INFINITY;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        mn = fmin(mn, v[k]);
+    __shared__ double sh[kRedThreads];
+    sh[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_min_final(int nb, const double *__restrict__ part,
+                                                           double *__restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    double mn = INFINITY;
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) mn = fmin(mn, part[b]);
+    sh[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Sums in a fixed order (grid-stride per thread, fixed tree per block, fixed
+// order over blocks), so they are reproducible bit for bit.
+//   [0] 1/2 m v^2  [1] m u  [2..4] m v  [5] sum nngb  [6] sum nforce
+__global__ __launch_bounds__(kRedThreads) void k_diag_partial(int64_t n, const double *__restrict__ m,
+                                                              const double *__restrict__ vx,
+                                                              const double *__restrict__ vy,
+                                                              const double *__restrict__ vz,
+                                                              const double *__restrict__ u,
+                                                              const int32_t *__restrict__ nngb,
+                                                              const int32_t *__restrict__ nforce,
+                                                              double *__restrict__ part)
+{
+    double acc[kRedVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        double mk = m[k];
+        acc[0] += 0.5 * mk * ((vx[k] * vx[k] + vy[k] * vy[k]) + vz[k] * vz[k]);
+        acc[1] += mk * u[k];
+        acc[2] += mk * vx[k];
+        acc[3] += mk * vy[k];
+        acc[4] += mk * vz[k];
+        acc[5] += (double)nngb[k];
+        acc[6] += (double)nforce[k];
+    }
+    __shared__ double sh[kRedVals][kRedThreads];
+    for (int a = 0; a < kRedVals; a++) sh[a][threadIdx.x] = acc[a];
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < kRedVals; a++) sh[a][threadIdx.x] += sh[a][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < kRedVals) part[blockIdx.x * kRedVals + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void k_diag_final(int nb, const double *__restrict__ part,
+                                                   double *__restrict__ scal,
+                                                   int64_t *__restrict__ counts)
+{
+    if (threadIdx.x >= kRedVals) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; b++) s += part[b * kRedVals + threadIdx.x];
+    if (threadIdx.x < 5) scal[3 + threadIdx.x] = s;
+    else if (threadIdx.x < 7) counts[threadIdx.x - 5] = (int64_t)s;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_offsets(int64_t n, int64_t *__restrict__ a)
+{
+    __shared__ int64_t sums[1024];
+    const int t = threadIdx.x;
+    const int64_t total = n + 1;
+    const int64_t chunk = (total + 1023) / 1024;
+    const int64_t s0 = t * chunk, s1 = s0 + chunk < total ? s0 + chunk : total;
+    int64_t s = 0;
+    for (int64_t k = s0; k < s1; k++) s += k < n ? a[k] : 0;
+    sums[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        int64_t v = t >= d ? sums[t - d] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    int64_t run = sums[t] - s;
+    for (int64_t k = s0; k < s1; k++) {
+        int64_t v = k < n ? a[k] : 0;
+        a[k] = run;
+        run += v;
+    }
+}
+
+inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+KdkArgs kdk_args(sph_ctx *c, int64_t n, double dt_host)
+{
+    KdkArgs K{};
+    K.n = n;
+    K.box = c->box;
+    K.dt_host = dt_host;
+    K.scal = c->d_scal;
+    K.x = c->s.x; K.y = c->s.y; K.z = c->s.z;
+    K.vx = c->s.vx; K.vy = c->s.vy; K.vz = c->s.vz; K.u = c->s.u;
+    K.ax = c->s.ax; K.ay = c->s.ay; K.az = c->s.az; K.du = c->s.du;
+    K.vpx = c->s.vpx; K.vpy = c->s.vpy; K.vpz = c->s.vpz; K.up = c->s.up;
+    return K;
+}
+
+} // namespace
+
+sph_status scatter(sph_ctx *c, int64_t n, const ScatterList &s, const uint32_t *index)
+{
+    if (n == 0 || s.count == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, index, s);
+    return hip_check(c, hipGetLastError(), "scatter");
+}
+
+sph_status eos_scatter(sph_ctx *c, int64_t n, const uint32_t *index, const double *u_caller,
+                       double *P, double *cs)
+{
+    if (n == 0 || (!P && !cs)) return SPH_OK;
+    hipLaunchKernelGGL(k_eos_scatter, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n,
+                       c->p.gamma, index, c->s.rho, u_caller, P, cs);
+    return hip_check(c, hipGetLastError(), "eos_scatter");
+}
+
+sph_status kick_drift(sph_ctx *c, int64_t n, double dt_host)
+{
+    KdkArgs K = kdk_args(c, n, dt_host);
+    hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(n > 0 ? n : 1, 256)), dim3(256), 0, c->stream, K);
+    return hip_check(c, hipGetLastError(), "kick_drift");
+}
+
+sph_status closing_kick(sph_ctx *c, int64_t n, double dt_host)
+{
+    if (n == 0) return SPH_OK;
+    KdkArgs K = kdk_args(c, n, dt_host);
+    hipLaunchKernelGGL(k_closing_kick, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, K);
+    return hip_check(c, hipGetLastError(), "closing_kick");
+}
+
+sph_status reduce_dt(sph_ctx *c, int64_t n)
+{
+    if (n == 0) return SPH_OK;
+    int nb = (int)std::min<int64_t>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
+    hipLaunchKernelGGL(k_min_partial, dim3(nb), dim3(kRedThreads), 0, c->stream, n, c->s.dt,
+                       c->d_part);
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kRedThreads), 0, c->stream, nb, c->d_part,
+                       c->d_scal);
+    return hip_check(c, hipGetLastError(), "reduce_dt");
+}
+
+sph_status scan_offsets(sph_ctx *c, int64_t n, int64_t *a)
+{
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, c->stream, n, a);
+    return hip_check(c, hipGetLastError(), "scan_offsets");
+}
+
+sph_status reduce_diag(sph_ctx *c, int64_t n)
+{
+    if (n == 0) return SPH_OK;
+    int nb = (int)std::min<int64_t>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
+    hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(kRedThreads), 0, c->stream, n, c->s.m,
+                       c->s.vx, c->s.vy, c->s.vz, c->s.u, c->s.nngb, c->s.nforce, c->d_part);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, c->stream, nb, c->d_part, c->d_scal,
+                       c->d_counts);
+    return hip_check(c, hipGetLastError(), "reduce_diag");
+}
+
+} // namespace sph

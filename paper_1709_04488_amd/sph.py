@@ -1,0 +1,333 @@
+"""ctypes binding of libsph.so (see include/sph.h).
+
+Argument marshalling only: PyTorch supplies device memory (float64 / int32
+CUDA tensors) and the HIP stream; every step of the hot path runs in the HIP
+kernels of libsph.  There is no fallback: if the library is missing or the
+tensors are not on the GPU, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsph.so")
+
+SPH_OK, SPH_EINVAL, SPH_ENOMEM, SPH_EDEVICE, SPH_ENOTCONVERGED = 0, -1, -2, -3, -4
+SPH_ESTENCIL, SPH_ENONFINITE, SPH_EBUDGET, SPH_ECAP, SPH_ESTATE = -5, -6, -7, -8, -9
+SPH_FP64, SPH_FP32_PAIR = 0, 1
+
+STATUS_NAMES = {0: "SPH_OK", -1: "SPH_EINVAL", -2: "SPH_ENOMEM", -3: "SPH_EDEVICE",
+                -4: "SPH_ENOTCONVERGED", -5: "SPH_ESTENCIL", -6: "SPH_ENONFINITE",
+                -7: "SPH_EBUDGET", -8: "SPH_ECAP", -9: "SPH_ESTATE"}
+
+EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream", "sph_set_params",
+            "sph_build_cells", "sph_density", "sph_forces", "sph_upload_state", "sph_step",
+            "sph_download_state", "sph_state_info", "sph_neighbours", "sph_sync",
+            "sph_last_error", "sph_device_bytes", "sph_enable_kernel_timing", "sph_kernel_times"]
+
+
+class SphError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("alpha_av", ctypes.c_double), ("beta_av", ctypes.c_double),
+                ("c_cfl", ctypes.c_double), ("h_rtol", ctypes.c_double),
+                ("h_max_iter", ctypes.c_int32), ("periodic", ctypes.c_int32),
+                ("box_lo", ctypes.c_double * 3), ("box_hi", ctypes.c_double * 3),
+                ("precision", ctypes.c_int32), ("leaf_size", ctypes.c_int32)]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int32)
+
+
+class _Particles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in (
+        "x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "rho", "omega", "pressure", "cs",
+        "ax", "ay", "az", "dudt", "vsig", "dt", "nngb", "nforce")]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("time", ctypes.c_double), ("dt_last", ctypes.c_double),
+                ("dt_next", ctypes.c_double), ("kinetic", ctypes.c_double),
+                ("thermal", ctypes.c_double), ("momentum", ctypes.c_double * 3),
+                ("steps", ctypes.c_int64), ("n_dens_pairs", ctypes.c_int64),
+                ("n_force_pairs", ctypes.c_int64), ("nr_iter_max", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load() -> ctypes.CDLL:
+    """Load libsph.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1709_04488_amd.build_lib.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER(_Params)
+    PS = ctypes.POINTER(_Particles)
+    sig = {
+        "sph_default_params": (None, [P]),
+        "sph_create": (ctypes.c_int, [ctypes.POINTER(vp), P, vp, ctypes.c_size_t]),
+        "sph_destroy": (ctypes.c_int, [vp]),
+        "sph_set_stream": (ctypes.c_int, [vp, vp]),
+        "sph_set_params": (ctypes.c_int, [vp, P]),
+        "sph_build_cells": (ctypes.c_int, [vp, PS]),
+        "sph_density": (ctypes.c_int, [vp, PS]),
+        "sph_forces": (ctypes.c_int, [vp, PS]),
+        "sph_upload_state": (ctypes.c_int, [vp, PS]),
+        "sph_step": (ctypes.c_int, [vp, d, ctypes.POINTER(d)]),
+        "sph_download_state": (ctypes.c_int, [vp, PS]),
+        "sph_state_info": (ctypes.c_int, [vp, ctypes.POINTER(_Stats)]),
+        "sph_neighbours": (ctypes.c_int, [vp, PS, i32, vp, vp, i64]),
+        "sph_sync": (ctypes.c_int, [vp]),
+        "sph_last_error": (ctypes.c_char_p, [vp]),
+        "sph_device_bytes": (ctypes.c_size_t, [vp]),
+        "sph_enable_kernel_timing": (ctypes.c_int, [vp, i32]),
+        "sph_kernel_times": (ctypes.c_int, [vp, i32, ctypes.POINTER(d), ctypes.POINTER(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+@dataclass
+class Params:
+    """Method parameters (sph_params).  Defaults as sph_default_params."""
+    eta: float = 1.2
+    gamma: float = 5.0 / 3.0
+    alpha: float = 1.0
+    beta: float = 2.0
+    ccfl: float = 0.2
+    h_rtol: float = 1e-12
+    h_max_iter: int = 50
+    periodic: bool = True
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+    precision: int = SPH_FP64
+    leaf_size: int = 16
+
+    @classmethod
+    def from_setup(cls, setup: dict, **kw) -> "Params":
+        keys = ("eta", "gamma", "alpha", "beta", "ccfl", "periodic", "lo", "hi")
+        return cls(**{k: setup[k] for k in keys if k in setup}, **kw)
+
+    def c(self) -> _Params:
+        p = _Params()
+        p.eta, p.gamma, p.alpha_av, p.beta_av, p.c_cfl = (self.eta, self.gamma, self.alpha,
+                                                          self.beta, self.ccfl)
+        p.h_rtol, p.h_max_iter = self.h_rtol, int(self.h_max_iter)
+        p.periodic = 1 if self.periodic else 0
+        for k in range(3):
+            p.box_lo[k] = float(self.lo[k])
+            p.box_hi[k] = float(self.hi[k])
+        p.precision = int(self.precision)
+        p.leaf_size = int(self.leaf_size)
+        return p
+
+
+FIELDS_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "rho", "omega", "pressure", "cs",
+              "ax", "ay", "az", "dudt", "vsig", "dt")
+FIELDS_I32 = ("nngb", "nforce")
+
+
+@dataclass
+class Particles:
+    """Device arrays of one particle set (caller index order)."""
+    t: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.t["x"].numel())
+
+    @classmethod
+    def from_host(cls, arrays: dict, device="cuda", outputs: bool = True) -> "Particles":
+        t = {}
+        for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h"):
+            if k in arrays:
+                t[k] = torch.as_tensor(arrays[k], dtype=torch.float64).to(device).contiguous()
+        n = t["x"].numel()
+        if outputs:
+            for k in FIELDS_F64:
+                if k not in t:
+                    t[k] = torch.zeros(n, dtype=torch.float64, device=device)
+            for k in FIELDS_I32:
+                t[k] = torch.zeros(n, dtype=torch.int32, device=device)
+        return cls(t)
+
+    def c(self, omit=()) -> _Particles:
+        ps = _Particles()
+        ps.n = self.n
+        for k in FIELDS_F64 + FIELDS_I32:
+            v = self.t.get(k)
+            if v is None or k in omit:
+                setattr(ps, k, None)
+                continue
+            if not v.is_cuda:
+                raise ValueError(f"{k} must be a GPU tensor")
+            want = torch.int32 if k in FIELDS_I32 else torch.float64
+            if v.dtype != want or not v.is_contiguous() or v.numel() != ps.n:
+                raise ValueError(f"{k} must be a contiguous {want} tensor of {ps.n} elements")
+            setattr(ps, k, v.data_ptr())
+        return ps
+
+    def host(self, *keys) -> dict:
+        return {k: self.t[k].detach().cpu().numpy() for k in (keys or self.t.keys())}
+
+
+class Context:
+    """One sph_ctx bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, params: Params = None, stream: torch.cuda.Stream = None,
+                 budget_bytes: int = 0):
+        self.lib = load()
+        self.params = params or Params()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._p = self.params.c()
+        h = ctypes.c_void_p()
+        rc = self.lib.sph_create(ctypes.byref(h), ctypes.byref(self._p),
+                                 ctypes.c_void_p(self.stream.cuda_stream), int(budget_bytes))
+        if rc != SPH_OK or not h.value:
+            raise SphError(rc, "sph_create failed")
+        self.h = h
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.sph_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc: int, what: str):
+        if rc != SPH_OK:
+            msg = self.lib.sph_last_error(self.h)
+            raise SphError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def set_params(self, params: Params):
+        self.params = params
+        self._p = params.c()
+        self._check(self.lib.sph_set_params(self.h, ctypes.byref(self._p)), "sph_set_params")
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        self._check(self.lib.sph_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)),
+                    "sph_set_stream")
+
+    def build_cells(self, p: Particles):
+        ps = p.c()
+        self._check(self.lib.sph_build_cells(self.h, ctypes.byref(ps)), "sph_build_cells")
+
+    def density(self, p: Particles, eos: bool = True):
+        ps = p.c(omit=() if eos else ("pressure", "cs"))
+        self._check(self.lib.sph_density(self.h, ctypes.byref(ps)), "sph_density")
+
+    def forces(self, p: Particles):
+        ps = p.c(omit=("pressure", "cs"))
+        self._check(self.lib.sph_forces(self.h, ctypes.byref(ps)), "sph_forces")
+
+    def evaluate(self, p: Particles):
+        """Density (h solve) then forces: one full evaluation."""
+        self.density(p)
+        self.forces(p)
+
+    def upload_state(self, p: Particles):
+        ps = p.c()
+        self._check(self.lib.sph_upload_state(self.h, ctypes.byref(ps)), "sph_upload_state")
+
+    def step(self, dt: float = 0.0):
+        self._check(self.lib.sph_step(self.h, float(dt), None), "sph_step")
+
+    def download_state(self, p: Particles):
+        ps = p.c()
+        self._check(self.lib.sph_download_state(self.h, ctypes.byref(ps)), "sph_download_state")
+
+    def state_info(self) -> dict:
+        st = _Stats()
+        self._check(self.lib.sph_state_info(self.h, ctypes.byref(st)), "sph_state_info")
+        return {"time": st.time, "dt_last": st.dt_last, "dt_next": st.dt_next,
+                "kinetic": st.kinetic, "thermal": st.thermal,
+                "momentum": tuple(st.momentum), "steps": st.steps,
+                "n_dens_pairs": st.n_dens_pairs, "n_force_pairs": st.n_force_pairs,
+                "nr_iter_max": st.nr_iter_max}
+
+    def neighbours(self, p: Particles, mode: int, cap: int = None):
+        """CSR lists at the given h -> (offsets int64[n+1], idx int32) on the device."""
+        n = p.n
+        dev = p.t["x"].device
+        offsets = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+        if cap is None:
+            cap = max(1, 128 * n)
+        idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        ps = p.c()
+        rc = self.lib.sph_neighbours(self.h, ctypes.byref(ps), int(mode),
+                                     ctypes.c_void_p(offsets.data_ptr()),
+                                     ctypes.c_void_p(idx.data_ptr()), int(cap))
+        if rc == SPH_ECAP:
+            total = int(offsets[-1].item())
+            return self.neighbours(p, mode, cap=total)
+        self._check(rc, "sph_neighbours")
+        return offsets, idx[:int(offsets[-1].item())]
+
+    def sync(self):
+        self._check(self.lib.sph_sync(self.h), "sph_sync")
+
+    def sync_status(self) -> int:
+        """sph_sync without raising: returns the status code."""
+        return int(self.lib.sph_sync(self.h))
+
+    def last_error(self) -> str:
+        return self.lib.sph_last_error(self.h).decode()
+
+    def device_bytes(self) -> int:
+        return int(self.lib.sph_device_bytes(self.h))
+
+    def enable_kernel_timing(self, on: bool = True):
+        self._check(self.lib.sph_enable_kernel_timing(self.h, 1 if on else 0), "timing")
+
+    def kernel_times(self, which: int):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        self._check(self.lib.sph_kernel_times(self.h, int(which), ctypes.byref(ms),
+                                              ctypes.byref(cnt)), "sph_kernel_times")
+        return ms.value, cnt.value
+
+    def reset_kernel_times(self):
+        for w in range(3):
+            self._check(self.lib.sph_kernel_times(self.h, w, None, None), "sph_kernel_times")
+
+
+def default_params_from_library() -> dict:
+    p = _Params()
+    load().sph_default_params(ctypes.byref(p))
+    return {f: (tuple(getattr(p, f)) if f in ("box_lo", "box_hi") else getattr(p, f))
+            for f, _ in _Params._fields_}

@@ -1,0 +1,274 @@
+"""Parity of the HIP path (through the C ABI) with the brute-force oracle.
+
+Tolerances (FP64 mode): neighbour lists and neighbour counts bit-exact;
+h, rho, omega, P, c_s, v_sig, dt within 1e-10 relative; a and du/dt within
+1e-10 of the per-particle scale S_i = sum_j |pair term| (a ~ 0 by
+cancellation on near-uniform sets makes a plain relative error meaningless).
+FP32-pair mode: h, rho, omega, v_sig, dt within 1e-5 relative, a and du/dt
+within 1e-4 of S_i, neighbour-count differences only from pairs within
+1e-5 of the kernel edge.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1709_04488_amd import workloads as W  # noqa: E402
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-5
+FP32_ATOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def sph():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_04488_amd import sph as s
+    s.load()
+    return s
+
+
+def _oracle_eval(orc, w, **over):
+    a = w.arrays
+    p = orc.Params(**{**w.setup, **over})
+    return orc.evaluate(p, a["x"], a["y"], a["z"], a["vx"], a["vy"], a["vz"], a["m"], a["u"], a["h"])
+
+
+def _gpu_eval(sph, w, precision=0, leaf_size=16, **over):
+    params = sph.Params.from_setup({**w.setup, **over}, precision=precision, leaf_size=leaf_size)
+    with sph.Context(params) as ctx:
+        p = sph.Particles.from_host(w.arrays)
+        ctx.evaluate(p)
+        ctx.sync()
+        return p.host()
+
+
+def _check(out, ref, tol=FP64_TOL, atol=FP64_TOL, counts_exact=True, label=""):
+    for k in ("h", "rho", "omega", "pressure", "cs", "vsig", "dt"):
+        rk = "P" if k == "pressure" else k
+        err = np.max(np.abs(out[k] / ref[rk] - 1.0))
+        assert err < tol, (label, k, err)
+    for k in ("ax", "ay", "az"):
+        err = np.max(np.abs(out[k] - ref[k]) / ref["scale_a"])
+        assert err < atol, (label, k, err)
+    err = np.max(np.abs(out["dudt"] - ref["dudt"]) / ref["scale_u"])
+    assert err < atol, (label, "dudt", err)
+    if counts_exact:
+        assert np.array_equal(out["nngb"], ref["nngb"]), label
+        assert np.array_equal(out["nforce"], ref["nforce"]), label
+
+
+def test_config0_full_parity_fp64(sph, orc):
+    w = W.config0()
+    print("case: config0 N=%d fp64" % w.n, flush=True)
+    ref = _oracle_eval(orc, w)
+    out = _gpu_eval(sph, w)
+    _check(out, ref, label="config0")
+
+
+@pytest.mark.parametrize("leaf", [8, 16, 32])
+def test_leaf_sizes_ragged_periodic(sph, orc, leaf):
+    # random (Poisson) positions, N not a multiple of any leaf size
+    rng = np.random.default_rng(77)
+    n = 3001
+    a = {"x": rng.uniform(0, 1, n), "y": rng.uniform(0, 1, n), "z": rng.uniform(0, 1, n),
+         "vx": rng.normal(0, 0.3, n), "vy": rng.normal(0, 0.3, n), "vz": rng.normal(0, 0.3, n),
+         "m": np.full(n, 1.0 / n), "u": rng.uniform(0.5, 1.5, n), "h": np.full(n, 0.08)}
+    w = W.Workload("poisson3001", a, W.default_setup())
+    print("case: poisson N=3001 leaf=%d" % leaf, flush=True)
+    ref = _oracle_eval(orc, w)
+    out = _gpu_eval(sph, w, leaf_size=leaf)
+    _check(out, ref, label=f"leaf{leaf}")
+
+
+def test_open_boundary_plummer(sph, orc):
+    w = W.plummer(2500, seed=31)
+    print("case: plummer N=2500 open", flush=True)
+    ref = _oracle_eval(orc, w)
+    out = _gpu_eval(sph, w)
+    _check(out, ref, label="plummer")
+
+
+def test_blob_in_lattice_small(sph, orc):
+    w = W.blob_in_lattice(14, seed=5)
+    print("case: blob N=%d" % w.n, flush=True)
+    ref = _oracle_eval(orc, w)
+    out = _gpu_eval(sph, w)
+    _check(out, ref, label="blob")
+
+
+def test_smallest_periodic_box(sph, orc):
+    # 5^3 lattice: 2h ~ 0.48 L, leaves span the box, per-pair minimum image
+    w = W.jittered_lattice(5, seed=9)
+    print("case: lattice5 periodic", flush=True)
+    ref = _oracle_eval(orc, w)
+    out = _gpu_eval(sph, w)
+    _check(out, ref, label="lattice5")
+
+
+@pytest.mark.parametrize("n", [6, 7, 17, 64])
+def test_tiny_open_sets(sph, orc, n):
+    rng = np.random.default_rng(n)
+    a = {"x": rng.normal(0, 1, n), "y": rng.normal(0, 1, n), "z": rng.normal(0, 1, n),
+         "vx": rng.normal(0, 1, n), "vy": rng.normal(0, 1, n), "vz": rng.normal(0, 1, n),
+         "m": np.full(n, 1.0), "u": np.full(n, 1.0), "h": np.full(n, 1.0)}
+    w = W.Workload(f"tiny{n}", a, W.default_setup(periodic=False))
+    print("case: tiny open N=%d" % n, flush=True)
+    ref = _oracle_eval(orc, w)
+    out = _gpu_eval(sph, w)
+    _check(out, ref, label=f"tiny{n}")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("case", ["config0", "plummer"])
+def test_neighbour_lists_bit_exact(sph, orc, mode, case):
+    w = W.config0() if case == "config0" else W.plummer(3000, seed=8)
+    a = w.arrays
+    p = orc.Params(**w.setup)
+    h = orc.density(p, a["x"], a["y"], a["z"], a["m"], a["h"])["h"]
+    # perturb h so that mode 1 differs from mode 0
+    h = h * np.random.default_rng(3).uniform(0.8, 1.25, w.n)
+    roff, ridx = orc.neighbours(p, a["x"], a["y"], a["z"], h, mode)
+    print("case: neighbours %s mode %d" % (case, mode), flush=True)
+    with sph.Context(sph.Params.from_setup(w.setup)) as ctx:
+        pp = sph.Particles.from_host({**a, "h": h})
+        off, idx = ctx.neighbours(pp, mode)
+        off = off.cpu().numpy()
+        idx = idx.cpu().numpy()
+    assert np.array_equal(off, roff)
+    assert np.array_equal(idx, ridx)
+
+
+def test_momentum_and_energy_identity_on_gpu_outputs(sph):
+    w = W.config0()
+    out = _gpu_eval(sph, w)
+    a = w.arrays
+    m = a["m"]
+    scale = np.sum(m * (np.abs(out["ax"]) + np.abs(out["ay"]) + np.abs(out["az"])))
+    for k in ("ax", "ay", "az"):
+        assert abs(np.sum(m * out[k])) < 1e-12 * scale
+    e = np.sum(m * (a["vx"] * out["ax"] + a["vy"] * out["ay"] + a["vz"] * out["az"] + out["dudt"]))
+    assert abs(e) < 1e-12 * np.sum(m * (np.abs(out["dudt"]) + scale))
+
+
+def test_deterministic_bitwise(sph):
+    w = W.blob_in_lattice(12, seed=2)
+    o1 = _gpu_eval(sph, w)
+    o2 = _gpu_eval(sph, w)
+    for k in ("h", "rho", "ax", "ay", "az", "dudt", "vsig", "nngb", "nforce"):
+        assert np.array_equal(o1[k], o2[k]), k
+
+
+def test_empty_set_is_a_no_op(sph):
+    with sph.Context(sph.Params()) as ctx:
+        p = sph.Particles.from_host({k: np.zeros(0) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h")})
+        ctx.evaluate(p)
+        ctx.sync()
+
+
+def test_no_root_reports_not_converged(sph):
+    # 5 equal-mass particles in isolation: h^3 rho = eta^3 m has no root
+    rng = np.random.default_rng(0)
+    a = {k: rng.uniform(0, 1, 5) for k in ("x", "y", "z", "vx", "vy", "vz")}
+    a.update(m=np.full(5, 0.2), u=np.ones(5), h=np.full(5, 0.3))
+    with sph.Context(sph.Params(periodic=False, h_max_iter=30)) as ctx:
+        p = sph.Particles.from_host(a)
+        ctx.density(p)
+        rc = ctx.sync_status()
+        assert rc == sph.SPH_ENOTCONVERGED, ctx.last_error()
+
+
+def test_box_too_small_reports_stencil(sph):
+    w = W.lattice(2)
+    with sph.Context(sph.Params()) as ctx:
+        p = sph.Particles.from_host(w.arrays)
+        ctx.density(p)
+        rc = ctx.sync_status()
+        assert rc == sph.SPH_ESTENCIL, ctx.last_error()
+
+
+def test_nan_input_reports_nonfinite(sph):
+    w = W.jittered_lattice(6, seed=1)
+    a = dict(w.arrays)
+    a["x"] = a["x"].copy()
+    a["x"][7] = np.nan
+    with sph.Context(sph.Params()) as ctx:
+        p = sph.Particles.from_host(a)
+        ctx.density(p)
+        rc = ctx.sync_status()
+        assert rc == sph.SPH_ENONFINITE, ctx.last_error()
+
+
+def test_bad_arguments_are_rejected(sph):
+    with pytest.raises(sph.SphError) as e:
+        sph.Context(sph.Params(leaf_size=12))
+    assert e.value.code == sph.SPH_EINVAL
+    with sph.Context(sph.Params()) as ctx:
+        p = sph.Particles.from_host(W.jittered_lattice(6, seed=1).arrays)
+        p.t["rho"] = None
+        with pytest.raises(sph.SphError) as e:
+            ctx.density(p)
+        assert e.value.code == sph.SPH_EINVAL
+        with pytest.raises(sph.SphError) as e:
+            ctx.step(0.0)
+        assert e.value.code == sph.SPH_ESTATE
+
+
+def test_budget_is_enforced(sph):
+    w = W.jittered_lattice(10, seed=1)
+    with sph.Context(sph.Params(), budget_bytes=100_000) as ctx:
+        p = sph.Particles.from_host(w.arrays)
+        with pytest.raises(sph.SphError) as e:
+            ctx.density(p)
+        assert e.value.code == sph.SPH_EBUDGET
+
+
+def test_kdk_steps_match_oracle(sph, orc):
+    w = W.jittered_lattice(10, seed=21)
+    a = w.arrays
+    nsteps = 10
+    st, energy, dts = orc.kdk(orc.Params(**w.setup), a["x"], a["y"], a["z"], a["vx"], a["vy"],
+                              a["vz"], a["m"], a["u"], a["h"], nsteps, 0.0)
+    print("case: kdk N=%d steps=%d" % (w.n, nsteps), flush=True)
+    with sph.Context(sph.Params.from_setup(w.setup)) as ctx:
+        p = sph.Particles.from_host(a)
+        ctx.upload_state(p)
+        for _ in range(nsteps):
+            ctx.step(0.0)
+        ctx.sync()
+        info = ctx.state_info()
+        q = sph.Particles.from_host(a)
+        ctx.download_state(q)
+        ctx.sync()
+        out = q.host()
+    for k in ("x", "y", "z"):
+        d = out[k] - st[k]
+        d -= np.round(d)
+        assert np.max(np.abs(d)) < 1e-10, k
+    for k in ("vx", "vy", "vz", "u", "h"):
+        assert np.max(np.abs(out[k] - st[k])) < 1e-8 * max(1.0, np.max(np.abs(st[k]))), k
+    assert info["time"] == pytest.approx(np.sum(dts), rel=1e-9)
+    e = info["kinetic"] + info["thermal"]
+    assert e == pytest.approx(energy[-1], rel=1e-10)
+
+
+def test_fp32_pair_mode_tolerances(sph, orc):
+    for w in (W.config0(), W.plummer(3000, seed=12)):
+        print("case: fp32 %s" % w.name, flush=True)
+        ref = _oracle_eval(orc, w)
+        out = _gpu_eval(sph, w, precision=sph.SPH_FP32_PAIR)
+        _check(out, ref, tol=FP32_TOL, atol=FP32_ATOL, counts_exact=False, label="fp32 " + w.name)
+        dn = np.abs(out["nngb"] - ref["nngb"])
+        assert np.mean(dn) < 0.01 and np.max(dn) <= 1
+
+
+def test_fp32_pair_momentum_conserved(sph):
+    w = W.config0()
+    out = _gpu_eval(sph, w, precision=sph.SPH_FP32_PAIR)
+    m = w.arrays["m"]
+    scale = np.sum(m * (np.abs(out["ax"]) + np.abs(out["ay"]) + np.abs(out["az"])))
+    for k in ("ax", "ay", "az"):
+        assert abs(np.sum(m * out[k])) < 1e-12 * scale
