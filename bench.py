@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Throughput of the grad-h SPH hot path on one MI355X.
+
+One step = one full evaluation of a particle set through the C ABI: neighbour
+search (Morton keys, radix sort, gathers, leaf/box tree), the density loop
+with the Newton-Raphson h solve started from the input guess, the force loop,
+the per-particle and global CFL step, and the scatter back to caller order.
+The metric is neighbour interactions per second: density pairs (j != i,
+r < 2 h_i at the final h) plus force pairs (j != i, r < 2 max(h_i, h_j)) of
+one evaluation, divided by its wall time.  Inputs are resident in HBM before
+the timed region starts.
+
+Default workload: N = 128^3 = 2,097,152 particles, jittered lattice in the
+periodic unit box with 30 % redrawn from a Gaussian blob (sigma 0.05),
+u lognormal(0, 0.3), velocities N(0, 0.2^2), eta = 1.2, M4 kernel,
+alpha_AV = 1, beta_AV = 2, gamma = 5/3.  FP64 is the headline value; the
+FP32-pair mode is measured on the same set and reported beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "neighbour interactions/s (density+force) FP64 vs FP32; p50/p99 request latency"
+
+# Algorithmic work per interaction, counted from the pair formulas (each +, -,
+# *, /, sqrt counts one flop):
+#   density pair, per Newton-Raphson iteration: separation 3, r^2 5, sqrt 1,
+#     q 1, f 5, accumulate m f 2, q f' and m (3f + q f') accumulation 9  -> 26
+#   force pair: separation 3, r^2 5, sqrt 1, rhat 3, two kernel gradients
+#     9 + 9, v_ij and v.rhat 8, pressure term 4, du/dt term 3, signal speed 3,
+#     max 1, accumulation 7 -> 56; viscosity on approaching pairs +15, about
+#     half of all pairs for random velocities -> 64 on average
+DENS_FLOPS_PER_PAIR_ITER = 26
+FORCE_FLOPS_PER_PAIR = 64
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector FP64 / FP32 (FMA = 2)
+
+
+def workload(name: str):
+    from paper_1709_04488_amd import workloads as W
+    if name == "c0":
+        return W.config0()
+    if name == "c1":
+        return W.config1()
+    if name == "c2":
+        return W.config2()
+    if name.startswith("c1s"):
+        return W.config1(n_side=int(name[3:]))
+    raise ValueError(name)
+
+
+def run_gpu(w, precision: int, steps: int, warmup: int, leaf: int, warm_start: bool = False):
+    import torch
+    from paper_1709_04488_amd import sph
+
+    params = sph.Params.from_setup(w.setup, precision=precision, leaf_size=leaf)
+    ctx = sph.Context(params)
+    p = sph.Particles.from_host(w.arrays)
+    h0 = p.t["h"].clone()
+
+    def one():
+        if not warm_start:
+            p.t["h"].copy_(h0)
+        ctx.density(p)
+        ctx.forces(p)
+
+    for _ in range(warmup):
+        one()
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.enable_kernel_timing(True)
+    ctx.reset_kernel_times()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    info = ctx.state_info()
+    kt = {name: ctx.kernel_times(i) for i, name in enumerate(("density", "force", "build"))}
+    ctx.enable_kernel_timing(False)
+    ms = (t1 - t0) * 1e3 / steps
+    inter = info["n_dens_pairs"] + info["n_force_pairs"]
+    res = {"ms_per_step": ms, "interactions": inter, "value": inter / (ms * 1e-3), "info": info,
+           "kernel_ms": {k: (v[0] / max(v[1], 1)) for k, v in kt.items()},
+           "kernel_launches": {k: v[1] for k, v in kt.items()},
+           "device_bytes": ctx.device_bytes()}
+    ctx.close()
+    return res
+
+
+def roofline(res, prec: str):
+    info = res["info"]
+    km = res["kernel_ms"]
+    dens_flops = info["dens_pair_evals"] * DENS_FLOPS_PER_PAIR_ITER
+    force_flops = info["force_pair_evals"] * FORCE_FLOPS_PER_PAIR
+    cand = {"density": (dens_flops, km["density"]), "force": (force_flops, km["force"])}
+    name = max(cand, key=lambda k: cand[k][1])
+    flops, t_ms = cand[name]
+    achieved = flops / (t_ms * 1e-3) / 1e12 if t_ms > 0 else 0.0
+    peak = PEAK_TFLOPS[prec]
+    return {"bound": "alu", "kernel": name, "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "flops_per_launch": flops, "avg_launch_ms": round(t_ms, 4),
+            "other_kernel": {k: {"flops_per_launch": v[0], "avg_launch_ms": round(v[1], 4),
+                                 "achieved_tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 3) if v[1] > 0 else 0}
+                             for k, v in cand.items() if k != name}}
+
+
+def cpu_baseline(w, seconds: float):
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    p = oracle.Params(**w.setup)
+    rng = np.random.default_rng(2024)
+    t0 = time.perf_counter()
+    inter = 0
+    nd = nf = 0
+    while time.perf_counter() - t0 < seconds:
+        s = rng.choice(w.n, 32, replace=False)
+        r = oracle.sampled_evaluation(p, w.arrays, s, force_sample=s[:8])
+        inter += int(r.n_dens.sum() + r.n_force.sum())
+        nd += s.size
+        nf += 8
+    el = time.perf_counter() - t0
+    return {"value": inter / el, "unit": "interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{nd} density + {nf} force particles drawn at random from the same "
+                      f"{w.n}-particle set, each solved by brute force over all N "
+                      f"({el:.1f} s)"}
+
+
+def calib_copy(gib: float = 1.0, reps: int = 5):
+    """Plain copy of a known number of bytes (for scaling HBM counters)."""
+    import torch
+    n = int(gib * (1 << 30) // 8)
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8,
+                      "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c1", help="c0, c1 (default), c2 or c1s<n_side>")
+    ap.add_argument("--precision", default="both", choices=["fp64", "fp32", "both"])
+    ap.add_argument("--leaf", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the hot path is evaluated on a single MI355X; "
+              f"--gpus {args.gpus} is not supported (sharding is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.calib_copy:
+        calib_copy()
+        return
+
+    t_gen = time.perf_counter()
+    w = workload(args.config)
+    gen_s = time.perf_counter() - t_gen
+    print(f"# workload {w.name} N={w.n} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    from paper_1709_04488_amd import sph
+    results = {}
+    if args.precision in ("fp64", "both"):
+        results["fp64"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, args.leaf)
+        print(f"# fp64: {results['fp64']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        results["fp64_warm"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, args.leaf,
+                                       warm_start=True)
+    if args.precision in ("fp32", "both"):
+        results["fp32"] = run_gpu(w, sph.SPH_FP32_PAIR, args.steps, args.warmup, args.leaf)
+        print(f"# fp32: {results['fp32']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    head_key = "fp64" if "fp64" in results else "fp32"
+    head = results[head_key]
+    prec_name = "fp64" if head_key == "fp64" else "fp32"
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head_key == "fp64" else "f32-pair/f64-accum",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: N={w.n}, "
+                               + ("periodic unit box" if w.setup["periodic"] else "isolated")
+                               + f", eta={w.setup['eta']}, M4, alpha_AV=1, beta_AV=2, "
+                               f"{'FP64' if head_key == 'fp64' else 'FP32-pair'}, "
+                               "cold h start from the input guess",
+                   "n": w.n, "leaf_size": args.leaf,
+                   "interactions_per_step": head["interactions"]},
+        "roofline": roofline(head, prec_name),
+        "nr_iter_max": head["info"]["nr_iter_max"],
+        "walk_overflows": head["info"]["walk_overflows"],
+        "dens_leaf_visits": head["info"]["dens_leaf_visits"],
+        "dens_walks": head["info"]["dens_walks"],
+        "density_pair_evals": head["info"]["dens_pair_evals"],
+        "kernel_ms": {k: round(v, 4) for k, v in head["kernel_ms"].items()},
+        "device_bytes": head["device_bytes"],
+    }
+    if "fp64_warm" in results:
+        r = results["fp64_warm"]
+        out["fp64_warm_start"] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                                  "nr_iter_max": r["info"]["nr_iter_max"]}
+    if "fp32" in results and head_key != "fp32":
+        r = results["fp32"]
+        out["fp32_pair"] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                            "speedup_vs_fp64": r["value"] / head["value"],
+                            "roofline": roofline(r, "fp32"),
+                            "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -130,19 +130,23 @@ typedef struct {
     int32_t *nforce;      /* force neighbours j != i with r_ij < 2 max(h_i, h_j) */
 } sph_particles;
 
-/* Diagnostics of the resident state, valid after sph_sync. */
+/* Diagnostics of the last evaluation (stateless or resident). */
 typedef struct {
-    double time;          /* sum of the steps taken */
-    double dt_last;       /* step taken by the last sph_step */
-    double dt_next;       /* min_i dt_i of the latest forces (next Courant step) */
-    double kinetic;       /* sum 1/2 m v^2 */
+    double time;          /* resident state: sum of the steps taken */
+    double dt_last;       /* resident state: step taken by the last sph_step */
+    double dt_next;       /* min_i dt_i of the latest forces (next CFL step) */
+    double kinetic;       /* sum 1/2 m v^2 (velocities the forces used) */
     double thermal;       /* sum m u */
     double momentum[3];   /* sum m v */
-    int64_t steps;
-    int64_t n_dens_pairs; /* density interactions of the last evaluation */
-    int64_t n_force_pairs;/* force interactions of the last evaluation */
-    int32_t nr_iter_max;  /* Newton-Raphson iterations of the last density pass */
-    int32_t pad_;
+    int64_t steps;        /* resident state: sph_step calls since upload */
+    int64_t n_dens_pairs; /* density interactions: sum_i nngb_i at the final h */
+    int64_t n_force_pairs;/* force interactions: sum_i nforce_i */
+    int64_t dens_pair_evals;  /* density pairs evaluated over all Newton-Raphson iterations */
+    int64_t force_pair_evals; /* force pairs evaluated */
+    int32_t nr_iter_max;  /* Newton-Raphson iterations of the last density pass (max) */
+    int32_t walk_overflows; /* leaves whose neighbour walk overflowed LDS (slow path) */
+    int64_t dens_leaf_visits; /* candidate leaves swept by the density loop (all iterations) */
+    int64_t dens_walks;   /* tree walks made by the density loop */
 } sph_state_stats;
 
 typedef struct sph_ctx sph_ctx;
@@ -219,7 +223,8 @@ sph_status sph_step(sph_ctx *ctx, double dt, double *dt_used);
  * vsig, dt, nngb, nforce (m is constant and not written). */
 sph_status sph_download_state(sph_ctx *ctx, sph_particles *ps);
 
-/* Diagnostics of the resident state (waits for the stream). */
+/* Diagnostics of the last sph_forces / sph_upload_state / sph_step
+ * (waits for the stream).  SPH_ESTATE before any evaluation. */
 sph_status sph_state_info(sph_ctx *ctx, sph_state_stats *info);
 
 /*

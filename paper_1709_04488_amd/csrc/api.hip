@@ -35,6 +35,7 @@ int64_t bytes_per_particle(const sph_params &p)
     b += 4 * 8;                // s: predictor arrays
     b += 3 * 4;                // s: fp32 offsets
     b += 13 * 8 + 4;           // t: re-sort buffers
+    b += 2 * 4;                // leaf starts, leaf of each particle
     (void)p;
     return b;
 }
@@ -83,7 +84,12 @@ void free_all(sph_ctx *c)
     c->keys[0] = c->keys[1] = nullptr;
     c->vals[0] = c->vals[1] = nullptr;
     c->perm = nullptr;
-    c->bytes = 4096;   // fixed buffers (status, scalars, box, partials)
+    c->skeys = nullptr;
+    c->scratch_u32 = nullptr;
+    c->lstart = nullptr;
+    c->leaf_id = nullptr;
+    c->tree_n = -1;
+    c->bytes = 4096;   // fixed buffers (status, scalars, box, partials, tree info)
     c->built = false;
     c->resident = false;
 }
@@ -103,26 +109,14 @@ sph_status alloc(sph_ctx *c, T **ptr, int64_t count)
     return SPH_OK;
 }
 
-int64_t node_count(int64_t n, int G)
-{
-    int64_t cnt = ceil_div(std::max<int64_t>(n, 1), G), tot = 0;
-    while (true) {
-        tot += cnt;
-        if (cnt == 1) break;
-        cnt = ceil_div(cnt, 8);
-    }
-    return tot;
-}
-
 } // namespace
 
 sph_status ensure_capacity(sph_ctx *c, int64_t n)
 {
     if (n > (int64_t)0xFFFFFFF0ll) return fail(c, SPH_EINVAL, "n exceeds 2^32 - 16");
-    int64_t nodes_needed = node_count(n, c->p.leaf_size);
-    if (n <= c->ncap && nodes_needed <= c->node_cap) return SPH_OK;
+    if (n <= c->ncap && node_count_bound(n) <= c->node_cap) return SPH_OK;
     int64_t cap = std::max<int64_t>(n, 1024);
-    int64_t need = bytes_per_particle(c->p) * cap + node_count(cap, 8) * (int64_t)sizeof(Node) +
+    int64_t need = bytes_per_particle(c->p) * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
                    256 * 4 * ceil_div(cap, kRsTile) + 4096;
     if (c->budget && (size_t)need > c->budget)
         return fail(c, SPH_EBUDGET, "working set of " + std::to_string(need) +
@@ -147,9 +141,10 @@ sph_status ensure_capacity(sph_ctx *c, int64_t n)
     A_(S.nngb, cap); A_(S.nforce, cap);
     A_(S.id, cap); A_(T.id, cap);
     A_(S.fx, cap); A_(S.fy, cap); A_(S.fz, cap);
+    A_(c->lstart, cap + 1); A_(c->leaf_id, cap);
 #undef A_
     if (s != SPH_OK) { free_all(c); return s; }
-    int64_t ncap_nodes = node_count(cap, 8);
+    int64_t ncap_nodes = node_count_bound(cap);
     hipError_t e1 = hipMalloc((void **)&c->nodes, sizeof(Node) * (size_t)ncap_nodes);
     int64_t hcap = 256 * ceil_div(cap, kRsTile);
     hipError_t e2 = hipMalloc((void **)&c->hist, sizeof(uint32_t) * (size_t)hcap);
@@ -272,9 +267,11 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return SPH_EDEVICE; }
     bool ok = hipMalloc((void **)&c->d_status, sizeof(int32_t) * kStatusWords) == hipSuccess &&
               hipMalloc((void **)&c->d_scal, sizeof(double) * 16) == hipSuccess &&
-              hipMalloc((void **)&c->d_counts, sizeof(int64_t) * 4) == hipSuccess &&
+              hipMalloc((void **)&c->d_counts, sizeof(int64_t) * 8) == hipSuccess &&
               hipMalloc((void **)&c->d_box, sizeof(double) * 8) == hipSuccess &&
               hipMalloc((void **)&c->d_part, sizeof(double) * 1024 * 8) == hipSuccess &&
+              hipMalloc((void **)&c->d_tree, sizeof(TreeInfo)) == hipSuccess &&
+              hipMalloc((void **)&c->d_work, sizeof(uint32_t) * 64) == hipSuccess &&
               hipHostMalloc((void **)&c->h_status, sizeof(int32_t) * kStatusWords) == hipSuccess &&
               hipHostMalloc((void **)&c->h_scal, sizeof(double) * 16) == hipSuccess;
     if (!ok) {
@@ -285,7 +282,7 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
     c->bytes = 4096;
     ok = hipMemset(c->d_status, 0, sizeof(int32_t) * kStatusWords) == hipSuccess &&
          hipMemset(c->d_scal, 0, sizeof(double) * 16) == hipSuccess &&
-         hipMemset(c->d_counts, 0, sizeof(int64_t) * 4) == hipSuccess;
+         hipMemset(c->d_counts, 0, sizeof(int64_t) * 8) == hipSuccess;
     if (!ok) { sph_destroy(c); return SPH_EDEVICE; }
     *out = c;
     return SPH_OK;
@@ -304,6 +301,8 @@ sph_status sph_destroy(sph_ctx *c)
     if (c->d_counts) (void)hipFree(c->d_counts);
     if (c->d_box) (void)hipFree(c->d_box);
     if (c->d_part) (void)hipFree(c->d_part);
+    if (c->d_tree) (void)hipFree(c->d_tree);
+    if (c->d_work) (void)hipFree(c->d_work);
     if (c->h_status) (void)hipHostFree(c->h_status);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
     delete c;
@@ -414,6 +413,8 @@ sph_status sph_forces(sph_ctx *c, sph_particles *ps)
         sl.count++;
     }
     TRY(scatter(c, n, sl, c->perm));
+    TRY(reduce_dt(c, n));
+    TRY(reduce_diag(c, n));
     return SPH_OK;
 }
 
@@ -516,15 +517,13 @@ sph_status sph_download_state(sph_ctx *c, sph_particles *ps)
 sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
 {
     if (!c || !info) return SPH_EINVAL;
-    if (!c->resident) return fail(c, SPH_ESTATE, "no resident state");
-    int64_t counts[2] = {0, 0};
+    if (c->n <= 0) return fail(c, SPH_ESTATE, "nothing evaluated yet");
+    int64_t counts[8];
     TRY(hip_check(c, hipMemcpyAsync(c->h_scal, c->d_scal, sizeof(double) * 8,
                                     hipMemcpyDeviceToHost, c->stream), "copy scalars"));
     TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
     TRY(hip_check(c, hipMemcpy(counts, c->d_counts, sizeof(counts), hipMemcpyDeviceToHost),
                   "copy counts"));
-    int32_t st[kStatusWords];
-    TRY(hip_check(c, hipMemcpy(st, c->d_status, sizeof(st), hipMemcpyDeviceToHost), "status"));
     std::memset(info, 0, sizeof(*info));
     info->dt_next = c->h_scal[0];
     info->dt_last = c->h_scal[1];
@@ -535,7 +534,12 @@ sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
     info->steps = c->steps;
     info->n_dens_pairs = counts[0];
     info->n_force_pairs = counts[1];
-    info->nr_iter_max = st[5];
+    info->dens_pair_evals = counts[2];
+    info->force_pair_evals = counts[3];
+    info->nr_iter_max = (int32_t)counts[4];
+    info->walk_overflows = (int32_t)counts[5];
+    info->dens_leaf_visits = counts[6];
+    info->dens_walks = counts[7];
     return SPH_OK;
 }
 

@@ -10,6 +10,8 @@
 // the bounding box of its particles and their largest h.
 #include "sph_internal.hpp"
 
+#include <algorithm>
+
 namespace sph {
 
 namespace {
@@ -233,6 +235,12 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t *__res
     }
 }
 
+__global__ void k_copy_u32(int64_t n, const uint32_t *__restrict__ a, uint32_t *__restrict__ b)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) b[k] = a[k];
+}
+
 __global__ void k_iota(int64_t n, uint32_t *__restrict__ v)
 {
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -240,49 +248,263 @@ __global__ void k_iota(int64_t n, uint32_t *__restrict__ v)
 }
 
 // ---- leaves and tree -------------------------------------------------------------
+//
+// Leaves are runs of at most G consecutive sorted particles that never cross
+// the boundary of a Morton cell about 4 h wide: a new segment starts between
+// sorted particles k-1 and k when their keys differ above the level whose
+// cell edge is the largest power-of-two fraction of the box not below
+// 4 max(h_k-1, h_k).  Without this rule a run of G particles can straddle a
+// jump of the Morton curve and get a box as large as the domain.
 
-__global__ __launch_bounds__(256) void k_leaves(int64_t n, int G, const double *__restrict__ x,
-                                                const double *__restrict__ y,
-                                                const double *__restrict__ z,
-                                                const double *__restrict__ h,
-                                                Node *__restrict__ leaves, int64_t L)
+constexpr int kScanTile = 1024;     // particles per block in the leaf scans
+constexpr int kScanThreads = 256;   // 4 particles per thread
+
+__device__ inline bool seg_break(int64_t k, const uint64_t *__restrict__ keys,
+                                 const double *__restrict__ h, double ext, int bits)
 {
-    int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (l >= L) return;
-    Node nd;
-    for (int a = 0; a < 3; a++) { nd.lo[a] = INFINITY; nd.hi[a] = -INFINITY; }
-    nd.hmax = 0.0;
-    nd.pad = 0.0;
-    int64_t k1 = (l + 1) * G < n ? (l + 1) * G : n;
-    for (int64_t k = l * G; k < k1; k++) {
-        double v[3] = {x[k], y[k], z[k]};
-        for (int a = 0; a < 3; a++) { nd.lo[a] = fmin(nd.lo[a], v[a]); nd.hi[a] = fmax(nd.hi[a], v[a]); }
-        nd.hmax = fmax(nd.hmax, h[k]);
+    if (k == 0) return true;
+    double hm = fmax(h[k - 1], h[k]);
+    int T = 1;
+    if (hm > 0.0 && ext > 0.0) {
+        double t = floor(log2(ext / (4.0 * hm)));
+        T = t < 1.0 ? 1 : (t > (double)bits ? bits : (int)t);
     }
-    leaves[l] = nd;
+    int sh = 3 * (bits - T);
+    return (keys[k - 1] >> sh) != (keys[k] >> sh);
 }
 
-__global__ __launch_bounds__(256) void k_tree_level(const Node *__restrict__ child, int64_t nchild,
-                                                    Node *__restrict__ parent, int64_t npar)
+// block-wide inclusive scan of one value per thread (max or sum)
+template <bool MAX>
+__device__ inline uint32_t block_scan(uint32_t v, uint32_t *sh)
 {
-    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= npar) return;
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        uint32_t o = t >= d ? sh[t - d] : 0u;
+        __syncthreads();
+        sh[t] = MAX ? (sh[t] > o ? sh[t] : o) : sh[t] + o;
+        __syncthreads();
+    }
+    uint32_t r = sh[t];
+    __syncthreads();
+    return r;
+}
+
+// per tile: break flags and the largest segment start inside the tile
+__global__ __launch_bounds__(kScanThreads) void k_seg_tiles(int64_t n, const uint64_t *__restrict__ keys,
+                                                            const double *__restrict__ h,
+                                                            const double *__restrict__ box,
+                                                            int bits, uint32_t *__restrict__ flag,
+                                                            uint32_t *__restrict__ tmax)
+{
+    __shared__ uint32_t sh[kScanThreads];
+    const double ext = fmax(fmax(box[3] - box[0], box[4] - box[1]), box[5] - box[2]);
+    const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * 4;
+    uint32_t mx = 0;
+    for (int e = 0; e < 4; e++) {
+        int64_t k = base + e;
+        if (k < n) {
+            bool b = seg_break(k, keys, h, ext, bits);
+            flag[k] = b ? 1u : 0u;
+            if (b) mx = (uint32_t)k;
+        }
+    }
+    uint32_t r = block_scan<true>(mx, sh);
+    if (threadIdx.x == kScanThreads - 1) tmax[blockIdx.x] = r;
+}
+
+// exclusive scan over the tile values, one block (max or sum)
+template <bool MAX>
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ a, int64_t ntile)
+{
+    __shared__ uint32_t sums[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (ntile + 1023) / 1024;
+    const int64_t s0 = t * chunk, s1 = s0 + chunk < ntile ? s0 + chunk : ntile;
+    uint32_t s = 0;
+    for (int64_t k = s0; k < s1; k++) s = MAX ? (a[k] > s ? a[k] : s) : s + a[k];
+    sums[t] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        uint32_t v = t >= d ? sums[t - d] : 0u;
+        __syncthreads();
+        sums[t] = MAX ? (sums[t] > v ? sums[t] : v) : sums[t] + v;
+        __syncthreads();
+    }
+    uint32_t run = t > 0 ? sums[t - 1] : 0u;
+    for (int64_t k = s0; k < s1; k++) {
+        uint32_t v = a[k];
+        a[k] = run;
+        run = MAX ? (v > run ? v : run) : run + v;
+    }
+}
+
+// per tile: segment start of every particle, leaf-start flags, leaf count
+__global__ __launch_bounds__(kScanThreads) void k_seg_apply(int64_t n, int G,
+                                                            uint32_t *__restrict__ flag,
+                                                            const uint32_t *__restrict__ tmax,
+                                                            uint32_t *__restrict__ tcnt)
+{
+    __shared__ uint32_t sh[kScanThreads];
+    const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * 4;
+    uint32_t loc[4];
+    uint32_t mx = 0;
+    for (int e = 0; e < 4; e++) {
+        int64_t k = base + e;
+        loc[e] = (k < n && flag[k]) ? (uint32_t)k : 0u;
+        mx = loc[e] > mx ? loc[e] : mx;
+    }
+    uint32_t incl = block_scan<true>(mx, sh);
+    uint32_t prev = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0u;
+    // sh was overwritten by the scan's final value per thread before return;
+    // recompute the exclusive prefix from the inclusive values
+    __syncthreads();
+    sh[threadIdx.x] = incl;
+    __syncthreads();
+    prev = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0u;
+    uint32_t seg = prev > tmax[blockIdx.x] ? prev : tmax[blockIdx.x];
+    uint32_t count = 0;
+    for (int e = 0; e < 4; e++) {
+        int64_t k = base + e;
+        if (k >= n) break;
+        if (flag[k]) seg = (uint32_t)k;
+        uint32_t ls = ((uint32_t)(k - seg) % (uint32_t)G) == 0u ? 1u : 0u;
+        flag[k] = ls;
+        count += ls;
+    }
+    __syncthreads();
+    uint32_t tot = block_scan<false>(count, sh);
+    if (threadIdx.x == kScanThreads - 1) tcnt[blockIdx.x] = tot;
+}
+
+// per tile: leaf index of every particle and the first particle of every leaf
+__global__ __launch_bounds__(kScanThreads) void k_leaf_ids(int64_t n, const uint32_t *__restrict__ flag,
+                                                           const uint32_t *__restrict__ toff,
+                                                           uint32_t *__restrict__ leaf_id,
+                                                           uint32_t *__restrict__ lstart)
+{
+    __shared__ uint32_t sh[kScanThreads];
+    const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * 4;
+    uint32_t cnt = 0;
+    for (int e = 0; e < 4; e++) {
+        int64_t k = base + e;
+        if (k < n) cnt += flag[k];
+    }
+    uint32_t incl = block_scan<false>(cnt, sh);
+    uint32_t run = toff[blockIdx.x] + incl - cnt;   // leaf starts before this thread's items
+    for (int e = 0; e < 4; e++) {
+        int64_t k = base + e;
+        if (k >= n) break;
+        if (flag[k]) {
+            lstart[run] = (uint32_t)k;
+            run++;
+        }
+        leaf_id[k] = run - 1;
+        if (k == n - 1) lstart[run] = (uint32_t)n;
+    }
+}
+
+// tree levels from the leaf count (one thread)
+__global__ void k_tree_info(int64_t n, int G, const uint32_t *__restrict__ toff,
+                            const uint32_t *__restrict__ tcnt, int64_t ntile,
+                            TreeInfo *__restrict__ T)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t L = (int64_t)toff[ntile - 1] + tcnt[ntile - 1];
+    T->leaf_size = G;
+    T->n = n;
+    int64_t cnt = L, off = 0;
+    int lev = 0;
+    for (; lev < kMaxLevels; lev++) {
+        T->off[lev] = off;
+        T->cnt[lev] = cnt;
+        off += cnt;
+        if (cnt <= 1) { lev++; break; }
+        cnt = (cnt + 7) / 8;
+    }
+    T->nlev = lev;
+    for (int l = lev; l < kMaxLevels; l++) { T->off[l] = off; T->cnt[l] = 0; }
+}
+
+__device__ inline Node merge_children(const Node *__restrict__ child, int64_t c0, int64_t c1)
+{
     Node nd;
     for (int a = 0; a < 3; a++) { nd.lo[a] = INFINITY; nd.hi[a] = -INFINITY; }
     nd.hmax = 0.0;
     nd.pad = 0.0;
-    int64_t c1 = 8 * p + 8 < nchild ? 8 * p + 8 : nchild;
-    for (int64_t c = 8 * p; c < c1; c++) {
-        Node ch = child[c];
+    for (int64_t c = c0; c < c1; c++) {
+        const Node &ch = child[c];
         for (int a = 0; a < 3; a++) { nd.lo[a] = fmin(nd.lo[a], ch.lo[a]); nd.hi[a] = fmax(nd.hi[a], ch.hi[a]); }
         nd.hmax = fmax(nd.hmax, ch.hmax);
     }
-    parent[p] = nd;
+    return nd;
+}
+
+__global__ __launch_bounds__(256) void k_leaves(const TreeInfo *__restrict__ T,
+                                                const uint32_t *__restrict__ lstart,
+                                                const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ z,
+                                                const double *__restrict__ h,
+                                                Node *__restrict__ nodes)
+{
+    const int64_t L = T->cnt[0];
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        Node nd;
+        for (int a = 0; a < 3; a++) { nd.lo[a] = INFINITY; nd.hi[a] = -INFINITY; }
+        nd.hmax = 0.0;
+        nd.pad = 0.0;
+        for (int64_t k = lstart[l]; k < (int64_t)lstart[l + 1]; k++) {
+            double v[3] = {x[k], y[k], z[k]};
+            for (int a = 0; a < 3; a++) { nd.lo[a] = fmin(nd.lo[a], v[a]); nd.hi[a] = fmax(nd.hi[a], v[a]); }
+            nd.hmax = fmax(nd.hmax, h[k]);
+        }
+        nodes[l] = nd;
+    }
+}
+
+constexpr int64_t kSmallLevel = 2048;   // children per level handled by one block
+constexpr int kBigLevels = 4;           // levels built grid-wide at most
+
+// level `lev` from level lev-1, grid-wide, when the child level is large
+__global__ __launch_bounds__(256) void k_tree_level_big(const TreeInfo *__restrict__ T,
+                                                        Node *__restrict__ nodes, int lev)
+{
+    if (lev >= T->nlev || T->cnt[lev - 1] <= kSmallLevel) return;
+    const Node *child = nodes + T->off[lev - 1];
+    Node *par = nodes + T->off[lev];
+    const int64_t nchild = T->cnt[lev - 1], npar = T->cnt[lev];
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npar;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c1 = 8 * p + 8 < nchild ? 8 * p + 8 : nchild;
+        par[p] = merge_children(child, 8 * p, c1);
+    }
+}
+
+// all remaining (small) levels by one block, level after level
+__global__ __launch_bounds__(1024) void k_tree_level_small(const TreeInfo *__restrict__ T,
+                                                           Node *__restrict__ nodes)
+{
+    const int nlev = T->nlev;
+    for (int lev = 1; lev < nlev; lev++) {
+        if (lev <= kBigLevels && T->cnt[lev - 1] > kSmallLevel) continue;
+        const Node *child = nodes + T->off[lev - 1];
+        Node *par = nodes + T->off[lev];
+        const int64_t nchild = T->cnt[lev - 1], npar = T->cnt[lev];
+        for (int64_t p = threadIdx.x; p < npar; p += blockDim.x) {
+            int64_t c1 = 8 * p + 8 < nchild ? 8 * p + 8 : nchild;
+            par[p] = merge_children(child, 8 * p, c1);
+        }
+        __syncthreads();
+    }
 }
 
 // FP32-pair mode: single-precision offsets of each particle from the centre of
 // its leaf box.
-__global__ __launch_bounds__(256) void k_offsets(int64_t n, int G, const double *__restrict__ x,
+__global__ __launch_bounds__(256) void k_offsets(int64_t n, const uint32_t *__restrict__ leaf_id,
+                                                 const double *__restrict__ x,
                                                  const double *__restrict__ y,
                                                  const double *__restrict__ z,
                                                  const Node *__restrict__ leaves,
@@ -291,7 +513,7 @@ __global__ __launch_bounds__(256) void k_offsets(int64_t n, int G, const double 
 {
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const Node &nd = leaves[k / G];
+    const Node &nd = leaves[leaf_id[k]];
     fx[k] = (float)(x[k] - 0.5 * (nd.lo[0] + nd.hi[0]));
     fy[k] = (float)(y[k] - 0.5 * (nd.lo[1] + nd.hi[1]));
     fz[k] = (float)(z[k] - 0.5 * (nd.lo[2] + nd.hi[2]));
@@ -316,6 +538,18 @@ __global__ __launch_bounds__(256) void k_force_prep(int64_t n, double gamma,
 }
 
 } // namespace
+
+// nodes of the tree over at most n leaves (every leaf holds >= 1 particle)
+int64_t node_count_bound(int64_t n)
+{
+    int64_t cnt = std::max<int64_t>(n, 1), tot = 0;
+    while (true) {
+        tot += cnt;
+        if (cnt <= 1) break;
+        cnt = ceil_div(cnt, 8);
+    }
+    return tot;
+}
 
 static inline unsigned grid_for(int64_t n, int threads)
 {
@@ -351,6 +585,9 @@ sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y, 
         cur ^= 1;
     }
     c->perm = c->vals[cur];
+    c->skeys = c->keys[cur];
+    c->scratch_u32 = (uint32_t *)c->keys[cur ^ 1];
+    c->tree_n = -1;
     return hip_check(c, hipGetLastError(), "build_order");
 }
 
@@ -364,33 +601,44 @@ sph_status gather(sph_ctx *c, int64_t n, const GatherList &g, bool identity_src_
 
 sph_status build_tree(sph_ctx *c, int64_t n)
 {
-    TreeInfo &T = c->tree;
+    c->tree_n = -1;
+    if (n == 0) return SPH_OK;
     const int G = c->p.leaf_size;
-    T.leaf_size = G;
-    T.n = n;
-    if (n == 0) { T.nlev = 0; return SPH_OK; }
-    int64_t cnt = ceil_div(n, G), off = 0;
-    int lev = 0;
-    while (true) {
-        T.off[lev] = off;
-        T.cnt[lev] = cnt;
-        off += cnt;
-        lev++;
-        if (cnt == 1) break;
-        cnt = ceil_div(cnt, 8);
-        if (lev >= kMaxLevels) return fail(c, SPH_EINVAL, "tree too deep");
+    if (!c->skeys || !c->scratch_u32 || !c->lstart || !c->leaf_id || !c->d_tree || !c->nodes)
+        return fail(c, SPH_ESTATE, "build_tree: order not built");
+    const int64_t ntile = ceil_div(n, kScanTile);
+    if (2 * ntile > c->hist_cap) return fail(c, SPH_ENOMEM, "scan tile capacity");
+    if (c->node_cap < node_count_bound(n)) return fail(c, SPH_ENOMEM, "node capacity");
+    uint32_t *tmax = c->hist, *tcnt = c->hist + ntile;
+    uint32_t *flag = c->scratch_u32;
+    hipLaunchKernelGGL(k_seg_tiles, dim3((unsigned)ntile), dim3(kScanThreads), 0, c->stream, n,
+                       c->skeys, c->s.h, c->d_box, kMortonBits, flag, tmax);
+    hipLaunchKernelGGL((k_scan_tiles<true>), dim3(1), dim3(1024), 0, c->stream, tmax, ntile);
+    hipLaunchKernelGGL(k_seg_apply, dim3((unsigned)ntile), dim3(kScanThreads), 0, c->stream, n, G,
+                       flag, tmax, tcnt);
+    // tcnt -> exclusive offsets in place; keep the counts for the total in tmax
+    hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)ceil_div(ntile, 256)), dim3(256), 0, c->stream,
+                       ntile, tcnt, tmax);
+    hipLaunchKernelGGL((k_scan_tiles<false>), dim3(1), dim3(1024), 0, c->stream, tcnt, ntile);
+    hipLaunchKernelGGL(k_tree_info, dim3(1), dim3(64), 0, c->stream, n, G, tcnt, tmax, ntile,
+                       c->d_tree);
+    hipLaunchKernelGGL(k_leaf_ids, dim3((unsigned)ntile), dim3(kScanThreads), 0, c->stream, n,
+                       flag, tcnt, c->leaf_id, c->lstart);
+    hipLaunchKernelGGL(k_leaves, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, c->d_tree,
+                       c->lstart, c->s.x, c->s.y, c->s.z, c->s.h, c->nodes);
+    int64_t bound = n;
+    for (int l = 1; l <= kBigLevels; l++) {
+        bound = ceil_div(bound, 8);
+        hipLaunchKernelGGL(k_tree_level_big, dim3(grid_for(bound, 256)), dim3(256), 0, c->stream,
+                           c->d_tree, c->nodes, l);
     }
-    T.nlev = lev;
-    if (off > c->node_cap) return fail(c, SPH_ENOMEM, "node capacity");
-    hipLaunchKernelGGL(k_leaves, dim3(grid_for(T.cnt[0], 256)), dim3(256), 0, c->stream, n, G,
-                       c->s.x, c->s.y, c->s.z, c->s.h, c->nodes, T.cnt[0]);
-    for (int l = 1; l < T.nlev; l++)
-        hipLaunchKernelGGL(k_tree_level, dim3(grid_for(T.cnt[l], 256)), dim3(256), 0, c->stream,
-                           c->nodes + T.off[l - 1], T.cnt[l - 1], c->nodes + T.off[l], T.cnt[l]);
+    hipLaunchKernelGGL(k_tree_level_small, dim3(1), dim3(1024), 0, c->stream, c->d_tree, c->nodes);
     if (c->p.precision == SPH_FP32_PAIR)
-        hipLaunchKernelGGL(k_offsets, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, G, c->s.x,
-                           c->s.y, c->s.z, c->nodes, c->s.fx, c->s.fy, c->s.fz);
-    return hip_check(c, hipGetLastError(), "build_tree");
+        hipLaunchKernelGGL(k_offsets, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n,
+                           c->leaf_id, c->s.x, c->s.y, c->s.z, c->nodes, c->s.fx, c->s.fy, c->s.fz);
+    sph_status st = hip_check(c, hipGetLastError(), "build_tree");
+    if (st == SPH_OK) c->tree_n = n;
+    return st;
 }
 
 sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted)

@@ -28,12 +28,41 @@ __device__ inline double wave_max(double v)
     return v;
 }
 
-// Blocks are dispatched round-robin over the XCDs; give each XCD a
-// contiguous run of leaves so that neighbouring leaves share an L2.
-__device__ inline int64_t xcd_leaf(int64_t b, int64_t nb)
+// Persistent work loop over the leaves.  Blocks are dispatched round-robin
+// over the 8 XCDs, so block b runs on XCD b % 8; each XCD first claims leaves
+// from its own contiguous eighth of the leaf range (neighbouring leaves then
+// share that XCD's L2), then helps the others.  Claims go through one atomic
+// counter per eighth; every leaf is processed by exactly one wave, so results
+// do not depend on which wave took it.
+template <class Fn>
+__device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work, Fn fn)
 {
-    int64_t per = (nb + kXcds - 1) / kXcds;
-    return (b % kXcds) * per + b / kXcds;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t per = (L + kXcds - 1) / kXcds;
+    const int x0 = (int)(blockIdx.x % kXcds);
+    for (int r = 0; r < kXcds; r++) {
+        const int x = (x0 + r) % kXcds;
+        const int64_t beg = x * per;
+        const int64_t end = beg + per < L ? beg + per : L;
+        if (beg >= end) continue;
+        for (;;) {
+            uint32_t claim = 0;
+            if (lane == 0) claim = atomicAdd(&work[x], 1u);
+            claim = __shfl(claim, 0);
+            const int64_t leaf = beg + (int64_t)claim;
+            if (leaf >= end) break;
+            fn(leaf);
+        }
+    }
+}
+
+// Copy the device tree description into LDS once per block.
+__device__ inline void load_tree(const TreeInfo *__restrict__ src, TreeInfo &dst)
+{
+    const int64_t *s = (const int64_t *)src;
+    int64_t *d = (int64_t *)&dst;
+    for (int k = threadIdx.x; k < kTreeWords; k += blockDim.x) d[k] = s[k];
+    __syncthreads();
 }
 
 // Squared gap between box [lo, hi] and node box (0 if they overlap), with the
@@ -77,6 +106,17 @@ __device__ inline T sym_dot2(T a, T b, T c, T d)
     T p = a * b;
     T q = c * d;
     return p + q;
+}
+
+// Kernel gradients of a pair and their sum, each product rounded before the
+// sum: keeps 0.5 (G_i + G_j) identical for (i, j) and (j, i).
+template <class T>
+__device__ inline void sym_grads(T gfi, T dfi, T gfj, T dfj, T &gi, T &gj, T &gsum)
+{
+#pragma clang fp contract(off)
+    gi = gfi * dfi;
+    gj = gfj * dfj;
+    gsum = gi + gj;
 }
 
 __device__ inline double min_image(double d, double L, double half)
@@ -196,7 +236,9 @@ __device__ inline Shift leaf_shift(const Node &home, const Node &cand, const Box
 // ---------------------------------------------------------------------------
 struct DensArgs {
     int64_t n;
-    TreeInfo T;
+    const TreeInfo *tree;
+    const uint32_t *lstart;
+    uint32_t *work;
     Box box;
     const Node *nodes;
     const double *x, *y, *z, *m;
@@ -204,6 +246,7 @@ struct DensArgs {
     double *h, *rho, *omega;
     int32_t *nngb;
     int32_t *status;
+    int64_t *counts;
     double eta3;
     double h_rtol;
     int32_t max_iter;
@@ -226,19 +269,23 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
     constexpr int LPP = kWave / G;
     constexpr int PER = G / LPP;
     __shared__ WalkBuf wb;
+    __shared__ TreeInfo T;
+    load_tree(A.tree, T);
     const int lane = threadIdx.x;
-    const int64_t L = A.T.cnt[0];
-    const int64_t leaf = xcd_leaf(blockIdx.x, gridDim.x);
-    if (leaf >= L) return;
     const int p = lane / LPP, q = lane % LPP;
-    const int64_t i = leaf * G + p;
-    const bool active = i < A.n;
-    const int64_t ii = active ? i : leaf * G;
+    const Box &bx = A.box;
+    int64_t evals = 0, walks = 0, visits = 0, overflows = 0;
+    int iter_max = 0;
+    for_each_home_leaf(T.cnt[0], A.work, [&](int64_t leaf) {
+    const int64_t first = A.lstart[leaf];
+    const int nhome = (int)(A.lstart[leaf + 1] - first);
+    const int64_t i = first + p;
+    const bool active = p < nhome;
+    const int64_t ii = active ? i : first;
     const double xi = A.x[ii], yi = A.y[ii], zi = A.z[ii], mi = A.m[ii];
     float fxi = 0.f, fyi = 0.f, fzi = 0.f;
     if (PREC == SPH_FP32_PAIR) { fxi = A.fx[ii]; fyi = A.fy[ii]; fzi = A.fz[ii]; }
     const Node home = A.nodes[leaf];
-    const Box &bx = A.box;
     double h = A.h[ii];
     double lo_b = 0.0, hi_b = INFINITY;
     bool conv = !active;
@@ -252,7 +299,9 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
         return [&bx, &home, R2](const Node &nd) { return box_gap2(home.lo, home.hi, nd, bx) < R2; };
     };
     const uint32_t *list = nullptr;
-    int ncand = walk(A.T, A.nodes, make_test(hcov), wb, &list);
+    int ncand = walk(T, A.nodes, make_test(hcov), wb, &list);
+    walks++;
+    if (ncand < 0) overflows++;
     int iter = 0;
     for (;;) {
         double s0 = 0.0, s2 = 0.0;
@@ -263,8 +312,8 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
         auto body = [&](int64_t c) {
             const Node cand = A.nodes[c];
             const Shift sh = leaf_shift(home, cand, bx, hcov);
-            const int64_t j0 = c * G;
-            const int jn = (int)(A.n - j0 < G ? A.n - j0 : G);
+            const int64_t j0 = A.lstart[c];
+            const int jn = (int)(A.lstart[c + 1] - j0);
             if (PREC == SPH_FP64) {
 #pragma unroll
                 for (int t = 0; t < PER; t++) {
@@ -326,7 +375,9 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
                 }
             }
         };
-        for_each_leaf(A.T, A.nodes, ncand, list, make_test(hcov), body);
+        for_each_leaf(T, A.nodes, ncand, list, make_test(hcov), body);
+        visits += ncand >= 0 ? ncand : T.cnt[0];
+        if (!conv) evals += cnt;
 #pragma unroll
         for (int o = 1; o < LPP; o <<= 1) {
             s0 += __shfl_xor(s0, o);
@@ -338,28 +389,33 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
             // g'(h) = -(sigma/h) sum m q f'(q) >= 0
             const double g = kSigma * s0 - A.eta3 * mi;
             const double gp = -kSigma * s2 * hinv;
-            if (g < 0.0) lo_b = fmax(lo_b, h); else hi_b = fmin(hi_b, h);
-            double hn;
-            if (g == 0.0) {
-                hn = h;
-            } else {
-                hn = gp > 0.0 ? h - g / gp : (g < 0.0 ? 2.0 * h : 0.5 * h);
-                hn = fmin(fmax(hn, 0.5 * h), 2.0 * h);
-                if (!(hn > lo_b && hn < hi_b)) hn = hi_b < INFINITY ? 0.5 * (lo_b + hi_b) : 2.0 * h;
-            }
             h_out = h;
             rho_out = kSigma * s0 * hinv * hinv * hinv;
             om_out = -s2 / (3.0 * s0);
             n_out = cnt;
-            if (fabs(hn - h) <= A.h_rtol * h || !(hn == hn)) conv = true;
-            else h = hn;
+            // the Newton step decides convergence before any safeguard: a step
+            // below the tolerance (down to a zero step at the root) is final
+            const double step = gp > 0.0 ? g / gp : INFINITY;
+            if (g == 0.0 || fabs(step) <= A.h_rtol * h) {
+                conv = true;
+            } else {
+                if (g < 0.0) lo_b = fmax(lo_b, h); else hi_b = fmin(hi_b, h);
+                double hn = gp > 0.0 ? h - step : (g < 0.0 ? 2.0 * h : 0.5 * h);
+                hn = fmin(fmax(hn, 0.5 * h), 2.0 * h);
+                // outside the bracket of known signs: bisect it
+                if (!(hn > lo_b && hn < hi_b)) hn = hi_b < INFINITY ? 0.5 * (lo_b + hi_b) : 2.0 * h;
+                if (!(hn == hn)) conv = true;
+                else h = hn;
+            }
         }
         iter++;
         if (__ballot(!conv) == 0ull || iter >= A.max_iter) break;
         const double hm = wave_max(conv ? 0.0 : h);
         if (hm > hcov) {
             hcov = 1.25 * hm;
-            ncand = walk(A.T, A.nodes, make_test(hcov), wb, &list);
+            ncand = walk(T, A.nodes, make_test(hcov), wb, &list);
+            walks++;
+            if (ncand < 0) overflows++;
         }
     }
     if (active && q == 0) {
@@ -383,9 +439,15 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
             }
         }
     }
+    iter_max = iter > iter_max ? iter : iter_max;
+    });
+    for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
     if (lane == 0) {
-        atomicMax(&A.status[5], iter);
-        if (ncand < 0) atomicAdd(&A.status[4], 1);
+        atomicAdd((unsigned long long *)&A.counts[2], (unsigned long long)evals);
+        atomicMax((unsigned long long *)&A.counts[4], (unsigned long long)iter_max);
+        if (overflows) atomicAdd((unsigned long long *)&A.counts[5], (unsigned long long)overflows);
+        atomicAdd((unsigned long long *)&A.counts[6], (unsigned long long)visits);
+        atomicAdd((unsigned long long *)&A.counts[7], (unsigned long long)walks);
     }
 }
 
@@ -394,7 +456,9 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
 // ---------------------------------------------------------------------------
 struct ForceArgs {
     int64_t n;
-    TreeInfo T;
+    const TreeInfo *tree;
+    const uint32_t *lstart;
+    uint32_t *work;
     Box box;
     const Node *nodes;
     const double *x, *y, *z, *vx, *vy, *vz, *m, *h, *hinv, *rho, *A, *c;
@@ -402,6 +466,7 @@ struct ForceArgs {
     double *ax, *ay, *az, *du, *vsig, *dt;
     int32_t *nforce;
     int32_t *status;
+    int64_t *counts;
     double alpha, beta, ccfl;
 };
 
@@ -411,14 +476,18 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
     constexpr int LPP = kWave / G;
     constexpr int PER = G / LPP;
     __shared__ WalkBuf wb;
+    __shared__ TreeInfo T;
+    load_tree(F.tree, T);
     const int lane = threadIdx.x;
-    const int64_t L = F.T.cnt[0];
-    const int64_t leaf = xcd_leaf(blockIdx.x, gridDim.x);
-    if (leaf >= L) return;
     const int p = lane / LPP, q = lane % LPP;
-    const int64_t i = leaf * G + p;
-    const bool active = i < F.n;
-    const int64_t ii = active ? i : leaf * G;
+    const Box &bx = F.box;
+    int64_t pairs_total = 0, overflows = 0;
+    for_each_home_leaf(T.cnt[0], F.work, [&](int64_t leaf) {
+    const int64_t first = F.lstart[leaf];
+    const int nhome = (int)(F.lstart[leaf + 1] - first);
+    const int64_t i = first + p;
+    const bool active = p < nhome;
+    const int64_t ii = active ? i : first;
     const double xi = F.x[ii], yi = F.y[ii], zi = F.z[ii];
     const double vxi = F.vx[ii], vyi = F.vy[ii], vzi = F.vz[ii];
     const double hi = F.h[ii], hinvi = F.hinv[ii], rhoi = F.rho[ii], Ai = F.A[ii], ci = F.c[ii];
@@ -427,7 +496,6 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
     float fxi = 0.f, fyi = 0.f, fzi = 0.f;
     if (PREC == SPH_FP32_PAIR) { fxi = F.fx[ii]; fyi = F.fy[ii]; fzi = F.fz[ii]; }
     const Node home = F.nodes[leaf];
-    const Box &bx = F.box;
     // symmetric criterion: a node can hold force neighbours of the home leaf
     // if its box is closer than 2 max(h over home, h over node)
     auto test = [&bx, &home](const Node &nd) {
@@ -435,7 +503,8 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
         return box_gap2(home.lo, home.hi, nd, bx) < R * R;
     };
     const uint32_t *list = nullptr;
-    int ncand = walk(F.T, F.nodes, test, wb, &list);
+    int ncand = walk(T, F.nodes, test, wb, &list);
+    if (ncand < 0) overflows++;
 
     double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
     int cnt = 0;
@@ -443,8 +512,8 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
     auto body = [&](int64_t c) {
         const Node cand = F.nodes[c];
         const Shift sh = leaf_shift(home, cand, bx, fmax(home.hmax, cand.hmax));
-        const int64_t j0 = c * G;
-        const int jn = (int)(F.n - j0 < G ? F.n - j0 : G);
+        const int64_t j0 = F.lstart[c];
+        const int jn = (int)(F.lstart[c + 1] - j0);
         float ox = 0.f, oy = 0.f, oz = 0.f;
         if (PREC == SPH_FP32_PAIR) {
             ox = (float)((0.5 * (home.lo[0] + home.hi[0]) - 0.5 * (cand.lo[0] + cand.hi[0])) +
@@ -488,7 +557,8 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
                 double fi, dfi, fj, dfj;
                 m4(r * hinvi, fi, dfi);
                 m4(r * hinvj, fj, dfj);
-                const double gi = gfi * dfi, gj = gfj * dfj;
+                double gi, gj, gsum;
+                sym_grads(gfi, dfi, gfj, dfj, gi, gj, gsum);
                 const double w = ((vxi - F.vx[j]) * ex + (vyi - F.vy[j]) * ey) + (vzi - F.vz[j]) * ez;
                 const double mj = F.m[j];
                 double cvec = -mj * sym_dot2(Ai, gi, F.A[j], gj);
@@ -497,7 +567,7 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
                 const double vs = (ci + cj) - beta * wneg;
                 vs_max = fmax(vs_max, vs);
                 const double visc = (mj / (0.5 * (rhoi + F.rho[j]))) * alpha * vs * wneg;
-                const double gbar = 0.5 * (gi + gj);
+                const double gbar = 0.5 * gsum;
                 cvec += visc * gbar;
                 cdu -= visc * 0.5 * wneg * gbar;
                 axi += cvec * ex;
@@ -532,7 +602,8 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
                 float fi, dfi, fj, dfj;
                 m4(r * hinvif, fi, dfi);
                 m4(r * hinvj, fj, dfj);
-                const float gi = gfif * dfi, gj = gfjf * dfj;
+                float gi, gj, gsum;
+                sym_grads(gfif, dfi, gfjf, dfj, gi, gj, gsum);
                 const float w = ((float)(vxi - F.vx[j]) * ex + (float)(vyi - F.vy[j]) * ey) +
                                 (float)(vzi - F.vz[j]) * ez;
                 const float mj = (float)F.m[j];
@@ -543,7 +614,7 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
                 const float vs = (cif + cj) - (float)beta * wneg;
                 vs_max = fmax(vs_max, (double)vs);
                 const float visc = (mj / (0.5f * ((float)rhoi + (float)F.rho[j]))) * (float)alpha * vs * wneg;
-                const float gbar = 0.5f * (gi + gj);
+                const float gbar = 0.5f * gsum;
                 cvec += visc * gbar;
                 cdu -= visc * 0.5f * wneg * gbar;
                 axi += (double)(cvec * ex);
@@ -553,7 +624,7 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
             }
         }
     };
-    for_each_leaf(F.T, F.nodes, ncand, list, test, body);
+    for_each_leaf(T, F.nodes, ncand, list, test, body);
 #pragma unroll
     for (int o = 1; o < LPP; o <<= 1) {
         axi += __shfl_xor(axi, o);
@@ -578,7 +649,13 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
             atomicAdd(&F.status[2], 1);
         }
     }
-    if (lane == 0 && ncand < 0) atomicAdd(&F.status[4], 1);
+    pairs_total += (q == 0 && active) ? cnt : 0;
+    });
+    for (int o = 32; o > 0; o >>= 1) pairs_total += __shfl_xor(pairs_total, o);
+    if (lane == 0) {
+        atomicAdd((unsigned long long *)&F.counts[3], (unsigned long long)pairs_total);
+        if (overflows) atomicAdd((unsigned long long *)&F.counts[5], (unsigned long long)overflows);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -586,7 +663,9 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
 // ---------------------------------------------------------------------------
 struct NgbArgs {
     int64_t n;
-    TreeInfo T;
+    const TreeInfo *tree;
+    const uint32_t *lstart;
+    uint32_t *work;
     Box box;
     const Node *nodes;
     const double *x, *y, *z, *h;
@@ -605,26 +684,30 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
     constexpr int LPP = kWave / G;
     constexpr int PER = G / LPP;
     __shared__ WalkBuf wb;
+    __shared__ TreeInfo T;
+    load_tree(N.tree, T);
     const int lane = threadIdx.x;
-    const int64_t L = N.T.cnt[0];
-    const int64_t leaf = xcd_leaf(blockIdx.x, gridDim.x);
-    if (leaf >= L) return;
     const int p = lane / LPP, q = lane % LPP;
-    const int64_t i = leaf * G + p;
-    const bool active = i < N.n;
-    const int64_t ii = active ? i : leaf * G;
+    const Box &bx = N.box;
+    const int32_t mode = N.mode;
+    int64_t overflows = 0;
+    for_each_home_leaf(T.cnt[0], N.work, [&](int64_t leaf) {
+    const int64_t first = N.lstart[leaf];
+    const int nhome = (int)(N.lstart[leaf + 1] - first);
+    const int64_t i = first + p;
+    const bool active = p < nhome;
+    const int64_t ii = active ? i : first;
     const double xi = N.x[ii], yi = N.y[ii], zi = N.z[ii], hi = N.h[ii];
     const double hi2x4 = (2.0 * hi) * (2.0 * hi);
     const Node home = N.nodes[leaf];
-    const Box &bx = N.box;
-    const int32_t mode = N.mode;
     auto test = [&bx, &home, mode](const Node &nd) {
         double hh = mode == 0 ? home.hmax : fmax(home.hmax, nd.hmax);
         double R = 2.0 * hh * (1.0 + 1e-10);
         return box_gap2(home.lo, home.hi, nd, bx) < R * R;
     };
     const uint32_t *list = nullptr;
-    int ncand = walk(N.T, N.nodes, test, wb, &list);
+    int ncand = walk(T, N.nodes, test, wb, &list);
+    if (ncand < 0) overflows++;
     // two sweeps in pass 2: count this lane's hits, then write them
     int64_t mine = 0;
     int64_t base = 0;
@@ -633,8 +716,8 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
         auto body = [&](int64_t c) {
             const Node cand = N.nodes[c];
             const Shift sh = leaf_shift(home, cand, bx, mode == 0 ? home.hmax : fmax(home.hmax, cand.hmax));
-            const int64_t j0 = c * G;
-            const int jn = (int)(N.n - j0 < G ? N.n - j0 : G);
+            const int64_t j0 = N.lstart[c];
+            const int jn = (int)(N.lstart[c + 1] - j0);
 #pragma unroll
             for (int t = 0; t < PER; t++) {
                 const int jj = q + LPP * t;
@@ -665,7 +748,7 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
                 }
             }
         };
-        for_each_leaf(N.T, N.nodes, ncand, list, test, body);
+        for_each_leaf(T, N.nodes, ncand, list, test, body);
         if (sweep == 0) {
             mine = k;
             // exclusive prefix over the LPP lanes of this particle
@@ -683,7 +766,8 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
             }
         }
     }
-    if (lane == 0 && ncand < 0) atomicAdd(&N.status[4], 1);
+    });
+    if (lane == 0 && overflows) atomicAdd(&N.status[4], (int)overflows);
 }
 
 // ascending order within each list (insertion sort; lists are ~60 long)
@@ -706,16 +790,20 @@ template <class Args>
 inline void fill_common(sph_ctx *c, int64_t n, Args &a)
 {
     a.n = n;
-    a.T = c->tree;
+    a.tree = c->d_tree;
+    a.lstart = c->lstart;
+    a.work = c->d_work;
     a.box = c->box;
     a.nodes = c->nodes;
 }
 
-inline unsigned leaf_grid(int64_t L)
+// Persistent grid: a multiple of the XCD count, enough one-wave blocks to
+// fill every CU several times over, never more than there can be leaves.
+inline unsigned leaf_grid(int64_t n)
 {
-    // a multiple of the XCD count so every XCD gets the same number of blocks
-    int64_t per = (L + kXcds - 1) / kXcds;
-    return (unsigned)(per * kXcds);
+    int64_t blocks = std::min<int64_t>(n, 256 * 24);
+    blocks = ((blocks + kXcds - 1) / kXcds) * kXcds;
+    return (unsigned)blocks;
 }
 
 } // namespace
@@ -729,14 +817,28 @@ sph_status run_density(sph_ctx *c, int64_t n)
     a.fx = c->s.fx; a.fy = c->s.fy; a.fz = c->s.fz;
     a.h = c->s.h; a.rho = c->s.rho; a.omega = c->s.omega; a.nngb = c->s.nngb;
     a.status = c->d_status;
+    a.counts = c->d_counts;
     a.eta3 = c->p.eta * c->p.eta * c->p.eta;
     // FP32-pair mode: the density sum carries single-precision pair terms
     // (relative noise ~1e-7), so the Newton step cannot settle below a few
     // 1e-7; its stop tolerance is floored at 2e-6.
     a.h_rtol = c->p.precision == SPH_FP32_PAIR ? std::max(c->p.h_rtol, 2e-6) : c->p.h_rtol;
     a.max_iter = c->p.h_max_iter;
-    const unsigned grid = leaf_grid(c->tree.cnt[0]);
+    {
+        const void *req[] = {a.nodes, a.x, a.y, a.z, a.m, a.h, a.rho, a.omega, a.nngb, a.status,
+                             a.counts};
+        for (const void *q : req)
+            if (!q) return fail(c, SPH_EINVAL, "density: internal buffer not allocated");
+        if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
+            return fail(c, SPH_EINVAL, "density: offsets not allocated");
+        if (c->tree_n != n || !a.tree || !a.lstart || !a.work) return fail(c, SPH_ESTATE, "density: tree not built");
+    }
+    const unsigned grid = leaf_grid(n);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
+    sph_status zs = zero_counts(c, 2, 1);
+    if (zs == SPH_OK) zs = zero_counts(c, 4, 4);
+    if (zs == SPH_OK) zs = zero_work(c);
+    if (zs != SPH_OK) return zs;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_begin(c, 0, &e0, &e1);
     switch (c->p.leaf_size) {
@@ -769,9 +871,23 @@ sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy,
     a.ax = c->s.ax; a.ay = c->s.ay; a.az = c->s.az; a.du = c->s.du;
     a.vsig = c->s.vsig; a.dt = c->s.dt; a.nforce = c->s.nforce;
     a.status = c->d_status;
+    a.counts = c->d_counts;
     a.alpha = c->p.alpha_av; a.beta = c->p.beta_av; a.ccfl = c->p.c_cfl;
-    const unsigned grid = leaf_grid(c->tree.cnt[0]);
+    {
+        const void *req[] = {a.nodes, a.x, a.y, a.z, a.vx, a.vy, a.vz, a.m, a.h, a.hinv, a.rho,
+                             a.A, a.c, a.ax, a.ay, a.az, a.du, a.vsig, a.dt, a.nforce, a.status,
+                             a.counts};
+        for (const void *q : req)
+            if (!q) return fail(c, SPH_EINVAL, "forces: internal buffer not allocated");
+        if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
+            return fail(c, SPH_EINVAL, "forces: offsets not allocated");
+        if (c->tree_n != n || !a.tree || !a.lstart || !a.work) return fail(c, SPH_ESTATE, "forces: tree not built");
+    }
+    const unsigned grid = leaf_grid(n);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
+    sph_status zs = zero_counts(c, 3, 1);
+    if (zs == SPH_OK) zs = zero_work(c);
+    if (zs != SPH_OK) return zs;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_begin(c, 1, &e0, &e1);
     switch (c->p.leaf_size) {
@@ -806,8 +922,20 @@ sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_s
     a.idx = idx;
     a.cap = cap;
     a.status = c->d_status;
-    const unsigned grid = leaf_grid(c->tree.cnt[0]);
+    {
+        const void *req[] = {a.nodes, a.x, a.y, a.z, a.h, a.id, a.status};
+        for (const void *q : req)
+            if (!q) return fail(c, SPH_EINVAL, "neighbours: internal buffer not allocated");
+        if (!offsets && !counts_sorted) return fail(c, SPH_EINVAL, "neighbours: no counts");
+        if (offsets && cap > 0 && !idx) return fail(c, SPH_EINVAL, "neighbours: no idx");
+        if (c->tree_n != n || !a.tree || !a.lstart || !a.work) return fail(c, SPH_ESTATE, "neighbours: tree not built");
+    }
+    const unsigned grid = leaf_grid(n);
     const int pass = offsets ? 2 : 1;
+    {
+        sph_status zs = zero_work(c);
+        if (zs != SPH_OK) return zs;
+    }
     switch (c->p.leaf_size) {
     case 8: hipLaunchKernelGGL((k_neighbours<8>), dim3(grid), dim3(kWave), 0, c->stream, a, pass); break;
     case 32: hipLaunchKernelGGL((k_neighbours<32>), dim3(grid), dim3(kWave), 0, c->stream, a, pass); break;

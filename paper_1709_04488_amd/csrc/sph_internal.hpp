@@ -30,13 +30,16 @@ struct alignas(64) Node {
     double pad;
 };
 
+// Tree description, written on the device by the build (the leaf count is
+// data dependent) and read by every pair kernel.
 struct TreeInfo {
     int32_t nlev;                  // levels including the leaf level (level 0)
     int32_t leaf_size;
     int64_t n;                     // particles
     int64_t off[kMaxLevels];       // first node of each level in the node array
-    int64_t cnt[kMaxLevels];       // nodes per level
+    int64_t cnt[kMaxLevels];       // nodes per level (cnt[0] = leaves)
 };
+constexpr int kTreeWords = (int)(sizeof(TreeInfo) / 8);
 
 struct Box {
     int32_t periodic;
@@ -106,7 +109,13 @@ struct sph_ctx {
     double *d_part = nullptr;            // reduction partials
     sph::Node *nodes = nullptr;
     int64_t node_cap = 0;
-    sph::TreeInfo tree{};
+    sph::TreeInfo *d_tree = nullptr;    // device-resident tree description
+    uint32_t *lstart = nullptr;         // leaf -> first sorted particle, [L+1]
+    uint32_t *leaf_id = nullptr;        // sorted particle -> leaf
+    uint32_t *d_work = nullptr;         // per-XCD claim counters of the pair kernels
+    uint64_t *skeys = nullptr;          // sorted keys of the last build
+    uint32_t *scratch_u32 = nullptr;    // per-particle scratch (free sort buffer)
+    int64_t tree_n = -1;                // n of the tree on the device (-1: none)
     sph::Box box{};
 
     sph::Sorted s;       // working / resident arrays
@@ -120,7 +129,11 @@ struct sph_ctx {
     // resident state
     bool resident = false;
     double *d_scal = nullptr;   // [0] dt_next [1] dt_last [2] time [3] KE [4] TE [5..7] P
-    int64_t *d_counts = nullptr;// [0] density pairs [1] force pairs
+    // [0] sum nngb [1] sum nforce (last evaluation), [2] density pair
+    // evaluations summed over Newton-Raphson iterations, [3] force pair
+    // evaluations, [4] max Newton-Raphson iterations, [5] walk overflows,
+    // [6] candidate leaves swept by the density loop, [7] density tree walks
+    int64_t *d_counts = nullptr;
     double *h_scal = nullptr;   // pinned mirror
     double *dt_used_out = nullptr;
     int64_t steps = 0;
@@ -155,6 +168,7 @@ sph_status build_tree(sph_ctx *c, int64_t n);
 // Per-particle force record (A, c, hinv) from rho, omega, u.
 sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted);
 sph_status iota(sph_ctx *c, int64_t n, uint32_t *v);
+int64_t node_count_bound(int64_t n);
 
 // ---- pairs.hip ---------------------------------------------------------------
 sph_status run_density(sph_ctx *c, int64_t n);
@@ -178,6 +192,10 @@ sph_status kick_drift(sph_ctx *c, int64_t n, double dt_host);
 sph_status closing_kick(sph_ctx *c, int64_t n, double dt_host);
 sph_status reduce_dt(sph_ctx *c, int64_t n);
 sph_status reduce_diag(sph_ctx *c, int64_t n);
+// zero d_counts[first..first+count) with a kernel (capture-safe, no memset)
+sph_status zero_counts(sph_ctx *c, int first, int count);
+// zero the per-XCD claim counters of the persistent pair kernels
+sph_status zero_work(sph_ctx *c);
 // exclusive prefix sum in place over a[0..n], treating a[n] as 0 on input
 sph_status scan_offsets(sph_ctx *c, int64_t n, int64_t *a);
 

@@ -201,6 +201,11 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(int64_t n, int64_t *__res
     }
 }
 
+__global__ void k_zero_counts(int64_t *__restrict__ c, int first, int count)
+{
+    if ((int)threadIdx.x < count) c[first + threadIdx.x] = 0;
+}
+
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
 KdkArgs kdk_args(sph_ctx *c, int64_t n, double dt_host)
@@ -259,6 +264,23 @@ sph_status reduce_dt(sph_ctx *c, int64_t n)
     hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kRedThreads), 0, c->stream, nb, c->d_part,
                        c->d_scal);
     return hip_check(c, hipGetLastError(), "reduce_dt");
+}
+
+__global__ void k_zero_work(uint32_t *__restrict__ w)
+{
+    if (threadIdx.x < kXcds) w[threadIdx.x] = 0u;
+}
+
+sph_status zero_work(sph_ctx *c)
+{
+    hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(64), 0, c->stream, c->d_work);
+    return hip_check(c, hipGetLastError(), "zero_work");
+}
+
+sph_status zero_counts(sph_ctx *c, int first, int count)
+{
+    hipLaunchKernelGGL(k_zero_counts, dim3(1), dim3(64), 0, c->stream, c->d_counts, first, count);
+    return hip_check(c, hipGetLastError(), "zero_counts");
 }
 
 sph_status scan_offsets(sph_ctx *c, int64_t n, int64_t *a)

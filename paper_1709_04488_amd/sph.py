@@ -60,8 +60,10 @@ class _Stats(ctypes.Structure):
                 ("dt_next", ctypes.c_double), ("kinetic", ctypes.c_double),
                 ("thermal", ctypes.c_double), ("momentum", ctypes.c_double * 3),
                 ("steps", ctypes.c_int64), ("n_dens_pairs", ctypes.c_int64),
-                ("n_force_pairs", ctypes.c_int64), ("nr_iter_max", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("n_force_pairs", ctypes.c_int64), ("dens_pair_evals", ctypes.c_int64),
+                ("force_pair_evals", ctypes.c_int64), ("nr_iter_max", ctypes.c_int32),
+                ("walk_overflows", ctypes.c_int32), ("dens_leaf_visits", ctypes.c_int64),
+                ("dens_walks", ctypes.c_int64)]
 
 
 _lib = None
@@ -278,7 +280,9 @@ class Context:
                 "kinetic": st.kinetic, "thermal": st.thermal,
                 "momentum": tuple(st.momentum), "steps": st.steps,
                 "n_dens_pairs": st.n_dens_pairs, "n_force_pairs": st.n_force_pairs,
-                "nr_iter_max": st.nr_iter_max}
+                "dens_pair_evals": st.dens_pair_evals, "force_pair_evals": st.force_pair_evals,
+                "nr_iter_max": st.nr_iter_max, "walk_overflows": st.walk_overflows,
+                "dens_leaf_visits": st.dens_leaf_visits, "dens_walks": st.dens_walks}
 
     def neighbours(self, p: Particles, mode: int, cap: int = None):
         """CSR lists at the given h -> (offsets int64[n+1], idx int32) on the device."""

@@ -61,4 +61,4 @@ def test_struct_layouts_match_header():
     from paper_1709_04488_amd import sph
     assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4
     assert ctypes.sizeof(sph._Particles) == 8 + 21 * 8
-    assert ctypes.sizeof(sph._Stats) == 8 * 8 + 3 * 8 + 8
+    assert ctypes.sizeof(sph._Stats) == 8 * 8 + 5 * 8 + 8 + 2 * 8
