@@ -1,13 +1,21 @@
 // Pair loops: density + Newton-Raphson h solve, hydro forces, neighbour export.
 //
-// Work decomposition (the GPU analogue of the paper's per-leaf-cell
-// neighbour gathering, section 4.2, with one leaf as the unit of work as in
-// its OpenMP loop, section 5.2.1): one wavefront per home leaf of G sorted
+// Work decomposition (the GPU analogue of the paper's per-leaf-cell neighbour
+// gathering, section 4.2, with a leaf as the unit of work as in its OpenMP
+// loop, section 5.2.1): one wavefront per home leaf of at most G sorted
 // particles, 64/G lanes per particle.  The wave walks the box tree to collect
-// the leaves that can hold neighbours of any of its particles into an LDS
-// list, then every lane sweeps its share of the particles of those leaves.
-// Each output is written by exactly one lane and summed in a fixed order, so
-// results are deterministic and need no atomics.
+// the leaves that can hold neighbours of its particles into an LDS list.
+// Candidate leaves are then handled 64/G at a time (64 candidate particles):
+//   stage  -- one coalesced load per field brings their positions into LDS;
+//   test   -- every lane tests its share of the staged candidates against its
+//             particle and records each hit as a one-byte slot index in its
+//             own LDS hit buffer (no pair arithmetic yet);
+//   flush  -- every lane evaluates the pair terms of its recorded hits.
+// The test is cheap and runs for every candidate; the expensive pair terms
+// run only for hits, with the lanes compacted (a wave-wide branch on "any
+// lane hit" would otherwise execute them for almost every candidate).  Each
+// output is accumulated by its own lanes in a fixed order, so results are
+// deterministic and need no atomics.
 #include "sph_internal.hpp"
 
 #include <algorithm>
@@ -25,6 +33,15 @@ __device__ inline void wave_lds_sync()
 __device__ inline double wave_max(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ inline int wave_max_int(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        int w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
     return v;
 }
 
@@ -133,31 +150,51 @@ __device__ inline float min_image_f(float d, float L, float half)
     return d;
 }
 
+// M4: f(q) = a^3/4 - b^3, f'(q) = 3 b^2 - 3/4 a^2 with a = (2-q)_+, b = (1-q)_+
+template <class T>
+__device__ inline void m4(T qq, T &f, T &df)
+{
+    T a = qq < T(2) ? T(2) - qq : T(0);
+    T b = qq < T(1) ? T(1) - qq : T(0);
+    T a2 = a * a, b2 = b * b;
+    f = T(0.25) * a2 * a - b2 * b;
+    df = T(3) * b2 - T(0.75) * a2;
+}
+
+// ---------------------------------------------------------------------------
+// Tree walk
+// ---------------------------------------------------------------------------
 struct WalkBuf {
     uint32_t a[kFront];
     uint32_t b[kFront];
+    uint32_t tmp[kWave];
 };
 
-// Breadth-first walk of the 8-ary tree, 64 child tests per step.  Returns the
-// number of candidate leaves (list in *out), or -1 if a frontier overflowed
-// the LDS capacity (then the caller scans every leaf).
+// Breadth-first walk of the 8-ary tree, 64 child tests per step.  Result: n
+// nodes of level `lev` in `list` that pass the test.  Normally lev = 0 (the
+// candidate leaves).  If expanding a level would overflow the LDS frontier,
+// the walk stops there and returns that level's nodes; the caller then tests
+// the leaves under each of them directly (bounded extra work instead of a
+// scan of every leaf).
+struct WalkResult {
+    int n;
+    int lev;
+    const uint32_t *list;
+};
+
 template <class Test>
-__device__ int walk(const TreeInfo &T, const Node *nodes, Test test, WalkBuf &wb,
-                    const uint32_t **out)
+__device__ WalkResult walk(const TreeInfo &T, const Node *nodes, Test test, WalkBuf &wb)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t lt = __lanemask_lt();
     uint32_t *cur = wb.a, *nxt = wb.b;
-    int top = T.nlev - 1;
-    if (top == 0) {
-        bool pass = lane == 0 && test(nodes[0]);
-        if (lane == 0) cur[0] = 0;
-        wave_lds_sync();
-        *out = cur;
-        return __ballot(pass) ? 1 : 0;
-    }
+    const int top = T.nlev - 1;
     if (lane == 0) cur[0] = 0;
     wave_lds_sync();
+    if (top == 0) {
+        bool pass = lane == 0 && test(nodes[0]);
+        return WalkResult{__ballot(pass) ? 1 : 0, 0, cur};
+    }
     int ncur = 1;
     for (int lev = top; lev > 0; lev--) {
         const Node *cl = nodes + T.off[lev - 1];
@@ -176,43 +213,55 @@ __device__ int walk(const TreeInfo &T, const Node *nodes, Test test, WalkBuf &wb
             nout += (int)__popcll(mask);
         }
         wave_lds_sync();
-        if (nout > kFront) return -1;
+        if (nout > kFront) return WalkResult{ncur, lev, cur};
         uint32_t *tmp = cur;
         cur = nxt;
         nxt = tmp;
         ncur = nout;
         if (ncur == 0) break;
     }
-    *out = cur;
-    return ncur;
+    return WalkResult{ncur, 0, cur};
 }
 
-// Visit every candidate leaf: from the LDS list, or (after an overflow) by
-// testing all leaves 64 at a time.  fn(c) is called wave-uniformly.
-template <class Test, class Fn>
-__device__ void for_each_leaf(const TreeInfo &T, const Node *nodes, int ncand,
-                              const uint32_t *list, Test test, Fn fn)
+// Visit the candidate leaves in groups of at most NL: fn(leaves, count) with
+// a wave-uniform count.  After a truncated walk the leaves under each
+// returned node are tested 64 at a time and the passing ones grouped.
+template <int NL, class Test, class Fn>
+__device__ int64_t for_each_leaf_group(const TreeInfo &T, const Node *nodes, const WalkResult &wr,
+                                       Test test, WalkBuf &wb, Fn fn)
 {
-    if (ncand >= 0) {
-        for (int t = 0; t < ncand; t++) fn((int64_t)list[t]);
-        return;
+    if (wr.lev == 0) {
+        for (int t0 = 0; t0 < wr.n; t0 += NL) fn(wr.list + t0, wr.n - t0 < NL ? wr.n - t0 : NL);
+        return wr.n;
     }
     const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t lt = __lanemask_lt();
     const int64_t L = T.cnt[0];
-    for (int64_t b = 0; b < L; b += kWave) {
-        int64_t c = b + lane;
-        uint64_t mask = __ballot(c < L && test(nodes[c]));
-        while (mask) {
-            int k = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            fn(b + k);
+    int64_t span = 1;
+    for (int l = 0; l < wr.lev; l++) span *= 8;
+    int64_t tested = 0;
+    for (int k = 0; k < wr.n; k++) {
+        const int64_t b0 = (int64_t)wr.list[k] * span;
+        const int64_t b1 = b0 + span < L ? b0 + span : L;
+        for (int64_t b = b0; b < b1; b += kWave) {
+            const int64_t c = b + lane;
+            const bool pass = c < b1 && test(nodes[c]);
+            const uint64_t mask = __ballot(pass);
+            if (pass) wb.tmp[__popcll(mask & lt)] = (uint32_t)c;
+            wave_lds_sync();
+            const int cnt = (int)__popcll(mask);
+            for (int t0 = 0; t0 < cnt; t0 += NL) fn(wb.tmp + t0, cnt - t0 < NL ? cnt - t0 : NL);
+            wave_lds_sync();
+            tested += b1 - b < kWave ? b1 - b : kWave;
         }
     }
+    return tested;
 }
 
 // Per candidate leaf: the periodic shift that the minimum image gives every
-// pair (i in home, j in c) closer than 2 hcov, when that shift is unique;
-// otherwise the pair loop applies the minimum image pair by pair.
+// pair (i in home, j in the leaf) closer than 2 hcov, when that shift is
+// unique (both boxes small against the period); otherwise the pair loop
+// applies the minimum image pair by pair.
 struct Shift {
     double s[3];
     bool per_pair;
@@ -229,6 +278,116 @@ __device__ inline Shift leaf_shift(const Node &home, const Node &cand, const Box
         if (!(reach < 0.49 * bx.len[a])) sh.per_pair = true;
     }
     return sh;
+}
+
+// Staged group of NL candidate leaves (64 candidate particles).  Per staged
+// leaf: how the separation is formed (shift vector or per-pair minimum image,
+// FP32 offset between leaf centres) and how many particles it holds.
+template <int NL>
+struct Stage {
+    double x[kWave], y[kWave], z[kWave], w[kWave];   // w: mass (density) or h (forces)
+    float fx[kWave], fy[kWave], fz[kWave];
+    uint32_t j[kWave];
+    double sx[NL], sy[NL], sz[NL];
+    float ox[NL], oy[NL], oz[NL];
+    int32_t jn[NL];
+    int32_t per_pair[NL];
+};
+
+// Stage `count` candidate leaves; lane l fills slot l % G of leaf l / G.
+template <int G, int NL, int PREC>
+__device__ inline void stage_group(Stage<NL> &S, const uint32_t *leaves, int count,
+                                   const uint32_t *__restrict__ lstart, const Node *__restrict__ nodes,
+                                   const Node &home, const Box &bx, double hcov,
+                                   const double *__restrict__ x, const double *__restrict__ y,
+                                   const double *__restrict__ z, const double *__restrict__ w,
+                                   const float *__restrict__ fx, const float *__restrict__ fy,
+                                   const float *__restrict__ fz)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int k = lane / G, slot = lane % G;
+    int jn = 0;
+    if (k < count) {
+        const uint32_t c = leaves[k];
+        const int64_t j0 = lstart[c];
+        jn = (int)(lstart[c + 1] - j0);
+        if (slot < jn) {
+            const int64_t j = j0 + slot;
+            S.x[lane] = x[j];
+            S.y[lane] = y[j];
+            S.z[lane] = z[j];
+            S.w[lane] = w[j];
+            if (PREC == SPH_FP32_PAIR) {
+                S.fx[lane] = fx[j];
+                S.fy[lane] = fy[j];
+                S.fz[lane] = fz[j];
+            }
+            S.j[lane] = (uint32_t)j;
+        }
+        if (slot == 0) {
+            const Node cand = nodes[c];
+            // hcov < 0: symmetric force criterion, reach 2 max(h over both leaves)
+            const Shift sh = leaf_shift(home, cand, bx, hcov < 0.0 ? fmax(home.hmax, cand.hmax) : hcov);
+            S.sx[k] = sh.s[0];
+            S.sy[k] = sh.s[1];
+            S.sz[k] = sh.s[2];
+            S.per_pair[k] = sh.per_pair ? 1 : 0;
+            S.jn[k] = jn;
+            if (PREC == SPH_FP32_PAIR) {
+                S.ox[k] = (float)((0.5 * (home.lo[0] + home.hi[0]) - 0.5 * (cand.lo[0] + cand.hi[0])) +
+                                  (sh.per_pair ? 0.0 : sh.s[0]));
+                S.oy[k] = (float)((0.5 * (home.lo[1] + home.hi[1]) - 0.5 * (cand.lo[1] + cand.hi[1])) +
+                                  (sh.per_pair ? 0.0 : sh.s[1]));
+                S.oz[k] = (float)((0.5 * (home.lo[2] + home.hi[2]) - 0.5 * (cand.lo[2] + cand.hi[2])) +
+                                  (sh.per_pair ? 0.0 : sh.s[2]));
+            }
+        }
+    } else if (slot == 0 && k < NL) {
+        S.jn[k] = 0;
+    }
+    wave_lds_sync();
+}
+
+// Separation of home particle i and staged entry s (leaf k = s / G); the same
+// expression serves the test and the flush, so both see identical bits.
+struct Home {
+    double x, y, z;
+    float fx, fy, fz;
+};
+
+template <int G, int NL, int PREC>
+__device__ inline void separation(const Stage<NL> &S, const Box &bx, const Home &hm, int s,
+                                  double &dx, double &dy, double &dz, double &r2)
+{
+    const int k = s / G;
+    if (PREC == SPH_FP64) {
+        dx = hm.x - S.x[s];
+        dy = hm.y - S.y[s];
+        dz = hm.z - S.z[s];
+        if (S.per_pair[k]) {
+            dx = min_image(dx, bx.len[0], bx.half[0]);
+            dy = min_image(dy, bx.len[1], bx.half[1]);
+            dz = min_image(dz, bx.len[2], bx.half[2]);
+        } else {
+            dx += S.sx[k];
+            dy += S.sy[k];
+            dz += S.sz[k];
+        }
+        r2 = exact_r2(dx, dy, dz);
+    } else {
+        float fdx = (hm.fx - S.fx[s]) + S.ox[k];
+        float fdy = (hm.fy - S.fy[s]) + S.oy[k];
+        float fdz = (hm.fz - S.fz[s]) + S.oz[k];
+        if (S.per_pair[k]) {
+            fdx = min_image_f(fdx, (float)bx.len[0], (float)bx.half[0]);
+            fdy = min_image_f(fdy, (float)bx.len[1], (float)bx.half[1]);
+            fdz = min_image_f(fdz, (float)bx.len[2], (float)bx.half[2]);
+        }
+        dx = fdx;
+        dy = fdy;
+        dz = fdz;
+        r2 = (double)(fdx * fdx + fdy * fdy + fdz * fdz);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -249,27 +408,20 @@ struct DensArgs {
     int64_t *counts;
     double eta3;
     double h_rtol;
+    double walk_margin;
     int32_t max_iter;
 };
-
-// M4: f(q) = a^3/4 - b^3, f'(q) = 3 b^2 - 3/4 a^2 with a = (2-q)_+, b = (1-q)_+
-template <class T>
-__device__ inline void m4(T qq, T &f, T &df)
-{
-    T a = qq < T(2) ? T(2) - qq : T(0);
-    T b = qq < T(1) ? T(1) - qq : T(0);
-    T a2 = a * a, b2 = b * b;
-    f = T(0.25) * a2 * a - b2 * b;
-    df = T(3) * b2 - T(0.75) * a2;
-}
 
 template <int G, int PREC>
 __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
 {
-    constexpr int LPP = kWave / G;
-    constexpr int PER = G / LPP;
+    constexpr int LPP = kWave / G;   // lanes per home particle
+    constexpr int NL = LPP;          // candidate leaves staged per group
+    constexpr int PER = G / LPP;     // staged entries per lane per staged leaf
     __shared__ WalkBuf wb;
     __shared__ TreeInfo T;
+    __shared__ Stage<NL> S;
+    __shared__ uint8_t hits[G][kWave];   // up to NL * PER = G hits per lane per group
     load_tree(A.tree, T);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
@@ -277,169 +429,151 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
     int64_t evals = 0, walks = 0, visits = 0, overflows = 0;
     int iter_max = 0;
     for_each_home_leaf(T.cnt[0], A.work, [&](int64_t leaf) {
-    const int64_t first = A.lstart[leaf];
-    const int nhome = (int)(A.lstart[leaf + 1] - first);
-    const int64_t i = first + p;
-    const bool active = p < nhome;
-    const int64_t ii = active ? i : first;
-    const double xi = A.x[ii], yi = A.y[ii], zi = A.z[ii], mi = A.m[ii];
-    float fxi = 0.f, fyi = 0.f, fzi = 0.f;
-    if (PREC == SPH_FP32_PAIR) { fxi = A.fx[ii]; fyi = A.fy[ii]; fzi = A.fz[ii]; }
-    const Node home = A.nodes[leaf];
-    double h = A.h[ii];
-    double lo_b = 0.0, hi_b = INFINITY;
-    bool conv = !active;
-    double h_out = h, rho_out = 0.0, om_out = 1.0;
-    int n_out = 0;
+        const int64_t first = A.lstart[leaf];
+        const int nhome = (int)(A.lstart[leaf + 1] - first);
+        const int64_t i = first + p;
+        const bool active = p < nhome;
+        const int64_t ii = active ? i : first;
+        Home hm;
+        hm.x = A.x[ii];
+        hm.y = A.y[ii];
+        hm.z = A.z[ii];
+        hm.fx = hm.fy = hm.fz = 0.f;
+        if (PREC == SPH_FP32_PAIR) { hm.fx = A.fx[ii]; hm.fy = A.fy[ii]; hm.fz = A.fz[ii]; }
+        const double mi = A.m[ii];
+        const Node home = A.nodes[leaf];
+        double h = A.h[ii];
+        double lo_b = 0.0, hi_b = INFINITY;
+        bool conv = !active;
+        double h_out = h, rho_out = 0.0, om_out = 1.0;
+        int n_out = 0;
 
-    double hcov = 1.25 * wave_max(active ? h : 0.0);
-    auto make_test = [&](double hc) {
-        double R = 2.0 * hc * (1.0 + 1e-10);
-        double R2 = R * R;
-        return [&bx, &home, R2](const Node &nd) { return box_gap2(home.lo, home.hi, nd, bx) < R2; };
-    };
-    const uint32_t *list = nullptr;
-    int ncand = walk(T, A.nodes, make_test(hcov), wb, &list);
-    walks++;
-    if (ncand < 0) overflows++;
-    int iter = 0;
-    for (;;) {
-        double s0 = 0.0, s2 = 0.0;
-        int cnt = 0;
-        const double hinv = 1.0 / h;
-        const double h2x4 = (2.0 * h) * (2.0 * h);
-        const float hinvf = (float)hinv, h2x4f = (float)h2x4;
-        auto body = [&](int64_t c) {
-            const Node cand = A.nodes[c];
-            const Shift sh = leaf_shift(home, cand, bx, hcov);
-            const int64_t j0 = A.lstart[c];
-            const int jn = (int)(A.lstart[c + 1] - j0);
-            if (PREC == SPH_FP64) {
+        double hcov = A.walk_margin * wave_max(active ? h : 0.0);
+        auto make_test = [&](double hc) {
+            const double R = 2.0 * hc * (1.0 + 1e-10);
+            const double R2 = R * R;
+            return [&bx, &home, R2](const Node &nd) { return box_gap2(home.lo, home.hi, nd, bx) < R2; };
+        };
+        WalkResult wr = walk(T, A.nodes, make_test(hcov), wb);
+        walks++;
+        if (wr.lev) overflows++;
+        int iter = 0;
+        for (;;) {
+            double s0 = 0.0, s2 = 0.0;
+            int cnt = 0;
+            const double hinv = 1.0 / h;
+            const double h2x4 = (2.0 * h) * (2.0 * h);
+            const float h2x4f = (float)h2x4;
+            auto group = [&](const uint32_t *leaves, int count) {
+                stage_group<G, NL, PREC>(S, leaves, count, A.lstart, A.nodes, home, bx, hcov, A.x, A.y,
+                                         A.z, A.m, A.fx, A.fy, A.fz);
+                // test: record hits as slot indices
+                int nh = 0;
 #pragma unroll
-                for (int t = 0; t < PER; t++) {
-                    const int jj = q + LPP * t;
-                    if (jj < jn) {
-                        const int64_t j = j0 + jj;
-                        double dx = xi - A.x[j], dy = yi - A.y[j], dz = zi - A.z[j];
-                        if (sh.per_pair) {
-                            dx = min_image(dx, bx.len[0], bx.half[0]);
-                            dy = min_image(dy, bx.len[1], bx.half[1]);
-                            dz = min_image(dz, bx.len[2], bx.half[2]);
-                        } else {
-                            dx += sh.s[0];
-                            dy += sh.s[1];
-                            dz += sh.s[2];
+                for (int k = 0; k < NL; k++) {
+                    const int jn = S.jn[k];
+#pragma unroll
+                    for (int t = 0; t < PER; t++) {
+                        const int slot = q + LPP * t;
+                        const int s = k * G + slot;
+                        if (slot < jn) {
+                            double dx, dy, dz, r2;
+                            separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
+                            const bool in = PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f;
+                            if (in) hits[nh++][lane] = (uint8_t)s;
                         }
-                        const double r2 = exact_r2(dx, dy, dz);
-                        if (r2 < h2x4) {
-                            const double mj = A.m[j];
+                    }
+                }
+                // flush: pair terms of the recorded hits
+                const int nmax = wave_max_int(nh);
+                for (int e = 0; e < nmax; e++) {
+                    if (e < nh) {
+                        const int s = hits[e][lane];
+                        double dx, dy, dz, r2;
+                        separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
+                        const double mj = S.w[s];
+                        if (PREC == SPH_FP64) {
                             double f, df;
                             const double qq = sqrt(r2) * hinv;
                             m4(qq, f, df);
                             s0 += mj * f;
                             s2 += mj * (qq * df);
-                            cnt += (j != i);
-                        }
-                    }
-                }
-            } else {
-                const float ox = (float)((0.5 * (home.lo[0] + home.hi[0]) -
-                                          0.5 * (cand.lo[0] + cand.hi[0])) + (sh.per_pair ? 0.0 : sh.s[0]));
-                const float oy = (float)((0.5 * (home.lo[1] + home.hi[1]) -
-                                          0.5 * (cand.lo[1] + cand.hi[1])) + (sh.per_pair ? 0.0 : sh.s[1]));
-                const float oz = (float)((0.5 * (home.lo[2] + home.hi[2]) -
-                                          0.5 * (cand.lo[2] + cand.hi[2])) + (sh.per_pair ? 0.0 : sh.s[2]));
-#pragma unroll
-                for (int t = 0; t < PER; t++) {
-                    const int jj = q + LPP * t;
-                    if (jj < jn) {
-                        const int64_t j = j0 + jj;
-                        float dx = (fxi - A.fx[j]) + ox, dy = (fyi - A.fy[j]) + oy,
-                              dz = (fzi - A.fz[j]) + oz;
-                        if (sh.per_pair) {
-                            dx = min_image_f(dx, (float)bx.len[0], (float)bx.half[0]);
-                            dy = min_image_f(dy, (float)bx.len[1], (float)bx.half[1]);
-                            dz = min_image_f(dz, (float)bx.len[2], (float)bx.half[2]);
-                        }
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        if (r2 < h2x4f) {
-                            const double mj = A.m[j];
+                        } else {
                             float f, df;
-                            const float qq = sqrtf(r2) * hinvf;
+                            const float qq = sqrtf((float)r2) * (float)hinv;
                             m4(qq, f, df);
                             s0 += mj * (double)f;
                             s2 += mj * (double)(qq * df);
-                            cnt += (j != i);
                         }
+                        cnt += (S.j[s] != (uint32_t)i);
                     }
                 }
-            }
-        };
-        for_each_leaf(T, A.nodes, ncand, list, make_test(hcov), body);
-        visits += ncand >= 0 ? ncand : T.cnt[0];
-        if (!conv) evals += cnt;
+                wave_lds_sync();
+            };
+            visits += for_each_leaf_group<NL>(T, A.nodes, wr, make_test(hcov), wb, group);
+            if (!conv) evals += cnt;
 #pragma unroll
-        for (int o = 1; o < LPP; o <<= 1) {
-            s0 += __shfl_xor(s0, o);
-            s2 += __shfl_xor(s2, o);
-            cnt += __shfl_xor(cnt, o);
-        }
-        if (!conv) {
-            // g(h) = h^3 rho(h) - eta^3 m = sigma sum m f - eta^3 m, non-decreasing;
-            // g'(h) = -(sigma/h) sum m q f'(q) >= 0
-            const double g = kSigma * s0 - A.eta3 * mi;
-            const double gp = -kSigma * s2 * hinv;
-            h_out = h;
-            rho_out = kSigma * s0 * hinv * hinv * hinv;
-            om_out = -s2 / (3.0 * s0);
-            n_out = cnt;
-            // the Newton step decides convergence before any safeguard: a step
-            // below the tolerance (down to a zero step at the root) is final
-            const double step = gp > 0.0 ? g / gp : INFINITY;
-            if (g == 0.0 || fabs(step) <= A.h_rtol * h) {
-                conv = true;
-            } else {
-                if (g < 0.0) lo_b = fmax(lo_b, h); else hi_b = fmin(hi_b, h);
-                double hn = gp > 0.0 ? h - step : (g < 0.0 ? 2.0 * h : 0.5 * h);
-                hn = fmin(fmax(hn, 0.5 * h), 2.0 * h);
-                // outside the bracket of known signs: bisect it
-                if (!(hn > lo_b && hn < hi_b)) hn = hi_b < INFINITY ? 0.5 * (lo_b + hi_b) : 2.0 * h;
-                if (!(hn == hn)) conv = true;
-                else h = hn;
+            for (int o = 1; o < LPP; o <<= 1) {
+                s0 += __shfl_xor(s0, o);
+                s2 += __shfl_xor(s2, o);
+                cnt += __shfl_xor(cnt, o);
+            }
+            if (!conv) {
+                // g(h) = h^3 rho(h) - eta^3 m = sigma sum m f - eta^3 m, non-decreasing;
+                // g'(h) = -(sigma/h) sum m q f'(q) >= 0
+                const double g = kSigma * s0 - A.eta3 * mi;
+                const double gp = -kSigma * s2 * hinv;
+                h_out = h;
+                rho_out = kSigma * s0 * hinv * hinv * hinv;
+                om_out = -s2 / (3.0 * s0);
+                n_out = cnt;
+                // the Newton step decides convergence before any safeguard: a step
+                // below the tolerance (down to a zero step at the root) is final
+                const double step = gp > 0.0 ? g / gp : INFINITY;
+                if (g == 0.0 || fabs(step) <= A.h_rtol * h) {
+                    conv = true;
+                } else {
+                    if (g < 0.0) lo_b = fmax(lo_b, h); else hi_b = fmin(hi_b, h);
+                    double hn = gp > 0.0 ? h - step : (g < 0.0 ? 2.0 * h : 0.5 * h);
+                    hn = fmin(fmax(hn, 0.5 * h), 2.0 * h);
+                    // outside the bracket of known signs: bisect it
+                    if (!(hn > lo_b && hn < hi_b)) hn = hi_b < INFINITY ? 0.5 * (lo_b + hi_b) : 2.0 * h;
+                    if (!(hn == hn)) conv = true;
+                    else h = hn;
+                }
+            }
+            iter++;
+            if (__ballot(!conv) == 0ull || iter >= A.max_iter) break;
+            const double hmx = wave_max(conv ? 0.0 : h);
+            if (hmx > hcov) {
+                hcov = A.walk_margin * hmx;
+                wr = walk(T, A.nodes, make_test(hcov), wb);
+                walks++;
+                if (wr.lev) overflows++;
             }
         }
-        iter++;
-        if (__ballot(!conv) == 0ull || iter >= A.max_iter) break;
-        const double hm = wave_max(conv ? 0.0 : h);
-        if (hm > hcov) {
-            hcov = 1.25 * hm;
-            ncand = walk(T, A.nodes, make_test(hcov), wb, &list);
-            walks++;
-            if (ncand < 0) overflows++;
-        }
-    }
-    if (active && q == 0) {
-        A.h[i] = h_out;
-        A.rho[i] = rho_out;
-        A.omega[i] = om_out;
-        A.nngb[i] = n_out;
-        bool bad = !isfinite(h_out) || !isfinite(rho_out) || !isfinite(om_out) || !(rho_out > 0.0);
-        if (bad) {
-            atomicOr(&A.status[0], kFlagNonFinite);
-            atomicAdd(&A.status[2], 1);
-        } else if (!conv) {
-            atomicOr(&A.status[0], kFlagNotConverged);
-            atomicAdd(&A.status[1], 1);
-        }
-        if (bx.periodic) {
-            double Lmin = fmin(fmin(bx.len[0], bx.len[1]), bx.len[2]);
-            if (!(4.0 * h_out < Lmin)) {
-                atomicOr(&A.status[0], kFlagStencil);
-                atomicAdd(&A.status[3], 1);
+        if (active && q == 0) {
+            A.h[i] = h_out;
+            A.rho[i] = rho_out;
+            A.omega[i] = om_out;
+            A.nngb[i] = n_out;
+            bool bad = !isfinite(h_out) || !isfinite(rho_out) || !isfinite(om_out) || !(rho_out > 0.0);
+            if (bad) {
+                atomicOr(&A.status[0], kFlagNonFinite);
+                atomicAdd(&A.status[2], 1);
+            } else if (!conv) {
+                atomicOr(&A.status[0], kFlagNotConverged);
+                atomicAdd(&A.status[1], 1);
+            }
+            if (bx.periodic) {
+                double Lmin = fmin(fmin(bx.len[0], bx.len[1]), bx.len[2]);
+                if (!(4.0 * h_out < Lmin)) {
+                    atomicOr(&A.status[0], kFlagStencil);
+                    atomicAdd(&A.status[3], 1);
+                }
             }
         }
-    }
-    iter_max = iter > iter_max ? iter : iter_max;
+        iter_max = iter > iter_max ? iter : iter_max;
     });
     for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
     if (lane == 0) {
@@ -474,182 +608,173 @@ template <int G, int PREC>
 __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
 {
     constexpr int LPP = kWave / G;
+    constexpr int NL = LPP;
     constexpr int PER = G / LPP;
     __shared__ WalkBuf wb;
     __shared__ TreeInfo T;
+    __shared__ Stage<NL> S;
+    __shared__ uint8_t hits[G][kWave];
     load_tree(F.tree, T);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
     const Box &bx = F.box;
+    const double alpha = F.alpha, beta = F.beta;
     int64_t pairs_total = 0, overflows = 0;
     for_each_home_leaf(T.cnt[0], F.work, [&](int64_t leaf) {
-    const int64_t first = F.lstart[leaf];
-    const int nhome = (int)(F.lstart[leaf + 1] - first);
-    const int64_t i = first + p;
-    const bool active = p < nhome;
-    const int64_t ii = active ? i : first;
-    const double xi = F.x[ii], yi = F.y[ii], zi = F.z[ii];
-    const double vxi = F.vx[ii], vyi = F.vy[ii], vzi = F.vz[ii];
-    const double hi = F.h[ii], hinvi = F.hinv[ii], rhoi = F.rho[ii], Ai = F.A[ii], ci = F.c[ii];
-    const double hi2x4 = (2.0 * hi) * (2.0 * hi);
-    const double gfi = kSigma * (hinvi * hinvi) * (hinvi * hinvi);
-    float fxi = 0.f, fyi = 0.f, fzi = 0.f;
-    if (PREC == SPH_FP32_PAIR) { fxi = F.fx[ii]; fyi = F.fy[ii]; fzi = F.fz[ii]; }
-    const Node home = F.nodes[leaf];
-    // symmetric criterion: a node can hold force neighbours of the home leaf
-    // if its box is closer than 2 max(h over home, h over node)
-    auto test = [&bx, &home](const Node &nd) {
-        double R = 2.0 * fmax(home.hmax, nd.hmax) * (1.0 + 1e-10);
-        return box_gap2(home.lo, home.hi, nd, bx) < R * R;
-    };
-    const uint32_t *list = nullptr;
-    int ncand = walk(T, F.nodes, test, wb, &list);
-    if (ncand < 0) overflows++;
+        const int64_t first = F.lstart[leaf];
+        const int nhome = (int)(F.lstart[leaf + 1] - first);
+        const int64_t i = first + p;
+        const bool active = p < nhome;
+        const int64_t ii = active ? i : first;
+        Home hm;
+        hm.x = F.x[ii];
+        hm.y = F.y[ii];
+        hm.z = F.z[ii];
+        hm.fx = hm.fy = hm.fz = 0.f;
+        if (PREC == SPH_FP32_PAIR) { hm.fx = F.fx[ii]; hm.fy = F.fy[ii]; hm.fz = F.fz[ii]; }
+        const double vxi = F.vx[ii], vyi = F.vy[ii], vzi = F.vz[ii];
+        const double hi = F.h[ii], hinvi = F.hinv[ii], rhoi = F.rho[ii], Ai = F.A[ii], ci = F.c[ii];
+        const double hi2x4 = (2.0 * hi) * (2.0 * hi);
+        const double gfi = kSigma * (hinvi * hinvi) * (hinvi * hinvi);
+        const float hinvif = (float)hinvi;
+        const float gfif = (float)kSigma * (hinvif * hinvif) * (hinvif * hinvif);
+        const Node home = F.nodes[leaf];
+        // symmetric criterion: a node can hold force neighbours of the home leaf
+        // if its box is closer than 2 max(h over home, h over node)
+        auto test = [&bx, &home](const Node &nd) {
+            const double R = 2.0 * fmax(home.hmax, nd.hmax) * (1.0 + 1e-10);
+            return box_gap2(home.lo, home.hi, nd, bx) < R * R;
+        };
+        const WalkResult wr = walk(T, F.nodes, test, wb);
+        if (wr.lev) overflows++;
 
-    double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
-    int cnt = 0;
-    const double alpha = F.alpha, beta = F.beta;
-    auto body = [&](int64_t c) {
-        const Node cand = F.nodes[c];
-        const Shift sh = leaf_shift(home, cand, bx, fmax(home.hmax, cand.hmax));
-        const int64_t j0 = F.lstart[c];
-        const int jn = (int)(F.lstart[c + 1] - j0);
-        float ox = 0.f, oy = 0.f, oz = 0.f;
-        if (PREC == SPH_FP32_PAIR) {
-            ox = (float)((0.5 * (home.lo[0] + home.hi[0]) - 0.5 * (cand.lo[0] + cand.hi[0])) +
-                         (sh.per_pair ? 0.0 : sh.s[0]));
-            oy = (float)((0.5 * (home.lo[1] + home.hi[1]) - 0.5 * (cand.lo[1] + cand.hi[1])) +
-                         (sh.per_pair ? 0.0 : sh.s[1]));
-            oz = (float)((0.5 * (home.lo[2] + home.hi[2]) - 0.5 * (cand.lo[2] + cand.hi[2])) +
-                         (sh.per_pair ? 0.0 : sh.s[2]));
-        }
+        double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
+        int cnt = 0;
+        auto group = [&](const uint32_t *leaves, int count) {
+            stage_group<G, NL, PREC>(S, leaves, count, F.lstart, F.nodes, home, bx, -1.0, F.x, F.y,
+                                     F.z, F.h, F.fx, F.fy, F.fz);
+            int nh = 0;
 #pragma unroll
-        for (int t = 0; t < PER; t++) {
-            const int jj = q + LPP * t;
-            if (jj >= jn) continue;
-            const int64_t j = j0 + jj;
-            const double hj = F.h[j];
-            const double hj2x4 = (2.0 * hj) * (2.0 * hj);
-            if (PREC == SPH_FP64) {
-                double dx = xi - F.x[j], dy = yi - F.y[j], dz = zi - F.z[j];
-                if (sh.per_pair) {
-                    dx = min_image(dx, bx.len[0], bx.half[0]);
-                    dy = min_image(dy, bx.len[1], bx.half[1]);
-                    dz = min_image(dz, bx.len[2], bx.half[2]);
-                } else {
-                    dx += sh.s[0];
-                    dy += sh.s[1];
-                    dz += sh.s[2];
+            for (int k = 0; k < NL; k++) {
+                const int jn = S.jn[k];
+#pragma unroll
+                for (int t = 0; t < PER; t++) {
+                    const int slot = q + LPP * t;
+                    const int s = k * G + slot;
+                    if (slot < jn) {
+                        double dx, dy, dz, r2;
+                        separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
+                        const double hj = S.w[s];
+                        const double hj2x4 = (2.0 * hj) * (2.0 * hj);
+                        bool in;
+                        if (PREC == SPH_FP64) in = r2 < hi2x4 || r2 < hj2x4;
+                        else in = (float)r2 < (float)hi2x4 || (float)r2 < (float)hj2x4;
+                        if (in && S.j[s] != (uint32_t)i) hits[nh++][lane] = (uint8_t)s;
+                    }
                 }
-                const double r2 = exact_r2(dx, dy, dz);
-                if (!((r2 < hi2x4 || r2 < hj2x4) && j != i)) continue;
+            }
+            const int nmax = wave_max_int(nh);
+            for (int e = 0; e < nmax; e++) {
+                if (e >= nh) continue;
+                const int s = hits[e][lane];
+                const int64_t j = S.j[s];
+                double dx, dy, dz, r2;
+                separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
                 cnt++;
                 const double cj = F.c[j];
                 if (r2 == 0.0) {
-                    vs_max = fmax(vs_max, ci + cj);
+                    vs_max = fmax(vs_max, PREC == SPH_FP64 ? ci + cj : (double)((float)ci + (float)cj));
                     continue;
                 }
-                const double r = sqrt(r2);
-                const double rinv = 1.0 / r;
-                const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-                const double hinvj = F.hinv[j];
-                const double gfj = kSigma * (hinvj * hinvj) * (hinvj * hinvj);
-                double fi, dfi, fj, dfj;
-                m4(r * hinvi, fi, dfi);
-                m4(r * hinvj, fj, dfj);
-                double gi, gj, gsum;
-                sym_grads(gfi, dfi, gfj, dfj, gi, gj, gsum);
-                const double w = ((vxi - F.vx[j]) * ex + (vyi - F.vy[j]) * ey) + (vzi - F.vz[j]) * ez;
-                const double mj = F.m[j];
-                double cvec = -mj * sym_dot2(Ai, gi, F.A[j], gj);
-                double cdu = Ai * mj * gi * w;
-                const double wneg = fmin(w, 0.0);
-                const double vs = (ci + cj) - beta * wneg;
-                vs_max = fmax(vs_max, vs);
-                const double visc = (mj / (0.5 * (rhoi + F.rho[j]))) * alpha * vs * wneg;
-                const double gbar = 0.5 * gsum;
-                cvec += visc * gbar;
-                cdu -= visc * 0.5 * wneg * gbar;
-                axi += cvec * ex;
-                ayi += cvec * ey;
-                azi += cvec * ez;
-                dui += cdu;
-            } else {
-                float dx = (fxi - F.fx[j]) + ox, dy = (fyi - F.fy[j]) + oy, dz = (fzi - F.fz[j]) + oz;
-                if (sh.per_pair) {
-                    dx = min_image_f(dx, (float)bx.len[0], (float)bx.half[0]);
-                    dy = min_image_f(dy, (float)bx.len[1], (float)bx.half[1]);
-                    dz = min_image_f(dz, (float)bx.len[2], (float)bx.half[2]);
+                if (PREC == SPH_FP64) {
+                    const double r = sqrt(r2);
+                    const double rinv = 1.0 / r;
+                    const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+                    const double hinvj = F.hinv[j];
+                    const double gfj = kSigma * (hinvj * hinvj) * (hinvj * hinvj);
+                    double fi, dfi, fj, dfj;
+                    m4(r * hinvi, fi, dfi);
+                    m4(r * hinvj, fj, dfj);
+                    double gi, gj, gsum;
+                    sym_grads(gfi, dfi, gfj, dfj, gi, gj, gsum);
+                    const double w = ((vxi - F.vx[j]) * ex + (vyi - F.vy[j]) * ey) + (vzi - F.vz[j]) * ez;
+                    const double mj = F.m[j];
+                    double cvec = -mj * sym_dot2(Ai, gi, F.A[j], gj);
+                    double cdu = Ai * mj * gi * w;
+                    const double wneg = fmin(w, 0.0);
+                    const double vs = (ci + cj) - beta * wneg;
+                    vs_max = fmax(vs_max, vs);
+                    const double visc = (mj / (0.5 * (rhoi + F.rho[j]))) * alpha * vs * wneg;
+                    const double gbar = 0.5 * gsum;
+                    cvec += visc * gbar;
+                    cdu -= visc * 0.5 * wneg * gbar;
+                    axi += cvec * ex;
+                    ayi += cvec * ey;
+                    azi += cvec * ez;
+                    dui += cdu;
+                } else {
+                    const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+                    const float r = sqrtf((float)r2);
+                    const float rinv = 1.0f / r;
+                    const float ex = fdx * rinv, ey = fdy * rinv, ez = fdz * rinv;
+                    const float hinvj = (float)F.hinv[j];
+                    // own and other kernel factors formed by the same float
+                    // expression, so the (j, i) pair sees exactly the values of
+                    // the (i, j) pair
+                    const float gfjf = (float)kSigma * (hinvj * hinvj) * (hinvj * hinvj);
+                    float fi, dfi, fj, dfj;
+                    m4(r * hinvif, fi, dfi);
+                    m4(r * hinvj, fj, dfj);
+                    float gi, gj, gsum;
+                    sym_grads(gfif, dfi, gfjf, dfj, gi, gj, gsum);
+                    const float w = ((float)(vxi - F.vx[j]) * ex + (float)(vyi - F.vy[j]) * ey) +
+                                    (float)(vzi - F.vz[j]) * ez;
+                    const float mj = (float)F.m[j];
+                    const float Aif = (float)Ai;
+                    const float cif = (float)ci, cjf = (float)cj;
+                    float cvec = -mj * sym_dot2(Aif, gi, (float)F.A[j], gj);
+                    float cdu = Aif * mj * gi * w;
+                    const float wneg = fminf(w, 0.0f);
+                    const float vs = (cif + cjf) - (float)beta * wneg;
+                    vs_max = fmax(vs_max, (double)vs);
+                    const float visc = (mj / (0.5f * ((float)rhoi + (float)F.rho[j]))) * (float)alpha * vs * wneg;
+                    const float gbar = 0.5f * gsum;
+                    cvec += visc * gbar;
+                    cdu -= visc * 0.5f * wneg * gbar;
+                    axi += (double)(cvec * ex);
+                    ayi += (double)(cvec * ey);
+                    azi += (double)(cvec * ez);
+                    dui += (double)cdu;
                 }
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (!((r2 < (float)hi2x4 || r2 < (float)hj2x4) && j != i)) continue;
-                cnt++;
-                const float cj = (float)F.c[j];
-                const float cif = (float)ci;
-                if (r2 == 0.0f) {
-                    vs_max = fmax(vs_max, (double)(cif + cj));
-                    continue;
-                }
-                const float r = sqrtf(r2);
-                const float rinv = 1.0f / r;
-                const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-                const float hinvj = (float)F.hinv[j];
-                const float hinvif = (float)hinvi;
-                // own and other kernel factors formed by the same float expression,
-                // so the (j, i) pair sees exactly the values of the (i, j) pair
-                const float gfif = (float)kSigma * (hinvif * hinvif) * (hinvif * hinvif);
-                const float gfjf = (float)kSigma * (hinvj * hinvj) * (hinvj * hinvj);
-                float fi, dfi, fj, dfj;
-                m4(r * hinvif, fi, dfi);
-                m4(r * hinvj, fj, dfj);
-                float gi, gj, gsum;
-                sym_grads(gfif, dfi, gfjf, dfj, gi, gj, gsum);
-                const float w = ((float)(vxi - F.vx[j]) * ex + (float)(vyi - F.vy[j]) * ey) +
-                                (float)(vzi - F.vz[j]) * ez;
-                const float mj = (float)F.m[j];
-                const float Aif = (float)Ai;
-                float cvec = -mj * sym_dot2(Aif, gi, (float)F.A[j], gj);
-                float cdu = Aif * mj * gi * w;
-                const float wneg = fminf(w, 0.0f);
-                const float vs = (cif + cj) - (float)beta * wneg;
-                vs_max = fmax(vs_max, (double)vs);
-                const float visc = (mj / (0.5f * ((float)rhoi + (float)F.rho[j]))) * (float)alpha * vs * wneg;
-                const float gbar = 0.5f * gsum;
-                cvec += visc * gbar;
-                cdu -= visc * 0.5f * wneg * gbar;
-                axi += (double)(cvec * ex);
-                ayi += (double)(cvec * ey);
-                azi += (double)(cvec * ez);
-                dui += (double)cdu;
+            }
+            wave_lds_sync();
+        };
+        for_each_leaf_group<NL>(T, F.nodes, wr, test, wb, group);
+#pragma unroll
+        for (int o = 1; o < LPP; o <<= 1) {
+            axi += __shfl_xor(axi, o);
+            ayi += __shfl_xor(ayi, o);
+            azi += __shfl_xor(azi, o);
+            dui += __shfl_xor(dui, o);
+            vs_max = fmax(vs_max, __shfl_xor(vs_max, o));
+            cnt += __shfl_xor(cnt, o);
+        }
+        if (active && q == 0) {
+            const double vsig = cnt > 0 ? vs_max : 2.0 * ci;
+            F.ax[i] = axi;
+            F.ay[i] = ayi;
+            F.az[i] = azi;
+            F.du[i] = dui;
+            F.vsig[i] = vsig;
+            F.dt[i] = F.ccfl * hi / vsig;
+            F.nforce[i] = cnt;
+            if (!isfinite(axi) || !isfinite(ayi) || !isfinite(azi) || !isfinite(dui) ||
+                !isfinite(vsig)) {
+                atomicOr(&F.status[0], kFlagNonFinite);
+                atomicAdd(&F.status[2], 1);
             }
         }
-    };
-    for_each_leaf(T, F.nodes, ncand, list, test, body);
-#pragma unroll
-    for (int o = 1; o < LPP; o <<= 1) {
-        axi += __shfl_xor(axi, o);
-        ayi += __shfl_xor(ayi, o);
-        azi += __shfl_xor(azi, o);
-        dui += __shfl_xor(dui, o);
-        vs_max = fmax(vs_max, __shfl_xor(vs_max, o));
-        cnt += __shfl_xor(cnt, o);
-    }
-    if (active && q == 0) {
-        const double vsig = cnt > 0 ? vs_max : 2.0 * ci;
-        F.ax[i] = axi;
-        F.ay[i] = ayi;
-        F.az[i] = azi;
-        F.du[i] = dui;
-        F.vsig[i] = vsig;
-        F.dt[i] = F.ccfl * hi / vsig;
-        F.nforce[i] = cnt;
-        if (!isfinite(axi) || !isfinite(ayi) || !isfinite(azi) || !isfinite(dui) ||
-            !isfinite(vsig)) {
-            atomicOr(&F.status[0], kFlagNonFinite);
-            atomicAdd(&F.status[2], 1);
-        }
-    }
-    pairs_total += (q == 0 && active) ? cnt : 0;
+        pairs_total += (q == 0 && active) ? cnt : 0;
     });
     for (int o = 32; o > 0; o >>= 1) pairs_total += __shfl_xor(pairs_total, o);
     if (lane == 0) {
@@ -692,80 +817,82 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
     const int32_t mode = N.mode;
     int64_t overflows = 0;
     for_each_home_leaf(T.cnt[0], N.work, [&](int64_t leaf) {
-    const int64_t first = N.lstart[leaf];
-    const int nhome = (int)(N.lstart[leaf + 1] - first);
-    const int64_t i = first + p;
-    const bool active = p < nhome;
-    const int64_t ii = active ? i : first;
-    const double xi = N.x[ii], yi = N.y[ii], zi = N.z[ii], hi = N.h[ii];
-    const double hi2x4 = (2.0 * hi) * (2.0 * hi);
-    const Node home = N.nodes[leaf];
-    auto test = [&bx, &home, mode](const Node &nd) {
-        double hh = mode == 0 ? home.hmax : fmax(home.hmax, nd.hmax);
-        double R = 2.0 * hh * (1.0 + 1e-10);
-        return box_gap2(home.lo, home.hi, nd, bx) < R * R;
-    };
-    const uint32_t *list = nullptr;
-    int ncand = walk(T, N.nodes, test, wb, &list);
-    if (ncand < 0) overflows++;
-    // two sweeps in pass 2: count this lane's hits, then write them
-    int64_t mine = 0;
-    int64_t base = 0;
-    for (int sweep = 0; sweep < (pass == 1 ? 1 : 2); sweep++) {
-        int64_t k = 0;
-        auto body = [&](int64_t c) {
-            const Node cand = N.nodes[c];
-            const Shift sh = leaf_shift(home, cand, bx, mode == 0 ? home.hmax : fmax(home.hmax, cand.hmax));
-            const int64_t j0 = N.lstart[c];
-            const int jn = (int)(N.lstart[c + 1] - j0);
-#pragma unroll
-            for (int t = 0; t < PER; t++) {
-                const int jj = q + LPP * t;
-                if (jj >= jn) continue;
-                const int64_t j = j0 + jj;
-                double dx = xi - N.x[j], dy = yi - N.y[j], dz = zi - N.z[j];
-                if (sh.per_pair) {
-                    dx = min_image(dx, bx.len[0], bx.half[0]);
-                    dy = min_image(dy, bx.len[1], bx.half[1]);
-                    dz = min_image(dz, bx.len[2], bx.half[2]);
-                } else {
-                    dx += sh.s[0];
-                    dy += sh.s[1];
-                    dz += sh.s[2];
-                }
-                const double r2 = exact_r2(dx, dy, dz);
-                bool in = r2 < hi2x4;
-                if (mode == 1) {
-                    const double hj = N.h[j];
-                    in = in || r2 < (2.0 * hj) * (2.0 * hj);
-                }
-                if (in && j != i && active) {
-                    if (sweep == 1) {
-                        int64_t pos = base + k;
-                        if (pos < N.cap) N.idx[pos] = (int32_t)N.id[j];
-                    }
-                    k++;
-                }
-            }
+        const int64_t first = N.lstart[leaf];
+        const int nhome = (int)(N.lstart[leaf + 1] - first);
+        const int64_t i = first + p;
+        const bool active = p < nhome;
+        const int64_t ii = active ? i : first;
+        const double xi = N.x[ii], yi = N.y[ii], zi = N.z[ii], hi = N.h[ii];
+        const double hi2x4 = (2.0 * hi) * (2.0 * hi);
+        const Node home = N.nodes[leaf];
+        auto test = [&bx, &home, mode](const Node &nd) {
+            const double hh = mode == 0 ? home.hmax : fmax(home.hmax, nd.hmax);
+            const double R = 2.0 * hh * (1.0 + 1e-10);
+            return box_gap2(home.lo, home.hi, nd, bx) < R * R;
         };
-        for_each_leaf(T, N.nodes, ncand, list, test, body);
-        if (sweep == 0) {
-            mine = k;
-            // exclusive prefix over the LPP lanes of this particle
-            int64_t incl = mine;
+        const WalkResult wr = walk(T, N.nodes, test, wb);
+        if (wr.lev) overflows++;
+        // two sweeps in pass 2: count this lane's hits, then write them
+        int64_t mine = 0, base = 0;
+        for (int sweep = 0; sweep < (pass == 1 ? 1 : 2); sweep++) {
+            int64_t k = 0;
+            auto group = [&](const uint32_t *leaves, int count) {
+                for (int g = 0; g < count; g++) {
+                    const int64_t c = leaves[g];
+                    const Node cand = N.nodes[c];
+                    const Shift sh = leaf_shift(home, cand, bx,
+                                                mode == 0 ? home.hmax : fmax(home.hmax, cand.hmax));
+                    const int64_t j0 = N.lstart[c];
+                    const int jn = (int)(N.lstart[c + 1] - j0);
 #pragma unroll
-            for (int o = 1; o < LPP; o <<= 1) {
-                int64_t v = (int64_t)__shfl_up((long long)incl, o, LPP);
-                if (q >= o) incl += v;
-            }
-            int64_t total = (int64_t)__shfl((long long)incl, (p * LPP) + LPP - 1);
-            if (pass == 1) {
-                if (active && q == 0) N.counts[i] = total;
-            } else {
-                base = active ? N.offsets[N.id[i]] + (incl - mine) : 0;
+                    for (int t = 0; t < PER; t++) {
+                        const int jj = q + LPP * t;
+                        if (jj >= jn) continue;
+                        const int64_t j = j0 + jj;
+                        double dx = xi - N.x[j], dy = yi - N.y[j], dz = zi - N.z[j];
+                        if (sh.per_pair) {
+                            dx = min_image(dx, bx.len[0], bx.half[0]);
+                            dy = min_image(dy, bx.len[1], bx.half[1]);
+                            dz = min_image(dz, bx.len[2], bx.half[2]);
+                        } else {
+                            dx += sh.s[0];
+                            dy += sh.s[1];
+                            dz += sh.s[2];
+                        }
+                        const double r2 = exact_r2(dx, dy, dz);
+                        bool in = r2 < hi2x4;
+                        if (mode == 1) {
+                            const double hj = N.h[j];
+                            in = in || r2 < (2.0 * hj) * (2.0 * hj);
+                        }
+                        if (in && j != i && active) {
+                            if (sweep == 1) {
+                                const int64_t pos = base + k;
+                                if (pos < N.cap) N.idx[pos] = (int32_t)N.id[j];
+                            }
+                            k++;
+                        }
+                    }
+                }
+            };
+            for_each_leaf_group<kWave>(T, N.nodes, wr, test, wb, group);
+            if (sweep == 0) {
+                mine = k;
+                // exclusive prefix over the LPP lanes of this particle
+                int64_t incl = mine;
+#pragma unroll
+                for (int o = 1; o < LPP; o <<= 1) {
+                    int64_t v = (int64_t)__shfl_up((long long)incl, o, LPP);
+                    if (q >= o) incl += v;
+                }
+                const int64_t total = (int64_t)__shfl((long long)incl, (p * LPP) + LPP - 1);
+                if (pass == 1) {
+                    if (active && q == 0) N.counts[i] = total;
+                } else {
+                    base = active ? N.offsets[N.id[i]] + (incl - mine) : 0;
+                }
             }
         }
-    }
     });
     if (lane == 0 && overflows) atomicAdd(&N.status[4], (int)overflows);
 }
@@ -823,15 +950,16 @@ sph_status run_density(sph_ctx *c, int64_t n)
     // (relative noise ~1e-7), so the Newton step cannot settle below a few
     // 1e-7; its stop tolerance is floored at 2e-6.
     a.h_rtol = c->p.precision == SPH_FP32_PAIR ? std::max(c->p.h_rtol, 2e-6) : c->p.h_rtol;
+    a.walk_margin = 1.1;
     a.max_iter = c->p.h_max_iter;
     {
         const void *req[] = {a.nodes, a.x, a.y, a.z, a.m, a.h, a.rho, a.omega, a.nngb, a.status,
-                             a.counts};
+                             a.counts, a.tree, a.lstart, a.work};
         for (const void *q : req)
             if (!q) return fail(c, SPH_EINVAL, "density: internal buffer not allocated");
         if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
             return fail(c, SPH_EINVAL, "density: offsets not allocated");
-        if (c->tree_n != n || !a.tree || !a.lstart || !a.work) return fail(c, SPH_ESTATE, "density: tree not built");
+        if (c->tree_n != n) return fail(c, SPH_ESTATE, "density: tree not built");
     }
     const unsigned grid = leaf_grid(n);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
@@ -876,12 +1004,12 @@ sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy,
     {
         const void *req[] = {a.nodes, a.x, a.y, a.z, a.vx, a.vy, a.vz, a.m, a.h, a.hinv, a.rho,
                              a.A, a.c, a.ax, a.ay, a.az, a.du, a.vsig, a.dt, a.nforce, a.status,
-                             a.counts};
+                             a.counts, a.tree, a.lstart, a.work};
         for (const void *q : req)
             if (!q) return fail(c, SPH_EINVAL, "forces: internal buffer not allocated");
         if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
             return fail(c, SPH_EINVAL, "forces: offsets not allocated");
-        if (c->tree_n != n || !a.tree || !a.lstart || !a.work) return fail(c, SPH_ESTATE, "forces: tree not built");
+        if (c->tree_n != n) return fail(c, SPH_ESTATE, "forces: tree not built");
     }
     const unsigned grid = leaf_grid(n);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
@@ -923,12 +1051,12 @@ sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_s
     a.cap = cap;
     a.status = c->d_status;
     {
-        const void *req[] = {a.nodes, a.x, a.y, a.z, a.h, a.id, a.status};
+        const void *req[] = {a.nodes, a.x, a.y, a.z, a.h, a.id, a.status, a.tree, a.lstart, a.work};
         for (const void *q : req)
             if (!q) return fail(c, SPH_EINVAL, "neighbours: internal buffer not allocated");
         if (!offsets && !counts_sorted) return fail(c, SPH_EINVAL, "neighbours: no counts");
         if (offsets && cap > 0 && !idx) return fail(c, SPH_EINVAL, "neighbours: no idx");
-        if (c->tree_n != n || !a.tree || !a.lstart || !a.work) return fail(c, SPH_ESTATE, "neighbours: tree not built");
+        if (c->tree_n != n) return fail(c, SPH_ESTATE, "neighbours: tree not built");
     }
     const unsigned grid = leaf_grid(n);
     const int pass = offsets ? 2 : 1;
