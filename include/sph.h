@@ -240,6 +240,21 @@ sph_status sph_state_info(sph_ctx *ctx, sph_state_stats *info);
 sph_status sph_neighbours(sph_ctx *ctx, const sph_particles *ps, int32_t mode,
                           int64_t *offsets, int32_t *idx, int64_t cap);
 
+/*
+ * Batched evaluation (many independent particle sets of uneven size).  The
+ * per-set preparation (sort, tree) is enqueued set by set, then the density
+ * (or force) loops of all sets run as ONE persistent kernel launch per group
+ * of sets sharing precision and leaf size (up to 128 sets per launch): waves
+ * claim leaves across all sets, so small sets fill the GPU together.  Each
+ * set's results are bit-for-bit those of the single-set call: the work done
+ * for a leaf depends on its own set only.  All contexts must be distinct,
+ * on one device and bound to the same stream; ps[r] belongs to ctx[r].
+ */
+sph_status sph_batch_density(sph_ctx *const *ctx, sph_particles *const *ps, int32_t count);
+sph_status sph_batch_forces(sph_ctx *const *ctx, sph_particles *const *ps, int32_t count);
+/* One sph_step of each resident state, pair loops batched as above. */
+sph_status sph_batch_step(sph_ctx *const *ctx, int32_t count, double dt);
+
 /* Wait for the context's stream; return and clear the sticky device status. */
 sph_status sph_sync(sph_ctx *ctx);
 

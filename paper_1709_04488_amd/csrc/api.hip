@@ -233,6 +233,189 @@ sph_status build_from(sph_ctx *c, const sph_particles *ps, bool with_m)
 
 } // namespace
 
+// ---- phases shared by the single and the batched entry points --------------
+
+namespace {
+
+sph_status density_pre(sph_ctx *c, const sph_particles *ps)
+{
+    TRY(check_ps(c, ps));
+    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z"); REQ(ps->m, "m"); REQ(ps->h, "h");
+    REQ(ps->rho, "rho"); REQ(ps->omega, "omega");
+    if ((ps->pressure || ps->cs)) REQ(ps->u, "u");
+    c->resident = false;
+    const int64_t n = ps->n;
+    TRY(ensure_capacity(c, n));
+    c->n = n;
+    if (n == 0) return SPH_OK;
+    TRY(build_from(c, ps, true));
+    return density_prepare(c, n);
+}
+
+sph_status density_post(sph_ctx *c, const sph_particles *ps)
+{
+    const int64_t n = ps->n;
+    if (n == 0) return SPH_OK;
+    ScatterList sl{};
+    const void *src[] = {c->s.h, c->s.rho, c->s.omega, c->s.nngb};
+    void *dst[] = {ps->h, ps->rho, ps->omega, ps->nngb};
+    int kinds[] = {0, 0, 0, 1};
+    for (int a = 0; a < 4; a++) {
+        if (!dst[a]) continue;
+        sl.kind[sl.count] = kinds[a];
+        sl.src[sl.count] = src[a];
+        sl.dst[sl.count] = dst[a];
+        sl.count++;
+    }
+    TRY(scatter(c, n, sl, c->perm));
+    return eos_scatter(c, n, c->perm, ps->u, ps->pressure, ps->cs);
+}
+
+sph_status forces_pre(sph_ctx *c, const sph_particles *ps)
+{
+    TRY(check_ps(c, ps));
+    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z");
+    REQ(ps->vx, "vx"); REQ(ps->vy, "vy"); REQ(ps->vz, "vz");
+    REQ(ps->m, "m"); REQ(ps->u, "u"); REQ(ps->h, "h"); REQ(ps->rho, "rho"); REQ(ps->omega, "omega");
+    REQ(ps->ax, "ax"); REQ(ps->ay, "ay"); REQ(ps->az, "az"); REQ(ps->dudt, "dudt");
+    REQ(ps->vsig, "vsig"); REQ(ps->dt, "dt");
+    const int64_t n = ps->n;
+    // the sort order of the last build is reused for the same arrays; the
+    // positions are gathered again, so the tree always matches them
+    bool reuse = c->built && !c->resident && c->built_x == ps->x && c->built_n == n;
+    c->resident = false;
+    TRY(ensure_capacity(c, n));
+    c->n = n;
+    if (n == 0) return SPH_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!reuse) {
+        TRY(build_order(c, n, ps->x, ps->y, ps->z));
+        c->built = true;
+        c->built_x = ps->x;
+        c->built_n = n;
+    }
+    timer_begin(c, 2, &e0, &e1);
+    GatherList g{};
+    const void *src[] = {ps->x, ps->y, ps->z, ps->m, ps->h, ps->rho, ps->omega, ps->u,
+                         ps->vx, ps->vy, ps->vz};
+    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.m, c->s.h, c->s.rho, c->s.omega, c->s.u,
+                   c->s.vx, c->s.vy, c->s.vz};
+    g.count = 11;
+    for (int a = 0; a < g.count; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
+    TRY(gather(c, n, g, false));
+    TRY(build_tree(c, n));
+    timer_end(c, 2, e0, e1);
+    TRY(force_prep(c, n, c->s.u));
+    return forces_prepare(c, n, c->s.vx, c->s.vy, c->s.vz);
+}
+
+sph_status forces_post(sph_ctx *c, const sph_particles *ps)
+{
+    const int64_t n = ps->n;
+    if (n == 0) return SPH_OK;
+    ScatterList sl{};
+    const void *ss[] = {c->s.ax, c->s.ay, c->s.az, c->s.du, c->s.vsig, c->s.dt, c->s.nforce};
+    void *sd[] = {ps->ax, ps->ay, ps->az, ps->dudt, ps->vsig, ps->dt, ps->nforce};
+    int kinds[] = {0, 0, 0, 0, 0, 0, 1};
+    for (int a = 0; a < 7; a++) {
+        if (!sd[a]) continue;
+        sl.kind[sl.count] = kinds[a];
+        sl.src[sl.count] = ss[a];
+        sl.dst[sl.count] = sd[a];
+        sl.count++;
+    }
+    TRY(scatter(c, n, sl, c->perm));
+    TRY(reduce_dt(c, n));
+    return reduce_diag(c, n);
+}
+
+// resident state, first half of a step: kicks, drift, re-sort, tree, density arguments
+sph_status step_pre(sph_ctx *c, double dt)
+{
+    if (!c->resident) return fail(c, SPH_ESTATE, "sph_step needs sph_upload_state first");
+    if (!std::isfinite(dt)) return fail(c, SPH_EINVAL, "dt is not finite");
+    const int64_t n = c->n;
+    TRY(kick_drift(c, n, dt));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_begin(c, 2, &e0, &e1);
+    TRY(build_order(c, n, c->s.x, c->s.y, c->s.z));
+    GatherList g{};
+    Sorted &S = c->s, &T = c->t;
+    double **sa[] = {&S.x, &S.y, &S.z, &S.vx, &S.vy, &S.vz, &S.m, &S.u, &S.h,
+                     &S.vpx, &S.vpy, &S.vpz, &S.up};
+    double **ta[] = {&T.x, &T.y, &T.z, &T.vx, &T.vy, &T.vz, &T.m, &T.u, &T.h,
+                     &T.vpx, &T.vpy, &T.vpz, &T.up};
+    const int nd = 13;
+    for (int a = 0; a < nd; a++) { g.kind[a] = 0; g.src[a] = *sa[a]; g.dst[a] = *ta[a]; }
+    g.kind[nd] = 1; g.src[nd] = S.id; g.dst[nd] = T.id;
+    g.count = nd + 1;
+    TRY(gather(c, n, g, false));
+    for (int a = 0; a < nd; a++) std::swap(*sa[a], *ta[a]);
+    std::swap(S.id, T.id);
+    TRY(build_tree(c, n));
+    timer_end(c, 2, e0, e1);
+    return density_prepare(c, n);
+}
+
+sph_status step_mid(sph_ctx *c)
+{
+    const int64_t n = c->n;
+    TRY(force_prep(c, n, c->s.up));
+    return forces_prepare(c, n, c->s.vpx, c->s.vpy, c->s.vpz);
+}
+
+sph_status step_post(sph_ctx *c, double dt, double *dt_used)
+{
+    const int64_t n = c->n;
+    TRY(closing_kick(c, n, dt));
+    TRY(reduce_dt(c, n));
+    TRY(reduce_diag(c, n));
+    c->steps++;
+    c->dt_used_out = dt_used;
+    return SPH_OK;
+}
+
+// Run the pair launches of a batch: group the sets by (precision, leaf size)
+// and launch each group in chunks of kMaxBatch.
+template <class Launch>
+sph_status launch_groups(sph_ctx *const *cs, int count, Launch launch)
+{
+    std::vector<sph_ctx *> grp;
+    std::vector<bool> done((size_t)count, false);
+    for (int a = 0; a < count; a++) {
+        if (done[a] || cs[a]->n == 0) continue;
+        grp.clear();
+        for (int b = a; b < count; b++) {
+            if (done[b] || cs[b]->n == 0) continue;
+            if (cs[b]->p.precision == cs[a]->p.precision && cs[b]->p.leaf_size == cs[a]->p.leaf_size) {
+                grp.push_back(cs[b]);
+                done[b] = true;
+            }
+        }
+        for (size_t k = 0; k < grp.size(); k += kMaxBatch) {
+            int cnt = (int)std::min<size_t>(kMaxBatch, grp.size() - k);
+            TRY(launch(grp.data() + k, cnt));
+        }
+    }
+    return SPH_OK;
+}
+
+sph_status check_batch(sph_ctx *const *cs, int32_t count)
+{
+    if (!cs || count < 0) return SPH_EINVAL;
+    for (int r = 0; r < count; r++)
+        if (!cs[r]) return SPH_EINVAL;
+    for (int r = 1; r < count; r++) {
+        if (cs[r]->stream != cs[0]->stream || cs[r]->device != cs[0]->device)
+            return fail(cs[r], SPH_EINVAL, "batched contexts must share one device and one stream");
+        for (int q = 0; q < r; q++)
+            if (cs[q] == cs[r]) return fail(cs[r], SPH_EINVAL, "a context appears twice in a batch");
+    }
+    return SPH_OK;
+}
+
+} // namespace
+
 extern "C" {
 
 void sph_default_params(sph_params *p)
@@ -272,6 +455,8 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
               hipMalloc((void **)&c->d_part, sizeof(double) * 1024 * 8) == hipSuccess &&
               hipMalloc((void **)&c->d_tree, sizeof(TreeInfo)) == hipSuccess &&
               hipMalloc((void **)&c->d_work, sizeof(uint32_t) * 64) == hipSuccess &&
+              hipMalloc(&c->d_dargs, kArgBytes) == hipSuccess &&
+              hipMalloc(&c->d_fargs, kArgBytes) == hipSuccess &&
               hipHostMalloc((void **)&c->h_status, sizeof(int32_t) * kStatusWords) == hipSuccess &&
               hipHostMalloc((void **)&c->h_scal, sizeof(double) * 16) == hipSuccess;
     if (!ok) {
@@ -303,6 +488,8 @@ sph_status sph_destroy(sph_ctx *c)
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_tree) (void)hipFree(c->d_tree);
     if (c->d_work) (void)hipFree(c->d_work);
+    if (c->d_dargs) (void)hipFree(c->d_dargs);
+    if (c->d_fargs) (void)hipFree(c->d_fargs);
     if (c->h_status) (void)hipHostFree(c->h_status);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
     delete c;
@@ -340,81 +527,48 @@ sph_status sph_build_cells(sph_ctx *c, const sph_particles *ps)
 
 sph_status sph_density(sph_ctx *c, sph_particles *ps)
 {
-    TRY(check_ps(c, ps));
-    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z"); REQ(ps->m, "m"); REQ(ps->h, "h");
-    REQ(ps->rho, "rho"); REQ(ps->omega, "omega");
-    if ((ps->pressure || ps->cs)) REQ(ps->u, "u");
-    c->resident = false;
-    const int64_t n = ps->n;
-    TRY(ensure_capacity(c, n));
-    c->n = n;
-    if (n == 0) return SPH_OK;
-    TRY(build_from(c, ps, true));
-    TRY(run_density(c, n));
-    ScatterList sl{};
-    const void *src[] = {c->s.h, c->s.rho, c->s.omega, c->s.nngb};
-    void *dst[] = {ps->h, ps->rho, ps->omega, ps->nngb};
-    int kinds[] = {0, 0, 0, 1};
-    for (int a = 0; a < 4; a++) {
-        if (!dst[a]) continue;
-        sl.kind[sl.count] = kinds[a];
-        sl.src[sl.count] = src[a];
-        sl.dst[sl.count] = dst[a];
-        sl.count++;
-    }
-    TRY(scatter(c, n, sl, c->perm));
-    TRY(eos_scatter(c, n, c->perm, ps->u, ps->pressure, ps->cs));
-    return SPH_OK;
+    TRY(density_pre(c, ps));
+    if (ps->n == 0) return SPH_OK;
+    TRY(density_launch(&c, 1, ps->n));
+    return density_post(c, ps);
 }
 
 sph_status sph_forces(sph_ctx *c, sph_particles *ps)
 {
-    TRY(check_ps(c, ps));
-    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z");
-    REQ(ps->vx, "vx"); REQ(ps->vy, "vy"); REQ(ps->vz, "vz");
-    REQ(ps->m, "m"); REQ(ps->u, "u"); REQ(ps->h, "h"); REQ(ps->rho, "rho"); REQ(ps->omega, "omega");
-    REQ(ps->ax, "ax"); REQ(ps->ay, "ay"); REQ(ps->az, "az"); REQ(ps->dudt, "dudt");
-    REQ(ps->vsig, "vsig"); REQ(ps->dt, "dt");
-    const int64_t n = ps->n;
-    bool reuse = c->built && !c->resident && c->built_x == ps->x && c->built_n == n;
-    c->resident = false;
-    TRY(ensure_capacity(c, n));
-    c->n = n;
-    if (n == 0) return SPH_OK;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (!reuse) {
-        TRY(build_order(c, n, ps->x, ps->y, ps->z));
-        c->built = true;
-        c->built_x = ps->x;
-        c->built_n = n;
-    }
-    timer_begin(c, 2, &e0, &e1);
-    GatherList g{};
-    const void *src[] = {ps->x, ps->y, ps->z, ps->m, ps->h, ps->rho, ps->omega, ps->u,
-                         ps->vx, ps->vy, ps->vz};
-    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.m, c->s.h, c->s.rho, c->s.omega, c->s.u,
-                   c->s.vx, c->s.vy, c->s.vz};
-    g.count = 11;
-    for (int a = 0; a < g.count; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
-    TRY(gather(c, n, g, false));
-    TRY(build_tree(c, n));
-    timer_end(c, 2, e0, e1);
-    TRY(force_prep(c, n, c->s.u));
-    TRY(run_forces(c, n, c->s.vx, c->s.vy, c->s.vz));
-    ScatterList sl{};
-    const void *ss[] = {c->s.ax, c->s.ay, c->s.az, c->s.du, c->s.vsig, c->s.dt, c->s.nforce};
-    void *sd[] = {ps->ax, ps->ay, ps->az, ps->dudt, ps->vsig, ps->dt, ps->nforce};
-    int kinds[] = {0, 0, 0, 0, 0, 0, 1};
-    for (int a = 0; a < 7; a++) {
-        if (!sd[a]) continue;
-        sl.kind[sl.count] = kinds[a];
-        sl.src[sl.count] = ss[a];
-        sl.dst[sl.count] = sd[a];
-        sl.count++;
-    }
-    TRY(scatter(c, n, sl, c->perm));
-    TRY(reduce_dt(c, n));
-    TRY(reduce_diag(c, n));
+    TRY(forces_pre(c, ps));
+    if (ps->n == 0) return SPH_OK;
+    TRY(forces_launch(&c, 1, ps->n));
+    return forces_post(c, ps);
+}
+
+sph_status sph_batch_density(sph_ctx *const *cs, sph_particles *const *ps, int32_t count)
+{
+    TRY(check_batch(cs, count));
+    if (count > 0 && !ps) return fail(cs[0], SPH_EINVAL, "particles is NULL");
+    for (int r = 0; r < count; r++) TRY(density_pre(cs[r], ps[r]));
+    TRY(launch_groups(cs, count, [](sph_ctx *const *g, int k) { return density_launch(g, k, 0); }));
+    for (int r = 0; r < count; r++) TRY(density_post(cs[r], ps[r]));
+    return SPH_OK;
+}
+
+sph_status sph_batch_forces(sph_ctx *const *cs, sph_particles *const *ps, int32_t count)
+{
+    TRY(check_batch(cs, count));
+    if (count > 0 && !ps) return fail(cs[0], SPH_EINVAL, "particles is NULL");
+    for (int r = 0; r < count; r++) TRY(forces_pre(cs[r], ps[r]));
+    TRY(launch_groups(cs, count, [](sph_ctx *const *g, int k) { return forces_launch(g, k, 0); }));
+    for (int r = 0; r < count; r++) TRY(forces_post(cs[r], ps[r]));
+    return SPH_OK;
+}
+
+sph_status sph_batch_step(sph_ctx *const *cs, int32_t count, double dt)
+{
+    TRY(check_batch(cs, count));
+    for (int r = 0; r < count; r++) TRY(step_pre(cs[r], dt));
+    TRY(launch_groups(cs, count, [](sph_ctx *const *g, int k) { return density_launch(g, k, 0); }));
+    for (int r = 0; r < count; r++) TRY(step_mid(cs[r]));
+    TRY(launch_groups(cs, count, [](sph_ctx *const *g, int k) { return forces_launch(g, k, 0); }));
+    for (int r = 0; r < count; r++) TRY(step_post(cs[r], dt, nullptr));
     return SPH_OK;
 }
 
@@ -454,37 +608,11 @@ sph_status sph_upload_state(sph_ctx *c, const sph_particles *ps)
 sph_status sph_step(sph_ctx *c, double dt, double *dt_used)
 {
     if (!c) return SPH_EINVAL;
-    if (!c->resident) return fail(c, SPH_ESTATE, "sph_step needs sph_upload_state first");
-    if (!std::isfinite(dt)) return fail(c, SPH_EINVAL, "dt is not finite");
-    const int64_t n = c->n;
-    TRY(kick_drift(c, n, dt));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    timer_begin(c, 2, &e0, &e1);
-    TRY(build_order(c, n, c->s.x, c->s.y, c->s.z));
-    GatherList g{};
-    Sorted &S = c->s, &T = c->t;
-    double **sa[] = {&S.x, &S.y, &S.z, &S.vx, &S.vy, &S.vz, &S.m, &S.u, &S.h,
-                     &S.vpx, &S.vpy, &S.vpz, &S.up};
-    double **ta[] = {&T.x, &T.y, &T.z, &T.vx, &T.vy, &T.vz, &T.m, &T.u, &T.h,
-                     &T.vpx, &T.vpy, &T.vpz, &T.up};
-    const int nd = 13;
-    for (int a = 0; a < nd; a++) { g.kind[a] = 0; g.src[a] = *sa[a]; g.dst[a] = *ta[a]; }
-    g.kind[nd] = 1; g.src[nd] = S.id; g.dst[nd] = T.id;
-    g.count = nd + 1;
-    TRY(gather(c, n, g, false));
-    for (int a = 0; a < nd; a++) std::swap(*sa[a], *ta[a]);
-    std::swap(S.id, T.id);
-    TRY(build_tree(c, n));
-    timer_end(c, 2, e0, e1);
-    TRY(run_density(c, n));
-    TRY(force_prep(c, n, S.up));
-    TRY(run_forces(c, n, S.vpx, S.vpy, S.vpz));
-    TRY(closing_kick(c, n, dt));
-    TRY(reduce_dt(c, n));
-    TRY(reduce_diag(c, n));
-    c->steps++;
-    c->dt_used_out = dt_used;
-    return SPH_OK;
+    TRY(step_pre(c, dt));
+    TRY(density_launch(&c, 1, c->n));
+    TRY(step_mid(c));
+    TRY(forces_launch(&c, 1, c->n));
+    return step_post(c, dt, dt_used);
 }
 
 sph_status sph_download_state(sph_ctx *c, sph_particles *ps)

@@ -20,6 +20,12 @@
 
 #include <algorithm>
 
+#define TRY_(expr)                     \
+    do {                               \
+        sph_status st_ = (expr);       \
+        if (st_ != SPH_OK) return st_; \
+    } while (0)
+
 namespace sph {
 namespace {
 
@@ -391,6 +397,46 @@ __device__ inline void separation(const Stage<NL> &S, const Box &bx, const Home 
 }
 
 // ---------------------------------------------------------------------------
+// Batches: one launch evaluates many independent particle sets.  Every
+// request has its own argument block in device memory; a wave claims a
+// global leaf index over the concatenation of the requests' leaves and maps
+// it back to (request, leaf) through an LDS prefix of the leaf counts.  The
+// work done for a leaf depends on its own request only, so a set gives the
+// same bits alone and inside any mix.
+// ---------------------------------------------------------------------------
+template <class Args>
+struct Batch {
+    int32_t nreq;
+    uint32_t *work;
+    const Args *req[kMaxBatch];
+};
+
+template <class Args>
+__device__ inline void batch_prefix(const Batch<Args> &B, int64_t *pre)
+{
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        pre[0] = 0;
+        for (int r = 0; r < B.nreq; r++) {
+            acc += B.req[r]->tree->cnt[0];
+            pre[r + 1] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// request holding global leaf g: largest r with pre[r] <= g
+__device__ inline int find_req(const int64_t *pre, int nreq, int64_t g)
+{
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
 // Density loop + h solve
 // ---------------------------------------------------------------------------
 struct DensArgs {
@@ -413,7 +459,7 @@ struct DensArgs {
 };
 
 template <int G, int PREC>
-__global__ __launch_bounds__(kWave) void k_density(DensArgs A)
+__global__ __launch_bounds__(kWave) void k_density(Batch<DensArgs> B)
 {
     constexpr int LPP = kWave / G;   // lanes per home particle
     constexpr int NL = LPP;          // candidate leaves staged per group
@@ -422,13 +468,37 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
     __shared__ TreeInfo T;
     __shared__ Stage<NL> S;
     __shared__ uint8_t hits[G][kWave];   // up to NL * PER = G hits per lane per group
-    load_tree(A.tree, T);
+    __shared__ int64_t pre[kMaxBatch + 1];
+    batch_prefix(B, pre);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
-    const Box &bx = A.box;
     int64_t evals = 0, walks = 0, visits = 0, overflows = 0;
     int iter_max = 0;
-    for_each_home_leaf(T.cnt[0], A.work, [&](int64_t leaf) {
+    int cur = -1;
+    DensArgs A;
+    // per-request diagnostics, flushed when the wave moves to another request
+    auto flush_counts = [&]() {
+        for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
+        if (lane == 0 && cur >= 0) {
+            atomicAdd((unsigned long long *)&A.counts[2], (unsigned long long)evals);
+            atomicMax((unsigned long long *)&A.counts[4], (unsigned long long)iter_max);
+            if (overflows) atomicAdd((unsigned long long *)&A.counts[5], (unsigned long long)overflows);
+            atomicAdd((unsigned long long *)&A.counts[6], (unsigned long long)visits);
+            atomicAdd((unsigned long long *)&A.counts[7], (unsigned long long)walks);
+        }
+        evals = walks = visits = overflows = 0;
+        iter_max = 0;
+    };
+    for_each_home_leaf(pre[B.nreq], B.work, [&](int64_t gleaf) {
+        const int r = find_req(pre, B.nreq, gleaf);
+        if (r != cur) {
+            flush_counts();
+            cur = r;
+            A = *B.req[r];
+            load_tree(A.tree, T);
+        }
+        const int64_t leaf = gleaf - pre[r];
+        const Box &bx = A.box;
         const int64_t first = A.lstart[leaf];
         const int nhome = (int)(A.lstart[leaf + 1] - first);
         const int64_t i = first + p;
@@ -575,14 +645,7 @@ __global__ __launch_bounds__(kWave) void k_density(DensArgs A)
         }
         iter_max = iter > iter_max ? iter : iter_max;
     });
-    for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
-    if (lane == 0) {
-        atomicAdd((unsigned long long *)&A.counts[2], (unsigned long long)evals);
-        atomicMax((unsigned long long *)&A.counts[4], (unsigned long long)iter_max);
-        if (overflows) atomicAdd((unsigned long long *)&A.counts[5], (unsigned long long)overflows);
-        atomicAdd((unsigned long long *)&A.counts[6], (unsigned long long)visits);
-        atomicAdd((unsigned long long *)&A.counts[7], (unsigned long long)walks);
-    }
+    flush_counts();
 }
 
 // ---------------------------------------------------------------------------
@@ -605,7 +668,7 @@ struct ForceArgs {
 };
 
 template <int G, int PREC>
-__global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
+__global__ __launch_bounds__(kWave) void k_forces(Batch<ForceArgs> B)
 {
     constexpr int LPP = kWave / G;
     constexpr int NL = LPP;
@@ -614,13 +677,32 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
     __shared__ TreeInfo T;
     __shared__ Stage<NL> S;
     __shared__ uint8_t hits[G][kWave];
-    load_tree(F.tree, T);
+    __shared__ int64_t pre[kMaxBatch + 1];
+    batch_prefix(B, pre);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
-    const Box &bx = F.box;
-    const double alpha = F.alpha, beta = F.beta;
     int64_t pairs_total = 0, overflows = 0;
-    for_each_home_leaf(T.cnt[0], F.work, [&](int64_t leaf) {
+    int cur = -1;
+    ForceArgs F;
+    auto flush_counts = [&]() {
+        for (int o = 32; o > 0; o >>= 1) pairs_total += __shfl_xor(pairs_total, o);
+        if (lane == 0 && cur >= 0) {
+            atomicAdd((unsigned long long *)&F.counts[3], (unsigned long long)pairs_total);
+            if (overflows) atomicAdd((unsigned long long *)&F.counts[5], (unsigned long long)overflows);
+        }
+        pairs_total = overflows = 0;
+    };
+    for_each_home_leaf(pre[B.nreq], B.work, [&](int64_t gleaf) {
+        const int r = find_req(pre, B.nreq, gleaf);
+        if (r != cur) {
+            flush_counts();
+            cur = r;
+            F = *B.req[r];
+            load_tree(F.tree, T);
+        }
+        const int64_t leaf = gleaf - pre[r];
+        const Box &bx = F.box;
+        const double alpha = F.alpha, beta = F.beta;
         const int64_t first = F.lstart[leaf];
         const int nhome = (int)(F.lstart[leaf + 1] - first);
         const int64_t i = first + p;
@@ -776,11 +858,7 @@ __global__ __launch_bounds__(kWave) void k_forces(ForceArgs F)
         }
         pairs_total += (q == 0 && active) ? cnt : 0;
     });
-    for (int o = 32; o > 0; o >>= 1) pairs_total += __shfl_xor(pairs_total, o);
-    if (lane == 0) {
-        atomicAdd((unsigned long long *)&F.counts[3], (unsigned long long)pairs_total);
-        if (overflows) atomicAdd((unsigned long long *)&F.counts[5], (unsigned long long)overflows);
-    }
+    flush_counts();
 }
 
 // ---------------------------------------------------------------------------
@@ -935,9 +1013,53 @@ inline unsigned leaf_grid(int64_t n)
 
 } // namespace
 
-sph_status run_density(sph_ctx *c, int64_t n)
+// ---- argument blocks and batched launches ---------------------------------
+
+namespace {
+
+template <class Args>
+__global__ void k_store_args(Args a, Args *dst)
 {
-    if (n == 0) return SPH_OK;
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = a;
+}
+
+struct CountsBatch {
+    int32_t n;
+    int32_t first, count;
+    int64_t *p[kMaxBatch];
+};
+
+__global__ void k_zero_counts_batch(CountsBatch cb)
+{
+    for (int r = blockIdx.x; r < cb.n; r += gridDim.x)
+        if ((int)threadIdx.x < cb.count) cb.p[r][cb.first + threadIdx.x] = 0;
+}
+
+__global__ void k_zero_work_one(uint32_t *__restrict__ w)
+{
+    if (threadIdx.x < kXcds) w[threadIdx.x] = 0u;
+}
+
+static_assert(sizeof(DensArgs) <= kArgBytes, "density argument block too large");
+static_assert(sizeof(ForceArgs) <= kArgBytes, "force argument block too large");
+
+sph_status zero_batch_counts(sph_ctx *const *cs, int count, int first, int nwords)
+{
+    CountsBatch cb{};
+    cb.n = count;
+    cb.first = first;
+    cb.count = nwords;
+    for (int r = 0; r < count; r++) cb.p[r] = cs[r]->d_counts;
+    hipLaunchKernelGGL(k_zero_counts_batch, dim3((unsigned)std::min(count, 64)), dim3(64), 0,
+                       cs[0]->stream, cb);
+    hipLaunchKernelGGL(k_zero_work_one, dim3(1), dim3(64), 0, cs[0]->stream, cs[0]->d_work);
+    return hip_check(cs[0], hipGetLastError(), "zero batch counters");
+}
+
+} // namespace
+
+sph_status density_prepare(sph_ctx *c, int64_t n)
+{
     DensArgs a{};
     fill_common(c, n, a);
     a.x = c->s.x; a.y = c->s.y; a.z = c->s.z; a.m = c->s.m;
@@ -952,44 +1074,21 @@ sph_status run_density(sph_ctx *c, int64_t n)
     a.h_rtol = c->p.precision == SPH_FP32_PAIR ? std::max(c->p.h_rtol, 2e-6) : c->p.h_rtol;
     a.walk_margin = 1.1;
     a.max_iter = c->p.h_max_iter;
-    {
-        const void *req[] = {a.nodes, a.x, a.y, a.z, a.m, a.h, a.rho, a.omega, a.nngb, a.status,
-                             a.counts, a.tree, a.lstart, a.work};
-        for (const void *q : req)
-            if (!q) return fail(c, SPH_EINVAL, "density: internal buffer not allocated");
-        if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
-            return fail(c, SPH_EINVAL, "density: offsets not allocated");
-        if (c->tree_n != n) return fail(c, SPH_ESTATE, "density: tree not built");
-    }
-    const unsigned grid = leaf_grid(n);
-    const bool f32 = c->p.precision == SPH_FP32_PAIR;
-    sph_status zs = zero_counts(c, 2, 1);
-    if (zs == SPH_OK) zs = zero_counts(c, 4, 4);
-    if (zs == SPH_OK) zs = zero_work(c);
-    if (zs != SPH_OK) return zs;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    timer_begin(c, 0, &e0, &e1);
-    switch (c->p.leaf_size) {
-    case 8:
-        if (f32) hipLaunchKernelGGL((k_density<8, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_density<8, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
-        break;
-    case 32:
-        if (f32) hipLaunchKernelGGL((k_density<32, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_density<32, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
-        break;
-    default:
-        if (f32) hipLaunchKernelGGL((k_density<16, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_density<16, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
-        break;
-    }
-    timer_end(c, 0, e0, e1);
-    return hip_check(c, hipGetLastError(), "density kernel");
+    const void *req[] = {a.nodes, a.x, a.y, a.z, a.m, a.h, a.rho, a.omega, a.nngb, a.status,
+                         a.counts, a.tree, a.lstart, a.work, c->d_dargs};
+    for (const void *q : req)
+        if (!q) return fail(c, SPH_EINVAL, "density: internal buffer not allocated");
+    if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
+        return fail(c, SPH_EINVAL, "density: offsets not allocated");
+    if (c->tree_n != n || n <= 0) return fail(c, SPH_ESTATE, "density: tree not built");
+    hipLaunchKernelGGL(k_store_args<DensArgs>, dim3(1), dim3(64), 0, c->stream, a,
+                       (DensArgs *)c->d_dargs);
+    return hip_check(c, hipGetLastError(), "density arguments");
 }
 
-sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy, const double *vz)
+sph_status forces_prepare(sph_ctx *c, int64_t n, const double *vx, const double *vy,
+                          const double *vz)
 {
-    if (n == 0) return SPH_OK;
     ForceArgs a{};
     fill_common(c, n, a);
     a.x = c->s.x; a.y = c->s.y; a.z = c->s.z;
@@ -1001,39 +1100,107 @@ sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy,
     a.status = c->d_status;
     a.counts = c->d_counts;
     a.alpha = c->p.alpha_av; a.beta = c->p.beta_av; a.ccfl = c->p.c_cfl;
-    {
-        const void *req[] = {a.nodes, a.x, a.y, a.z, a.vx, a.vy, a.vz, a.m, a.h, a.hinv, a.rho,
-                             a.A, a.c, a.ax, a.ay, a.az, a.du, a.vsig, a.dt, a.nforce, a.status,
-                             a.counts, a.tree, a.lstart, a.work};
-        for (const void *q : req)
-            if (!q) return fail(c, SPH_EINVAL, "forces: internal buffer not allocated");
-        if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
-            return fail(c, SPH_EINVAL, "forces: offsets not allocated");
-        if (c->tree_n != n) return fail(c, SPH_ESTATE, "forces: tree not built");
+    const void *req[] = {a.nodes, a.x, a.y, a.z, a.vx, a.vy, a.vz, a.m, a.h, a.hinv, a.rho,
+                         a.A, a.c, a.ax, a.ay, a.az, a.du, a.vsig, a.dt, a.nforce, a.status,
+                         a.counts, a.tree, a.lstart, a.work, c->d_fargs};
+    for (const void *q : req)
+        if (!q) return fail(c, SPH_EINVAL, "forces: internal buffer not allocated");
+    if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
+        return fail(c, SPH_EINVAL, "forces: offsets not allocated");
+    if (c->tree_n != n || n <= 0) return fail(c, SPH_ESTATE, "forces: tree not built");
+    hipLaunchKernelGGL(k_store_args<ForceArgs>, dim3(1), dim3(64), 0, c->stream, a,
+                       (ForceArgs *)c->d_fargs);
+    return hip_check(c, hipGetLastError(), "force arguments");
+}
+
+// One persistent launch over the prepared sets cs[0..count) (same stream,
+// same precision and leaf size, count <= kMaxBatch).
+sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax)
+{
+    if (count <= 0) return SPH_OK;
+    sph_ctx *c = cs[0];
+    if (count > kMaxBatch) return fail(c, SPH_EINVAL, "batch larger than kMaxBatch");
+    TRY_(zero_batch_counts(cs, count, 2, 6));
+    Batch<DensArgs> B{};
+    B.nreq = count;
+    B.work = c->d_work;
+    int64_t leaves_bound = 0;
+    for (int r = 0; r < count; r++) {
+        B.req[r] = (const DensArgs *)cs[r]->d_dargs;
+        leaves_bound += cs[r]->n;
     }
-    const unsigned grid = leaf_grid(n);
+    (void)nmax;
+    const unsigned grid = leaf_grid(leaves_bound);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
-    sph_status zs = zero_counts(c, 3, 1);
-    if (zs == SPH_OK) zs = zero_work(c);
-    if (zs != SPH_OK) return zs;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_begin(c, 0, &e0, &e1);
+    switch (c->p.leaf_size) {
+    case 8:
+        if (f32) hipLaunchKernelGGL((k_density<8, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        else hipLaunchKernelGGL((k_density<8, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        break;
+    case 32:
+        if (f32) hipLaunchKernelGGL((k_density<32, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        else hipLaunchKernelGGL((k_density<32, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        break;
+    default:
+        if (f32) hipLaunchKernelGGL((k_density<16, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        else hipLaunchKernelGGL((k_density<16, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        break;
+    }
+    timer_end(c, 0, e0, e1);
+    return hip_check(c, hipGetLastError(), "density kernel");
+}
+
+sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax)
+{
+    if (count <= 0) return SPH_OK;
+    sph_ctx *c = cs[0];
+    if (count > kMaxBatch) return fail(c, SPH_EINVAL, "batch larger than kMaxBatch");
+    TRY_(zero_batch_counts(cs, count, 3, 1));
+    Batch<ForceArgs> B{};
+    B.nreq = count;
+    B.work = c->d_work;
+    int64_t leaves_bound = 0;
+    for (int r = 0; r < count; r++) {
+        B.req[r] = (const ForceArgs *)cs[r]->d_fargs;
+        leaves_bound += cs[r]->n;
+    }
+    (void)nmax;
+    const unsigned grid = leaf_grid(leaves_bound);
+    const bool f32 = c->p.precision == SPH_FP32_PAIR;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_begin(c, 1, &e0, &e1);
     switch (c->p.leaf_size) {
     case 8:
-        if (f32) hipLaunchKernelGGL((k_forces<8, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_forces<8, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        if (f32) hipLaunchKernelGGL((k_forces<8, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        else hipLaunchKernelGGL((k_forces<8, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, B);
         break;
     case 32:
-        if (f32) hipLaunchKernelGGL((k_forces<32, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_forces<32, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        if (f32) hipLaunchKernelGGL((k_forces<32, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        else hipLaunchKernelGGL((k_forces<32, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, B);
         break;
     default:
-        if (f32) hipLaunchKernelGGL((k_forces<16, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_forces<16, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, a);
+        if (f32) hipLaunchKernelGGL((k_forces<16, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        else hipLaunchKernelGGL((k_forces<16, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, B);
         break;
     }
     timer_end(c, 1, e0, e1);
     return hip_check(c, hipGetLastError(), "force kernel");
+}
+
+sph_status run_density(sph_ctx *c, int64_t n)
+{
+    if (n == 0) return SPH_OK;
+    TRY_(density_prepare(c, n));
+    return density_launch(&c, 1, n);
+}
+
+sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy, const double *vz)
+{
+    if (n == 0) return SPH_OK;
+    TRY_(forces_prepare(c, n, vx, vy, vz));
+    return forces_launch(&c, 1, n);
 }
 
 sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_sorted,

@@ -20,6 +20,8 @@ constexpr int kWave = 64;
 constexpr int kMaxLevels = 16;   // tree levels above the leaves (8-ary)
 constexpr int kFront = 512;      // per-wave LDS capacity of a walk frontier / candidate list
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks dispatched round-robin
+constexpr int kMaxBatch = 128;   // particle sets per batched pair-kernel launch
+constexpr int kArgBytes = 1024;  // device argument block of one pair-kernel launch
 
 // Tree node: bounding box of the particles below it and their largest h.
 // 64 bytes, so one node is half a 128-byte cache line.
@@ -113,6 +115,8 @@ struct sph_ctx {
     uint32_t *lstart = nullptr;         // leaf -> first sorted particle, [L+1]
     uint32_t *leaf_id = nullptr;        // sorted particle -> leaf
     uint32_t *d_work = nullptr;         // per-XCD claim counters of the pair kernels
+    void *d_dargs = nullptr;            // device argument block of the density loop
+    void *d_fargs = nullptr;            // device argument block of the force loop
     uint64_t *skeys = nullptr;          // sorted keys of the last build
     uint32_t *scratch_u32 = nullptr;    // per-particle scratch (free sort buffer)
     int64_t tree_n = -1;                // n of the tree on the device (-1: none)
@@ -174,6 +178,14 @@ int64_t node_count_bound(int64_t n);
 sph_status run_density(sph_ctx *c, int64_t n);
 sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy,
                       const double *vz);
+// batched pair loops: prepare writes each set's argument block on its
+// stream; launch runs one persistent kernel over cs[0..count) (same stream,
+// precision and leaf size)
+sph_status density_prepare(sph_ctx *c, int64_t n);
+sph_status forces_prepare(sph_ctx *c, int64_t n, const double *vx, const double *vy,
+                          const double *vz);
+sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax);
+sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax);
 sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_sorted,
                           const int64_t *offsets_sorted, int32_t *idx, int64_t cap);
 

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "SPH_OK", -1: "SPH_EINVAL", -2: "SPH_ENOMEM", -3: "SPH_EDEVIC
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream", "sph_set_params",
             "sph_build_cells", "sph_density", "sph_forces", "sph_upload_state", "sph_step",
             "sph_download_state", "sph_state_info", "sph_neighbours", "sph_sync",
-            "sph_last_error", "sph_device_bytes", "sph_enable_kernel_timing", "sph_kernel_times"]
+            "sph_last_error", "sph_device_bytes", "sph_enable_kernel_timing", "sph_kernel_times",
+            "sph_batch_density", "sph_batch_forces", "sph_batch_step"]
 
 
 class SphError(RuntimeError):
@@ -103,6 +104,9 @@ def load() -> ctypes.CDLL:
         "sph_device_bytes": (ctypes.c_size_t, [vp]),
         "sph_enable_kernel_timing": (ctypes.c_int, [vp, i32]),
         "sph_kernel_times": (ctypes.c_int, [vp, i32, ctypes.POINTER(d), ctypes.POINTER(i64)]),
+        "sph_batch_density": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(PS), i32]),
+        "sph_batch_forces": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(PS), i32]),
+        "sph_batch_step": (ctypes.c_int, [ctypes.POINTER(vp), i32, d]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -335,3 +339,42 @@ def default_params_from_library() -> dict:
     load().sph_default_params(ctypes.byref(p))
     return {f: (tuple(getattr(p, f)) if f in ("box_lo", "box_hi") else getattr(p, f))
             for f, _ in _Params._fields_}
+
+
+def _batch_arrays(ctxs, parts, omit):
+    n = len(ctxs)
+    hs = (ctypes.c_void_p * n)(*[c.h.value for c in ctxs])
+    structs = [p.c(omit=omit) for p in parts]
+    ptrs = (ctypes.POINTER(_Particles) * n)(*[ctypes.pointer(s) for s in structs])
+    return hs, ptrs, structs
+
+
+def _batch_check(ctxs, rc, what):
+    if rc != SPH_OK:
+        msgs = [c.last_error() for c in ctxs if c.last_error()]
+        raise SphError(rc, f"{what}: {'; '.join(msgs)}")
+
+
+def batch_density(ctxs, parts, eos: bool = True):
+    """sph_batch_density over contexts sharing one stream."""
+    lib = load()
+    hs, ptrs, keep = _batch_arrays(ctxs, parts, () if eos else ("pressure", "cs"))
+    _batch_check(ctxs, lib.sph_batch_density(hs, ptrs, len(ctxs)), "sph_batch_density")
+
+
+def batch_forces(ctxs, parts):
+    lib = load()
+    hs, ptrs, keep = _batch_arrays(ctxs, parts, ("pressure", "cs"))
+    _batch_check(ctxs, lib.sph_batch_forces(hs, ptrs, len(ctxs)), "sph_batch_forces")
+
+
+def batch_evaluate(ctxs, parts):
+    batch_density(ctxs, parts)
+    batch_forces(ctxs, parts)
+
+
+def batch_step(ctxs, dt: float = 0.0):
+    lib = load()
+    n = len(ctxs)
+    hs = (ctypes.c_void_p * n)(*[c.h.value for c in ctxs])
+    _batch_check(ctxs, lib.sph_batch_step(hs, n, float(dt)), "sph_batch_step")
