@@ -34,6 +34,9 @@
  * Streams.  Every call enqueues work on the context's HIP stream and returns
  *           without waiting, unless stated otherwise.  Results are valid after
  *           the stream has drained (sph_sync, or any later stream-ordered use).
+ *           The library issues nothing on the null stream for a context bound
+ *           to another stream, so contexts on separate (non-blocking) streams
+ *           run concurrently without ordering against each other.
  * Errors.   Argument errors are returned at once (SPH_EINVAL).  Conditions the
  *           device detects (non-finite values, an h solve that did not
  *           converge, a smoothing length too large for the periodic box) are
@@ -158,6 +161,7 @@ void sph_default_params(sph_params *p);
  * Create a context bound to the current HIP device and to `hip_stream`
  * (a hipStream_t; NULL = the null stream).  hbm_budget_bytes caps the
  * library's own device allocations (0 = no cap).  *ctx is NULL on error.
+ * Initialises its status and scalar words on hip_stream and waits for that.
  */
 sph_status sph_create(sph_ctx **ctx, const sph_params *p, void *hip_stream,
                       size_t hbm_budget_bytes);
@@ -165,7 +169,8 @@ sph_status sph_create(sph_ctx **ctx, const sph_params *p, void *hip_stream,
 /* Free everything the context owns.  Waits for its stream.  NULL is a no-op. */
 sph_status sph_destroy(sph_ctx *ctx);
 
-/* Rebind the context to another stream (subsequent calls enqueue there). */
+/* Rebind the context to another stream: waits for the work already enqueued
+ * on the old stream, then subsequent calls enqueue on the new one. */
 sph_status sph_set_stream(sph_ctx *ctx, void *hip_stream);
 
 /* Replace the method parameters (same validation as sph_create). */
@@ -218,6 +223,18 @@ sph_status sph_upload_state(sph_ctx *ctx, const sph_particles *ps);
  */
 sph_status sph_step(sph_ctx *ctx, double dt, double *dt_used);
 
+/*
+ * HIP graph of resident steps.  sph_capture_steps records TWO consecutive
+ * sph_step(ctx, dt) calls (same dt semantics; dt <= 0 reads the CFL step on
+ * the device at replay time) into a graph held by the context, without
+ * executing them; sph_replay_steps launches it on the context's stream (two
+ * steps per replay, results bit-for-bit those of two sph_step calls).  The
+ * graph holds no memset or copy nodes.  Needs a resident state and a
+ * non-null stream; a new upload or a reallocation drops the graph.
+ */
+sph_status sph_capture_steps(sph_ctx *ctx, double dt);
+sph_status sph_replay_steps(sph_ctx *ctx);
+
 /* Write the resident state back in the caller's original index order:
  * x, y, z, v, u, h and, where non-NULL, rho, omega, pressure, cs, a, dudt,
  * vsig, dt, nngb, nforce (m is constant and not written). */
@@ -263,6 +280,11 @@ const char *sph_last_error(const sph_ctx *ctx);
 
 /* Bytes of device memory the context currently holds. */
 size_t sph_device_bytes(const sph_ctx *ctx);
+
+/* Bytes of device memory a context needs for n particles with these
+ * parameters (what it would allocate; no allocation is made).  For
+ * admission control by HBM budget. */
+size_t sph_plan_bytes(const sph_params *p, int64_t n);
 
 /*
  * Timing of individual kernels with HIP events on the context's stream.

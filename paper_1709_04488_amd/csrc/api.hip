@@ -70,6 +70,11 @@ void set_box(sph_ctx *c)
 
 void free_all(sph_ctx *c)
 {
+    // a captured graph refers to the buffers about to be freed
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
     for (void *ptr : c->allocs) (void)hipFree(ptr);
     c->allocs.clear();
     if (c->nodes) (void)hipFree(c->nodes);
@@ -465,9 +470,13 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
         return SPH_ENOMEM;
     }
     c->bytes = 4096;
-    ok = hipMemset(c->d_status, 0, sizeof(int32_t) * kStatusWords) == hipSuccess &&
-         hipMemset(c->d_scal, 0, sizeof(double) * 16) == hipSuccess &&
-         hipMemset(c->d_counts, 0, sizeof(int64_t) * 8) == hipSuccess;
+    // every operation of a context goes to its own stream: a null-stream
+    // memset is not ordered with a non-blocking stream and could land in the
+    // middle of the first calls' work
+    ok = hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * kStatusWords, c->stream) == hipSuccess &&
+         hipMemsetAsync(c->d_scal, 0, sizeof(double) * 16, c->stream) == hipSuccess &&
+         hipMemsetAsync(c->d_counts, 0, sizeof(int64_t) * 8, c->stream) == hipSuccess &&
+         hipStreamSynchronize(c->stream) == hipSuccess;
     if (!ok) { sph_destroy(c); return SPH_EDEVICE; }
     *out = c;
     return SPH_OK;
@@ -477,6 +486,10 @@ sph_status sph_destroy(sph_ctx *c)
 {
     if (!c) return SPH_OK;
     (void)hipStreamSynchronize(c->stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
     free_all(c);
     for (int w = 0; w < 3; w++)
         for (auto &pr : c->timer.pending[w]) c->timer.pool.push_back(pr);
@@ -499,6 +512,8 @@ sph_status sph_destroy(sph_ctx *c)
 sph_status sph_set_stream(sph_ctx *c, void *hip_stream)
 {
     if (!c) return SPH_EINVAL;
+    // the context's buffers may still be in use on the old stream
+    TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
     c->stream = (hipStream_t)hip_stream;
     return SPH_OK;
 }
@@ -583,6 +598,10 @@ sph_status sph_upload_state(sph_ctx *c, const sph_particles *ps)
     TRY(ensure_capacity(c, n));
     c->n = n;
     if (n == 0) return fail(c, SPH_EINVAL, "resident state needs n > 0");
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
     TRY(build_order(c, n, ps->x, ps->y, ps->z));
     GatherList g{};
     const void *src[] = {ps->x, ps->y, ps->z, ps->vx, ps->vy, ps->vz, ps->m, ps->u, ps->h};
@@ -613,6 +632,73 @@ sph_status sph_step(sph_ctx *c, double dt, double *dt_used)
     TRY(step_mid(c));
     TRY(forces_launch(&c, 1, c->n));
     return step_post(c, dt, dt_used);
+}
+
+namespace {
+void drop_graph(sph_ctx *c)
+{
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+} // namespace
+
+sph_status sph_capture_steps(sph_ctx *c, double dt)
+{
+    if (!c) return SPH_EINVAL;
+    if (!c->resident) return fail(c, SPH_ESTATE, "capture needs a resident state");
+    if (!c->stream) return fail(c, SPH_EINVAL, "capture needs a non-null stream");
+    if (!std::isfinite(dt)) return fail(c, SPH_EINVAL, "dt is not finite");
+    drop_graph(c);
+    const bool timing = c->timer.on;
+    c->timer.on = false;   // no event records inside the graph
+    TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    TRY(hip_check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal),
+                  "hipStreamBeginCapture"));
+    const int64_t steps0 = c->steps;
+    sph_status st = SPH_OK;
+    // two steps: the re-sort alternates between two buffer sets, so after an
+    // even number of steps every array is back where the graph expects it
+    for (int k = 0; k < 2 && st == SPH_OK; k++) {
+        st = step_pre(c, dt);
+        if (st == SPH_OK) st = density_launch(&c, 1, c->n);
+        if (st == SPH_OK) st = step_mid(c);
+        if (st == SPH_OK) st = forces_launch(&c, 1, c->n);
+        if (st == SPH_OK) st = step_post(c, dt, nullptr);
+    }
+    c->steps = steps0;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->timer.on = timing;
+    if (st != SPH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_check(c, e, "hipStreamEndCapture");
+    c->graph = g;
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(c);
+        return hip_check(c, e, "hipGraphInstantiate");
+    }
+    // move the graph's set-up onto the device now rather than at the first replay
+    e = hipGraphUpload(c->graph_exec, c->stream);
+    if (e != hipSuccess) {
+        drop_graph(c);
+        return hip_check(c, e, "hipGraphUpload");
+    }
+    c->graph_dt = dt;
+    return SPH_OK;
+}
+
+sph_status sph_replay_steps(sph_ctx *c)
+{
+    if (!c) return SPH_EINVAL;
+    if (!c->graph_exec || !c->resident) return fail(c, SPH_ESTATE, "no captured steps");
+    TRY(hip_check(c, hipGraphLaunch(c->graph_exec, c->stream), "hipGraphLaunch"));
+    c->steps += 2;
+    return SPH_OK;
 }
 
 sph_status sph_download_state(sph_ctx *c, sph_particles *ps)
@@ -650,8 +736,9 @@ sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
     TRY(hip_check(c, hipMemcpyAsync(c->h_scal, c->d_scal, sizeof(double) * 8,
                                     hipMemcpyDeviceToHost, c->stream), "copy scalars"));
     TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
-    TRY(hip_check(c, hipMemcpy(counts, c->d_counts, sizeof(counts), hipMemcpyDeviceToHost),
-                  "copy counts"));
+    TRY(hip_check(c, hipMemcpyAsync(counts, c->d_counts, sizeof(counts), hipMemcpyDeviceToHost,
+                                    c->stream), "copy counts"));
+    TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
     std::memset(info, 0, sizeof(*info));
     info->dt_next = c->h_scal[0];
     info->dt_last = c->h_scal[1];
@@ -701,8 +788,9 @@ sph_status sph_neighbours(sph_ctx *c, const sph_particles *ps, int32_t mode, int
     TRY(scan_offsets(c, n, offsets));
     int64_t total = 0;
     TRY(hip_check(c, hipStreamSynchronize(c->stream), "sync"));
-    TRY(hip_check(c, hipMemcpy(&total, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost),
-                  "copy total"));
+    TRY(hip_check(c, hipMemcpyAsync(&total, offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                    c->stream), "copy total"));
+    TRY(hip_check(c, hipStreamSynchronize(c->stream), "sync"));
     if (total > cap) return fail(c, SPH_ECAP, "neighbour lists need " + std::to_string(total) +
                                                   " entries, cap is " + std::to_string(cap));
     TRY(run_neighbours(c, n, mode, counts_sorted, offsets, idx, cap));
@@ -714,18 +802,20 @@ sph_status sph_sync(sph_ctx *c)
     if (!c) return SPH_EINVAL;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
-    e = hipMemcpy(c->h_status, c->d_status, sizeof(int32_t) * kStatusWords, hipMemcpyDeviceToHost);
+    e = hipMemcpyAsync(c->h_status, c->d_status, sizeof(int32_t) * kStatusWords,
+                       hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && c->dt_used_out && c->resident)
+        e = hipMemcpyAsync(c->h_scal + 1, c->d_scal + 1, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_check(c, e, "read status");
-    if (c->dt_used_out && c->resident) {
-        double v = 0.0;
-        if (hipMemcpy(&v, c->d_scal + 1, sizeof(double), hipMemcpyDeviceToHost) == hipSuccess)
-            *c->dt_used_out = v;
-        c->dt_used_out = nullptr;
-    }
+    if (c->dt_used_out && c->resident) *c->dt_used_out = c->h_scal[1];
+    c->dt_used_out = nullptr;
     int32_t st[kStatusWords];
     std::memcpy(st, c->h_status, sizeof(st));
     if (st[0] != 0 || st[4] != 0 || st[5] != 0) {
-        e = hipMemset(c->d_status, 0, sizeof(int32_t) * kStatusWords);
+        e = hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * kStatusWords, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return hip_check(c, e, "clear status");
     }
     if (st[0] & kFlagNonFinite)
@@ -747,6 +837,14 @@ const char *sph_last_error(const sph_ctx *c)
 }
 
 size_t sph_device_bytes(const sph_ctx *c) { return c ? c->bytes : 0; }
+
+size_t sph_plan_bytes(const sph_params *p, int64_t n)
+{
+    if (!p || n < 0) return 0;
+    const int64_t cap = std::max<int64_t>(n, 1024);
+    return (size_t)(bytes_per_particle(*p) * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
+                    256 * 4 * ceil_div(cap, kRsTile) + 4096 + 3 * kArgBytes);
+}
 
 sph_status sph_enable_kernel_timing(sph_ctx *c, int32_t enable)
 {

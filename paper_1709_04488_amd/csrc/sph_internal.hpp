@@ -145,6 +145,11 @@ struct sph_ctx {
     int32_t *d_status = nullptr;
     int32_t *h_status = nullptr;   // pinned mirror
 
+    // captured pair of resident steps
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    double graph_dt = 0.0;
+
     sph::Timer timer;
 };
 

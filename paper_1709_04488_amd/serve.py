@@ -1,0 +1,479 @@
+"""Serving SPH requests on one GPU with continuous batching.
+
+Two request kinds:
+  * ``evaluate``  -- one density + force evaluation of a particle set;
+  * ``integrate`` -- ``nsteps`` kick-drift-kick steps of a particle set kept
+                     resident on the device, steps replayed from a captured
+                     HIP graph.
+
+The scheduler is plain Python and device-agnostic:
+  * requests are admitted first-come first-served once they have arrived,
+    a slot is free and their device memory fits the HBM budget;
+  * admission is continuous: a request arriving while others run starts as
+    soon as a slot and memory free up, without waiting for a batch boundary;
+  * a slot keeps its context (and its device memory, grown to the largest
+    set it served) between requests, so the budget counts slot capacity plus
+    the particle arrays of running requests.
+The executor does the device work.  ``GpuExecutor`` gives every slot its own
+HIP stream, so the kernels of concurrent requests overlap on the device; in
+``batched`` mode the evaluate requests admitted together are run through one
+batched persistent launch instead.  ``FakeExecutor`` (CPU, simulated clock)
+exercises the scheduler without a GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import heapq
+import json
+import math
+import sys
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GIB = 1 << 30
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds from the start of the run
+    kind: str                      # "evaluate" or "integrate"
+    arrays: dict                   # host float64 arrays x..h
+    setup: dict
+    precision: int = 0             # 0 FP64, 1 FP32-pair
+    nsteps: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.arrays["x"].size)
+
+
+@dataclass
+class Record:
+    rid: int
+    n: int
+    kind: str
+    precision: int
+    arrival: float
+    admitted: float = math.nan
+    done: float = math.nan
+    slot: int = -1
+    interactions: int = 0
+    error: str = ""
+    outputs: dict = field(default_factory=dict)
+    info: dict = field(default_factory=dict)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+# ----------------------------------------------------------------------------
+# clocks
+# ----------------------------------------------------------------------------
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def sleep_until(self, t: float):
+        dt = t - self.now()
+        if dt > 0:
+            time.sleep(min(dt, 0.05))
+
+
+class SimClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def sleep_until(self, t: float):
+        self.t = max(self.t, t)
+
+
+# ----------------------------------------------------------------------------
+# scheduler
+# ----------------------------------------------------------------------------
+class Scheduler:
+    def __init__(self, executor, budget_bytes: int, max_slots: int, clock=None):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.clock = clock or WallClock()
+        self.slot_cap = [0] * self.max_slots      # particles each slot's context can hold
+        self.slot_busy = [False] * self.max_slots
+        self.array_bytes = {}                     # running rid -> bytes of its particle arrays
+        self.peak_bytes = 0
+        self.events = []                          # (time, what, rid)
+
+    # memory currently held: slot capacities + arrays of running requests
+    def used_bytes(self) -> int:
+        return sum(self.ex.slot_bytes(c) for c in self.slot_cap) + sum(self.array_bytes.values())
+
+    def _fit(self, req: Request):
+        """Free slot for req and the extra bytes admitting it costs, or None."""
+        used = self.used_bytes()
+        best = None
+        for s in range(self.max_slots):
+            if self.slot_busy[s]:
+                continue
+            cap = self.slot_cap[s]
+            extra = self.ex.slot_bytes(max(cap, req.n)) - self.ex.slot_bytes(cap)
+            extra += self.ex.array_bytes(req)
+            if used + extra <= self.budget:
+                # prefer the slot that grows least, then the smallest capacity
+                key = (extra, cap)
+                if best is None or key < best[0]:
+                    best = (key, s, extra)
+        return None if best is None else (best[1], best[2])
+
+    def _never_fits(self, req: Request) -> bool:
+        return self.ex.slot_bytes(req.n) + self.ex.array_bytes(req) > self.budget
+
+    def run(self, requests):
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        recs = {r.rid: Record(r.rid, r.n, r.kind, r.precision, r.arrival) for r in pending}
+        queue = []
+        running = {}
+        k = 0
+        while k < len(pending) or queue or running:
+            now = self.clock.now()
+            while k < len(pending) and pending[k].arrival <= now:
+                queue.append(pending[k])
+                k += 1
+            # admit in arrival order; a request that can never fit is rejected
+            started = []
+            while queue:
+                req = queue[0]
+                if self._never_fits(req):
+                    queue.pop(0)
+                    recs[req.rid].error = "exceeds HBM budget"
+                    recs[req.rid].done = now
+                    continue
+                fit = self._fit(req)
+                if fit is None:
+                    break
+                slot, _ = fit
+                queue.pop(0)
+                self.slot_busy[slot] = True
+                self.slot_cap[slot] = max(self.slot_cap[slot], req.n)
+                self.array_bytes[req.rid] = self.ex.array_bytes(req)
+                self.peak_bytes = max(self.peak_bytes, self.used_bytes())
+                rec = recs[req.rid]
+                rec.admitted = now
+                rec.slot = slot
+                started.append((req, slot))
+                self.events.append((now, "admit", req.rid))
+            if started:
+                handles = self.ex.start(started)
+                for (req, slot), h in zip(started, handles):
+                    running[req.rid] = (req, slot, h)
+            # completions
+            finished = [rid for rid, (req, slot, h) in running.items() if self.ex.poll(h)]
+            for rid in finished:
+                req, slot, h = running.pop(rid)
+                rec = recs[rid]
+                try:
+                    out = self.ex.finish(h)
+                    rec.outputs = out.get("outputs", {})
+                    rec.interactions = int(out.get("interactions", 0))
+                    rec.info = out.get("info", {})
+                except Exception as e:  # reported per request, the server keeps going
+                    rec.error = str(e)
+                rec.done = self.clock.now()
+                self.slot_busy[slot] = False
+                self.array_bytes.pop(rid, None)
+                self.events.append((rec.done, "done", rid))
+            if not started and not finished:
+                nxt = pending[k].arrival if k < len(pending) else math.inf
+                self.ex.wait(self.clock, nxt)
+        return [recs[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
+
+
+def summarize(recs, makespan: float) -> dict:
+    ok = [r for r in recs if not r.error]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    inter = sum(r.interactions for r in ok)
+    return {"requests": len(recs), "completed": len(ok), "errors": len(recs) - len(ok),
+            "makespan_s": makespan, "throughput_interactions_per_s": inter / makespan if makespan > 0 else 0.0,
+            "requests_per_s": len(ok) / makespan if makespan > 0 else 0.0,
+            "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "latency_max_ms": float(lat.max() * 1e3)}
+
+
+# ----------------------------------------------------------------------------
+# executors
+# ----------------------------------------------------------------------------
+class FakeExecutor:
+    """Simulated device: a request takes cost(req) seconds once started; up to
+    `lanes` requests progress at once (processor sharing is not modelled)."""
+
+    def __init__(self, clock, cost, bytes_per_particle: int = 500, fixed: int = 1 << 20):
+        self.clock = clock
+        self.cost = cost
+        self.bpp = bytes_per_particle
+        self.fixed = fixed
+        self.starts = []
+        self.active = {}
+
+    def slot_bytes(self, cap: int) -> int:
+        return 0 if cap == 0 else self.fixed + self.bpp * cap
+
+    def array_bytes(self, req: Request) -> int:
+        return 168 * req.n
+
+    def start(self, items):
+        hs = []
+        for req, slot in items:
+            t = self.clock.now()
+            self.starts.append((t, req.rid, slot))
+            h = {"req": req, "end": t + self.cost(req)}
+            self.active[req.rid] = h["end"]
+            hs.append(h)
+        return hs
+
+    def poll(self, h) -> bool:
+        return self.clock.now() >= h["end"]
+
+    def finish(self, h):
+        self.active.pop(h["req"].rid, None)
+        return {"interactions": 100 * h["req"].n}
+
+    def wait(self, clock, next_arrival: float):
+        # advance to the next event: an arrival or the earliest completion
+        t = min([next_arrival] + list(self.active.values()))
+        clock.sleep_until(t if math.isfinite(t) else clock.now() + 1e-3)
+
+
+class _Slot:
+    def __init__(self, idx, stream, ctx):
+        self.idx = idx
+        self.stream = stream
+        self.ctx = ctx
+
+
+class GpuExecutor:
+    """Requests on the MI355X through the sph C ABI, one HIP stream per slot."""
+
+    OUT_EVAL = ("h", "rho", "omega", "pressure", "cs", "ax", "ay", "az", "dudt", "vsig", "dt",
+                "nngb", "nforce")
+
+    def __init__(self, max_slots: int, mode: str = "streams", leaf_for=None, keep_outputs=False):
+        import torch
+
+        from . import sph
+        self.torch = torch
+        self.sph = sph
+        self.mode = mode
+        self.keep_outputs = keep_outputs
+        self.leaf_for = leaf_for or (lambda req: 16)
+        self.shared = torch.cuda.Stream()
+        self.slots = []
+        for s in range(max_slots):
+            stream = self.shared if mode == "batched" else torch.cuda.Stream()
+            self.slots.append(_Slot(s, stream, None))
+
+    def params(self, req: Request):
+        return self.sph.Params.from_setup(req.setup, precision=req.precision,
+                                          leaf_size=self.leaf_for(req))
+
+    def slot_bytes(self, cap: int) -> int:
+        return 0 if cap == 0 else self.sph.plan_bytes(self.sph.Params(leaf_size=8), cap)
+
+    def array_bytes(self, req: Request) -> int:
+        return req.n * 8 * 19 + req.n * 4 * 2
+
+    def _ctx(self, slot: _Slot, req: Request):
+        if slot.ctx is None:
+            slot.ctx = self.sph.Context(self.params(req), stream=slot.stream)
+        else:
+            slot.ctx.set_params(self.params(req))
+        return slot.ctx
+
+    def _upload(self, req: Request, stream):
+        torch = self.torch
+        with torch.cuda.stream(stream):
+            t = {}
+            for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h"):
+                host = torch.from_numpy(np.ascontiguousarray(req.arrays[k], dtype=np.float64)).pin_memory()
+                t[k] = host.to("cuda", non_blocking=True)
+            n = req.n
+            for k in self.sph.FIELDS_F64:
+                if k not in t:
+                    t[k] = torch.zeros(n, dtype=torch.float64, device="cuda")
+            for k in self.sph.FIELDS_I32:
+                t[k] = torch.zeros(n, dtype=torch.int32, device="cuda")
+        return self.sph.Particles(t)
+
+    def _zeros(self, n: int, stream):
+        torch = self.torch
+        with torch.cuda.stream(stream):
+            t = {k: torch.zeros(n, dtype=torch.float64, device="cuda") for k in self.sph.FIELDS_F64}
+            for k in self.sph.FIELDS_I32:
+                t[k] = torch.zeros(n, dtype=torch.int32, device="cuda")
+        return self.sph.Particles(t)
+
+    def start(self, items):
+        torch = self.torch
+        handles = [None] * len(items)
+        batch = []
+        for k, (req, sidx) in enumerate(items):
+            slot = self.slots[sidx]
+            ctx = self._ctx(slot, req)
+            p = self._upload(req, slot.stream)
+            h = {"req": req, "slot": slot, "ctx": ctx, "p": p, "event": torch.cuda.Event()}
+            if req.kind == "evaluate" and self.mode == "batched":
+                batch.append(h)
+            elif req.kind == "evaluate":
+                with torch.cuda.stream(slot.stream):
+                    ctx.evaluate(p)
+                h["event"].record(slot.stream)
+            else:
+                with torch.cuda.stream(slot.stream):
+                    ctx.upload_state(p)
+                    ctx.capture_steps(0.0)
+                    for _ in range(req.nsteps // 2):
+                        ctx.replay_steps()
+                    if req.nsteps % 2:
+                        ctx.step(0.0)
+                h["event"].record(slot.stream)
+            handles[k] = h
+        if batch:
+            self.sph.batch_evaluate([h["ctx"] for h in batch], [h["p"] for h in batch])
+            ev = torch.cuda.Event()
+            ev.record(self.shared)
+            for h in batch:
+                h["event"] = ev
+        return handles
+
+    def poll(self, h) -> bool:
+        return h["event"].query()
+
+    def finish(self, h):
+        ctx, p, req = h["ctx"], h["p"], h["req"]
+        rc = ctx.sync_status()
+        if rc != self.sph.SPH_OK:
+            raise self.sph.SphError(rc, ctx.last_error())
+        info = ctx.state_info()
+        out = {"info": info}
+        if req.kind == "evaluate":
+            out["interactions"] = info["n_dens_pairs"] + info["n_force_pairs"]
+            if self.keep_outputs:
+                out["outputs"] = p.host(*self.OUT_EVAL)
+        else:
+            out["interactions"] = (info["n_dens_pairs"] + info["n_force_pairs"]) * max(req.nsteps, 1)
+            q = self._zeros(req.n, h["slot"].stream)
+            ctx.download_state(q)
+            ctx.sync()
+            if self.keep_outputs:
+                out["outputs"] = q.host("x", "y", "z", "vx", "vy", "vz", "u", "h")
+        h["p"] = None
+        return out
+
+    def wait(self, clock, next_arrival: float):
+        time.sleep(0.0002)
+
+
+# ----------------------------------------------------------------------------
+# the two served workloads
+# ----------------------------------------------------------------------------
+def evaluate_requests(count: int, rate: float, seed: int = 3, n_max_side: int = None):
+    """Serving mix: jittered-lattice boxes, N log-uniform in [1e3, 2e5]
+    snapped to n^3, FP64 or FP32-pair with probability 1/2, Poisson
+    arrivals at `rate` per second (rate = inf: all at t = 0)."""
+    from . import workloads as W
+    spec = W.config3_requests(count, seed=seed)
+    rng = np.random.default_rng(seed + 7)
+    t = 0.0
+    reqs = []
+    for rid, (side, prec, wseed) in enumerate(spec):
+        if n_max_side:
+            side = min(side, n_max_side)
+        w = W.jittered_lattice(side, seed=wseed)
+        if math.isfinite(rate):
+            t += rng.exponential(1.0 / rate)
+        reqs.append(Request(rid, t if math.isfinite(rate) else 0.0, "evaluate", w.arrays, w.setup,
+                            precision=int(prec)))
+    return reqs
+
+
+def integrate_requests(count: int, nsteps: int, rate: float = math.inf, seed: int = 4,
+                       n_max_side: int = None, precision: int = 1):
+    """Served integration: blob-in-lattice boxes, N log-uniform in [1e4, 1e6]
+    snapped to n^3, FP32-pair pair arithmetic with FP64 state."""
+    from . import workloads as W
+    spec = W.config4_requests(count, seed=seed)
+    rng = np.random.default_rng(seed + 7)
+    t = 0.0
+    reqs = []
+    for rid, (side, wseed) in enumerate(spec):
+        if n_max_side:
+            side = min(side, n_max_side)
+        w = W.blob_in_lattice(side, seed=wseed)
+        if math.isfinite(rate):
+            t += rng.exponential(1.0 / rate)
+        reqs.append(Request(rid, t if math.isfinite(rate) else 0.0, "integrate", w.arrays, w.setup,
+                            precision=precision, nsteps=nsteps))
+    return reqs
+
+
+def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=False):
+    import torch
+    ex = GpuExecutor(slots, mode=mode, leaf_for=leaf_for, keep_outputs=keep_outputs)
+    sched = Scheduler(ex, budget, slots, WallClock())
+    t0 = sched.clock.now()
+    recs = sched.run(reqs)
+    torch.cuda.synchronize()
+    makespan = max(r.done for r in recs) - t0
+    out = summarize(recs, makespan)
+    out["peak_bytes"] = sched.peak_bytes
+    return recs, out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="serve SPH requests on one GPU")
+    ap.add_argument("--workload", choices=["evaluate", "integrate"], default="evaluate")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--budget-gib", type=float, default=None,
+                    help="HBM budget (default 1 GiB for evaluate, 16 GiB for integrate)")
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--mode", choices=["streams", "batched"], default="streams")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the measured saturated capacity")
+    ap.add_argument("--max-side", type=int, default=None)
+    args = ap.parse_args(argv)
+    gib = args.budget_gib if args.budget_gib else (1.0 if args.workload == "evaluate" else 16.0)
+    budget = int(gib * GIB)
+    if args.workload == "evaluate":
+        burst = evaluate_requests(args.requests, math.inf, n_max_side=args.max_side)
+        _, closed = serve(burst, budget, args.slots, args.mode)
+        rate = args.load * closed["requests_per_s"]
+        reqs = evaluate_requests(args.requests, rate, n_max_side=args.max_side)
+        _, opened = serve(reqs, budget, args.slots, args.mode)
+        res = {"workload": "evaluate", "mode": args.mode, "slots": args.slots,
+               "budget_bytes": budget, "saturated": closed, "arrival_rate_per_s": rate,
+               "poisson": opened}
+    else:
+        reqs = integrate_requests(args.requests, args.steps, n_max_side=args.max_side)
+        recs, out = serve(reqs, budget, args.slots, args.mode)
+        steps = sum(r.info.get("steps", 0) for r in recs if not r.error)
+        res = {"workload": "integrate", "mode": args.mode, "slots": args.slots,
+               "budget_bytes": budget, "steps_per_request": args.steps, "result": out,
+               "steps_total": steps,
+               "per_step_latency_p50_ms": float(np.percentile(
+                   [r.latency / max(args.steps, 1) * 1e3 for r in recs if not r.error], 50)),
+               "per_step_latency_p99_ms": float(np.percentile(
+                   [r.latency / max(args.steps, 1) * 1e3 for r in recs if not r.error], 99))}
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

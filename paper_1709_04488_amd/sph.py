@@ -28,7 +28,8 @@ EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream",
             "sph_build_cells", "sph_density", "sph_forces", "sph_upload_state", "sph_step",
             "sph_download_state", "sph_state_info", "sph_neighbours", "sph_sync",
             "sph_last_error", "sph_device_bytes", "sph_enable_kernel_timing", "sph_kernel_times",
-            "sph_batch_density", "sph_batch_forces", "sph_batch_step"]
+            "sph_batch_density", "sph_batch_forces", "sph_batch_step", "sph_capture_steps",
+            "sph_replay_steps", "sph_plan_bytes"]
 
 
 class SphError(RuntimeError):
@@ -107,6 +108,9 @@ def load() -> ctypes.CDLL:
         "sph_batch_density": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(PS), i32]),
         "sph_batch_forces": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(PS), i32]),
         "sph_batch_step": (ctypes.c_int, [ctypes.POINTER(vp), i32, d]),
+        "sph_capture_steps": (ctypes.c_int, [vp, d]),
+        "sph_replay_steps": (ctypes.c_int, [vp]),
+        "sph_plan_bytes": (ctypes.c_size_t, [P, i64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -273,6 +277,14 @@ class Context:
     def step(self, dt: float = 0.0):
         self._check(self.lib.sph_step(self.h, float(dt), None), "sph_step")
 
+    def capture_steps(self, dt: float = 0.0):
+        """Record two sph_step(dt) calls into a HIP graph (not executed)."""
+        self._check(self.lib.sph_capture_steps(self.h, float(dt)), "sph_capture_steps")
+
+    def replay_steps(self):
+        """Launch the captured graph: two steps."""
+        self._check(self.lib.sph_replay_steps(self.h), "sph_replay_steps")
+
     def download_state(self, p: Particles):
         ps = p.c()
         self._check(self.lib.sph_download_state(self.h, ctypes.byref(ps)), "sph_download_state")
@@ -378,3 +390,9 @@ def batch_step(ctxs, dt: float = 0.0):
     n = len(ctxs)
     hs = (ctypes.c_void_p * n)(*[c.h.value for c in ctxs])
     _batch_check(ctxs, lib.sph_batch_step(hs, n, float(dt)), "sph_batch_step")
+
+
+def plan_bytes(params: Params, n: int) -> int:
+    """Device bytes a context needs for n particles (sph_plan_bytes)."""
+    p = params.c()
+    return int(load().sph_plan_bytes(ctypes.byref(p), int(n)))
