@@ -365,6 +365,8 @@ sph_status step_pre(sph_ctx *c, double dt)
 sph_status step_mid(sph_ctx *c)
 {
     const int64_t n = c->n;
+    // the force walk needs the boxes' largest h after the h solve
+    TRY(refresh_hmax(c, n));
     TRY(force_prep(c, n, c->s.up));
     return forces_prepare(c, n, c->s.vpx, c->s.vpy, c->s.vpz);
 }
@@ -613,6 +615,7 @@ sph_status sph_upload_state(sph_ctx *c, const sph_particles *ps)
                                     hipMemcpyDeviceToDevice, c->stream), "copy ids"));
     TRY(build_tree(c, n));
     TRY(run_density(c, n));
+    TRY(refresh_hmax(c, n));
     TRY(force_prep(c, n, c->s.u));
     TRY(run_forces(c, n, c->s.vx, c->s.vy, c->s.vz));
     TRY(reduce_dt(c, n));

@@ -465,6 +465,22 @@ __global__ __launch_bounds__(256) void k_leaves(const TreeInfo *__restrict__ T,
     }
 }
 
+// largest h of every leaf after the h solve changed h (boxes are unchanged),
+// one thread per leaf over its consecutive particles
+__global__ __launch_bounds__(256) void k_leaf_hmax(const TreeInfo *__restrict__ T,
+                                                   const uint32_t *__restrict__ lstart,
+                                                   const double *__restrict__ h,
+                                                   Node *__restrict__ nodes)
+{
+    const int64_t L = T->cnt[0];
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        double hm = 0.0;
+        for (int64_t k = lstart[l]; k < (int64_t)lstart[l + 1]; k++) hm = fmax(hm, h[k]);
+        nodes[l].hmax = hm;
+    }
+}
+
 constexpr int64_t kSmallLevel = 2048;   // children per level handled by one block
 constexpr int kBigLevels = 4;           // levels built grid-wide at most
 
@@ -599,6 +615,18 @@ sph_status gather(sph_ctx *c, int64_t n, const GatherList &g, bool identity_src_
     return hip_check(c, hipGetLastError(), "gather");
 }
 
+// nodes above the leaves, merged level by level
+static void upper_levels(sph_ctx *c, int64_t n)
+{
+    int64_t bound = n;
+    for (int l = 1; l <= kBigLevels; l++) {
+        bound = ceil_div(bound, 8);
+        hipLaunchKernelGGL(k_tree_level_big, dim3(grid_for(bound, 256)), dim3(256), 0, c->stream,
+                           c->d_tree, c->nodes, l);
+    }
+    hipLaunchKernelGGL(k_tree_level_small, dim3(1), dim3(1024), 0, c->stream, c->d_tree, c->nodes);
+}
+
 sph_status build_tree(sph_ctx *c, int64_t n)
 {
     c->tree_n = -1;
@@ -626,19 +654,23 @@ sph_status build_tree(sph_ctx *c, int64_t n)
                        flag, tcnt, c->leaf_id, c->lstart);
     hipLaunchKernelGGL(k_leaves, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, c->d_tree,
                        c->lstart, c->s.x, c->s.y, c->s.z, c->s.h, c->nodes);
-    int64_t bound = n;
-    for (int l = 1; l <= kBigLevels; l++) {
-        bound = ceil_div(bound, 8);
-        hipLaunchKernelGGL(k_tree_level_big, dim3(grid_for(bound, 256)), dim3(256), 0, c->stream,
-                           c->d_tree, c->nodes, l);
-    }
-    hipLaunchKernelGGL(k_tree_level_small, dim3(1), dim3(1024), 0, c->stream, c->d_tree, c->nodes);
+    upper_levels(c, n);
     if (c->p.precision == SPH_FP32_PAIR)
         hipLaunchKernelGGL(k_offsets, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n,
                            c->leaf_id, c->s.x, c->s.y, c->s.z, c->nodes, c->s.fx, c->s.fy, c->s.fz);
     sph_status st = hip_check(c, hipGetLastError(), "build_tree");
     if (st == SPH_OK) c->tree_n = n;
     return st;
+}
+
+sph_status refresh_hmax(sph_ctx *c, int64_t n)
+{
+    if (n == 0) return SPH_OK;
+    if (c->tree_n != n) return fail(c, SPH_ESTATE, "refresh_hmax: tree not built");
+    hipLaunchKernelGGL(k_leaf_hmax, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, c->d_tree,
+                       c->lstart, c->s.h, c->nodes);
+    upper_levels(c, n);
+    return hip_check(c, hipGetLastError(), "refresh_hmax");
 }
 
 sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted)

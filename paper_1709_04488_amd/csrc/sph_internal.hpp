@@ -175,6 +175,8 @@ sph_status gather(sph_ctx *c, int64_t n, const GatherList &g, bool identity_src_
 // Leaf boxes and tree over c->s.{x,y,z,h}; FP32 offsets when requested.
 sph_status build_tree(sph_ctx *c, int64_t n);
 // Per-particle force record (A, c, hinv) from rho, omega, u.
+// leaf and node hmax from the current sorted h (after the h solve), boxes kept
+sph_status refresh_hmax(sph_ctx *c, int64_t n);
 sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted);
 sph_status iota(sph_ctx *c, int64_t n, uint32_t *v);
 int64_t node_count_bound(int64_t n);

@@ -263,6 +263,26 @@ def test_kdk_steps_match_oracle(sph, orc):
     assert e == pytest.approx(energy[-1], rel=1e-10)
 
 
+@pytest.mark.parametrize("which", ["plummer", "blob"])
+def test_resident_forces_after_h_grows(sph, orc, which):
+    """Resident state from initial h at half the solution: the h solve doubles
+    h, and the force walk must use the new h (all force pairs found)."""
+    w = W.plummer(3000, seed=31) if which == "plummer" else W.blob_in_lattice(12, seed=32)
+    a = dict(w.arrays)
+    a["h"] = 0.5 * a["h"]
+    print("case: resident %s N=%d h0/2" % (w.name, w.n), flush=True)
+    p = orc.Params(**w.setup)
+    ref = orc.evaluate(p, a["x"], a["y"], a["z"], a["vx"], a["vy"], a["vz"], a["m"], a["u"], a["h"])
+    with sph.Context(sph.Params.from_setup(w.setup)) as ctx:
+        ctx.upload_state(sph.Particles.from_host(a))
+        q = sph.Particles.from_host(a)
+        ctx.download_state(q)
+        ctx.sync()
+        out = q.host()
+    assert np.median(out["h"] / a["h"]) > 1.5
+    _check(out, ref, label="resident " + w.name)
+
+
 def test_fp32_pair_mode_tolerances(sph, orc):
     for w in (W.config0(), W.plummer(3000, seed=12)):
         print("case: fp32 %s" % w.name, flush=True)
