@@ -98,7 +98,32 @@ def run_gpu(w, precision: int, steps: int, warmup: int, leaf: int, warm_start: b
     return res
 
 
-def roofline(res, prec: str):
+def measured_traffic(tag: str, kernel: str):
+    """HBM bytes per launch of a pair loop from the committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters read for a
+    plain copy of known size), or None when there is no such run for this
+    workload or the pair-loop source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1709_04488_amd", "csrc", "pairs.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(tag)
+    if not rec:
+        return None
+    if rec.get("pairs_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    b = rec.get("bytes_per_launch", {}).get(kernel)
+    return None if b is None else int(round(b["read"] + b["written"]))
+
+
+def prof_tag(args, prec: str):
+    """Key of the committed counter runs that match this invocation (the
+    profiled runs use the default leaf size)."""
+    return f"{args.config}_{prec}" if args.leaf == 16 else None
+
+
+def roofline(res, prec: str, tag: str = None, phase: str = "cold"):
     info = res["info"]
     km = res["kernel_ms"]
     dens_flops = info["dens_pair_evals"] * DENS_FLOPS_PER_PAIR_ITER
@@ -108,8 +133,10 @@ def roofline(res, prec: str):
     flops, t_ms = cand[name]
     achieved = flops / (t_ms * 1e-3) / 1e12 if t_ms > 0 else 0.0
     peak = PEAK_TFLOPS[prec]
+    key = f"{name}_{phase}" if name == "density" else f"{name}_all"
+    traffic = measured_traffic(tag, key) if tag else None
     return {"bound": "alu", "kernel": name, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
             "flops_per_launch": flops, "avg_launch_ms": round(t_ms, 4),
             "other_kernel": {k: {"flops_per_launch": v[0], "avg_launch_ms": round(v[1], 4),
                                  "achieved_tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 3) if v[1] > 0 else 0}
@@ -220,7 +247,7 @@ def main():
                                "cold h start from the input guess",
                    "n": w.n, "leaf_size": args.leaf,
                    "interactions_per_step": head["interactions"]},
-        "roofline": roofline(head, prec_name),
+        "roofline": roofline(head, prec_name, tag=prof_tag(args, prec_name)),
         "nr_iter_max": head["info"]["nr_iter_max"],
         "walk_overflows": head["info"]["walk_overflows"],
         "dens_leaf_visits": head["info"]["dens_leaf_visits"],
@@ -237,7 +264,7 @@ def main():
         r = results["fp32"]
         out["fp32_pair"] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
                             "speedup_vs_fp64": r["value"] / head["value"],
-                            "roofline": roofline(r, "fp32"),
+                            "roofline": roofline(r, "fp32", tag=prof_tag(args, "fp32")),
                             "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

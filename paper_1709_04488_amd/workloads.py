@@ -18,9 +18,9 @@ Recipes (code units, equal masses m = 1/N):
   (a seeded permutation) redrawn from a Gaussian blob N(0.5, sigma_b^2) per
   axis, wrapped into the box; u lognormal(0, 0.3), v ~ N(0, 0.2^2).
 * ``plummer`` -- a Plummer sphere (density and 1D dispersion as in the
-  paper's Plummer test, section 6.4) with scale radius a, radius cut,
+  Plummer-sphere test of section 6.7, eq. EQN:PLUMMERRHO) with scale radius a, radius cut,
   isolated boundary, velocities N(0, sigma^2(r)) per component and
-  u = sigma^2(r)/(gamma - 1) (the paper's hybrid Plummer set-up, section 6.5).
+  u = sigma^2(r)/(gamma - 1) (the hybrid star-and-gas Plummer set-up, section 6.8).
 * ``lattice`` -- a perfect n^3 cubic lattice, at rest (used by invariants).
 """
 from __future__ import annotations
