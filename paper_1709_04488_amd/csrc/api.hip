@@ -79,8 +79,12 @@ void free_all(sph_ctx *c)
     c->allocs.clear();
     if (c->nodes) (void)hipFree(c->nodes);
     if (c->hist) (void)hipFree(c->hist);
+    if (c->cache) (void)hipFree(c->cache);
     c->nodes = nullptr;
     c->hist = nullptr;
+    c->cache = nullptr;
+    c->cache_blocks = 0;
+    c->cache_leaf = 0;
     c->ncap = 0;
     c->node_cap = 0;
     c->hist_cap = 0;
@@ -116,13 +120,50 @@ sph_status alloc(sph_ctx *c, T **ptr, int64_t count)
 
 } // namespace
 
+// The density loop's candidate cache, sized for the pair grid of the current
+// capacity at the current leaf size.
+static sph_status ensure_cache(sph_ctx *c)
+{
+    const int G = c->p.leaf_size;
+    const int64_t blocks = pair_grid(c->ncap);
+    if (c->cache && c->cache_leaf == G && c->cache_blocks >= blocks) return SPH_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
+    if (c->cache) {
+        // a captured graph refers to the cache about to be freed
+        if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->graph_exec = nullptr;
+        c->graph = nullptr;
+        (void)hipFree(c->cache);
+        c->bytes -= (size_t)cache_bytes(c->cache_leaf, c->cache_blocks);
+        c->cache = nullptr;
+        c->cache_blocks = 0;
+        c->cache_leaf = 0;
+    }
+    const int64_t bytes = cache_bytes(G, blocks);
+    if (c->budget && c->bytes + (size_t)bytes > c->budget)
+        return fail(c, SPH_EBUDGET, "candidate cache of " + std::to_string(bytes) +
+                                        " bytes exceeds the HBM budget");
+    e = hipMalloc((void **)&c->cache, (size_t)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c->cache = nullptr;
+        return fail(c, SPH_ENOMEM, "hipMalloc failed (candidate cache)");
+    }
+    c->bytes += (size_t)bytes;
+    c->cache_blocks = blocks;
+    c->cache_leaf = G;
+    return SPH_OK;
+}
+
 sph_status ensure_capacity(sph_ctx *c, int64_t n)
 {
     if (n > (int64_t)0xFFFFFFF0ll) return fail(c, SPH_EINVAL, "n exceeds 2^32 - 16");
-    if (n <= c->ncap && node_count_bound(n) <= c->node_cap) return SPH_OK;
+    if (n <= c->ncap && node_count_bound(n) <= c->node_cap) return ensure_cache(c);
     int64_t cap = std::max<int64_t>(n, 1024);
     int64_t need = bytes_per_particle(c->p) * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
-                   256 * 4 * ceil_div(cap, kRsTile) + 4096;
+                   256 * 4 * ceil_div(cap, kRsTile) + 4096 + cache_bytes(c->p.leaf_size, pair_grid(cap));
     if (c->budget && (size_t)need > c->budget)
         return fail(c, SPH_EBUDGET, "working set of " + std::to_string(need) +
                                         " bytes exceeds the HBM budget of " +
@@ -162,7 +203,7 @@ sph_status ensure_capacity(sph_ctx *c, int64_t n)
     c->node_cap = ncap_nodes;
     c->hist_cap = hcap;
     c->ncap = cap;
-    return SPH_OK;
+    return ensure_cache(c);
 }
 
 void timer_begin(sph_ctx *c, int which, hipEvent_t *b, hipEvent_t *e)
@@ -846,7 +887,8 @@ size_t sph_plan_bytes(const sph_params *p, int64_t n)
     if (!p || n < 0) return 0;
     const int64_t cap = std::max<int64_t>(n, 1024);
     return (size_t)(bytes_per_particle(*p) * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
-                    256 * 4 * ceil_div(cap, kRsTile) + 4096 + 3 * kArgBytes);
+                    256 * 4 * ceil_div(cap, kRsTile) + 4096 + 3 * kArgBytes +
+                    cache_bytes(p->leaf_size, pair_grid(cap)));
 }
 
 sph_status sph_enable_kernel_timing(sph_ctx *c, int32_t enable)

@@ -71,7 +71,9 @@ __device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work
         for (;;) {
             uint32_t claim = 0;
             if (lane == 0) claim = atomicAdd(&work[x], 1u);
-            claim = __shfl(claim, 0);
+            // wave-uniform from here on (scalar registers): the leaf's argument
+            // block, node and particle range are then loaded once per wave
+            claim = __builtin_amdgcn_readfirstlane(__shfl(claim, 0));
             const int64_t leaf = beg + (int64_t)claim;
             if (leaf >= end) break;
             fn(leaf);
@@ -404,10 +406,16 @@ __device__ inline void separation(const Stage<NL> &S, const Box &bx, const Home 
 // work done for a leaf depends on its own request only, so a set gives the
 // same bits alone and inside any mix.
 // ---------------------------------------------------------------------------
+// Pair kernels are built for 3 waves per SIMD (<= 168 VGPRs): measured on
+// MI355X faster than the compiler's own choice of 2 (~230 VGPRs) and than 4,
+// where the force loop spills heavily.
+constexpr int kPairWavesPerSimd = 3;
+
 template <class Args>
 struct Batch {
     int32_t nreq;
     uint32_t *work;
+    double *cache;   // density loop: per-block candidate cache (nullptr: none)
     const Args *req[kMaxBatch];
 };
 
@@ -459,7 +467,7 @@ struct DensArgs {
 };
 
 template <int G, int PREC>
-__global__ __launch_bounds__(kWave) void k_density(Batch<DensArgs> B)
+__global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_density(Batch<DensArgs> B)
 {
     constexpr int LPP = kWave / G;   // lanes per home particle
     constexpr int NL = LPP;          // candidate leaves staged per group
@@ -472,6 +480,14 @@ __global__ __launch_bounds__(kWave) void k_density(Batch<DensArgs> B)
     batch_prefix(B, pre);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
+    // Candidate cache of this block: for every lane up to K entries (r^2, m)
+    // of its share of the candidates within 2 Rc of its particle, in the
+    // order a sweep meets them; laid out [entry][lane] so each entry index is
+    // one coalesced 512-byte row.  The mass of the particle itself is stored
+    // negated so the cached pass can leave it out of the neighbour count.
+    constexpr int K = cache_entries_per_lane(G);
+    double *const cr2 = B.cache ? B.cache + (size_t)blockIdx.x * (2 * K * kWave) : nullptr;
+    double *const cm = cr2 ? cr2 + K * kWave : nullptr;
     int64_t evals = 0, walks = 0, visits = 0, overflows = 0;
     int iter_max = 0;
     int cur = -1;
@@ -528,12 +544,45 @@ __global__ __launch_bounds__(kWave) void k_density(Batch<DensArgs> B)
         walks++;
         if (wr.lev) overflows++;
         int iter = 0;
+        // cache state of this lane's particle: `cached` = its list holds every
+        // candidate within 2 Rc (no lane of the particle overflowed); valid
+        // while h <= Rc
+        bool cached = false;
+        bool build = false;
+        double Rc = 0.0, rc2 = -1.0;
+        int nc = 0;
         for (;;) {
             double s0 = 0.0, s2 = 0.0;
             int cnt = 0;
             const double hinv = 1.0 / h;
             const double h2x4 = (2.0 * h) * (2.0 * h);
             const float h2x4f = (float)h2x4;
+            // the pair terms of one hit, shared by the sweep and the cached pass
+            auto accumulate = [&](double r2, double mj) {
+                if (PREC == SPH_FP64) {
+                    double f, df;
+                    const double qq = sqrt(r2) * hinv;
+                    m4(qq, f, df);
+                    s0 += mj * f;
+                    s2 += mj * (qq * df);
+                } else {
+                    float f, df;
+                    const float qq = sqrtf((float)r2) * (float)hinv;
+                    m4(qq, f, df);
+                    s0 += mj * (double)f;
+                    s2 += mj * (double)(qq * df);
+                }
+            };
+            const bool sweep = cr2 == nullptr || __ballot(!conv && !cached) != 0ull;
+            if (sweep) {
+                // every particle still iterating (re)builds its list around its current h
+                build = cr2 != nullptr && !conv;
+                if (build) {
+                    Rc = fmin(kCacheGrow * h, hcov);
+                    rc2 = (2.0 * Rc) * (2.0 * Rc) * (1.0 + 1e-6);
+                }
+                nc = 0;
+            }
             auto group = [&](const uint32_t *leaves, int count) {
                 stage_group<G, NL, PREC>(S, leaves, count, A.lstart, A.nodes, home, bx, hcov, A.x, A.y,
                                          A.z, A.m, A.fx, A.fy, A.fz);
@@ -549,38 +598,66 @@ __global__ __launch_bounds__(kWave) void k_density(Batch<DensArgs> B)
                         if (slot < jn) {
                             double dx, dy, dz, r2;
                             separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
-                            const bool in = PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f;
-                            if (in) hits[nh++][lane] = (uint8_t)s;
+                            // building a list: record everything inside 2 Rc (a
+                            // superset of the hits, since h <= Rc)
+                            const bool rec = build ? r2 < rc2
+                                                   : (PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f);
+                            if (rec) hits[nh++][lane] = (uint8_t)s;
                         }
                     }
                 }
-                // flush: pair terms of the recorded hits
+                // flush: append the recorded entries to the list (when
+                // building) and take the pair terms of the hits among them
                 const int nmax = wave_max_int(nh);
                 for (int e = 0; e < nmax; e++) {
                     if (e < nh) {
                         const int s = hits[e][lane];
                         double dx, dy, dz, r2;
                         separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
-                        const double mj = S.w[s];
-                        if (PREC == SPH_FP64) {
-                            double f, df;
-                            const double qq = sqrt(r2) * hinv;
-                            m4(qq, f, df);
-                            s0 += mj * f;
-                            s2 += mj * (qq * df);
-                        } else {
-                            float f, df;
-                            const float qq = sqrtf((float)r2) * (float)hinv;
-                            m4(qq, f, df);
-                            s0 += mj * (double)f;
-                            s2 += mj * (double)(qq * df);
+                        const bool self = S.j[s] == (uint32_t)i;
+                        if (build) {
+                            if (nc < K) {
+                                cr2[nc * kWave + lane] = r2;
+                                cm[nc * kWave + lane] = self ? -S.w[s] : S.w[s];
+                            }
+                            nc++;
                         }
-                        cnt += (S.j[s] != (uint32_t)i);
+                        const bool in = PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f;
+                        if (in) {
+                            accumulate(r2, S.w[s]);
+                            cnt += self ? 0 : 1;
+                        }
                     }
                 }
                 wave_lds_sync();
             };
-            visits += for_each_leaf_group<NL>(T, A.nodes, wr, make_test(hcov), wb, group);
+            if (sweep) {
+                visits += for_each_leaf_group<NL>(T, A.nodes, wr, make_test(hcov), wb, group);
+                if (build) {
+                    int ovf = nc > K ? 1 : 0;
+#pragma unroll
+                    for (int o = 1; o < LPP; o <<= 1) ovf |= __shfl_xor(ovf, o);
+                    cached = ovf == 0;
+                } else {
+                    cached = false;
+                }
+            } else {
+                // every particle still iterating has a complete list and h <= Rc:
+                // the entries inside 2h, in list order, are exactly the hits a
+                // sweep would find, in the order it would find them
+                const int nmax = wave_max_int(conv ? 0 : nc);
+                for (int e = 0; e < nmax; e++) {
+                    if (!conv && e < nc) {
+                        const double r2 = cr2[e * kWave + lane];
+                        const bool in = PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f;
+                        if (in) {
+                            const double mw = cm[e * kWave + lane];
+                            accumulate(r2, fabs(mw));
+                            cnt += signbit(mw) ? 0 : 1;
+                        }
+                    }
+                }
+            }
             if (!conv) evals += cnt;
 #pragma unroll
             for (int o = 1; o < LPP; o <<= 1) {
@@ -612,6 +689,7 @@ __global__ __launch_bounds__(kWave) void k_density(Batch<DensArgs> B)
                     else h = hn;
                 }
             }
+            if (cached && !(h <= Rc)) cached = false;
             iter++;
             if (__ballot(!conv) == 0ull || iter >= A.max_iter) break;
             const double hmx = wave_max(conv ? 0.0 : h);
@@ -668,7 +746,7 @@ struct ForceArgs {
 };
 
 template <int G, int PREC>
-__global__ __launch_bounds__(kWave) void k_forces(Batch<ForceArgs> B)
+__global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<ForceArgs> B)
 {
     constexpr int LPP = kWave / G;
     constexpr int NL = LPP;
@@ -1004,12 +1082,6 @@ inline void fill_common(sph_ctx *c, int64_t n, Args &a)
 
 // Persistent grid: a multiple of the XCD count, enough one-wave blocks to
 // fill every CU several times over, never more than there can be leaves.
-inline unsigned leaf_grid(int64_t n)
-{
-    int64_t blocks = std::min<int64_t>(n, 256 * 24);
-    blocks = ((blocks + kXcds - 1) / kXcds) * kXcds;
-    return (unsigned)blocks;
-}
 
 } // namespace
 
@@ -1130,7 +1202,18 @@ sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax)
         leaves_bound += cs[r]->n;
     }
     (void)nmax;
-    const unsigned grid = leaf_grid(leaves_bound);
+    unsigned grid = pair_grid(leaves_bound);
+    // the candidate cache of the set whose cache serves the most blocks at this
+    // leaf size; the grid never exceeds it (without one the loop sweeps)
+    const sph_ctx *owner = nullptr;
+    for (int r = 0; r < count; r++)
+        if (cs[r]->cache && cs[r]->cache_leaf == c->p.leaf_size &&
+            (!owner || cs[r]->cache_blocks > owner->cache_blocks))
+            owner = cs[r];
+    if (owner) {
+        B.cache = owner->cache;
+        if ((int64_t)grid > owner->cache_blocks) grid = (unsigned)owner->cache_blocks;
+    }
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_begin(c, 0, &e0, &e1);
@@ -1167,7 +1250,7 @@ sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax)
         leaves_bound += cs[r]->n;
     }
     (void)nmax;
-    const unsigned grid = leaf_grid(leaves_bound);
+    const unsigned grid = pair_grid(leaves_bound);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_begin(c, 1, &e0, &e1);
@@ -1225,7 +1308,7 @@ sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_s
         if (offsets && cap > 0 && !idx) return fail(c, SPH_EINVAL, "neighbours: no idx");
         if (c->tree_n != n) return fail(c, SPH_ESTATE, "neighbours: tree not built");
     }
-    const unsigned grid = leaf_grid(n);
+    const unsigned grid = pair_grid(n);
     const int pass = offsets ? 2 : 1;
     {
         sph_status zs = zero_work(c);

@@ -23,6 +23,29 @@ constexpr int kXcds = 8;         // MI355X: 8 XCDs, blocks dispatched round-robi
 constexpr int kMaxBatch = 128;   // particle sets per batched pair-kernel launch
 constexpr int kArgBytes = 1024;  // device argument block of one pair-kernel launch
 
+// Persistent pair-kernel grid: one wave per block, at most as many blocks as
+// the GPU holds at once (256 CUs x 16 waves at the pair kernels' register and
+// LDS use), at least one block per 8 particles below that, a multiple of the
+// XCD count.
+constexpr int64_t kMaxPairBlocks = 256 * 16;
+inline unsigned pair_grid(int64_t n)
+{
+    int64_t blocks = (n + 7) / 8;
+    blocks = blocks < kXcds ? kXcds : (blocks > kMaxPairBlocks ? kMaxPairBlocks : blocks);
+    blocks = ((blocks + kXcds - 1) / kXcds) * kXcds;
+    return (unsigned)blocks;
+}
+
+// Density-loop candidate cache: 128 entries per particle (2 G per lane), each
+// an FP64 r^2 and an FP64 mass; built around Rc = kCacheGrow h (capped by the
+// walk radius) so that Newton steps within that bound reuse it.
+constexpr double kCacheGrow = 1.15;
+__host__ __device__ constexpr int cache_entries_per_lane(int G) { return 2 * G; }
+inline int64_t cache_bytes(int G, int64_t blocks)
+{
+    return blocks * 2 * cache_entries_per_lane(G) * kWave * (int64_t)sizeof(double);
+}
+
 // Tree node: bounding box of the particles below it and their largest h.
 // 64 bytes, so one node is half a 128-byte cache line.
 struct alignas(64) Node {
@@ -115,6 +138,9 @@ struct sph_ctx {
     uint32_t *lstart = nullptr;         // leaf -> first sorted particle, [L+1]
     uint32_t *leaf_id = nullptr;        // sorted particle -> leaf
     uint32_t *d_work = nullptr;         // per-XCD claim counters of the pair kernels
+    double *cache = nullptr;            // density-loop candidate cache, per pair-kernel block
+    int64_t cache_blocks = 0;           // blocks the cache serves ...
+    int32_t cache_leaf = 0;             // ... at this leaf size
     void *d_dargs = nullptr;            // device argument block of the density loop
     void *d_fargs = nullptr;            // device argument block of the force loop
     uint64_t *skeys = nullptr;          // sorted keys of the last build
