@@ -101,8 +101,9 @@ class SimClock:
 # scheduler
 # ----------------------------------------------------------------------------
 class Scheduler:
-    def __init__(self, executor, budget_bytes: int, max_slots: int, clock=None):
+    def __init__(self, executor, budget_bytes: int, max_slots: int, clock=None, progress=None):
         self.ex = executor
+        self.progress = progress                  # callable(done, total) or None
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.clock = clock or WallClock()
@@ -190,6 +191,8 @@ class Scheduler:
                 self.slot_busy[slot] = False
                 self.array_bytes.pop(rid, None)
                 self.events.append((rec.done, "done", rid))
+                if self.progress:
+                    self.progress(sum(1 for r in recs.values() if not math.isnan(r.done)), len(recs))
             if not started and not finished:
                 nxt = pending[k].arrival if k < len(pending) else math.inf
                 self.ex.wait(self.clock, nxt)
@@ -424,10 +427,16 @@ def integrate_requests(count: int, nsteps: int, rate: float = math.inf, seed: in
     return reqs
 
 
-def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=False):
+def _progress(done: int, total: int):
+    if done == total or done % 16 == 0:
+        print(f"# served {done}/{total}", file=sys.stderr, flush=True)
+
+
+def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=False,
+          progress=False):
     import torch
     ex = GpuExecutor(slots, mode=mode, leaf_for=leaf_for, keep_outputs=keep_outputs)
-    sched = Scheduler(ex, budget, slots, WallClock())
+    sched = Scheduler(ex, budget, slots, WallClock(), progress=_progress if progress else None)
     t0 = sched.clock.now()
     recs = sched.run(reqs)
     torch.cuda.synchronize()
@@ -454,16 +463,16 @@ def main(argv=None):
     budget = int(gib * GIB)
     if args.workload == "evaluate":
         burst = evaluate_requests(args.requests, math.inf, n_max_side=args.max_side)
-        _, closed = serve(burst, budget, args.slots, args.mode)
+        _, closed = serve(burst, budget, args.slots, args.mode, progress=True)
         rate = args.load * closed["requests_per_s"]
         reqs = evaluate_requests(args.requests, rate, n_max_side=args.max_side)
-        _, opened = serve(reqs, budget, args.slots, args.mode)
+        _, opened = serve(reqs, budget, args.slots, args.mode, progress=True)
         res = {"workload": "evaluate", "mode": args.mode, "slots": args.slots,
                "budget_bytes": budget, "saturated": closed, "arrival_rate_per_s": rate,
                "poisson": opened}
     else:
         reqs = integrate_requests(args.requests, args.steps, n_max_side=args.max_side)
-        recs, out = serve(reqs, budget, args.slots, args.mode)
+        recs, out = serve(reqs, budget, args.slots, args.mode, progress=True)
         steps = sum(r.info.get("steps", 0) for r in recs if not r.error)
         res = {"workload": "integrate", "mode": args.mode, "slots": args.slots,
                "budget_bytes": budget, "steps_per_request": args.steps, "result": out,
