@@ -118,9 +118,9 @@ def measured_traffic(tag: str, kernel: str):
 
 
 def prof_tag(args, prec: str):
-    """Key of the committed counter runs that match this invocation (the
-    profiled runs use the default leaf size)."""
-    return f"{args.config}_{prec}" if args.leaf == 16 else None
+    """Key of the committed counter runs that match this invocation: workload,
+    precision and leaf size."""
+    return f"{args.config}_{prec}_g{args.leaf_used[prec]}"
 
 
 def roofline(res, prec: str, tag: str = None, phase: str = "cold"):
@@ -186,7 +186,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c1", help="c0, c1 (default), c2 or c1s<n_side>")
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32", "both"])
-    ap.add_argument("--leaf", type=int, default=16)
+    ap.add_argument("--leaf", default="auto",
+                    help="leaf size 8, 16 or 32, or auto (autotuner, per precision, untimed)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
@@ -214,14 +215,29 @@ def main():
     print(f"# workload {w.name} N={w.n} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
     from paper_1709_04488_amd import sph
+    from paper_1709_04488_amd import tune
+    leaf = {}
+    tuned = {}
+    for name, prec in (("fp64", sph.SPH_FP64), ("fp32", sph.SPH_FP32_PAIR)):
+        if args.precision not in (name, "both"):
+            continue
+        if args.leaf == "auto":
+            tuned[name] = tune.LeafTuner().measure(w.arrays, w.setup, prec)
+            leaf[name] = tuned[name]["leaf"]
+            print(f"# autotuner {name}: leaf {leaf[name]} "
+                  f"({', '.join(f'{g}: {s * 1e3:.1f} ms' for g, s in tuned[name]['seconds'].items())})",
+                  file=sys.stderr, flush=True)
+        else:
+            leaf[name] = int(args.leaf)
+    args.leaf_used = leaf
     results = {}
     if args.precision in ("fp64", "both"):
-        results["fp64"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, args.leaf)
+        results["fp64"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, leaf["fp64"])
         print(f"# fp64: {results['fp64']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-        results["fp64_warm"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, args.leaf,
+        results["fp64_warm"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, leaf["fp64"],
                                        warm_start=True)
     if args.precision in ("fp32", "both"):
-        results["fp32"] = run_gpu(w, sph.SPH_FP32_PAIR, args.steps, args.warmup, args.leaf)
+        results["fp32"] = run_gpu(w, sph.SPH_FP32_PAIR, args.steps, args.warmup, leaf["fp32"])
         print(f"# fp32: {results['fp32']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     head_key = "fp64" if "fp64" in results else "fp32"
@@ -245,7 +261,8 @@ def main():
                                + f", eta={w.setup['eta']}, M4, alpha_AV=1, beta_AV=2, "
                                f"{'FP64' if head_key == 'fp64' else 'FP32-pair'}, "
                                "cold h start from the input guess",
-                   "n": w.n, "leaf_size": args.leaf,
+                   "n": w.n, "leaf_size": leaf[prec_name],
+                   "leaf_choice": "autotuner" if args.leaf == "auto" else "fixed",
                    "interactions_per_step": head["interactions"]},
         "roofline": roofline(head, prec_name, tag=prof_tag(args, prec_name)),
         "nr_iter_max": head["info"]["nr_iter_max"],
@@ -263,9 +280,12 @@ def main():
     if "fp32" in results and head_key != "fp32":
         r = results["fp32"]
         out["fp32_pair"] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                            "leaf_size": leaf["fp32"],
                             "speedup_vs_fp64": r["value"] / head["value"],
                             "roofline": roofline(r, "fp32", tag=prof_tag(args, "fp32")),
                             "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()}}
+    if tuned:
+        out["autotuner"] = tuned
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

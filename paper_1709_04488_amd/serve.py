@@ -288,7 +288,9 @@ class GpuExecutor:
                                           leaf_size=self.leaf_for(req))
 
     def slot_bytes(self, cap: int) -> int:
-        return 0 if cap == 0 else self.sph.plan_bytes(self.sph.Params(leaf_size=8), cap)
+        # a slot may run any leaf size; plan for the one that needs the most
+        return 0 if cap == 0 else max(self.sph.plan_bytes(self.sph.Params(leaf_size=g), cap)
+                                      for g in (8, 16, 32))
 
     def array_bytes(self, req: Request) -> int:
         return req.n * 8 * 19 + req.n * 4 * 2
@@ -458,29 +460,40 @@ def main(argv=None):
     ap.add_argument("--load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured saturated capacity")
     ap.add_argument("--max-side", type=int, default=None)
+    ap.add_argument("--leaf", default="auto",
+                    help="leaf size 8, 16 or 32, or auto: the autotuner picks per request class")
+    ap.add_argument("--tune-table", default=None, help="JSON table of the autotuner to load and update")
     args = ap.parse_args(argv)
+    if args.leaf == "auto":
+        from .tune import LeafTuner
+        leaf_for = LeafTuner(path=args.tune_table)
+    else:
+        g = int(args.leaf)
+        leaf_for = lambda req: g  # noqa: E731
     gib = args.budget_gib if args.budget_gib else (1.0 if args.workload == "evaluate" else 16.0)
     budget = int(gib * GIB)
     if args.workload == "evaluate":
         burst = evaluate_requests(args.requests, math.inf, n_max_side=args.max_side)
-        _, closed = serve(burst, budget, args.slots, args.mode, progress=True)
+        _, closed = serve(burst, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True)
         rate = args.load * closed["requests_per_s"]
         reqs = evaluate_requests(args.requests, rate, n_max_side=args.max_side)
-        _, opened = serve(reqs, budget, args.slots, args.mode, progress=True)
-        res = {"workload": "evaluate", "mode": args.mode, "slots": args.slots,
+        _, opened = serve(reqs, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True)
+        res = {"workload": "evaluate", "mode": args.mode, "slots": args.slots, "leaf": args.leaf,
                "budget_bytes": budget, "saturated": closed, "arrival_rate_per_s": rate,
                "poisson": opened}
     else:
         reqs = integrate_requests(args.requests, args.steps, n_max_side=args.max_side)
-        recs, out = serve(reqs, budget, args.slots, args.mode, progress=True)
+        recs, out = serve(reqs, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True)
         steps = sum(r.info.get("steps", 0) for r in recs if not r.error)
-        res = {"workload": "integrate", "mode": args.mode, "slots": args.slots,
+        res = {"workload": "integrate", "mode": args.mode, "slots": args.slots, "leaf": args.leaf,
                "budget_bytes": budget, "steps_per_request": args.steps, "result": out,
                "steps_total": steps,
                "per_step_latency_p50_ms": float(np.percentile(
                    [r.latency / max(args.steps, 1) * 1e3 for r in recs if not r.error], 50)),
                "per_step_latency_p99_ms": float(np.percentile(
                    [r.latency / max(args.steps, 1) * 1e3 for r in recs if not r.error], 99))}
+    if args.leaf == "auto":
+        res["autotuner"] = leaf_for.table
     print(json.dumps(res), flush=True)
 
 
