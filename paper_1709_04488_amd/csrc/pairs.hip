@@ -288,23 +288,48 @@ __device__ inline Shift leaf_shift(const Node &home, const Node &cand, const Box
     return sh;
 }
 
-// Staged group of NL candidate leaves (64 candidate particles).  Per staged
-// leaf: how the separation is formed (shift vector or per-pair minimum image,
-// FP32 offset between leaf centres) and how many particles it holds.
-template <int NL>
+// ---------------------------------------------------------------------------
+// Staging and the compacted candidate tests shared by the pair loops
+// ---------------------------------------------------------------------------
+// A wave holds the G home particles of one leaf, LPP = 64 / G lanes each.
+// Candidate leaves are staged NL = 128 / G at a time (128 candidate slots).
+// For every (home particle, staged leaf) combination the wave first measures
+// the distance from the particle to the leaf's box; only combinations that can
+// hold a pair are expanded, four candidate tests per lane, dealt out densely
+// over the 64 lanes.  Hits are bits of a per-particle mask over the 128 slots
+// (set with an LDS atomic OR, so the result does not depend on lane timing);
+// the flush walks each particle's mask in ascending slot order, its set bits
+// shared round-robin by the particle's own lanes.
+
+constexpr int kSlots = 2 * kWave;   // candidate slots per staged group
+constexpr int kTestsPerLane = 4;    // candidate tests per lane per combination
+
+template <int G, int PREC>
 struct Stage {
-    double x[kWave], y[kWave], z[kWave], w[kWave];   // w: mass (density) or h (forces)
-    float fx[kWave], fy[kWave], fz[kWave];
-    uint32_t j[kWave];
-    double sx[NL], sy[NL], sz[NL];
-    float ox[NL], oy[NL], oz[NL];
+    static constexpr int NL = kSlots / G;
+    static constexpr int NF = PREC == SPH_FP32_PAIR ? kSlots : 1;
+    double x[kSlots], y[kSlots], z[kSlots], w[kSlots];   // w: mass (density) or h (forces)
+    float fx[NF], fy[NF], fz[NF];
+    uint32_t j[kSlots];
+    // per staged leaf
+    double lo[NL][3], hi[NL][3];
+    double sx[NL], sy[NL], sz[NL];   // shift added to x_i - x_j (per-leaf periodic image)
+    double hmax[NL];
+    float ox[NL], oy[NL], oz[NL];    // FP32-pair: leaf-centre offset (with the shift)
     int32_t jn[NL];
-    int32_t per_pair[NL];
+    int32_t per_pair[NL];            // minimum image pair by pair instead of a shift
+    // per home particle
+    double hx[G], hy[G], hz[G];
+    float hfx[G], hfy[G], hfz[G];
+    double thr[G];                   // record threshold on r^2 (< 0: particle takes no part)
+    uint64_t mask[G][2];             // hits over the 128 slots
+    uint8_t combo[kSlots];           // compacted (particle, leaf) combinations
 };
 
-// Stage `count` candidate leaves; lane l fills slot l % G of leaf l / G.
-template <int G, int NL, int PREC>
-__device__ inline void stage_group(Stage<NL> &S, const uint32_t *leaves, int count,
+// Stage `count` (<= NL) candidate leaves; lane l fills slots l and l + 64,
+// slot s holding particle s % G of staged leaf s / G.
+template <int G, int PREC>
+__device__ inline void stage_group(Stage<G, PREC> &S, const uint32_t *leaves, int count,
                                    const uint32_t *__restrict__ lstart, const Node *__restrict__ nodes,
                                    const Node &home, const Box &bx, double hcov,
                                    const double *__restrict__ x, const double *__restrict__ y,
@@ -312,66 +337,71 @@ __device__ inline void stage_group(Stage<NL> &S, const uint32_t *leaves, int cou
                                    const float *__restrict__ fx, const float *__restrict__ fy,
                                    const float *__restrict__ fz)
 {
+    constexpr int NL = Stage<G, PREC>::NL;
     const int lane = threadIdx.x & (kWave - 1);
-    const int k = lane / G, slot = lane % G;
-    int jn = 0;
-    if (k < count) {
-        const uint32_t c = leaves[k];
-        const int64_t j0 = lstart[c];
-        jn = (int)(lstart[c + 1] - j0);
-        if (slot < jn) {
-            const int64_t j = j0 + slot;
-            S.x[lane] = x[j];
-            S.y[lane] = y[j];
-            S.z[lane] = z[j];
-            S.w[lane] = w[j];
-            if (PREC == SPH_FP32_PAIR) {
-                S.fx[lane] = fx[j];
-                S.fy[lane] = fy[j];
-                S.fz[lane] = fz[j];
+#pragma unroll
+    for (int half = 0; half < 2; half++) {
+        const int s = lane + half * kWave;
+        const int k = s / G, slot = s % G;
+        if (k < count) {
+            const uint32_t c = leaves[k];
+            const int64_t j0 = lstart[c];
+            const int jn = (int)(lstart[c + 1] - j0);
+            if (slot < jn) {
+                const int64_t j = j0 + slot;
+                S.x[s] = x[j];
+                S.y[s] = y[j];
+                S.z[s] = z[j];
+                S.w[s] = w[j];
+                if (PREC == SPH_FP32_PAIR) {
+                    S.fx[s] = fx[j];
+                    S.fy[s] = fy[j];
+                    S.fz[s] = fz[j];
+                }
+                S.j[s] = (uint32_t)j;
             }
-            S.j[lane] = (uint32_t)j;
-        }
-        if (slot == 0) {
-            const Node cand = nodes[c];
-            // hcov < 0: symmetric force criterion, reach 2 max(h over both leaves)
-            const Shift sh = leaf_shift(home, cand, bx, hcov < 0.0 ? fmax(home.hmax, cand.hmax) : hcov);
-            S.sx[k] = sh.s[0];
-            S.sy[k] = sh.s[1];
-            S.sz[k] = sh.s[2];
-            S.per_pair[k] = sh.per_pair ? 1 : 0;
-            S.jn[k] = jn;
-            if (PREC == SPH_FP32_PAIR) {
-                S.ox[k] = (float)((0.5 * (home.lo[0] + home.hi[0]) - 0.5 * (cand.lo[0] + cand.hi[0])) +
-                                  (sh.per_pair ? 0.0 : sh.s[0]));
-                S.oy[k] = (float)((0.5 * (home.lo[1] + home.hi[1]) - 0.5 * (cand.lo[1] + cand.hi[1])) +
-                                  (sh.per_pair ? 0.0 : sh.s[1]));
-                S.oz[k] = (float)((0.5 * (home.lo[2] + home.hi[2]) - 0.5 * (cand.lo[2] + cand.hi[2])) +
-                                  (sh.per_pair ? 0.0 : sh.s[2]));
+            if (slot == 0) {
+                const Node cand = nodes[c];
+                // hcov < 0: symmetric force criterion, reach 2 max(h over both leaves)
+                const Shift sh = leaf_shift(home, cand, bx, hcov < 0.0 ? fmax(home.hmax, cand.hmax) : hcov);
+                for (int a = 0; a < 3; a++) {
+                    S.lo[k][a] = cand.lo[a];
+                    S.hi[k][a] = cand.hi[a];
+                }
+                S.hmax[k] = cand.hmax;
+                S.sx[k] = sh.s[0];
+                S.sy[k] = sh.s[1];
+                S.sz[k] = sh.s[2];
+                S.per_pair[k] = sh.per_pair ? 1 : 0;
+                S.jn[k] = jn;
+                if (PREC == SPH_FP32_PAIR) {
+                    S.ox[k] = (float)((0.5 * (home.lo[0] + home.hi[0]) - 0.5 * (cand.lo[0] + cand.hi[0])) +
+                                      (sh.per_pair ? 0.0 : sh.s[0]));
+                    S.oy[k] = (float)((0.5 * (home.lo[1] + home.hi[1]) - 0.5 * (cand.lo[1] + cand.hi[1])) +
+                                      (sh.per_pair ? 0.0 : sh.s[1]));
+                    S.oz[k] = (float)((0.5 * (home.lo[2] + home.hi[2]) - 0.5 * (cand.lo[2] + cand.hi[2])) +
+                                      (sh.per_pair ? 0.0 : sh.s[2]));
+                }
             }
+        } else if (slot == 0 && k < NL) {
+            S.jn[k] = 0;
         }
-    } else if (slot == 0 && k < NL) {
-        S.jn[k] = 0;
     }
     wave_lds_sync();
 }
 
-// Separation of home particle i and staged entry s (leaf k = s / G); the same
-// expression serves the test and the flush, so both see identical bits.
-struct Home {
-    double x, y, z;
-    float fx, fy, fz;
-};
-
-template <int G, int NL, int PREC>
-__device__ inline void separation(const Stage<NL> &S, const Box &bx, const Home &hm, int s,
-                                  double &dx, double &dy, double &dz, double &r2)
+// Separation x_i - x_j of a home particle (given by value) and staged slot s;
+// the same expression serves every test and flush, so they see identical bits.
+template <int G, int PREC>
+__device__ inline void separation(const Stage<G, PREC> &S, const Box &bx, double hx, double hy,
+                                  double hz, float hfx, float hfy, float hfz, int s, double &dx,
+                                  double &dy, double &dz, double &r2)
 {
     const int k = s / G;
     if (PREC == SPH_FP64) {
-        dx = hm.x - S.x[s];
-        dy = hm.y - S.y[s];
-        dz = hm.z - S.z[s];
+        dx = hx - S.x[s];
+        dy = hy - S.y[s];
+        dz = hz - S.z[s];
         if (S.per_pair[k]) {
             dx = min_image(dx, bx.len[0], bx.half[0]);
             dy = min_image(dy, bx.len[1], bx.half[1]);
@@ -383,9 +413,9 @@ __device__ inline void separation(const Stage<NL> &S, const Box &bx, const Home 
         }
         r2 = exact_r2(dx, dy, dz);
     } else {
-        float fdx = (hm.fx - S.fx[s]) + S.ox[k];
-        float fdy = (hm.fy - S.fy[s]) + S.oy[k];
-        float fdz = (hm.fz - S.fz[s]) + S.oz[k];
+        float fdx = (hfx - S.fx[s]) + S.ox[k];
+        float fdy = (hfy - S.fy[s]) + S.oy[k];
+        float fdz = (hfz - S.fz[s]) + S.oz[k];
         if (S.per_pair[k]) {
             fdx = min_image_f(fdx, (float)bx.len[0], (float)bx.half[0]);
             fdy = min_image_f(fdy, (float)bx.len[1], (float)bx.half[1]);
@@ -396,6 +426,104 @@ __device__ inline void separation(const Stage<NL> &S, const Box &bx, const Home 
         dz = fdz;
         r2 = (double)(fdx * fdx + fdy * fdy + fdz * fdz);
     }
+}
+
+// Squared distance from home particle p to staged leaf k's box in the frame of
+// the separation; 0 for a per-pair leaf (every candidate is then tested).
+template <int G, int PREC>
+__device__ inline double box_dist2(const Stage<G, PREC> &S, int p, int k)
+{
+    if (S.per_pair[k]) return 0.0;
+    const double c[3] = {S.hx[p] + S.sx[k], S.hy[p] + S.sy[k], S.hz[p] + S.sz[k]};
+    double d2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double lo = S.lo[k][a], hi = S.hi[k][a];
+        const double d = c[a] < lo ? lo - c[a] : (c[a] > hi ? c[a] - hi : 0.0);
+        d2 += d * d;
+    }
+    return d2;
+}
+
+// The relative slack of the box test: it must accept every combination whose
+// candidates the record test can accept (rounding of the two differently
+// formed distances; FP32-pair separations carry single-precision error).
+template <int PREC>
+__device__ constexpr double box_slack() { return PREC == SPH_FP64 ? 1.0 + 1e-6 : 1.0 + 1e-4; }
+
+// Hit masks of one staged group: bit s of S.mask[p] set iff rec(p, s), with
+// rec evaluated only where relevant(p, k) holds for the slot's leaf k.
+template <int G, int PREC, class Relevant, class Record>
+__device__ inline void group_tests(Stage<G, PREC> &S, int count, Relevant relevant, Record rec)
+{
+    constexpr int NL = Stage<G, PREC>::NL;
+    constexpr int LPC = G / kTestsPerLane;   // lanes per combination
+    constexpr int CPR = kWave / LPC;         // combinations per round
+    static_assert(G * NL == kSlots && LPC * kTestsPerLane == G, "combination layout");
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t lt = __lanemask_lt();
+    // combination c = p * NL + k; this lane judges c = lane and c = lane + 64
+    bool r0, r1;
+    {
+        const int p = lane / NL, k = lane % NL;
+        r0 = k < count && relevant(p, k);
+    }
+    {
+        const int c = lane + kWave;
+        const int p = c / NL, k = c % NL;
+        r1 = k < count && relevant(p, k);
+    }
+    const uint64_t m0 = __ballot(r0), m1 = __ballot(r1);
+    const int n0 = (int)__popcll(m0);
+    if (r0) S.combo[__popcll(m0 & lt)] = (uint8_t)lane;
+    if (r1) S.combo[n0 + (int)__popcll(m1 & lt)] = (uint8_t)(lane + kWave);
+    const int C = n0 + (int)__popcll(m1);
+    wave_lds_sync();
+    const int u = lane % LPC;
+    // combinations of one round start their tests at different slots, which
+    // spreads their LDS reads over the banks
+    const int rot = lane / LPC;
+    for (int b = 0; b < C; b += CPR) {
+        const int idx = b + lane / LPC;
+        if (idx < C) {
+            const int c = S.combo[idx];
+            const int p = c / NL, k = c % NL;
+            const int jn = S.jn[k];
+            uint64_t bits = 0;
+#pragma unroll
+            for (int t = 0; t < kTestsPerLane; t++) {
+                const int slot = u + LPC * ((t + rot) % kTestsPerLane);
+                if (slot < jn) {
+                    const int s = k * G + slot;
+                    if (rec(p, s)) bits |= 1ull << (s & 63);
+                }
+            }
+            if (bits)
+                atomicOr((unsigned long long *)&S.mask[p][(k * G) >> 6], (unsigned long long)bits);
+        }
+    }
+    wave_lds_sync();
+}
+
+// The set bits of a 128-bit mask in ascending order, shared round-robin by
+// the LPP lanes of a particle: this lane takes the bits of rank e = e0,
+// e0 + LPP, ... (0 <= e0 < LPP) and calls fn(slot, e).  Returns the number of
+// set bits.
+template <int LPP, class Fn>
+__device__ inline int for_my_bits(uint64_t w0, uint64_t w1, int e0, Fn fn)
+{
+    const int n = (int)__popcll(w0) + (int)__popcll(w1);
+    for (int t = 0; t < e0; t++) {
+        if (w0) w0 &= w0 - 1; else w1 &= w1 - 1;
+    }
+    for (int e = e0; e < n; e += LPP) {
+        const int s = w0 ? (int)__builtin_ctzll(w0) : 64 + (int)__builtin_ctzll(w1);
+        fn(s, e);
+        for (int t = 0; t < LPP; t++) {
+            if (w0) w0 &= w0 - 1; else w1 &= w1 - 1;
+        }
+    }
+    return n;
 }
 
 // ---------------------------------------------------------------------------
@@ -420,13 +548,14 @@ struct Batch {
 };
 
 template <class Args>
-__device__ inline void batch_prefix(const Batch<Args> &B, int64_t *pre)
+__device__ inline void batch_prefix(const Batch<Args> &B, uint32_t *pre)
 {
+    // the host keeps the total leaf count (<= total particles) below 2^32
     if (threadIdx.x == 0) {
-        int64_t acc = 0;
+        uint32_t acc = 0;
         pre[0] = 0;
         for (int r = 0; r < B.nreq; r++) {
-            acc += B.req[r]->tree->cnt[0];
+            acc += (uint32_t)B.req[r]->tree->cnt[0];
             pre[r + 1] = acc;
         }
     }
@@ -434,12 +563,12 @@ __device__ inline void batch_prefix(const Batch<Args> &B, int64_t *pre)
 }
 
 // request holding global leaf g: largest r with pre[r] <= g
-__device__ inline int find_req(const int64_t *pre, int nreq, int64_t g)
+__device__ inline int find_req(const uint32_t *pre, int nreq, int64_t g)
 {
     int lo = 0, hi = nreq - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+        if ((int64_t)pre[mid] <= g) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -460,6 +589,7 @@ struct DensArgs {
     int32_t *nngb;
     int32_t *status;
     int64_t *counts;
+    const double *mrange;   // smallest and largest mass of the set
     double eta3;
     double h_rtol;
     double walk_margin;
@@ -470,24 +600,26 @@ template <int G, int PREC>
 __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_density(Batch<DensArgs> B)
 {
     constexpr int LPP = kWave / G;   // lanes per home particle
-    constexpr int NL = LPP;          // candidate leaves staged per group
-    constexpr int PER = G / LPP;     // staged entries per lane per staged leaf
+    constexpr int NL = kSlots / G;   // candidate leaves staged per group
+    constexpr int KP = kCacheEntriesPerParticle;
+    constexpr int ROWS = KP / LPP;   // cache rows of 64 entries
     __shared__ WalkBuf wb;
     __shared__ TreeInfo T;
-    __shared__ Stage<NL> S;
-    __shared__ uint8_t hits[G][kWave];   // up to NL * PER = G hits per lane per group
-    __shared__ int64_t pre[kMaxBatch + 1];
+    __shared__ Stage<G, PREC> S;
+    __shared__ uint32_t pre[kMaxBatch + 1];
     batch_prefix(B, pre);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
-    // Candidate cache of this block: for every lane up to K entries (r^2, m)
-    // of its share of the candidates within 2 Rc of its particle, in the
-    // order a sweep meets them; laid out [entry][lane] so each entry index is
-    // one coalesced 512-byte row.  The mass of the particle itself is stored
-    // negated so the cached pass can leave it out of the neighbour count.
-    constexpr int K = cache_entries_per_lane(G);
-    double *const cr2 = B.cache ? B.cache + (size_t)blockIdx.x * (2 * K * kWave) : nullptr;
-    double *const cm = cr2 ? cr2 + K * kWave : nullptr;
+    // Candidate lists of this block: for every home particle up to KP entries
+    // (r^2, and m unless all masses are equal) of the candidates within 2 Rc
+    // of it, in the order a sweep meets them.  Entry e of particle p sits in
+    // row e / LPP, column p LPP + e % LPP, and lane (p, q) owns the entries
+    // e = q (mod LPP) both when a sweep writes them and when later Newton
+    // steps read them back, summing them in the same order: a step from the
+    // list gives the bits of a sweep.  The particle itself is marked (mass or,
+    // with equal masses, r^2 = 0 stored negated) to keep it out of the count.
+    double *const cr2 = B.cache + (size_t)blockIdx.x * (2 * ROWS * kWave);
+    double *const cm = cr2 + ROWS * kWave;
     int64_t evals = 0, walks = 0, visits = 0, overflows = 0;
     int iter_max = 0;
     int cur = -1;
@@ -520,19 +652,28 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_density(Batch<Dens
         const int64_t i = first + p;
         const bool active = p < nhome;
         const int64_t ii = active ? i : first;
-        Home hm;
-        hm.x = A.x[ii];
-        hm.y = A.y[ii];
-        hm.z = A.z[ii];
-        hm.fx = hm.fy = hm.fz = 0.f;
-        if (PREC == SPH_FP32_PAIR) { hm.fx = A.fx[ii]; hm.fy = A.fy[ii]; hm.fz = A.fz[ii]; }
+        const double hx = A.x[ii], hy = A.y[ii], hz = A.z[ii];
+        float hfx = 0.f, hfy = 0.f, hfz = 0.f;
+        if (PREC == SPH_FP32_PAIR) { hfx = A.fx[ii]; hfy = A.fy[ii]; hfz = A.fz[ii]; }
         const double mi = A.m[ii];
+        const double mu = A.mrange[0];
+        const bool equal_m = mu == A.mrange[1];
         const Node home = A.nodes[leaf];
         double h = A.h[ii];
         double lo_b = 0.0, hi_b = INFINITY;
         bool conv = !active;
         double h_out = h, rho_out = 0.0, om_out = 1.0;
         int n_out = 0;
+        if (q == 0) {
+            S.hx[p] = hx;
+            S.hy[p] = hy;
+            S.hz[p] = hz;
+            S.hfx[p] = hfx;
+            S.hfy[p] = hfy;
+            S.hfz[p] = hfz;
+            S.mask[p][0] = 0;
+            S.mask[p][1] = 0;
+        }
 
         double hcov = A.walk_margin * wave_max(active ? h : 0.0);
         auto make_test = [&](double hc) {
@@ -544,117 +685,100 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_density(Batch<Dens
         walks++;
         if (wr.lev) overflows++;
         int iter = 0;
-        // cache state of this lane's particle: `cached` = its list holds every
-        // candidate within 2 Rc (no lane of the particle overflowed); valid
-        // while h <= Rc
+        // list state of this particle: `cached` = the list holds every
+        // candidate within 2 Rc (count <= KP); valid while h <= Rc
         bool cached = false;
-        bool build = false;
-        double Rc = 0.0, rc2 = -1.0;
-        int nc = 0;
+        double Rc = 0.0;
+        int count = 0;
         for (;;) {
             double s0 = 0.0, s2 = 0.0;
             int cnt = 0;
             const double hinv = 1.0 / h;
             const double h2x4 = (2.0 * h) * (2.0 * h);
             const float h2x4f = (float)h2x4;
-            // the pair terms of one hit, shared by the sweep and the cached pass
-            auto accumulate = [&](double r2, double mj) {
+            // pair terms of one list entry (r^2 and the mark of the particle itself)
+            auto accumulate = [&](double r2, double mw) {
+                const bool in = PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f;
+                if (!in) return;
+                const double mj = equal_m ? mu : fabs(mw);
+                const double ra2 = fabs(r2);
                 if (PREC == SPH_FP64) {
                     double f, df;
-                    const double qq = sqrt(r2) * hinv;
+                    const double qq = sqrt(ra2) * hinv;
                     m4(qq, f, df);
                     s0 += mj * f;
                     s2 += mj * (qq * df);
                 } else {
                     float f, df;
-                    const float qq = sqrtf((float)r2) * (float)hinv;
+                    const float qq = sqrtf((float)ra2) * (float)hinv;
                     m4(qq, f, df);
                     s0 += mj * (double)f;
                     s2 += mj * (double)(qq * df);
                 }
+                cnt += signbit(equal_m ? r2 : mw) ? 0 : 1;
             };
-            const bool sweep = cr2 == nullptr || __ballot(!conv && !cached) != 0ull;
-            if (sweep) {
-                // every particle still iterating (re)builds its list around its current h
-                build = cr2 != nullptr && !conv;
-                if (build) {
+            if (__ballot(!conv && !cached) != 0ull) {
+                // sweep: every particle still iterating takes its pair terms from
+                // the candidates directly and rebuilds its list around its
+                // current h (the first KP entries; a longer list is not kept)
+                double rc2 = -1.0;
+                if (!conv) {
                     Rc = fmin(kCacheGrow * h, hcov);
                     rc2 = (2.0 * Rc) * (2.0 * Rc) * (1.0 + 1e-6);
                 }
-                nc = 0;
-            }
-            auto group = [&](const uint32_t *leaves, int count) {
-                stage_group<G, NL, PREC>(S, leaves, count, A.lstart, A.nodes, home, bx, hcov, A.x, A.y,
-                                         A.z, A.m, A.fx, A.fy, A.fz);
-                // test: record hits as slot indices
-                int nh = 0;
-#pragma unroll
-                for (int k = 0; k < NL; k++) {
-                    const int jn = S.jn[k];
-#pragma unroll
-                    for (int t = 0; t < PER; t++) {
-                        const int slot = q + LPP * t;
-                        const int s = k * G + slot;
-                        if (slot < jn) {
-                            double dx, dy, dz, r2;
-                            separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
-                            // building a list: record everything inside 2 Rc (a
-                            // superset of the hits, since h <= Rc)
-                            const bool rec = build ? r2 < rc2
-                                                   : (PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f);
-                            if (rec) hits[nh++][lane] = (uint8_t)s;
-                        }
-                    }
-                }
-                // flush: append the recorded entries to the list (when
-                // building) and take the pair terms of the hits among them
-                const int nmax = wave_max_int(nh);
-                for (int e = 0; e < nmax; e++) {
-                    if (e < nh) {
-                        const int s = hits[e][lane];
-                        double dx, dy, dz, r2;
-                        separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
-                        const bool self = S.j[s] == (uint32_t)i;
-                        if (build) {
-                            if (nc < K) {
-                                cr2[nc * kWave + lane] = r2;
-                                cm[nc * kWave + lane] = self ? -S.w[s] : S.w[s];
-                            }
-                            nc++;
-                        }
-                        const bool in = PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f;
-                        if (in) {
-                            accumulate(r2, S.w[s]);
-                            cnt += self ? 0 : 1;
-                        }
-                    }
-                }
+                if (q == 0) S.thr[p] = rc2;
                 wave_lds_sync();
-            };
-            if (sweep) {
+                int base = 0;
+                auto group = [&](const uint32_t *leaves, int ng) {
+                    stage_group<G, PREC>(S, leaves, ng, A.lstart, A.nodes, home, bx, hcov, A.x, A.y,
+                                         A.z, A.m, A.fx, A.fy, A.fz);
+                    group_tests<G, PREC>(
+                        S, ng,
+                        [&](int pp, int k) {
+                            const double thr = S.thr[pp];
+                            return thr >= 0.0 && box_dist2(S, pp, k) <= thr * box_slack<PREC>();
+                        },
+                        [&](int pp, int sl) {
+                            double dx, dy, dz, r2;
+                            separation<G, PREC>(S, bx, S.hx[pp], S.hy[pp], S.hz[pp], S.hfx[pp],
+                                                S.hfy[pp], S.hfz[pp], sl, dx, dy, dz, r2);
+                            return r2 < S.thr[pp];
+                        });
+                    const uint64_t w0 = S.mask[p][0], w1 = S.mask[p][1];
+                    // list position base + e belongs to lane (base + e) % LPP
+                    const int e0 = (q - base % LPP + LPP) % LPP;
+                    const int n = for_my_bits<LPP>(w0, w1, e0, [&](int sl, int e) {
+                        const int pos = base + e;
+                        double dx, dy, dz, r2;
+                        separation<G, PREC>(S, bx, hx, hy, hz, hfx, hfy, hfz, sl, dx, dy, dz, r2);
+                        const bool self = S.j[sl] == (uint32_t)i;
+                        const double mw = self ? -S.w[sl] : S.w[sl];
+                        const double rw = self ? -r2 : r2;
+                        if (pos < KP) {
+                            const int at = (pos / LPP) * kWave + lane;
+                            cr2[at] = equal_m ? rw : r2;
+                            if (!equal_m) cm[at] = mw;
+                        }
+                        accumulate(equal_m ? rw : r2, mw);
+                    });
+                    base += n;
+                    if (q == 0) {
+                        S.mask[p][0] = 0;
+                        S.mask[p][1] = 0;
+                    }
+                    wave_lds_sync();
+                };
                 visits += for_each_leaf_group<NL>(T, A.nodes, wr, make_test(hcov), wb, group);
-                if (build) {
-                    int ovf = nc > K ? 1 : 0;
-#pragma unroll
-                    for (int o = 1; o < LPP; o <<= 1) ovf |= __shfl_xor(ovf, o);
-                    cached = ovf == 0;
-                } else {
-                    cached = false;
-                }
+                count = base;
+                cached = !conv && count <= KP;
             } else {
                 // every particle still iterating has a complete list and h <= Rc:
-                // the entries inside 2h, in list order, are exactly the hits a
-                // sweep would find, in the order it would find them
-                const int nmax = wave_max_int(conv ? 0 : nc);
-                for (int e = 0; e < nmax; e++) {
-                    if (!conv && e < nc) {
-                        const double r2 = cr2[e * kWave + lane];
-                        const bool in = PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f;
-                        if (in) {
-                            const double mw = cm[e * kWave + lane];
-                            accumulate(r2, fabs(mw));
-                            cnt += signbit(mw) ? 0 : 1;
-                        }
+                // the entries inside 2h, in list order, are the hits of a sweep
+                const int rows = wave_max_int(conv ? 0 : (count + LPP - 1) / LPP);
+                for (int rr = 0; rr < rows; rr++) {
+                    if (!conv && rr * LPP + q < count) {
+                        const double r2 = cr2[rr * kWave + lane];
+                        accumulate(r2, equal_m ? 0.0 : cm[rr * kWave + lane]);
                     }
                 }
             }
@@ -722,6 +846,7 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_density(Batch<Dens
             }
         }
         iter_max = iter > iter_max ? iter : iter_max;
+        wave_lds_sync();   // the home table is rewritten for the next leaf
     });
     flush_counts();
 }
@@ -749,13 +874,11 @@ template <int G, int PREC>
 __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<ForceArgs> B)
 {
     constexpr int LPP = kWave / G;
-    constexpr int NL = LPP;
-    constexpr int PER = G / LPP;
+    constexpr int NL = kSlots / G;
     __shared__ WalkBuf wb;
     __shared__ TreeInfo T;
-    __shared__ Stage<NL> S;
-    __shared__ uint8_t hits[G][kWave];
-    __shared__ int64_t pre[kMaxBatch + 1];
+    __shared__ Stage<G, PREC> S;
+    __shared__ uint32_t pre[kMaxBatch + 1];
     batch_prefix(B, pre);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
@@ -786,12 +909,9 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<Force
         const int64_t i = first + p;
         const bool active = p < nhome;
         const int64_t ii = active ? i : first;
-        Home hm;
-        hm.x = F.x[ii];
-        hm.y = F.y[ii];
-        hm.z = F.z[ii];
-        hm.fx = hm.fy = hm.fz = 0.f;
-        if (PREC == SPH_FP32_PAIR) { hm.fx = F.fx[ii]; hm.fy = F.fy[ii]; hm.fz = F.fz[ii]; }
+        const double hx = F.x[ii], hy = F.y[ii], hz = F.z[ii];
+        float hfx = 0.f, hfy = 0.f, hfz = 0.f;
+        if (PREC == SPH_FP32_PAIR) { hfx = F.fx[ii]; hfy = F.fy[ii]; hfz = F.fz[ii]; }
         const double vxi = F.vx[ii], vyi = F.vy[ii], vzi = F.vz[ii];
         const double hi = F.h[ii], hinvi = F.hinv[ii], rhoi = F.rho[ii], Ai = F.A[ii], ci = F.c[ii];
         const double hi2x4 = (2.0 * hi) * (2.0 * hi);
@@ -799,6 +919,17 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<Force
         const float hinvif = (float)hinvi;
         const float gfif = (float)kSigma * (hinvif * hinvif) * (hinvif * hinvif);
         const Node home = F.nodes[leaf];
+        if (q == 0) {
+            S.hx[p] = hx;
+            S.hy[p] = hy;
+            S.hz[p] = hz;
+            S.hfx[p] = hfx;
+            S.hfy[p] = hfy;
+            S.hfz[p] = hfz;
+            S.thr[p] = active ? hi2x4 : -1.0;
+            S.mask[p][0] = 0;
+            S.mask[p][1] = 0;
+        }
         // symmetric criterion: a node can hold force neighbours of the home leaf
         // if its box is closer than 2 max(h over home, h over node)
         auto test = [&bx, &home](const Node &nd) {
@@ -810,51 +941,48 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<Force
 
         double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
         int cnt = 0;
-        auto group = [&](const uint32_t *leaves, int count) {
-            stage_group<G, NL, PREC>(S, leaves, count, F.lstart, F.nodes, home, bx, -1.0, F.x, F.y,
-                                     F.z, F.h, F.fx, F.fy, F.fz);
-            int nh = 0;
-#pragma unroll
-            for (int k = 0; k < NL; k++) {
-                const int jn = S.jn[k];
-#pragma unroll
-                for (int t = 0; t < PER; t++) {
-                    const int slot = q + LPP * t;
-                    const int s = k * G + slot;
-                    if (slot < jn) {
-                        double dx, dy, dz, r2;
-                        separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
-                        const double hj = S.w[s];
-                        const double hj2x4 = (2.0 * hj) * (2.0 * hj);
-                        bool in;
-                        if (PREC == SPH_FP64) in = r2 < hi2x4 || r2 < hj2x4;
-                        else in = (float)r2 < (float)hi2x4 || (float)r2 < (float)hj2x4;
-                        if (in && S.j[s] != (uint32_t)i) hits[nh++][lane] = (uint8_t)s;
-                    }
-                }
-            }
-            const int nmax = wave_max_int(nh);
-            for (int e = 0; e < nmax; e++) {
-                if (e >= nh) continue;
-                const int s = hits[e][lane];
-                const int64_t j = S.j[s];
+        auto group = [&](const uint32_t *leaves, int ng) {
+            stage_group<G, PREC>(S, leaves, ng, F.lstart, F.nodes, home, bx, -1.0, F.x, F.y, F.z, F.h,
+                                 F.fx, F.fy, F.fz);
+            group_tests<G, PREC>(
+                S, ng,
+                [&](int pp, int k) {
+                    const double thr = S.thr[pp];
+                    const double hk = 2.0 * S.hmax[k];
+                    return thr >= 0.0 && box_dist2(S, pp, k) <= fmax(thr, hk * hk) * box_slack<PREC>();
+                },
+                [&](int pp, int sl) {
+                    double dx, dy, dz, r2;
+                    separation<G, PREC>(S, bx, S.hx[pp], S.hy[pp], S.hz[pp], S.hfx[pp], S.hfy[pp],
+                                        S.hfz[pp], sl, dx, dy, dz, r2);
+                    const double thr = S.thr[pp];
+                    const double hj = S.w[sl];
+                    const double hj2x4 = (2.0 * hj) * (2.0 * hj);
+                    bool in;
+                    if (PREC == SPH_FP64) in = r2 < thr || r2 < hj2x4;
+                    else in = (float)r2 < (float)thr || (float)r2 < (float)hj2x4;
+                    return in && S.j[sl] != (uint32_t)(first + pp);
+                });
+            const uint64_t w0 = S.mask[p][0], w1 = S.mask[p][1];
+            // the particle's hits of this group (same count on all its lanes)
+            cnt += for_my_bits<LPP>(w0, w1, q, [&](int sl, int) {
+                const int64_t j = S.j[sl];
                 double dx, dy, dz, r2;
-                separation<G, NL, PREC>(S, bx, hm, s, dx, dy, dz, r2);
-                cnt++;
+                separation<G, PREC>(S, bx, hx, hy, hz, hfx, hfy, hfz, sl, dx, dy, dz, r2);
                 const double cj = F.c[j];
                 if (r2 == 0.0) {
                     vs_max = fmax(vs_max, PREC == SPH_FP64 ? ci + cj : (double)((float)ci + (float)cj));
-                    continue;
+                    return;
                 }
                 if (PREC == SPH_FP64) {
-                    const double r = sqrt(r2);
-                    const double rinv = 1.0 / r;
+                    const double rr = sqrt(r2);
+                    const double rinv = 1.0 / rr;
                     const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
                     const double hinvj = F.hinv[j];
                     const double gfj = kSigma * (hinvj * hinvj) * (hinvj * hinvj);
                     double fi, dfi, fj, dfj;
-                    m4(r * hinvi, fi, dfi);
-                    m4(r * hinvj, fj, dfj);
+                    m4(rr * hinvi, fi, dfi);
+                    m4(rr * hinvj, fj, dfj);
                     double gi, gj, gsum;
                     sym_grads(gfi, dfi, gfj, dfj, gi, gj, gsum);
                     const double w = ((vxi - F.vx[j]) * ex + (vyi - F.vy[j]) * ey) + (vzi - F.vz[j]) * ez;
@@ -874,8 +1002,8 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<Force
                     dui += cdu;
                 } else {
                     const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
-                    const float r = sqrtf((float)r2);
-                    const float rinv = 1.0f / r;
+                    const float rr = sqrtf((float)r2);
+                    const float rinv = 1.0f / rr;
                     const float ex = fdx * rinv, ey = fdy * rinv, ez = fdz * rinv;
                     const float hinvj = (float)F.hinv[j];
                     // own and other kernel factors formed by the same float
@@ -883,8 +1011,8 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<Force
                     // the (i, j) pair
                     const float gfjf = (float)kSigma * (hinvj * hinvj) * (hinvj * hinvj);
                     float fi, dfi, fj, dfj;
-                    m4(r * hinvif, fi, dfi);
-                    m4(r * hinvj, fj, dfj);
+                    m4(rr * hinvif, fi, dfi);
+                    m4(rr * hinvj, fj, dfj);
                     float gi, gj, gsum;
                     sym_grads(gfif, dfi, gfjf, dfj, gi, gj, gsum);
                     const float w = ((float)(vxi - F.vx[j]) * ex + (float)(vyi - F.vy[j]) * ey) +
@@ -906,6 +1034,10 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<Force
                     azi += (double)(cvec * ez);
                     dui += (double)cdu;
                 }
+            });
+            if (q == 0) {
+                S.mask[p][0] = 0;
+                S.mask[p][1] = 0;
             }
             wave_lds_sync();
         };
@@ -917,7 +1049,6 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<Force
             azi += __shfl_xor(azi, o);
             dui += __shfl_xor(dui, o);
             vs_max = fmax(vs_max, __shfl_xor(vs_max, o));
-            cnt += __shfl_xor(cnt, o);
         }
         if (active && q == 0) {
             const double vsig = cnt > 0 ? vs_max : 2.0 * ci;
@@ -935,6 +1066,7 @@ __global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<Force
             }
         }
         pairs_total += (q == 0 && active) ? cnt : 0;
+        wave_lds_sync();   // the home table is rewritten for the next leaf
     });
     flush_counts();
 }
@@ -1139,6 +1271,7 @@ sph_status density_prepare(sph_ctx *c, int64_t n)
     a.h = c->s.h; a.rho = c->s.rho; a.omega = c->s.omega; a.nngb = c->s.nngb;
     a.status = c->d_status;
     a.counts = c->d_counts;
+    a.mrange = c->d_scal + 8;
     a.eta3 = c->p.eta * c->p.eta * c->p.eta;
     // FP32-pair mode: the density sum carries single-precision pair terms
     // (relative noise ~1e-7), so the Newton step cannot settle below a few
@@ -1153,6 +1286,7 @@ sph_status density_prepare(sph_ctx *c, int64_t n)
     if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
         return fail(c, SPH_EINVAL, "density: offsets not allocated");
     if (c->tree_n != n || n <= 0) return fail(c, SPH_ESTATE, "density: tree not built");
+    TRY_(reduce_mass_range(c, n));
     hipLaunchKernelGGL(k_store_args<DensArgs>, dim3(1), dim3(64), 0, c->stream, a,
                        (DensArgs *)c->d_dargs);
     return hip_check(c, hipGetLastError(), "density arguments");
@@ -1201,19 +1335,20 @@ sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax)
         B.req[r] = (const DensArgs *)cs[r]->d_dargs;
         leaves_bound += cs[r]->n;
     }
+    if (leaves_bound > (int64_t)0xFFFFFFFFll)
+        return fail(c, SPH_EINVAL, "a batch holds more than 2^32 - 1 particles");
     (void)nmax;
     unsigned grid = pair_grid(leaves_bound);
-    // the candidate cache of the set whose cache serves the most blocks at this
-    // leaf size; the grid never exceeds it (without one the loop sweeps)
+    // the candidate lists of the set whose scratch serves the most blocks at
+    // this leaf size; the grid never exceeds it
     const sph_ctx *owner = nullptr;
     for (int r = 0; r < count; r++)
         if (cs[r]->cache && cs[r]->cache_leaf == c->p.leaf_size &&
             (!owner || cs[r]->cache_blocks > owner->cache_blocks))
             owner = cs[r];
-    if (owner) {
-        B.cache = owner->cache;
-        if ((int64_t)grid > owner->cache_blocks) grid = (unsigned)owner->cache_blocks;
-    }
+    if (!owner) return fail(c, SPH_ESTATE, "density: no candidate-list scratch for this leaf size");
+    B.cache = owner->cache;
+    if ((int64_t)grid > owner->cache_blocks) grid = (unsigned)owner->cache_blocks;
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_begin(c, 0, &e0, &e1);
@@ -1249,6 +1384,8 @@ sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax)
         B.req[r] = (const ForceArgs *)cs[r]->d_fargs;
         leaves_bound += cs[r]->n;
     }
+    if (leaves_bound > (int64_t)0xFFFFFFFFll)
+        return fail(c, SPH_EINVAL, "a batch holds more than 2^32 - 1 particles");
     (void)nmax;
     const unsigned grid = pair_grid(leaves_bound);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;

@@ -36,14 +36,15 @@ inline unsigned pair_grid(int64_t n)
     return (unsigned)blocks;
 }
 
-// Density-loop candidate cache: 128 entries per particle (2 G per lane), each
-// an FP64 r^2 and an FP64 mass; built around Rc = kCacheGrow h (capped by the
-// walk radius) so that Newton steps within that bound reuse it.
+// Density-loop candidate lists: up to 160 entries per home particle, each an
+// FP64 r^2 and an FP64 mass, for the candidates within 2 Rc, Rc = kCacheGrow h
+// (capped by the walk radius), so that Newton steps within that bound reuse
+// them.  A block holds the lists of one leaf's G particles.
 constexpr double kCacheGrow = 1.15;
-__host__ __device__ constexpr int cache_entries_per_lane(int G) { return 2 * G; }
+constexpr int kCacheEntriesPerParticle = 160;
 inline int64_t cache_bytes(int G, int64_t blocks)
 {
-    return blocks * 2 * cache_entries_per_lane(G) * kWave * (int64_t)sizeof(double);
+    return blocks * 2 * (int64_t)kCacheEntriesPerParticle * G * (int64_t)sizeof(double);
 }
 
 // Tree node: bounding box of the particles below it and their largest h.
@@ -159,6 +160,7 @@ struct sph_ctx {
     // resident state
     bool resident = false;
     double *d_scal = nullptr;   // [0] dt_next [1] dt_last [2] time [3] KE [4] TE [5..7] P
+                                // [8] smallest, [9] largest mass of the last density pass
     // [0] sum nngb [1] sum nforce (last evaluation), [2] density pair
     // evaluations summed over Newton-Raphson iterations, [3] force pair
     // evaluations, [4] max Newton-Raphson iterations, [5] walk overflows,
@@ -236,6 +238,8 @@ sph_status eos_scatter(sph_ctx *c, int64_t n, const uint32_t *index, const doubl
 sph_status kick_drift(sph_ctx *c, int64_t n, double dt_host);
 sph_status closing_kick(sph_ctx *c, int64_t n, double dt_host);
 sph_status reduce_dt(sph_ctx *c, int64_t n);
+// smallest and largest sorted mass -> d_scal[8], d_scal[9]
+sph_status reduce_mass_range(sph_ctx *c, int64_t n);
 sph_status reduce_diag(sph_ctx *c, int64_t n);
 // zero d_counts[first..first+count) with a kernel (capture-safe, no memset)
 sph_status zero_counts(sph_ctx *c, int first, int count);

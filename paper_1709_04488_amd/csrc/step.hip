@@ -130,6 +130,59 @@ __global__ __launch_bounds__(kRedThreads) void k_min_final(int nb, const double 
     if (threadIdx.x == 0) out[0] = sh[0];
 }
 
+// smallest and largest mass -> out[0], out[1] (equal masses let the density
+// loop keep only r^2 in its candidate lists)
+__global__ __launch_bounds__(kRedThreads) void k_mrange_partial(int64_t n, const double *__restrict__ m,
+                                                                double *__restrict__ part)
+{
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        lo = fmin(lo, m[k]);
+        hi = fmax(hi, m[k]);
+    }
+    __shared__ double sl[kRedThreads], sh[kRedThreads];
+    sl[threadIdx.x] = lo;
+    sh[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sl[threadIdx.x] = fmin(sl[threadIdx.x], sl[threadIdx.x + s]);
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sl[0];
+        part[2 * blockIdx.x + 1] = sh[0];
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_mrange_final(int nb, const double *__restrict__ part,
+                                                              double *__restrict__ out)
+{
+    __shared__ double sl[kRedThreads], sh[kRedThreads];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) {
+        lo = fmin(lo, part[2 * b]);
+        hi = fmax(hi, part[2 * b + 1]);
+    }
+    sl[threadIdx.x] = lo;
+    sh[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sl[threadIdx.x] = fmin(sl[threadIdx.x], sl[threadIdx.x + s]);
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sl[0];
+        out[1] = sh[0];
+    }
+}
+
 // Sums in a fixed order (grid-stride per thread, fixed tree per block, fixed
 // order over blocks), so they are reproducible bit for bit.
 //   [0] 1/2 m v^2  [1] m u  [2..4] m v  [5] sum nngb  [6] sum nforce
@@ -253,6 +306,17 @@ sph_status closing_kick(sph_ctx *c, int64_t n, double dt_host)
     KdkArgs K = kdk_args(c, n, dt_host);
     hipLaunchKernelGGL(k_closing_kick, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, K);
     return hip_check(c, hipGetLastError(), "closing_kick");
+}
+
+sph_status reduce_mass_range(sph_ctx *c, int64_t n)
+{
+    if (n == 0) return SPH_OK;
+    const int nb = (int)std::min<int64_t>(kRedBlocks / 2, (n + kRedThreads - 1) / kRedThreads);
+    hipLaunchKernelGGL(k_mrange_partial, dim3(nb), dim3(kRedThreads), 0, c->stream, n, c->s.m,
+                       c->d_part);
+    hipLaunchKernelGGL(k_mrange_final, dim3(1), dim3(kRedThreads), 0, c->stream, nb, c->d_part,
+                       c->d_scal + 8);
+    return hip_check(c, hipGetLastError(), "reduce_mass_range");
 }
 
 sph_status reduce_dt(sph_ctx *c, int64_t n)
