@@ -192,7 +192,7 @@ sph_status ensure_capacity(sph_ctx *c, int64_t n)
     if (s != SPH_OK) { free_all(c); return s; }
     int64_t ncap_nodes = node_count_bound(cap);
     hipError_t e1 = hipMalloc((void **)&c->nodes, sizeof(Node) * (size_t)ncap_nodes);
-    int64_t hcap = 256 * ceil_div(cap, kRsTile);
+    int64_t hcap = 256 * ceil_div(cap, kRsTile) + 256;   // tile counts per digit + digit totals
     hipError_t e2 = hipMalloc((void **)&c->hist, sizeof(uint32_t) * (size_t)hcap);
     if (e1 != hipSuccess || e2 != hipSuccess) {
         (void)hipGetLastError();

@@ -67,14 +67,19 @@ __global__ __launch_bounds__(kBoxThreads) void k_box_partial(int64_t n, const do
 __global__ __launch_bounds__(64) void k_box_final(int nb, const double *__restrict__ part,
                                                   double *__restrict__ box)
 {
-    if (threadIdx.x != 0) return;
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nb; b++)
+    for (int b = threadIdx.x; b < nb; b += 64)
         for (int a = 0; a < 3; a++) {
             mn[a] = fmin(mn[a], part[b * 6 + a]);
             mx[a] = fmax(mx[a], part[b * 6 + 3 + a]);
         }
-    for (int a = 0; a < 3; a++) { box[a] = mn[a]; box[3 + a] = mx[a]; }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int a = 0; a < 3; a++) {
+            mn[a] = fmin(mn[a], __shfl_xor(mn[a], o));
+            mx[a] = fmax(mx[a], __shfl_xor(mx[a], o));
+        }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; a++) { box[a] = mn[a]; box[3 + a] = mx[a]; }
 }
 
 __device__ inline uint64_t spread3(uint64_t v)
@@ -115,6 +120,22 @@ __global__ __launch_bounds__(256) void k_keys(int64_t n, const double *__restric
 
 // ---- LSD radix sort, 8-bit digits ------------------------------------------
 
+// inclusive block-wide sum scan, 256 threads, one value each; sh[255] holds
+// the total on return
+__device__ inline uint32_t block_scan_256(uint32_t v, uint32_t *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const uint32_t o = t >= d ? sh[t - d] : 0u;
+        __syncthreads();
+        sh[t] += o;
+        __syncthreads();
+    }
+    return sh[t];
+}
+
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(int64_t n, const uint64_t *__restrict__ keys,
                                                         int shift, uint32_t *__restrict__ hist,
                                                         int64_t ntiles)
@@ -131,29 +152,25 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(int64_t n, const uint64_
     hist[threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of `total` counts in place by one block.
-__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t *__restrict__ a, int64_t total)
+// Per digit (one block each): exclusive scan over the tiles of that digit's
+// counts, in place, 256 tiles at a time; the digit's total goes to totals[d].
+// The digits' own offsets (a scan of the 256 totals) are formed by every
+// scatter block.
+__global__ __launch_bounds__(256) void k_rs_digit_scan(uint32_t *__restrict__ hist, int64_t ntiles,
+                                                       uint32_t *__restrict__ totals)
 {
-    __shared__ uint32_t sums[1024];
-    int t = threadIdx.x;
-    int64_t chunk = (total + 1023) / 1024;
-    int64_t s0 = t * chunk, s1 = s0 + chunk < total ? s0 + chunk : total;
-    uint32_t s = 0;
-    for (int64_t k = s0; k < s1; k++) s += a[k];
-    sums[t] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        uint32_t v = t >= d ? sums[t - d] : 0u;
-        __syncthreads();
-        sums[t] += v;
+    __shared__ uint32_t sh[256];
+    uint32_t *a = hist + (int64_t)blockIdx.x * ntiles;
+    uint32_t run = 0;
+    for (int64_t b0 = 0; b0 < ntiles; b0 += 256) {
+        const int64_t k = b0 + threadIdx.x;
+        const uint32_t v = k < ntiles ? a[k] : 0u;
+        const uint32_t incl = block_scan_256(v, sh);
+        if (k < ntiles) a[k] = run + incl - v;
+        run += sh[255];
         __syncthreads();
     }
-    uint32_t run = sums[t] - s;
-    for (int64_t k = s0; k < s1; k++) {
-        uint32_t v = a[k];
-        a[k] = run;
-        run += v;
-    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = run;
 }
 
 // Stable scatter.  Wave w of the block owns keys [tile + w*1024, +1024) and
@@ -165,13 +182,23 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
                                                            uint64_t *__restrict__ kout,
                                                            uint32_t *__restrict__ vout, int shift,
                                                            const uint32_t *__restrict__ offs,
-                                                           int64_t ntiles)
+                                                           int64_t ntiles,
+                                                           const uint32_t *__restrict__ totals)
 {
     __shared__ uint32_t wcnt[kRsThreads / kWave][256];
+    __shared__ uint32_t dbase[256];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     for (int k = threadIdx.x; k < (kRsThreads / kWave) * 256; k += kRsThreads)
         (&wcnt[0][0])[k] = 0;
+    // first position of each digit: exclusive scan of the digit totals
+    static_assert(kRsThreads == 256, "one thread per digit");
+    {
+        const uint32_t v = totals[threadIdx.x];
+        const uint32_t incl = block_scan_256(v, dbase);
+        __syncthreads();
+        dbase[threadIdx.x] = incl - v;
+    }
     __syncthreads();
     const uint64_t lt = __lanemask_lt();
     const int64_t base = blockIdx.x * (int64_t)kRsTile + w * (kRsItems * kWave);
@@ -211,7 +238,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
         int64_t k = base + r * kWave + lane;
         if (k < n) {
             uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
-            uint32_t pos = offs[d * ntiles + blockIdx.x] + wcnt[w][d] + rank[r];
+            uint32_t pos = dbase[d] + offs[d * ntiles + blockIdx.x] + wcnt[w][d] + rank[r];
             kout[pos] = key[r];
             vout[pos] = val[r];
         }
@@ -594,10 +621,11 @@ sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y, 
         int shift = 8 * ps;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(kRsThreads), 0, c->stream, n,
                            c->keys[cur], shift, c->hist, ntiles);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, c->stream, c->hist, 256 * ntiles);
+        hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(256), 0, c->stream, c->hist, ntiles,
+                           c->hist + 256 * ntiles);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(kRsThreads), 0, c->stream, n,
                            c->keys[cur], c->vals[cur], c->keys[cur ^ 1], c->vals[cur ^ 1], shift,
-                           c->hist, ntiles);
+                           c->hist, ntiles, c->hist + 256 * ntiles);
         cur ^= 1;
     }
     c->perm = c->vals[cur];

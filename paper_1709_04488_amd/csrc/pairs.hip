@@ -534,10 +534,11 @@ __device__ inline int for_my_bits(uint64_t w0, uint64_t w1, int e0, Fn fn)
 // work done for a leaf depends on its own request only, so a set gives the
 // same bits alone and inside any mix.
 // ---------------------------------------------------------------------------
-// Pair kernels are built for 3 waves per SIMD (<= 168 VGPRs): measured on
-// MI355X faster than the compiler's own choice of 2 (~230 VGPRs) and than 4,
-// where the force loop spills heavily.
-constexpr int kPairWavesPerSimd = 3;
+// Waves per SIMD the pair kernels are built for.  Measured on MI355X: the
+// FP64 loops run fastest at 3 (<= 168 VGPRs), the FP32-pair loops at 2 (the
+// compiler's own register budget); at 4 the FP64 force loop spills heavily.
+template <int PREC>
+constexpr int pair_waves_per_simd() { return PREC == SPH_FP64 ? 3 : 2; }
 
 template <class Args>
 struct Batch {
@@ -597,7 +598,7 @@ struct DensArgs {
 };
 
 template <int G, int PREC>
-__global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_density(Batch<DensArgs> B)
+__global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(Batch<DensArgs> B)
 {
     constexpr int LPP = kWave / G;   // lanes per home particle
     constexpr int NL = kSlots / G;   // candidate leaves staged per group
@@ -871,7 +872,7 @@ struct ForceArgs {
 };
 
 template <int G, int PREC>
-__global__ __launch_bounds__(kWave, kPairWavesPerSimd) void k_forces(Batch<ForceArgs> B)
+__global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(Batch<ForceArgs> B)
 {
     constexpr int LPP = kWave / G;
     constexpr int NL = kSlots / G;

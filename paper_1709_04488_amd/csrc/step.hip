@@ -218,15 +218,26 @@ __global__ __launch_bounds__(kRedThreads) void k_diag_partial(int64_t n, const d
     if (threadIdx.x < kRedVals) part[blockIdx.x * kRedVals + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(64) void k_diag_final(int nb, const double *__restrict__ part,
-                                                   double *__restrict__ scal,
-                                                   int64_t *__restrict__ counts)
+// fixed order: thread t sums the partials b = t (mod 256) in order, then a
+// fixed tree over the 256 threads
+__global__ __launch_bounds__(kRedThreads) void k_diag_final(int nb, const double *__restrict__ part,
+                                                            double *__restrict__ scal,
+                                                            int64_t *__restrict__ counts)
 {
-    if (threadIdx.x >= kRedVals) return;
-    double s = 0.0;
-    for (int b = 0; b < nb; b++) s += part[b * kRedVals + threadIdx.x];
-    if (threadIdx.x < 5) scal[3 + threadIdx.x] = s;
-    else if (threadIdx.x < 7) counts[threadIdx.x - 5] = (int64_t)s;
+    __shared__ double sh[kRedVals][kRedThreads];
+    double acc[kRedVals];
+    for (int v = 0; v < kRedVals; v++) acc[v] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kRedThreads)
+        for (int v = 0; v < kRedVals; v++) acc[v] += part[b * kRedVals + v];
+    for (int v = 0; v < kRedVals; v++) sh[v][threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int st = kRedThreads / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int v = 0; v < kRedVals; v++) sh[v][threadIdx.x] += sh[v][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) scal[3 + threadIdx.x] = sh[threadIdx.x][0];
+    else if (threadIdx.x < 7) counts[threadIdx.x - 5] = (int64_t)sh[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(1024) void k_scan_offsets(int64_t n, int64_t *__restrict__ a)
@@ -359,8 +370,8 @@ sph_status reduce_diag(sph_ctx *c, int64_t n)
     int nb = (int)std::min<int64_t>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
     hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(kRedThreads), 0, c->stream, n, c->s.m,
                        c->s.vx, c->s.vy, c->s.vz, c->s.u, c->s.nngb, c->s.nforce, c->d_part);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, c->stream, nb, c->d_part, c->d_scal,
-                       c->d_counts);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kRedThreads), 0, c->stream, nb, c->d_part,
+                       c->d_scal, c->d_counts);
     return hip_check(c, hipGetLastError(), "reduce_diag");
 }
 
