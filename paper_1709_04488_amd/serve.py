@@ -134,6 +134,23 @@ class Scheduler:
                     best = (key, s, extra)
         return None if best is None else (best[1], best[2])
 
+    def _release_idle(self, req: Request):
+        """Free the capacity of idle slots, largest first, until req fits.
+        Slot capacities only grow while slots are reused, so without this an
+        idle server whose slots hold most of the budget could never admit the
+        next request."""
+        idle = sorted((s for s in range(self.max_slots)
+                       if not self.slot_busy[s] and self.slot_cap[s] > 0),
+                      key=lambda s: -self.slot_cap[s])
+        for s in idle:
+            self.ex.release(s)
+            self.slot_cap[s] = 0
+            self.events.append((self.clock.now(), "release", s))
+            fit = self._fit(req)
+            if fit is not None:
+                return fit
+        return None
+
     def _never_fits(self, req: Request) -> bool:
         return self.ex.slot_bytes(req.n) + self.ex.array_bytes(req) > self.budget
 
@@ -157,7 +174,7 @@ class Scheduler:
                     recs[req.rid].error = "exceeds HBM budget"
                     recs[req.rid].done = now
                     continue
-                fit = self._fit(req)
+                fit = self._fit(req) or self._release_idle(req)
                 if fit is None:
                     break
                 slot, _ = fit
@@ -225,6 +242,7 @@ class FakeExecutor:
         self.fixed = fixed
         self.starts = []
         self.active = {}
+        self.released = []
 
     def slot_bytes(self, cap: int) -> int:
         return 0 if cap == 0 else self.fixed + self.bpp * cap
@@ -248,6 +266,9 @@ class FakeExecutor:
     def finish(self, h):
         self.active.pop(h["req"].rid, None)
         return {"interactions": 100 * h["req"].n}
+
+    def release(self, slot: int):
+        self.released.append(slot)
 
     def wait(self, clock, next_arrival: float):
         # advance to the next event: an arrival or the earliest completion
@@ -381,6 +402,12 @@ class GpuExecutor:
                 out["outputs"] = q.host("x", "y", "z", "vx", "vy", "vz", "u", "h")
         h["p"] = None
         return out
+
+    def release(self, slot: int):
+        sl = self.slots[slot]
+        if sl.ctx is not None:
+            sl.ctx.close()
+            sl.ctx = None
 
     def wait(self, clock, next_arrival: float):
         time.sleep(0.0002)

@@ -81,3 +81,18 @@ def test_summary_percentiles():
     assert s["latency_p50_ms"] == pytest.approx(np.percentile(lat, 50) * 1e3)
     assert s["latency_p99_ms"] == pytest.approx(np.percentile(lat, 99) * 1e3)
     assert s["completed"] == 100
+
+
+@pytest.mark.timeout(30)
+def test_idle_slot_capacity_is_released_when_it_blocks_admission():
+    # two large requests leave both slots holding capacity; the next, larger
+    # request fits the budget only once that idle capacity is released
+    per = lambda n: (1 << 20) + 500 * n + 168 * n  # noqa: E731
+    budget = int(1.4e9)
+    reqs = [_req(0, 1_000_000, 0.0), _req(1, 1_000_000, 0.0), _req(2, 1_500_000, 5.0)]
+    assert 2 * per(1_000_000) <= budget < per(1_500_000) + 2 * (1 << 20) + 500 * 1_000_000 * 2
+    recs, ex, sched = _run(reqs, budget, 2, lambda r: 1.0)
+    assert all(not r.error for r in recs)
+    assert recs[2].admitted == pytest.approx(5.0)
+    assert ex.released, "idle capacity was never released"
+    assert sched.peak_bytes <= budget
