@@ -83,8 +83,7 @@ void free_all(sph_ctx *c)
     c->nodes = nullptr;
     c->hist = nullptr;
     c->cache = nullptr;
-    c->cache_blocks = 0;
-    c->cache_leaf = 0;
+    c->cache_size = 0;
     c->ncap = 0;
     c->node_cap = 0;
     c->hist_cap = 0;
@@ -120,40 +119,38 @@ sph_status alloc(sph_ctx *c, T **ptr, int64_t count)
 
 } // namespace
 
-// The density loop's candidate cache, sized for the pair grid of the current
-// capacity at the current leaf size.
+// The density loop's candidate-list scratch: enough bytes for the pair grid
+// of the current capacity at the current leaf size.  It only grows, so a
+// context that alternates between leaf sizes (the autotuner may change it per
+// request) does not reallocate.
 static sph_status ensure_cache(sph_ctx *c)
 {
-    const int G = c->p.leaf_size;
-    const int64_t blocks = pair_grid(c->ncap);
-    if (c->cache && c->cache_leaf == G && c->cache_blocks >= blocks) return SPH_OK;
+    const int64_t bytes = cache_bytes(c->p.leaf_size, pair_grid(c->ncap));
+    if (c->cache && c->cache_size >= bytes) return SPH_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
     if (c->cache) {
-        // a captured graph refers to the cache about to be freed
+        // a captured graph refers to the scratch about to be freed
         if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
         c->graph_exec = nullptr;
         c->graph = nullptr;
         (void)hipFree(c->cache);
-        c->bytes -= (size_t)cache_bytes(c->cache_leaf, c->cache_blocks);
+        c->bytes -= (size_t)c->cache_size;
         c->cache = nullptr;
-        c->cache_blocks = 0;
-        c->cache_leaf = 0;
+        c->cache_size = 0;
     }
-    const int64_t bytes = cache_bytes(G, blocks);
     if (c->budget && c->bytes + (size_t)bytes > c->budget)
-        return fail(c, SPH_EBUDGET, "candidate cache of " + std::to_string(bytes) +
+        return fail(c, SPH_EBUDGET, "candidate-list scratch of " + std::to_string(bytes) +
                                         " bytes exceeds the HBM budget");
     e = hipMalloc((void **)&c->cache, (size_t)bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         c->cache = nullptr;
-        return fail(c, SPH_ENOMEM, "hipMalloc failed (candidate cache)");
+        return fail(c, SPH_ENOMEM, "hipMalloc failed (candidate lists)");
     }
     c->bytes += (size_t)bytes;
-    c->cache_blocks = blocks;
-    c->cache_leaf = G;
+    c->cache_size = bytes;
     return SPH_OK;
 }
 

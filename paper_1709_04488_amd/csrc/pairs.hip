@@ -1344,12 +1344,11 @@ sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax)
     // this leaf size; the grid never exceeds it
     const sph_ctx *owner = nullptr;
     for (int r = 0; r < count; r++)
-        if (cs[r]->cache && cs[r]->cache_leaf == c->p.leaf_size &&
-            (!owner || cs[r]->cache_blocks > owner->cache_blocks))
-            owner = cs[r];
-    if (!owner) return fail(c, SPH_ESTATE, "density: no candidate-list scratch for this leaf size");
+        if (cs[r]->cache && (!owner || cs[r]->cache_size > owner->cache_size)) owner = cs[r];
+    const int64_t blocks = owner ? owner->cache_size / cache_bytes(c->p.leaf_size, 1) : 0;
+    if (blocks < kXcds) return fail(c, SPH_ESTATE, "density: no candidate-list scratch");
     B.cache = owner->cache;
-    if ((int64_t)grid > owner->cache_blocks) grid = (unsigned)owner->cache_blocks;
+    if ((int64_t)grid > blocks) grid = (unsigned)(blocks / kXcds * kXcds);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_begin(c, 0, &e0, &e1);

@@ -24,10 +24,11 @@ constexpr int kMaxBatch = 128;   // particle sets per batched pair-kernel launch
 constexpr int kArgBytes = 1024;  // device argument block of one pair-kernel launch
 
 // Persistent pair-kernel grid: one wave per block, at most as many blocks as
-// the GPU holds at once (256 CUs x 16 waves at the pair kernels' register and
-// LDS use), at least one block per 8 particles below that, a multiple of the
-// XCD count.
-constexpr int64_t kMaxPairBlocks = 256 * 16;
+// the GPU holds at once (256 CUs x 12 waves: the pair kernels run at 3 waves
+// per SIMD or fewer), at least one block per 8 particles below that, a
+// multiple of the XCD count.  Each block owns a slice of the density loop's
+// candidate-list scratch, so the cap also bounds that scratch.
+constexpr int64_t kMaxPairBlocks = 256 * 12;
 inline unsigned pair_grid(int64_t n)
 {
     int64_t blocks = (n + 7) / 8;
@@ -139,9 +140,8 @@ struct sph_ctx {
     uint32_t *lstart = nullptr;         // leaf -> first sorted particle, [L+1]
     uint32_t *leaf_id = nullptr;        // sorted particle -> leaf
     uint32_t *d_work = nullptr;         // per-XCD claim counters of the pair kernels
-    double *cache = nullptr;            // density-loop candidate cache, per pair-kernel block
-    int64_t cache_blocks = 0;           // blocks the cache serves ...
-    int32_t cache_leaf = 0;             // ... at this leaf size
+    double *cache = nullptr;            // density-loop candidate lists, a slice per pair-kernel block
+    int64_t cache_size = 0;             // its bytes (cache_bytes(G, 1) per block at leaf size G)
     void *d_dargs = nullptr;            // device argument block of the density loop
     void *d_fargs = nullptr;            // device argument block of the force loop
     uint64_t *skeys = nullptr;          // sorted keys of the last build

@@ -108,6 +108,7 @@ class Scheduler:
         self.max_slots = int(max_slots)
         self.clock = clock or WallClock()
         self.slot_cap = [0] * self.max_slots      # particles each slot's context can hold
+        self.slot_leaf = [0] * self.max_slots     # largest leaf size its context has run
         self.slot_busy = [False] * self.max_slots
         self.array_bytes = {}                     # running rid -> bytes of its particle arrays
         self.peak_bytes = 0
@@ -115,7 +116,8 @@ class Scheduler:
 
     # memory currently held: slot capacities + arrays of running requests
     def used_bytes(self) -> int:
-        return sum(self.ex.slot_bytes(c) for c in self.slot_cap) + sum(self.array_bytes.values())
+        return (sum(self.ex.slot_bytes(c, g) for c, g in zip(self.slot_cap, self.slot_leaf)) +
+                sum(self.array_bytes.values()))
 
     def _fit(self, req: Request):
         """Free slot for req and the extra bytes admitting it costs, or None."""
@@ -125,7 +127,11 @@ class Scheduler:
             if self.slot_busy[s]:
                 continue
             cap = self.slot_cap[s]
-            extra = self.ex.slot_bytes(max(cap, req.n)) - self.ex.slot_bytes(cap)
+            # the slot's context grows to the request's n; its scratch keeps
+            # the size of the largest leaf size it has run
+            leaf = max(self.slot_leaf[s], self.ex.leaf_of(req))
+            extra = (self.ex.slot_bytes(max(cap, req.n), leaf) -
+                     self.ex.slot_bytes(cap, self.slot_leaf[s]))
             extra += self.ex.array_bytes(req)
             if used + extra <= self.budget:
                 # prefer the slot that grows least, then the smallest capacity
@@ -145,6 +151,7 @@ class Scheduler:
         for s in idle:
             self.ex.release(s)
             self.slot_cap[s] = 0
+            self.slot_leaf[s] = 0
             self.events.append((self.clock.now(), "release", s))
             fit = self._fit(req)
             if fit is not None:
@@ -152,7 +159,7 @@ class Scheduler:
         return None
 
     def _never_fits(self, req: Request) -> bool:
-        return self.ex.slot_bytes(req.n) + self.ex.array_bytes(req) > self.budget
+        return self.ex.slot_bytes(req.n, self.ex.leaf_of(req)) + self.ex.array_bytes(req) > self.budget
 
     def run(self, requests):
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -181,6 +188,7 @@ class Scheduler:
                 queue.pop(0)
                 self.slot_busy[slot] = True
                 self.slot_cap[slot] = max(self.slot_cap[slot], req.n)
+                self.slot_leaf[slot] = max(self.slot_leaf[slot], self.ex.leaf_of(req))
                 self.array_bytes[req.rid] = self.ex.array_bytes(req)
                 self.peak_bytes = max(self.peak_bytes, self.used_bytes())
                 rec = recs[req.rid]
@@ -244,8 +252,11 @@ class FakeExecutor:
         self.active = {}
         self.released = []
 
-    def slot_bytes(self, cap: int) -> int:
+    def slot_bytes(self, cap: int, leaf: int = 16) -> int:
         return 0 if cap == 0 else self.fixed + self.bpp * cap
+
+    def leaf_of(self, req: Request) -> int:
+        return 16
 
     def array_bytes(self, req: Request) -> int:
         return 168 * req.n
@@ -308,10 +319,11 @@ class GpuExecutor:
         return self.sph.Params.from_setup(req.setup, precision=req.precision,
                                           leaf_size=self.leaf_for(req))
 
-    def slot_bytes(self, cap: int) -> int:
-        # a slot may run any leaf size; plan for the one that needs the most
-        return 0 if cap == 0 else max(self.sph.plan_bytes(self.sph.Params(leaf_size=g), cap)
-                                      for g in (8, 16, 32))
+    def slot_bytes(self, cap: int, leaf: int = 16) -> int:
+        return 0 if cap == 0 else self.sph.plan_bytes(self.sph.Params(leaf_size=leaf or 16), cap)
+
+    def leaf_of(self, req: Request) -> int:
+        return int(self.leaf_for(req))
 
     def array_bytes(self, req: Request) -> int:
         return req.n * 8 * 19 + req.n * 4 * 2
@@ -499,8 +511,15 @@ def main(argv=None):
         leaf_for = lambda req: g  # noqa: E731
     gib = args.budget_gib if args.budget_gib else (1.0 if args.workload == "evaluate" else 16.0)
     budget = int(gib * GIB)
+    def pretune(reqs):
+        # measure every request class before the timed runs
+        if args.leaf == "auto":
+            for r in reqs:
+                leaf_for(r)
+
     if args.workload == "evaluate":
         burst = evaluate_requests(args.requests, math.inf, n_max_side=args.max_side)
+        pretune(burst)
         _, closed = serve(burst, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True)
         rate = args.load * closed["requests_per_s"]
         reqs = evaluate_requests(args.requests, rate, n_max_side=args.max_side)
@@ -510,6 +529,7 @@ def main(argv=None):
                "poisson": opened}
     else:
         reqs = integrate_requests(args.requests, args.steps, n_max_side=args.max_side)
+        pretune(reqs)
         recs, out = serve(reqs, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True)
         steps = sum(r.info.get("steps", 0) for r in recs if not r.error)
         res = {"workload": "integrate", "mode": args.mode, "slots": args.slots, "leaf": args.leaf,
