@@ -468,6 +468,10 @@ __device__ inline Node merge_children(const Node *__restrict__ child, int64_t c0
     return nd;
 }
 
+// Leaf boxes and largest h: 16 lanes per leaf read its (consecutive)
+// particles together, then reduce with shuffles inside their 16-lane group.
+constexpr int kLeafLanes = 16;
+
 __global__ __launch_bounds__(256) void k_leaves(const TreeInfo *__restrict__ T,
                                                 const uint32_t *__restrict__ lstart,
                                                 const double *__restrict__ x,
@@ -477,18 +481,31 @@ __global__ __launch_bounds__(256) void k_leaves(const TreeInfo *__restrict__ T,
                                                 Node *__restrict__ nodes)
 {
     const int64_t L = T->cnt[0];
-    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L;
-         l += (int64_t)gridDim.x * blockDim.x) {
-        Node nd;
-        for (int a = 0; a < 3; a++) { nd.lo[a] = INFINITY; nd.hi[a] = -INFINITY; }
-        nd.hmax = 0.0;
-        nd.pad = 0.0;
-        for (int64_t k = lstart[l]; k < (int64_t)lstart[l + 1]; k++) {
-            double v[3] = {x[k], y[k], z[k]};
-            for (int a = 0; a < 3; a++) { nd.lo[a] = fmin(nd.lo[a], v[a]); nd.hi[a] = fmax(nd.hi[a], v[a]); }
-            nd.hmax = fmax(nd.hmax, h[k]);
+    const int q = threadIdx.x % kLeafLanes;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kLeafLanes);
+    // the 16 lanes of a group share l, so they take the same trips
+    for (int64_t l = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kLeafLanes; l < L; l += stride) {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double hm = 0.0;
+        for (int64_t k = lstart[l] + q; k < (int64_t)lstart[l + 1]; k += kLeafLanes) {
+            const double v[3] = {x[k], y[k], z[k]};
+            for (int a = 0; a < 3; a++) { lo[a] = fmin(lo[a], v[a]); hi[a] = fmax(hi[a], v[a]); }
+            hm = fmax(hm, h[k]);
         }
-        nodes[l] = nd;
+        for (int o = kLeafLanes / 2; o > 0; o >>= 1) {
+            for (int a = 0; a < 3; a++) {
+                lo[a] = fmin(lo[a], __shfl_xor(lo[a], o));
+                hi[a] = fmax(hi[a], __shfl_xor(hi[a], o));
+            }
+            hm = fmax(hm, __shfl_xor(hm, o));
+        }
+        if (q == 0) {
+            Node nd;
+            for (int a = 0; a < 3; a++) { nd.lo[a] = lo[a]; nd.hi[a] = hi[a]; }
+            nd.hmax = hm;
+            nd.pad = 0.0;
+            nodes[l] = nd;
+        }
     }
 }
 
@@ -500,11 +517,13 @@ __global__ __launch_bounds__(256) void k_leaf_hmax(const TreeInfo *__restrict__ 
                                                    Node *__restrict__ nodes)
 {
     const int64_t L = T->cnt[0];
-    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L;
-         l += (int64_t)gridDim.x * blockDim.x) {
+    const int q = threadIdx.x % kLeafLanes;
+    const int64_t stride = (int64_t)gridDim.x * (blockDim.x / kLeafLanes);
+    for (int64_t l = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kLeafLanes; l < L; l += stride) {
         double hm = 0.0;
-        for (int64_t k = lstart[l]; k < (int64_t)lstart[l + 1]; k++) hm = fmax(hm, h[k]);
-        nodes[l].hmax = hm;
+        for (int64_t k = lstart[l] + q; k < (int64_t)lstart[l + 1]; k += kLeafLanes) hm = fmax(hm, h[k]);
+        for (int o = kLeafLanes / 2; o > 0; o >>= 1) hm = fmax(hm, __shfl_xor(hm, o));
+        if (q == 0) nodes[l].hmax = hm;
     }
 }
 

@@ -505,6 +505,31 @@ __device__ inline void group_tests(Stage<G, PREC> &S, int count, Relevant releva
     wave_lds_sync();
 }
 
+// As for_my_bits, but this lane's bits two at a time: fn(sa, sb) with sb < 0
+// when sa is its last, so the caller can issue both pairs' loads before
+// using either.
+template <int LPP, class Fn>
+__device__ inline int for_my_bit_pairs(uint64_t w0, uint64_t w1, int e0, Fn fn)
+{
+    const int n = (int)__popcll(w0) + (int)__popcll(w1);
+    auto pop = [&]() {
+        if (w0) w0 &= w0 - 1; else w1 &= w1 - 1;
+    };
+    auto low = [&]() { return w0 ? (int)__builtin_ctzll(w0) : 64 + (int)__builtin_ctzll(w1); };
+    for (int t = 0; t < e0; t++) pop();
+    for (int e = e0; e < n; e += 2 * LPP) {
+        const int sa = low();
+        for (int t = 0; t < LPP; t++) pop();
+        int sb = -1;
+        if (e + LPP < n) {
+            sb = low();
+            for (int t = 0; t < LPP; t++) pop();
+        }
+        fn(sa, sb);
+    }
+    return n;
+}
+
 // The set bits of a 128-bit mask in ascending order, shared round-robin by
 // the LPP lanes of a particle: this lane takes the bits of rank e = e0,
 // e0 + LPP, ... (0 <= e0 < LPP) and calls fn(slot, e).  Returns the number of
@@ -965,12 +990,27 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     return in && S.j[sl] != (uint32_t)(first + pp);
                 });
             const uint64_t w0 = S.mask[p][0], w1 = S.mask[p][1];
-            // the particle's hits of this group (same count on all its lanes)
-            cnt += for_my_bits<LPP>(w0, w1, q, [&](int sl, int) {
+            // the record of a neighbour that the pair terms read
+            struct JData {
+                double c, hinv, vx, vy, vz, m, A, rho;
+            };
+            auto load_j = [&](int sl) {
                 const int64_t j = S.j[sl];
+                JData d;
+                d.c = F.c[j];
+                d.hinv = F.hinv[j];
+                d.vx = F.vx[j];
+                d.vy = F.vy[j];
+                d.vz = F.vz[j];
+                d.m = F.m[j];
+                d.A = F.A[j];
+                d.rho = F.rho[j];
+                return d;
+            };
+            auto pair_terms = [&](int sl, const JData &d) {
                 double dx, dy, dz, r2;
                 separation<G, PREC>(S, bx, hx, hy, hz, hfx, hfy, hfz, sl, dx, dy, dz, r2);
-                const double cj = F.c[j];
+                const double cj = d.c;
                 if (r2 == 0.0) {
                     vs_max = fmax(vs_max, PREC == SPH_FP64 ? ci + cj : (double)((float)ci + (float)cj));
                     return;
@@ -979,21 +1019,21 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const double rr = sqrt(r2);
                     const double rinv = 1.0 / rr;
                     const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-                    const double hinvj = F.hinv[j];
+                    const double hinvj = d.hinv;
                     const double gfj = kSigma * (hinvj * hinvj) * (hinvj * hinvj);
                     double fi, dfi, fj, dfj;
                     m4(rr * hinvi, fi, dfi);
                     m4(rr * hinvj, fj, dfj);
                     double gi, gj, gsum;
                     sym_grads(gfi, dfi, gfj, dfj, gi, gj, gsum);
-                    const double w = ((vxi - F.vx[j]) * ex + (vyi - F.vy[j]) * ey) + (vzi - F.vz[j]) * ez;
-                    const double mj = F.m[j];
-                    double cvec = -mj * sym_dot2(Ai, gi, F.A[j], gj);
+                    const double w = ((vxi - d.vx) * ex + (vyi - d.vy) * ey) + (vzi - d.vz) * ez;
+                    const double mj = d.m;
+                    double cvec = -mj * sym_dot2(Ai, gi, d.A, gj);
                     double cdu = Ai * mj * gi * w;
                     const double wneg = fmin(w, 0.0);
                     const double vs = (ci + cj) - beta * wneg;
                     vs_max = fmax(vs_max, vs);
-                    const double visc = (mj / (0.5 * (rhoi + F.rho[j]))) * alpha * vs * wneg;
+                    const double visc = (mj / (0.5 * (rhoi + d.rho))) * alpha * vs * wneg;
                     const double gbar = 0.5 * gsum;
                     cvec += visc * gbar;
                     cdu -= visc * 0.5 * wneg * gbar;
@@ -1006,7 +1046,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const float rr = sqrtf((float)r2);
                     const float rinv = 1.0f / rr;
                     const float ex = fdx * rinv, ey = fdy * rinv, ez = fdz * rinv;
-                    const float hinvj = (float)F.hinv[j];
+                    const float hinvj = (float)d.hinv;
                     // own and other kernel factors formed by the same float
                     // expression, so the (j, i) pair sees exactly the values of
                     // the (i, j) pair
@@ -1016,17 +1056,17 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     m4(rr * hinvj, fj, dfj);
                     float gi, gj, gsum;
                     sym_grads(gfif, dfi, gfjf, dfj, gi, gj, gsum);
-                    const float w = ((float)(vxi - F.vx[j]) * ex + (float)(vyi - F.vy[j]) * ey) +
-                                    (float)(vzi - F.vz[j]) * ez;
-                    const float mj = (float)F.m[j];
+                    const float w = ((float)(vxi - d.vx) * ex + (float)(vyi - d.vy) * ey) +
+                                    (float)(vzi - d.vz) * ez;
+                    const float mj = (float)d.m;
                     const float Aif = (float)Ai;
                     const float cif = (float)ci, cjf = (float)cj;
-                    float cvec = -mj * sym_dot2(Aif, gi, (float)F.A[j], gj);
+                    float cvec = -mj * sym_dot2(Aif, gi, (float)d.A, gj);
                     float cdu = Aif * mj * gi * w;
                     const float wneg = fminf(w, 0.0f);
                     const float vs = (cif + cjf) - (float)beta * wneg;
                     vs_max = fmax(vs_max, (double)vs);
-                    const float visc = (mj / (0.5f * ((float)rhoi + (float)F.rho[j]))) * (float)alpha * vs * wneg;
+                    const float visc = (mj / (0.5f * ((float)rhoi + (float)d.rho))) * (float)alpha * vs * wneg;
                     const float gbar = 0.5f * gsum;
                     cvec += visc * gbar;
                     cdu -= visc * 0.5f * wneg * gbar;
@@ -1035,7 +1075,22 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     azi += (double)(cvec * ez);
                     dui += (double)cdu;
                 }
-            });
+            };
+            // the particle's hits of this group (same count on all its lanes).
+            // FP32-pair: two at a time, both neighbours' records requested
+            // before either is used (measured faster; at the FP64 register
+            // budget the second record costs more than it hides)
+            if (PREC == SPH_FP32_PAIR) {
+                cnt += for_my_bit_pairs<LPP>(w0, w1, q, [&](int sa, int sb) {
+                    const JData da = load_j(sa);
+                    JData db = da;
+                    if (sb >= 0) db = load_j(sb);
+                    pair_terms(sa, da);
+                    if (sb >= 0) pair_terms(sb, db);
+                });
+            } else {
+                cnt += for_my_bits<LPP>(w0, w1, q, [&](int sl, int) { pair_terms(sl, load_j(sl)); });
+            }
             if (q == 0) {
                 S.mask[p][0] = 0;
                 S.mask[p][1] = 0;
