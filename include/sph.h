@@ -150,6 +150,12 @@ typedef struct {
     int32_t walk_overflows; /* leaves whose neighbour walk overflowed LDS (slow path) */
     int64_t dens_leaf_visits; /* candidate leaves swept by the density loop (all iterations) */
     int64_t dens_walks;   /* tree walks made by the density loop */
+    int64_t nr_iter_total;    /* density evaluations summed over particles (mean = / n) */
+    /* the next four only while instrumentation bit 1 is set (else 0) */
+    int64_t dens_candidate_tests; /* particle-candidate distance tests, density loop */
+    int64_t dens_box_tests;   /* particle-leaf box tests, density loop */
+    int64_t force_candidate_tests; /* particle-candidate distance tests, force loop */
+    int64_t force_box_tests;  /* particle-leaf box tests, force loop */
 } sph_state_stats;
 
 typedef struct sph_ctx sph_ctx;
@@ -287,11 +293,14 @@ size_t sph_device_bytes(const sph_ctx *ctx);
 size_t sph_plan_bytes(const sph_params *p, int64_t n);
 
 /*
- * Timing of individual kernels with HIP events on the context's stream.
- * When enabled, the density-loop and force-loop kernels are bracketed by
- * events; sph_kernel_times (waits for the stream) returns the summed
- * milliseconds and launch counts since the last reset.  which: 0 density
- * loop, 1 force loop, 2 neighbour build (keys, sort, gather, tree).
+ * Instrumentation.  enable bit 0: timing of individual kernels with HIP
+ * events on the context's stream -- the density-loop and force-loop kernels
+ * are bracketed by events; sph_kernel_times (waits for the stream) returns the
+ * summed milliseconds and launch counts since the last reset.  which: 0
+ * density loop, 1 force loop, 2 neighbour build (keys, sort, gather, tree).
+ * enable bit 1: the pair loops also count their particle-box and
+ * particle-candidate tests (sph_state_stats *_box_tests, *_candidate_tests;
+ * zero otherwise), at a cost of a few percent.  Other bits: SPH_EINVAL.
  */
 sph_status sph_enable_kernel_timing(sph_ctx *ctx, int32_t enable);
 sph_status sph_kernel_times(sph_ctx *ctx, int32_t which, double *ms, int64_t *launches);

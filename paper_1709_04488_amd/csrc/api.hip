@@ -495,7 +495,7 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return SPH_EDEVICE; }
     bool ok = hipMalloc((void **)&c->d_status, sizeof(int32_t) * kStatusWords) == hipSuccess &&
               hipMalloc((void **)&c->d_scal, sizeof(double) * 16) == hipSuccess &&
-              hipMalloc((void **)&c->d_counts, sizeof(int64_t) * 8) == hipSuccess &&
+              hipMalloc((void **)&c->d_counts, sizeof(int64_t) * kCountWords) == hipSuccess &&
               hipMalloc((void **)&c->d_box, sizeof(double) * 8) == hipSuccess &&
               hipMalloc((void **)&c->d_part, sizeof(double) * 1024 * 8) == hipSuccess &&
               hipMalloc((void **)&c->d_tree, sizeof(TreeInfo)) == hipSuccess &&
@@ -515,7 +515,7 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
     // middle of the first calls' work
     ok = hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * kStatusWords, c->stream) == hipSuccess &&
          hipMemsetAsync(c->d_scal, 0, sizeof(double) * 16, c->stream) == hipSuccess &&
-         hipMemsetAsync(c->d_counts, 0, sizeof(int64_t) * 8, c->stream) == hipSuccess &&
+         hipMemsetAsync(c->d_counts, 0, sizeof(int64_t) * kCountWords, c->stream) == hipSuccess &&
          hipStreamSynchronize(c->stream) == hipSuccess;
     if (!ok) { sph_destroy(c); return SPH_EDEVICE; }
     *out = c;
@@ -773,7 +773,7 @@ sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
 {
     if (!c || !info) return SPH_EINVAL;
     if (c->n <= 0) return fail(c, SPH_ESTATE, "nothing evaluated yet");
-    int64_t counts[8];
+    int64_t counts[kCountWords];
     TRY(hip_check(c, hipMemcpyAsync(c->h_scal, c->d_scal, sizeof(double) * 8,
                                     hipMemcpyDeviceToHost, c->stream), "copy scalars"));
     TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
@@ -788,14 +788,19 @@ sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
     info->thermal = c->h_scal[4];
     for (int a = 0; a < 3; a++) info->momentum[a] = c->h_scal[5 + a];
     info->steps = c->steps;
-    info->n_dens_pairs = counts[0];
-    info->n_force_pairs = counts[1];
-    info->dens_pair_evals = counts[2];
-    info->force_pair_evals = counts[3];
-    info->nr_iter_max = (int32_t)counts[4];
-    info->walk_overflows = (int32_t)counts[5];
-    info->dens_leaf_visits = counts[6];
-    info->dens_walks = counts[7];
+    info->n_dens_pairs = counts[kCntNngb];
+    info->n_force_pairs = counts[kCntNforce];
+    info->dens_pair_evals = counts[kCntDensEvals];
+    info->force_pair_evals = counts[kCntForceEvals];
+    info->nr_iter_max = (int32_t)counts[kCntNrMax];
+    info->walk_overflows = (int32_t)(counts[kCntDensOverflows] + counts[kCntForceOverflows]);
+    info->dens_leaf_visits = counts[kCntDensVisits];
+    info->dens_walks = counts[kCntDensWalks];
+    info->nr_iter_total = counts[kCntNrTotal];
+    info->dens_candidate_tests = counts[kCntDensTests];
+    info->dens_box_tests = counts[kCntDensBoxes];
+    info->force_candidate_tests = counts[kCntForceTests];
+    info->force_box_tests = counts[kCntForceBoxes];
     return SPH_OK;
 }
 
@@ -891,7 +896,9 @@ size_t sph_plan_bytes(const sph_params *p, int64_t n)
 sph_status sph_enable_kernel_timing(sph_ctx *c, int32_t enable)
 {
     if (!c) return SPH_EINVAL;
-    c->timer.on = enable != 0;
+    if (enable & ~3) return fail(c, SPH_EINVAL, "enable takes bits 0 and 1 only");
+    c->timer.on = (enable & 1) != 0;
+    c->count_tests = (enable & 2) != 0;
     return SPH_OK;
 }
 

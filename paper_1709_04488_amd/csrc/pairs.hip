@@ -454,7 +454,8 @@ __device__ constexpr double box_slack() { return PREC == SPH_FP64 ? 1.0 + 1e-6 :
 // Hit masks of one staged group: bit s of S.mask[p] set iff rec(p, s), with
 // rec evaluated only where relevant(p, k) holds for the slot's leaf k.
 template <int G, int PREC, class Relevant, class Record>
-__device__ inline void group_tests(Stage<G, PREC> &S, int count, Relevant relevant, Record rec)
+__device__ inline void group_tests(Stage<G, PREC> &S, int count, Relevant relevant, Record rec,
+                                   bool diag, int64_t &boxes, int64_t &tests)
 {
     constexpr int NL = Stage<G, PREC>::NL;
     constexpr int LPC = G / kTestsPerLane;   // lanes per combination
@@ -478,6 +479,14 @@ __device__ inline void group_tests(Stage<G, PREC> &S, int count, Relevant releva
     if (r0) S.combo[__popcll(m0 & lt)] = (uint8_t)lane;
     if (r1) S.combo[n0 + (int)__popcll(m1 & lt)] = (uint8_t)(lane + kWave);
     const int C = n0 + (int)__popcll(m1);
+    // diagnostics (when asked for), wave-uniform: every judged combination is
+    // a box test, and a passing one tests each particle of its leaf (7-bit
+    // count per lane)
+    if (diag) {
+        boxes += (int64_t)count * G;
+        const int mine = (r0 ? S.jn[lane % NL] : 0) + (r1 ? S.jn[(lane + kWave) % NL] : 0);
+        for (int b = 0; b < 7; b++) tests += (int64_t)__popcll(__ballot((mine >> b) & 1)) << b;
+    }
     wave_lds_sync();
     const int u = lane % LPC;
     // combinations of one round start their tests at different slots, which
@@ -616,6 +625,7 @@ struct DensArgs {
     int32_t *status;
     int64_t *counts;
     const double *mrange;   // smallest and largest mass of the set
+    int32_t count_tests;    // also count box and candidate tests (diagnostics)
     double eta3;
     double h_rtol;
     double walk_margin;
@@ -646,7 +656,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
     // with equal masses, r^2 = 0 stored negated) to keep it out of the count.
     double *const cr2 = B.cache + (size_t)blockIdx.x * (2 * ROWS * kWave);
     double *const cm = cr2 + ROWS * kWave;
-    int64_t evals = 0, walks = 0, visits = 0, overflows = 0;
+    int64_t evals = 0, walks = 0, visits = 0, overflows = 0, nr_total = 0, tests = 0, boxes = 0;
     int iter_max = 0;
     int cur = -1;
     DensArgs A;
@@ -654,13 +664,19 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
     auto flush_counts = [&]() {
         for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
         if (lane == 0 && cur >= 0) {
-            atomicAdd((unsigned long long *)&A.counts[2], (unsigned long long)evals);
-            atomicMax((unsigned long long *)&A.counts[4], (unsigned long long)iter_max);
-            if (overflows) atomicAdd((unsigned long long *)&A.counts[5], (unsigned long long)overflows);
-            atomicAdd((unsigned long long *)&A.counts[6], (unsigned long long)visits);
-            atomicAdd((unsigned long long *)&A.counts[7], (unsigned long long)walks);
+            auto add = [&](int k, int64_t v) {
+                if (v) atomicAdd((unsigned long long *)&A.counts[k], (unsigned long long)v);
+            };
+            add(kCntDensEvals, evals);
+            atomicMax((unsigned long long *)&A.counts[kCntNrMax], (unsigned long long)iter_max);
+            add(kCntDensOverflows, overflows);
+            add(kCntDensVisits, visits);
+            add(kCntDensWalks, walks);
+            add(kCntNrTotal, nr_total);
+            add(kCntDensTests, tests);
+            add(kCntDensBoxes, boxes);
         }
-        evals = walks = visits = overflows = 0;
+        evals = walks = visits = overflows = nr_total = tests = boxes = 0;
         iter_max = 0;
     };
     for_each_home_leaf(pre[B.nreq], B.work, [&](int64_t gleaf) {
@@ -769,7 +785,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                             separation<G, PREC>(S, bx, S.hx[pp], S.hy[pp], S.hz[pp], S.hfx[pp],
                                                 S.hfy[pp], S.hfz[pp], sl, dx, dy, dz, r2);
                             return r2 < S.thr[pp];
-                        });
+                        },
+                        A.count_tests != 0, boxes, tests);
                     const uint64_t w0 = S.mask[p][0], w1 = S.mask[p][1];
                     // list position base + e belongs to lane (base + e) % LPP
                     const int e0 = (q - base % LPP + LPP) % LPP;
@@ -809,6 +826,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 }
             }
             if (!conv) evals += cnt;
+            // one evaluation for every particle still iterating (uniform)
+            nr_total += (int64_t)__popcll(__ballot(!conv && q == 0));
 #pragma unroll
             for (int o = 1; o < LPP; o <<= 1) {
                 s0 += __shfl_xor(s0, o);
@@ -894,6 +913,7 @@ struct ForceArgs {
     int32_t *status;
     int64_t *counts;
     double alpha, beta, ccfl;
+    int32_t count_tests;    // also count box and candidate tests (diagnostics)
 };
 
 template <int G, int PREC>
@@ -908,16 +928,21 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
     batch_prefix(B, pre);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
-    int64_t pairs_total = 0, overflows = 0;
+    int64_t pairs_total = 0, overflows = 0, tests = 0, boxes = 0;
     int cur = -1;
     ForceArgs F;
     auto flush_counts = [&]() {
         for (int o = 32; o > 0; o >>= 1) pairs_total += __shfl_xor(pairs_total, o);
         if (lane == 0 && cur >= 0) {
-            atomicAdd((unsigned long long *)&F.counts[3], (unsigned long long)pairs_total);
-            if (overflows) atomicAdd((unsigned long long *)&F.counts[5], (unsigned long long)overflows);
+            auto add = [&](int k, int64_t v) {
+                if (v) atomicAdd((unsigned long long *)&F.counts[k], (unsigned long long)v);
+            };
+            add(kCntForceEvals, pairs_total);
+            add(kCntForceOverflows, overflows);
+            add(kCntForceTests, tests);
+            add(kCntForceBoxes, boxes);
         }
-        pairs_total = overflows = 0;
+        pairs_total = overflows = tests = boxes = 0;
     };
     for_each_home_leaf(pre[B.nreq], B.work, [&](int64_t gleaf) {
         const int r = find_req(pre, B.nreq, gleaf);
@@ -988,7 +1013,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     if (PREC == SPH_FP64) in = r2 < thr || r2 < hj2x4;
                     else in = (float)r2 < (float)thr || (float)r2 < (float)hj2x4;
                     return in && S.j[sl] != (uint32_t)(first + pp);
-                });
+                },
+                F.count_tests != 0, boxes, tests);
             const uint64_t w0 = S.mask[p][0], w1 = S.mask[p][1];
             // the record of a neighbour that the pair terms read
             struct JData {
@@ -1268,9 +1294,6 @@ inline void fill_common(sph_ctx *c, int64_t n, Args &a)
     a.nodes = c->nodes;
 }
 
-// Persistent grid: a multiple of the XCD count, enough one-wave blocks to
-// fill every CU several times over, never more than there can be leaves.
-
 } // namespace
 
 // ---- argument blocks and batched launches ---------------------------------
@@ -1328,6 +1351,7 @@ sph_status density_prepare(sph_ctx *c, int64_t n)
     a.status = c->d_status;
     a.counts = c->d_counts;
     a.mrange = c->d_scal + 8;
+    a.count_tests = c->count_tests ? 1 : 0;
     a.eta3 = c->p.eta * c->p.eta * c->p.eta;
     // FP32-pair mode: the density sum carries single-precision pair terms
     // (relative noise ~1e-7), so the Newton step cannot settle below a few
@@ -1362,6 +1386,7 @@ sph_status forces_prepare(sph_ctx *c, int64_t n, const double *vx, const double 
     a.status = c->d_status;
     a.counts = c->d_counts;
     a.alpha = c->p.alpha_av; a.beta = c->p.beta_av; a.ccfl = c->p.c_cfl;
+    a.count_tests = c->count_tests ? 1 : 0;
     const void *req[] = {a.nodes, a.x, a.y, a.z, a.vx, a.vy, a.vz, a.m, a.h, a.hinv, a.rho,
                          a.A, a.c, a.ax, a.ay, a.az, a.du, a.vsig, a.dt, a.nforce, a.status,
                          a.counts, a.tree, a.lstart, a.work, c->d_fargs};
@@ -1382,7 +1407,7 @@ sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax)
     if (count <= 0) return SPH_OK;
     sph_ctx *c = cs[0];
     if (count > kMaxBatch) return fail(c, SPH_EINVAL, "batch larger than kMaxBatch");
-    TRY_(zero_batch_counts(cs, count, 2, 6));
+    TRY_(zero_batch_counts(cs, count, kCntDensFirst, kCntDensWords));
     Batch<DensArgs> B{};
     B.nreq = count;
     B.work = c->d_work;
@@ -1430,7 +1455,7 @@ sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax)
     if (count <= 0) return SPH_OK;
     sph_ctx *c = cs[0];
     if (count > kMaxBatch) return fail(c, SPH_EINVAL, "batch larger than kMaxBatch");
-    TRY_(zero_batch_counts(cs, count, 3, 1));
+    TRY_(zero_batch_counts(cs, count, kCntForceFirst, kCntForceWords));
     Batch<ForceArgs> B{};
     B.nreq = count;
     B.work = c->d_work;

@@ -85,6 +85,32 @@ enum : int32_t {
 };
 constexpr int kStatusWords = 8;
 
+// Device counters of the last evaluation.  [0, 1] are written by the
+// conserved-quantity reduction; the density loop zeroes and fills
+// [kCntDensFirst, kCntDensFirst + kCntDensWords), the force loop
+// [kCntForceFirst, kCntForceFirst + kCntForceWords).
+enum : int {
+    kCntNngb = 0,            // sum of density neighbour counts
+    kCntNforce = 1,          // sum of force neighbour counts
+    kCntDensEvals = 2,       // density pairs evaluated, all Newton-Raphson iterations
+    kCntNrMax = 3,           // largest Newton-Raphson iteration count of a wave
+    kCntDensOverflows = 4,   // density walks that overflowed the LDS frontier
+    kCntDensVisits = 5,      // candidate leaves staged by density sweeps
+    kCntDensWalks = 6,       // density tree walks
+    kCntNrTotal = 7,         // density evaluations summed over particles
+    kCntDensTests = 8,       // particle-candidate distance tests, density
+    kCntDensBoxes = 9,       // particle-leaf box tests, density
+    kCntForceEvals = 10,     // force pairs evaluated
+    kCntForceOverflows = 11, // force walks that overflowed the LDS frontier
+    kCntForceTests = 12,     // particle-candidate distance tests, force
+    kCntForceBoxes = 13,     // particle-leaf box tests, force
+    kCountWords = 16,
+    kCntDensFirst = kCntDensEvals,
+    kCntDensWords = kCntDensBoxes - kCntDensEvals + 1,
+    kCntForceFirst = kCntForceEvals,
+    kCntForceWords = kCntForceBoxes - kCntForceEvals + 1,
+};
+
 // Arrays in sorted (Morton) order.  FP32-pair mode adds float offsets from the
 // centre of each particle's leaf.
 struct Sorted {
@@ -161,10 +187,7 @@ struct sph_ctx {
     bool resident = false;
     double *d_scal = nullptr;   // [0] dt_next [1] dt_last [2] time [3] KE [4] TE [5..7] P
                                 // [8] smallest, [9] largest mass of the last density pass
-    // [0] sum nngb [1] sum nforce (last evaluation), [2] density pair
-    // evaluations summed over Newton-Raphson iterations, [3] force pair
-    // evaluations, [4] max Newton-Raphson iterations, [5] walk overflows,
-    // [6] candidate leaves swept by the density loop, [7] density tree walks
+    // device counters, indexed by the kCnt* constants
     int64_t *d_counts = nullptr;
     double *h_scal = nullptr;   // pinned mirror
     double *dt_used_out = nullptr;
@@ -179,6 +202,7 @@ struct sph_ctx {
     double graph_dt = 0.0;
 
     sph::Timer timer;
+    bool count_tests = false;   // pair loops also count box and candidate tests
 };
 
 namespace sph {

@@ -65,7 +65,9 @@ class _Stats(ctypes.Structure):
                 ("n_force_pairs", ctypes.c_int64), ("dens_pair_evals", ctypes.c_int64),
                 ("force_pair_evals", ctypes.c_int64), ("nr_iter_max", ctypes.c_int32),
                 ("walk_overflows", ctypes.c_int32), ("dens_leaf_visits", ctypes.c_int64),
-                ("dens_walks", ctypes.c_int64)]
+                ("dens_walks", ctypes.c_int64), ("nr_iter_total", ctypes.c_int64),
+                ("dens_candidate_tests", ctypes.c_int64), ("dens_box_tests", ctypes.c_int64),
+                ("force_candidate_tests", ctypes.c_int64), ("force_box_tests", ctypes.c_int64)]
 
 
 _lib = None
@@ -298,7 +300,12 @@ class Context:
                 "n_dens_pairs": st.n_dens_pairs, "n_force_pairs": st.n_force_pairs,
                 "dens_pair_evals": st.dens_pair_evals, "force_pair_evals": st.force_pair_evals,
                 "nr_iter_max": st.nr_iter_max, "walk_overflows": st.walk_overflows,
-                "dens_leaf_visits": st.dens_leaf_visits, "dens_walks": st.dens_walks}
+                "dens_leaf_visits": st.dens_leaf_visits, "dens_walks": st.dens_walks,
+                "nr_iter_total": st.nr_iter_total,
+                "dens_candidate_tests": st.dens_candidate_tests,
+                "dens_box_tests": st.dens_box_tests,
+                "force_candidate_tests": st.force_candidate_tests,
+                "force_box_tests": st.force_box_tests}
 
     def neighbours(self, p: Particles, mode: int, cap: int = None):
         """CSR lists at the given h -> (offsets int64[n+1], idx int32) on the device."""
@@ -331,8 +338,9 @@ class Context:
     def device_bytes(self) -> int:
         return int(self.lib.sph_device_bytes(self.h))
 
-    def enable_kernel_timing(self, on: bool = True):
-        self._check(self.lib.sph_enable_kernel_timing(self.h, 1 if on else 0), "timing")
+    def enable_kernel_timing(self, on: bool = True, count_tests: bool = False):
+        flags = (1 if on else 0) | (2 if count_tests else 0)
+        self._check(self.lib.sph_enable_kernel_timing(self.h, flags), "timing")
 
     def kernel_times(self, which: int):
         ms = ctypes.c_double()

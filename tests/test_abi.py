@@ -61,4 +61,33 @@ def test_struct_layouts_match_header():
     from paper_1709_04488_amd import sph
     assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4
     assert ctypes.sizeof(sph._Particles) == 8 + 21 * 8
-    assert ctypes.sizeof(sph._Stats) == 8 * 8 + 5 * 8 + 8 + 2 * 8
+    assert ctypes.sizeof(sph._Stats) == 8 * 8 + 5 * 8 + 8 + 2 * 8 + 5 * 8
+
+
+def test_struct_offsets_match_the_c_compiler(tmp_path):
+    # every field offset and struct size of the binding equals what gcc lays
+    # out from include/sph.h
+    import shutil
+    import subprocess
+    from paper_1709_04488_amd import sph
+    if not shutil.which("gcc"):
+        pytest.skip("no gcc")
+    pairs = (("sph_params", sph._Params), ("sph_particles", sph._Particles),
+             ("sph_state_stats", sph._Stats))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sph.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field in py._fields_:
+            f = field[0]
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line.strip()}
+    for cname, py in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field in py._fields_:
+            assert got[(cname, field[0])] == getattr(py, field[0]).offset, (cname, field[0])

@@ -283,6 +283,31 @@ def test_resident_forces_after_h_grows(sph, orc, which):
     _check(out, ref, label="resident " + w.name)
 
 
+def test_paper_tolerance_mode_satisfies_its_own_bound(sph, orc):
+    """With the paper's ~1 % stopping rule (section 2.1.1) the result is not
+    parity-checked, only held to that rule.  The iteration stops at an h whose
+    Newton step is at most h_rtol h; there g = h^3 rho - eta^3 m equals the
+    step times g' = 3 h^2 rho Omega, so |h^3 rho / (eta^3 m) - 1| is at most
+    about 3 Omega h_rtol (1 + that residual).  h is the last Newton step away
+    from the root, up to that step's own second-order term."""
+    w = W.config0()
+    print("case: h_rtol 1e-2", flush=True)
+    params = sph.Params.from_setup(w.setup)
+    params.h_rtol = 1e-2
+    with sph.Context(params) as ctx:
+        p = sph.Particles.from_host(w.arrays)
+        ctx.density(p)
+        ctx.sync()
+        out = p.host("h", "rho", "omega")
+    m = w.arrays["m"]
+    eta = w.setup["eta"]
+    rel = np.abs(out["h"] ** 3 * out["rho"] / (eta ** 3 * m) - 1.0)
+    bound = 3.0 * np.abs(out["omega"]) * 1e-2 * 1.05
+    assert np.all(rel <= bound), float(np.max(rel / bound))
+    ref = _oracle_eval(orc, w)
+    assert np.max(np.abs(out["h"] / ref["h"] - 1.0)) < 1e-2 * 1.05
+
+
 def test_fp32_pair_mode_tolerances(sph, orc):
     for w in (W.config0(), W.plummer(3000, seed=12)):
         print("case: fp32 %s" % w.name, flush=True)
