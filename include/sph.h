@@ -92,7 +92,8 @@ typedef struct {
     double alpha_av;   /* artificial viscosity strength (0 disables it) */
     double beta_av;    /* signal-speed coefficient */
     double c_cfl;      /* CFL multiplier */
-    double h_rtol;     /* Newton-Raphson stop: |h_new - h| <= h_rtol h */
+    double h_rtol;     /* Newton-Raphson stop: the last step would change h
+                          by <= h_rtol h and rho by <= h_rtol rho */
     int32_t h_max_iter;/* Newton-Raphson iteration cap (>= 1) */
     int32_t periodic;  /* 1: periodic box [box_lo, box_hi); 0: isolated */
     double box_lo[3];
@@ -194,9 +195,11 @@ sph_status sph_build_cells(sph_ctx *ctx, const sph_particles *ps);
 /*
  * Density loop and h solve (eqs. EQN:SPHRHO, EQN:HRHO, EQN:OMEGA): for each i
  * the h_i with h_i^3 rho_i(h_i) = eta^3 m_i, found by safeguarded
- * Newton-Raphson from the guess in ps->h to |dh| <= h_rtol h (the self term
- * j = i is part of rho_i).  Writes h, rho, omega, and if non-NULL pressure
- * (gamma-1) rho u (reads u then), cs = sqrt(gamma P / rho), nngb.
+ * Newton-Raphson on h - eta (m_i / rho_i(h))^(1/3) from the guess in ps->h,
+ * stopped when the next step would change h_i by at most h_rtol h_i and rho_i
+ * by at most h_rtol rho_i (the self term j = i is part of rho_i).  Writes h,
+ * rho, omega, and if non-NULL pressure (gamma-1) rho u (reads u then),
+ * cs = sqrt(gamma P / rho), nngb.
  * Rebuilds the neighbour structure for the current positions first.
  */
 sph_status sph_density(sph_ctx *ctx, sph_particles *ps);

@@ -835,22 +835,31 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 cnt += __shfl_xor(cnt, o);
             }
             if (!conv) {
-                // g(h) = h^3 rho(h) - eta^3 m = sigma sum m f - eta^3 m, non-decreasing;
-                // g'(h) = -(sigma/h) sum m q f'(q) >= 0
+                // the root of g(h) = h^3 rho(h) - eta^3 m = sigma sum m f - eta^3 m
+                // (non-decreasing in h) is the h of the h-rho relation.  Newton runs
+                // on the equivalent F(h) = h - eta (m / rho(h))^(1/3), which is
+                // exactly linear where rho does not vary over the kernel and so
+                // converges in fewer steps than Newton on the cubic g; F has the
+                // sign of g, and F'(h) = 1 - (h*/h)(1 - Omega) with h* = h - F
                 const double g = kSigma * s0 - A.eta3 * mi;
-                const double gp = -kSigma * s2 * hinv;
+                const double hs = h * cbrt(A.eta3 * mi / (kSigma * s0));
+                const double om = -s2 / (3.0 * s0);
+                const double fp = 1.0 - (hs * hinv) * (1.0 - om);
                 h_out = h;
                 rho_out = kSigma * s0 * hinv * hinv * hinv;
-                om_out = -s2 / (3.0 * s0);
+                om_out = om;
                 n_out = cnt;
-                // the Newton step decides convergence before any safeguard: a step
-                // below the tolerance (down to a zero step at the root) is final
-                const double step = gp > 0.0 ? g / gp : INFINITY;
-                if (g == 0.0 || fabs(step) <= A.h_rtol * h) {
+                // the Newton step decides convergence before any safeguard: h and rho
+                // are final once the step would change h by at most h_rtol h and rho
+                // (d ln rho / d ln h = 3 (Omega - 1)) by at most h_rtol rho, down to
+                // a zero step at the root
+                const double step = fp > 0.0 ? (h - hs) / fp : INFINITY;
+                const double sens = fmax(1.0, 3.0 * fabs(om - 1.0));
+                if (g == 0.0 || fabs(step) * sens <= A.h_rtol * h) {
                     conv = true;
                 } else {
                     if (g < 0.0) lo_b = fmax(lo_b, h); else hi_b = fmin(hi_b, h);
-                    double hn = gp > 0.0 ? h - step : (g < 0.0 ? 2.0 * h : 0.5 * h);
+                    double hn = fp > 0.0 ? h - step : (g < 0.0 ? 2.0 * h : 0.5 * h);
                     hn = fmin(fmax(hn, 0.5 * h), 2.0 * h);
                     // outside the bracket of known signs: bisect it
                     if (!(hn > lo_b && hn < hi_b)) hn = hi_b < INFINITY ? 0.5 * (lo_b + hi_b) : 2.0 * h;
