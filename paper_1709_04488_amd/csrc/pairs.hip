@@ -29,6 +29,45 @@
 namespace sph {
 namespace {
 
+// Views of pointers the pair kernels only read.  Through the constant address
+// space a load with a wave-uniform address becomes a scalar load into SGPRs
+// (the argument blocks, the home leaf's node); through the global address
+// space a per-lane load is a plain vector load instead of a flat access, whose
+// completion LDS waits would otherwise also have to cover.
+template <class T>
+__device__ inline const __attribute__((address_space(4))) T *as_const(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T *as_global(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+// A whole read-only record, word by word through one of those views.
+template <class T>
+__device__ inline T load_const(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0 && alignof(T) >= 4, "word-sized record");
+    T v;
+    const auto *src = as_const((const uint32_t *)p);
+    uint32_t *dst = (uint32_t *)&v;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); k++) dst[k] = src[k];
+    return v;
+}
+template <class T>
+__device__ inline T load_global(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0 && alignof(T) >= 4, "word-sized record");
+    T v;
+    const auto *src = as_global((const uint32_t *)p);
+    uint32_t *dst = (uint32_t *)&v;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); k++) dst[k] = src[k];
+    return v;
+}
+
 __device__ inline void wave_lds_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -84,7 +123,7 @@ __device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work
 // Copy the device tree description into LDS once per block.
 __device__ inline void load_tree(const TreeInfo *__restrict__ src, TreeInfo &dst)
 {
-    const int64_t *s = (const int64_t *)src;
+    const auto *s = as_global((const int64_t *)src);
     int64_t *d = (int64_t *)&dst;
     for (int k = threadIdx.x; k < kTreeWords; k += blockDim.x) d[k] = s[k];
     __syncthreads();
@@ -214,7 +253,7 @@ __device__ WalkResult walk(const TreeInfo &T, const Node *nodes, Test test, Walk
             bool valid = t < total;
             int64_t node = valid ? (int64_t)cur[t >> 3] * 8 + (t & 7) : 0;
             valid = valid && node < nchild;
-            bool pass = valid && test(cl[node]);
+            bool pass = valid && test(load_global(cl + node));
             uint64_t mask = __ballot(pass);
             int pos = nout + (int)__popcll(mask & lt);
             if (pass && pos < kFront) nxt[pos] = (uint32_t)node;
@@ -253,7 +292,7 @@ __device__ int64_t for_each_leaf_group(const TreeInfo &T, const Node *nodes, con
         const int64_t b1 = b0 + span < L ? b0 + span : L;
         for (int64_t b = b0; b < b1; b += kWave) {
             const int64_t c = b + lane;
-            const bool pass = c < b1 && test(nodes[c]);
+            const bool pass = c < b1 && test(load_global(nodes + c));
             const uint64_t mask = __ballot(pass);
             if (pass) wb.tmp[__popcll(mask & lt)] = (uint32_t)c;
             wave_lds_sync();
@@ -345,23 +384,23 @@ __device__ inline void stage_group(Stage<G, PREC> &S, const uint32_t *leaves, in
         const int k = s / G, slot = s % G;
         if (k < count) {
             const uint32_t c = leaves[k];
-            const int64_t j0 = lstart[c];
-            const int jn = (int)(lstart[c + 1] - j0);
+            const int64_t j0 = as_global(lstart)[c];
+            const int jn = (int)(as_global(lstart)[c + 1] - j0);
             if (slot < jn) {
                 const int64_t j = j0 + slot;
-                S.x[s] = x[j];
-                S.y[s] = y[j];
-                S.z[s] = z[j];
-                S.w[s] = w[j];
+                S.x[s] = as_global(x)[j];
+                S.y[s] = as_global(y)[j];
+                S.z[s] = as_global(z)[j];
+                S.w[s] = as_global(w)[j];
                 if (PREC == SPH_FP32_PAIR) {
-                    S.fx[s] = fx[j];
-                    S.fy[s] = fy[j];
-                    S.fz[s] = fz[j];
+                    S.fx[s] = as_global(fx)[j];
+                    S.fy[s] = as_global(fy)[j];
+                    S.fz[s] = as_global(fz)[j];
                 }
                 S.j[s] = (uint32_t)j;
             }
             if (slot == 0) {
-                const Node cand = nodes[c];
+                const Node cand = load_global(nodes + c);
                 // hcov < 0: symmetric force criterion, reach 2 max(h over both leaves)
                 const Shift sh = leaf_shift(home, cand, bx, hcov < 0.0 ? fmax(home.hmax, cand.hmax) : hcov);
                 for (int a = 0; a < 3; a++) {
@@ -568,11 +607,13 @@ __device__ inline int for_my_bits(uint64_t w0, uint64_t w1, int e0, Fn fn)
 // work done for a leaf depends on its own request only, so a set gives the
 // same bits alone and inside any mix.
 // ---------------------------------------------------------------------------
-// Waves per SIMD the pair kernels are built for.  Measured on MI355X: the
-// FP64 loops run fastest at 3 (<= 168 VGPRs), the FP32-pair loops at 2 (the
-// compiler's own register budget); at 4 the FP64 force loop spills heavily.
+// Waves per SIMD the pair kernels are built for (<= 168 VGPRs).  Measured on
+// MI355X: both precisions run fastest at 3; at 2 the latency of the LDS and
+// memory traffic is hidden too poorly.  4 is out of reach as they stand: one
+// wave's LDS (walk frontier and staging, 11.4-12.9 KB) allows at most 3.5 per
+// SIMD, and 128 VGPRs would spill heavily.
 template <int PREC>
-constexpr int pair_waves_per_simd() { return PREC == SPH_FP64 ? 3 : 2; }
+constexpr int pair_waves_per_simd() { return 3; }
 
 template <class Args>
 struct Batch {
@@ -659,16 +700,16 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
     int64_t evals = 0, walks = 0, visits = 0, overflows = 0, nr_total = 0, tests = 0, boxes = 0;
     int iter_max = 0;
     int cur = -1;
-    DensArgs A;
+    const __attribute__((address_space(4))) DensArgs *Ap = nullptr;
     // per-request diagnostics, flushed when the wave moves to another request
     auto flush_counts = [&]() {
         for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
         if (lane == 0 && cur >= 0) {
             auto add = [&](int k, int64_t v) {
-                if (v) atomicAdd((unsigned long long *)&A.counts[k], (unsigned long long)v);
+                if (v) atomicAdd((unsigned long long *)&Ap->counts[k], (unsigned long long)v);
             };
             add(kCntDensEvals, evals);
-            atomicMax((unsigned long long *)&A.counts[kCntNrMax], (unsigned long long)iter_max);
+            atomicMax((unsigned long long *)&Ap->counts[kCntNrMax], (unsigned long long)iter_max);
             add(kCntDensOverflows, overflows);
             add(kCntDensVisits, visits);
             add(kCntDensWalks, walks);
@@ -680,28 +721,34 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
         iter_max = 0;
     };
     for_each_home_leaf(pre[B.nreq], B.work, [&](int64_t gleaf) {
-        const int r = find_req(pre, B.nreq, gleaf);
+        // the request and its argument block are wave-uniform (scalar registers)
+        const int r = __builtin_amdgcn_readfirstlane(find_req(pre, B.nreq, gleaf));
         if (r != cur) {
             flush_counts();
             cur = r;
-            A = *B.req[r];
-            load_tree(A.tree, T);
+            Ap = as_const(B.req[r]);
+            load_tree(Ap->tree, T);
         }
-        const int64_t leaf = gleaf - pre[r];
-        const Box &bx = A.box;
-        const int64_t first = A.lstart[leaf];
-        const int nhome = (int)(A.lstart[leaf + 1] - first);
+        const auto &A = *Ap;
+        const int64_t leaf = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
+        const Box bx = load_const(&B.req[r]->box);
+        const int64_t first = as_const(A.lstart)[leaf];
+        const int nhome = (int)(as_const(A.lstart)[leaf + 1] - first);
         const int64_t i = first + p;
         const bool active = p < nhome;
         const int64_t ii = active ? i : first;
-        const double hx = A.x[ii], hy = A.y[ii], hz = A.z[ii];
+        const double hx = as_global(A.x)[ii], hy = as_global(A.y)[ii], hz = as_global(A.z)[ii];
         float hfx = 0.f, hfy = 0.f, hfz = 0.f;
-        if (PREC == SPH_FP32_PAIR) { hfx = A.fx[ii]; hfy = A.fy[ii]; hfz = A.fz[ii]; }
-        const double mi = A.m[ii];
-        const double mu = A.mrange[0];
-        const bool equal_m = mu == A.mrange[1];
-        const Node home = A.nodes[leaf];
-        double h = A.h[ii];
+        if (PREC == SPH_FP32_PAIR) {
+            hfx = as_global(A.fx)[ii];
+            hfy = as_global(A.fy)[ii];
+            hfz = as_global(A.fz)[ii];
+        }
+        const double mi = as_global(A.m)[ii];
+        const double mu = as_const(A.mrange)[0];
+        const bool equal_m = mu == as_const(A.mrange)[1];
+        const Node home = load_const(A.nodes + leaf);
+        double h = as_global((const double *)A.h)[ii];
         double lo_b = 0.0, hi_b = INFINITY;
         bool conv = !active;
         double h_out = h, rho_out = 0.0, om_out = 1.0;
@@ -939,12 +986,12 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
     const int p = lane / LPP, q = lane % LPP;
     int64_t pairs_total = 0, overflows = 0, tests = 0, boxes = 0;
     int cur = -1;
-    ForceArgs F;
+    const __attribute__((address_space(4))) ForceArgs *Fp = nullptr;
     auto flush_counts = [&]() {
         for (int o = 32; o > 0; o >>= 1) pairs_total += __shfl_xor(pairs_total, o);
         if (lane == 0 && cur >= 0) {
             auto add = [&](int k, int64_t v) {
-                if (v) atomicAdd((unsigned long long *)&F.counts[k], (unsigned long long)v);
+                if (v) atomicAdd((unsigned long long *)&Fp->counts[k], (unsigned long long)v);
             };
             add(kCntForceEvals, pairs_total);
             add(kCntForceOverflows, overflows);
@@ -954,31 +1001,37 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         pairs_total = overflows = tests = boxes = 0;
     };
     for_each_home_leaf(pre[B.nreq], B.work, [&](int64_t gleaf) {
-        const int r = find_req(pre, B.nreq, gleaf);
+        const int r = __builtin_amdgcn_readfirstlane(find_req(pre, B.nreq, gleaf));
         if (r != cur) {
             flush_counts();
             cur = r;
-            F = *B.req[r];
-            load_tree(F.tree, T);
+            Fp = as_const(B.req[r]);
+            load_tree(Fp->tree, T);
         }
-        const int64_t leaf = gleaf - pre[r];
-        const Box &bx = F.box;
+        const auto &F = *Fp;
+        const int64_t leaf = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
+        const Box bx = load_const(&B.req[r]->box);
         const double alpha = F.alpha, beta = F.beta;
-        const int64_t first = F.lstart[leaf];
-        const int nhome = (int)(F.lstart[leaf + 1] - first);
+        const int64_t first = as_const(F.lstart)[leaf];
+        const int nhome = (int)(as_const(F.lstart)[leaf + 1] - first);
         const int64_t i = first + p;
         const bool active = p < nhome;
         const int64_t ii = active ? i : first;
-        const double hx = F.x[ii], hy = F.y[ii], hz = F.z[ii];
+        const double hx = as_global(F.x)[ii], hy = as_global(F.y)[ii], hz = as_global(F.z)[ii];
         float hfx = 0.f, hfy = 0.f, hfz = 0.f;
-        if (PREC == SPH_FP32_PAIR) { hfx = F.fx[ii]; hfy = F.fy[ii]; hfz = F.fz[ii]; }
-        const double vxi = F.vx[ii], vyi = F.vy[ii], vzi = F.vz[ii];
-        const double hi = F.h[ii], hinvi = F.hinv[ii], rhoi = F.rho[ii], Ai = F.A[ii], ci = F.c[ii];
+        if (PREC == SPH_FP32_PAIR) {
+            hfx = as_global(F.fx)[ii];
+            hfy = as_global(F.fy)[ii];
+            hfz = as_global(F.fz)[ii];
+        }
+        const double vxi = as_global(F.vx)[ii], vyi = as_global(F.vy)[ii], vzi = as_global(F.vz)[ii];
+        const double hi = as_global(F.h)[ii], hinvi = as_global(F.hinv)[ii];
+        const double rhoi = as_global(F.rho)[ii], Ai = as_global(F.A)[ii], ci = as_global(F.c)[ii];
         const double hi2x4 = (2.0 * hi) * (2.0 * hi);
         const double gfi = kSigma * (hinvi * hinvi) * (hinvi * hinvi);
         const float hinvif = (float)hinvi;
         const float gfif = (float)kSigma * (hinvif * hinvif) * (hinvif * hinvif);
-        const Node home = F.nodes[leaf];
+        const Node home = load_const(F.nodes + leaf);
         if (q == 0) {
             S.hx[p] = hx;
             S.hy[p] = hy;
@@ -1032,14 +1085,14 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             auto load_j = [&](int sl) {
                 const int64_t j = S.j[sl];
                 JData d;
-                d.c = F.c[j];
-                d.hinv = F.hinv[j];
-                d.vx = F.vx[j];
-                d.vy = F.vy[j];
-                d.vz = F.vz[j];
-                d.m = F.m[j];
-                d.A = F.A[j];
-                d.rho = F.rho[j];
+                d.c = as_global(F.c)[j];
+                d.hinv = as_global(F.hinv)[j];
+                d.vx = as_global(F.vx)[j];
+                d.vy = as_global(F.vy)[j];
+                d.vz = as_global(F.vz)[j];
+                d.m = as_global(F.m)[j];
+                d.A = as_global(F.A)[j];
+                d.rho = as_global(F.rho)[j];
                 return d;
             };
             auto pair_terms = [&](int sl, const JData &d) {
