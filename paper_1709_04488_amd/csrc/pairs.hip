@@ -19,6 +19,7 @@
 #include "sph_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 #define TRY_(expr)                     \
     do {                               \
@@ -211,9 +212,11 @@ __device__ inline void m4(T qq, T &f, T &df)
 // ---------------------------------------------------------------------------
 // Tree walk
 // ---------------------------------------------------------------------------
+// The walk's result stays in `list`; the second frontier buffer a walk needs
+// is lent by the caller (the pair loops lend their staging slots, which hold
+// nothing while a walk runs).
 struct WalkBuf {
-    uint32_t a[kFront];
-    uint32_t b[kFront];
+    uint32_t list[kFront];
     uint32_t tmp[kWave];
 };
 
@@ -229,12 +232,26 @@ struct WalkResult {
     const uint32_t *list;
 };
 
+// Leaves the walk's result in wb.list, copying it there from the spare
+// buffer when the last expansion wrote it there.
+__device__ inline WalkResult walk_result(WalkBuf &wb, const uint32_t *cur, int n, int lev)
+{
+    if (cur != wb.list) {
+        const int lane = threadIdx.x & (kWave - 1);
+        for (int t = lane; t < n; t += kWave) wb.list[t] = cur[t];
+        wave_lds_sync();
+    }
+    return WalkResult{n, lev, wb.list};
+}
+
+// spare: kFront entries of LDS the walk may overwrite
 template <class Test>
-__device__ WalkResult walk(const TreeInfo &T, const Node *nodes, Test test, WalkBuf &wb)
+__device__ WalkResult walk(const TreeInfo &T, const Node *nodes, Test test, WalkBuf &wb,
+                           uint32_t *spare)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t lt = __lanemask_lt();
-    uint32_t *cur = wb.a, *nxt = wb.b;
+    uint32_t *cur = wb.list, *nxt = spare;
     const int top = T.nlev - 1;
     if (lane == 0) cur[0] = 0;
     wave_lds_sync();
@@ -260,14 +277,14 @@ __device__ WalkResult walk(const TreeInfo &T, const Node *nodes, Test test, Walk
             nout += (int)__popcll(mask);
         }
         wave_lds_sync();
-        if (nout > kFront) return WalkResult{ncur, lev, cur};
+        if (nout > kFront) return walk_result(wb, cur, ncur, lev);
         uint32_t *tmp = cur;
         cur = nxt;
         nxt = tmp;
         ncur = nout;
         if (ncur == 0) break;
     }
-    return WalkResult{ncur, 0, cur};
+    return walk_result(wb, cur, ncur, 0);
 }
 
 // Visit the candidate leaves in groups of at most NL: fn(leaves, count) with
@@ -343,12 +360,27 @@ __device__ inline Shift leaf_shift(const Node &home, const Node &cand, const Box
 constexpr int kSlots = 2 * kWave;   // candidate slots per staged group
 constexpr int kTestsPerLane = 4;    // candidate tests per lane per combination
 
+// Per-slot candidate data: FP64 positions, or in FP32-pair mode the
+// single-precision offsets from the leaf centres; w is the mass (density) or
+// h (forces).
+struct SlotsFP64 {
+    double x[kSlots], y[kSlots], z[kSlots], w[kSlots];
+};
+struct SlotsFP32 {
+    double w[kSlots];
+    float fx[kSlots], fy[kSlots], fz[kSlots];
+};
+static_assert(sizeof(SlotsFP32) >= kFront * sizeof(uint32_t) &&
+                  sizeof(SlotsFP64) >= kFront * sizeof(uint32_t),
+              "the staging slots double as the walk's spare frontier buffer");
+
 template <int G, int PREC>
 struct Stage {
     static constexpr int NL = kSlots / G;
-    static constexpr int NF = PREC == SPH_FP32_PAIR ? kSlots : 1;
-    double x[kSlots], y[kSlots], z[kSlots], w[kSlots];   // w: mass (density) or h (forces)
-    float fx[NF], fy[NF], fz[NF];
+    union {
+        std::conditional_t<PREC == SPH_FP64, SlotsFP64, SlotsFP32> c;
+        uint32_t walk_spare[kFront];   // lent to walks, which run between groups
+    };
     uint32_t j[kSlots];
     // per staged leaf
     double lo[NL][3], hi[NL][3];
@@ -388,14 +420,15 @@ __device__ inline void stage_group(Stage<G, PREC> &S, const uint32_t *leaves, in
             const int jn = (int)(as_global(lstart)[c + 1] - j0);
             if (slot < jn) {
                 const int64_t j = j0 + slot;
-                S.x[s] = as_global(x)[j];
-                S.y[s] = as_global(y)[j];
-                S.z[s] = as_global(z)[j];
-                S.w[s] = as_global(w)[j];
-                if (PREC == SPH_FP32_PAIR) {
-                    S.fx[s] = as_global(fx)[j];
-                    S.fy[s] = as_global(fy)[j];
-                    S.fz[s] = as_global(fz)[j];
+                S.c.w[s] = as_global(w)[j];
+                if constexpr (PREC == SPH_FP64) {
+                    S.c.x[s] = as_global(x)[j];
+                    S.c.y[s] = as_global(y)[j];
+                    S.c.z[s] = as_global(z)[j];
+                } else {
+                    S.c.fx[s] = as_global(fx)[j];
+                    S.c.fy[s] = as_global(fy)[j];
+                    S.c.fz[s] = as_global(fz)[j];
                 }
                 S.j[s] = (uint32_t)j;
             }
@@ -437,10 +470,10 @@ __device__ inline void separation(const Stage<G, PREC> &S, const Box &bx, double
                                   double &dy, double &dz, double &r2)
 {
     const int k = s / G;
-    if (PREC == SPH_FP64) {
-        dx = hx - S.x[s];
-        dy = hy - S.y[s];
-        dz = hz - S.z[s];
+    if constexpr (PREC == SPH_FP64) {
+        dx = hx - S.c.x[s];
+        dy = hy - S.c.y[s];
+        dz = hz - S.c.z[s];
         if (S.per_pair[k]) {
             dx = min_image(dx, bx.len[0], bx.half[0]);
             dy = min_image(dy, bx.len[1], bx.half[1]);
@@ -452,9 +485,9 @@ __device__ inline void separation(const Stage<G, PREC> &S, const Box &bx, double
         }
         r2 = exact_r2(dx, dy, dz);
     } else {
-        float fdx = (hfx - S.fx[s]) + S.ox[k];
-        float fdy = (hfy - S.fy[s]) + S.oy[k];
-        float fdz = (hfz - S.fz[s]) + S.oz[k];
+        float fdx = (hfx - S.c.fx[s]) + S.ox[k];
+        float fdy = (hfy - S.c.fy[s]) + S.oy[k];
+        float fdz = (hfz - S.c.fz[s]) + S.oz[k];
         if (S.per_pair[k]) {
             fdx = min_image_f(fdx, (float)bx.len[0], (float)bx.half[0]);
             fdy = min_image_f(fdy, (float)bx.len[1], (float)bx.half[1]);
@@ -607,13 +640,12 @@ __device__ inline int for_my_bits(uint64_t w0, uint64_t w1, int e0, Fn fn)
 // work done for a leaf depends on its own request only, so a set gives the
 // same bits alone and inside any mix.
 // ---------------------------------------------------------------------------
-// Waves per SIMD the pair kernels are built for (<= 168 VGPRs).  Measured on
-// MI355X: both precisions run fastest at 3; at 2 the latency of the LDS and
-// memory traffic is hidden too poorly.  4 is out of reach as they stand: one
-// wave's LDS (walk frontier and staging, 11.4-12.9 KB) allows at most 3.5 per
-// SIMD, and 128 VGPRs would spill heavily.
+// Waves per SIMD the pair kernels are built for (<= 128 VGPRs, <= 10 KB of
+// LDS per wave).  Measured on MI355X: occupancy decides these latency-bound
+// loops; each step from 2 to 4 waves per SIMD pays for the register spills it
+// costs.
 template <int PREC>
-constexpr int pair_waves_per_simd() { return 3; }
+constexpr int pair_waves_per_simd() { return 4; }
 
 template <class Args>
 struct Batch {
@@ -770,7 +802,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             const double R2 = R * R;
             return [&bx, &home, R2](const Node &nd) { return box_gap2(home.lo, home.hi, nd, bx) < R2; };
         };
-        WalkResult wr = walk(T, A.nodes, make_test(hcov), wb);
+        WalkResult wr = walk(T, A.nodes, make_test(hcov), wb, S.walk_spare);
         walks++;
         if (wr.lev) overflows++;
         int iter = 0;
@@ -842,7 +874,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                         double dx, dy, dz, r2;
                         separation<G, PREC>(S, bx, hx, hy, hz, hfx, hfy, hfz, sl, dx, dy, dz, r2);
                         const bool self = S.j[sl] == (uint32_t)i;
-                        const double mw = self ? -S.w[sl] : S.w[sl];
+                        const double mw = self ? -S.c.w[sl] : S.c.w[sl];
                         const double rw = self ? -r2 : r2;
                         if (pos < KP) {
                             const int at = (pos / LPP) * kWave + lane;
@@ -920,7 +952,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             const double hmx = wave_max(conv ? 0.0 : h);
             if (hmx > hcov) {
                 hcov = A.walk_margin * hmx;
-                wr = walk(T, A.nodes, make_test(hcov), wb);
+                wr = walk(T, A.nodes, make_test(hcov), wb, S.walk_spare);
                 walks++;
                 if (wr.lev) overflows++;
             }
@@ -1049,7 +1081,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             const double R = 2.0 * fmax(home.hmax, nd.hmax) * (1.0 + 1e-10);
             return box_gap2(home.lo, home.hi, nd, bx) < R * R;
         };
-        const WalkResult wr = walk(T, F.nodes, test, wb);
+        const WalkResult wr = walk(T, F.nodes, test, wb, S.walk_spare);
         if (wr.lev) overflows++;
 
         double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
@@ -1069,7 +1101,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     separation<G, PREC>(S, bx, S.hx[pp], S.hy[pp], S.hz[pp], S.hfx[pp], S.hfy[pp],
                                         S.hfz[pp], sl, dx, dy, dz, r2);
                     const double thr = S.thr[pp];
-                    const double hj = S.w[sl];
+                    const double hj = S.c.w[sl];
                     const double hj2x4 = (2.0 * hj) * (2.0 * hj);
                     bool in;
                     if (PREC == SPH_FP64) in = r2 < thr || r2 < hj2x4;
@@ -1241,6 +1273,7 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
     constexpr int LPP = kWave / G;
     constexpr int PER = G / LPP;
     __shared__ WalkBuf wb;
+    __shared__ uint32_t spare[kFront];
     __shared__ TreeInfo T;
     load_tree(N.tree, T);
     const int lane = threadIdx.x;
@@ -1262,7 +1295,7 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
             const double R = 2.0 * hh * (1.0 + 1e-10);
             return box_gap2(home.lo, home.hi, nd, bx) < R * R;
         };
-        const WalkResult wr = walk(T, N.nodes, test, wb);
+        const WalkResult wr = walk(T, N.nodes, test, wb, spare);
         if (wr.lev) overflows++;
         // two sweeps in pass 2: count this lane's hits, then write them
         int64_t mine = 0, base = 0;

@@ -24,11 +24,11 @@ constexpr int kMaxBatch = 128;   // particle sets per batched pair-kernel launch
 constexpr int kArgBytes = 1024;  // device argument block of one pair-kernel launch
 
 // Persistent pair-kernel grid: one wave per block, at most as many blocks as
-// the GPU holds at once (256 CUs x 12 waves: the pair kernels run at 3 waves
-// per SIMD or fewer), at least one block per 8 particles below that, a
+// the GPU holds at once (256 CUs x 16 waves: the pair kernels run at 4 waves
+// per SIMD), at least one block per 8 particles below that, a
 // multiple of the XCD count.  Each block owns a slice of the density loop's
 // candidate-list scratch, so the cap also bounds that scratch.
-constexpr int64_t kMaxPairBlocks = 256 * 12;
+constexpr int64_t kMaxPairBlocks = 256 * 16;
 inline unsigned pair_grid(int64_t n)
 {
     int64_t blocks = (n + 7) / 8;
