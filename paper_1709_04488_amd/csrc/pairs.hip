@@ -398,8 +398,9 @@ struct Stage {
 };
 
 // Stage `count` (<= NL) candidate leaves; lane l fills slots l and l + 64,
-// slot s holding particle s % G of staged leaf s / G.
-template <int G, int PREC>
+// slot s holding particle s % G of staged leaf s / G.  REACH2: w holds h and
+// the slot keeps the squared gather reach (2h)^2 instead.
+template <int G, int PREC, bool REACH2 = false>
 __device__ inline void stage_group(Stage<G, PREC> &S, const uint32_t *leaves, int count,
                                    const uint32_t *__restrict__ lstart, const Node *__restrict__ nodes,
                                    const Node &home, const Box &bx, double hcov,
@@ -420,7 +421,8 @@ __device__ inline void stage_group(Stage<G, PREC> &S, const uint32_t *leaves, in
             const int jn = (int)(as_global(lstart)[c + 1] - j0);
             if (slot < jn) {
                 const int64_t j = j0 + slot;
-                S.c.w[s] = as_global(w)[j];
+                const double wv = as_global(w)[j];
+                S.c.w[s] = REACH2 ? (2.0 * wv) * (2.0 * wv) : wv;
                 if constexpr (PREC == SPH_FP64) {
                     S.c.x[s] = as_global(x)[j];
                     S.c.y[s] = as_global(y)[j];
@@ -1085,10 +1087,10 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         if (wr.lev) overflows++;
 
         double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
-        int cnt = 0;
+        int cnt = 0, selfs = 0;
         auto group = [&](const uint32_t *leaves, int ng) {
-            stage_group<G, PREC>(S, leaves, ng, F.lstart, F.nodes, home, bx, -1.0, F.x, F.y, F.z, F.h,
-                                 F.fx, F.fy, F.fz);
+            stage_group<G, PREC, true>(S, leaves, ng, F.lstart, F.nodes, home, bx, -1.0, F.x, F.y, F.z,
+                                       F.h, F.fx, F.fy, F.fz);
             group_tests<G, PREC>(
                 S, ng,
                 [&](int pp, int k) {
@@ -1100,13 +1102,11 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     double dx, dy, dz, r2;
                     separation<G, PREC>(S, bx, S.hx[pp], S.hy[pp], S.hz[pp], S.hfx[pp], S.hfy[pp],
                                         S.hfz[pp], sl, dx, dy, dz, r2);
+                    // the particle itself passes too; the flush drops it
                     const double thr = S.thr[pp];
-                    const double hj = S.c.w[sl];
-                    const double hj2x4 = (2.0 * hj) * (2.0 * hj);
-                    bool in;
-                    if (PREC == SPH_FP64) in = r2 < thr || r2 < hj2x4;
-                    else in = (float)r2 < (float)thr || (float)r2 < (float)hj2x4;
-                    return in && S.j[sl] != (uint32_t)(first + pp);
+                    const double hj2x4 = S.c.w[sl];
+                    if (PREC == SPH_FP64) return r2 < thr || r2 < hj2x4;
+                    return (float)r2 < (float)thr || (float)r2 < (float)hj2x4;
                 },
                 F.count_tests != 0, boxes, tests);
             const uint64_t w0 = S.mask[p][0], w1 = S.mask[p][1];
@@ -1200,16 +1200,23 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             // FP32-pair: two at a time, both neighbours' records requested
             // before either is used (measured faster; at the FP64 register
             // budget the second record costs more than it hides)
+            // the particle itself is among the hits of its own leaf: it takes
+            // no pair terms and is not counted
+            const uint32_t self = (uint32_t)i;
             if (PREC == SPH_FP32_PAIR) {
                 cnt += for_my_bit_pairs<LPP>(w0, w1, q, [&](int sa, int sb) {
                     const JData da = load_j(sa);
                     JData db = da;
                     if (sb >= 0) db = load_j(sb);
-                    pair_terms(sa, da);
-                    if (sb >= 0) pair_terms(sb, db);
+                    if (S.j[sa] != self) pair_terms(sa, da); else selfs++;
+                    if (sb >= 0) {
+                        if (S.j[sb] != self) pair_terms(sb, db); else selfs++;
+                    }
                 });
             } else {
-                cnt += for_my_bits<LPP>(w0, w1, q, [&](int sl, int) { pair_terms(sl, load_j(sl)); });
+                cnt += for_my_bits<LPP>(w0, w1, q, [&](int sl, int) {
+                    if (S.j[sl] != self) pair_terms(sl, load_j(sl)); else selfs++;
+                });
             }
             if (q == 0) {
                 S.mask[p][0] = 0;
@@ -1225,7 +1232,9 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             azi += __shfl_xor(azi, o);
             dui += __shfl_xor(dui, o);
             vs_max = fmax(vs_max, __shfl_xor(vs_max, o));
+            selfs += __shfl_xor(selfs, o);
         }
+        cnt -= selfs;
         if (active && q == 0) {
             const double vsig = cnt > 0 ? vs_max : 2.0 * ci;
             F.ax[i] = axi;
