@@ -466,7 +466,9 @@ __device__ inline void stage_group(Stage<G, PREC> &S, const uint32_t *leaves, in
 
 // Separation x_i - x_j of a home particle (given by value) and staged slot s;
 // the same expression serves every test and flush, so they see identical bits.
-template <int G, int PREC>
+// PP = false: no staged leaf needs the pair-by-pair minimum image (the
+// caller has checked), which drops that branch.
+template <int G, int PREC, bool PP = true>
 __device__ inline void separation(const Stage<G, PREC> &S, const Box &bx, double hx, double hy,
                                   double hz, float hfx, float hfy, float hfz, int s, double &dx,
                                   double &dy, double &dz, double &r2)
@@ -476,7 +478,7 @@ __device__ inline void separation(const Stage<G, PREC> &S, const Box &bx, double
         dx = hx - S.c.x[s];
         dy = hy - S.c.y[s];
         dz = hz - S.c.z[s];
-        if (S.per_pair[k]) {
+        if (PP && S.per_pair[k]) {
             dx = min_image(dx, bx.len[0], bx.half[0]);
             dy = min_image(dy, bx.len[1], bx.half[1]);
             dz = min_image(dz, bx.len[2], bx.half[2]);
@@ -490,7 +492,7 @@ __device__ inline void separation(const Stage<G, PREC> &S, const Box &bx, double
         float fdx = (hfx - S.c.fx[s]) + S.ox[k];
         float fdy = (hfy - S.c.fy[s]) + S.oy[k];
         float fdz = (hfz - S.c.fz[s]) + S.oz[k];
-        if (S.per_pair[k]) {
+        if (PP && S.per_pair[k]) {
             fdx = min_image_f(fdx, (float)bx.len[0], (float)bx.half[0]);
             fdy = min_image_f(fdy, (float)bx.len[1], (float)bx.half[1]);
             fdz = min_image_f(fdz, (float)bx.len[2], (float)bx.half[2]);
@@ -507,16 +509,15 @@ __device__ inline void separation(const Stage<G, PREC> &S, const Box &bx, double
 template <int G, int PREC>
 __device__ inline double box_dist2(const Stage<G, PREC> &S, int p, int k)
 {
-    if (S.per_pair[k]) return 0.0;
     const double c[3] = {S.hx[p] + S.sx[k], S.hy[p] + S.sy[k], S.hz[p] + S.sz[k]};
     double d2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const double lo = S.lo[k][a], hi = S.hi[k][a];
-        const double d = c[a] < lo ? lo - c[a] : (c[a] > hi ? c[a] - hi : 0.0);
+        // the gap below lo or above hi, 0 inside (at most one is positive)
+        const double d = fmax(fmax(S.lo[k][a] - c[a], c[a] - S.hi[k][a]), 0.0);
         d2 += d * d;
     }
-    return d2;
+    return S.per_pair[k] ? 0.0 : d2;
 }
 
 // The relative slack of the box test: it must accept every combination whose
@@ -525,8 +526,10 @@ __device__ inline double box_dist2(const Stage<G, PREC> &S, int p, int k)
 template <int PREC>
 __device__ constexpr double box_slack() { return PREC == SPH_FP64 ? 1.0 + 1e-6 : 1.0 + 1e-4; }
 
-// Hit masks of one staged group: bit s of S.mask[p] set iff rec(p, s), with
-// rec evaluated only where relevant(p, k) holds for the slot's leaf k.
+// Hit masks of one staged group: bit s of S.mask[p] set iff rec(p, s, pp), with
+// rec evaluated only where relevant(p, k) holds for the slot's leaf k; pp is
+// std::true_type when some staged leaf needs the pair-by-pair minimum image,
+// std::false_type otherwise (for separation's PP parameter).
 template <int G, int PREC, class Relevant, class Record>
 __device__ inline void group_tests(Stage<G, PREC> &S, int count, Relevant relevant, Record rec,
                                    bool diag, int64_t &boxes, int64_t &tests)
@@ -566,38 +569,52 @@ __device__ inline void group_tests(Stage<G, PREC> &S, int count, Relevant releva
     // combinations of one round start their tests at different slots, which
     // spreads their LDS reads over the banks
     const int rot = lane / LPC;
-    for (int b = 0; b < C; b += CPR) {
-        const int idx = b + lane / LPC;
-        if (idx < C) {
-            const int c = S.combo[idx];
-            const int p = c / NL, k = c % NL;
-            const int jn = S.jn[k];
-            uint64_t bits = 0;
+    // every test runs (slots past the leaf's end read stale but in-bounds
+    // LDS) and its slot predicate masks the result: no branch per test
+    auto rounds = [&](auto pp_possible) {
+        for (int b = 0; b < C; b += CPR) {
+            const int idx = b + lane / LPC;
+            if (idx < C) {
+                const int c = S.combo[idx];
+                const int p = c / NL, k = c % NL;
+                const int jn = S.jn[k];
+                uint64_t bits = 0;
 #pragma unroll
-            for (int t = 0; t < kTestsPerLane; t++) {
-                const int slot = u + LPC * ((t + rot) % kTestsPerLane);
-                if (slot < jn) {
+                for (int t = 0; t < kTestsPerLane; t++) {
+                    const int slot = u + LPC * ((t + rot) % kTestsPerLane);
                     const int s = k * G + slot;
-                    if (rec(p, s)) bits |= 1ull << (s & 63);
+                    const bool hit = (slot < jn) & rec(p, s, pp_possible);
+                    bits |= (uint64_t)hit << (s & 63);
                 }
+                if (bits)
+                    atomicOr((unsigned long long *)&S.mask[p][(k * G) >> 6], (unsigned long long)bits);
             }
-            if (bits)
-                atomicOr((unsigned long long *)&S.mask[p][(k * G) >> 6], (unsigned long long)bits);
         }
-    }
+    };
+    if (__ballot(lane < count && S.per_pair[lane < NL ? lane : 0]) != 0ull)
+        rounds(std::true_type{});
+    else
+        rounds(std::false_type{});
     wave_lds_sync();
 }
 
 // As for_my_bits, but this lane's bits two at a time: fn(sa, sb) with sb < 0
 // when sa is its last, so the caller can issue both pairs' loads before
 // using either.
+// Clear the lowest set bit of the 128-bit mask (w0, w1), without a branch.
+__device__ inline void pop_low(uint64_t &w0, uint64_t &w1)
+{
+    const bool lo = w0 != 0;
+    const uint64_t a = w0 & (w0 - 1), b = w1 & (w1 - 1);
+    w0 = lo ? a : w0;
+    w1 = lo ? w1 : b;
+}
+
 template <int LPP, class Fn>
 __device__ inline int for_my_bit_pairs(uint64_t w0, uint64_t w1, int e0, Fn fn)
 {
     const int n = (int)__popcll(w0) + (int)__popcll(w1);
-    auto pop = [&]() {
-        if (w0) w0 &= w0 - 1; else w1 &= w1 - 1;
-    };
+    auto pop = [&]() { pop_low(w0, w1); };
     auto low = [&]() { return w0 ? (int)__builtin_ctzll(w0) : 64 + (int)__builtin_ctzll(w1); };
     for (int t = 0; t < e0; t++) pop();
     for (int e = e0; e < n; e += 2 * LPP) {
@@ -621,15 +638,12 @@ template <int LPP, class Fn>
 __device__ inline int for_my_bits(uint64_t w0, uint64_t w1, int e0, Fn fn)
 {
     const int n = (int)__popcll(w0) + (int)__popcll(w1);
-    for (int t = 0; t < e0; t++) {
-        if (w0) w0 &= w0 - 1; else w1 &= w1 - 1;
-    }
+    for (int t = 0; t < e0; t++) pop_low(w0, w1);
     for (int e = e0; e < n; e += LPP) {
         const int s = w0 ? (int)__builtin_ctzll(w0) : 64 + (int)__builtin_ctzll(w1);
         fn(s, e);
-        for (int t = 0; t < LPP; t++) {
-            if (w0) w0 &= w0 - 1; else w1 &= w1 - 1;
-        }
+#pragma unroll
+        for (int t = 0; t < LPP; t++) pop_low(w0, w1);
     }
     return n;
 }
@@ -861,10 +875,11 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                             const double thr = S.thr[pp];
                             return thr >= 0.0 && box_dist2(S, pp, k) <= thr * box_slack<PREC>();
                         },
-                        [&](int pp, int sl) {
+                        [&](int pp, int sl, auto ppc) {
                             double dx, dy, dz, r2;
-                            separation<G, PREC>(S, bx, S.hx[pp], S.hy[pp], S.hz[pp], S.hfx[pp],
-                                                S.hfy[pp], S.hfz[pp], sl, dx, dy, dz, r2);
+                            separation<G, PREC, decltype(ppc)::value>(
+                                S, bx, S.hx[pp], S.hy[pp], S.hz[pp], S.hfx[pp], S.hfy[pp], S.hfz[pp],
+                                sl, dx, dy, dz, r2);
                             return r2 < S.thr[pp];
                         },
                         A.count_tests != 0, boxes, tests);
@@ -1098,10 +1113,11 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const double hk = 2.0 * S.hmax[k];
                     return thr >= 0.0 && box_dist2(S, pp, k) <= fmax(thr, hk * hk) * box_slack<PREC>();
                 },
-                [&](int pp, int sl) {
+                [&](int pp, int sl, auto ppc) {
                     double dx, dy, dz, r2;
-                    separation<G, PREC>(S, bx, S.hx[pp], S.hy[pp], S.hz[pp], S.hfx[pp], S.hfy[pp],
-                                        S.hfz[pp], sl, dx, dy, dz, r2);
+                    separation<G, PREC, decltype(ppc)::value>(S, bx, S.hx[pp], S.hy[pp], S.hz[pp],
+                                                              S.hfx[pp], S.hfy[pp], S.hfz[pp], sl, dx,
+                                                              dy, dz, r2);
                     // the particle itself passes too; the flush drops it
                     const double thr = S.thr[pp];
                     const double hj2x4 = S.c.w[sl];
