@@ -504,6 +504,27 @@ __device__ inline void separation(const Stage<G, PREC> &S, const Box &bx, double
     }
 }
 
+// r_ij^2 for a superset filter (the caller's threshold carries a relative
+// slack far above rounding): in FP64 without pair-by-pair images the leaf's
+// shift joins the home position first, which the compiler shares between the
+// tests of one (particle, leaf) combination; otherwise the exact separation.
+template <int G, int PREC, bool PP>
+__device__ inline double filter_r2(const Stage<G, PREC> &S, const Box &bx, int p, int s)
+{
+    if constexpr (PREC == SPH_FP64 && !PP) {
+        const int k = s / G;
+        const double dx = (S.hx[p] + S.sx[k]) - S.c.x[s];
+        const double dy = (S.hy[p] + S.sy[k]) - S.c.y[s];
+        const double dz = (S.hz[p] + S.sz[k]) - S.c.z[s];
+        return dx * dx + dy * dy + dz * dz;
+    } else {
+        double dx, dy, dz, r2;
+        separation<G, PREC, PP>(S, bx, S.hx[p], S.hy[p], S.hz[p], S.hfx[p], S.hfy[p], S.hfz[p], s,
+                                dx, dy, dz, r2);
+        return r2;
+    }
+}
+
 // Squared distance from home particle p to staged leaf k's box in the frame of
 // the separation; 0 for a per-pair leaf (every candidate is then tested).
 template <int G, int PREC>
@@ -531,7 +552,7 @@ __device__ constexpr double box_slack() { return PREC == SPH_FP64 ? 1.0 + 1e-6 :
 // std::true_type when some staged leaf needs the pair-by-pair minimum image,
 // std::false_type otherwise (for separation's PP parameter).
 template <int G, int PREC, class Relevant, class Record>
-__device__ inline void group_tests(Stage<G, PREC> &S, int count, Relevant relevant, Record rec,
+__device__ inline bool group_tests(Stage<G, PREC> &S, int count, Relevant relevant, Record rec,
                                    bool diag, int64_t &boxes, int64_t &tests)
 {
     constexpr int NL = Stage<G, PREC>::NL;
@@ -591,11 +612,13 @@ __device__ inline void group_tests(Stage<G, PREC> &S, int count, Relevant releva
             }
         }
     };
-    if (__ballot(lane < count && S.per_pair[lane < NL ? lane : 0]) != 0ull)
+    const bool any_pp = __ballot(lane < count && S.per_pair[lane < NL ? lane : 0]) != 0ull;
+    if (any_pp)
         rounds(std::true_type{});
     else
         rounds(std::false_type{});
     wave_lds_sync();
+    return any_pp;
 }
 
 // As for_my_bits, but this lane's bits two at a time: fn(sa, sb) with sb < 0
@@ -834,10 +857,12 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             const double h2x4 = (2.0 * h) * (2.0 * h);
             const float h2x4f = (float)h2x4;
             // pair terms of one list entry (r^2 and the mark of the particle itself)
+            // Branch-free: an entry outside 2h adds 0 * f (+0 or -0, which leave
+            // the sums' bits unchanged) and no count; the lanes of a wave almost
+            // never agree on skipping, so a branch would save no work.
             auto accumulate = [&](double r2, double mw) {
                 const bool in = PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f;
-                if (!in) return;
-                const double mj = equal_m ? mu : fabs(mw);
+                const double mj = in ? (equal_m ? mu : fabs(mw)) : 0.0;
                 const double ra2 = fabs(r2);
                 if (PREC == SPH_FP64) {
                     double f, df;
@@ -852,7 +877,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                     s0 += mj * (double)f;
                     s2 += mj * (double)(qq * df);
                 }
-                cnt += signbit(equal_m ? r2 : mw) ? 0 : 1;
+                cnt += (in && !signbit(equal_m ? r2 : mw)) ? 1 : 0;
             };
             if (__ballot(!conv && !cached) != 0ull) {
                 // sweep: every particle still iterating takes its pair terms from
@@ -869,37 +894,37 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 auto group = [&](const uint32_t *leaves, int ng) {
                     stage_group<G, PREC>(S, leaves, ng, A.lstart, A.nodes, home, bx, hcov, A.x, A.y,
                                          A.z, A.m, A.fx, A.fy, A.fz);
-                    group_tests<G, PREC>(
+                    const bool any_pp = group_tests<G, PREC>(
                         S, ng,
                         [&](int pp, int k) {
                             const double thr = S.thr[pp];
                             return thr >= 0.0 && box_dist2(S, pp, k) <= thr * box_slack<PREC>();
                         },
                         [&](int pp, int sl, auto ppc) {
-                            double dx, dy, dz, r2;
-                            separation<G, PREC, decltype(ppc)::value>(
-                                S, bx, S.hx[pp], S.hy[pp], S.hz[pp], S.hfx[pp], S.hfy[pp], S.hfz[pp],
-                                sl, dx, dy, dz, r2);
-                            return r2 < S.thr[pp];
+                            return filter_r2<G, PREC, decltype(ppc)::value>(S, bx, pp, sl) < S.thr[pp];
                         },
                         A.count_tests != 0, boxes, tests);
                     const uint64_t w0 = S.mask[p][0], w1 = S.mask[p][1];
                     // list position base + e belongs to lane (base + e) % LPP
                     const int e0 = (q - base % LPP + LPP) % LPP;
-                    const int n = for_my_bits<LPP>(w0, w1, e0, [&](int sl, int e) {
-                        const int pos = base + e;
-                        double dx, dy, dz, r2;
-                        separation<G, PREC>(S, bx, hx, hy, hz, hfx, hfy, hfz, sl, dx, dy, dz, r2);
-                        const bool self = S.j[sl] == (uint32_t)i;
-                        const double mw = self ? -S.c.w[sl] : S.c.w[sl];
-                        const double rw = self ? -r2 : r2;
-                        if (pos < KP) {
-                            const int at = (pos / LPP) * kWave + lane;
-                            cr2[at] = equal_m ? rw : r2;
-                            if (!equal_m) cm[at] = mw;
-                        }
-                        accumulate(equal_m ? rw : r2, mw);
-                    });
+                    auto flush = [&](auto ppc) {
+                        return for_my_bits<LPP>(w0, w1, e0, [&](int sl, int e) {
+                            const int pos = base + e;
+                            double dx, dy, dz, r2;
+                            separation<G, PREC, decltype(ppc)::value>(S, bx, hx, hy, hz, hfx, hfy, hfz,
+                                                                      sl, dx, dy, dz, r2);
+                            const bool self = S.j[sl] == (uint32_t)i;
+                            const double mw = self ? -S.c.w[sl] : S.c.w[sl];
+                            const double rw = self ? -r2 : r2;
+                            if (pos < KP) {
+                                const int at = (pos / LPP) * kWave + lane;
+                                cr2[at] = equal_m ? rw : r2;
+                                if (!equal_m) cm[at] = mw;
+                            }
+                            accumulate(equal_m ? rw : r2, mw);
+                        });
+                    };
+                    const int n = any_pp ? flush(std::true_type{}) : flush(std::false_type{});
                     base += n;
                     if (q == 0) {
                         S.mask[p][0] = 0;
@@ -913,12 +938,14 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             } else {
                 // every particle still iterating has a complete list and h <= Rc:
                 // the entries inside 2h, in list order, are the hits of a sweep
+                // (rows <= ROWS: a cached list has at most KP entries.)  Rows past
+                // this lane's entries pass r^2 = (2h)^2, which adds nothing
                 const int rows = wave_max_int(conv ? 0 : (count + LPP - 1) / LPP);
                 for (int rr = 0; rr < rows; rr++) {
-                    if (!conv && rr * LPP + q < count) {
-                        const double r2 = cr2[rr * kWave + lane];
-                        accumulate(r2, equal_m ? 0.0 : cm[rr * kWave + lane]);
-                    }
+                    const bool mine = !conv && rr * LPP + q < count;
+                    const double r2 = cr2[rr * kWave + lane];
+                    const double mw = equal_m ? 0.0 : cm[rr * kWave + lane];
+                    accumulate(mine ? r2 : h2x4, mw);
                 }
             }
             if (!conv) evals += cnt;
