@@ -31,7 +31,8 @@ int64_t bytes_per_particle(const sph_params &p)
 {
     int64_t b = 0;
     b += 2 * 8 + 2 * 4;        // sort keys / values, ping-pong
-    b += 20 * 8 + 2 * 4 + 4;   // s: doubles, nngb/nforce, id
+    b += 17 * 8 + 2 * 4 + 4;   // s: doubles, nngb/nforce, id
+    b += (int64_t)sizeof(ForceRec);   // s: force records
     b += 4 * 8;                // s: predictor arrays
     b += 3 * 4;                // s: fp32 offsets
     b += 13 * 8 + 4;           // t: re-sort buffers
@@ -176,11 +177,12 @@ sph_status ensure_capacity(sph_ctx *c, int64_t n)
     A_(c->keys[0], cap); A_(c->keys[1], cap);
     A_(c->vals[0], cap); A_(c->vals[1], cap);
     double **sd[] = {&S.x, &S.y, &S.z, &S.vx, &S.vy, &S.vz, &S.m, &S.u, &S.h, &S.rho, &S.omega,
-                     &S.A, &S.c, &S.hinv, &S.ax, &S.ay, &S.az, &S.du, &S.vsig, &S.dt,
+                     &S.ax, &S.ay, &S.az, &S.du, &S.vsig, &S.dt,
                      &S.vpx, &S.vpy, &S.vpz, &S.up,
                      &T.x, &T.y, &T.z, &T.vx, &T.vy, &T.vz, &T.m, &T.u, &T.h,
                      &T.vpx, &T.vpy, &T.vpz, &T.up};
     for (double **pp : sd) A_(*pp, cap);
+    A_(S.frec, cap);
     A_(S.nngb, cap); A_(S.nforce, cap);
     A_(S.id, cap); A_(T.id, cap);
     A_(S.fx, cap); A_(S.fy, cap); A_(S.fz, cap);
@@ -348,8 +350,8 @@ sph_status forces_pre(sph_ctx *c, const sph_particles *ps)
     TRY(gather(c, n, g, false));
     TRY(build_tree(c, n));
     timer_end(c, 2, e0, e1);
-    TRY(force_prep(c, n, c->s.u));
-    return forces_prepare(c, n, c->s.vx, c->s.vy, c->s.vz);
+    TRY(force_prep(c, n, c->s.u, c->s.vx, c->s.vy, c->s.vz));
+    return forces_prepare(c, n);
 }
 
 sph_status forces_post(sph_ctx *c, const sph_particles *ps)
@@ -405,8 +407,8 @@ sph_status step_mid(sph_ctx *c)
     const int64_t n = c->n;
     // the force walk needs the boxes' largest h after the h solve
     TRY(refresh_hmax(c, n));
-    TRY(force_prep(c, n, c->s.up));
-    return forces_prepare(c, n, c->s.vpx, c->s.vpy, c->s.vpz);
+    TRY(force_prep(c, n, c->s.up, c->s.vpx, c->s.vpy, c->s.vpz));
+    return forces_prepare(c, n);
 }
 
 sph_status step_post(sph_ctx *c, double dt, double *dt_used)
@@ -654,8 +656,8 @@ sph_status sph_upload_state(sph_ctx *c, const sph_particles *ps)
     TRY(build_tree(c, n));
     TRY(run_density(c, n));
     TRY(refresh_hmax(c, n));
-    TRY(force_prep(c, n, c->s.u));
-    TRY(run_forces(c, n, c->s.vx, c->s.vy, c->s.vz));
+    TRY(force_prep(c, n, c->s.u, c->s.vx, c->s.vy, c->s.vz));
+    TRY(run_forces(c, n));
     TRY(reduce_dt(c, n));
     TRY(hip_check(c, hipMemsetAsync(c->d_scal + 1, 0, sizeof(double) * 2, c->stream), "reset time"));
     TRY(reduce_diag(c, n));

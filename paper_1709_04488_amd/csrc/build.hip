@@ -581,22 +581,34 @@ __global__ __launch_bounds__(256) void k_offsets(int64_t n, const uint32_t *__re
     fz[k] = (float)(z[k] - 0.5 * (nd.lo[2] + nd.hi[2]));
 }
 
-// A_i = P_i / (Omega_i rho_i^2), c_i = sqrt(gamma P_i / rho_i), 1/h_i with
-// P_i = (gamma - 1) rho_i u_i.
+// Force record of particle k: A_k = P_k / (Omega_k rho_k^2),
+// c_k = sqrt(gamma P_k / rho_k), 1/h_k, v_k, m_k, rho_k with
+// P_k = (gamma - 1) rho_k u_k.
 __global__ __launch_bounds__(256) void k_force_prep(int64_t n, double gamma,
                                                     const double *__restrict__ rho,
                                                     const double *__restrict__ omega,
                                                     const double *__restrict__ u,
                                                     const double *__restrict__ h,
-                                                    double *__restrict__ A, double *__restrict__ c,
-                                                    double *__restrict__ hinv)
+                                                    const double *__restrict__ m,
+                                                    const double *__restrict__ vx,
+                                                    const double *__restrict__ vy,
+                                                    const double *__restrict__ vz,
+                                                    ForceRec *__restrict__ rec)
 {
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
-    double P = (gamma - 1.0) * rho[k] * u[k];
-    A[k] = P / (omega[k] * rho[k] * rho[k]);
-    c[k] = sqrt(gamma * P / rho[k]);
-    hinv[k] = 1.0 / h[k];
+    const double r = rho[k];
+    const double P = (gamma - 1.0) * r * u[k];
+    ForceRec f;
+    f.c = sqrt(gamma * P / r);
+    f.hinv = 1.0 / h[k];
+    f.vx = vx[k];
+    f.vy = vy[k];
+    f.vz = vz[k];
+    f.m = m[k];
+    f.A = P / (omega[k] * r * r);
+    f.rho = r;
+    rec[k] = f;
 }
 
 } // namespace
@@ -720,12 +732,13 @@ sph_status refresh_hmax(sph_ctx *c, int64_t n)
     return hip_check(c, hipGetLastError(), "refresh_hmax");
 }
 
-sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted)
+sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted, const double *vx,
+                      const double *vy, const double *vz)
 {
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_force_prep, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n,
-                       c->p.gamma, c->s.rho, c->s.omega, u_sorted, c->s.h, c->s.A, c->s.c,
-                       c->s.hinv);
+                       c->p.gamma, c->s.rho, c->s.omega, u_sorted, c->s.h, c->s.m, vx, vy, vz,
+                       c->s.frec);
     return hip_check(c, hipGetLastError(), "force_prep");
 }
 

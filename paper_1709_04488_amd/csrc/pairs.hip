@@ -1038,7 +1038,8 @@ struct ForceArgs {
     uint32_t *work;
     Box box;
     const Node *nodes;
-    const double *x, *y, *z, *vx, *vy, *vz, *m, *h, *hinv, *rho, *A, *c;
+    const double *x, *y, *z, *h;
+    const ForceRec *rec;
     const float *fx, *fy, *fz;
     double *ax, *ay, *az, *du, *vsig, *dt;
     int32_t *nforce;
@@ -1100,9 +1101,10 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             hfy = as_global(F.fy)[ii];
             hfz = as_global(F.fz)[ii];
         }
-        const double vxi = as_global(F.vx)[ii], vyi = as_global(F.vy)[ii], vzi = as_global(F.vz)[ii];
-        const double hi = as_global(F.h)[ii], hinvi = as_global(F.hinv)[ii];
-        const double rhoi = as_global(F.rho)[ii], Ai = as_global(F.A)[ii], ci = as_global(F.c)[ii];
+        const ForceRec ri = load_global(F.rec + ii);
+        const double vxi = ri.vx, vyi = ri.vy, vzi = ri.vz;
+        const double hi = as_global(F.h)[ii], hinvi = ri.hinv;
+        const double rhoi = ri.rho, Ai = ri.A, ci = ri.c;
         const double hi2x4 = (2.0 * hi) * (2.0 * hi);
         const double gfi = kSigma * (hinvi * hinvi) * (hinvi * hinvi);
         const float hinvif = (float)hinvi;
@@ -1153,23 +1155,9 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                 },
                 F.count_tests != 0, boxes, tests);
             const uint64_t w0 = S.mask[p][0], w1 = S.mask[p][1];
-            // the record of a neighbour that the pair terms read
-            struct JData {
-                double c, hinv, vx, vy, vz, m, A, rho;
-            };
-            auto load_j = [&](int sl) {
-                const int64_t j = S.j[sl];
-                JData d;
-                d.c = as_global(F.c)[j];
-                d.hinv = as_global(F.hinv)[j];
-                d.vx = as_global(F.vx)[j];
-                d.vy = as_global(F.vy)[j];
-                d.vz = as_global(F.vz)[j];
-                d.m = as_global(F.m)[j];
-                d.A = as_global(F.A)[j];
-                d.rho = as_global(F.rho)[j];
-                return d;
-            };
+            // the record of a neighbour that the pair terms read (one line)
+            using JData = ForceRec;
+            auto load_j = [&](int sl) { return load_global(F.rec + S.j[sl]); };
             auto pair_terms = [&](int sl, const JData &d) {
                 double dx, dy, dz, r2;
                 separation<G, PREC>(S, bx, hx, hy, hz, hfx, hfy, hfz, sl, dx, dy, dz, r2);
@@ -1519,14 +1507,13 @@ sph_status density_prepare(sph_ctx *c, int64_t n)
     return hip_check(c, hipGetLastError(), "density arguments");
 }
 
-sph_status forces_prepare(sph_ctx *c, int64_t n, const double *vx, const double *vy,
-                          const double *vz)
+sph_status forces_prepare(sph_ctx *c, int64_t n)
 {
     ForceArgs a{};
     fill_common(c, n, a);
     a.x = c->s.x; a.y = c->s.y; a.z = c->s.z;
-    a.vx = vx; a.vy = vy; a.vz = vz;
-    a.m = c->s.m; a.h = c->s.h; a.hinv = c->s.hinv; a.rho = c->s.rho; a.A = c->s.A; a.c = c->s.c;
+    a.h = c->s.h;
+    a.rec = c->s.frec;
     a.fx = c->s.fx; a.fy = c->s.fy; a.fz = c->s.fz;
     a.ax = c->s.ax; a.ay = c->s.ay; a.az = c->s.az; a.du = c->s.du;
     a.vsig = c->s.vsig; a.dt = c->s.dt; a.nforce = c->s.nforce;
@@ -1534,9 +1521,9 @@ sph_status forces_prepare(sph_ctx *c, int64_t n, const double *vx, const double 
     a.counts = c->d_counts;
     a.alpha = c->p.alpha_av; a.beta = c->p.beta_av; a.ccfl = c->p.c_cfl;
     a.count_tests = c->count_tests ? 1 : 0;
-    const void *req[] = {a.nodes, a.x, a.y, a.z, a.vx, a.vy, a.vz, a.m, a.h, a.hinv, a.rho,
-                         a.A, a.c, a.ax, a.ay, a.az, a.du, a.vsig, a.dt, a.nforce, a.status,
-                         a.counts, a.tree, a.lstart, a.work, c->d_fargs};
+    const void *req[] = {a.nodes, a.x, a.y, a.z, a.h, a.rec, a.ax, a.ay, a.az, a.du, a.vsig,
+                         a.dt, a.nforce, a.status, a.counts, a.tree, a.lstart, a.work,
+                         c->d_fargs};
     for (const void *q : req)
         if (!q) return fail(c, SPH_EINVAL, "forces: internal buffer not allocated");
     if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
@@ -1643,10 +1630,10 @@ sph_status run_density(sph_ctx *c, int64_t n)
     return density_launch(&c, 1, n);
 }
 
-sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy, const double *vz)
+sph_status run_forces(sph_ctx *c, int64_t n)
 {
     if (n == 0) return SPH_OK;
-    TRY_(forces_prepare(c, n, vx, vy, vz));
+    TRY_(forces_prepare(c, n));
     return forces_launch(&c, 1, n);
 }
 

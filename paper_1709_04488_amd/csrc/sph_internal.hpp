@@ -111,6 +111,12 @@ enum : int {
     kCntForceWords = kCntForceBoxes - kCntForceEvals + 1,
 };
 
+// What the force loop reads of every neighbour j, in one 64-byte line:
+// c_j, 1/h_j, v_j, m_j, A_j = P_j / (Omega_j rho_j^2) and rho_j.
+struct alignas(64) ForceRec {
+    double c, hinv, vx, vy, vz, m, A, rho;
+};
+
 // Arrays in sorted (Morton) order.  FP32-pair mode adds float offsets from the
 // centre of each particle's leaf.
 struct Sorted {
@@ -118,7 +124,7 @@ struct Sorted {
     double *vx = nullptr, *vy = nullptr, *vz = nullptr;
     double *m = nullptr, *u = nullptr, *h = nullptr;
     double *rho = nullptr, *omega = nullptr;
-    double *A = nullptr, *c = nullptr, *hinv = nullptr;   // force record
+    ForceRec *frec = nullptr;                  // force record
     double *ax = nullptr, *ay = nullptr, *az = nullptr, *du = nullptr;
     double *vsig = nullptr, *dt = nullptr;
     int32_t *nngb = nullptr, *nforce = nullptr;
@@ -226,23 +232,22 @@ struct GatherList {
 sph_status gather(sph_ctx *c, int64_t n, const GatherList &g, bool identity_src_index);
 // Leaf boxes and tree over c->s.{x,y,z,h}; FP32 offsets when requested.
 sph_status build_tree(sph_ctx *c, int64_t n);
-// Per-particle force record (A, c, hinv) from rho, omega, u.
 // leaf and node hmax from the current sorted h (after the h solve), boxes kept
 sph_status refresh_hmax(sph_ctx *c, int64_t n);
-sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted);
+// Force records from rho, omega, h, m and the given sorted u and velocities.
+sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted, const double *vx,
+                      const double *vy, const double *vz);
 sph_status iota(sph_ctx *c, int64_t n, uint32_t *v);
 int64_t node_count_bound(int64_t n);
 
 // ---- pairs.hip ---------------------------------------------------------------
 sph_status run_density(sph_ctx *c, int64_t n);
-sph_status run_forces(sph_ctx *c, int64_t n, const double *vx, const double *vy,
-                      const double *vz);
+sph_status run_forces(sph_ctx *c, int64_t n);
 // batched pair loops: prepare writes each set's argument block on its
 // stream; launch runs one persistent kernel over cs[0..count) (same stream,
 // precision and leaf size)
 sph_status density_prepare(sph_ctx *c, int64_t n);
-sph_status forces_prepare(sph_ctx *c, int64_t n, const double *vx, const double *vy,
-                          const double *vz);
+sph_status forces_prepare(sph_ctx *c, int64_t n);
 sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax);
 sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax);
 sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_sorted,
