@@ -1,10 +1,11 @@
 #!/usr/bin/env python3
 """Throughput of the grad-h SPH hot path on one MI355X.
 
-One step = one full evaluation of a particle set through the C ABI: neighbour
-search (Morton keys, radix sort, gathers, leaf/box tree), the density loop
-with the Newton-Raphson h solve started from the input guess, the force loop,
-the per-particle and global CFL step, and the scatter back to caller order.
+One step = one full evaluation of a particle set through the C ABI
+(sph_evaluate): neighbour search (Morton keys, radix sort, gathers, leaf/box
+tree), the density loop with the Newton-Raphson h solve started from the input
+guess, the force loop, the per-particle and global CFL step, and the scatter
+back to caller order.
 The metric is neighbour interactions per second: density pairs (j != i,
 r < 2 h_i at the final h) plus force pairs (j != i, r < 2 max(h_i, h_j)) of
 one evaluation, divided by its wall time.  Inputs are resident in HBM before
@@ -74,8 +75,7 @@ def run_gpu(w, precision: int, steps: int, warmup: int, leaf: int, warm_start: b
     def one():
         if not warm_start:
             p.t["h"].copy_(h0)
-        ctx.density(p)
-        ctx.forces(p)
+        ctx.evaluate(p)
 
     for _ in range(warmup):
         one()

@@ -106,12 +106,15 @@ typedef struct {
  * One particle set, device pointers, caller index order.  Which arrays each
  * call reads (R) or writes (W):
  *
- *                   x,y,z  m   h    u  vx,vy,vz  rho,omega  pressure,cs  ax..dt  nngb nforce
- *   sph_build_cells   R        R
- *   sph_density       R    R   RW                W          W(opt)             W(opt)
- *   sph_forces        R    R   R    R  R         R          W(opt)       W            W(opt)
- *   sph_upload_state  R    R   R    R  R
- *   sph_download_state W       W    W  W         W          W(opt)       W(opt)
+ *                     x,y,z  m   h    u    v    rho,omega  pressure,cs  ax..dt  nngb    nforce
+ *   sph_build_cells     R          R
+ *   sph_density         R      R   RW   (R)       W          W(opt)               W(opt)
+ *   sph_forces          R      R   R    R    R    R                       W               W(opt)
+ *   sph_evaluate        R      R   RW   R    R    W          W(opt)       W       W(opt)  W(opt)
+ *   sph_upload_state    R      R   R    R    R
+ *   sph_download_state  W          W    W    W    W(opt)     W(opt)       W(opt)  W(opt)  W(opt)
+ *
+ * (R): read only when pressure or cs is requested.  v = vx, vy, vz.
  *
  * h on entry to sph_density is the initial guess of each smoothing length
  * (> 0); on return it holds the converged value.  dt is the per-particle
@@ -215,6 +218,19 @@ sph_status sph_density(sph_ctx *ctx, sph_particles *ps);
 sph_status sph_forces(sph_ctx *ctx, sph_particles *ps);
 
 /*
+ * One full evaluation: the density loop and h solve of sph_density, then the
+ * force loop of sph_forces, with the set kept in sorted order on the device
+ * in between (one sort and one gather of the inputs, the boxes' largest h
+ * refreshed after the h solve instead of a second tree build, one scatter of
+ * all outputs).  Reads x, y, z, v, m, u and the guess in h; writes h, rho,
+ * omega, ax, ay, az, dudt, vsig, dt and, where non-NULL, pressure, cs, nngb,
+ * nforce.  Equals sph_density followed by sph_forces to rounding: neighbour
+ * counts and h, rho, omega are identical, the force sums may run in another
+ * order.
+ */
+sph_status sph_evaluate(sph_ctx *ctx, sph_particles *ps);
+
+/*
  * Copy a particle set (x, y, z, v, m, u, h) into context-owned device memory
  * for time integration with sph_step.  Evaluates density and forces of the
  * initial state.  Keeps nothing that points into ps.
@@ -278,6 +294,10 @@ sph_status sph_neighbours(sph_ctx *ctx, const sph_particles *ps, int32_t mode,
  */
 sph_status sph_batch_density(sph_ctx *const *ctx, sph_particles *const *ps, int32_t count);
 sph_status sph_batch_forces(sph_ctx *const *ctx, sph_particles *const *ps, int32_t count);
+/* sph_evaluate over many sets: the density loops of all sets in one launch
+ * per group, then their force loops; each set's results are bit-for-bit
+ * those of sph_evaluate on that set alone. */
+sph_status sph_batch_evaluate(sph_ctx *const *ctx, sph_particles *const *ps, int32_t count);
 /* One sph_step of each resident state, pair loops batched as above. */
 sph_status sph_batch_step(sph_ctx *const *ctx, int32_t count, double dt);
 

@@ -461,6 +461,58 @@ sph_status check_batch(sph_ctx *const *cs, int32_t count)
     return SPH_OK;
 }
 
+// sph_evaluate in phases shared with the batched call: sort, gather and
+// tree, density arguments / leaf hmax, force records and force arguments /
+// scatter of every output.
+sph_status evaluate_pre(sph_ctx *c, const sph_particles *ps)
+{
+    TRY(check_ps(c, ps));
+    REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z");
+    REQ(ps->vx, "vx"); REQ(ps->vy, "vy"); REQ(ps->vz, "vz");
+    REQ(ps->m, "m"); REQ(ps->u, "u"); REQ(ps->h, "h"); REQ(ps->rho, "rho"); REQ(ps->omega, "omega");
+    REQ(ps->ax, "ax"); REQ(ps->ay, "ay"); REQ(ps->az, "az"); REQ(ps->dudt, "dudt");
+    REQ(ps->vsig, "vsig"); REQ(ps->dt, "dt");
+    c->resident = false;
+    const int64_t n = ps->n;
+    TRY(ensure_capacity(c, n));
+    c->n = n;
+    if (n == 0) return SPH_OK;
+    // one sort and one gather of every input; the sorted set stays on the
+    // device from the density loop to the force loop
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_begin(c, 2, &e0, &e1);
+    TRY(build_order(c, n, ps->x, ps->y, ps->z));
+    GatherList g{};
+    const void *src[] = {ps->x, ps->y, ps->z, ps->h, ps->m, ps->u, ps->vx, ps->vy, ps->vz};
+    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.h, c->s.m, c->s.u, c->s.vx, c->s.vy, c->s.vz};
+    g.count = 9;
+    for (int a = 0; a < g.count; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
+    TRY(gather(c, n, g, false));
+    TRY(build_tree(c, n));
+    timer_end(c, 2, e0, e1);
+    c->built = true;
+    c->built_x = ps->x;
+    c->built_n = n;
+    return density_prepare(c, n);
+}
+
+sph_status evaluate_mid(sph_ctx *c)
+{
+    const int64_t n = c->n;
+    if (n == 0) return SPH_OK;
+    // the force walk needs the boxes' largest h after the h solve
+    TRY(refresh_hmax(c, n));
+    TRY(force_prep(c, n, c->s.u, c->s.vx, c->s.vy, c->s.vz));
+    return forces_prepare(c, n);
+}
+
+sph_status evaluate_post(sph_ctx *c, const sph_particles *ps)
+{
+    if (ps->n == 0) return SPH_OK;
+    TRY(density_post(c, ps));
+    return forces_post(c, ps);
+}
+
 } // namespace
 
 extern "C" {
@@ -596,6 +648,28 @@ sph_status sph_forces(sph_ctx *c, sph_particles *ps)
     if (ps->n == 0) return SPH_OK;
     TRY(forces_launch(&c, 1, ps->n));
     return forces_post(c, ps);
+}
+
+sph_status sph_evaluate(sph_ctx *c, sph_particles *ps)
+{
+    TRY(evaluate_pre(c, ps));
+    if (ps->n == 0) return SPH_OK;
+    TRY(density_launch(&c, 1, ps->n));
+    TRY(evaluate_mid(c));
+    TRY(forces_launch(&c, 1, ps->n));
+    return evaluate_post(c, ps);
+}
+
+sph_status sph_batch_evaluate(sph_ctx *const *cs, sph_particles *const *ps, int32_t count)
+{
+    TRY(check_batch(cs, count));
+    if (count > 0 && !ps) return fail(cs[0], SPH_EINVAL, "particles is NULL");
+    for (int r = 0; r < count; r++) TRY(evaluate_pre(cs[r], ps[r]));
+    TRY(launch_groups(cs, count, [](sph_ctx *const *g, int k) { return density_launch(g, k, 0); }));
+    for (int r = 0; r < count; r++) TRY(evaluate_mid(cs[r]));
+    TRY(launch_groups(cs, count, [](sph_ctx *const *g, int k) { return forces_launch(g, k, 0); }));
+    for (int r = 0; r < count; r++) TRY(evaluate_post(cs[r], ps[r]));
+    return SPH_OK;
 }
 
 sph_status sph_batch_density(sph_ctx *const *cs, sph_particles *const *ps, int32_t count)

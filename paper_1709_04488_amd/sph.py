@@ -25,10 +25,12 @@ STATUS_NAMES = {0: "SPH_OK", -1: "SPH_EINVAL", -2: "SPH_ENOMEM", -3: "SPH_EDEVIC
                 -7: "SPH_EBUDGET", -8: "SPH_ECAP", -9: "SPH_ESTATE"}
 
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream", "sph_set_params",
-            "sph_build_cells", "sph_density", "sph_forces", "sph_upload_state", "sph_step",
+            "sph_build_cells", "sph_density", "sph_forces", "sph_evaluate", "sph_upload_state",
+            "sph_step",
             "sph_download_state", "sph_state_info", "sph_neighbours", "sph_sync",
             "sph_last_error", "sph_device_bytes", "sph_enable_kernel_timing", "sph_kernel_times",
-            "sph_batch_density", "sph_batch_forces", "sph_batch_step", "sph_capture_steps",
+            "sph_batch_density", "sph_batch_forces", "sph_batch_evaluate", "sph_batch_step",
+            "sph_capture_steps",
             "sph_replay_steps", "sph_plan_bytes"]
 
 
@@ -97,6 +99,7 @@ def load() -> ctypes.CDLL:
         "sph_build_cells": (ctypes.c_int, [vp, PS]),
         "sph_density": (ctypes.c_int, [vp, PS]),
         "sph_forces": (ctypes.c_int, [vp, PS]),
+        "sph_evaluate": (ctypes.c_int, [vp, PS]),
         "sph_upload_state": (ctypes.c_int, [vp, PS]),
         "sph_step": (ctypes.c_int, [vp, d, ctypes.POINTER(d)]),
         "sph_download_state": (ctypes.c_int, [vp, PS]),
@@ -109,6 +112,7 @@ def load() -> ctypes.CDLL:
         "sph_kernel_times": (ctypes.c_int, [vp, i32, ctypes.POINTER(d), ctypes.POINTER(i64)]),
         "sph_batch_density": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(PS), i32]),
         "sph_batch_forces": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(PS), i32]),
+        "sph_batch_evaluate": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(PS), i32]),
         "sph_batch_step": (ctypes.c_int, [ctypes.POINTER(vp), i32, d]),
         "sph_capture_steps": (ctypes.c_int, [vp, d]),
         "sph_replay_steps": (ctypes.c_int, [vp]),
@@ -268,7 +272,13 @@ class Context:
         self._check(self.lib.sph_forces(self.h, ctypes.byref(ps)), "sph_forces")
 
     def evaluate(self, p: Particles):
-        """Density (h solve) then forces: one full evaluation."""
+        """Density (h solve) then forces: one full evaluation in one call, the
+        set kept in sorted order on the device in between (sph_evaluate)."""
+        ps = p.c()
+        self._check(self.lib.sph_evaluate(self.h, ctypes.byref(ps)), "sph_evaluate")
+
+    def density_then_forces(self, p: Particles):
+        """The same evaluation as two calls, sph_density then sph_forces."""
         self.density(p)
         self.forces(p)
 
@@ -389,8 +399,10 @@ def batch_forces(ctxs, parts):
 
 
 def batch_evaluate(ctxs, parts):
-    batch_density(ctxs, parts)
-    batch_forces(ctxs, parts)
+    """sph_evaluate over many sets (sph_batch_evaluate)."""
+    lib = load()
+    hs, ptrs, keep = _batch_arrays(ctxs, parts, ())
+    _batch_check(ctxs, lib.sph_batch_evaluate(hs, ptrs, len(ctxs)), "sph_batch_evaluate")
 
 
 def batch_step(ctxs, dt: float = 0.0):

@@ -28,7 +28,7 @@ def _lib_path():
 def test_header_declares_the_boundary_calls():
     names = _declared()
     for required in ("sph_create", "sph_destroy", "sph_build_cells", "sph_density", "sph_forces",
-                     "sph_step", "sph_upload_state", "sph_download_state", "sph_neighbours",
+                     "sph_evaluate", "sph_step", "sph_upload_state", "sph_download_state", "sph_neighbours",
                      "sph_sync", "sph_last_error"):
         assert required in names
 

@@ -36,21 +36,31 @@ def _fields():
             "nngb", "nforce")
 
 
-def test_batch_equals_alone_bitwise(sph):
+@pytest.mark.parametrize("two_calls", [False, True])
+def test_batch_equals_alone_bitwise(sph, two_calls):
+    """sph_batch_evaluate against sph_evaluate per set, and sph_batch_density
+    + sph_batch_forces against sph_density + sph_forces per set."""
     mix = _mix()
     alone = []
     for w, prec, leaf in mix:
         with sph.Context(sph.Params.from_setup(w.setup, precision=prec, leaf_size=leaf)) as ctx:
             p = sph.Particles.from_host(w.arrays)
-            ctx.evaluate(p)
+            if two_calls:
+                ctx.density_then_forces(p)
+            else:
+                ctx.evaluate(p)
             ctx.sync()
             alone.append(p.host())
     stream = torch.cuda.current_stream()
     ctxs = [sph.Context(sph.Params.from_setup(w.setup, precision=prec, leaf_size=leaf), stream=stream)
             for w, prec, leaf in mix]
     parts = [sph.Particles.from_host(w.arrays) for w, _, _ in mix]
-    print("case: batch of %d sets" % len(mix), flush=True)
-    sph.batch_evaluate(ctxs, parts)
+    print("case: batch of %d sets, two_calls=%s" % (len(mix), two_calls), flush=True)
+    if two_calls:
+        sph.batch_density(ctxs, parts)
+        sph.batch_forces(ctxs, parts)
+    else:
+        sph.batch_evaluate(ctxs, parts)
     for c in ctxs:
         c.sync()
     for k, (a, p) in enumerate(zip(alone, parts)):

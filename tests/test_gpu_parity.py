@@ -41,11 +41,15 @@ def _oracle_eval(orc, w, **over):
     return orc.evaluate(p, a["x"], a["y"], a["z"], a["vx"], a["vy"], a["vz"], a["m"], a["u"], a["h"])
 
 
-def _gpu_eval(sph, w, precision=0, leaf_size=16, **over):
+def _gpu_eval(sph, w, precision=0, leaf_size=16, two_calls=False, **over):
+    """sph_evaluate, or with two_calls sph_density then sph_forces."""
     params = sph.Params.from_setup({**w.setup, **over}, precision=precision, leaf_size=leaf_size)
     with sph.Context(params) as ctx:
         p = sph.Particles.from_host(w.arrays)
-        ctx.evaluate(p)
+        if two_calls:
+            ctx.density_then_forces(p)
+        else:
+            ctx.evaluate(p)
         ctx.sync()
         return p.host()
 
@@ -69,12 +73,34 @@ def _check(out, ref, tol=FP64_TOL, atol=FP64_TOL, counts_exact=True, label="", f
         assert np.array_equal(out["nforce"], ref["nforce"]), label
 
 
-def test_config0_full_parity_fp64(sph, orc):
+@pytest.mark.parametrize("two_calls", [False, True])
+def test_config0_full_parity_fp64(sph, orc, two_calls):
     w = W.config0()
-    print("case: config0 N=%d fp64" % w.n, flush=True)
+    print("case: config0 N=%d fp64 two_calls=%s" % (w.n, two_calls), flush=True)
     ref = _oracle_eval(orc, w)
-    out = _gpu_eval(sph, w)
+    out = _gpu_eval(sph, w, two_calls=two_calls)
     _check(out, ref, label="config0")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_evaluate_equals_density_then_forces(sph, precision):
+    """One sph_evaluate call against sph_density + sph_forces on the same set:
+    the density results and every count are the same bits (same sort, same
+    tree); the forces may sum in another order (the second call builds its
+    tree with the converged h), so they agree to rounding."""
+    w = W.plummer(3000, seed=8)
+    print("case: evaluate vs two calls, plummer3000 precision=%d" % precision, flush=True)
+    one = _gpu_eval(sph, w, precision=precision)
+    two = _gpu_eval(sph, w, precision=precision, two_calls=True)
+    for k in ("h", "rho", "omega", "pressure", "cs", "nngb", "nforce"):
+        assert np.array_equal(one[k], two[k]), k
+    tol = 1e-12 if precision == 0 else 1e-5
+    scale = np.sqrt(two["ax"] ** 2 + two["ay"] ** 2 + two["az"] ** 2).max()
+    for k in ("ax", "ay", "az"):
+        assert np.max(np.abs(one[k] - two[k])) <= tol * scale, k
+    assert np.max(np.abs(one["dudt"] - two["dudt"])) <= tol * np.abs(two["dudt"]).max()
+    for k in ("vsig", "dt"):
+        assert np.max(np.abs(one[k] / two[k] - 1.0)) <= tol, k
 
 
 @pytest.mark.parametrize("leaf", [8, 16, 32])
