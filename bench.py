@@ -294,6 +294,11 @@ def main():
         "dens_leaf_visits": head["info"]["dens_leaf_visits"],
         "dens_walks": head["info"]["dens_walks"],
         "density_pair_evals": head["info"]["dens_pair_evals"],
+        # pair-term evaluations per second of kernel time, every Newton step
+        # counted (density) and each force pair once
+        "pair_evals_per_s": {
+            "density": head["info"]["dens_pair_evals"] / (head["kernel_ms"]["density"] * 1e-3),
+            "force": head["info"]["force_pair_evals"] / (head["kernel_ms"]["force"] * 1e-3)},
         "nr_iter_mean": head["info"]["nr_iter_total"] / w.n,
         "candidate_tests_per_s": None if args.main_only else {
             "density": head["info"]["dens_candidate_tests"] / (head["kernel_ms"]["density"] * 1e-3),
