@@ -1194,8 +1194,10 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     dui += cdu;
                 } else {
                     const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
-                    const float rr = sqrtf((float)r2);
-                    const float rinv = 1.0f / rr;
+                    // hardware reciprocal square root and reciprocal (1 ulp each),
+                    // functions of symmetric operands, so (j, i) sees the same values
+                    const float rinv = __builtin_amdgcn_rsqf((float)r2);
+                    const float rr = (float)r2 * rinv;
                     const float ex = fdx * rinv, ey = fdy * rinv, ez = fdz * rinv;
                     const float hinvj = (float)d.hinv;
                     // own and other kernel factors formed by the same float
@@ -1217,7 +1219,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const float wneg = fminf(w, 0.0f);
                     const float vs = (cif + cjf) - (float)beta * wneg;
                     vs_max = fmax(vs_max, (double)vs);
-                    const float visc = (mj / (0.5f * ((float)rhoi + (float)d.rho))) * (float)alpha * vs * wneg;
+                    const float visc = (mj * __builtin_amdgcn_rcpf(0.5f * ((float)rhoi + (float)d.rho))) *
+                                       (float)alpha * vs * wneg;
                     const float gbar = 0.5f * gsum;
                     cvec += visc * gbar;
                     cdu -= visc * 0.5f * wneg * gbar;
