@@ -198,6 +198,33 @@ __device__ inline float min_image_f(float d, float L, float half)
     return d;
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton-Raphson
+// steps on 1/y^2 - x (each squares the relative error), to about 1 ulp in
+// eight operations instead of a correctly rounded square root and division.
+__device__ inline double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const double r = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, r, y);
+    }
+    return y;
+}
+
+// 1/x for x > 0: the hardware estimate refined by two Newton-Raphson steps
+// on 1/y - x, to about 1 ulp.
+__device__ inline double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const double e = fma(-x, y, 1.0);
+        y = fma(y, e, y);
+    }
+    return y;
+}
+
 // M4: f(q) = a^3/4 - b^3, f'(q) = 3 b^2 - 3/4 a^2 with a = (2-q)_+, b = (1-q)_+
 template <class T>
 __device__ inline void m4(T qq, T &f, T &df)
@@ -866,7 +893,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 const double ra2 = fabs(r2);
                 if (PREC == SPH_FP64) {
                     double f, df;
-                    const double qq = sqrt(ra2) * hinv;
+                    // r = r^2 / sqrt(r^2) through rsqrt_nr (0 for the particle itself)
+                    const double qq = (ra2 > 0.0 ? ra2 * rsqrt_nr(ra2) : 0.0) * hinv;
                     m4(qq, f, df);
                     s0 += mj * f;
                     s2 += mj * (qq * df);
@@ -1167,8 +1195,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     return;
                 }
                 if (PREC == SPH_FP64) {
-                    const double rr = sqrt(r2);
-                    const double rinv = 1.0 / rr;
+                    const double rinv = rsqrt_nr(r2);
+                    const double rr = r2 * rinv;
                     const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
                     const double hinvj = d.hinv;
                     const double gfj = kSigma * (hinvj * hinvj) * (hinvj * hinvj);
@@ -1184,7 +1212,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const double wneg = fmin(w, 0.0);
                     const double vs = (ci + cj) - beta * wneg;
                     vs_max = fmax(vs_max, vs);
-                    const double visc = (mj / (0.5 * (rhoi + d.rho))) * alpha * vs * wneg;
+                    const double visc = (mj * rcp_nr(0.5 * (rhoi + d.rho))) * alpha * vs * wneg;
                     const double gbar = 0.5 * gsum;
                     cvec += visc * gbar;
                     cdu -= visc * 0.5 * wneg * gbar;
