@@ -508,9 +508,26 @@ sph_status evaluate_mid(sph_ctx *c)
 
 sph_status evaluate_post(sph_ctx *c, const sph_particles *ps)
 {
-    if (ps->n == 0) return SPH_OK;
-    TRY(density_post(c, ps));
-    return forces_post(c, ps);
+    const int64_t n = ps->n;
+    if (n == 0) return SPH_OK;
+    // every output in one pass over the permutation, the equation of state
+    // from the sorted rho and u (the same values sph_density scatters)
+    ScatterList sl{};
+    const void *src[] = {c->s.h, c->s.rho, c->s.omega, c->s.nngb, c->s.ax, c->s.ay, c->s.az,
+                         c->s.du, c->s.vsig, c->s.dt, c->s.nforce};
+    void *dst[] = {ps->h, ps->rho, ps->omega, ps->nngb, ps->ax, ps->ay, ps->az, ps->dudt,
+                   ps->vsig, ps->dt, ps->nforce};
+    const int kinds[] = {0, 0, 0, 1, 0, 0, 0, 0, 0, 0, 1};
+    for (int a = 0; a < 11; a++) {
+        if (!dst[a]) continue;
+        sl.kind[sl.count] = kinds[a];
+        sl.src[sl.count] = src[a];
+        sl.dst[sl.count] = dst[a];
+        sl.count++;
+    }
+    TRY(scatter_eos(c, n, sl, c->perm, c->s.u, ps->pressure, ps->cs));
+    TRY(reduce_dt(c, n));
+    return reduce_diag(c, n);
 }
 
 } // namespace

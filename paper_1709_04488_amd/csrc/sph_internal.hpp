@@ -264,6 +264,9 @@ struct ScatterList {
 sph_status scatter(sph_ctx *c, int64_t n, const ScatterList &s, const uint32_t *index);
 sph_status eos_scatter(sph_ctx *c, int64_t n, const uint32_t *index, const double *u_caller,
                        double *P, double *cs);
+// scatter plus the equation of state (P, cs may be NULL) from sorted rho, u
+sph_status scatter_eos(sph_ctx *c, int64_t n, const ScatterList &s, const uint32_t *index,
+                       const double *u_sorted, double *P, double *cs);
 sph_status kick_drift(sph_ctx *c, int64_t n, double dt_host);
 sph_status closing_kick(sph_ctx *c, int64_t n, double dt_host);
 sph_status reduce_dt(sph_ctx *c, int64_t n);

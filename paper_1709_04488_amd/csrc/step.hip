@@ -40,6 +40,31 @@ __global__ __launch_bounds__(256) void k_eos_scatter(int64_t n, double gamma,
     if (cs) cs[d] = sqrt(gamma * Pk / rho[k]);
 }
 
+// k_scatter and, where P or cs is given, the equation of state of k_eos_scatter
+// from the sorted rho and u, in one pass over the permutation.
+__global__ __launch_bounds__(256) void k_scatter_eos(int64_t n, const uint32_t *__restrict__ index,
+                                                     ScatterList s, double gamma,
+                                                     const double *__restrict__ rho,
+                                                     const double *__restrict__ u_sorted,
+                                                     double *__restrict__ P, double *__restrict__ cs)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int64_t dst = index[k];
+    for (int a = 0; a < s.count; a++) {
+        switch (s.kind[a]) {
+        case 0: ((double *)s.dst[a])[dst] = ((const double *)s.src[a])[k]; break;
+        case 1: ((uint32_t *)s.dst[a])[dst] = ((const uint32_t *)s.src[a])[k]; break;
+        default: ((float *)s.dst[a])[dst] = ((const float *)s.src[a])[k]; break;
+        }
+    }
+    if (P || cs) {
+        double Pk = (gamma - 1.0) * rho[k] * u_sorted[k];
+        if (P) P[dst] = Pk;
+        if (cs) cs[dst] = sqrt(gamma * Pk / rho[k]);
+    }
+}
+
 struct KdkArgs {
     int64_t n;
     Box box;
@@ -293,6 +318,15 @@ sph_status scatter(sph_ctx *c, int64_t n, const ScatterList &s, const uint32_t *
     if (n == 0 || s.count == 0) return SPH_OK;
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, index, s);
     return hip_check(c, hipGetLastError(), "scatter");
+}
+
+sph_status scatter_eos(sph_ctx *c, int64_t n, const ScatterList &s, const uint32_t *index,
+                       const double *u_sorted, double *P, double *cs)
+{
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_scatter_eos, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, index, s,
+                       c->p.gamma, c->s.rho, u_sorted, P, cs);
+    return hip_check(c, hipGetLastError(), "scatter_eos");
 }
 
 sph_status eos_scatter(sph_ctx *c, int64_t n, const uint32_t *index, const double *u_caller,
