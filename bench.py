@@ -213,7 +213,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the hot path is evaluated on a single MI355X; "
-              f"--gpus {args.gpus} is not supported (sharding is described in DESIGN.md)",
+              f"--gpus {args.gpus} is not supported (single-GPU benchmark)",
               file=sys.stderr)
         sys.exit(2)
 
