@@ -292,6 +292,17 @@ class _Slot:
         self.idx = idx
         self.stream = stream
         self.ctx = ctx
+        self.pinned = {}      # name -> reusable pinned host buffer (grown on demand)
+
+    def host_buffer(self, torch, name: str, count: int, dtype):
+        """Pinned host staging of at least `count` elements, reused by every
+        request of this slot (a slot runs one request at a time, and its
+        copies finish before the next request starts)."""
+        buf = self.pinned.get(name)
+        if buf is None or buf.numel() < count:
+            buf = torch.empty(max(count, 1), dtype=dtype).pin_memory()
+            self.pinned[name] = buf
+        return buf[:count]
 
 
 class GpuExecutor:
@@ -300,14 +311,18 @@ class GpuExecutor:
     OUT_EVAL = ("h", "rho", "omega", "pressure", "cs", "ax", "ay", "az", "dudt", "vsig", "dt",
                 "nngb", "nforce")
 
-    def __init__(self, max_slots: int, mode: str = "streams", leaf_for=None, keep_outputs=False):
+    def __init__(self, max_slots: int, mode: str = "streams", leaf_for=None, keep_outputs=False,
+                 download=True):
         import torch
 
         from . import sph
         self.torch = torch
         self.sph = sph
         self.mode = mode
+        # a request is done when its results are in host memory (download);
+        # keep_outputs also stores them in the request's record
         self.keep_outputs = keep_outputs
+        self.download = download or keep_outputs
         self.leaf_for = leaf_for or (lambda req: 16)
         self.shared = torch.cuda.Stream()
         self.slots = []
@@ -335,20 +350,45 @@ class GpuExecutor:
             slot.ctx.set_params(self.params(req))
         return slot.ctx
 
-    def _upload(self, req: Request, stream):
+    # the inputs are the first 9 of the 19 FP64 fields (x .. h), the
+    # evaluation's FP64 outputs the last 11 (h .. dt): one copy each way
+    N_IN = 9
+
+    def _upload(self, req: Request, slot: _Slot):
+        """All fields of a request in one device block (19 FP64 rows, 2 int32
+        rows); the 9 input rows arrive in one copy from the slot's pinned
+        staging buffer."""
         torch = self.torch
-        with torch.cuda.stream(stream):
-            t = {}
-            for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h"):
-                host = torch.from_numpy(np.ascontiguousarray(req.arrays[k], dtype=np.float64)).pin_memory()
-                t[k] = host.to("cuda", non_blocking=True)
-            n = req.n
-            for k in self.sph.FIELDS_F64:
-                if k not in t:
-                    t[k] = torch.zeros(n, dtype=torch.float64, device="cuda")
-            for k in self.sph.FIELDS_I32:
-                t[k] = torch.zeros(n, dtype=torch.int32, device="cuda")
-        return self.sph.Particles(t)
+        F = self.sph.FIELDS_F64
+        n = req.n
+        host = slot.host_buffer(torch, "in", self.N_IN * n, torch.float64).view(self.N_IN, n)
+        for i, k in enumerate(F[:self.N_IN]):
+            host[i].copy_(torch.from_numpy(np.ascontiguousarray(req.arrays[k], dtype=np.float64)))
+        with torch.cuda.stream(slot.stream):
+            dev = torch.empty((len(F), n), dtype=torch.float64, device="cuda")
+            idev = torch.empty((len(self.sph.FIELDS_I32), n), dtype=torch.int32, device="cuda")
+            dev[:self.N_IN].copy_(host, non_blocking=True)
+        t = {k: dev[i] for i, k in enumerate(F)}
+        t.update({k: idev[i] for i, k in enumerate(self.sph.FIELDS_I32)})
+        return self.sph.Particles(t), dev, idev
+
+    def _results(self, h) -> dict:
+        """The evaluation's outputs in host memory (two copies through the
+        slot's pinned buffers); numpy views of those buffers unless kept."""
+        torch = self.torch
+        slot, dev, idev = h["slot"], h["dev"], h["idev"]
+        n = dev.shape[1]
+        first = self.N_IN - 1                      # h: the last input, the first output
+        outs = self.sph.FIELDS_F64[first:]
+        hf = slot.host_buffer(torch, "out", len(outs) * n, torch.float64).view(len(outs), n)
+        hi = slot.host_buffer(torch, "iout", idev.numel(), torch.int32).view(idev.shape[0], n)
+        with torch.cuda.stream(slot.stream):
+            hf.copy_(dev[first:], non_blocking=True)
+            hi.copy_(idev, non_blocking=True)
+        slot.stream.synchronize()
+        res = {k: hf[i].numpy() for i, k in enumerate(outs)}
+        res.update({k: hi[i].numpy() for i, k in enumerate(self.sph.FIELDS_I32)})
+        return {k: res[k] for k in self.OUT_EVAL}
 
     def _zeros(self, n: int, stream):
         torch = self.torch
@@ -365,8 +405,9 @@ class GpuExecutor:
         for k, (req, sidx) in enumerate(items):
             slot = self.slots[sidx]
             ctx = self._ctx(slot, req)
-            p = self._upload(req, slot.stream)
-            h = {"req": req, "slot": slot, "ctx": ctx, "p": p, "event": torch.cuda.Event()}
+            p, dev, idev = self._upload(req, slot)
+            h = {"req": req, "slot": slot, "ctx": ctx, "p": p, "dev": dev, "idev": idev,
+                 "event": torch.cuda.Event()}
             if req.kind == "evaluate" and self.mode == "batched":
                 batch.append(h)
             elif req.kind == "evaluate":
@@ -403,16 +444,20 @@ class GpuExecutor:
         out = {"info": info}
         if req.kind == "evaluate":
             out["interactions"] = info["n_dens_pairs"] + info["n_force_pairs"]
-            if self.keep_outputs:
-                out["outputs"] = p.host(*self.OUT_EVAL)
+            if self.download:
+                res = self._results(h)
+                if self.keep_outputs:
+                    out["outputs"] = {k: v.copy() for k, v in res.items()}
         else:
             out["interactions"] = (info["n_dens_pairs"] + info["n_force_pairs"]) * max(req.nsteps, 1)
             q = self._zeros(req.n, h["slot"].stream)
             ctx.download_state(q)
             ctx.sync()
-            if self.keep_outputs:
-                out["outputs"] = q.host("x", "y", "z", "vx", "vy", "vz", "u", "h")
-        h["p"] = None
+            if self.download:
+                res = q.host("x", "y", "z", "vx", "vy", "vz", "u", "h")
+                if self.keep_outputs:
+                    out["outputs"] = res
+        h["p"] = h["dev"] = h["idev"] = None
         return out
 
     def release(self, slot: int):
@@ -474,9 +519,12 @@ def _progress(done: int, total: int):
 
 
 def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=False,
-          progress=False):
+          progress=False, download=True):
+    """Serve `reqs`; a request completes when its results are in host memory
+    (download=False stops at the device, for measurements of that part)."""
     import torch
-    ex = GpuExecutor(slots, mode=mode, leaf_for=leaf_for, keep_outputs=keep_outputs)
+    ex = GpuExecutor(slots, mode=mode, leaf_for=leaf_for, keep_outputs=keep_outputs,
+                     download=download)
     sched = Scheduler(ex, budget, slots, WallClock(), progress=_progress if progress else None)
     t0 = sched.clock.now()
     recs = sched.run(reqs)
