@@ -388,8 +388,9 @@ constexpr int kSlots = 2 * kWave;   // candidate slots per staged group
 constexpr int kTestsPerLane = 4;    // candidate tests per lane per combination
 
 // Per-slot candidate data: FP64 positions, or in FP32-pair mode the
-// single-precision offsets from the leaf centres; w is the mass (density) or
-// h (forces).
+// single-precision offsets from the leaf centres; w is the mass (density; not
+// staged when all masses are equal) or the squared gather reach (2h)^2
+// (forces).
 struct SlotsFP64 {
     double x[kSlots], y[kSlots], z[kSlots], w[kSlots];
 };
@@ -427,7 +428,7 @@ struct Stage {
 // Stage `count` (<= NL) candidate leaves; lane l fills slots l and l + 64,
 // slot s holding particle s % G of staged leaf s / G.  REACH2: w holds h and
 // the slot keeps the squared gather reach (2h)^2 instead.
-template <int G, int PREC, bool REACH2 = false>
+template <int G, int PREC, bool REACH2 = false, bool MAYBE_NO_W = false>
 __device__ inline void stage_group(Stage<G, PREC> &S, const uint32_t *leaves, int count,
                                    const uint32_t *__restrict__ lstart, const Node *__restrict__ nodes,
                                    const Node &home, const Box &bx, double hcov,
@@ -448,8 +449,10 @@ __device__ inline void stage_group(Stage<G, PREC> &S, const uint32_t *leaves, in
             const int jn = (int)(as_global(lstart)[c + 1] - j0);
             if (slot < jn) {
                 const int64_t j = j0 + slot;
-                const double wv = as_global(w)[j];
-                S.c.w[s] = REACH2 ? (2.0 * wv) * (2.0 * wv) : wv;
+                if (!MAYBE_NO_W || w) {   // MAYBE_NO_W: w == nullptr, the caller reads no w
+                    const double wv = as_global(w)[j];
+                    S.c.w[s] = REACH2 ? (2.0 * wv) * (2.0 * wv) : wv;
+                }
                 if constexpr (PREC == SPH_FP64) {
                     S.c.x[s] = as_global(x)[j];
                     S.c.y[s] = as_global(y)[j];
@@ -920,8 +923,13 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 wave_lds_sync();
                 int base = 0;
                 auto group = [&](const uint32_t *leaves, int ng) {
-                    stage_group<G, PREC>(S, leaves, ng, A.lstart, A.nodes, home, bx, hcov, A.x, A.y,
-                                         A.z, A.m, A.fx, A.fy, A.fz);
+                    // FP32-pair stages no mass when all masses are equal (measured
+                    // faster; the FP64 loop is faster staging it anyway)
+                    constexpr bool skip_m = PREC == SPH_FP32_PAIR;
+                    stage_group<G, PREC, false, skip_m>(S, leaves, ng, A.lstart, A.nodes, home, bx,
+                                                        hcov, A.x, A.y, A.z,
+                                                        skip_m && equal_m ? nullptr : A.m, A.fx,
+                                                        A.fy, A.fz);
                     const bool any_pp = group_tests<G, PREC>(
                         S, ng,
                         [&](int pp, int k) {
@@ -946,7 +954,10 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                                 S, bx, PREC == SPH_FP64 ? S.hx[p] : hx, PREC == SPH_FP64 ? S.hy[p] : hy,
                                 PREC == SPH_FP64 ? S.hz[p] : hz, hfx, hfy, hfz, sl, dx, dy, dz, r2);
                             const bool self = S.j[sl] == (uint32_t)i;
-                            const double mw = self ? -S.c.w[sl] : S.c.w[sl];
+                            // (with equal masses mw is not used, and FP32-pair
+                            // does not stage it)
+                            double mw = 0.0;
+                            if (PREC == SPH_FP64 || !equal_m) mw = self ? -S.c.w[sl] : S.c.w[sl];
                             const double rw = self ? -r2 : r2;
                             if (pos < KP) {
                                 const int at = (pos / LPP) * kWave + lane;

@@ -118,6 +118,27 @@ def test_leaf_sizes_ragged_periodic(sph, orc, leaf):
     _check(out, ref, label=f"leaf{leaf}")
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_unequal_masses(sph, orc, precision):
+    """Masses spread over a factor 3: the density loop keeps r^2 and m in its
+    candidate lists (the equal-mass path keeps r^2 only and stages no mass)."""
+    rng = np.random.default_rng(91)
+    n = 2500
+    a = {"x": rng.uniform(0, 1, n), "y": rng.uniform(0, 1, n), "z": rng.uniform(0, 1, n),
+         "vx": rng.normal(0, 0.3, n), "vy": rng.normal(0, 0.3, n), "vz": rng.normal(0, 0.3, n),
+         "m": rng.uniform(0.5, 1.5, n) / n, "u": rng.uniform(0.5, 1.5, n),
+         "h": np.full(n, 0.085)}
+    w = W.Workload("poisson2500_unequal_m", a, W.default_setup())
+    print("case: poisson N=2500 unequal masses precision=%d" % precision, flush=True)
+    ref = _oracle_eval(orc, w)
+    out = _gpu_eval(sph, w, precision=precision)
+    if precision == 0:
+        _check(out, ref, label="unequal m fp64")
+    else:
+        _check(out, ref, tol=FP32_TOL, atol=FP32_ATOL, counts_exact=False,
+               label="unequal m fp32", field_tol=FP32_FIELD_TOL)
+
+
 def test_open_boundary_plummer(sph, orc):
     w = W.plummer(2500, seed=31)
     print("case: plummer N=2500 open", flush=True)
