@@ -111,11 +111,10 @@ def run_gpu(w, precision: int, steps: int, warmup: int, leaf: int, warm_start: b
     return res
 
 
-def measured_traffic(tag: str, kernel: str):
-    """HBM bytes per launch of a pair loop from the committed rocprofv3 counter
-    runs (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters read for a
-    plain copy of known size), or None when there is no such run for this
-    workload or the pair-loop source has changed since it was taken."""
+def _profile_record(tag: str):
+    """The committed rocprofv3 record of this workload, precision and leaf size
+    (profiles/traffic.json), or None when there is none or the pair-loop
+    source has changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_1709_04488_amd", "csrc", "pairs.hip")
@@ -126,8 +125,24 @@ def measured_traffic(tag: str, kernel: str):
         return None
     if rec.get("pairs_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    b = rec.get("bytes_per_launch", {}).get(kernel)
+    return rec
+
+
+def measured_traffic(tag: str, kernel: str):
+    """HBM bytes per launch of a pair loop from the committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters read for a
+    plain copy of known size), or None (see _profile_record)."""
+    rec = _profile_record(tag)
+    b = rec.get("bytes_per_launch", {}).get(kernel) if rec else None
     return None if b is None else int(round(b["read"] + b["written"]))
+
+
+def measured_valu_insts(tag: str, kernel: str):
+    """VALU instructions per launch (counter SQ_INSTS_VALU, wave-level) from the
+    same committed record, or None."""
+    rec = _profile_record(tag)
+    v = rec.get("valu_insts_per_launch", {}).get(kernel) if rec else None
+    return None if v is None else float(v)
 
 
 def prof_tag(args, prec: str):
@@ -148,8 +163,13 @@ def roofline(res, prec: str, tag: str = None, phase: str = "cold"):
     peak = PEAK_TFLOPS[prec]
     key = f"{name}_{phase}" if name == "density" else f"{name}_all"
     traffic = measured_traffic(tag, key) if tag else None
+    # share of the VALU issue cycles of the 256 CUs (one wave instruction per CU
+    # and cycle at 2.4 GHz) that the kernel's instructions fill
+    insts = measured_valu_insts(tag, key) if tag else None
+    valu_issue = round(insts / (256 * 2.4e9 * t_ms * 1e-3), 3) if insts and t_ms > 0 else None
     return {"bound": "alu", "kernel": name, "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
+            "valu_issue_frac": valu_issue,
             "flops_per_launch": flops, "avg_launch_ms": round(t_ms, 4),
             "other_kernel": {k: {"flops_per_launch": v[0], "avg_launch_ms": round(v[1], 4),
                                  "achieved_tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 3) if v[1] > 0 else 0}
