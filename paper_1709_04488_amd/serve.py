@@ -312,7 +312,7 @@ class GpuExecutor:
                 "nngb", "nforce")
 
     def __init__(self, max_slots: int, mode: str = "streams", leaf_for=None, keep_outputs=False,
-                 download=True):
+                 download=True, threads=True):
         import torch
 
         from . import sph
@@ -329,6 +329,20 @@ class GpuExecutor:
         for s in range(max_slots):
             stream = self.shared if mode == "batched" else torch.cuda.Stream()
             self.slots.append(_Slot(s, stream, None))
+        # streams mode: one worker thread per slot carries a request from the
+        # upload through its kernels to the results in host memory, so host
+        # copies and launches of different slots overlap (copies and C calls
+        # run without the interpreter lock); each slot's context is used by
+        # one thread at a time
+        self.pool = None
+        if threads and mode == "streams":
+            from concurrent.futures import ThreadPoolExecutor
+            self.pool = ThreadPoolExecutor(max_workers=max_slots)
+
+    def close(self):
+        if self.pool is not None:
+            self.pool.shutdown(wait=True)
+            self.pool = None
 
     def params(self, req: Request):
         return self.sph.Params.from_setup(req.setup, precision=req.precision,
@@ -398,31 +412,46 @@ class GpuExecutor:
                 t[k] = torch.zeros(n, dtype=torch.int32, device="cuda")
         return self.sph.Particles(t)
 
+    def _prepare(self, req: Request, slot: _Slot) -> dict:
+        ctx = self._ctx(slot, req)
+        p, dev, idev = self._upload(req, slot)
+        return {"req": req, "slot": slot, "ctx": ctx, "p": p, "dev": dev, "idev": idev,
+                "event": self.torch.cuda.Event()}
+
+    def _launch(self, h):
+        """Enqueue one request's work on its slot's stream."""
+        torch, req, ctx, p, slot = self.torch, h["req"], h["ctx"], h["p"], h["slot"]
+        with torch.cuda.stream(slot.stream):
+            if req.kind == "evaluate":
+                ctx.evaluate(p)
+            else:
+                ctx.upload_state(p)
+                ctx.capture_steps(0.0)
+                for _ in range(req.nsteps // 2):
+                    ctx.replay_steps()
+                if req.nsteps % 2:
+                    ctx.step(0.0)
+        h["event"].record(slot.stream)
+
+    def _serve_one(self, req: Request, slot: _Slot) -> dict:
+        """A worker thread's whole request: upload, kernels, results on the host."""
+        h = self._prepare(req, slot)
+        self._launch(h)
+        return self._finish(h)
+
     def start(self, items):
+        if self.pool is not None:
+            return [{"req": req, "future": self.pool.submit(self._serve_one, req, self.slots[sidx])}
+                    for req, sidx in items]
         torch = self.torch
         handles = [None] * len(items)
         batch = []
         for k, (req, sidx) in enumerate(items):
-            slot = self.slots[sidx]
-            ctx = self._ctx(slot, req)
-            p, dev, idev = self._upload(req, slot)
-            h = {"req": req, "slot": slot, "ctx": ctx, "p": p, "dev": dev, "idev": idev,
-                 "event": torch.cuda.Event()}
+            h = self._prepare(req, self.slots[sidx])
             if req.kind == "evaluate" and self.mode == "batched":
                 batch.append(h)
-            elif req.kind == "evaluate":
-                with torch.cuda.stream(slot.stream):
-                    ctx.evaluate(p)
-                h["event"].record(slot.stream)
             else:
-                with torch.cuda.stream(slot.stream):
-                    ctx.upload_state(p)
-                    ctx.capture_steps(0.0)
-                    for _ in range(req.nsteps // 2):
-                        ctx.replay_steps()
-                    if req.nsteps % 2:
-                        ctx.step(0.0)
-                h["event"].record(slot.stream)
+                self._launch(h)
             handles[k] = h
         if batch:
             self.sph.batch_evaluate([h["ctx"] for h in batch], [h["p"] for h in batch])
@@ -433,9 +462,16 @@ class GpuExecutor:
         return handles
 
     def poll(self, h) -> bool:
+        if "future" in h:
+            return h["future"].done()
         return h["event"].query()
 
     def finish(self, h):
+        if "future" in h:
+            return h["future"].result()
+        return self._finish(h)
+
+    def _finish(self, h):
         ctx, p, req = h["ctx"], h["p"], h["req"]
         rc = ctx.sync_status()
         if rc != self.sph.SPH_OK:
@@ -519,15 +555,19 @@ def _progress(done: int, total: int):
 
 
 def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=False,
-          progress=False, download=True):
+          progress=False, download=True, threads=True):
     """Serve `reqs`; a request completes when its results are in host memory
-    (download=False stops at the device, for measurements of that part)."""
+    (download=False stops at the device, for measurements of that part).
+    threads: in streams mode, one worker thread per slot."""
     import torch
     ex = GpuExecutor(slots, mode=mode, leaf_for=leaf_for, keep_outputs=keep_outputs,
-                     download=download)
+                     download=download, threads=threads)
     sched = Scheduler(ex, budget, slots, WallClock(), progress=_progress if progress else None)
     t0 = sched.clock.now()
-    recs = sched.run(reqs)
+    try:
+        recs = sched.run(reqs)
+    finally:
+        ex.close()
     torch.cuda.synchronize()
     makespan = max(r.done for r in recs) - t0
     out = summarize(recs, makespan)
@@ -550,6 +590,8 @@ def main(argv=None):
     ap.add_argument("--leaf", default="auto",
                     help="leaf size 8, 16 or 32, or auto: the autotuner picks per request class")
     ap.add_argument("--tune-table", default=None, help="JSON table of the autotuner to load and update")
+    ap.add_argument("--no-threads", action="store_true",
+                    help="streams mode: drive every slot from the main thread")
     args = ap.parse_args(argv)
     if args.leaf == "auto":
         from .tune import LeafTuner
@@ -568,17 +610,20 @@ def main(argv=None):
     if args.workload == "evaluate":
         burst = evaluate_requests(args.requests, math.inf, n_max_side=args.max_side)
         pretune(burst)
-        _, closed = serve(burst, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True)
+        _, closed = serve(burst, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True,
+                             threads=not args.no_threads)
         rate = args.load * closed["requests_per_s"]
         reqs = evaluate_requests(args.requests, rate, n_max_side=args.max_side)
-        _, opened = serve(reqs, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True)
+        _, opened = serve(reqs, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True,
+                             threads=not args.no_threads)
         res = {"workload": "evaluate", "mode": args.mode, "slots": args.slots, "leaf": args.leaf,
                "budget_bytes": budget, "saturated": closed, "arrival_rate_per_s": rate,
                "poisson": opened}
     else:
         reqs = integrate_requests(args.requests, args.steps, n_max_side=args.max_side)
         pretune(reqs)
-        recs, out = serve(reqs, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True)
+        recs, out = serve(reqs, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True,
+                             threads=not args.no_threads)
         steps = sum(r.info.get("steps", 0) for r in recs if not r.error)
         res = {"workload": "integrate", "mode": args.mode, "slots": args.slots, "leaf": args.leaf,
                "budget_bytes": budget, "steps_per_request": args.steps, "result": out,
