@@ -90,15 +90,18 @@ class _CParams(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("ccfl", ctypes.c_double), ("periodic", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("lo", ctypes.c_double * 3),
-                ("hi", ctypes.c_double * 3)]
+                ("ac_signal", ctypes.c_int32), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("alpha_ac", ctypes.c_double)]
 
 
 @dataclass
 class Params:
     """Method parameters.  Defaults: eta = 1.2 (section 2.1.1), gamma = 5/3,
     alpha_AV = 1, beta_AV = 2 alpha_AV (section 2.1.1), C_CFL = 0.2
-    (section 2.1.4)."""
+    (section 2.1.4), no artificial conductivity (alpha_AC = 0; eq.
+    EQN:MON97ENERGYDISS).  ac_signal picks the conductivity signal speed:
+    0 = Wadsley 2008 |v_ij . rhat_ij| (the paper's default), 1 = Price 2008
+    sqrt(|P_i - P_j| / rhobar_ij)."""
     eta: float = 1.2
     gamma: float = 5.0 / 3.0
     alpha: float = 1.0
@@ -107,12 +110,15 @@ class Params:
     periodic: bool = True
     lo: tuple = (0.0, 0.0, 0.0)
     hi: tuple = (1.0, 1.0, 1.0)
+    alpha_ac: float = 0.0
+    ac_signal: int = 0
 
     def c(self) -> _CParams:
         p = _CParams()
         p.eta, p.gamma, p.alpha, p.beta, p.ccfl = self.eta, self.gamma, self.alpha, self.beta, self.ccfl
         p.periodic = 1 if self.periodic else 0
-        p.pad_ = 0
+        p.ac_signal = int(self.ac_signal)
+        p.alpha_ac = float(self.alpha_ac)
         for k in range(3):
             p.lo[k] = float(self.lo[k])
             p.hi[k] = float(self.hi[k])

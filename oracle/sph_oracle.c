@@ -39,8 +39,9 @@ typedef struct {
     double beta;     /* beta_AV (= 2 alpha_AV in the paper) */
     double ccfl;     /* C_CFL, eq. EQN:SPH_DT */
     int32_t periodic;
-    int32_t pad_;
+    int32_t ac_signal; /* conductivity signal speed: 0 Wadsley 2008, 1 Price 2008 */
     double lo[3], hi[3];
+    double alpha_ac; /* alpha_AC, eq. EQN:MON97ENERGYDISS (0: no conductivity) */
 } orc_params;
 
 /* ---------------------------------------------------------------------------
@@ -296,8 +297,8 @@ void orc_eos(int64_t n, double gamma, const double *rho, const double *u,
 
 /* ---------------------------------------------------------------------------
  * Force loop (eqs. EQN:GRADHMOMEQN, EQN:GRADHENEQN, EQN:MON97ARTVISC,
- * EQN:MON97ENERGYDISS with alpha_AC = 0) and the signal speed / CFL step
- * (eq. EQN:SPH_DT and the v_sig definition beside it).
+ * EQN:MON97ENERGYDISS) and the signal speed / CFL step (eq. EQN:SPH_DT and
+ * the v_sig definition beside it).
  *
  * For every j != i with r_ij < 2 max(h_i, h_j) (both W(h_i) and W(h_j)
  * appear in the momentum equation):
@@ -312,6 +313,13 @@ void orc_eos(int64_t n, double gamma, const double *rho, const double *u,
  *     rhobar = (rho_i + rho_j)/2,  Gbar = (G_i + G_j)/2
  *     a_i  +=  (m_j / rhobar) alpha vs w Gbar
  *     du_i += -(m_j / rhobar) alpha vs w^2/2 rhat_ij . Gbar
+ *   artificial conductivity (second sum of eq. EQN:MON97ENERGYDISS, every
+ *   pair, whatever the sign of w):
+ *     v'  =  |w|                           (Wadsley 2008, ac_signal = 0)
+ *         =  sqrt(|P_i - P_j| / rhobar)    (Price 2008, ac_signal = 1)
+ *     du_i += (m_j / rhobar) alpha_AC v' (u_i - u_j) rhat_ij . Gbar
+ *   (rhat_ij . Gbar is the mean of the two dW/dr, <= 0, so heat flows from
+ *   the hotter particle to the colder one)
  * Coincident pairs (r_ij = 0) add nothing to a or du and enter vsig with
  * w = 0.  With no neighbour at all vsig_i = 2 c_i (the self-pair value).
  * dt_i = C_CFL h_i / vsig_i.
@@ -371,6 +379,12 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
                 double gbar = 0.5 * (gi + gj);
                 cvec += (m[j] / rhobar) * p->alpha * vs * w * gbar;
                 cdu += -(m[j] / rhobar) * p->alpha * vs * 0.5 * w * w * gbar;
+            }
+            if (p->alpha_ac != 0.0) {
+                double rhobar = 0.5 * (rho[i] + rho[j]);
+                double gbar = 0.5 * (gi + gj);
+                double vc = p->ac_signal == 1 ? sqrt(fabs(Pi - Pj) / rhobar) : fabs(w);
+                cdu += (m[j] / rhobar) * p->alpha_ac * vc * (u[i] - u[j]) * gbar;
             }
             axi += cvec * ex;
             ayi += cvec * ey;

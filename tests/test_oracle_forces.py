@@ -190,3 +190,73 @@ def test_coincident_pair_adds_nothing_to_forces(orc):
     out = orc.forces(p, [0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [1.0, -1.0], [0.0, 0.0],
                      [0.0, 0.0], one, one, one, one, one)
     assert out["ax"][0] == 0.0 and out["dudt"][0] == 0.0 and out["nforce"][0] == 1
+
+
+# --- artificial conductivity (second sum of eq. EQN:MON97ENERGYDISS) --------
+
+def _hot_cold_pair(orc, signal):
+    # Worked example.  x1 - x2 = 1 along x; m = 1, Omega = 1; rho_1 = 1,
+    # rho_2 = 3 (rhobar = 2); h_1 = 1, h_2 = 0.8; v1 = -0.25, v2 = +0.25
+    # (w = v12 . rhat = -0.5); u_1 = 2, u_2 = 1; gamma = 5/3, so P_1 = 4/3,
+    # P_2 = 2.  dW/dr(1, 1) = f'(1)/pi = -(3/4)/pi; dW/dr(1, 0.8) =
+    # f'(1.25)/(0.8^4 pi) = -(27/64)(625/256)/pi = -(16875/16384)/pi;
+    # rhat . Gbar = -(29163/32768)/pi.  The conductivity part of du_1 is
+    # (m/rhobar) alpha_AC v' (u_1 - u_2) rhat . Gbar = (1/2) v' (-29163/32768)/pi
+    # and du_2 gets the opposite value (m equal, rhat . Gbar symmetric).
+    p = _params(orc, periodic=False, alpha_ac=1.0, ac_signal=signal)
+    p0 = _params(orc, periodic=False, alpha_ac=0.0, ac_signal=signal)
+    args = ([0.5, -0.5], [0.0, 0.0], [0.0, 0.0], [-0.25, 0.25], [0.0, 0.0], [0.0, 0.0],
+            [1.0, 1.0], [2.0, 1.0], [1.0, 0.8], [1.0, 3.0], [1.0, 1.0])
+    return orc.forces(p, *args), orc.forces(p0, *args)
+
+
+@pytest.mark.parametrize("signal,vprime", [(0, 0.5), (1, 1.0 / math.sqrt(3.0))])
+def test_conductivity_two_particles_by_hand(orc, signal, vprime):
+    # v' = |w| = 1/2 (Wadsley 2008); v' = sqrt(|P_1 - P_2| / rhobar) =
+    # sqrt((2/3) / 2) = 1/sqrt(3) (Price 2008)
+    on, off = _hot_cold_pair(orc, signal)
+    want = 0.5 * vprime * (-29163.0 / 32768.0) / math.pi
+    assert on["dudt"][0] - off["dudt"][0] == pytest.approx(want, rel=1e-13)
+    assert on["dudt"][1] - off["dudt"][1] == pytest.approx(-want, rel=1e-13)
+    for k in ("ax", "ay", "az", "vsig", "dt"):
+        np.testing.assert_array_equal(on[k], off[k])
+
+
+def _mixed_gas(orc, seed):
+    # the small periodic workload with unequal masses and a spread of u
+    w = W.config0()
+    a = dict(w.arrays)
+    rng = np.random.default_rng(seed)
+    a["m"] = a["m"] * rng.uniform(0.5, 1.5, w.n)
+    a["u"] = a["u"] * rng.uniform(0.2, 3.0, w.n)
+    return a
+
+
+@pytest.mark.parametrize("signal", [0, 1])
+def test_conductivity_conserves_energy_and_moves_heat_downhill(orc, signal):
+    a = _mixed_gas(orc, 5)
+    p0 = _params(orc)
+    off = _eval(orc, p0, a)
+    on = orc.forces(_params(orc, alpha_ac=1.0, ac_signal=signal), a["x"], a["y"], a["z"],
+                    a["vx"], a["vy"], a["vz"], a["m"], a["u"], off["h"], off["rho"],
+                    off["omega"])
+    m, u = a["m"], a["u"]
+    d = on["dudt"] - off["dudt"]
+    assert np.count_nonzero(d) > 0.9 * len(d)
+    # pairwise antisymmetric: the conductivity only moves thermal energy
+    assert abs(np.sum(m * d)) <= 1e-13 * np.sum(m * np.abs(d))
+    # and only from hotter to colder particles:
+    # sum_i m_i u_i du_i = 1/2 sum_ij m_i m_j/rhobar alpha v' (u_i - u_j)^2 rhat.Gbar <= 0
+    assert np.sum(m * u * d) < 0.0
+    for k in ("ax", "ay", "az", "vsig"):
+        np.testing.assert_array_equal(on[k], off[k])
+
+
+@pytest.mark.parametrize("signal", [0, 1])
+def test_conductivity_vanishes_for_uniform_u(orc, signal):
+    w = W.config0()
+    a = {**w.arrays, "u": np.full(w.n, 1.7)}
+    off = _eval(orc, _params(orc), a)
+    on = _eval(orc, _params(orc, alpha_ac=1.0, ac_signal=signal), a)
+    assert np.count_nonzero(off["dudt"]) > 0
+    np.testing.assert_array_equal(on["dudt"], off["dudt"])
