@@ -71,11 +71,22 @@ typedef enum {
 
 enum { SPH_FP64 = 0, SPH_FP32_PAIR = 1 };
 
+/* artificial-conductivity signal speed v'_SIG (section 2.1.2) */
+enum { SPH_AC_WADSLEY = 0, SPH_AC_PRICE = 1 };
+
 /*
  * Method parameters.  Defaults (sph_default_params): eta = 1.2 (section
  * 2.1.1), gamma = 5/3, alpha_av = 1, beta_av = 2 alpha_av (section 2.1.1),
  * c_cfl = 0.2 (section 2.1.4), h_rtol = 1e-12, h_max_iter = 50, periodic
- * unit box, FP64, leaf_size 16.
+ * unit box, FP64, leaf_size 16, no artificial conductivity (alpha_ac = 0,
+ * ac_signal = SPH_AC_WADSLEY).
+ *
+ * Artificial conductivity (second sum of eq. EQN:MON97ENERGYDISS): with
+ * alpha_ac > 0 every force pair adds
+ *   du_i/dt += (m_j / rhobar_ij) alpha_ac v' (u_i - u_j) rhat_ij . gradW_bar_ij
+ * to du/dt; accelerations, v_sig and dt do not change.  The kernel rebuilds
+ * u_j and P_j from the adiabatic EOS (u = c^2 / (gamma (gamma - 1)),
+ * P = rho c^2 / gamma).
  *
  * precision = SPH_FP64: every pair term in double precision.
  * precision = SPH_FP32_PAIR: pair separations are formed in single precision
@@ -100,6 +111,9 @@ typedef struct {
     double box_hi[3];
     int32_t precision; /* SPH_FP64 or SPH_FP32_PAIR */
     int32_t leaf_size; /* particles per tree leaf: 8, 16 or 32 */
+    double alpha_ac;   /* artificial conductivity strength (>= 0; 0 disables it) */
+    int32_t ac_signal; /* SPH_AC_WADSLEY: v' = |v_ij . rhat_ij| (the paper's
+                          default); SPH_AC_PRICE: v' = sqrt(|P_i - P_j| / rhobar_ij) */
 } sph_params;
 
 /*

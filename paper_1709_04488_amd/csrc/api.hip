@@ -51,6 +51,10 @@ sph_status check_params(sph_ctx *c, const sph_params *p)
         return fail(c, SPH_EINVAL, "precision must be SPH_FP64 or SPH_FP32_PAIR");
     if (p->leaf_size != 8 && p->leaf_size != 16 && p->leaf_size != 32)
         return fail(c, SPH_EINVAL, "leaf_size must be 8, 16 or 32");
+    if (!(p->alpha_ac >= 0.0) || !std::isfinite(p->alpha_ac))
+        return fail(c, SPH_EINVAL, "alpha_ac must be finite and >= 0");
+    if (p->ac_signal != SPH_AC_WADSLEY && p->ac_signal != SPH_AC_PRICE)
+        return fail(c, SPH_EINVAL, "ac_signal must be SPH_AC_WADSLEY or SPH_AC_PRICE");
     if (p->periodic)
         for (int a = 0; a < 3; a++)
             if (!(p->box_hi[a] > p->box_lo[a]) || !std::isfinite(p->box_hi[a] - p->box_lo[a]))
@@ -549,6 +553,8 @@ void sph_default_params(sph_params *p)
     for (int a = 0; a < 3; a++) { p->box_lo[a] = 0.0; p->box_hi[a] = 1.0; }
     p->precision = SPH_FP64;
     p->leaf_size = 16;
+    p->alpha_ac = 0.0;
+    p->ac_signal = SPH_AC_WADSLEY;
 }
 
 sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size_t budget)

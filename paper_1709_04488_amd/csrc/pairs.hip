@@ -1089,10 +1089,16 @@ struct ForceArgs {
     int32_t *status;
     int64_t *counts;
     double alpha, beta, ccfl;
+    // artificial conductivity: strength, 1 / (gamma (gamma - 1)), 1 / gamma,
+    // and the signal speed (0: |v_ij . rhat_ij|, 1: sqrt(|P_i - P_j| / rhobar))
+    double alpha_ac, u_per_c2, inv_gamma;
+    int32_t ac_price;
     int32_t count_tests;    // also count box and candidate tests (diagnostics)
 };
 
-template <int G, int PREC>
+// AC: the launch carries artificial conductivity (some set of the batch has
+// alpha_AC > 0; a set with alpha_AC = 0 then adds exact zeros)
+template <int G, int PREC, bool AC>
 __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(Batch<ForceArgs> B)
 {
     constexpr int LPP = kWave / G;
@@ -1132,6 +1138,9 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         const int64_t leaf = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
         const Box bx = load_const(&B.req[r]->box);
         const double alpha = F.alpha, beta = F.beta;
+        const double alpha_ac = AC ? F.alpha_ac : 0.0, u_per_c2 = AC ? F.u_per_c2 : 0.0;
+        const double inv_gamma = AC ? F.inv_gamma : 0.0;
+        const bool ac_price = AC && F.ac_price != 0;
         const int64_t first = as_const(F.lstart)[leaf];
         const int nhome = (int)(as_const(F.lstart)[leaf + 1] - first);
         const int64_t i = first + p;
@@ -1230,10 +1239,19 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const double wneg = fmin(w, 0.0);
                     const double vs = (ci + cj) - beta * wneg;
                     vs_max = fmax(vs_max, vs);
-                    const double visc = (mj * rcp_nr(0.5 * (rhoi + d.rho))) * alpha * vs * wneg;
+                    const double rbinv = rcp_nr(0.5 * (rhoi + d.rho));
+                    const double visc = (mj * rbinv) * alpha * vs * wneg;
                     const double gbar = 0.5 * gsum;
                     cvec += visc * gbar;
                     cdu -= visc * 0.5 * wneg * gbar;
+                    if constexpr (AC) {
+                        // u and P of both particles from their sound speeds
+                        const double c2i = ci * ci, c2j = cj * cj;
+                        const double vc = ac_price
+                            ? sqrt(fabs(rhoi * c2i - d.rho * c2j) * inv_gamma * rbinv)
+                            : fabs(w);
+                        cdu += (mj * rbinv) * alpha_ac * vc * ((c2i - c2j) * u_per_c2) * gbar;
+                    }
                     axi += cvec * ex;
                     ayi += cvec * ey;
                     azi += cvec * ez;
@@ -1265,11 +1283,21 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const float wneg = fminf(w, 0.0f);
                     const float vs = (cif + cjf) - (float)beta * wneg;
                     vs_max = fmax(vs_max, (double)vs);
-                    const float visc = (mj * __builtin_amdgcn_rcpf(0.5f * ((float)rhoi + (float)d.rho))) *
-                                       (float)alpha * vs * wneg;
+                    const float rbinv = __builtin_amdgcn_rcpf(0.5f * ((float)rhoi + (float)d.rho));
+                    const float visc = (mj * rbinv) * (float)alpha * vs * wneg;
                     const float gbar = 0.5f * gsum;
                     cvec += visc * gbar;
                     cdu -= visc * 0.5f * wneg * gbar;
+                    if constexpr (AC) {
+                        // differences of u and P formed in double precision
+                        const double c2i = ci * ci, c2j = cj * cj;
+                        const float du_ij = (float)((c2i - c2j) * u_per_c2);
+                        const float vc =
+                            ac_price
+                                ? sqrtf((float)(fabs(rhoi * c2i - d.rho * c2j) * inv_gamma) * rbinv)
+                                : fabsf(w);
+                        cdu += (mj * rbinv) * (float)alpha_ac * vc * du_ij * gbar;
+                    }
                     axi += (double)(cvec * ex);
                     ayi += (double)(cvec * ey);
                     azi += (double)(cvec * ez);
@@ -1569,6 +1597,10 @@ sph_status forces_prepare(sph_ctx *c, int64_t n)
     a.status = c->d_status;
     a.counts = c->d_counts;
     a.alpha = c->p.alpha_av; a.beta = c->p.beta_av; a.ccfl = c->p.c_cfl;
+    a.alpha_ac = c->p.alpha_ac;
+    a.u_per_c2 = 1.0 / (c->p.gamma * (c->p.gamma - 1.0));
+    a.inv_gamma = 1.0 / c->p.gamma;
+    a.ac_price = c->p.ac_signal == SPH_AC_PRICE ? 1 : 0;
     a.count_tests = c->count_tests ? 1 : 0;
     const void *req[] = {a.nodes, a.x, a.y, a.z, a.h, a.rec, a.ax, a.ay, a.az, a.du, a.vsig,
                          a.dt, a.nforce, a.status, a.counts, a.tree, a.lstart, a.work,
@@ -1652,21 +1684,25 @@ sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax)
     (void)nmax;
     const unsigned grid = pair_grid(leaves_bound);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
+    bool ac = false;
+    for (int r = 0; r < count; r++) ac = ac || cs[r]->p.alpha_ac != 0.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_begin(c, 1, &e0, &e1);
+    auto launch = [&](auto g) {
+        constexpr int G = decltype(g)::value;
+        if (f32 && ac)
+            hipLaunchKernelGGL((k_forces<G, SPH_FP32_PAIR, true>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        else if (f32)
+            hipLaunchKernelGGL((k_forces<G, SPH_FP32_PAIR, false>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        else if (ac)
+            hipLaunchKernelGGL((k_forces<G, SPH_FP64, true>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        else
+            hipLaunchKernelGGL((k_forces<G, SPH_FP64, false>), dim3(grid), dim3(kWave), 0, c->stream, B);
+    };
     switch (c->p.leaf_size) {
-    case 8:
-        if (f32) hipLaunchKernelGGL((k_forces<8, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, B);
-        else hipLaunchKernelGGL((k_forces<8, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, B);
-        break;
-    case 32:
-        if (f32) hipLaunchKernelGGL((k_forces<32, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, B);
-        else hipLaunchKernelGGL((k_forces<32, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, B);
-        break;
-    default:
-        if (f32) hipLaunchKernelGGL((k_forces<16, SPH_FP32_PAIR>), dim3(grid), dim3(kWave), 0, c->stream, B);
-        else hipLaunchKernelGGL((k_forces<16, SPH_FP64>), dim3(grid), dim3(kWave), 0, c->stream, B);
-        break;
+    case 8: launch(std::integral_constant<int, 8>{}); break;
+    case 32: launch(std::integral_constant<int, 32>{}); break;
+    default: launch(std::integral_constant<int, 16>{}); break;
     }
     timer_end(c, 1, e0, e1);
     return hip_check(c, hipGetLastError(), "force kernel");

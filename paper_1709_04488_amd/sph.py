@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsph.so")
 SPH_OK, SPH_EINVAL, SPH_ENOMEM, SPH_EDEVICE, SPH_ENOTCONVERGED = 0, -1, -2, -3, -4
 SPH_ESTENCIL, SPH_ENONFINITE, SPH_EBUDGET, SPH_ECAP, SPH_ESTATE = -5, -6, -7, -8, -9
 SPH_FP64, SPH_FP32_PAIR = 0, 1
+SPH_AC_WADSLEY, SPH_AC_PRICE = 0, 1
 
 STATUS_NAMES = {0: "SPH_OK", -1: "SPH_EINVAL", -2: "SPH_ENOMEM", -3: "SPH_EDEVICE",
                 -4: "SPH_ENOTCONVERGED", -5: "SPH_ESTENCIL", -6: "SPH_ENONFINITE",
@@ -46,7 +47,8 @@ class _Params(ctypes.Structure):
                 ("c_cfl", ctypes.c_double), ("h_rtol", ctypes.c_double),
                 ("h_max_iter", ctypes.c_int32), ("periodic", ctypes.c_int32),
                 ("box_lo", ctypes.c_double * 3), ("box_hi", ctypes.c_double * 3),
-                ("precision", ctypes.c_int32), ("leaf_size", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
+                ("alpha_ac", ctypes.c_double), ("ac_signal", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -141,10 +143,13 @@ class Params:
     hi: tuple = (1.0, 1.0, 1.0)
     precision: int = SPH_FP64
     leaf_size: int = 16
+    alpha_ac: float = 0.0
+    ac_signal: int = SPH_AC_WADSLEY
 
     @classmethod
     def from_setup(cls, setup: dict, **kw) -> "Params":
-        keys = ("eta", "gamma", "alpha", "beta", "ccfl", "periodic", "lo", "hi")
+        keys = ("eta", "gamma", "alpha", "beta", "ccfl", "periodic", "lo", "hi", "alpha_ac",
+                "ac_signal")
         return cls(**{k: setup[k] for k in keys if k in setup}, **kw)
 
     def c(self) -> _Params:
@@ -158,6 +163,8 @@ class Params:
             p.box_hi[k] = float(self.hi[k])
         p.precision = int(self.precision)
         p.leaf_size = int(self.leaf_size)
+        p.alpha_ac = float(self.alpha_ac)
+        p.ac_signal = int(self.ac_signal)
         return p
 
 

@@ -54,12 +54,15 @@ def test_default_params_match_paper_values():
     assert d["beta_av"] == g["beta_over_alpha_av"] * d["alpha_av"]
     assert d["c_cfl"] == g["ccfl_typical"]
     assert d["leaf_size"] in (8, 16, 32)
+    # no conductivity unless asked for; the paper's default signal speed
+    assert d["alpha_ac"] == 0.0 and d["ac_signal"] == sph.SPH_AC_WADSLEY
 
 
 def test_struct_layouts_match_header():
     # sizes of the ABI structs as the C compiler lays them out
     from paper_1709_04488_amd import sph
-    assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4
+    # ... + alpha_ac, ac_signal and 4 bytes of tail padding
+    assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4 + 8 + 4 + 4
     assert ctypes.sizeof(sph._Particles) == 8 + 21 * 8
     assert ctypes.sizeof(sph._Stats) == 8 * 8 + 5 * 8 + 8 + 2 * 8 + 5 * 8
 

@@ -93,6 +93,40 @@ def test_batch_matches_oracle(sph, orc):
         c.close()
 
 
+def test_batch_with_conductivity_in_one_set(sph, orc):
+    """One set with alpha_AC = 1 makes the launch carry the conductivity
+    term; it equals that set alone bit for bit, and the sets with alpha_AC =
+    0 (which then add exact zeros) match the oracle."""
+    sets = [w for w, _, _ in _mix()[:3]]
+    setups = [{**sets[0].setup, "alpha_ac": 1.0, "ac_signal": 1}, sets[1].setup, sets[2].setup]
+    mix = list(zip(sets, setups))
+    print("case: batch of 3 sets, the first with alpha_ac = 1", flush=True)
+    with sph.Context(sph.Params.from_setup(setups[0], precision=0)) as ctx:
+        p0 = sph.Particles.from_host(sets[0].arrays)
+        ctx.evaluate(p0)
+        ctx.sync()
+        alone = p0.host()
+    stream = torch.cuda.current_stream()
+    ctxs = [sph.Context(sph.Params.from_setup(st, precision=0), stream=stream) for st in setups]
+    parts = [sph.Particles.from_host(w.arrays) for w in sets]
+    sph.batch_evaluate(ctxs, parts)
+    for c in ctxs:
+        c.sync()
+    outs = [p.host() for p in parts]
+    for f in _fields():
+        assert np.array_equal(outs[0][f], alone[f]), f
+    for (w, st), out in zip(mix, outs):
+        a = w.arrays
+        ref = orc.evaluate(orc.Params(**st), a["x"], a["y"], a["z"], a["vx"], a["vy"], a["vz"],
+                           a["m"], a["u"], a["h"])
+        for k in ("ax", "ay", "az"):
+            assert np.max(np.abs(out[k] - ref[k]) / ref["scale_a"]) < 1e-10, (w.name, k)
+        assert np.max(np.abs(out["dudt"] - ref["dudt"]) / ref["scale_u"]) < 1e-10, w.name
+        assert np.array_equal(out["nforce"], ref["nforce"])
+    for c in ctxs:
+        c.close()
+
+
 def test_batch_step_equals_single_steps(sph):
     mix = [(W.jittered_lattice(8, seed=11), 0, 16), (W.blob_in_lattice(10, seed=12), 0, 16),
            (W.jittered_lattice(9, seed=13), 1, 16)]

@@ -139,6 +139,36 @@ def test_unequal_masses(sph, orc, precision):
                label="unequal m fp32", field_tol=FP32_FIELD_TOL)
 
 
+def _hot_cold_gas(n, seed, **setup):
+    # a Poisson gas with unequal masses and u spread over a factor 15
+    rng = np.random.default_rng(seed)
+    a = {"x": rng.uniform(0, 1, n), "y": rng.uniform(0, 1, n), "z": rng.uniform(0, 1, n),
+         "vx": rng.normal(0, 0.3, n), "vy": rng.normal(0, 0.3, n), "vz": rng.normal(0, 0.3, n),
+         "m": rng.uniform(0.5, 1.5, n) / n, "u": rng.uniform(0.2, 3.0, n),
+         "h": np.full(n, 0.085)}
+    return W.Workload(f"hotcold{n}", a, {**W.default_setup(), **setup})
+
+
+@pytest.mark.parametrize("signal", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_artificial_conductivity(sph, orc, precision, signal):
+    """alpha_AC = 1 (second sum of eq. MON97ENERGYDISS) with the Wadsley
+    (signal 0) or Price (signal 1) signal speed."""
+    w = _hot_cold_gas(2500, 95, alpha_ac=1.0, ac_signal=signal)
+    print("case: hot-cold gas N=2500 alpha_ac=1 signal=%d precision=%d" % (signal, precision),
+          flush=True)
+    ref = _oracle_eval(orc, w)
+    # the term is large here, so the comparison is not vacuous
+    off = _oracle_eval(orc, w, alpha_ac=0.0)
+    assert np.median(np.abs(ref["dudt"] - off["dudt"]) / ref["scale_u"]) > 1e-2
+    out = _gpu_eval(sph, w, precision=precision)
+    if precision == 0:
+        _check(out, ref, label=f"ac{signal} fp64")
+    else:
+        _check(out, ref, tol=FP32_TOL, atol=FP32_ATOL, counts_exact=False,
+               label=f"ac{signal} fp32", field_tol=FP32_FIELD_TOL)
+
+
 def test_open_boundary_plummer(sph, orc):
     w = W.plummer(2500, seed=31)
     print("case: plummer N=2500 open", flush=True)
@@ -258,9 +288,11 @@ def test_nan_input_reports_nonfinite(sph):
 
 
 def test_bad_arguments_are_rejected(sph):
-    with pytest.raises(sph.SphError) as e:
-        sph.Context(sph.Params(leaf_size=12))
-    assert e.value.code == sph.SPH_EINVAL
+    for bad in ({"leaf_size": 12}, {"alpha_ac": -1.0}, {"alpha_ac": float("inf")},
+                {"ac_signal": 2}):
+        with pytest.raises(sph.SphError) as e:
+            sph.Context(sph.Params(**bad))
+        assert e.value.code == sph.SPH_EINVAL, bad
     with sph.Context(sph.Params()) as ctx:
         p = sph.Particles.from_host(W.jittered_lattice(6, seed=1).arrays)
         p.t["rho"] = None
