@@ -16,7 +16,8 @@
  *   force loop        -- grad-h momentum and energy equations (eqs.
  *                        EQN:GRADHMOMEQN, EQN:GRADHENEQN) with Monaghan
  *                        artificial viscosity (eqs. EQN:MON97ARTVISC,
- *                        EQN:MON97ENERGYDISS, alpha_AC = 0), the signal speed
+ *                        EQN:MON97ENERGYDISS) and optional artificial
+ *                        conductivity (EQN:MON97ENERGYDISS), the signal speed
  *                        and the CFL time-step (eq. EQN:SPH_DT)
  *   time integration  -- kick-drift-kick leapfrog (eqs. EQN:LFKDK1/EQN:LFKDK2)
  *
@@ -71,7 +72,7 @@ typedef enum {
 
 enum { SPH_FP64 = 0, SPH_FP32_PAIR = 1 };
 
-/* artificial-conductivity signal speed v'_SIG (section 2.1.2) */
+/* artificial-conductivity signal speed v'_SIG (section 2.1.1) */
 enum { SPH_AC_WADSLEY = 0, SPH_AC_PRICE = 1 };
 
 /*
@@ -223,7 +224,8 @@ sph_status sph_density(sph_ctx *ctx, sph_particles *ps);
 
 /*
  * Force loop (eqs. EQN:GRADHMOMEQN, EQN:GRADHENEQN, EQN:MON97ARTVISC,
- * EQN:MON97ENERGYDISS with alpha_AC = 0; signal speed and eq. EQN:SPH_DT).
+ * EQN:MON97ENERGYDISS, the conductivity term when alpha_ac > 0; signal speed
+ * and eq. EQN:SPH_DT).
  * Reads x, y, z, v, m, u, h, rho, omega; writes ax, ay, az, dudt, vsig, dt
  * and, if non-NULL, nforce.  Pairs with r_ij = 0 add nothing to a or du/dt.
  * Reuses the neighbour structure of the last sph_density / sph_build_cells

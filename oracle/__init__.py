@@ -13,7 +13,8 @@ Functions and the passages they follow (GANDALF paper, arXiv:1709.04488):
 * ``density``    -- eqs. EQN:SPHRHO, EQN:HRHO, EQN:OMEGA (section 2.1.1).
 * ``eos``        -- ideal gas P = (gamma-1) rho u (below EQN:GRADHMOMEQN).
 * ``forces``     -- eqs. EQN:GRADHMOMEQN, EQN:GRADHENEQN, EQN:MON97ARTVISC,
-  EQN:MON97ENERGYDISS (alpha_AC = 0), signal speed and EQN:SPH_DT.
+  EQN:MON97ENERGYDISS (artificial viscosity, and artificial conductivity
+  when alpha_ac > 0), signal speed and EQN:SPH_DT.
 * ``neighbours`` -- the neighbour sets those sums run over.
 * ``kdk``        -- eqs. EQN:LFKDK1/EQN:LFKDK2 with the section 5.1 loop order.
 * ``sampled_evaluation`` -- the same quantities for a few particles of a
