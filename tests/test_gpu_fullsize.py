@@ -99,3 +99,20 @@ def test_full_size_sampled_parity(sph, sets, oracle_ref, name, precision):
         _compare(out, s, fs, ref, FP64_TOL, FP64_TOL, {}, True, f"{name} fp64")
     else:
         _compare(out, s, fs, ref, FP32_TOL, FP32_ATOL, FP32_FIELD_TOL, False, f"{name} fp32")
+
+
+@pytest.mark.parametrize("precision,signal", [(0, 0), (1, 1)])
+def test_full_size_conductivity(sph, orc, sets, precision, signal):
+    """The 2,097,152-particle set with artificial conductivity (alpha_AC = 1;
+    Wadsley signal speed in FP64, Price in FP32-pair), same sample."""
+    w0 = sets["blob"]
+    w = W.Workload(w0.name, w0.arrays, {**w0.setup, "alpha_ac": 1.0, "ac_signal": signal})
+    s, fs = _sample(w, 77)
+    ref = orc.sampled_evaluation(orc.Params(**w.setup), w.arrays, s, fs)
+    print(f"case: full size {w.name} N={w.n} alpha_ac=1 signal={signal} precision={precision}",
+          flush=True)
+    out = _gpu(sph, w, precision)
+    if precision == 0:
+        _compare(out, s, fs, ref, FP64_TOL, FP64_TOL, {}, True, f"ac{signal} fp64")
+    else:
+        _compare(out, s, fs, ref, FP32_TOL, FP32_ATOL, FP32_FIELD_TOL, False, f"ac{signal} fp32")

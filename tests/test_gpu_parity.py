@@ -313,13 +313,17 @@ def test_budget_is_enforced(sph):
         assert e.value.code == sph.SPH_EBUDGET
 
 
-def test_kdk_steps_match_oracle(sph, orc):
+@pytest.mark.parametrize("ac", [None, 0, 1])
+def test_kdk_steps_match_oracle(sph, orc, ac):
+    # ac: artificial conductivity off, or alpha_AC = 1 with that signal speed
     w = W.jittered_lattice(10, seed=21)
+    if ac is not None:
+        w = W.Workload(w.name, w.arrays, {**w.setup, "alpha_ac": 1.0, "ac_signal": ac})
     a = w.arrays
     nsteps = 10
     st, energy, dts = orc.kdk(orc.Params(**w.setup), a["x"], a["y"], a["z"], a["vx"], a["vy"],
                               a["vz"], a["m"], a["u"], a["h"], nsteps, 0.0)
-    print("case: kdk N=%d steps=%d" % (w.n, nsteps), flush=True)
+    print("case: kdk N=%d steps=%d ac=%s" % (w.n, nsteps, ac), flush=True)
     with sph.Context(sph.Params.from_setup(w.setup)) as ctx:
         p = sph.Particles.from_host(a)
         ctx.upload_state(p)

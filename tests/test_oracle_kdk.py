@@ -67,10 +67,13 @@ def test_second_order_convergence(orc):
     assert 3.2 < ratio < 4.8
 
 
-def test_energy_conserved_without_dissipation(orc):
+@pytest.mark.parametrize("alpha_ac", [0.0, 1.0])
+def test_energy_conserved_without_dissipation(orc, alpha_ac):
+    # artificial conductivity only moves thermal energy between particles, so
+    # the total energy is still conserved to the integrator's order
     w = W.jittered_lattice(5, seed=12)
     a = w.arrays
-    p = _params(orc, alpha=0.0, beta=0.0)
+    p = _params(orc, alpha=0.0, beta=0.0, alpha_ac=alpha_ac)
     errs = []
     for dt in (2e-3, 1e-3):
         _, e, _ = _run(orc, p, a, int(round(0.02 / dt)), dt)

@@ -1,14 +1,16 @@
 """The sampled oracle (used at sizes where O(N^2) is out of reach) must give
 bit-for-bit the full brute-force values on sets small enough for both."""
 import numpy as np
+import pytest
 
 from paper_1709_04488_amd import workloads as W
 
 
-def test_sampled_equals_full_periodic(orc):
+@pytest.mark.parametrize("ac", [{}, {"alpha_ac": 1.0, "ac_signal": 1}])
+def test_sampled_equals_full_periodic(orc, ac):
     w = W.blob_in_lattice(12, seed=4)
     a = w.arrays
-    p = orc.Params(**w.setup)
+    p = orc.Params(**{**w.setup, **ac})
     full = orc.evaluate(p, a["x"], a["y"], a["z"], a["vx"], a["vy"], a["vz"], a["m"], a["u"], a["h"])
     sample = np.random.default_rng(0).choice(w.n, 12, replace=False)
     res = orc.sampled_evaluation(p, a, sample)
