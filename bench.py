@@ -61,11 +61,12 @@ def workload(name: str):
 
 
 def run_gpu(w, precision: int, steps: int, warmup: int, leaf: int, warm_start: bool = False,
-            h_rtol: float = None, count_tests: bool = True):
+            h_rtol: float = None, count_tests: bool = True, over: dict = None):
     import torch
     from paper_1709_04488_amd import sph
 
-    params = sph.Params.from_setup(w.setup, precision=precision, leaf_size=leaf)
+    params = sph.Params.from_setup({**w.setup, **(over or {})}, precision=precision,
+                                   leaf_size=leaf)
     if h_rtol is not None:
         params.h_rtol = h_rtol
     ctx = sph.Context(params)
@@ -279,6 +280,9 @@ def main():
         # (section 2.1.1); a throughput mode, never parity-checked
         results["fp64_paper_tol"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, leaf["fp64"],
                                             h_rtol=PAPER_H_RTOL)
+        # with artificial conductivity, the paper's default signal speed
+        results["fp64_ac"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, leaf["fp64"],
+                                     over={"alpha_ac": 1.0, "ac_signal": sph.SPH_AC_WADSLEY})
     if args.precision in ("fp32", "both"):
         results["fp32"] = run_gpu(w, sph.SPH_FP32_PAIR, args.steps, args.warmup, leaf["fp32"],
                                   count_tests=not args.main_only)
@@ -339,6 +343,13 @@ def main():
             "h_rtol": PAPER_H_RTOL, "value": r["value"], "ms_per_step": r["ms_per_step"],
             "nr_iter_mean": r["info"]["nr_iter_total"] / w.n,
             "note": "throughput mode with the paper's ~1 % h-rho tolerance; not parity-checked"}
+    if "fp64_ac" in results:
+        r = results["fp64_ac"]
+        out["fp64_conductivity"] = {
+            "alpha_ac": 1.0, "signal_speed": "wadsley", "value": r["value"],
+            "ms_per_step": r["ms_per_step"],
+            "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()},
+            "note": "same step with the artificial-conductivity term in the force loop"}
     if "fp32" in results and head_key != "fp32":
         r = results["fp32"]
         out["fp32_pair"] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
