@@ -198,7 +198,9 @@ sph_status sph_destroy(sph_ctx *ctx);
  * on the old stream, then subsequent calls enqueue on the new one. */
 sph_status sph_set_stream(sph_ctx *ctx, void *hip_stream);
 
-/* Replace the method parameters (same validation as sph_create). */
+/* Replace the method parameters (same validation as sph_create).  Drops the
+ * steps captured by sph_capture_steps (they carry the old parameters), after
+ * waiting for the context's stream; capture again to replay. */
 sph_status sph_set_params(sph_ctx *ctx, const sph_params *p);
 
 /*
@@ -271,7 +273,8 @@ sph_status sph_step(sph_ctx *ctx, double dt, double *dt_used);
  * executing them; sph_replay_steps launches it on the context's stream (two
  * steps per replay, results bit-for-bit those of two sph_step calls).  The
  * graph holds no memset or copy nodes.  Needs a resident state and a
- * non-null stream; a new upload or a reallocation drops the graph.
+ * non-null stream; a new upload, a reallocation or sph_set_params drops the
+ * graph.
  */
 sph_status sph_capture_steps(sph_ctx *ctx, double dt);
 sph_status sph_replay_steps(sph_ctx *ctx);

@@ -73,13 +73,19 @@ void set_box(sph_ctx *c)
     }
 }
 
-void free_all(sph_ctx *c)
+// release the captured step graph, if any
+void drop_graph(sph_ctx *c)
 {
-    // a captured graph refers to the buffers about to be freed
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     c->graph_exec = nullptr;
     c->graph = nullptr;
+}
+
+void free_all(sph_ctx *c)
+{
+    // a captured graph refers to the buffers about to be freed
+    drop_graph(c);
     for (void *ptr : c->allocs) (void)hipFree(ptr);
     c->allocs.clear();
     if (c->nodes) (void)hipFree(c->nodes);
@@ -136,10 +142,7 @@ static sph_status ensure_cache(sph_ctx *c)
     if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
     if (c->cache) {
         // a captured graph refers to the scratch about to be freed
-        if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-        if (c->graph) (void)hipGraphDestroy(c->graph);
-        c->graph_exec = nullptr;
-        c->graph = nullptr;
+        drop_graph(c);
         (void)hipFree(c->cache);
         c->bytes -= (size_t)c->cache_size;
         c->cache = nullptr;
@@ -603,10 +606,6 @@ sph_status sph_destroy(sph_ctx *c)
 {
     if (!c) return SPH_OK;
     (void)hipStreamSynchronize(c->stream);
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
     free_all(c);
     for (int w = 0; w < 3; w++)
         for (auto &pr : c->timer.pending[w]) c->timer.pool.push_back(pr);
@@ -640,6 +639,12 @@ sph_status sph_set_params(sph_ctx *c, const sph_params *p)
     if (!c) return SPH_EINVAL;
     TRY(check_params(c, p));
     bool regrow = p->leaf_size < c->p.leaf_size;
+    if (c->graph_exec || c->graph) {
+        // captured steps carry the old parameters (argument blocks and kernel
+        // variants): let any replay in flight finish, then drop them
+        TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+        drop_graph(c);
+    }
     c->p = *p;
     set_box(c);
     c->built = false;
@@ -737,10 +742,7 @@ sph_status sph_upload_state(sph_ctx *c, const sph_particles *ps)
     TRY(ensure_capacity(c, n));
     c->n = n;
     if (n == 0) return fail(c, SPH_EINVAL, "resident state needs n > 0");
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
+    drop_graph(c);
     TRY(build_order(c, n, ps->x, ps->y, ps->z));
     GatherList g{};
     const void *src[] = {ps->x, ps->y, ps->z, ps->vx, ps->vy, ps->vz, ps->m, ps->u, ps->h};
@@ -773,16 +775,6 @@ sph_status sph_step(sph_ctx *c, double dt, double *dt_used)
     TRY(forces_launch(&c, 1, c->n));
     return step_post(c, dt, dt_used);
 }
-
-namespace {
-void drop_graph(sph_ctx *c)
-{
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
-}
-} // namespace
 
 sph_status sph_capture_steps(sph_ctx *c, double dt)
 {

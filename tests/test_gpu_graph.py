@@ -68,3 +68,49 @@ def test_capture_needs_resident_state(sph):
         with pytest.raises(sph.SphError) as e:
             ctx.replay_steps()
         assert e.value.code == sph.SPH_ESTATE
+
+
+def test_set_params_drops_captured_steps(sph):
+    """Captured steps carry the parameters of their capture: sph_set_params
+    drops them, and steps captured again (after a new upload, whose initial
+    forces use the new parameters) with artificial conductivity on equal
+    eager steps with it on."""
+    w = W.blob_in_lattice(12, seed=32)
+    stream = torch.cuda.Stream()
+    p0 = sph.Params.from_setup(w.setup)
+    p1 = sph.Params.from_setup({**w.setup, "alpha_ac": 1.0, "ac_signal": sph.SPH_AC_PRICE})
+    eager = sph.Context(p1, stream=stream)
+    graph = sph.Context(p0, stream=stream)
+    with torch.cuda.stream(stream):
+        pe = sph.Particles.from_host(w.arrays)
+        pg = sph.Particles.from_host(w.arrays)
+    eager.upload_state(pe)
+    graph.upload_state(pg)
+    graph.capture_steps(0.0)
+    print("case: set_params after capture", flush=True)
+    graph.set_params(p1)
+    with pytest.raises(sph.SphError) as e:
+        graph.replay_steps()
+    assert e.value.code == sph.SPH_ESTATE
+    # the initial forces of the upload used the old parameters: upload again
+    with torch.cuda.stream(stream):
+        pg = sph.Particles.from_host(w.arrays)
+    graph.upload_state(pg)
+    graph.capture_steps(0.0)
+    for _ in range(2):
+        eager.step(0.0)
+        eager.step(0.0)
+        graph.replay_steps()
+    stream.synchronize()
+    with torch.cuda.stream(stream):
+        qe = sph.Particles.from_host(w.arrays)
+        qg = sph.Particles.from_host(w.arrays)
+    eager.download_state(qe)
+    graph.download_state(qg)
+    eager.sync()
+    graph.sync()
+    a, b = qe.host(), qg.host()
+    for f in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "rho", "ax", "dudt", "dt"):
+        assert np.array_equal(a[f], b[f]), f
+    eager.close()
+    graph.close()
