@@ -149,19 +149,20 @@ def _hot_cold_gas(n, seed, **setup):
     return W.Workload(f"hotcold{n}", a, {**W.default_setup(), **setup})
 
 
-@pytest.mark.parametrize("signal", [0, 1])
-@pytest.mark.parametrize("precision", [0, 1])
-def test_artificial_conductivity(sph, orc, precision, signal):
+@pytest.mark.parametrize("precision,signal,leaf", [
+    (0, 0, 16), (0, 1, 16), (1, 0, 16), (1, 1, 16),
+    (0, 1, 8), (1, 0, 8), (0, 0, 32), (1, 1, 32)])
+def test_artificial_conductivity(sph, orc, precision, signal, leaf):
     """alpha_AC = 1 (second sum of eq. MON97ENERGYDISS) with the Wadsley
-    (signal 0) or Price (signal 1) signal speed."""
+    (signal 0) or Price (signal 1) signal speed, every leaf size."""
     w = _hot_cold_gas(2500, 95, alpha_ac=1.0, ac_signal=signal)
-    print("case: hot-cold gas N=2500 alpha_ac=1 signal=%d precision=%d" % (signal, precision),
-          flush=True)
+    print("case: hot-cold gas N=2500 alpha_ac=1 signal=%d precision=%d leaf=%d"
+          % (signal, precision, leaf), flush=True)
     ref = _oracle_eval(orc, w)
     # the term is large here, so the comparison is not vacuous
     off = _oracle_eval(orc, w, alpha_ac=0.0)
     assert np.median(np.abs(ref["dudt"] - off["dudt"]) / ref["scale_u"]) > 1e-2
-    out = _gpu_eval(sph, w, precision=precision)
+    out = _gpu_eval(sph, w, precision=precision, leaf_size=leaf)
     if precision == 0:
         _check(out, ref, label=f"ac{signal} fp64")
     else:
