@@ -253,13 +253,7 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t *__res
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     int64_t src = identity ? k : (int64_t)perm[k];
-    for (int a = 0; a < g.count; a++) {
-        switch (g.kind[a]) {
-        case 0: ((double *)g.dst[a])[k] = ((const double *)g.src[a])[src]; break;
-        case 1: ((uint32_t *)g.dst[a])[k] = ((const uint32_t *)g.src[a])[src]; break;
-        default: ((float *)g.dst[a])[k] = ((const float *)g.src[a])[src]; break;
-        }
-    }
+    copy_listed(g, src, k);
 }
 
 __global__ void k_copy_u32(int64_t n, const uint32_t *__restrict__ a, uint32_t *__restrict__ b)

@@ -262,6 +262,35 @@ struct ScatterList {
     void *dst[24];
 };
 sph_status scatter(sph_ctx *c, int64_t n, const ScatterList &s, const uint32_t *index);
+
+// dst[a][to] = src[a][from] for every array of a Gather/ScatterList, copied as
+// bits (8 bytes for kind 0, 4 otherwise).  Up to 16 loads are issued before
+// their stores: the lists carry no no-alias guarantee, so a load after a store
+// would wait for it, and a one-array-at-a-time loop runs ~10 dependent memory
+// round trips per element.
+template <class List>
+__device__ inline void copy_listed(const List &L, int64_t from, int64_t to)
+{
+    constexpr int kChunk = 16;
+    for (int a0 = 0; a0 < L.count; a0 += kChunk) {
+        uint64_t v[kChunk];
+#pragma unroll
+        for (int j = 0; j < kChunk; j++) {
+            const int a = a0 + j;
+            if (a < L.count)
+                v[j] = L.kind[a] == 0 ? ((const uint64_t *)L.src[a])[from]
+                                      : (uint64_t)((const uint32_t *)L.src[a])[from];
+        }
+#pragma unroll
+        for (int j = 0; j < kChunk; j++) {
+            const int a = a0 + j;
+            if (a < L.count) {
+                if (L.kind[a] == 0) ((uint64_t *)L.dst[a])[to] = v[j];
+                else ((uint32_t *)L.dst[a])[to] = (uint32_t)v[j];
+            }
+        }
+    }
+}
 sph_status eos_scatter(sph_ctx *c, int64_t n, const uint32_t *index, const double *u_caller,
                        double *P, double *cs);
 // scatter plus the equation of state (P, cs may be NULL) from sorted rho, u

@@ -17,13 +17,7 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t n, const uint32_t *__re
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     int64_t dst = index[k];
-    for (int a = 0; a < s.count; a++) {
-        switch (s.kind[a]) {
-        case 0: ((double *)s.dst[a])[dst] = ((const double *)s.src[a])[k]; break;
-        case 1: ((uint32_t *)s.dst[a])[dst] = ((const uint32_t *)s.src[a])[k]; break;
-        default: ((float *)s.dst[a])[dst] = ((const float *)s.src[a])[k]; break;
-        }
-    }
+    copy_listed(s, k, dst);
 }
 
 __global__ __launch_bounds__(256) void k_eos_scatter(int64_t n, double gamma,
@@ -51,13 +45,7 @@ __global__ __launch_bounds__(256) void k_scatter_eos(int64_t n, const uint32_t *
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     int64_t dst = index[k];
-    for (int a = 0; a < s.count; a++) {
-        switch (s.kind[a]) {
-        case 0: ((double *)s.dst[a])[dst] = ((const double *)s.src[a])[k]; break;
-        case 1: ((uint32_t *)s.dst[a])[dst] = ((const uint32_t *)s.src[a])[k]; break;
-        default: ((float *)s.dst[a])[dst] = ((const float *)s.src[a])[k]; break;
-        }
-    }
+    copy_listed(s, k, dst);
     if (P || cs) {
         double Pk = (gamma - 1.0) * rho[k] * u_sorted[k];
         if (P) P[dst] = Pk;
