@@ -187,6 +187,9 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
 {
     __shared__ uint32_t wcnt[kRsThreads / kWave][256];
     __shared__ uint32_t dbase[256];
+    __shared__ uint32_t tbase[256];            // first slot of each digit in the tile
+    __shared__ uint64_t skey[kRsTile];         // the tile in digit order
+    __shared__ uint32_t sval[kRsTile];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     for (int k = threadIdx.x; k < (kRsThreads / kWave) * 256; k += kRsThreads)
@@ -225,23 +228,43 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
         wave_lds_sync();
     }
     __syncthreads();
-    if (threadIdx.x < 256) {
-        uint32_t run = 0;
-        for (int ww = 0; ww < kRsThreads / kWave; ww++) {
-            uint32_t v = wcnt[ww][threadIdx.x];
-            wcnt[ww][threadIdx.x] = run;
-            run += v;
-        }
+    // per digit (one thread each): the waves' offsets inside the tile's run
+    // of that digit, then the run's first slot in the tile
+    uint32_t run = 0;
+    for (int ww = 0; ww < kRsThreads / kWave; ww++) {
+        uint32_t v = wcnt[ww][threadIdx.x];
+        wcnt[ww][threadIdx.x] = run;
+        run += v;
+    }
+    {
+        const uint32_t incl = block_scan_256(run, tbase);
+        __syncthreads();
+        tbase[threadIdx.x] = incl - run;
     }
     __syncthreads();
+    // stage the tile in digit order (stable: wave, then item, then lane)
     for (int r = 0; r < kRsItems; r++) {
         int64_t k = base + r * kWave + lane;
         if (k < n) {
             uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
-            uint32_t pos = dbase[d] + offs[d * ntiles + blockIdx.x] + wcnt[w][d] + rank[r];
-            kout[pos] = key[r];
-            vout[pos] = val[r];
+            uint32_t lp = tbase[d] + wcnt[w][d] + rank[r];
+            skey[lp] = key[r];
+            sval[lp] = val[r];
         }
+    }
+    __syncthreads();
+    // slot i of the tile goes to (global start of its digit's run in this tile)
+    // + (i - tile start of that run); dbase + offs >= tbase, so no wrap
+    dbase[threadIdx.x] += offs[threadIdx.x * ntiles + blockIdx.x] - tbase[threadIdx.x];
+    __syncthreads();
+    const int64_t left = n - blockIdx.x * (int64_t)kRsTile;   // >= 1
+    const int tile_n = left < kRsTile ? (int)left : kRsTile;
+    for (int i = threadIdx.x; i < tile_n; i += kRsThreads) {
+        const uint64_t kk = skey[i];
+        const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+        const uint32_t pos = dbase[d] + (uint32_t)i;
+        kout[pos] = kk;
+        vout[pos] = sval[i];
     }
 }
 
