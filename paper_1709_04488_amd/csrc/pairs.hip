@@ -871,7 +871,12 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             const double R2 = R * R;
             return [&bx, &home, R2](const Node &nd) { return box_gap2(home.lo, home.hi, nd, bx) < R2; };
         };
+        // the walk and the staging are chains of dependent loads: the wave
+        // issues them at raised priority, ahead of waves in their arithmetic
+        // (measured: the force loop 1 % faster, the density loop unchanged)
+        __builtin_amdgcn_s_setprio(2);
         WalkResult wr = walk(T, A.nodes, make_test(hcov), wb, S.walk_spare);
+        __builtin_amdgcn_s_setprio(0);
         walks++;
         if (wr.lev) overflows++;
         int iter = 0;
@@ -926,10 +931,12 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                     // FP32-pair stages no mass when all masses are equal (measured
                     // faster; the FP64 loop is faster staging it anyway)
                     constexpr bool skip_m = PREC == SPH_FP32_PAIR;
+                    __builtin_amdgcn_s_setprio(2);
                     stage_group<G, PREC, false, skip_m>(S, leaves, ng, A.lstart, A.nodes, home, bx,
                                                         hcov, A.x, A.y, A.z,
                                                         skip_m && equal_m ? nullptr : A.m, A.fx,
                                                         A.fy, A.fz);
+                    __builtin_amdgcn_s_setprio(0);
                     const bool any_pp = group_tests<G, PREC>(
                         S, ng,
                         [&](int pp, int k) {
@@ -1039,7 +1046,9 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             const double hmx = wave_max(conv ? 0.0 : h);
             if (hmx > hcov) {
                 hcov = A.walk_margin * hmx;
+                __builtin_amdgcn_s_setprio(2);
                 wr = walk(T, A.nodes, make_test(hcov), wb, S.walk_spare);
+                __builtin_amdgcn_s_setprio(0);
                 walks++;
                 if (wr.lev) overflows++;
             }
@@ -1179,14 +1188,19 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             const double R = 2.0 * fmax(home.hmax, nd.hmax) * (1.0 + 1e-10);
             return box_gap2(home.lo, home.hi, nd, bx) < R * R;
         };
+        // walk and staging at raised priority, as in the density loop
+        __builtin_amdgcn_s_setprio(2);
         const WalkResult wr = walk(T, F.nodes, test, wb, S.walk_spare);
+        __builtin_amdgcn_s_setprio(0);
         if (wr.lev) overflows++;
 
         double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
         int cnt = 0, selfs = 0;
         auto group = [&](const uint32_t *leaves, int ng) {
+            __builtin_amdgcn_s_setprio(2);
             stage_group<G, PREC, true>(S, leaves, ng, F.lstart, F.nodes, home, bx, -1.0, F.x, F.y, F.z,
                                        F.h, F.fx, F.fy, F.fz);
+            __builtin_amdgcn_s_setprio(0);
             group_tests<G, PREC>(
                 S, ng,
                 [&](int pp, int k) {
