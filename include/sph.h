@@ -85,7 +85,9 @@ enum { SPH_AC_WADSLEY = 0, SPH_AC_PRICE = 1 };
  * Artificial conductivity (second sum of eq. EQN:MON97ENERGYDISS): with
  * alpha_ac > 0 every force pair adds
  *   du_i/dt += (m_j / rhobar_ij) alpha_ac v' (u_i - u_j) rhat_ij . gradW_bar_ij
- * to du/dt; accelerations, v_sig and dt do not change.  The kernel rebuilds
+ * to du/dt (rhobar_ij = (rho_i + rho_j)/2; gradW_bar_ij the mean of the
+ * kernel gradients at h_i and h_j, as in the viscosity); accelerations, v_sig
+ * and dt do not change.  The kernel rebuilds
  * u_j and P_j from the adiabatic EOS (u = c^2 / (gamma (gamma - 1)),
  * P = rho c^2 / gamma).
  *
