@@ -148,8 +148,9 @@ def measured_valu_insts(tag: str, kernel: str):
 
 def prof_tag(args, prec: str):
     """Key of the committed counter runs that match this invocation: workload,
-    precision and leaf size."""
-    return f"{args.config}_{prec}_g{args.leaf_used[prec]}"
+    precision, leaf size and, when on, the artificial conductivity."""
+    ac = f"_ac{args.alpha_ac:g}{args.ac_signal}" if args.alpha_ac > 0.0 else ""
+    return f"{args.config}_{prec}_g{args.leaf_used[prec]}{ac}"
 
 
 def roofline(res, prec: str, tag: str = None, phase: str = "cold"):
@@ -229,6 +230,9 @@ def main():
                     help="time only the cold-start evaluations (no warm-start or 1 %% tolerance "
                          "legs, no test-counting pass): the launches a profile of the headline "
                          "figure should see")
+    ap.add_argument("--alpha-ac", type=float, default=0.0,
+                    help="artificial conductivity strength for every run (default 0: none)")
+    ap.add_argument("--ac-signal", default="wadsley", choices=["wadsley", "price"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -249,6 +253,10 @@ def main():
 
     t_gen = time.perf_counter()
     w = workload(args.config)
+    if args.alpha_ac > 0.0:
+        from paper_1709_04488_amd import workloads as W
+        w = W.Workload(w.name, w.arrays, {**w.setup, "alpha_ac": args.alpha_ac,
+                                          "ac_signal": 0 if args.ac_signal == "wadsley" else 1})
     gen_s = time.perf_counter() - t_gen
     print(f"# workload {w.name} N={w.n} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
@@ -307,7 +315,9 @@ def main():
         "config": {"workload": f"{w.name}: N={w.n}, "
                                + ("periodic unit box" if w.setup["periodic"] else "isolated")
                                + f", eta={w.setup['eta']}, M4, alpha_AV=1, beta_AV=2, "
-                               f"{'FP64' if head_key == 'fp64' else 'FP32-pair'}, "
+                               + (f"alpha_AC={args.alpha_ac:g} ({args.ac_signal}), "
+                                  if args.alpha_ac > 0.0 else "")
+                               + f"{'FP64' if head_key == 'fp64' else 'FP32-pair'}, "
                                "cold h start from the input guess",
                    "n": w.n, "leaf_size": leaf[prec_name],
                    "leaf_choice": "autotuner" if args.leaf == "auto" else "fixed",

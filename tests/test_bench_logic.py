@@ -69,3 +69,14 @@ def test_counter_records_follow_the_pair_loop_source(tmp_path):
     # unknown workload, precision or leaf size: nothing
     b.ROOT = _tree(tmp_path / "none", src)
     assert b.measured_traffic("c9_fp64_g16", "density_cold") is None
+
+
+def test_counter_record_key_names_workload_precision_leaf_and_conductivity():
+    import argparse
+    b = _bench()
+    a = argparse.Namespace(config="c1", alpha_ac=0.0, ac_signal="wadsley",
+                           leaf_used={"fp64": 16, "fp32": 32})
+    assert b.prof_tag(a, "fp64") == "c1_fp64_g16"
+    assert b.prof_tag(a, "fp32") == "c1_fp32_g32"
+    a.alpha_ac = 1.0
+    assert b.prof_tag(a, "fp64") == "c1_fp64_g16_ac1wadsley"
