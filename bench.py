@@ -17,6 +17,14 @@ u lognormal(0, 0.3), velocities N(0, 0.2^2), eta = 1.2, M4 kernel,
 alpha_AV = 1, beta_AV = 2, gamma = 5/3.  FP64 is the headline value; the
 FP32-pair mode is measured on the same set and reported beside it.
 
+Also reported in the same line (unless --main-only): the largest set, a
+4,194,304-particle Plummer sphere (open boundary) in FP32-pair mode with its
+own roofline; and the two served workloads with throughput and p50/p99
+latency: 512 evaluation requests (N log-uniform in [1e3, 2e5], FP64 or
+FP32-pair, HBM budget 1 GiB; a closed burst, then Poisson arrivals at 0.8 of
+that capacity) and 64 integration requests (N log-uniform in [1e4, 1e6],
+200 KDK steps each, FP32-pair, resident state and graph replay).
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -201,6 +209,66 @@ def cpu_baseline(w, seconds: float):
                       f"({el:.1f} s)"}
 
 
+def largest_leg(args):
+    """The 4,194,304-particle Plummer sphere in FP32-pair mode (the largest
+    set), leaf size by the autotuner, with the roofline of its dominant pair
+    loop."""
+    from paper_1709_04488_amd import sph, tune
+    from paper_1709_04488_amd import workloads as W
+    w = W.config2()
+    print(f"# largest: {w.name} N={w.n}", file=sys.stderr, flush=True)
+    tuned = tune.LeafTuner().measure(w.arrays, w.setup, sph.SPH_FP32_PAIR)
+    g = tuned["leaf"]
+    r = run_gpu(w, sph.SPH_FP32_PAIR, max(args.steps // 2, 5), args.warmup, g,
+                count_tests=False)
+    print(f"# largest fp32: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    tag = f"c2_fp32_g{g}"
+    return {"workload": f"{w.name}: N={w.n}, isolated Plummer sphere (a = 0.05, cut at r = 1), "
+                        "FP32-pair, cold h start from the input guess",
+            "n": w.n, "leaf_size": g, "steps": max(args.steps // 2, 5),
+            "value": r["value"], "unit": "interactions/s", "ms_per_step": r["ms_per_step"],
+            "interactions_per_step": r["interactions"],
+            "nr_iter_mean": r["info"]["nr_iter_total"] / w.n,
+            "roofline": roofline(r, "fp32", tag=tag),
+            "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()},
+            "autotuner": tuned}
+
+
+def serving_legs(args):
+    """The two served workloads (continuous batching under an HBM budget),
+    throughput with p50/p99 latency from arrival to results in host memory."""
+    from paper_1709_04488_amd import serve
+    t0 = time.perf_counter()
+    ev = serve.run_served("evaluate", requests=512, slots=8, mode="streams", load=0.8)
+    print(f"# served evaluate: {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    it = serve.run_served("integrate", requests=64, steps=args.serve_steps, slots=8,
+                          mode="streams")
+    print(f"# served integrate: {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    keep = ("requests", "completed", "errors", "makespan_s", "throughput_interactions_per_s",
+            "requests_per_s", "latency_p50_ms", "latency_p99_ms", "latency_max_ms", "peak_bytes")
+    return {
+        "evaluate_512": {
+            "workload": "512 evaluation requests, jittered-lattice boxes, N log-uniform in "
+                        "[1e3, 2e5] snapped to n^3, FP64 or FP32-pair with probability 1/2, "
+                        "HBM budget 1 GiB, 8 slots, one stream each",
+            "budget_bytes": ev["budget_bytes"],
+            "saturated_all_at_t0": {k: ev["saturated"][k] for k in keep},
+            "poisson_arrivals_per_s": ev["arrival_rate_per_s"],
+            "poisson": {k: ev["poisson"][k] for k in keep}},
+        "integrate_64": {
+            "workload": f"64 integration requests, blob-in-lattice boxes, N log-uniform in "
+                        f"[1e4, 1e6] snapped to n^3, {args.serve_steps} KDK steps each, "
+                        "FP32-pair pair terms, FP64 state, resident, graph replay, "
+                        "HBM budget 16 GiB, 8 slots",
+            "budget_bytes": it["budget_bytes"],
+            "steps_total": it["steps_total"],
+            "result": {k: it["result"][k] for k in keep},
+            "per_step_latency_p50_ms": it["per_step_latency_p50_ms"],
+            "per_step_latency_p99_ms": it["per_step_latency_p99_ms"]},
+    }
+
+
 def calib_copy(gib: float = 1.0, reps: int = 5):
     """Plain copy of a known number of bytes (for scaling HBM counters)."""
     import torch
@@ -233,6 +301,11 @@ def main():
     ap.add_argument("--alpha-ac", type=float, default=0.0,
                     help="artificial conductivity strength for every run (default 0: none)")
     ap.add_argument("--ac-signal", default="wadsley", choices=["wadsley", "price"])
+    ap.add_argument("--no-largest", action="store_true",
+                    help="skip the 4,194,304-particle Plummer leg (FP32-pair)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the two served workloads")
+    ap.add_argument("--serve-steps", type=int, default=200,
+                    help="KDK steps per served integration request")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -369,6 +442,10 @@ def main():
                             "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()}}
     if tuned:
         out["autotuner"] = tuned
+    if not args.main_only and not args.no_largest and args.config != "c2":
+        out["largest_fp32_pair"] = largest_leg(args)
+    if not args.main_only and not args.no_serving:
+        out["serving"] = serving_legs(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

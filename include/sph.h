@@ -35,6 +35,11 @@
  * Streams.  Every call enqueues work on the context's HIP stream and returns
  *           without waiting, unless stated otherwise.  Results are valid after
  *           the stream has drained (sph_sync, or any later stream-ordered use).
+ *           Exception: a call that needs more capacity than the context holds
+ *           (its first call, a larger n, or a smaller leaf_size than before)
+ *           first waits for the stream, then frees and reallocates the
+ *           context's buffers.  A context sized once by a call at its largest
+ *           n and leaf size never waits again.
  *           The library issues nothing on the null stream for a context bound
  *           to another stream, so contexts on separate (non-blocking) streams
  *           run concurrently without ordering against each other.
@@ -177,6 +182,10 @@ typedef struct {
     int64_t dens_box_tests;   /* particle-leaf box tests, density loop */
     int64_t force_candidate_tests; /* particle-candidate distance tests, force loop */
     int64_t force_box_tests;  /* particle-leaf box tests, force loop */
+    int32_t density_walk_overflows; /* of walk_overflows: those of the density loop */
+    int32_t force_walk_overflows;   /* of walk_overflows: those of the force loop */
+    int64_t dens_list_overflows;    /* particles whose density candidate list outgrew its
+                                       capacity in a sweep (swept again at the next Newton step) */
 } sph_state_stats;
 
 typedef struct sph_ctx sph_ctx;

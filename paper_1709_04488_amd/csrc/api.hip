@@ -892,6 +892,9 @@ sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
     info->dens_box_tests = counts[kCntDensBoxes];
     info->force_candidate_tests = counts[kCntForceTests];
     info->force_box_tests = counts[kCntForceBoxes];
+    info->density_walk_overflows = (int32_t)counts[kCntDensOverflows];
+    info->force_walk_overflows = (int32_t)counts[kCntForceOverflows];
+    info->dens_list_overflows = counts[kCntDensListOverflows];
     return SPH_OK;
 }
 

@@ -799,6 +799,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
     double *const cr2 = B.cache + (size_t)blockIdx.x * (2 * ROWS * kWave);
     double *const cm = cr2 + ROWS * kWave;
     int64_t evals = 0, walks = 0, visits = 0, overflows = 0, nr_total = 0, tests = 0, boxes = 0;
+    int64_t list_over = 0;
     int iter_max = 0;
     int cur = -1;
     const __attribute__((address_space(4))) DensArgs *Ap = nullptr;
@@ -817,8 +818,9 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             add(kCntNrTotal, nr_total);
             add(kCntDensTests, tests);
             add(kCntDensBoxes, boxes);
+            add(kCntDensListOverflows, list_over);
         }
-        evals = walks = visits = overflows = nr_total = tests = boxes = 0;
+        evals = walks = visits = overflows = nr_total = tests = boxes = list_over = 0;
         iter_max = 0;
     };
     for_each_home_leaf(pre[B.nreq], B.work, [&](int64_t gleaf) {
@@ -985,6 +987,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 visits += for_each_leaf_group<NL>(T, A.nodes, wr, make_test(hcov), wb, group);
                 count = base;
                 cached = !conv && count <= KP;
+                list_over += (int64_t)__popcll(__ballot(!conv && q == 0 && count > KP));
             } else {
                 // every particle still iterating has a complete list and h <= Rc:
                 // the entries inside 2h, in list order, are the hits of a sweep
@@ -1637,6 +1640,7 @@ sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax)
     sph_ctx *c = cs[0];
     if (count > kMaxBatch) return fail(c, SPH_EINVAL, "batch larger than kMaxBatch");
     TRY_(zero_batch_counts(cs, count, kCntDensFirst, kCntDensWords));
+    TRY_(zero_batch_counts(cs, count, kCntDensListOverflows, 1));
     Batch<DensArgs> B{};
     B.nreq = count;
     B.work = c->d_work;

@@ -104,6 +104,7 @@ enum : int {
     kCntForceOverflows = 11, // force walks that overflowed the LDS frontier
     kCntForceTests = 12,     // particle-candidate distance tests, force
     kCntForceBoxes = 13,     // particle-leaf box tests, force
+    kCntDensListOverflows = 14, // particles whose candidate list outgrew its capacity in a sweep
     kCountWords = 16,
     kCntDensFirst = kCntDensEvals,
     kCntDensWords = kCntDensBoxes - kCntDensEvals + 1,

@@ -575,6 +575,58 @@ def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=
     return recs, out
 
 
+def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200,
+               budget_gib: float = None, slots: int = 8, mode: str = "streams",
+               load: float = 0.8, max_side: int = None, leaf="auto", tune_table: str = None,
+               threads: bool = True, progress: bool = True) -> dict:
+    """Serve one of the two workloads and summarise it.  evaluate: a closed
+    burst (every request at t = 0) gives the saturated capacity, then Poisson
+    arrivals at `load` times that rate; integrate: `requests` resident
+    integrations of `steps` KDK steps each.  Every request class is tuned
+    before the timed runs when leaf is "auto"."""
+    if leaf == "auto":
+        from .tune import LeafTuner
+        leaf_for = LeafTuner(path=tune_table)
+    else:
+        g = int(leaf)
+        leaf_for = lambda req: g  # noqa: E731
+    gib = budget_gib if budget_gib else (1.0 if workload == "evaluate" else 16.0)
+    budget = int(gib * GIB)
+
+    def pretune(reqs):
+        if leaf == "auto":
+            for r in reqs:
+                leaf_for(r)
+
+    if workload == "evaluate":
+        burst = evaluate_requests(requests, math.inf, n_max_side=max_side)
+        pretune(burst)
+        _, closed = serve(burst, budget, slots, mode, leaf_for=leaf_for, progress=progress,
+                          threads=threads)
+        rate = load * closed["requests_per_s"]
+        reqs = evaluate_requests(requests, rate, n_max_side=max_side)
+        _, opened = serve(reqs, budget, slots, mode, leaf_for=leaf_for, progress=progress,
+                          threads=threads)
+        res = {"workload": "evaluate", "mode": mode, "slots": slots, "leaf": leaf,
+               "budget_bytes": budget, "saturated": closed, "arrival_rate_per_s": rate,
+               "poisson": opened}
+    else:
+        reqs = integrate_requests(requests, steps, n_max_side=max_side)
+        pretune(reqs)
+        recs, out = serve(reqs, budget, slots, mode, leaf_for=leaf_for, progress=progress,
+                          threads=threads)
+        nsteps = sum(r.info.get("steps", 0) for r in recs if not r.error)
+        per_step = [r.latency / max(steps, 1) * 1e3 for r in recs if not r.error] or [0.0]
+        res = {"workload": "integrate", "mode": mode, "slots": slots, "leaf": leaf,
+               "budget_bytes": budget, "steps_per_request": steps, "result": out,
+               "steps_total": nsteps,
+               "per_step_latency_p50_ms": float(np.percentile(per_step, 50)),
+               "per_step_latency_p99_ms": float(np.percentile(per_step, 99))}
+    if leaf == "auto":
+        res["autotuner"] = leaf_for.table
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="serve SPH requests on one GPU")
     ap.add_argument("--workload", choices=["evaluate", "integrate"], default="evaluate")
@@ -593,47 +645,9 @@ def main(argv=None):
     ap.add_argument("--no-threads", action="store_true",
                     help="streams mode: drive every slot from the main thread")
     args = ap.parse_args(argv)
-    if args.leaf == "auto":
-        from .tune import LeafTuner
-        leaf_for = LeafTuner(path=args.tune_table)
-    else:
-        g = int(args.leaf)
-        leaf_for = lambda req: g  # noqa: E731
-    gib = args.budget_gib if args.budget_gib else (1.0 if args.workload == "evaluate" else 16.0)
-    budget = int(gib * GIB)
-    def pretune(reqs):
-        # measure every request class before the timed runs
-        if args.leaf == "auto":
-            for r in reqs:
-                leaf_for(r)
-
-    if args.workload == "evaluate":
-        burst = evaluate_requests(args.requests, math.inf, n_max_side=args.max_side)
-        pretune(burst)
-        _, closed = serve(burst, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True,
-                             threads=not args.no_threads)
-        rate = args.load * closed["requests_per_s"]
-        reqs = evaluate_requests(args.requests, rate, n_max_side=args.max_side)
-        _, opened = serve(reqs, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True,
-                             threads=not args.no_threads)
-        res = {"workload": "evaluate", "mode": args.mode, "slots": args.slots, "leaf": args.leaf,
-               "budget_bytes": budget, "saturated": closed, "arrival_rate_per_s": rate,
-               "poisson": opened}
-    else:
-        reqs = integrate_requests(args.requests, args.steps, n_max_side=args.max_side)
-        pretune(reqs)
-        recs, out = serve(reqs, budget, args.slots, args.mode, leaf_for=leaf_for, progress=True,
-                             threads=not args.no_threads)
-        steps = sum(r.info.get("steps", 0) for r in recs if not r.error)
-        res = {"workload": "integrate", "mode": args.mode, "slots": args.slots, "leaf": args.leaf,
-               "budget_bytes": budget, "steps_per_request": args.steps, "result": out,
-               "steps_total": steps,
-               "per_step_latency_p50_ms": float(np.percentile(
-                   [r.latency / max(args.steps, 1) * 1e3 for r in recs if not r.error], 50)),
-               "per_step_latency_p99_ms": float(np.percentile(
-                   [r.latency / max(args.steps, 1) * 1e3 for r in recs if not r.error], 99))}
-    if args.leaf == "auto":
-        res["autotuner"] = leaf_for.table
+    res = run_served(args.workload, args.requests, args.steps, args.budget_gib, args.slots,
+                     args.mode, args.load, args.max_side, args.leaf, args.tune_table,
+                     threads=not args.no_threads)
     print(json.dumps(res), flush=True)
 
 

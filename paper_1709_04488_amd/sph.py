@@ -71,7 +71,9 @@ class _Stats(ctypes.Structure):
                 ("walk_overflows", ctypes.c_int32), ("dens_leaf_visits", ctypes.c_int64),
                 ("dens_walks", ctypes.c_int64), ("nr_iter_total", ctypes.c_int64),
                 ("dens_candidate_tests", ctypes.c_int64), ("dens_box_tests", ctypes.c_int64),
-                ("force_candidate_tests", ctypes.c_int64), ("force_box_tests", ctypes.c_int64)]
+                ("force_candidate_tests", ctypes.c_int64), ("force_box_tests", ctypes.c_int64),
+                ("density_walk_overflows", ctypes.c_int32), ("force_walk_overflows", ctypes.c_int32),
+                ("dens_list_overflows", ctypes.c_int64)]
 
 
 _lib = None
@@ -322,7 +324,10 @@ class Context:
                 "dens_candidate_tests": st.dens_candidate_tests,
                 "dens_box_tests": st.dens_box_tests,
                 "force_candidate_tests": st.force_candidate_tests,
-                "force_box_tests": st.force_box_tests}
+                "force_box_tests": st.force_box_tests,
+                "density_walk_overflows": st.density_walk_overflows,
+                "force_walk_overflows": st.force_walk_overflows,
+                "dens_list_overflows": st.dens_list_overflows}
 
     def neighbours(self, p: Particles, mode: int, cap: int = None):
         """CSR lists at the given h -> (offsets int64[n+1], idx int32) on the device."""

@@ -95,8 +95,10 @@ def test_batch_matches_oracle(sph, orc):
 
 def test_batch_with_conductivity_in_one_set(sph, orc):
     """One set with alpha_AC = 1 makes the launch carry the conductivity
-    term; it equals that set alone bit for bit, and the sets with alpha_AC =
-    0 (which then add exact zeros) match the oracle."""
+    term; it equals that set alone bit for bit.  The sets with alpha_AC = 0
+    then run the conductivity variant of the force loop, which adds exact
+    zeros for them: each equals its own single-set run (the variant without
+    the term) bit for bit, and the oracle."""
     sets = [w for w, _, _ in _mix()[:3]]
     setups = [{**sets[0].setup, "alpha_ac": 1.0, "ac_signal": 1}, sets[1].setup, sets[2].setup]
     mix = list(zip(sets, setups))
@@ -115,6 +117,14 @@ def test_batch_with_conductivity_in_one_set(sph, orc):
     outs = [p.host() for p in parts]
     for f in _fields():
         assert np.array_equal(outs[0][f], alone[f]), f
+    for (w, st), out in list(zip(mix, outs))[1:]:
+        with sph.Context(sph.Params.from_setup(st, precision=0)) as ctx:
+            p1 = sph.Particles.from_host(w.arrays)
+            ctx.evaluate(p1)
+            ctx.sync()
+            own = p1.host()
+        for f in _fields():
+            assert np.array_equal(out[f], own[f]), (w.name, f)
     for (w, st), out in zip(mix, outs):
         a = w.arrays
         ref = orc.evaluate(orc.Params(**st), a["x"], a["y"], a["z"], a["vx"], a["vy"], a["vz"],

@@ -4,9 +4,14 @@ Tolerances (FP64 mode): neighbour lists and neighbour counts bit-exact;
 h, rho, omega, P, c_s, v_sig, dt within 1e-10 relative; a and du/dt within
 1e-10 of the per-particle scale S_i = sum_j |pair term| (a ~ 0 by
 cancellation on near-uniform sets makes a plain relative error meaningless).
-FP32-pair mode: h, rho, omega, v_sig, dt within 1e-5 relative, a and du/dt
-within 1e-4 of S_i, neighbour-count differences only from pairs within
-1e-5 of the kernel edge.
+FP32-pair mode: h, rho, P, c_s, v_sig, dt within 1e-5 relative, omega
+within 5e-5, a and du/dt within 1e-4 of S_i.  The FP32 errors are checked to
+have their two expected sources and no other: (1) the h solve stops within
+its floored tolerance of the root (h within 1e-5), and (2) at the GPU's own h
+the single-precision pair terms leave rho and omega within 1e-6 of the
+oracle's sums at that same h; neighbour-count differences come only from
+pairs within 1e-5 of the kernel edge (each count lies between the oracle's
+counts at 2h(1 - 1e-5) and 2h(1 + 1e-5)).
 """
 import numpy as np
 import pytest
@@ -20,10 +25,14 @@ from paper_1709_04488_amd import workloads as W  # noqa: E402
 FP64_TOL = 1e-10
 FP32_TOL = 1e-5
 FP32_ATOL = 1e-4
-# FP32-pair mode, frozen after the first measurement on MI355X: Omega is a
-# ratio of derivative sums and carries ~1e-5 relative error on the Plummer
-# set (max seen 1.4e-5); the other scalars stay below 1e-5
-FP32_FIELD_TOL = {"omega": 1e-4}
+# FP32-pair mode: Omega moves with h by d ln Omega / d ln h, which reaches
+# ~10 at the edge of the Plummer set, so the ~2e-6 stop tolerance of the h
+# solve shows up as up to 1.4e-5 in Omega (measured); 5e-5 is that maximum
+# with a factor 3.5.  The pair arithmetic's own share is held to 1e-6 at the
+# GPU's h (fp32_error_sources).
+FP32_FIELD_TOL = {"omega": 5e-5}
+FP32_EDGE = 1e-5      # relative band around the kernel edge q = 2
+FP32_PAIR_TOL = 1e-6  # rho, Omega at the GPU's own h
 
 
 @pytest.fixture(scope="module")
@@ -137,6 +146,7 @@ def test_unequal_masses(sph, orc, precision):
     else:
         _check(out, ref, tol=FP32_TOL, atol=FP32_ATOL, counts_exact=False,
                label="unequal m fp32", field_tol=FP32_FIELD_TOL)
+        fp32_error_sources(orc, w, out, ref)
 
 
 def _hot_cold_gas(n, seed, **setup):
@@ -391,6 +401,34 @@ def test_paper_tolerance_mode_satisfies_its_own_bound(sph, orc):
     assert drho < 1e-2 * 1.05
 
 
+def fp32_error_sources(orc, w, out, ref, force_counts=True, edge_only=None):
+    """The FP32-pair errors have their expected sources only (module doc).
+    edge_only: boolean mask of particles whose density comes almost wholly
+    from pairs near the kernel edge, where f ~ (2 - q)^3 / 4 magnifies the
+    single-precision error of q by 3 q / (2 - q); they are held to 1e-4 at
+    their own h instead."""
+    a = w.arrays
+    p = orc.Params(**w.setup)
+    x, y, z, m = a["x"], a["y"], a["z"], a["m"]
+    at = orc.rho_at(p, x, y, z, m, out["h"])
+    om_at = 1.0 + out["h"] * at["drhodh"] / (3.0 * at["rho"])
+    r_rho = np.abs(out["rho"] / at["rho"] - 1.0)
+    r_om = np.abs(out["omega"] / om_at - 1.0)
+    tol = np.full(w.n, FP32_PAIR_TOL)
+    if edge_only is not None:
+        tol[edge_only] = 1e-4
+    print(f"{w.name} fp32 at own h: rho {r_rho.max():.3e} omega {r_om.max():.3e}")
+    assert np.all(r_rho < tol) and np.all(r_om < tol)
+    lo = orc.rho_at(p, x, y, z, m, ref["h"] * (1.0 - FP32_EDGE))["nngb"]
+    hi = orc.rho_at(p, x, y, z, m, ref["h"] * (1.0 + FP32_EDGE))["nngb"]
+    print(f"{w.name} fp32 density counts differing: {int(np.sum(out['nngb'] != ref['nngb']))}")
+    assert np.all(lo <= out["nngb"]) and np.all(out["nngb"] <= hi)
+    if force_counts:
+        flo = np.diff(orc.neighbours(p, x, y, z, ref["h"] * (1.0 - FP32_EDGE), 1)[0])
+        fhi = np.diff(orc.neighbours(p, x, y, z, ref["h"] * (1.0 + FP32_EDGE), 1)[0])
+        assert np.all(flo <= out["nforce"]) and np.all(out["nforce"] <= fhi)
+
+
 def test_fp32_pair_mode_tolerances(sph, orc):
     for w in (W.config0(), W.plummer(3000, seed=12)):
         print("case: fp32 %s" % w.name, flush=True)
@@ -398,8 +436,7 @@ def test_fp32_pair_mode_tolerances(sph, orc):
         out = _gpu_eval(sph, w, precision=sph.SPH_FP32_PAIR)
         _check(out, ref, tol=FP32_TOL, atol=FP32_ATOL, counts_exact=False, label="fp32 " + w.name,
                field_tol=FP32_FIELD_TOL)
-        dn = np.abs(out["nngb"] - ref["nngb"])
-        assert np.mean(dn) < 0.01 and np.max(dn) <= 1
+        fp32_error_sources(orc, w, out, ref)
 
 
 def test_fp32_pair_momentum_conserved(sph):
