@@ -39,7 +39,8 @@
  *           (its first call, a larger n, or a smaller leaf_size than before)
  *           first waits for the stream, then frees and reallocates the
  *           context's buffers.  A context sized once by a call at its largest
- *           n and leaf size never waits again.
+ *           n and leaf size never waits again; sph_evaluate_noalloc never
+ *           allocates at all.
  *           The library issues nothing on the null stream for a context bound
  *           to another stream, so contexts on separate (non-blocking) streams
  *           run concurrently without ordering against each other.
@@ -258,6 +259,24 @@ sph_status sph_forces(sph_ctx *ctx, sph_particles *ps);
  * order.
  */
 sph_status sph_evaluate(sph_ctx *ctx, sph_particles *ps);
+
+/*
+ * sph_evaluate for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, outputs and errors as sph_evaluate, results bit for bit those of
+ * sph_evaluate, but every buffer the call needs beyond the caller's arrays
+ * and the context's fixed words (set up by sph_create) lives in one static
+ * device array of the library, of fixed size (about 40 MB, held on each
+ * device the library runs on until the process ends): the call makes no
+ * device allocation or free and never waits for the stream.
+ * Limit: n <= sph_noalloc_max_n() (32768); larger n returns SPH_ECAP.
+ * The static array is shared by every context on a device and keeps the last
+ * call's contents: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.  Like sph_evaluate it
+ * ends a resident state; the context's own buffers are left as they were.
+ */
+sph_status sph_evaluate_noalloc(sph_ctx *ctx, sph_particles *ps);
+int64_t sph_noalloc_max_n(void);
 
 /*
  * Copy a particle set (x, y, z, v, m, u, h) into context-owned device memory

@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <type_traits>
 
 namespace sph {
 
@@ -40,6 +42,9 @@ int64_t bytes_per_particle(const sph_params &p)
     (void)p;
     return b;
 }
+
+// radix-sort tile counts per digit plus the 256 digit totals
+int64_t hist_words(int64_t cap) { return 256 * ceil_div(cap, kRsTile) + 256; }
 
 sph_status check_params(sph_ctx *c, const sph_params *p)
 {
@@ -88,8 +93,6 @@ void free_all(sph_ctx *c)
     drop_graph(c);
     for (void *ptr : c->allocs) (void)hipFree(ptr);
     c->allocs.clear();
-    if (c->nodes) (void)hipFree(c->nodes);
-    if (c->hist) (void)hipFree(c->hist);
     if (c->cache) (void)hipFree(c->cache);
     c->nodes = nullptr;
     c->hist = nullptr;
@@ -162,25 +165,17 @@ static sph_status ensure_cache(sph_ctx *c)
     return SPH_OK;
 }
 
-sph_status ensure_capacity(sph_ctx *c, int64_t n)
+// Every buffer sized by the particle capacity, in one list shared by the
+// allocating path (one hipMalloc per buffer) and the no-allocation entry point
+// (slices of a static device array): take(&ptr, count) provides count
+// elements for ptr.  The density loop's candidate lists are not in the list
+// (the allocating path sizes them by leaf size, ensure_cache).
+template <class Take>
+sph_status lay_out(sph_ctx *c, int64_t cap, Take take)
 {
-    if (n > (int64_t)0xFFFFFFF0ll) return fail(c, SPH_EINVAL, "n exceeds 2^32 - 16");
-    if (n <= c->ncap && node_count_bound(n) <= c->node_cap) return ensure_cache(c);
-    int64_t cap = std::max<int64_t>(n, 1024);
-    int64_t need = bytes_per_particle(c->p) * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
-                   256 * 4 * ceil_div(cap, kRsTile) + 4096 + cache_bytes(c->p.leaf_size, pair_grid(cap));
-    if (c->budget && (size_t)need > c->budget)
-        return fail(c, SPH_EBUDGET, "working set of " + std::to_string(need) +
-                                        " bytes exceeds the HBM budget of " +
-                                        std::to_string(c->budget));
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
-    bool was_resident = c->resident;
-    free_all(c);
-    if (was_resident) return fail(c, SPH_ESTATE, "resident state lost on reallocation");
     sph_status s = SPH_OK;
     Sorted &S = c->s, &T = c->t;
-#define A_(ptr, cnt) if (s == SPH_OK) s = alloc(c, &(ptr), (cnt))
+#define A_(ptr, cnt) if (s == SPH_OK) s = take(&(ptr), (cnt))
     A_(c->keys[0], cap); A_(c->keys[1], cap);
     A_(c->vals[0], cap); A_(c->vals[1], cap);
     double **sd[] = {&S.x, &S.y, &S.z, &S.vx, &S.vy, &S.vz, &S.m, &S.u, &S.h, &S.rho, &S.omega,
@@ -194,21 +189,34 @@ sph_status ensure_capacity(sph_ctx *c, int64_t n)
     A_(S.id, cap); A_(T.id, cap);
     A_(S.fx, cap); A_(S.fy, cap); A_(S.fz, cap);
     A_(c->lstart, cap + 1); A_(c->leaf_id, cap);
+    A_(c->nodes, node_count_bound(cap));
+    A_(c->hist, hist_words(cap));
 #undef A_
-    if (s != SPH_OK) { free_all(c); return s; }
-    int64_t ncap_nodes = node_count_bound(cap);
-    hipError_t e1 = hipMalloc((void **)&c->nodes, sizeof(Node) * (size_t)ncap_nodes);
-    int64_t hcap = 256 * ceil_div(cap, kRsTile) + 256;   // tile counts per digit + digit totals
-    hipError_t e2 = hipMalloc((void **)&c->hist, sizeof(uint32_t) * (size_t)hcap);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
-        (void)hipGetLastError();
-        free_all(c);
-        return fail(c, SPH_ENOMEM, "hipMalloc failed (tree)");
-    }
-    c->bytes += sizeof(Node) * (size_t)ncap_nodes + sizeof(uint32_t) * (size_t)hcap;
-    c->node_cap = ncap_nodes;
-    c->hist_cap = hcap;
+    if (s != SPH_OK) return s;
+    c->node_cap = node_count_bound(cap);
+    c->hist_cap = hist_words(cap);
     c->ncap = cap;
+    return SPH_OK;
+}
+
+sph_status ensure_capacity(sph_ctx *c, int64_t n)
+{
+    if (n > (int64_t)0xFFFFFFF0ll) return fail(c, SPH_EINVAL, "n exceeds 2^32 - 16");
+    if (n <= c->ncap && node_count_bound(n) <= c->node_cap) return ensure_cache(c);
+    int64_t cap = std::max<int64_t>(n, 1024);
+    int64_t need = bytes_per_particle(c->p) * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
+                   4 * hist_words(cap) + 4096 + cache_bytes(c->p.leaf_size, pair_grid(cap));
+    if (c->budget && (size_t)need > c->budget)
+        return fail(c, SPH_EBUDGET, "working set of " + std::to_string(need) +
+                                        " bytes exceeds the HBM budget of " +
+                                        std::to_string(c->budget));
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
+    bool was_resident = c->resident;
+    free_all(c);
+    if (was_resident) return fail(c, SPH_ESTATE, "resident state lost on reallocation");
+    sph_status s = lay_out(c, cap, [c](auto **ptr, int64_t count) { return alloc(c, ptr, count); });
+    if (s != SPH_OK) { free_all(c); return s; }
     return ensure_cache(c);
 }
 
@@ -471,7 +479,7 @@ sph_status check_batch(sph_ctx *const *cs, int32_t count)
 // sph_evaluate in phases shared with the batched call: sort, gather and
 // tree, density arguments / leaf hmax, force records and force arguments /
 // scatter of every output.
-sph_status evaluate_pre(sph_ctx *c, const sph_particles *ps)
+sph_status evaluate_pre(sph_ctx *c, const sph_particles *ps, bool laid_out = false)
 {
     TRY(check_ps(c, ps));
     REQ(ps->x, "x"); REQ(ps->y, "y"); REQ(ps->z, "z");
@@ -481,7 +489,7 @@ sph_status evaluate_pre(sph_ctx *c, const sph_particles *ps)
     REQ(ps->vsig, "vsig"); REQ(ps->dt, "dt");
     c->resident = false;
     const int64_t n = ps->n;
-    TRY(ensure_capacity(c, n));
+    if (!laid_out) TRY(ensure_capacity(c, n));
     c->n = n;
     if (n == 0) return SPH_OK;
     // one sort and one gather of every input; the sorted set stays on the
@@ -537,6 +545,136 @@ sph_status evaluate_post(sph_ctx *c, const sph_particles *ps)
     return reduce_diag(c, n);
 }
 
+
+// ---- the no-allocation entry point ---------------------------------------------
+//
+// sph_evaluate_noalloc runs sph_evaluate with every capacity-sized buffer
+// (sort keys, sorted copies, tree, candidate lists) carved out of one static
+// device array instead of the context's own allocations, so the call makes no
+// device allocation, free or stream synchronisation.  The array holds the
+// buffers of kStaticMaxN particles; the pair kernels' persistent grid is
+// capped by the candidate-list slices that fit (kStaticListBlocks at leaf
+// size 32, more at smaller leaves).  Every call on one device shares that
+// device's copy: calls that overlap on a device race.
+constexpr int64_t kStaticMaxN = 32768;
+constexpr int64_t kStaticListBlocks = 256;
+
+constexpr int64_t static_node_bound(int64_t n)
+{
+    int64_t cnt = n < 1 ? 1 : n, tot = 0;
+    for (;;) {
+        tot += cnt;
+        if (cnt <= 1) break;
+        cnt = (cnt + 7) / 8;
+    }
+    return tot;
+}
+// the static array: every buffer of lay_out at capacity kStaticMaxN (256-byte
+// aligned slices: 60 buffers at most), and the candidate lists
+constexpr int64_t kStaticBytes =
+    kStaticMaxN * 400 + static_node_bound(kStaticMaxN) * (int64_t)sizeof(Node) +
+    4 * (256 * ((kStaticMaxN + 4095) / 4096) + 256) + 60 * 256 +
+    kStaticListBlocks * 2 * (int64_t)kCacheEntriesPerParticle * 32 * (int64_t)sizeof(double);
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64];
+static hipError_t g_scratch_err[64];
+static bool g_scratch_done[64];
+
+// The device address of this device's copy of `scratch`, taken once per device
+// with that device current (host code never uses the array's name itself).
+void init_static_scratch(sph_ctx *c)
+{
+    c->static_scratch = nullptr;
+    if (c->device < 0 || c->device >= 64) {
+        c->static_err = "device index out of range for the static scratch table";
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[c->device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_err[c->device] = e;
+        g_scratch_ptr[c->device] = e == hipSuccess ? ptr : nullptr;
+        if (e != hipSuccess) (void)hipGetLastError();
+        g_scratch_done[c->device] = true;
+    }
+    c->static_scratch = g_scratch_ptr[c->device];
+    if (!c->static_scratch)
+        c->static_err = std::string("hipGetSymbolAddress(scratch): ") +
+                        hipGetErrorString(g_scratch_err[c->device]);
+}
+
+// The capacity-sized buffers of a context, saved around a call that points
+// them into the static array.
+struct SavedBuffers {
+    uint64_t *keys[2];
+    uint32_t *vals[2];
+    uint32_t *hist;
+    int64_t hist_cap;
+    uint32_t *perm;
+    Node *nodes;
+    int64_t node_cap;
+    uint32_t *lstart, *leaf_id;
+    double *cache;
+    int64_t cache_size;
+    uint64_t *skeys;
+    uint32_t *scratch_u32;
+    int64_t tree_n, ncap;
+    Sorted s, t;
+};
+
+SavedBuffers save_buffers(const sph_ctx *c)
+{
+    return SavedBuffers{{c->keys[0], c->keys[1]}, {c->vals[0], c->vals[1]}, c->hist, c->hist_cap,
+                        c->perm, c->nodes, c->node_cap, c->lstart, c->leaf_id, c->cache,
+                        c->cache_size, c->skeys, c->scratch_u32, c->tree_n, c->ncap, c->s, c->t};
+}
+
+void restore_buffers(sph_ctx *c, const SavedBuffers &b)
+{
+    c->keys[0] = b.keys[0]; c->keys[1] = b.keys[1];
+    c->vals[0] = b.vals[0]; c->vals[1] = b.vals[1];
+    c->hist = b.hist; c->hist_cap = b.hist_cap;
+    c->perm = b.perm;
+    c->nodes = b.nodes; c->node_cap = b.node_cap;
+    c->lstart = b.lstart; c->leaf_id = b.leaf_id;
+    c->cache = b.cache; c->cache_size = b.cache_size;
+    c->skeys = b.skeys; c->scratch_u32 = b.scratch_u32;
+    c->tree_n = b.tree_n; c->ncap = b.ncap;
+    c->s = b.s; c->t = b.t;
+}
+
+// Point every capacity-sized buffer of c into [base, base + kStaticBytes).
+sph_status carve_static(sph_ctx *c, unsigned char *base)
+{
+    int64_t used = 0;
+    auto take_bytes = [&](int64_t bytes) -> unsigned char * {
+        const int64_t at = (used + 255) & ~(int64_t)255;
+        if (at + bytes > kStaticBytes) return nullptr;
+        used = at + bytes;
+        return base + at;
+    };
+    sph_status s = lay_out(c, kStaticMaxN, [&](auto **ptr, int64_t count) {
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(*ptr)>>;
+        unsigned char *q = take_bytes(std::max<int64_t>(count, 1) * (int64_t)sizeof(T));
+        if (!q) return fail(c, SPH_ENOMEM, "static scratch layout overflow");
+        *ptr = (T *)q;
+        return SPH_OK;
+    });
+    if (s != SPH_OK) return s;
+    // the candidate lists take the rest, whole per-block slices at this leaf size
+    const int64_t at = (used + 255) & ~(int64_t)255;
+    const int64_t per = cache_bytes(c->p.leaf_size, 1);
+    const int64_t blocks = std::min<int64_t>((kStaticBytes - at) / per, kMaxPairBlocks) / kXcds * kXcds;
+    if (blocks < kXcds) return fail(c, SPH_ENOMEM, "static scratch holds no candidate lists");
+    c->cache = (double *)(base + at);
+    c->cache_size = blocks * per;
+    return SPH_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -573,6 +711,7 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
     c->stream = (hipStream_t)hip_stream;
     c->budget = budget;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return SPH_EDEVICE; }
+    init_static_scratch(c);
     bool ok = hipMalloc((void **)&c->d_status, sizeof(int32_t) * kStatusWords) == hipSuccess &&
               hipMalloc((void **)&c->d_scal, sizeof(double) * 16) == hipSuccess &&
               hipMalloc((void **)&c->d_counts, sizeof(int64_t) * kCountWords) == hipSuccess &&
@@ -687,6 +826,35 @@ sph_status sph_evaluate(sph_ctx *c, sph_particles *ps)
     TRY(forces_launch(&c, 1, ps->n));
     return evaluate_post(c, ps);
 }
+
+sph_status sph_evaluate_noalloc(sph_ctx *c, sph_particles *ps)
+{
+    TRY(check_ps(c, ps));
+    if (ps->n > kStaticMaxN)
+        return fail(c, SPH_ECAP, "sph_evaluate_noalloc: n = " + std::to_string(ps->n) +
+                                     " exceeds its maximum of " + std::to_string(kStaticMaxN));
+    if (!c->static_scratch) return fail(c, SPH_EDEVICE, "static scratch: " + c->static_err);
+    const SavedBuffers saved = save_buffers(c);
+    const bool timing = c->timer.on;
+    c->timer.on = false;   // event creation is not allowed here
+    sph_status s = carve_static(c, (unsigned char *)c->static_scratch);
+    if (s == SPH_OK) s = evaluate_pre(c, ps, true);
+    if (s == SPH_OK && ps->n > 0) {
+        s = density_launch(&c, 1, ps->n);
+        if (s == SPH_OK) s = evaluate_mid(c);
+        if (s == SPH_OK) s = forces_launch(&c, 1, ps->n);
+        if (s == SPH_OK) s = evaluate_post(c, ps);
+    }
+    // the context's own buffers are back; the structure built in the static
+    // array is not theirs, and (as after sph_evaluate) no state is resident
+    restore_buffers(c, saved);
+    c->built = false;
+    c->resident = false;
+    c->timer.on = timing;
+    return s;
+}
+
+int64_t sph_noalloc_max_n(void) { return kStaticMaxN; }
 
 sph_status sph_batch_evaluate(sph_ctx *const *cs, sph_particles *const *ps, int32_t count)
 {

@@ -210,6 +210,11 @@ struct sph_ctx {
 
     sph::Timer timer;
     bool count_tests = false;   // pair loops also count box and candidate tests
+
+    // this device's copy of the library's static scratch array (the
+    // no-allocation entry point); nullptr if its address could not be taken
+    void *static_scratch = nullptr;
+    std::string static_err;
 };
 
 namespace sph {

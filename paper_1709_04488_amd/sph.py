@@ -32,7 +32,7 @@ EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream",
             "sph_last_error", "sph_device_bytes", "sph_enable_kernel_timing", "sph_kernel_times",
             "sph_batch_density", "sph_batch_forces", "sph_batch_evaluate", "sph_batch_step",
             "sph_capture_steps",
-            "sph_replay_steps", "sph_plan_bytes"]
+            "sph_replay_steps", "sph_plan_bytes", "sph_evaluate_noalloc", "sph_noalloc_max_n"]
 
 
 class SphError(RuntimeError):
@@ -121,6 +121,8 @@ def load() -> ctypes.CDLL:
         "sph_capture_steps": (ctypes.c_int, [vp, d]),
         "sph_replay_steps": (ctypes.c_int, [vp]),
         "sph_plan_bytes": (ctypes.c_size_t, [P, i64]),
+        "sph_evaluate_noalloc": (ctypes.c_int, [vp, PS]),
+        "sph_noalloc_max_n": (i64, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -285,6 +287,12 @@ class Context:
         set kept in sorted order on the device in between (sph_evaluate)."""
         ps = p.c()
         self._check(self.lib.sph_evaluate(self.h, ctypes.byref(ps)), "sph_evaluate")
+
+    def evaluate_noalloc(self, p: Particles):
+        """sph_evaluate without device allocation: the library's static
+        scratch array holds every buffer (n <= sph_noalloc_max_n())."""
+        ps = p.c()
+        self._check(self.lib.sph_evaluate_noalloc(self.h, ctypes.byref(ps)), "sph_evaluate_noalloc")
 
     def density_then_forces(self, p: Particles):
         """The same evaluation as two calls, sph_density then sph_forces."""
