@@ -76,19 +76,84 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Cross-lane moves inside a 16-lane DPP row, for butterfly reductions: the
+// value of lane l ^ O for O = 1, 2 (quad permutes); for O = 4 and 8 the value
+// of the mirrored lane of l's 8- or 16-lane group, which is lane l ^ O's value
+// wherever the value is already uniform over groups of O lanes -- as it is at
+// that step of a butterfly.  No LDS and no lane-address registers.
+template <int O>
+__device__ inline int xlane(int v)
+{
+    static_assert(O == 1 || O == 2 || O == 4 || O == 8, "within one DPP row");
+    constexpr int ctrl = O == 1 ? 0xB1 : O == 2 ? 0x4E : O == 4 ? 0x141 : 0x140;
+    return __builtin_amdgcn_update_dpp(v, v, ctrl, 0xF, 0xF, false);
+}
+template <int O>
+__device__ inline double xlane(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)xlane<O>((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)xlane<O>((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over each group of K consecutive lanes (K = 1, 2, 4, 8, 16), the same
+// bits on every lane of the group (IEEE addition is commutative).
+template <int K, class T>
+__device__ inline T group_sum(T v)
+{
+    if constexpr (K >= 2) v += xlane<1>(v);
+    if constexpr (K >= 4) v += xlane<2>(v);
+    if constexpr (K >= 8) v += xlane<4>(v);
+    if constexpr (K >= 16) v += xlane<8>(v);
+    return v;
+}
+template <int K>
+__device__ inline double group_max(double v)
+{
+    if constexpr (K >= 2) v = fmax(v, xlane<1>(v));
+    if constexpr (K >= 4) v = fmax(v, xlane<2>(v));
+    if constexpr (K >= 8) v = fmax(v, xlane<4>(v));
+    if constexpr (K >= 16) v = fmax(v, xlane<8>(v));
+    return v;
+}
+
+// Wave-wide maxima: each 16-lane row by DPP, then the four rows' values read
+// into scalar registers (wave-uniform result).
 __device__ inline double wave_max(double v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
+    v = group_max<16>(v);
+    auto row = [&](int l) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, l);
+        const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+        return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    };
+    return fmax(fmax(row(0), row(16)), fmax(row(32), row(48)));
+}
+
+// Wave-wide sum of small non-negative per-lane counts, wave-uniform.
+__device__ inline int64_t wave_sum_int(int v)
+{
+    v = group_sum<16>(v);
+    return (int64_t)__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+           (int64_t)__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
 __device__ inline int wave_max_int(int v)
 {
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o);
-        v = w > v ? w : v;
-    }
-    return v;
+    int w = xlane<1>(v);
+    v = w > v ? w : v;
+    w = xlane<2>(v);
+    v = w > v ? w : v;
+    w = xlane<4>(v);
+    v = w > v ? w : v;
+    w = xlane<8>(v);
+    v = w > v ? w : v;
+    const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    const int ab = a > b ? a : b, cd = c > d ? c : d;
+    return ab > cd ? ab : cd;
 }
 
 // Persistent work loop over the leaves.  Blocks are dispatched round-robin
@@ -113,7 +178,7 @@ __device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work
             if (lane == 0) claim = atomicAdd(&work[x], 1u);
             // wave-uniform from here on (scalar registers): the leaf's argument
             // block, node and particle range are then loaded once per wave
-            claim = __builtin_amdgcn_readfirstlane(__shfl(claim, 0));
+            claim = (uint32_t)__builtin_amdgcn_readlane((int)claim, 0);
             const int64_t leaf = beg + (int64_t)claim;
             if (leaf >= end) break;
             fn(leaf);
@@ -805,7 +870,6 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
     const __attribute__((address_space(4))) DensArgs *Ap = nullptr;
     // per-request diagnostics, flushed when the wave moves to another request
     auto flush_counts = [&]() {
-        for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o);
         if (lane == 0 && cur >= 0) {
             auto add = [&](int k, int64_t v) {
                 if (v) atomicAdd((unsigned long long *)&Ap->counts[k], (unsigned long long)v);
@@ -882,6 +946,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
         walks++;
         if (wr.lev) overflows++;
         int iter = 0;
+        int evals_leaf = 0;   // this lane's density pairs evaluated for this leaf
         // list state of this particle: `cached` = the list holds every
         // candidate within 2 Rc (count <= KP); valid while h <= Rc
         bool cached = false;
@@ -903,8 +968,9 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 const double ra2 = fabs(r2);
                 if (PREC == SPH_FP64) {
                     double f, df;
-                    // r = r^2 / sqrt(r^2) through rsqrt_nr (0 for the particle itself)
-                    const double qq = (ra2 > 0.0 ? ra2 * rsqrt_nr(ra2) : 0.0) * hinv;
+                    // r = r^2 / sqrt(r^2) through rsqrt_nr, without a branch: the
+                    // particle itself (r^2 = 0) gives 0 * finite = 0
+                    const double qq = (ra2 * rsqrt_nr(fmax(ra2, 1e-300))) * hinv;
                     m4(qq, f, df);
                     s0 += mj * f;
                     s2 += mj * (qq * df);
@@ -993,23 +1059,34 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 // the entries inside 2h, in list order, are the hits of a sweep
                 // (rows <= ROWS: a cached list has at most KP entries.)  Rows past
                 // this lane's entries pass r^2 = (2h)^2, which adds nothing
+                // Rows are read kRowBatch at a time, every load issued before the
+                // first sum (ROWS is a multiple of kRowBatch, so the rows read past
+                // `rows` stay inside the block's slice; they count as not mine)
+                constexpr int kRowBatch = 4;
+                static_assert(ROWS % kRowBatch == 0, "list rows come in whole batches");
                 const int rows = wave_max_int(conv ? 0 : (count + LPP - 1) / LPP);
-                for (int rr = 0; rr < rows; rr++) {
-                    const bool mine = !conv && rr * LPP + q < count;
-                    const double r2 = cr2[rr * kWave + lane];
-                    const double mw = equal_m ? 0.0 : cm[rr * kWave + lane];
-                    accumulate(mine ? r2 : h2x4, mw);
+                const double *__restrict__ lr2 = cr2 + lane;
+                const double *__restrict__ lm = cm + lane;
+                for (int r0 = 0; r0 < rows; r0 += kRowBatch) {
+                    double r2b[kRowBatch], mwb[kRowBatch];
+#pragma unroll
+                    for (int b = 0; b < kRowBatch; b++) {
+                        r2b[b] = lr2[(r0 + b) * kWave];
+                        mwb[b] = equal_m ? 0.0 : lm[(r0 + b) * kWave];
+                    }
+#pragma unroll
+                    for (int b = 0; b < kRowBatch; b++) {
+                        const bool mine = !conv && (r0 + b) * LPP + q < count;
+                        accumulate(mine ? r2b[b] : h2x4, mwb[b]);
+                    }
                 }
             }
-            if (!conv) evals += cnt;
+            if (!conv) evals_leaf += cnt;
             // one evaluation for every particle still iterating (uniform)
             nr_total += (int64_t)__popcll(__ballot(!conv && q == 0));
-#pragma unroll
-            for (int o = 1; o < LPP; o <<= 1) {
-                s0 += __shfl_xor(s0, o);
-                s2 += __shfl_xor(s2, o);
-                cnt += __shfl_xor(cnt, o);
-            }
+            s0 = group_sum<LPP>(s0);
+            s2 = group_sum<LPP>(s2);
+            cnt = group_sum<LPP>(cnt);
             if (!conv) {
                 // the root of g(h) = h^3 rho(h) - eta^3 m = sigma sum m f - eta^3 m
                 // (non-decreasing in h) is the h of the h-rho relation.  Newton runs
@@ -1078,6 +1155,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             }
         }
         iter_max = iter > iter_max ? iter : iter_max;
+        evals += wave_sum_int(evals_leaf);
         wave_lds_sync();   // the home table is rewritten for the next leaf
     });
     flush_counts();
@@ -1126,7 +1204,6 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
     int cur = -1;
     const __attribute__((address_space(4))) ForceArgs *Fp = nullptr;
     auto flush_counts = [&]() {
-        for (int o = 32; o > 0; o >>= 1) pairs_total += __shfl_xor(pairs_total, o);
         if (lane == 0 && cur >= 0) {
             auto add = [&](int k, int64_t v) {
                 if (v) atomicAdd((unsigned long long *)&Fp->counts[k], (unsigned long long)v);
@@ -1350,15 +1427,12 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             wave_lds_sync();
         };
         for_each_leaf_group<NL>(T, F.nodes, wr, test, wb, group);
-#pragma unroll
-        for (int o = 1; o < LPP; o <<= 1) {
-            axi += __shfl_xor(axi, o);
-            ayi += __shfl_xor(ayi, o);
-            azi += __shfl_xor(azi, o);
-            dui += __shfl_xor(dui, o);
-            vs_max = fmax(vs_max, __shfl_xor(vs_max, o));
-            selfs += __shfl_xor(selfs, o);
-        }
+        axi = group_sum<LPP>(axi);
+        ayi = group_sum<LPP>(ayi);
+        azi = group_sum<LPP>(azi);
+        dui = group_sum<LPP>(dui);
+        vs_max = group_max<LPP>(vs_max);
+        selfs = group_sum<LPP>(selfs);
         cnt -= selfs;
         if (active && q == 0) {
             const double vsig = cnt > 0 ? vs_max : 2.0 * ci;
@@ -1375,7 +1449,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                 atomicAdd(&F.status[2], 1);
             }
         }
-        pairs_total += (q == 0 && active) ? cnt : 0;
+        pairs_total += wave_sum_int((q == 0 && active) ? cnt : 0);
         wave_lds_sync();   // the home table is rewritten for the next leaf
     });
     flush_counts();
