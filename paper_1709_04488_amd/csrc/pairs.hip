@@ -277,6 +277,17 @@ __device__ inline double rsqrt_nr(double x)
     return y;
 }
 
+// 1/sqrt(x) for x > 0 with one Newton-Raphson step on the hardware estimate:
+// the estimate's relative error is squared once, to well below 1e-13 -- the
+// density sums need q = r/h to far better than their 1e-10 parity bound, not
+// to the last bit.
+__device__ inline double rsqrt_nr1(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double r = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, r, y);
+}
+
 // 1/x for x > 0: the hardware estimate refined by two Newton-Raphson steps
 // on 1/y - x, to about 1 ulp.
 __device__ inline double rcp_nr(double x)
@@ -294,8 +305,8 @@ __device__ inline double rcp_nr(double x)
 template <class T>
 __device__ inline void m4(T qq, T &f, T &df)
 {
-    T a = qq < T(2) ? T(2) - qq : T(0);
-    T b = qq < T(1) ? T(1) - qq : T(0);
+    T a = fmax(T(2) - qq, T(0));
+    T b = fmax(T(1) - qq, T(0));
     T a2 = a * a, b2 = b * b;
     f = T(0.25) * a2 * a - b2 * b;
     df = T(3) * b2 - T(0.75) * a2;
@@ -958,30 +969,32 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             const double hinv = 1.0 / h;
             const double h2x4 = (2.0 * h) * (2.0 * h);
             const float h2x4f = (float)h2x4;
-            // pair terms of one list entry (r^2 and the mark of the particle itself)
+            // pair terms of one list entry (r^2, and the mass when masses differ).
             // Branch-free: an entry outside 2h adds 0 * f (+0 or -0, which leave
             // the sums' bits unchanged) and no count; the lanes of a wave almost
-            // never agree on skipping, so a branch would save no work.
+            // never agree on skipping, so a branch would save no work.  The
+            // particle itself is an entry (r^2 = 0) and is counted here; the
+            // count drops it after the reduction.
             auto accumulate = [&](double r2, double mw) {
                 const bool in = PREC == SPH_FP64 ? r2 < h2x4 : (float)r2 < h2x4f;
-                const double mj = in ? (equal_m ? mu : fabs(mw)) : 0.0;
-                const double ra2 = fabs(r2);
+                const double mj = in ? (equal_m ? mu : mw) : 0.0;
                 if (PREC == SPH_FP64) {
                     double f, df;
-                    // r = r^2 / sqrt(r^2) through rsqrt_nr, without a branch: the
-                    // particle itself (r^2 = 0) gives 0 * finite = 0
-                    const double qq = (ra2 * rsqrt_nr(fmax(ra2, 1e-300))) * hinv;
+                    // r = r^2 / sqrt(r^2) without a branch (r^2 = 0 gives
+                    // 0 * finite = 0; the 1e-300 leaves any r^2 above 1e-284
+                    // unchanged); one refinement of the hardware estimate
+                    const double qq = (r2 * rsqrt_nr1(r2 + 1e-300)) * hinv;
                     m4(qq, f, df);
                     s0 += mj * f;
                     s2 += mj * (qq * df);
                 } else {
                     float f, df;
-                    const float qq = sqrtf((float)ra2) * (float)hinv;
+                    const float qq = sqrtf((float)r2) * (float)hinv;
                     m4(qq, f, df);
                     s0 += mj * (double)f;
                     s2 += mj * (double)(qq * df);
                 }
-                cnt += (in && !signbit(equal_m ? r2 : mw)) ? 1 : 0;
+                cnt += in ? 1 : 0;
             };
             if (__ballot(!conv && !cached) != 0ull) {
                 // sweep: every particle still iterating takes its pair terms from
@@ -1028,18 +1041,16 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                             separation<G, PREC, decltype(ppc)::value>(
                                 S, bx, PREC == SPH_FP64 ? S.hx[p] : hx, PREC == SPH_FP64 ? S.hy[p] : hy,
                                 PREC == SPH_FP64 ? S.hz[p] : hz, hfx, hfy, hfz, sl, dx, dy, dz, r2);
-                            const bool self = S.j[sl] == (uint32_t)i;
                             // (with equal masses mw is not used, and FP32-pair
                             // does not stage it)
                             double mw = 0.0;
-                            if (PREC == SPH_FP64 || !equal_m) mw = self ? -S.c.w[sl] : S.c.w[sl];
-                            const double rw = self ? -r2 : r2;
+                            if (PREC == SPH_FP64 || !equal_m) mw = S.c.w[sl];
                             if (pos < KP) {
                                 const int at = (pos / LPP) * kWave + lane;
-                                cr2[at] = equal_m ? rw : r2;
+                                cr2[at] = r2;
                                 if (!equal_m) cm[at] = mw;
                             }
-                            accumulate(equal_m ? rw : r2, mw);
+                            accumulate(r2, mw);
                         });
                     };
                     const int n = any_pp ? flush(std::true_type{}) : flush(std::false_type{});
@@ -1067,6 +1078,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 const int rows = wave_max_int(conv ? 0 : (count + LPP - 1) / LPP);
                 const double *__restrict__ lr2 = cr2 + lane;
                 const double *__restrict__ lm = cm + lane;
+                const int lim = conv ? 0 : count;   // entries of this particle still iterating
                 for (int r0 = 0; r0 < rows; r0 += kRowBatch) {
                     double r2b[kRowBatch], mwb[kRowBatch];
 #pragma unroll
@@ -1076,17 +1088,17 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                     }
 #pragma unroll
                     for (int b = 0; b < kRowBatch; b++) {
-                        const bool mine = !conv && (r0 + b) * LPP + q < count;
+                        const bool mine = (r0 + b) * LPP + q < lim;
                         accumulate(mine ? r2b[b] : h2x4, mwb[b]);
                     }
                 }
             }
-            if (!conv) evals_leaf += cnt;
             // one evaluation for every particle still iterating (uniform)
             nr_total += (int64_t)__popcll(__ballot(!conv && q == 0));
             s0 = group_sum<LPP>(s0);
             s2 = group_sum<LPP>(s2);
-            cnt = group_sum<LPP>(cnt);
+            cnt = group_sum<LPP>(cnt) - 1;   // without the particle itself
+            if (!conv && q == 0) evals_leaf += cnt;
             if (!conv) {
                 // the root of g(h) = h^3 rho(h) - eta^3 m = sigma sum m f - eta^3 m
                 // (non-decreasing in h) is the h of the h-rho relation.  Newton runs
