@@ -17,6 +17,10 @@ Functions and the passages they follow (GANDALF paper, arXiv:1709.04488):
   when alpha_ac > 0), signal speed and EQN:SPH_DT.
 * ``neighbours`` -- the neighbour sets those sums run over.
 * ``kdk``        -- eqs. EQN:LFKDK1/EQN:LFKDK2 with the section 5.1 loop order.
+* ``mm97_rate``, ``cd10_update`` -- the artificial-viscosity switches section
+  2.1.1 names (Morris & Monaghan 1997; Cullen & Dehnen 2010), in their
+  published forms; ``forces`` takes per-particle alpha and returns the
+  velocity divergence and curl they use.
 * ``sampled_evaluation`` -- the same quantities for a few particles of a
   large set, each computed one by one from its own neighbourhood.
 """
@@ -77,11 +81,15 @@ def _load():
         lib.orc_eos.restype = None
         lib.orc_eos.argtypes = [i64, d, vp, vp, vp, vp]
         lib.orc_forces.restype = ctypes.c_int
-        lib.orc_forces.argtypes = [vp, i64] + [vp] * 11 + [i64, vp] + [vp] * 9
+        lib.orc_forces.argtypes = [vp, i64] + [vp] * 11 + [i64, vp] + [vp] * 12
         lib.orc_neighbours.restype = ctypes.c_int
         lib.orc_neighbours.argtypes = [vp, i64, vp, vp, vp, vp, i32, i64, vp, vp, vp, i64]
         lib.orc_kdk.restype = ctypes.c_int
-        lib.orc_kdk.argtypes = [vp, i64] + [vp] * 9 + [i32, d, vp, vp]
+        lib.orc_kdk.argtypes = [vp, i64] + [vp] * 9 + [i32, d, vp, vp, vp]
+        lib.orc_mm97_rate.restype = None
+        lib.orc_mm97_rate.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        lib.orc_cd10_update.restype = None
+        lib.orc_cd10_update.argtypes = [vp, i64, d] + [vp] * 7
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -92,7 +100,14 @@ class _CParams(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("ccfl", ctypes.c_double), ("periodic", ctypes.c_int32),
                 ("ac_signal", ctypes.c_int32), ("lo", ctypes.c_double * 3),
-                ("hi", ctypes.c_double * 3), ("alpha_ac", ctypes.c_double)]
+                ("hi", ctypes.c_double * 3), ("alpha_ac", ctypes.c_double),
+                ("av_switch", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
+                ("av_ell", ctypes.c_double)]
+
+AV_NONE, AV_MM97, AV_CD10 = 0, 1, 2
+# published decay constants: MM97 tau = h/(0.1 c); CD10 tau = h/(2 0.05 v_sig)
+AV_ELL_DEFAULT = {AV_MM97: 0.1, AV_CD10: 0.05}
 
 
 @dataclass
@@ -113,6 +128,10 @@ class Params:
     hi: tuple = (1.0, 1.0, 1.0)
     alpha_ac: float = 0.0
     ac_signal: int = 0
+    av_switch: int = 0          # AV_NONE, AV_MM97 or AV_CD10
+    alpha_min: float = 0.1
+    alpha_max: float = 1.0
+    av_ell: float = 0.0         # 0: the switch's published value
 
     def c(self) -> _CParams:
         p = _CParams()
@@ -120,6 +139,9 @@ class Params:
         p.periodic = 1 if self.periodic else 0
         p.ac_signal = int(self.ac_signal)
         p.alpha_ac = float(self.alpha_ac)
+        p.av_switch = int(self.av_switch)
+        p.alpha_min, p.alpha_max = float(self.alpha_min), float(self.alpha_max)
+        p.av_ell = float(self.av_ell) if self.av_ell > 0.0 else AV_ELL_DEFAULT.get(self.av_switch, 0.0)
         for k in range(3):
             p.lo[k] = float(self.lo[k])
             p.hi[k] = float(self.hi[k])
@@ -208,8 +230,11 @@ def eos(gamma: float, rho, u):
     return P, c
 
 
-def forces(params: Params, x, y, z, vx, vy, vz, m, u, h, rho, omega, sel=None) -> dict:
-    """a, du/dt, v_sig, dt_i, per-particle scales and force-neighbour counts."""
+def forces(params: Params, x, y, z, vx, vy, vz, m, u, h, rho, omega, sel=None,
+           alpha=None) -> dict:
+    """a, du/dt, v_sig, dt_i, per-particle scales, force-neighbour counts,
+    velocity divergence and curl; alpha: per-particle viscosity strengths
+    (pair value (alpha_i + alpha_j)/2), default alpha_AV everywhere."""
     lib = _load()
     arrs = [_f64(a) for a in (x, y, z, vx, vy, vz, m, u, h, rho, omega)]
     n = arrs[0].size
@@ -218,19 +243,23 @@ def forces(params: Params, x, y, z, vx, vy, vz, m, u, h, rho, omega, sel=None) -
     keys = ("ax", "ay", "az", "dudt", "vsig", "dt", "scale_a", "scale_u")
     out = {key: np.empty(k, np.float64) for key in keys}
     out["nforce"] = np.empty(k, np.int32)
+    out["divv"] = np.empty(k, np.float64)
+    out["curlv"] = np.empty(k, np.float64)
+    al = None if alpha is None else _f64(alpha)
     cp = _CParams.from_buffer_copy(params.c())
     rc = lib.orc_forces(ctypes.byref(cp), n, *[_ptr(a) for a in arrs], k, _ptr(sel_a),
-                        *[_ptr(out[key]) for key in keys], _ptr(out["nforce"]))
+                        *[_ptr(out[key]) for key in keys], _ptr(out["nforce"]), _ptr(al),
+                        _ptr(out["divv"]), _ptr(out["curlv"]))
     if rc != ORC_OK:
         raise OracleError(rc, "forces")
     return out
 
 
-def evaluate(params: Params, x, y, z, vx, vy, vz, m, u, h_guess) -> dict:
+def evaluate(params: Params, x, y, z, vx, vy, vz, m, u, h_guess, alpha=None) -> dict:
     """Full evaluation: density (h solve), EOS, forces, for every particle."""
     d = density(params, x, y, z, m, h_guess)
     P, c = eos(params.gamma, d["rho"], u)
-    f = forces(params, x, y, z, vx, vy, vz, m, u, d["h"], d["rho"], d["omega"])
+    f = forces(params, x, y, z, vx, vy, vz, m, u, d["h"], d["rho"], d["omega"], alpha=alpha)
     out = dict(d)
     out.update(f)
     out["P"], out["cs"] = P, c
@@ -261,22 +290,48 @@ def neighbours(params: Params, x, y, z, h, mode: int, sel=None):
     return off, idx[:total]
 
 
-def kdk(params: Params, x, y, z, vx, vy, vz, m, u, h_guess, nsteps: int, dt_fixed: float = 0.0):
-    """Integrate nsteps KDK steps.  Returns (state dict, energy[nsteps+1], dt[nsteps])."""
+def kdk(params: Params, x, y, z, vx, vy, vz, m, u, h_guess, nsteps: int, dt_fixed: float = 0.0,
+        alpha=None):
+    """Integrate nsteps KDK steps.  Returns (state dict, energy[nsteps+1], dt[nsteps]).
+    With an AV switch, alpha holds the initial per-particle strengths and the
+    state dict the final ones (key "alpha")."""
     lib = _load()
     st = {k: _f64(a).copy() for k, a in zip(("x", "y", "z", "vx", "vy", "vz", "u", "h"),
                                            (x, y, z, vx, vy, vz, u, h_guess))}
     m = _f64(m)
     n = m.size
+    if params.av_switch:
+        st["alpha"] = _f64(alpha if alpha is not None else np.full(n, params.alpha_max)).copy()
     energy = np.empty(nsteps + 1, np.float64)
     dts = np.empty(max(nsteps, 1), np.float64)
     cp = _CParams.from_buffer_copy(params.c())
     rc = lib.orc_kdk(ctypes.byref(cp), n, _ptr(st["x"]), _ptr(st["y"]), _ptr(st["z"]),
                      _ptr(st["vx"]), _ptr(st["vy"]), _ptr(st["vz"]), _ptr(m), _ptr(st["u"]),
-                     _ptr(st["h"]), int(nsteps), float(dt_fixed), _ptr(energy), _ptr(dts))
+                     _ptr(st["h"]), int(nsteps), float(dt_fixed), _ptr(energy), _ptr(dts),
+                     _ptr(st.get("alpha")))
     if rc != ORC_OK:
         raise OracleError(rc, "kdk")
     return st, energy, dts[:nsteps]
+
+
+def mm97_rate(params: Params, alpha, divv, c, h):
+    """d alpha / dt of the Morris & Monaghan 1997 switch."""
+    lib = _load()
+    arrs = [_f64(a) for a in (alpha, divv, c, h)]
+    out = np.empty_like(arrs[0])
+    cp = _CParams.from_buffer_copy(params.c())
+    lib.orc_mm97_rate(ctypes.byref(cp), arrs[0].size, *[_ptr(a) for a in arrs], _ptr(out))
+    return out
+
+
+def cd10_update(params: Params, dt: float, alpha, divv, divv_prev, curlv, vsig, c, h):
+    """alpha after one step of length dt under the Cullen & Dehnen 2010 switch."""
+    lib = _load()
+    al = _f64(alpha).copy()
+    arrs = [_f64(a) for a in (divv, divv_prev, curlv, vsig, c, h)]
+    cp = _CParams.from_buffer_copy(params.c())
+    lib.orc_cd10_update(ctypes.byref(cp), al.size, float(dt), _ptr(al), *[_ptr(a) for a in arrs])
+    return al
 
 
 # --- sampled evaluation for sets too large for O(N^2) -------------------------
@@ -320,7 +375,8 @@ def _local_density(params: Params, x, y, z, m, hg, d2, targets, Rs):
         Rs = float(np.max(need)) * 1.5
 
 
-def sampled_evaluation(params: Params, arrays: dict, sample, force_sample=None) -> SampledResult:
+def sampled_evaluation(params: Params, arrays: dict, sample, force_sample=None,
+                       alpha=None) -> SampledResult:
     """Oracle values for a few particles of a large set, one particle at a time.
 
     Density, h, omega, P, c for every particle of ``sample`` (each h is the
@@ -333,7 +389,8 @@ def sampled_evaluation(params: Params, arrays: dict, sample, force_sample=None) 
     only choose which particles get an exact root; they never enter a sum.
     This closure assumes that no other particle has a smoothing length larger
     than half its distance to i, which holds for the smooth density fields of
-    the synthetic workloads.
+    the synthetic workloads.  alpha: per-particle viscosity strengths (the AV
+    switches), indexed like the arrays.
     """
     t0 = time.perf_counter()
     x, y, z = (_f64(arrays[k]) for k in ("x", "y", "z"))
@@ -351,7 +408,7 @@ def sampled_evaluation(params: Params, arrays: dict, sample, force_sample=None) 
     known = {int(i): (hh, rr, oo) for i, hh, rr, oo in
              zip(sample.tolist(), d["h"].tolist(), d["rho"].tolist(), d["omega"].tolist())}
 
-    keys = ("ax", "ay", "az", "dudt", "vsig", "dt", "scale_a", "scale_u")
+    keys = ("ax", "ay", "az", "dudt", "vsig", "dt", "scale_a", "scale_u", "divv", "curlv")
     fvals = {k: np.empty(fsample.size) for k in keys}
     nforce = np.empty(fsample.size, np.int64)
     closure = 0
@@ -385,7 +442,8 @@ def sampled_evaluation(params: Params, arrays: dict, sample, force_sample=None) 
         os_ = np.array([known[j][2] for j in inside.tolist()])
         ii = int(np.searchsorted(inside, i))
         fo = forces(params, x[inside], y[inside], z[inside], vx[inside], vy[inside], vz[inside],
-                    m[inside], u[inside], hs, rs, os_, sel=[ii])
+                    m[inside], u[inside], hs, rs, os_, sel=[ii],
+                    alpha=None if alpha is None else np.asarray(alpha)[inside])
         for key in keys:
             fvals[key][k] = fo[key][0]
         nforce[k] = int(fo["nforce"][0])

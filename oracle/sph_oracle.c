@@ -42,6 +42,12 @@ typedef struct {
     int32_t ac_signal; /* conductivity signal speed: 0 Wadsley 2008, 1 Price 2008 */
     double lo[3], hi[3];
     double alpha_ac; /* alpha_AC, eq. EQN:MON97ENERGYDISS (0: no conductivity) */
+    /* artificial-viscosity switch named in section 2.1.1: 0 none (alpha_AV for
+     * every pair), 1 Morris & Monaghan 1997, 2 Cullen & Dehnen 2010 */
+    int32_t av_switch;
+    int32_t pad_;
+    double alpha_min, alpha_max; /* floor and ceiling of the per-particle alpha */
+    double av_ell;   /* decay constant: tau = h/(ell c) (MM97), h/(2 ell v_sig) (CD10) */
 } orc_params;
 
 /* ---------------------------------------------------------------------------
@@ -320,6 +326,13 @@ void orc_eos(int64_t n, double gamma, const double *rho, const double *u,
  *     du_i += (m_j / rhobar) alpha_AC v' (u_i - u_j) rhat_ij . Gbar
  *   (rhat_ij . Gbar is the mean of the two dW/dr, <= 0, so heat flows from
  *   the hotter particle to the colder one)
+ * Per-particle viscosity strengths (alpha != NULL, the AV switches): alpha_AV
+ * of the pair is (alpha_i + alpha_j)/2; beta_AV stays the global value.
+ * Velocity divergence and curl (outputs divv, curlv, may be NULL), the SPH
+ * estimates consistent with the grad-h density (eq. EQN:OMEGA):
+ *   divv_i = -1/(Omega_i rho_i) sum_{r_ij < 2 h_i} m_j v_ij . G_i
+ *   curlv_i = |1/(Omega_i rho_i) sum_{r_ij < 2 h_i} m_j v_ij x G_i|
+ * (G_i vanishes beyond 2 h_i, so they run over the density neighbours).
  * Coincident pairs (r_ij = 0) add nothing to a or du and enter vsig with
  * w = 0.  With no neighbour at all vsig_i = 2 c_i (the self-pair value).
  * dt_i = C_CFL h_i / vsig_i.
@@ -331,7 +344,8 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
                const double *m, const double *u, const double *h, const double *rho,
                const double *omega, int64_t nsel, const int64_t *sel,
                double *ax, double *ay, double *az, double *dudt, double *vsig,
-               double *dt, double *scale_a, double *scale_u, int32_t *nforce)
+               double *dt, double *scale_a, double *scale_u, int32_t *nforce,
+               const double *alpha, double *divv, double *curlv)
 {
     if (n < 0 || nsel < 0) return ORC_EINVAL;
     if (sel == NULL) nsel = n;
@@ -347,6 +361,7 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
         double vs_max = 2.0 * ci;
         int have_ngb = 0;
         int32_t cnt = 0;
+        double dv = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
         for (int64_t j = 0; j < n; j++) {
             if (j == i) continue;
             double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
@@ -377,9 +392,15 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
             if (w < 0.0) {
                 double rhobar = 0.5 * (rho[i] + rho[j]);
                 double gbar = 0.5 * (gi + gj);
-                cvec += (m[j] / rhobar) * p->alpha * vs * w * gbar;
-                cdu += -(m[j] / rhobar) * p->alpha * vs * 0.5 * w * w * gbar;
+                double aij = alpha ? 0.5 * (alpha[i] + alpha[j]) : p->alpha;
+                cvec += (m[j] / rhobar) * aij * vs * w * gbar;
+                cdu += -(m[j] / rhobar) * aij * vs * 0.5 * w * w * gbar;
             }
+            /* v_ij . G_i = w gi and v_ij x G_i = gi (v_ij x rhat) */
+            dv += m[j] * w * gi;
+            cx += m[j] * gi * (vyij * ez - vzij * ey);
+            cy += m[j] * gi * (vzij * ex - vxij * ez);
+            cz += m[j] * gi * (vxij * ey - vyij * ex);
             if (p->alpha_ac != 0.0) {
                 double rhobar = 0.5 * (rho[i] + rho[j]);
                 double gbar = 0.5 * (gi + gj);
@@ -402,8 +423,61 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
         scale_a[k] = sa;
         scale_u[k] = su;
         nforce[k] = cnt;
+        if (divv) divv[k] = -dv / (omega[i] * rho[i]);
+        if (curlv) curlv[k] = sqrt((cx * cx + cy * cy) + cz * cz) / (omega[i] * rho[i]);
     }
     return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * Artificial-viscosity switches (section 2.1.1 names both; the paper gives no
+ * formulas, these are the published ones).
+ *
+ * Morris & Monaghan 1997: each particle carries alpha_i with
+ *   d alpha_i / dt = -(alpha_i - alpha_min) ell c_i / h_i
+ *                    + max(-divv_i, 0) (alpha_max - alpha_i)
+ * (decay on tau = h/(ell c) towards alpha_min; the source max(-div v, 0) of
+ * MM97 carries the (alpha_max - alpha) factor of Rosswog et al. 2000 that
+ * keeps alpha below alpha_max).  alpha is integrated by the same
+ * kick-drift-kick as u.
+ * ------------------------------------------------------------------------- */
+void orc_mm97_rate(const orc_params *p, int64_t n, const double *alpha, const double *divv,
+                   const double *c, const double *h, double *adot)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double decay = -(alpha[i] - p->alpha_min) * p->av_ell * c[i] / h[i];
+        double src = divv[i] < 0.0 ? -divv[i] * (p->alpha_max - alpha[i]) : 0.0;
+        adot[i] = decay + src;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Cullen & Dehnen 2010, applied once per step after the forces at the end of
+ * the step (step length dt):
+ *   ddivv_i   = (divv_i - divv_prev_i) / dt      (finite-difference rate)
+ *   xi_i      = |divv_i| / (|divv_i| + curlv_i + 1e-4 c_i / h_i)   (shear limiter)
+ *   A_i       = xi_i max(-ddivv_i, 0)
+ *   alpha_loc = alpha_max h_i^2 A_i / (vsig_i^2 + h_i^2 A_i), at least alpha_min
+ *   alpha_i   = alpha_loc                                if alpha_i < alpha_loc
+ *             = alpha_loc + (alpha_i - alpha_loc) exp(-dt 2 ell vsig_i / h_i)  otherwise
+ * The rate of divv and the Balsara-type limiter stand in for CD10's
+ * gradient-of-acceleration estimate and its R-weighted limiter.
+ * ------------------------------------------------------------------------- */
+void orc_cd10_update(const orc_params *p, int64_t n, double dt, double *alpha,
+                     const double *divv, const double *divv_prev, const double *curlv,
+                     const double *vsig, const double *c, const double *h)
+{
+    for (int64_t i = 0; i < n; i++) {
+        double rate = (divv[i] - divv_prev[i]) / dt;
+        double ad = fabs(divv[i]);
+        double xi = ad / (ad + curlv[i] + 1e-4 * c[i] / h[i]);
+        double A = rate < 0.0 ? -xi * rate : 0.0;
+        double h2A = h[i] * h[i] * A;
+        double aloc = p->alpha_max * h2A / (vsig[i] * vsig[i] + h2A);
+        if (aloc < p->alpha_min) aloc = p->alpha_min;
+        if (alpha[i] < aloc) alpha[i] = aloc;
+        else alpha[i] = aloc + (alpha[i] - aloc) * exp(-dt * 2.0 * p->av_ell * vsig[i] / h[i]);
+    }
 }
 
 /* ---------------------------------------------------------------------------
@@ -480,37 +554,58 @@ static double total_energy(int64_t n, const double *m, const double *vx, const d
     return e;
 }
 
+/* Density and forces of every particle.  av holds the switch state:
+ * alpha (viscosity strength per particle, NULL without a switch) and the
+ * outputs divv, curlv, vsig, c (sound speed) of this evaluation. */
+typedef struct {
+    const double *alpha;
+    double *divv, *curlv, *vsig, *c;
+} orc_av_io;
+
 static int eval_all(const orc_params *p, int64_t n, const double *x, const double *y,
                     const double *z, const double *vx, const double *vy, const double *vz,
                     const double *m, const double *u, double *h, double *rho,
                     double *omega, double *ax, double *ay, double *az, double *du,
-                    double *dt, double *work)
+                    double *dt, double *work, orc_av_io av)
 {
-    double *hn = work, *drho = work + n, *vsig = work + 2 * n, *sa = work + 3 * n,
-           *su = work + 4 * n;
+    double *hn = work, *drho = work + n, *sa = work + 3 * n, *su = work + 4 * n;
     int32_t *cnt = (int32_t *)(work + 5 * n);
+    double *vsig = av.vsig ? av.vsig : work + 2 * n;
     int rc = orc_density(p, n, x, y, z, m, h, n, NULL, hn, rho, drho, omega, cnt);
     if (rc != ORC_OK) return rc;
     memcpy(h, hn, sizeof(double) * (size_t)n);
-    return orc_forces(p, n, x, y, z, vx, vy, vz, m, u, h, rho, omega, n, NULL, ax, ay, az,
-                      du, vsig, dt, sa, su, cnt);
+    rc = orc_forces(p, n, x, y, z, vx, vy, vz, m, u, h, rho, omega, n, NULL, ax, ay, az,
+                    du, vsig, dt, sa, su, cnt, av.alpha, av.divv, av.curlv);
+    if (rc == ORC_OK && av.c)
+        for (int64_t i = 0; i < n; i++) av.c[i] = sqrt(p->gamma * (p->gamma - 1.0) * u[i]);
+    return rc;
 }
 
+/* alpha (in/out, n values) is the per-particle viscosity strength of the
+ * switch in p->av_switch; ignored (may be NULL) without a switch. */
 int orc_kdk(const orc_params *p, int64_t n, double *x, double *y, double *z, double *vx,
             double *vy, double *vz, const double *m, double *u, double *h,
-            int32_t nsteps, double dt_fixed, double *energy, double *dt_used)
+            int32_t nsteps, double dt_fixed, double *energy, double *dt_used, double *alpha)
 {
     if (n <= 0 || nsteps < 0) return ORC_EINVAL;
+    const int sw = p->av_switch;
+    if (sw && !alpha) return ORC_EINVAL;
     size_t N = (size_t)n;
-    double *buf = (double *)malloc(sizeof(double) * N * 21);
+    double *buf = (double *)malloc(sizeof(double) * N * 30);
     if (!buf) return ORC_ENOMEM;
     double *rho = buf, *omega = buf + N, *ax = buf + 2 * N, *ay = buf + 3 * N,
            *az = buf + 4 * N, *du = buf + 5 * N, *dt = buf + 6 * N, *vxh = buf + 7 * N,
            *vyh = buf + 8 * N, *vzh = buf + 9 * N, *uh = buf + 10 * N, *vxp = buf + 11 * N,
            *vyp = buf + 12 * N, *vzp = buf + 13 * N, *up = buf + 14 * N, *work = buf + 15 * N;
     /* work: 5N doubles + N int32 (eval_all scratch) */
-    int rc = eval_all(p, n, x, y, z, vx, vy, vz, m, u, h, rho, omega, ax, ay, az, du, dt, work);
+    double *divv = buf + 21 * N, *curlv = buf + 22 * N, *vsig = buf + 23 * N,
+           *cs = buf + 24 * N, *adot = buf + 25 * N, *alh = buf + 26 * N, *alp = buf + 27 * N,
+           *dprev = buf + 28 * N;
+    orc_av_io av = {sw ? alpha : NULL, divv, curlv, vsig, cs};
+    int rc = eval_all(p, n, x, y, z, vx, vy, vz, m, u, h, rho, omega, ax, ay, az, du, dt, work, av);
     if (rc != ORC_OK) { free(buf); return rc; }
+    if (sw == 1) orc_mm97_rate(p, n, alpha, divv, cs, h, adot);
+    if (sw == 2) memcpy(dprev, divv, sizeof(double) * N);
     if (energy) energy[0] = total_energy(n, m, vx, vy, vz, u);
     double L[3];
     for (int k = 0; k < 3; k++) L[k] = p->hi[k] - p->lo[k];
@@ -540,15 +635,28 @@ int orc_kdk(const orc_params *p, int64_t n, double *x, double *y, double *z, dou
             vyp[i] = vyh[i] + 0.5 * d * ay[i];
             vzp[i] = vzh[i] + 0.5 * d * az[i];
             up[i] = uh[i] + 0.5 * d * du[i];
+            if (sw == 1) {
+                alh[i] = alpha[i] + 0.5 * d * adot[i];
+                alp[i] = alh[i] + 0.5 * d * adot[i];
+            }
         }
+        /* the forces at the end of the step see the predicted alpha (MM97) or
+         * the alpha of the start of the step (CD10) */
+        av.alpha = sw == 1 ? alp : (sw == 2 ? alpha : NULL);
         rc = eval_all(p, n, x, y, z, vxp, vyp, vzp, m, up, h, rho, omega, ax, ay, az, du, dt,
-                      work);
+                      work, av);
         if (rc != ORC_OK) { free(buf); return rc; }
+        if (sw == 1) orc_mm97_rate(p, n, alp, divv, cs, h, adot);
+        if (sw == 2) {
+            orc_cd10_update(p, n, d, alpha, divv, dprev, curlv, vsig, cs, h);
+            memcpy(dprev, divv, sizeof(double) * N);
+        }
         for (int64_t i = 0; i < n; i++) {
             vx[i] = vxh[i] + 0.5 * d * ax[i];
             vy[i] = vyh[i] + 0.5 * d * ay[i];
             vz[i] = vzh[i] + 0.5 * d * az[i];
             u[i] = uh[i] + 0.5 * d * du[i];
+            if (sw == 1) alpha[i] = alh[i] + 0.5 * d * adot[i];
         }
         if (energy) energy[s + 1] = total_energy(n, m, vx, vy, vz, u);
     }
