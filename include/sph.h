@@ -81,6 +81,9 @@ enum { SPH_FP64 = 0, SPH_FP32_PAIR = 1 };
 /* artificial-conductivity signal speed v'_SIG (section 2.1.1) */
 enum { SPH_AC_WADSLEY = 0, SPH_AC_PRICE = 1 };
 
+/* artificial-viscosity switch (section 2.1.1 names both) */
+enum { SPH_AV_NONE = 0, SPH_AV_MM97 = 1, SPH_AV_CD10 = 2 };
+
 /*
  * Method parameters.  Defaults (sph_default_params): eta = 1.2 (section
  * 2.1.1), gamma = 5/3, alpha_av = 1, beta_av = 2 alpha_av (section 2.1.1),
@@ -96,6 +99,29 @@ enum { SPH_AC_WADSLEY = 0, SPH_AC_PRICE = 1 };
  * and dt do not change.  The kernel rebuilds
  * u_j and P_j from the adiabatic EOS (u = c^2 / (gamma (gamma - 1)),
  * P = rho c^2 / gamma).
+ *
+ * Artificial-viscosity switches (section 2.1.1 names Morris & Monaghan 1997
+ * and Cullen & Dehnen 2010; their published forms): every particle carries
+ * its own alpha_i and the viscosity of a pair uses (alpha_i + alpha_j)/2
+ * (beta_av stays global).  With av_switch != SPH_AV_NONE the resident state
+ * (sph_upload_state / sph_step) evolves alpha, from ps->alpha at upload
+ * (NULL: alpha_av for every particle):
+ *   SPH_AV_MM97: d alpha/dt = -(alpha - alpha_min) ell c / h
+ *                             + max(-div v, 0) (alpha_max - alpha),
+ *                integrated by the kick-drift-kick like u (the forces at the
+ *                end of a step see the predicted alpha);
+ *   SPH_AV_CD10: after the forces at the end of each step (length dt):
+ *                A = xi max(-(div v - div v_prev)/dt, 0),
+ *                xi = |div v| / (|div v| + |curl v| + 1e-4 c/h),
+ *                alpha_loc = max(alpha_max h^2 A / (v_sig^2 + h^2 A), alpha_min),
+ *                alpha = alpha_loc if alpha < alpha_loc, else
+ *                alpha_loc + (alpha - alpha_loc) exp(-2 ell v_sig dt / h).
+ * ell = av_ell, or 0.1 (MM97) / 0.05 (CD10) when av_ell = 0.  div v and
+ * curl v are the grad-h SPH estimates
+ *   div v_i  = -1/(Omega_i rho_i) sum_j m_j v_ij . grad_i W(r_ij, h_i),
+ *   curl v_i = |1/(Omega_i rho_i) sum_j m_j v_ij x grad_i W(r_ij, h_i)|.
+ * Stateless sph_forces / sph_evaluate use ps->alpha when it is not NULL and
+ * write ps->divv / ps->curlv when those are not NULL, whatever av_switch is.
  *
  * precision = SPH_FP64: every pair term in double precision.
  * precision = SPH_FP32_PAIR: pair separations are formed in single precision
@@ -123,6 +149,10 @@ typedef struct {
     double alpha_ac;   /* artificial conductivity strength (>= 0; 0 disables it) */
     int32_t ac_signal; /* SPH_AC_WADSLEY: v' = |v_ij . rhat_ij| (the paper's
                           default); SPH_AC_PRICE: v' = sqrt(|P_i - P_j| / rhobar_ij) */
+    int32_t av_switch; /* SPH_AV_NONE (default), SPH_AV_MM97 or SPH_AV_CD10 */
+    double alpha_min;  /* switches: floor of alpha (default 0.1) */
+    double alpha_max;  /* switches: ceiling of alpha (default 1) */
+    double av_ell;     /* switches: decay constant ell (0: 0.1 MM97, 0.05 CD10) */
 } sph_params;
 
 /*
@@ -158,6 +188,10 @@ typedef struct {
     double *dt;           /* per-particle CFL step */
     int32_t *nngb;        /* density neighbours j != i with r_ij < 2 h_i */
     int32_t *nforce;      /* force neighbours j != i with r_ij < 2 max(h_i, h_j) */
+    double *alpha;        /* optional: per-particle alpha_AV (input; sph_download_state
+                             writes the evolved values) */
+    double *divv;         /* optional output: velocity divergence */
+    double *curlv;        /* optional output: magnitude of the velocity curl */
 } sph_particles;
 
 /* Diagnostics of the last evaluation (stateless or resident). */

@@ -29,17 +29,18 @@ namespace {
 constexpr int kRsTile = 4096;
 
 // per-particle device bytes of everything sized by the capacity
-int64_t bytes_per_particle(const sph_params &p)
+constexpr int64_t bytes_per_particle()
 {
     int64_t b = 0;
     b += 2 * 8 + 2 * 4;        // sort keys / values, ping-pong
     b += 17 * 8 + 2 * 4 + 4;   // s: doubles, nngb/nforce, id
     b += (int64_t)sizeof(ForceRec);   // s: force records
     b += 4 * 8;                // s: predictor arrays
+    b += 6 * 8;                // s: viscosity switches (alpha, predictor, rate, div v of
+                               //    the last step, div v, |curl v|)
     b += 3 * 4;                // s: fp32 offsets
-    b += 13 * 8 + 4;           // t: re-sort buffers
+    b += 16 * 8 + 4;           // t: re-sort buffers
     b += 2 * 4;                // leaf starts, leaf of each particle
-    (void)p;
     return b;
 }
 
@@ -60,6 +61,11 @@ sph_status check_params(sph_ctx *c, const sph_params *p)
         return fail(c, SPH_EINVAL, "alpha_ac must be finite and >= 0");
     if (p->ac_signal != SPH_AC_WADSLEY && p->ac_signal != SPH_AC_PRICE)
         return fail(c, SPH_EINVAL, "ac_signal must be SPH_AC_WADSLEY or SPH_AC_PRICE");
+    if (p->av_switch != SPH_AV_NONE && p->av_switch != SPH_AV_MM97 && p->av_switch != SPH_AV_CD10)
+        return fail(c, SPH_EINVAL, "av_switch must be SPH_AV_NONE, SPH_AV_MM97 or SPH_AV_CD10");
+    if (!(p->alpha_min >= 0.0) || !(p->alpha_max >= p->alpha_min) || !std::isfinite(p->alpha_max) ||
+        !(p->av_ell >= 0.0) || !std::isfinite(p->av_ell))
+        return fail(c, SPH_EINVAL, "need 0 <= alpha_min <= alpha_max (finite) and av_ell >= 0");
     if (p->periodic)
         for (int a = 0; a < 3; a++)
             if (!(p->box_hi[a] > p->box_lo[a]) || !std::isfinite(p->box_hi[a] - p->box_lo[a]))
@@ -181,8 +187,9 @@ sph_status lay_out(sph_ctx *c, int64_t cap, Take take)
     double **sd[] = {&S.x, &S.y, &S.z, &S.vx, &S.vy, &S.vz, &S.m, &S.u, &S.h, &S.rho, &S.omega,
                      &S.ax, &S.ay, &S.az, &S.du, &S.vsig, &S.dt,
                      &S.vpx, &S.vpy, &S.vpz, &S.up,
+                     &S.al, &S.alp, &S.adot, &S.dprev, &S.divv, &S.curlv,
                      &T.x, &T.y, &T.z, &T.vx, &T.vy, &T.vz, &T.m, &T.u, &T.h,
-                     &T.vpx, &T.vpy, &T.vpz, &T.up};
+                     &T.vpx, &T.vpy, &T.vpz, &T.up, &T.al, &T.alp, &T.dprev};
     for (double **pp : sd) A_(*pp, cap);
     A_(S.frec, cap);
     A_(S.nngb, cap); A_(S.nforce, cap);
@@ -204,7 +211,7 @@ sph_status ensure_capacity(sph_ctx *c, int64_t n)
     if (n > (int64_t)0xFFFFFFF0ll) return fail(c, SPH_EINVAL, "n exceeds 2^32 - 16");
     if (n <= c->ncap && node_count_bound(n) <= c->node_cap) return ensure_cache(c);
     int64_t cap = std::max<int64_t>(n, 1024);
-    int64_t need = bytes_per_particle(c->p) * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
+    int64_t need = bytes_per_particle() * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
                    4 * hist_words(cap) + 4096 + cache_bytes(c->p.leaf_size, pair_grid(cap));
     if (c->budget && (size_t)need > c->budget)
         return fail(c, SPH_EBUDGET, "working set of " + std::to_string(need) +
@@ -357,12 +364,14 @@ sph_status forces_pre(sph_ctx *c, const sph_particles *ps)
     timer_begin(c, 2, &e0, &e1);
     GatherList g{};
     const void *src[] = {ps->x, ps->y, ps->z, ps->m, ps->h, ps->rho, ps->omega, ps->u,
-                         ps->vx, ps->vy, ps->vz};
+                         ps->vx, ps->vy, ps->vz, ps->alpha};
     void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.m, c->s.h, c->s.rho, c->s.omega, c->s.u,
-                   c->s.vx, c->s.vy, c->s.vz};
-    g.count = 11;
+                   c->s.vx, c->s.vy, c->s.vz, c->s.al};
+    g.count = ps->alpha ? 12 : 11;
     for (int a = 0; a < g.count; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
     TRY(gather(c, n, g, false));
+    c->f_alpha = ps->alpha ? c->s.al : nullptr;
+    c->f_div = ps->divv || ps->curlv;
     TRY(build_tree(c, n));
     timer_end(c, 2, e0, e1);
     TRY(force_prep(c, n, c->s.u, c->s.vx, c->s.vy, c->s.vz));
@@ -374,10 +383,12 @@ sph_status forces_post(sph_ctx *c, const sph_particles *ps)
     const int64_t n = ps->n;
     if (n == 0) return SPH_OK;
     ScatterList sl{};
-    const void *ss[] = {c->s.ax, c->s.ay, c->s.az, c->s.du, c->s.vsig, c->s.dt, c->s.nforce};
-    void *sd[] = {ps->ax, ps->ay, ps->az, ps->dudt, ps->vsig, ps->dt, ps->nforce};
-    int kinds[] = {0, 0, 0, 0, 0, 0, 1};
-    for (int a = 0; a < 7; a++) {
+    const void *ss[] = {c->s.ax, c->s.ay, c->s.az, c->s.du, c->s.vsig, c->s.dt, c->s.nforce,
+                        c->s.divv, c->s.curlv};
+    void *sd[] = {ps->ax, ps->ay, ps->az, ps->dudt, ps->vsig, ps->dt, ps->nforce, ps->divv,
+                  ps->curlv};
+    int kinds[] = {0, 0, 0, 0, 0, 0, 1, 0, 0};
+    for (int a = 0; a < 9; a++) {
         if (!sd[a]) continue;
         sl.kind[sl.count] = kinds[a];
         sl.src[sl.count] = ss[a];
@@ -402,10 +413,13 @@ sph_status step_pre(sph_ctx *c, double dt)
     GatherList g{};
     Sorted &S = c->s, &T = c->t;
     double **sa[] = {&S.x, &S.y, &S.z, &S.vx, &S.vy, &S.vz, &S.m, &S.u, &S.h,
-                     &S.vpx, &S.vpy, &S.vpz, &S.up};
+                     &S.vpx, &S.vpy, &S.vpz, &S.up, &S.al, &S.alp, &S.dprev};
     double **ta[] = {&T.x, &T.y, &T.z, &T.vx, &T.vy, &T.vz, &T.m, &T.u, &T.h,
-                     &T.vpx, &T.vpy, &T.vpz, &T.up};
-    const int nd = 13;
+                     &T.vpx, &T.vpy, &T.vpz, &T.up, &T.al, &T.alp, &T.dprev};
+    // the switch state moves with the particles: alpha, its predictor (MM97),
+    // div v of the last step (CD10)
+    const int nd = !c->res_alpha ? 13 : (c->p.av_switch == SPH_AV_MM97 ? 15
+                                         : (c->p.av_switch == SPH_AV_CD10 ? 16 : 14));
     for (int a = 0; a < nd; a++) { g.kind[a] = 0; g.src[a] = *sa[a]; g.dst[a] = *ta[a]; }
     g.kind[nd] = 1; g.src[nd] = S.id; g.dst[nd] = T.id;
     g.count = nd + 1;
@@ -417,9 +431,19 @@ sph_status step_pre(sph_ctx *c, double dt)
     return density_prepare(c, n);
 }
 
+// the per-particle alpha the resident force loop uses: the predictor under
+// MM97, the alpha of the start of the step under CD10 (or a constant one
+// given at upload)
+void resident_force_inputs(sph_ctx *c)
+{
+    c->f_alpha = !c->res_alpha ? nullptr : (c->p.av_switch == SPH_AV_MM97 ? c->s.alp : c->s.al);
+    c->f_div = c->p.av_switch != SPH_AV_NONE;
+}
+
 sph_status step_mid(sph_ctx *c)
 {
     const int64_t n = c->n;
+    resident_force_inputs(c);
     // the force walk needs the boxes' largest h after the h solve
     TRY(refresh_hmax(c, n));
     TRY(force_prep(c, n, c->s.up, c->s.vpx, c->s.vpy, c->s.vpz));
@@ -429,6 +453,10 @@ sph_status step_mid(sph_ctx *c)
 sph_status step_post(sph_ctx *c, double dt, double *dt_used)
 {
     const int64_t n = c->n;
+    // viscosity switches from this step's forces: the MM97 rate (for the
+    // closing kick), the CD10 update
+    TRY(av_rate(c, n, c->s.alp));
+    TRY(av_cd10(c, n, false));
     TRY(closing_kick(c, n, dt));
     TRY(reduce_dt(c, n));
     TRY(reduce_diag(c, n));
@@ -498,11 +526,15 @@ sph_status evaluate_pre(sph_ctx *c, const sph_particles *ps, bool laid_out = fal
     timer_begin(c, 2, &e0, &e1);
     TRY(build_order(c, n, ps->x, ps->y, ps->z));
     GatherList g{};
-    const void *src[] = {ps->x, ps->y, ps->z, ps->h, ps->m, ps->u, ps->vx, ps->vy, ps->vz};
-    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.h, c->s.m, c->s.u, c->s.vx, c->s.vy, c->s.vz};
-    g.count = 9;
+    const void *src[] = {ps->x, ps->y, ps->z, ps->h, ps->m, ps->u, ps->vx, ps->vy, ps->vz,
+                         ps->alpha};
+    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.h, c->s.m, c->s.u, c->s.vx, c->s.vy, c->s.vz,
+                   c->s.al};
+    g.count = ps->alpha ? 10 : 9;
     for (int a = 0; a < g.count; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
     TRY(gather(c, n, g, false));
+    c->f_alpha = ps->alpha ? c->s.al : nullptr;
+    c->f_div = ps->divv || ps->curlv;
     TRY(build_tree(c, n));
     timer_end(c, 2, e0, e1);
     c->built = true;
@@ -529,11 +561,11 @@ sph_status evaluate_post(sph_ctx *c, const sph_particles *ps)
     // from the sorted rho and u (the same values sph_density scatters)
     ScatterList sl{};
     const void *src[] = {c->s.h, c->s.rho, c->s.omega, c->s.nngb, c->s.ax, c->s.ay, c->s.az,
-                         c->s.du, c->s.vsig, c->s.dt, c->s.nforce};
+                         c->s.du, c->s.vsig, c->s.dt, c->s.nforce, c->s.divv, c->s.curlv};
     void *dst[] = {ps->h, ps->rho, ps->omega, ps->nngb, ps->ax, ps->ay, ps->az, ps->dudt,
-                   ps->vsig, ps->dt, ps->nforce};
-    const int kinds[] = {0, 0, 0, 1, 0, 0, 0, 0, 0, 0, 1};
-    for (int a = 0; a < 11; a++) {
+                   ps->vsig, ps->dt, ps->nforce, ps->divv, ps->curlv};
+    const int kinds[] = {0, 0, 0, 1, 0, 0, 0, 0, 0, 0, 1, 0, 0};
+    for (int a = 0; a < 13; a++) {
         if (!dst[a]) continue;
         sl.kind[sl.count] = kinds[a];
         sl.src[sl.count] = src[a];
@@ -570,10 +602,10 @@ constexpr int64_t static_node_bound(int64_t n)
     return tot;
 }
 // the static array: every buffer of lay_out at capacity kStaticMaxN (256-byte
-// aligned slices: 60 buffers at most), and the candidate lists
+// aligned slices: 80 buffers at most), and the candidate lists
 constexpr int64_t kStaticBytes =
-    kStaticMaxN * 400 + static_node_bound(kStaticMaxN) * (int64_t)sizeof(Node) +
-    4 * (256 * ((kStaticMaxN + 4095) / 4096) + 256) + 60 * 256 +
+    kStaticMaxN * bytes_per_particle() + static_node_bound(kStaticMaxN) * (int64_t)sizeof(Node) +
+    4 * (256 * ((kStaticMaxN + 4095) / 4096) + 256) + 80 * 256 +
     kStaticListBlocks * 2 * (int64_t)kCacheEntriesPerParticle * 32 * (int64_t)sizeof(double);
 
 static __device__ __align__(256) unsigned char scratch[kStaticBytes];
@@ -696,6 +728,10 @@ void sph_default_params(sph_params *p)
     p->leaf_size = 16;
     p->alpha_ac = 0.0;
     p->ac_signal = SPH_AC_WADSLEY;
+    p->av_switch = SPH_AV_NONE;
+    p->alpha_min = 0.1;
+    p->alpha_max = 1.0;
+    p->av_ell = 0.0;
 }
 
 sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size_t budget)
@@ -913,18 +949,27 @@ sph_status sph_upload_state(sph_ctx *c, const sph_particles *ps)
     drop_graph(c);
     TRY(build_order(c, n, ps->x, ps->y, ps->z));
     GatherList g{};
-    const void *src[] = {ps->x, ps->y, ps->z, ps->vx, ps->vy, ps->vz, ps->m, ps->u, ps->h};
-    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.vx, c->s.vy, c->s.vz, c->s.m, c->s.u, c->s.h};
-    g.count = 9;
+    const void *src[] = {ps->x, ps->y, ps->z, ps->vx, ps->vy, ps->vz, ps->m, ps->u, ps->h,
+                         ps->alpha};
+    void *dst[] = {c->s.x, c->s.y, c->s.z, c->s.vx, c->s.vy, c->s.vz, c->s.m, c->s.u, c->s.h,
+                   c->s.al};
+    g.count = ps->alpha ? 10 : 9;
     for (int a = 0; a < g.count; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
     TRY(gather(c, n, g, false));
+    c->res_alpha = ps->alpha != nullptr || c->p.av_switch != SPH_AV_NONE;
+    if (c->res_alpha && !ps->alpha) TRY(fill(c, n, c->s.al, c->p.alpha_av));
     TRY(hip_check(c, hipMemcpyAsync(c->s.id, c->perm, sizeof(uint32_t) * (size_t)n,
                                     hipMemcpyDeviceToDevice, c->stream), "copy ids"));
     TRY(build_tree(c, n));
     TRY(run_density(c, n));
     TRY(refresh_hmax(c, n));
     TRY(force_prep(c, n, c->s.u, c->s.vx, c->s.vy, c->s.vz));
+    // the initial forces see the uploaded alpha
+    c->f_alpha = c->res_alpha ? c->s.al : nullptr;
+    c->f_div = c->p.av_switch != SPH_AV_NONE;
     TRY(run_forces(c, n));
+    TRY(av_rate(c, n, c->s.al));
+    TRY(av_cd10(c, n, true));
     TRY(reduce_dt(c, n));
     TRY(hip_check(c, hipMemsetAsync(c->d_scal + 1, 0, sizeof(double) * 2, c->stream), "reset time"));
     TRY(reduce_diag(c, n));
@@ -1012,13 +1057,16 @@ sph_status sph_download_state(sph_ctx *c, sph_particles *ps)
     ScatterList sl{};
     const void *src[] = {c->s.x, c->s.y, c->s.z, c->s.vx, c->s.vy, c->s.vz, c->s.u, c->s.h,
                          c->s.rho, c->s.omega, c->s.ax, c->s.ay, c->s.az, c->s.du, c->s.vsig,
-                         c->s.dt, c->s.nngb, c->s.nforce};
+                         c->s.dt, c->s.nngb, c->s.nforce, c->s.al, c->s.divv, c->s.curlv};
     void *dst[] = {(void *)ps->x, (void *)ps->y, (void *)ps->z, (void *)ps->vx, (void *)ps->vy,
                    (void *)ps->vz, (void *)ps->u, ps->h, ps->rho, ps->omega, ps->ax, ps->ay,
-                   ps->az, ps->dudt, ps->vsig, ps->dt, ps->nngb, ps->nforce};
-    for (int a = 0; a < 18; a++) {
+                   ps->az, ps->dudt, ps->vsig, ps->dt, ps->nngb, ps->nforce,
+                   c->res_alpha ? ps->alpha : nullptr,
+                   c->p.av_switch != SPH_AV_NONE ? ps->divv : nullptr,
+                   c->p.av_switch != SPH_AV_NONE ? ps->curlv : nullptr};
+    for (int a = 0; a < 21; a++) {
         if (!dst[a]) continue;
-        sl.kind[sl.count] = a >= 16 ? 1 : 0;
+        sl.kind[sl.count] = (a == 16 || a == 17) ? 1 : 0;
         sl.src[sl.count] = src[a];
         sl.dst[sl.count] = dst[a];
         sl.count++;
@@ -1150,7 +1198,7 @@ size_t sph_plan_bytes(const sph_params *p, int64_t n)
 {
     if (!p || n < 0) return 0;
     const int64_t cap = std::max<int64_t>(n, 1024);
-    return (size_t)(bytes_per_particle(*p) * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
+    return (size_t)(bytes_per_particle() * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
                     256 * 4 * ceil_div(cap, kRsTile) + 4096 + 3 * kArgBytes +
                     cache_bytes(p->leaf_size, pair_grid(cap)));
 }

@@ -1196,11 +1196,19 @@ struct ForceArgs {
     double alpha_ac, u_per_c2, inv_gamma;
     int32_t ac_price;
     int32_t count_tests;    // also count box and candidate tests (diagnostics)
+    // per-particle viscosity strengths (sorted; nullptr: alpha for every pair),
+    // Omega (sorted) and the div v, |curl v| outputs (nullptr: not wanted)
+    const double *alpha_p;
+    const double *omega;
+    double *divv, *curlv;
 };
 
 // AC: the launch carries artificial conductivity (some set of the batch has
-// alpha_AC > 0; a set with alpha_AC = 0 then adds exact zeros)
-template <int G, int PREC, bool AC>
+// alpha_AC > 0; a set with alpha_AC = 0 then adds exact zeros).
+// SW: the launch carries per-particle alpha or the velocity divergence and
+// curl (the artificial-viscosity switches); a set without them uses alpha_AV
+// for every pair as the plain variant does.
+template <int G, int PREC, bool AC, bool SW>
 __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(Batch<ForceArgs> B)
 {
     constexpr int LPP = kWave / G;
@@ -1239,6 +1247,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         const int64_t leaf = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
         const Box bx = load_const(&B.req[r]->box);
         const double alpha = F.alpha, beta = F.beta;
+        const double *const alpha_p = SW ? F.alpha_p : nullptr;
         const double alpha_ac = AC ? F.alpha_ac : 0.0, u_per_c2 = AC ? F.u_per_c2 : 0.0;
         const double inv_gamma = AC ? F.inv_gamma : 0.0;
         const bool ac_price = AC && F.ac_price != 0;
@@ -1258,6 +1267,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         const double vxi = ri.vx, vyi = ri.vy, vzi = ri.vz;
         const double hi = as_global(F.h)[ii], hinvi = ri.hinv;
         const double rhoi = ri.rho, Ai = ri.A, ci = ri.c;
+        const double alpha_i = (SW && alpha_p) ? as_global(alpha_p)[ii] : alpha;
         const double hi2x4 = (2.0 * hi) * (2.0 * hi);
         const double gfi = kSigma * (hinvi * hinvi) * (hinvi * hinvi);
         const float hinvif = (float)hinvi;
@@ -1287,6 +1297,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         if (wr.lev) overflows++;
 
         double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
+        double dvs = 0.0, cxs = 0.0, cys = 0.0, czs = 0.0;   // div v, curl v sums (SW)
         int cnt = 0, selfs = 0;
         auto group = [&](const uint32_t *leaves, int ng) {
             __builtin_amdgcn_s_setprio(2);
@@ -1327,6 +1338,10 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     vs_max = fmax(vs_max, PREC == SPH_FP64 ? ci + cj : (double)((float)ci + (float)cj));
                     return;
                 }
+                // the pair's viscosity strength: (alpha_i + alpha_j)/2 with
+                // per-particle values, alpha_AV otherwise
+                const double aij = (SW && alpha_p) ? 0.5 * (alpha_i + as_global(alpha_p)[S.j[sl]])
+                                                   : alpha;
                 if (PREC == SPH_FP64) {
                     const double rinv = rsqrt_nr(r2);
                     const double rr = r2 * rinv;
@@ -1346,7 +1361,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const double vs = (ci + cj) - beta * wneg;
                     vs_max = fmax(vs_max, vs);
                     const double rbinv = rcp_nr(0.5 * (rhoi + d.rho));
-                    const double visc = (mj * rbinv) * alpha * vs * wneg;
+                    const double visc = (mj * rbinv) * aij * vs * wneg;
                     const double gbar = 0.5 * gsum;
                     cvec += visc * gbar;
                     cdu -= visc * 0.5 * wneg * gbar;
@@ -1362,6 +1377,14 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     ayi += cvec * ey;
                     azi += cvec * ez;
                     dui += cdu;
+                    if constexpr (SW) {
+                        // v_ij . G_i = w gi and v_ij x G_i = gi (v_ij x rhat)
+                        const double vxij = vxi - d.vx, vyij = vyi - d.vy, vzij = vzi - d.vz;
+                        dvs += mj * w * gi;
+                        cxs += mj * gi * (vyij * ez - vzij * ey);
+                        cys += mj * gi * (vzij * ex - vxij * ez);
+                        czs += mj * gi * (vxij * ey - vyij * ex);
+                    }
                 } else {
                     const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
                     // hardware reciprocal square root and reciprocal (1 ulp each),
@@ -1390,7 +1413,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const float vs = (cif + cjf) - (float)beta * wneg;
                     vs_max = fmax(vs_max, (double)vs);
                     const float rbinv = __builtin_amdgcn_rcpf(0.5f * ((float)rhoi + (float)d.rho));
-                    const float visc = (mj * rbinv) * (float)alpha * vs * wneg;
+                    const float visc = (mj * rbinv) * (float)aij * vs * wneg;
                     const float gbar = 0.5f * gsum;
                     cvec += visc * gbar;
                     cdu -= visc * 0.5f * wneg * gbar;
@@ -1408,6 +1431,14 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     ayi += (double)(cvec * ey);
                     azi += (double)(cvec * ez);
                     dui += (double)cdu;
+                    if constexpr (SW) {
+                        const float vxij = (float)(vxi - d.vx), vyij = (float)(vyi - d.vy);
+                        const float vzij = (float)(vzi - d.vz);
+                        dvs += (double)(mj * w * gi);
+                        cxs += (double)(mj * gi * (vyij * ez - vzij * ey));
+                        cys += (double)(mj * gi * (vzij * ex - vxij * ez));
+                        czs += (double)(mj * gi * (vxij * ey - vyij * ex));
+                    }
                 }
             };
             // the particle's hits of this group (same count on all its lanes).
@@ -1446,6 +1477,12 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         vs_max = group_max<LPP>(vs_max);
         selfs = group_sum<LPP>(selfs);
         cnt -= selfs;
+        if constexpr (SW) {
+            dvs = group_sum<LPP>(dvs);
+            cxs = group_sum<LPP>(cxs);
+            cys = group_sum<LPP>(cys);
+            czs = group_sum<LPP>(czs);
+        }
         if (active && q == 0) {
             const double vsig = cnt > 0 ? vs_max : 2.0 * ci;
             F.ax[i] = axi;
@@ -1455,6 +1492,11 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             F.vsig[i] = vsig;
             F.dt[i] = F.ccfl * hi / vsig;
             F.nforce[i] = cnt;
+            if (SW && F.divv) {
+                const double orho = as_global(F.omega)[i] * rhoi;
+                F.divv[i] = -dvs / orho;
+                F.curlv[i] = sqrt((cxs * cxs + cys * cys) + czs * czs) / orho;
+            }
             if (!isfinite(axi) || !isfinite(ayi) || !isfinite(azi) || !isfinite(dui) ||
                 !isfinite(vsig)) {
                 atomicOr(&F.status[0], kFlagNonFinite);
@@ -1704,6 +1746,10 @@ sph_status forces_prepare(sph_ctx *c, int64_t n)
     a.u_per_c2 = 1.0 / (c->p.gamma * (c->p.gamma - 1.0));
     a.inv_gamma = 1.0 / c->p.gamma;
     a.ac_price = c->p.ac_signal == SPH_AC_PRICE ? 1 : 0;
+    a.alpha_p = c->f_alpha;
+    a.omega = c->s.omega;
+    a.divv = c->f_div ? c->s.divv : nullptr;
+    a.curlv = c->f_div ? c->s.curlv : nullptr;
     a.count_tests = c->count_tests ? 1 : 0;
     const void *req[] = {a.nodes, a.x, a.y, a.z, a.h, a.rec, a.ax, a.ay, a.az, a.du, a.vsig,
                          a.dt, a.nforce, a.status, a.counts, a.tree, a.lstart, a.work,
@@ -1788,20 +1834,33 @@ sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax)
     (void)nmax;
     const unsigned grid = pair_grid(leaves_bound);
     const bool f32 = c->p.precision == SPH_FP32_PAIR;
-    bool ac = false;
-    for (int r = 0; r < count; r++) ac = ac || cs[r]->p.alpha_ac != 0.0;
+    bool ac = false, sw = false;
+    for (int r = 0; r < count; r++) {
+        ac = ac || cs[r]->p.alpha_ac != 0.0;
+        sw = sw || cs[r]->f_alpha != nullptr || cs[r]->f_div;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     timer_begin(c, 1, &e0, &e1);
     auto launch = [&](auto g) {
         constexpr int G = decltype(g)::value;
-        if (f32 && ac)
-            hipLaunchKernelGGL((k_forces<G, SPH_FP32_PAIR, true>), dim3(grid), dim3(kWave), 0, c->stream, B);
-        else if (f32)
-            hipLaunchKernelGGL((k_forces<G, SPH_FP32_PAIR, false>), dim3(grid), dim3(kWave), 0, c->stream, B);
-        else if (ac)
-            hipLaunchKernelGGL((k_forces<G, SPH_FP64, true>), dim3(grid), dim3(kWave), 0, c->stream, B);
-        else
-            hipLaunchKernelGGL((k_forces<G, SPH_FP64, false>), dim3(grid), dim3(kWave), 0, c->stream, B);
+        auto variant = [&](auto prec, auto with_ac, auto with_sw) {
+            hipLaunchKernelGGL((k_forces<G, decltype(prec)::value, decltype(with_ac)::value,
+                                         decltype(with_sw)::value>),
+                               dim3(grid), dim3(kWave), 0, c->stream, B);
+        };
+        using F32 = std::integral_constant<int, SPH_FP32_PAIR>;
+        using F64 = std::integral_constant<int, SPH_FP64>;
+        using T = std::true_type;
+        using N = std::false_type;
+        if (f32) {
+            if (sw) { if (ac) variant(F32{}, T{}, T{}); else variant(F32{}, N{}, T{}); }
+            else if (ac) variant(F32{}, T{}, N{});
+            else variant(F32{}, N{}, N{});
+        } else {
+            if (sw) { if (ac) variant(F64{}, T{}, T{}); else variant(F64{}, N{}, T{}); }
+            else if (ac) variant(F64{}, T{}, N{});
+            else variant(F64{}, N{}, N{});
+        }
     };
     switch (c->p.leaf_size) {
     case 8: launch(std::integral_constant<int, 8>{}); break;

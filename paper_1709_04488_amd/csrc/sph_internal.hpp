@@ -132,6 +132,10 @@ struct Sorted {
     uint32_t *id = nullptr;                    // original (caller) index
     // resident-state integration arrays
     double *vpx = nullptr, *vpy = nullptr, *vpz = nullptr, *up = nullptr;
+    // artificial-viscosity switches: alpha (state), its predictor and rate
+    // (MM97), div v of the previous step (CD10); div v and |curl v| outputs
+    double *al = nullptr, *alp = nullptr, *adot = nullptr, *dprev = nullptr;
+    double *divv = nullptr, *curlv = nullptr;
     // FP32-pair mode
     float *fx = nullptr, *fy = nullptr, *fz = nullptr;
 };
@@ -192,6 +196,7 @@ struct sph_ctx {
 
     // resident state
     bool resident = false;
+    bool res_alpha = false;     // the resident state carries per-particle alpha
     double *d_scal = nullptr;   // [0] dt_next [1] dt_last [2] time [3] KE [4] TE [5..7] P
                                 // [8] smallest, [9] largest mass of the last density pass
     // device counters, indexed by the kCnt* constants
@@ -210,6 +215,12 @@ struct sph_ctx {
 
     sph::Timer timer;
     bool count_tests = false;   // pair loops also count box and candidate tests
+
+    // per-call inputs of the force loop: the sorted per-particle alpha it
+    // uses (nullptr: alpha_av for every pair), whether it writes div v and
+    // |curl v| (set by the phase functions before forces_prepare)
+    const double *f_alpha = nullptr;
+    bool f_div = false;
 
     // this device's copy of the library's static scratch array (the
     // no-allocation entry point); nullptr if its address could not be taken
@@ -304,6 +315,12 @@ sph_status scatter_eos(sph_ctx *c, int64_t n, const ScatterList &s, const uint32
                        const double *u_sorted, double *P, double *cs);
 sph_status kick_drift(sph_ctx *c, int64_t n, double dt_host);
 sph_status closing_kick(sph_ctx *c, int64_t n, double dt_host);
+// artificial-viscosity switches on the resident state: MM97 rate adot from
+// the predicted alpha and the latest div v; CD10 update of alpha (and
+// dprev = div v) with the step length on the device
+sph_status av_rate(sph_ctx *c, int64_t n, const double *alpha_now);
+sph_status av_cd10(sph_ctx *c, int64_t n, bool first);
+sph_status fill(sph_ctx *c, int64_t n, double *v, double value);
 sph_status reduce_dt(sph_ctx *c, int64_t n);
 // smallest and largest sorted mass -> d_scal[8], d_scal[9]
 sph_status reduce_mass_range(sph_ctx *c, int64_t n);

@@ -61,6 +61,9 @@ struct KdkArgs {
     double *x, *y, *z, *vx, *vy, *vz, *u;
     const double *ax, *ay, *az, *du;
     double *vpx, *vpy, *vpz, *up;
+    // MM97 switch (nullptr otherwise): alpha kicked like u, its predictor
+    double *al, *alp;
+    const double *adot;
 };
 
 __device__ inline double wrap(double q, double lo, double L)
@@ -96,6 +99,11 @@ __global__ __launch_bounds__(256) void k_kick_drift(KdkArgs K)
     K.vpy[k] = vh[1] + hd * K.ay[k];
     K.vpz[k] = vh[2] + hd * K.az[k];
     K.up[k] = uh + hd * K.du[k];
+    if (K.al) {
+        const double ah = K.al[k] + hd * K.adot[k];
+        K.al[k] = ah;
+        K.alp[k] = ah + hd * K.adot[k];
+    }
 }
 
 // v = v_1/2 + a' dt/2, u = u_1/2 + du' dt/2 with the dt of the opening kick.
@@ -108,6 +116,61 @@ __global__ __launch_bounds__(256) void k_closing_kick(KdkArgs K)
     K.vy[k] += hd * K.ay[k];
     K.vz[k] += hd * K.az[k];
     K.u[k] += hd * K.du[k];
+    if (K.al) K.al[k] += hd * K.adot[k];
+}
+
+__global__ __launch_bounds__(256) void k_fill(int64_t n, double *__restrict__ v, double value)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) v[k] = value;
+}
+
+// Morris & Monaghan 1997 rate of alpha from the alpha the forces used, their
+// div v, and c and h of the same evaluation (c from the force record):
+//   d alpha/dt = -(alpha - alpha_min) ell c / h + max(-div v, 0) (alpha_max - alpha)
+__global__ __launch_bounds__(256) void k_av_mm97(int64_t n, double amin, double amax, double ell,
+                                                 const double *__restrict__ alpha,
+                                                 const double *__restrict__ divv,
+                                                 const ForceRec *__restrict__ rec,
+                                                 const double *__restrict__ h,
+                                                 double *__restrict__ adot)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double a = alpha[k], d = divv[k];
+    const double decay = -(a - amin) * ell * rec[k].c / h[k];
+    const double src = d < 0.0 ? -d * (amax - a) : 0.0;
+    adot[k] = decay + src;
+}
+
+// Cullen & Dehnen 2010 update of alpha after the forces at the end of a step
+// (length scal[1]); first = true at upload only sets dprev.
+__global__ __launch_bounds__(256) void k_av_cd10(int64_t n, double amin, double amax, double ell,
+                                                 const double *__restrict__ scal, bool first,
+                                                 double *__restrict__ alpha,
+                                                 const double *__restrict__ divv,
+                                                 double *__restrict__ dprev,
+                                                 const double *__restrict__ curlv,
+                                                 const double *__restrict__ vsig,
+                                                 const ForceRec *__restrict__ rec,
+                                                 const double *__restrict__ h)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double d = divv[k];
+    if (!first) {
+        const double dt = scal[1];
+        const double rate = (d - dprev[k]) / dt;
+        const double ad = fabs(d), hk = h[k], vs = vsig[k];
+        const double xi = ad / (ad + curlv[k] + 1e-4 * rec[k].c / hk);
+        const double A = rate < 0.0 ? -xi * rate : 0.0;
+        const double h2A = hk * hk * A;
+        double aloc = amax * h2A / (vs * vs + h2A);
+        if (aloc < amin) aloc = amin;
+        const double a = alpha[k];
+        alpha[k] = a < aloc ? aloc : aloc + (a - aloc) * exp(-dt * 2.0 * ell * vs / hk);
+    }
+    dprev[k] = d;
 }
 
 // min over dt_i -> scal[0]
@@ -296,7 +359,18 @@ KdkArgs kdk_args(sph_ctx *c, int64_t n, double dt_host)
     K.vx = c->s.vx; K.vy = c->s.vy; K.vz = c->s.vz; K.u = c->s.u;
     K.ax = c->s.ax; K.ay = c->s.ay; K.az = c->s.az; K.du = c->s.du;
     K.vpx = c->s.vpx; K.vpy = c->s.vpy; K.vpz = c->s.vpz; K.up = c->s.up;
+    if (c->p.av_switch == SPH_AV_MM97) {
+        K.al = c->s.al;
+        K.alp = c->s.alp;
+        K.adot = c->s.adot;
+    }
     return K;
+}
+
+double av_ell(const sph_params &p)
+{
+    if (p.av_ell > 0.0) return p.av_ell;
+    return p.av_switch == SPH_AV_MM97 ? 0.1 : 0.05;
 }
 
 } // namespace
@@ -331,6 +405,31 @@ sph_status kick_drift(sph_ctx *c, int64_t n, double dt_host)
     KdkArgs K = kdk_args(c, n, dt_host);
     hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(n > 0 ? n : 1, 256)), dim3(256), 0, c->stream, K);
     return hip_check(c, hipGetLastError(), "kick_drift");
+}
+
+sph_status fill(sph_ctx *c, int64_t n, double *v, double value)
+{
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, v, value);
+    return hip_check(c, hipGetLastError(), "fill");
+}
+
+sph_status av_rate(sph_ctx *c, int64_t n, const double *alpha_now)
+{
+    if (n == 0 || c->p.av_switch != SPH_AV_MM97) return SPH_OK;
+    hipLaunchKernelGGL(k_av_mm97, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n,
+                       c->p.alpha_min, c->p.alpha_max, av_ell(c->p), alpha_now, c->s.divv,
+                       c->s.frec, c->s.h, c->s.adot);
+    return hip_check(c, hipGetLastError(), "av_rate");
+}
+
+sph_status av_cd10(sph_ctx *c, int64_t n, bool first)
+{
+    if (n == 0 || c->p.av_switch != SPH_AV_CD10) return SPH_OK;
+    hipLaunchKernelGGL(k_av_cd10, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n,
+                       c->p.alpha_min, c->p.alpha_max, av_ell(c->p), c->d_scal, first, c->s.al,
+                       c->s.divv, c->s.dprev, c->s.curlv, c->s.vsig, c->s.frec, c->s.h);
+    return hip_check(c, hipGetLastError(), "av_cd10");
 }
 
 sph_status closing_kick(sph_ctx *c, int64_t n, double dt_host)

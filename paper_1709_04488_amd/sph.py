@@ -20,6 +20,7 @@ SPH_OK, SPH_EINVAL, SPH_ENOMEM, SPH_EDEVICE, SPH_ENOTCONVERGED = 0, -1, -2, -3, 
 SPH_ESTENCIL, SPH_ENONFINITE, SPH_EBUDGET, SPH_ECAP, SPH_ESTATE = -5, -6, -7, -8, -9
 SPH_FP64, SPH_FP32_PAIR = 0, 1
 SPH_AC_WADSLEY, SPH_AC_PRICE = 0, 1
+SPH_AV_NONE, SPH_AV_MM97, SPH_AV_CD10 = 0, 1, 2
 
 STATUS_NAMES = {0: "SPH_OK", -1: "SPH_EINVAL", -2: "SPH_ENOMEM", -3: "SPH_EDEVICE",
                 -4: "SPH_ENOTCONVERGED", -5: "SPH_ESTENCIL", -6: "SPH_ENONFINITE",
@@ -48,7 +49,9 @@ class _Params(ctypes.Structure):
                 ("h_max_iter", ctypes.c_int32), ("periodic", ctypes.c_int32),
                 ("box_lo", ctypes.c_double * 3), ("box_hi", ctypes.c_double * 3),
                 ("precision", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
-                ("alpha_ac", ctypes.c_double), ("ac_signal", ctypes.c_int32)]
+                ("alpha_ac", ctypes.c_double), ("ac_signal", ctypes.c_int32),
+                ("av_switch", ctypes.c_int32), ("alpha_min", ctypes.c_double),
+                ("alpha_max", ctypes.c_double), ("av_ell", ctypes.c_double)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -58,7 +61,7 @@ _I = ctypes.POINTER(ctypes.c_int32)
 class _Particles(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in (
         "x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "rho", "omega", "pressure", "cs",
-        "ax", "ay", "az", "dudt", "vsig", "dt", "nngb", "nforce")]
+        "ax", "ay", "az", "dudt", "vsig", "dt", "nngb", "nforce", "alpha", "divv", "curlv")]
 
 
 class _Stats(ctypes.Structure):
@@ -149,11 +152,15 @@ class Params:
     leaf_size: int = 16
     alpha_ac: float = 0.0
     ac_signal: int = SPH_AC_WADSLEY
+    av_switch: int = SPH_AV_NONE
+    alpha_min: float = 0.1
+    alpha_max: float = 1.0
+    av_ell: float = 0.0
 
     @classmethod
     def from_setup(cls, setup: dict, **kw) -> "Params":
         keys = ("eta", "gamma", "alpha", "beta", "ccfl", "periodic", "lo", "hi", "alpha_ac",
-                "ac_signal")
+                "ac_signal", "av_switch", "alpha_min", "alpha_max", "av_ell")
         return cls(**{k: setup[k] for k in keys if k in setup}, **kw)
 
     def c(self) -> _Params:
@@ -169,11 +176,16 @@ class Params:
         p.leaf_size = int(self.leaf_size)
         p.alpha_ac = float(self.alpha_ac)
         p.ac_signal = int(self.ac_signal)
+        p.av_switch = int(self.av_switch)
+        p.alpha_min, p.alpha_max = float(self.alpha_min), float(self.alpha_max)
+        p.av_ell = float(self.av_ell)
         return p
 
 
 FIELDS_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "rho", "omega", "pressure", "cs",
               "ax", "ay", "az", "dudt", "vsig", "dt")
+# optional arrays (after nngb/nforce in the C struct): only passed when present
+FIELDS_OPT = ("alpha", "divv", "curlv")
 FIELDS_I32 = ("nngb", "nforce")
 
 
@@ -188,8 +200,11 @@ class Particles:
 
     @classmethod
     def from_host(cls, arrays: dict, device="cuda", outputs: bool = True) -> "Particles":
+        """Device copies of the inputs (and of the optional alpha when given),
+        zeroed outputs.  divv / curlv are left out unless asked for with
+        with_divv()."""
         t = {}
-        for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h"):
+        for k in ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "alpha"):
             if k in arrays:
                 t[k] = torch.as_tensor(arrays[k], dtype=torch.float64).to(device).contiguous()
         n = t["x"].numel()
@@ -204,7 +219,7 @@ class Particles:
     def c(self, omit=()) -> _Particles:
         ps = _Particles()
         ps.n = self.n
-        for k in FIELDS_F64 + FIELDS_I32:
+        for k in FIELDS_F64 + FIELDS_I32 + FIELDS_OPT:
             v = self.t.get(k)
             if v is None or k in omit:
                 setattr(ps, k, None)
@@ -216,6 +231,13 @@ class Particles:
                 raise ValueError(f"{k} must be a contiguous {want} tensor of {ps.n} elements")
             setattr(ps, k, v.data_ptr())
         return ps
+
+    def with_divv(self) -> "Particles":
+        """Also request the velocity divergence and curl outputs."""
+        dev = self.t["x"].device
+        for k in ("divv", "curlv"):
+            self.t[k] = torch.zeros(self.n, dtype=torch.float64, device=dev)
+        return self
 
     def host(self, *keys) -> dict:
         return {k: self.t[k].detach().cpu().numpy() for k in (keys or self.t.keys())}

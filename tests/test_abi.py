@@ -61,9 +61,11 @@ def test_default_params_match_paper_values():
 def test_struct_layouts_match_header():
     # sizes of the ABI structs as the C compiler lays them out
     from paper_1709_04488_amd import sph
-    # ... + alpha_ac, ac_signal and 4 bytes of tail padding
-    assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4 + 8 + 4 + 4
-    assert ctypes.sizeof(sph._Particles) == 8 + 21 * 8
+    # ... + alpha_ac, ac_signal, av_switch (filling the old tail padding),
+    # alpha_min, alpha_max, av_ell
+    assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4 + 8 + 4 + 4 + 3 * 8
+    # ... + the optional alpha, divv, curlv
+    assert ctypes.sizeof(sph._Particles) == 8 + 24 * 8
     # ... + the density and force walk overflows (2 x int32) and the list overflows
     assert ctypes.sizeof(sph._Stats) == 8 * 8 + 5 * 8 + 8 + 2 * 8 + 5 * 8 + 2 * 4 + 8
 
