@@ -17,6 +17,10 @@ Functions and the passages they follow (GANDALF paper, arXiv:1709.04488):
   when alpha_ac > 0), signal speed and EQN:SPH_DT.
 * ``neighbours`` -- the neighbour sets those sums run over.
 * ``kdk``        -- eqs. EQN:LFKDK1/EQN:LFKDK2 with the section 5.1 loop order.
+* ``mfv``        -- meshless finite-volume geometry (section 2.2): number
+  density and h (EQN:MFV_NDENS, EQN:MFV_HN), gradient matrix E
+  (EQN:MFVEMATRIX), B = E^-1, least-squares gradients (EQN:MFVGRADIENT,
+  EQN:MFVPSI) with the SPH fallback above condition number 100.
 * ``mm97_rate``, ``cd10_update`` -- the artificial-viscosity switches section
   2.1.1 names (Morris & Monaghan 1997; Cullen & Dehnen 2010), in their
   published forms; ``forces`` takes per-particle alpha and returns the
@@ -90,6 +94,8 @@ def _load():
         lib.orc_mm97_rate.argtypes = [vp, i64, vp, vp, vp, vp, vp]
         lib.orc_cd10_update.restype = None
         lib.orc_cd10_update.argtypes = [vp, i64, d] + [vp] * 7
+        lib.orc_mfv_gradients.restype = ctypes.c_int
+        lib.orc_mfv_gradients.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, i64, vp, vp, vp, vp]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -332,6 +338,32 @@ def cd10_update(params: Params, dt: float, alpha, divv, divv_prev, curlv, vsig, 
     cp = _CParams.from_buffer_copy(params.c())
     lib.orc_cd10_update(ctypes.byref(cp), al.size, float(dt), _ptr(al), *[_ptr(a) for a in arrs])
     return al
+
+
+def mfv(params: Params, x, y, z, h_guess, fields=(), sel=None) -> dict:
+    """Number density n, h, B = E^-1 (xx, xy, xz, yy, yz, zz), condition
+    number and the gradients of each field (shape [k, nfields, 3])."""
+    lib = _load()
+    x, y, z = (_f64(a) for a in (x, y, z))
+    n = x.size
+    ones = np.ones(n)
+    d = density(params, x, y, z, ones, h_guess)            # h^3 n = eta^3
+    sel_a = None if sel is None else np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
+    k = n if sel_a is None else sel_a.size
+    fl = [_f64(f) for f in fields]
+    fp = (ctypes.c_void_p * max(len(fl), 1))(*[f.ctypes.data for f in fl])
+    B = np.empty((k, 6))
+    cond = np.empty(k)
+    grad = np.empty((k, max(len(fl), 1), 3))
+    cp = _CParams.from_buffer_copy(params.c())
+    rc = lib.orc_mfv_gradients(ctypes.byref(cp), n, _ptr(x), _ptr(y), _ptr(z), _ptr(d["h"]),
+                               _ptr(d["rho"]), len(fl), fp, k, _ptr(sel_a), _ptr(B), _ptr(cond),
+                               _ptr(grad))
+    if rc != ORC_OK:
+        raise OracleError(rc, "mfv")
+    pick = slice(None) if sel_a is None else sel_a
+    return {"h": d["h"][pick], "ndens": d["rho"][pick], "nngb": d["nngb"][pick], "B": B,
+            "cond": cond, "grad": grad[:, :len(fl), :]}
 
 
 # --- sampled evaluation for sets too large for O(N^2) -------------------------

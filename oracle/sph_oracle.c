@@ -665,3 +665,105 @@ int orc_kdk(const orc_params *p, int64_t n, double *x, double *y, double *z, dou
 }
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* ---------------------------------------------------------------------------
+ * Meshless finite-volume geometry (section 2.2).
+ *
+ * Number density and smoothing length (eqs. EQN:MFV_NDENS, EQN:MFV_HN):
+ * n_i = sum_j W(r_ij, h_i) with h_i = eta n_i^(-1/3) -- the density solve
+ * above with every mass set to 1 (then rho_i = n_i and h^3 rho = eta^3).
+ *
+ * Given h_i and n_i, for each selected particle:
+ *   psi_j(r_i)   = W(r_ij, h_i) / n_i
+ *   E_i          = sum_j (r_j - r_i)(r_j - r_i)^T psi_j(r_i)    (EQN:MFVEMATRIX)
+ *   B_i          = E_i^-1
+ *   psit_j(r_i)  = B_i (r_j - r_i) psi_j(r_i)                   (EQN:MFVPSI)
+ *   grad f_i     = sum_j (f_j - f_i) psit_j(r_i)                (EQN:MFVGRADIENT)
+ * Condition number: cond_i = |E_i|_F |B_i|_F / 3 (Frobenius norms, 1 for a
+ * multiple of the identity).  When it exceeds 100 the gradient is the
+ * direct SPH estimate instead, psit_j -> V_i grad_i W(r_ij, h_i) with
+ * V_i = 1/n_i (section 2.2.2).  The sums run over j with r_ij < 2 h_i (W
+ * vanishes beyond); the particle itself contributes nothing (r = 0).
+ * B is returned as xx, xy, xz, yy, yz, zz (6 per particle), grad as
+ * nfields x 3 per particle.
+ * ------------------------------------------------------------------------- */
+static int inv3(const double E[3][3], double B[3][3])
+{
+    double c00 = E[1][1] * E[2][2] - E[1][2] * E[2][1];
+    double c01 = E[1][2] * E[2][0] - E[1][0] * E[2][2];
+    double c02 = E[1][0] * E[2][1] - E[1][1] * E[2][0];
+    double det = E[0][0] * c00 + E[0][1] * c01 + E[0][2] * c02;
+    if (det == 0.0 || !isfinite(det)) return 0;
+    double id = 1.0 / det;
+    B[0][0] = c00 * id;
+    B[1][0] = c01 * id;
+    B[2][0] = c02 * id;
+    B[0][1] = (E[0][2] * E[2][1] - E[0][1] * E[2][2]) * id;
+    B[1][1] = (E[0][0] * E[2][2] - E[0][2] * E[2][0]) * id;
+    B[2][1] = (E[0][1] * E[2][0] - E[0][0] * E[2][1]) * id;
+    B[0][2] = (E[0][1] * E[1][2] - E[0][2] * E[1][1]) * id;
+    B[1][2] = (E[0][2] * E[1][0] - E[0][0] * E[1][2]) * id;
+    B[2][2] = (E[0][0] * E[1][1] - E[0][1] * E[1][0]) * id;
+    return 1;
+}
+
+int orc_mfv_gradients(const orc_params *p, int64_t n, const double *x, const double *y,
+                      const double *z, const double *h, const double *ndens, int32_t nfields,
+                      const double *const *f, int64_t nsel, const int64_t *sel, double *Bout,
+                      double *cond, double *grad)
+{
+    if (n < 0 || nsel < 0 || nfields < 0 || nfields > 8) return ORC_EINVAL;
+    if (sel == NULL) nsel = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nsel; k++) {
+        int64_t i = sel ? sel[k] : k;
+        double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+        double E[3][3] = {{0}}, B[3][3];
+        for (int64_t j = 0; j < n; j++) {
+            double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
+            if (!(r2 < hi2x4)) continue;
+            double d[3] = {-dx, -dy, -dz};   /* r_j - r_i */
+            double psi = orc_W(sqrt(r2), h[i]) / ndens[i];
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++) E[a][b] += d[a] * d[b] * psi;
+        }
+        int ok = inv3(E, B);
+        double nE = 0.0, nB = 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                nE += E[a][b] * E[a][b];
+                nB += ok ? B[a][b] * B[a][b] : INFINITY;
+            }
+        double cn = sqrt(nE) * sqrt(nB) / 3.0;
+        int sph = !(cn <= 100.0);
+        for (int q = 0; q < nfields; q++)
+            for (int a = 0; a < 3; a++) grad[(k * nfields + q) * 3 + a] = 0.0;
+        for (int64_t j = 0; j < n; j++) {
+            double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
+            if (!(r2 < hi2x4) || r2 == 0.0) continue;
+            double d[3] = {-dx, -dy, -dz};
+            double r = sqrt(r2);
+            double psit[3];
+            if (!sph) {
+                double psi = orc_W(r, h[i]) / ndens[i];
+                for (int a = 0; a < 3; a++)
+                    psit[a] = (B[a][0] * d[0] + B[a][1] * d[1] + B[a][2] * d[2]) * psi;
+            } else {
+                /* V_i grad_i W = (1/n_i) dW/dr (r_i - r_j)/r */
+                double g = orc_dWdr(r, h[i]) / ndens[i] / r;
+                for (int a = 0; a < 3; a++) psit[a] = -d[a] * g;
+            }
+            for (int q = 0; q < nfields; q++) {
+                double df = f[q][j] - f[q][i];
+                for (int a = 0; a < 3; a++) grad[(k * nfields + q) * 3 + a] += df * psit[a];
+            }
+        }
+        if (Bout) {
+            double *o = Bout + 6 * k;
+            o[0] = B[0][0]; o[1] = B[0][1]; o[2] = B[0][2];
+            o[3] = B[1][1]; o[4] = B[1][2]; o[5] = B[2][2];
+        }
+        if (cond) cond[k] = cn;
+    }
+    return ORC_OK;
+}
