@@ -353,6 +353,38 @@ sph_status sph_download_state(sph_ctx *ctx, sph_particles *ps);
 sph_status sph_state_info(sph_ctx *ctx, sph_state_stats *info);
 
 /*
+ * Meshless finite-volume geometry (section 2.2), for the MFV/MFM schemes:
+ *   number density n_i = sum_j W(r_ij, h_i) with h_i = eta n_i^(-1/3)
+ *     (eqs. EQN:MFV_NDENS, EQN:MFV_HN; eta from the context's parameters,
+ *     about 1 for MFV in 3D) -- the density solve of sph_density with every
+ *     mass 1, same Newton-Raphson and stopping rule;
+ *   gradient matrix E_i = sum_j (r_j - r_i)(r_j - r_i)^T psi_j(r_i) with
+ *     psi_j(r_i) = W(r_ij, h_i) / n_i (eq. EQN:MFVEMATRIX) and B_i = E_i^-1;
+ *   least-squares gradients grad f_i = sum_j (f_j - f_i) B_i (r_j - r_i)
+ *     psi_j(r_i) (eqs. EQN:MFVGRADIENT, EQN:MFVPSI) of up to 4 fields; where
+ *     cond_i = |E_i|_F |B_i|_F / 3 exceeds 100 the SPH estimate
+ *     n_i^-1 sum_j (f_j - f_i) grad_i W(r_ij, h_i) is returned instead.
+ * All arrays are device arrays in caller order.  h: in the guess, out the
+ * solved value.  ndens, nngb, B[k], cond, grad[3 q + a] may be NULL (not
+ * written).  B holds xx, xy, xz, yy, yz, zz.  Waits for nothing; errors as
+ * for sph_density (SPH_ENOTCONVERGED etc. through sph_sync).
+ */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z;
+    double *h;
+    double *ndens;            /* n_i */
+    int32_t *nngb;            /* neighbours j != i with r_ij < 2 h_i */
+    double *B[6];             /* E^-1: xx, xy, xz, yy, yz, zz */
+    double *cond;             /* |E|_F |E^-1|_F / 3 */
+    int32_t nfields;          /* 0..4 */
+    const double *f[4];       /* fields whose gradients are wanted */
+    double *grad[12];         /* d f_q / d x_a at [3 q + a] */
+} sph_mfv_set;
+
+sph_status sph_mfv_gradients(sph_ctx *ctx, sph_mfv_set *s);
+
+/*
  * Neighbour lists, for tests and export, at the given h (no h solve):
  *   mode 0: j != i with r_ij^2 < (2 h_i)^2        (density neighbours)
  *   mode 1: j != i with r_ij^2 < (2 h_i)^2 or r_ij^2 < (2 h_j)^2  (force)

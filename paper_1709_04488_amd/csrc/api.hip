@@ -1153,6 +1153,81 @@ sph_status sph_neighbours(sph_ctx *c, const sph_particles *ps, int32_t mode, int
     return hip_check(c, hipStreamSynchronize(c->stream), "sync");
 }
 
+sph_status sph_mfv_gradients(sph_ctx *c, sph_mfv_set *s)
+{
+    if (!c) return SPH_EINVAL;
+    if (!s) return fail(c, SPH_EINVAL, "set is NULL");
+    if (s->n < 0) return fail(c, SPH_EINVAL, "n < 0");
+    if (s->nfields < 0 || s->nfields > 4) return fail(c, SPH_EINVAL, "nfields must be 0..4");
+    const int64_t n = s->n;
+    if (n > 0) {
+        if (!s->x || !s->y || !s->z || !s->h) return fail(c, SPH_EINVAL, "x, y, z and h are required");
+        for (int k = 0; k < s->nfields; k++)
+            if (!s->f[k]) return fail(c, SPH_EINVAL, "a field is NULL");
+    }
+    c->resident = false;
+    TRY(ensure_capacity(c, n));
+    c->n = n;
+    if (n == 0) return SPH_OK;
+    Sorted &S = c->s, &T = c->t;
+    // sorted homes of the fields (the re-sort buffers are free outside a
+    // resident state) and of the outputs (the force-loop outputs are free)
+    double *fs[4] = {T.vx, T.vy, T.vz, T.u};
+    double *Bs[6] = {S.ax, S.ay, S.az, S.du, S.vsig, S.dt};
+    double *gs[12] = {S.vpx, S.vpy, S.vpz, S.up, S.al, S.alp, S.adot, S.dprev, S.curlv,
+                      T.x, T.y, T.z};
+    double *conds = S.divv;
+    TRY(build_order(c, n, s->x, s->y, s->z));
+    GatherList g{};
+    const void *src[] = {s->x, s->y, s->z, s->h};
+    void *dst[] = {S.x, S.y, S.z, S.h};
+    for (int a = 0; a < 4; a++) { g.kind[a] = 0; g.src[a] = src[a]; g.dst[a] = dst[a]; }
+    g.count = 4;
+    for (int k = 0; k < s->nfields; k++) {
+        g.kind[g.count] = 0;
+        g.src[g.count] = s->f[k];
+        g.dst[g.count] = fs[k];
+        g.count++;
+    }
+    TRY(gather(c, n, g, false));
+    // number density: the density solve with unit masses (h^3 n = eta^3)
+    TRY(fill(c, n, S.m, 1.0));
+    TRY(build_tree(c, n));
+    c->built = false;
+    TRY(run_density(c, n));
+    TRY(refresh_hmax(c, n));
+    double *Bo[6], *go[12];
+    for (int k = 0; k < 6; k++) Bo[k] = s->B[k] ? Bs[k] : nullptr;
+    for (int k = 0; k < 12; k++) go[k] = (k < 3 * s->nfields && s->grad[k]) ? gs[k] : nullptr;
+    TRY(run_mfv(c, n, s->nfields, fs, Bo, s->cond ? conds : nullptr, go));
+    ScatterList sl{};
+    auto add = [&](const void *from, void *to, int kind) {
+        if (!to) return;
+        sl.kind[sl.count] = kind;
+        sl.src[sl.count] = from;
+        sl.dst[sl.count] = to;
+        sl.count++;
+    };
+    add(S.h, s->h, 0);
+    add(S.rho, s->ndens, 0);
+    add(S.nngb, s->nngb, 1);
+    for (int k = 0; k < 6; k++) add(Bs[k], s->B[k], 0);
+    add(conds, s->cond, 0);
+    TRY(scatter(c, n, sl, c->perm));
+    if (s->nfields > 0) {
+        ScatterList sg{};
+        for (int k = 0; k < 3 * s->nfields; k++) {
+            if (!s->grad[k]) continue;
+            sg.kind[sg.count] = 0;
+            sg.src[sg.count] = gs[k];
+            sg.dst[sg.count] = s->grad[k];
+            sg.count++;
+        }
+        if (sg.count) TRY(scatter(c, n, sg, c->perm));
+    }
+    return SPH_OK;
+}
+
 sph_status sph_sync(sph_ctx *c)
 {
     if (!c) return SPH_EINVAL;

@@ -1624,6 +1624,172 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
     if (lane == 0 && overflows) atomicAdd(&N.status[4], (int)overflows);
 }
 
+// ---------------------------------------------------------------------------
+// Meshless finite-volume geometry (section 2.2): for each particle, over its
+// neighbours j with r_ij < 2 h_i (h solved on the number density), with
+// d = r_j - r_i and psi_j = W(r_ij, h_i) / n_i:
+//   E  = sum_j d d^T psi_j                    (EQN:MFVEMATRIX), B = E^-1
+//   g  = sum_j (f_j - f_i) d psi_j,  grad f = B g   (EQN:MFVGRADIENT with
+//        EQN:MFVPSI: B is constant over the sum and comes out of it)
+//   gs = sum_j (f_j - f_i) grad_i W(r_ij, h_i), the SPH gradient n_i^-1 gs
+//        used when cond(E) = |E|_F |B|_F / 3 exceeds 100.
+// One wave per home leaf, LPP lanes per particle taking every LPP-th slot
+// of each candidate leaf (the direct loop of the neighbour export: this is
+// not the hot path), sums reduced over the particle's lanes.
+// ---------------------------------------------------------------------------
+constexpr int kMfvFields = 4;
+struct MfvArgs {
+    int64_t n;
+    const TreeInfo *tree;
+    const uint32_t *lstart;
+    uint32_t *work;
+    Box box;
+    const Node *nodes;
+    const double *x, *y, *z, *h, *ndens;
+    int32_t nf;
+    const double *f[kMfvFields];
+    double *B[6];                  // xx, xy, xz, yy, yz, zz
+    double *cond;
+    double *grad[3 * kMfvFields];  // field q, axis a at 3 q + a
+    int32_t *status;
+};
+
+template <int G>
+__global__ __launch_bounds__(kWave) void k_mfv(MfvArgs M)
+{
+    constexpr int LPP = kWave / G;
+    constexpr int PER = G / LPP;
+    __shared__ WalkBuf wb;
+    __shared__ uint32_t spare[kFront];
+    __shared__ TreeInfo T;
+    load_tree(M.tree, T);
+    const int lane = threadIdx.x;
+    const int p = lane / LPP, q = lane % LPP;
+    const Box &bx = M.box;
+    const int nf = M.nf;
+    int64_t overflows = 0;
+    for_each_home_leaf(T.cnt[0], M.work, [&](int64_t leaf) {
+        const int64_t first = M.lstart[leaf];
+        const int nhome = (int)(M.lstart[leaf + 1] - first);
+        const int64_t i = first + p;
+        const bool active = p < nhome;
+        const int64_t ii = active ? i : first;
+        const double xi = M.x[ii], yi = M.y[ii], zi = M.z[ii], hi = M.h[ii];
+        const double hinv = 1.0 / hi, ninv = 1.0 / M.ndens[ii];
+        const double hi2x4 = (2.0 * hi) * (2.0 * hi);
+        const double wf = kSigma * hinv * hinv * hinv;
+        double fi[kMfvFields];
+#pragma unroll
+        for (int k = 0; k < kMfvFields; k++) fi[k] = k < nf ? M.f[k][ii] : 0.0;
+        const Node home = M.nodes[leaf];
+        auto test = [&bx, &home](const Node &nd) {
+            const double R = 2.0 * home.hmax * (1.0 + 1e-10);
+            return box_gap2(home.lo, home.hi, nd, bx) < R * R;
+        };
+        const WalkResult wr = walk(T, M.nodes, test, wb, spare);
+        if (wr.lev) overflows++;
+        double E[6] = {0, 0, 0, 0, 0, 0};
+        double g[3 * kMfvFields], gs[3 * kMfvFields];
+#pragma unroll
+        for (int k = 0; k < 3 * kMfvFields; k++) g[k] = gs[k] = 0.0;
+        auto group = [&](const uint32_t *leaves, int count) {
+            for (int c0 = 0; c0 < count; c0++) {
+                const int64_t c = leaves[c0];
+                const Node cand = M.nodes[c];
+                const Shift sh = leaf_shift(home, cand, bx, home.hmax);
+                const int64_t j0 = M.lstart[c];
+                const int jn = (int)(M.lstart[c + 1] - j0);
+#pragma unroll
+                for (int t = 0; t < PER; t++) {
+                    const int jj = q + LPP * t;
+                    if (jj >= jn) continue;
+                    const int64_t j = j0 + jj;
+                    double dx = xi - M.x[j], dy = yi - M.y[j], dz = zi - M.z[j];
+                    if (sh.per_pair) {
+                        dx = min_image(dx, bx.len[0], bx.half[0]);
+                        dy = min_image(dy, bx.len[1], bx.half[1]);
+                        dz = min_image(dz, bx.len[2], bx.half[2]);
+                    } else {
+                        dx += sh.s[0];
+                        dy += sh.s[1];
+                        dz += sh.s[2];
+                    }
+                    const double r2 = exact_r2(dx, dy, dz);
+                    if (!(active && r2 < hi2x4 && r2 > 0.0)) continue;
+                    const double d[3] = {-dx, -dy, -dz};   // r_j - r_i
+                    const double r = sqrt(r2);
+                    double fk, dfk;
+                    m4(r * hinv, fk, dfk);
+                    const double psi = wf * fk * ninv;
+                    // grad_i W = dW/dr (r_i - r_j) / r = -(dW/dr / r) d
+                    const double gw = -(wf * hinv * dfk) / r;
+                    E[0] += d[0] * d[0] * psi;
+                    E[1] += d[0] * d[1] * psi;
+                    E[2] += d[0] * d[2] * psi;
+                    E[3] += d[1] * d[1] * psi;
+                    E[4] += d[1] * d[2] * psi;
+                    E[5] += d[2] * d[2] * psi;
+#pragma unroll
+                    for (int k = 0; k < kMfvFields; k++) {
+                        if (k >= nf) break;
+                        const double df = M.f[k][j] - fi[k];
+#pragma unroll
+                        for (int a = 0; a < 3; a++) {
+                            g[3 * k + a] += df * d[a] * psi;
+                            gs[3 * k + a] += df * gw * d[a];
+                        }
+                    }
+                }
+            }
+        };
+        for_each_leaf_group<kWave>(T, M.nodes, wr, test, wb, group);
+#pragma unroll
+        for (int k = 0; k < 6; k++) E[k] = group_sum<LPP>(E[k]);
+#pragma unroll
+        for (int k = 0; k < 3 * kMfvFields; k++) {
+            g[k] = group_sum<LPP>(g[k]);
+            gs[k] = group_sum<LPP>(gs[k]);
+        }
+        if (active && q == 0) {
+            // B = E^-1 of the symmetric E by cofactors
+            const double c00 = E[3] * E[5] - E[4] * E[4];
+            const double c01 = E[2] * E[4] - E[1] * E[5];
+            const double c02 = E[1] * E[4] - E[2] * E[3];
+            const double c11 = E[0] * E[5] - E[2] * E[2];
+            const double c12 = E[1] * E[2] - E[0] * E[4];
+            const double c22 = E[0] * E[3] - E[1] * E[1];
+            const double det = E[0] * c00 + E[1] * c01 + E[2] * c02;
+            const double id = 1.0 / det;
+            const double B[6] = {c00 * id, c01 * id, c02 * id, c11 * id, c12 * id, c22 * id};
+            auto frob2 = [](const double *s) {
+                return (s[0] * s[0] + s[3] * s[3] + s[5] * s[5]) +
+                       2.0 * (s[1] * s[1] + s[2] * s[2] + s[4] * s[4]);
+            };
+            const bool inv_ok = det != 0.0 && isfinite(det);
+            const double cn = inv_ok ? sqrt(frob2(E)) * sqrt(frob2(B)) / 3.0 : INFINITY;
+            const bool sph = !(cn <= 100.0);
+#pragma unroll
+            for (int k = 0; k < 6; k++)
+                if (M.B[k]) M.B[k][i] = inv_ok ? B[k] : NAN;
+            if (M.cond) M.cond[i] = cn;
+            for (int k = 0; k < nf; k++) {
+                const double *gk = g + 3 * k;
+                double out[3];
+                if (!sph) {
+                    out[0] = B[0] * gk[0] + B[1] * gk[1] + B[2] * gk[2];
+                    out[1] = B[1] * gk[0] + B[3] * gk[1] + B[4] * gk[2];
+                    out[2] = B[2] * gk[0] + B[4] * gk[1] + B[5] * gk[2];
+                } else {
+                    for (int a = 0; a < 3; a++) out[a] = gs[3 * k + a] * ninv;
+                }
+                for (int a = 0; a < 3; a++)
+                    if (M.grad[3 * k + a]) M.grad[3 * k + a][i] = out[a];
+            }
+        }
+    });
+    if (lane == 0 && overflows) atomicAdd(&M.status[4], (int)overflows);
+}
+
 // ascending order within each list (insertion sort; lists are ~60 long)
 __global__ __launch_bounds__(256) void k_sort_lists(int64_t n, const int64_t *__restrict__ off,
                                                     int32_t *__restrict__ idx, int64_t cap)
@@ -1883,6 +2049,31 @@ sph_status run_forces(sph_ctx *c, int64_t n)
     if (n == 0) return SPH_OK;
     TRY_(forces_prepare(c, n));
     return forces_launch(&c, 1, n);
+}
+
+sph_status run_mfv(sph_ctx *c, int64_t n, int nf, const double *const *f, double *const *B,
+                   double *cond, double *const *grad)
+{
+    if (n == 0) return SPH_OK;
+    if (nf < 0 || nf > kMfvFields) return fail(c, SPH_EINVAL, "mfv: at most 4 fields");
+    MfvArgs a{};
+    fill_common(c, n, a);
+    a.x = c->s.x; a.y = c->s.y; a.z = c->s.z; a.h = c->s.h; a.ndens = c->s.rho;
+    a.nf = nf;
+    for (int k = 0; k < nf; k++) a.f[k] = f[k];
+    for (int k = 0; k < 6; k++) a.B[k] = B[k];
+    a.cond = cond;
+    for (int k = 0; k < 3 * nf; k++) a.grad[k] = grad[k];
+    a.status = c->d_status;
+    if (c->tree_n != n) return fail(c, SPH_ESTATE, "mfv: tree not built");
+    TRY_(zero_work(c));
+    const unsigned grid = pair_grid(n);
+    switch (c->p.leaf_size) {
+    case 8: hipLaunchKernelGGL((k_mfv<8>), dim3(grid), dim3(kWave), 0, c->stream, a); break;
+    case 32: hipLaunchKernelGGL((k_mfv<32>), dim3(grid), dim3(kWave), 0, c->stream, a); break;
+    default: hipLaunchKernelGGL((k_mfv<16>), dim3(grid), dim3(kWave), 0, c->stream, a); break;
+    }
+    return hip_check(c, hipGetLastError(), "mfv kernel");
 }
 
 sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_sorted,

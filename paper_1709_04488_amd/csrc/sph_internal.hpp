@@ -267,6 +267,10 @@ sph_status density_prepare(sph_ctx *c, int64_t n);
 sph_status forces_prepare(sph_ctx *c, int64_t n);
 sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax);
 sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax);
+// meshless finite-volume gradient matrix and gradients over the built tree,
+// with h and the number density (c->s.rho) already solved; sorted arrays
+sph_status run_mfv(sph_ctx *c, int64_t n, int nf, const double *const *f, double *const *B,
+                   double *cond, double *const *grad);
 sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_sorted,
                           const int64_t *offsets_sorted, int32_t *idx, int64_t cap);
 

@@ -33,7 +33,8 @@ EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream",
             "sph_last_error", "sph_device_bytes", "sph_enable_kernel_timing", "sph_kernel_times",
             "sph_batch_density", "sph_batch_forces", "sph_batch_evaluate", "sph_batch_step",
             "sph_capture_steps",
-            "sph_replay_steps", "sph_plan_bytes", "sph_evaluate_noalloc", "sph_noalloc_max_n"]
+            "sph_replay_steps", "sph_plan_bytes", "sph_evaluate_noalloc", "sph_noalloc_max_n",
+            "sph_mfv_gradients"]
 
 
 class SphError(RuntimeError):
@@ -62,6 +63,14 @@ class _Particles(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in (
         "x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "rho", "omega", "pressure", "cs",
         "ax", "ay", "az", "dudt", "vsig", "dt", "nngb", "nforce", "alpha", "divv", "curlv")]
+
+
+class _MfvSet(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("h", ctypes.c_void_p), ("ndens", ctypes.c_void_p),
+                ("nngb", ctypes.c_void_p), ("B", ctypes.c_void_p * 6), ("cond", ctypes.c_void_p),
+                ("nfields", ctypes.c_int32), ("f", ctypes.c_void_p * 4),
+                ("grad", ctypes.c_void_p * 12)]
 
 
 class _Stats(ctypes.Structure):
@@ -126,6 +135,7 @@ def load() -> ctypes.CDLL:
         "sph_plan_bytes": (ctypes.c_size_t, [P, i64]),
         "sph_evaluate_noalloc": (ctypes.c_int, [vp, PS]),
         "sph_noalloc_max_n": (i64, []),
+        "sph_mfv_gradients": (ctypes.c_int, [vp, ctypes.POINTER(_MfvSet)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -315,6 +325,32 @@ class Context:
         scratch array holds every buffer (n <= sph_noalloc_max_n())."""
         ps = p.c()
         self._check(self.lib.sph_evaluate_noalloc(self.h, ctypes.byref(ps)), "sph_evaluate_noalloc")
+
+    def mfv_gradients(self, x, y, z, h, fields=()) -> dict:
+        """Meshless finite-volume geometry (sph_mfv_gradients) of device
+        arrays x, y, z and the guess h (updated in place): number density,
+        B = E^-1 (shape [n, 6]), condition number, gradients ([n, k, 3])."""
+        n = int(x.numel())
+        dev = x.device
+        out = {"ndens": torch.zeros(n, dtype=torch.float64, device=dev),
+               "nngb": torch.zeros(n, dtype=torch.int32, device=dev),
+               "B": torch.zeros((6, n), dtype=torch.float64, device=dev),
+               "cond": torch.zeros(n, dtype=torch.float64, device=dev),
+               "grad": torch.zeros((max(len(fields), 1) * 3, n), dtype=torch.float64, device=dev)}
+        s = _MfvSet()
+        s.n = n
+        s.x, s.y, s.z, s.h = x.data_ptr(), y.data_ptr(), z.data_ptr(), h.data_ptr()
+        s.ndens, s.nngb, s.cond = (out["ndens"].data_ptr(), out["nngb"].data_ptr(),
+                                   out["cond"].data_ptr())
+        for k in range(6):
+            s.B[k] = out["B"][k].data_ptr()
+        s.nfields = len(fields)
+        for k, f in enumerate(fields):
+            s.f[k] = f.data_ptr()
+            for a in range(3):
+                s.grad[3 * k + a] = out["grad"][3 * k + a].data_ptr()
+        self._check(self.lib.sph_mfv_gradients(self.h, ctypes.byref(s)), "sph_mfv_gradients")
+        return out
 
     def density_then_forces(self, p: Particles):
         """The same evaluation as two calls, sph_density then sph_forces."""

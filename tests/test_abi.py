@@ -79,7 +79,7 @@ def test_struct_offsets_match_the_c_compiler(tmp_path):
     if not shutil.which("gcc"):
         pytest.skip("no gcc")
     pairs = (("sph_params", sph._Params), ("sph_particles", sph._Particles),
-             ("sph_state_stats", sph._Stats))
+             ("sph_state_stats", sph._Stats), ("sph_mfv_set", sph._MfvSet))
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sph.h"', "int main(void) {"]
     for cname, py in pairs:
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
