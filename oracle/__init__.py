@@ -17,6 +17,8 @@ Functions and the passages they follow (GANDALF paper, arXiv:1709.04488):
   when alpha_ac > 0), signal speed and EQN:SPH_DT.
 * ``neighbours`` -- the neighbour sets those sums run over.
 * ``kdk``        -- eqs. EQN:LFKDK1/EQN:LFKDK2 with the section 5.1 loop order.
+* ``kdk_block``  -- the same with hierarchical block time-steps (section
+  2.1.4) and the predictive/reactive limiter (section 2.1.5).
 * ``mfv``        -- meshless finite-volume geometry (section 2.2): number
   density and h (EQN:MFV_NDENS, EQN:MFV_HN), gradient matrix E
   (EQN:MFVEMATRIX), B = E^-1, least-squares gradients (EQN:MFVGRADIENT,
@@ -96,6 +98,8 @@ def _load():
         lib.orc_cd10_update.argtypes = [vp, i64, d] + [vp] * 7
         lib.orc_mfv_gradients.restype = ctypes.c_int
         lib.orc_mfv_gradients.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, i64, vp, vp, vp, vp]
+        lib.orc_kdk_block.restype = ctypes.c_int
+        lib.orc_kdk_block.argtypes = [vp, i64] + [vp] * 9 + [i32, i32, i32, vp, vp, vp, vp, vp]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -318,6 +322,33 @@ def kdk(params: Params, x, y, z, vx, vy, vz, m, u, h_guess, nsteps: int, dt_fixe
     if rc != ORC_OK:
         raise OracleError(rc, "kdk")
     return st, energy, dts[:nsteps]
+
+
+def kdk_block(params: Params, x, y, z, vx, vy, vz, m, u, h_guess, nfull: int, lmax: int = 20,
+              lim: int = 2):
+    """Block time-step KDK over nfull level-0 steps.  Returns (state dict,
+    energy[nfull+1] at the full synchronisations, sub-steps, levels, time);
+    the state dict also holds "updates", the active particles summed over
+    the sub-steps."""
+    lib = _load()
+    st = {k: _f64(a).copy() for k, a in zip(("x", "y", "z", "vx", "vy", "vz", "u", "h"),
+                                           (x, y, z, vx, vy, vz, u, h_guess))}
+    m = _f64(m)
+    n = m.size
+    energy = np.empty(nfull + 1)
+    nsub = ctypes.c_int64(0)
+    tout = ctypes.c_double(0.0)
+    upd = ctypes.c_int64(0)
+    lev = np.empty(n, np.int32)
+    cp = _CParams.from_buffer_copy(params.c())
+    rc = lib.orc_kdk_block(ctypes.byref(cp), n, _ptr(st["x"]), _ptr(st["y"]), _ptr(st["z"]),
+                           _ptr(st["vx"]), _ptr(st["vy"]), _ptr(st["vz"]), _ptr(m), _ptr(st["u"]),
+                           _ptr(st["h"]), int(lmax), int(lim), int(nfull), _ptr(energy),
+                           ctypes.byref(nsub), _ptr(lev), ctypes.byref(tout), ctypes.byref(upd))
+    if rc != ORC_OK:
+        raise OracleError(rc, "kdk_block")
+    st["updates"] = int(upd.value)
+    return st, energy, int(nsub.value), lev, float(tout.value)
 
 
 def mm97_rate(params: Params, alpha, divv, c, h):

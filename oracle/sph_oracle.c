@@ -767,3 +767,256 @@ int orc_mfv_gradients(const orc_params *p, int64_t n, const double *x, const dou
     }
     return ORC_OK;
 }
+
+/* ---------------------------------------------------------------------------
+ * Hierarchical block time-steps (section 2.1.4) with a predictive and
+ * reactive time-step limiter in the manner of Saitoh & Makino 2009
+ * (section 2.1.5), kick-drift-kick.
+ *
+ * Timeline: one level-0 step of length dt_max holds 2^lmax integer ticks; a
+ * particle on level l takes steps of 2^(lmax - l) ticks.  At a full
+ * synchronisation (start, and whenever the level-0 step ends) dt_max is
+ * recomputed from the CFL steps dt_i of every particle as
+ *   dt_max = min_i dt_i 2^k,  k the largest integer with dt_max <= max_i dt_i
+ * (the paper fixes dt_max from the time-steps available; this choice makes
+ * the deepest occupied level step at exactly the smallest dt_i, and a set
+ * whose dt_i lie within a factor 2 is integrated exactly as by the global
+ * scheme), and every particle takes the level
+ *   level(dt_i) = smallest l <= lmax with dt_max 2^-l <= dt_i
+ * (the comparisons are exact: 2^k scales without rounding).  Each sub-step:
+ *   T' = min_i t_end_i; every particle drifts x += v_half (T' - T); the
+ *   particles with t_end_i = T' are active;
+ *   all particles are predicted to T': v* = v_half + a (T' - t_mid), u
+ *   likewise (t_mid the middle of the particle's step; for an active
+ *   particle this is the usual predictor v_half + a dt/2);
+ *   density (h solve) and forces for the active particles only, with the
+ *   stored h, rho, Omega and the predicted v, u of inactive neighbours;
+ *   limiter information, over the force neighbours j of each active i
+ *   (r_ij < 2 max(h_i, h_j)): lmx_i = max level_j (old levels), and every
+ *   inactive j with level_j < level_i - lim is marked with level_i;
+ *   closing kick of the active particles with their new a, du;
+ *   new levels of the active particles: any deeper level at once; one level
+ *   shallower only when T' is a multiple of that shallower step, else the
+ *   old level; never shallower than lmx_i - lim (predictive limiter);
+ *   a marked inactive particle j moves to level mark_j - lim, its step ends
+ *   at the first multiple of the new step after T', and its opening kick is
+ *   corrected to the shortened step: v_half -= a (old - new step)/2, u
+ *   likewise (reactive limiter);
+ *   opening kick of the active particles with their new step.
+ * At a full synchronisation the new levels are the fresh ones (with the
+ * predictive limiter from this sub-step's neighbour levels; none at the
+ * start).  The run stops after nfull level-0 steps, synchronised, before the
+ * next opening kick.  energy[k] = sum 1/2 m v^2 + m u at the k-th full
+ * synchronisation; nsub = sub-steps taken; levels = final levels;
+ * time_out = elapsed time; active_total = active particles summed over the
+ * sub-steps (the particle updates the scheme made).  Returns ORC_EBOX-like errors of the solves, or
+ * ORC_EINVAL if a particle needs a level beyond lmax.
+ * ------------------------------------------------------------------------- */
+static double block_dtmax(int64_t n, const double *dt)
+{
+    double lo = dt[0], hi = dt[0];
+    for (int64_t i = 1; i < n; i++) {
+        if (dt[i] < lo) lo = dt[i];
+        if (dt[i] > hi) hi = dt[i];
+    }
+    int k = 0;
+    while (k < 1000 && ldexp(lo, k + 1) <= hi) k++;
+    return ldexp(lo, k);
+}
+
+static int level_of(double dt, double dtmax, int lmax)
+{
+    int l = 0;
+    while (l < lmax && ldexp(dtmax, -l) > dt) l++;
+    return ldexp(dtmax, -l) > dt ? -1 : l;
+}
+
+int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *z, double *vx,
+                  double *vy, double *vz, const double *m, double *u, double *h, int32_t lmax,
+                  int32_t lim, int32_t nfull, double *energy, int64_t *nsub, int32_t *levels,
+                  double *time_out, int64_t *active_total)
+{
+    if (n <= 0 || lmax < 0 || lmax > 40 || lim < 0 || nfull < 0) return ORC_EINVAL;
+    size_t N = (size_t)n;
+    double *buf = (double *)malloc(sizeof(double) * N * 30);
+    int64_t *ib = (int64_t *)malloc(sizeof(int64_t) * N * 6);
+    if (!buf || !ib) { free(buf); free(ib); return ORC_ENOMEM; }
+    double *vhx = buf, *vhy = buf + N, *vhz = buf + 2 * N, *uh = buf + 3 * N, *ax = buf + 4 * N,
+           *ay = buf + 5 * N, *az = buf + 6 * N, *du = buf + 7 * N, *rho = buf + 8 * N,
+           *omega = buf + 9 * N, *dt = buf + 10 * N, *vpx = buf + 11 * N, *vpy = buf + 12 * N,
+           *vpz = buf + 13 * N, *up = buf + 14 * N, *hn = buf + 15 * N, *t1 = buf + 16 * N,
+           *t2 = buf + 17 * N, *t3 = buf + 18 * N, *t4 = buf + 19 * N, *t5 = buf + 20 * N,
+           *t6 = buf + 21 * N, *t7 = buf + 22 * N, *t8 = buf + 23 * N, *t9 = buf + 24 * N;
+    int64_t *ts = ib, *te = ib + N, *lev = ib + 2 * N, *lmx = ib + 3 * N, *mark = ib + 4 * N,
+            *sel = ib + 5 * N;
+    int32_t *cnt = (int32_t *)t9;
+    const int64_t P0 = (int64_t)1 << lmax;
+    double Lb[3];
+    for (int k = 0; k < 3; k++) Lb[k] = p->hi[k] - p->lo[k];
+    int rc = ORC_OK;
+    double tnow = 0.0;
+    int64_t subs = 0, updates = 0;
+
+    /* initial evaluation of every particle */
+    rc = orc_density(p, n, x, y, z, m, h, n, NULL, hn, rho, t1, omega, cnt);
+    if (rc != ORC_OK) goto out;
+    memcpy(h, hn, sizeof(double) * N);
+    rc = orc_forces(p, n, x, y, z, vx, vy, vz, m, u, h, rho, omega, n, NULL, ax, ay, az, du, t2,
+                    dt, t3, t4, cnt, NULL, NULL, NULL);
+    if (rc != ORC_OK) goto out;
+    double dtmax = block_dtmax(n, dt);
+    for (int64_t i = 0; i < n; i++) {
+        int l = level_of(dt[i], dtmax, lmax);
+        if (l < 0) { rc = ORC_EINVAL; goto out; }
+        lev[i] = l;
+        ts[i] = 0;
+        te[i] = P0 >> l;
+    }
+    if (energy) energy[0] = total_energy(n, m, vx, vy, vz, u);
+    int64_t T = 0;
+    int32_t full = 0;
+    double tick = dtmax / (double)P0;
+    /* opening kicks */
+    for (int64_t i = 0; i < n; i++) {
+        double hs = 0.5 * (double)(te[i] - ts[i]) * tick;
+        vhx[i] = vx[i] + ax[i] * hs;
+        vhy[i] = vy[i] + ay[i] * hs;
+        vhz[i] = vz[i] + az[i] * hs;
+        uh[i] = u[i] + du[i] * hs;
+    }
+    while (full < nfull) {
+        int64_t Tn = te[0];
+        for (int64_t i = 1; i < n; i++) if (te[i] < Tn) Tn = te[i];
+        double dlt = (double)(Tn - T) * tick;
+        int64_t na = 0;
+        for (int64_t i = 0; i < n; i++) {
+            double *pos[3] = {&x[i], &y[i], &z[i]};
+            double vel[3] = {vhx[i], vhy[i], vhz[i]};
+            for (int k = 0; k < 3; k++) {
+                double q = *pos[k] + dlt * vel[k];
+                if (p->periodic) {
+                    if (q >= p->hi[k]) q -= Lb[k];
+                    else if (q < p->lo[k]) q += Lb[k];
+                }
+                *pos[k] = q;
+            }
+            double dm = ((double)Tn - 0.5 * (double)(ts[i] + te[i])) * tick;
+            vpx[i] = vhx[i] + ax[i] * dm;
+            vpy[i] = vhy[i] + ay[i] * dm;
+            vpz[i] = vhz[i] + az[i] * dm;
+            up[i] = uh[i] + du[i] * dm;
+            if (te[i] == Tn) sel[na++] = i;
+            lmx[i] = 0;
+            mark[i] = -1;
+        }
+        /* density and forces of the active particles */
+        rc = orc_density(p, n, x, y, z, m, h, na, sel, t1, t2, t3, t4, cnt);
+        if (rc != ORC_OK) goto out;
+        for (int64_t k = 0; k < na; k++) {
+            int64_t i = sel[k];
+            h[i] = t1[k];
+            rho[i] = t2[k];
+            omega[i] = t4[k];
+        }
+        rc = orc_forces(p, n, x, y, z, vpx, vpy, vpz, m, up, h, rho, omega, na, sel, t1, t2, t3,
+                        t4, t5, t6, t7, t8, cnt, NULL, NULL, NULL);
+        if (rc != ORC_OK) goto out;
+        for (int64_t k = 0; k < na; k++) {
+            int64_t i = sel[k];
+            ax[i] = t1[k]; ay[i] = t2[k]; az[i] = t3[k]; du[i] = t4[k]; dt[i] = t6[k];
+        }
+        /* limiter information over the force neighbours of the active particles */
+        for (int64_t k = 0; k < na; k++) {
+            int64_t i = sel[k];
+            double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+            int64_t mx = 0;
+            for (int64_t j = 0; j < n; j++) {
+                if (j == i) continue;
+                double ddx, ddy, ddz, r2 = pair_r2(p, x, y, z, i, j, &ddx, &ddy, &ddz);
+                if (!(r2 < hi2x4 || r2 < (2.0 * h[j]) * (2.0 * h[j]))) continue;
+                if (lev[j] > mx) mx = lev[j];
+                if (te[j] != Tn && lev[j] < lev[i] - lim && lev[i] > mark[j]) mark[j] = lev[i];
+            }
+            lmx[i] = mx;
+        }
+        /* closing kicks */
+        for (int64_t k = 0; k < na; k++) {
+            int64_t i = sel[k];
+            double hs = 0.5 * (double)(te[i] - ts[i]) * tick;
+            vx[i] = vhx[i] + ax[i] * hs;
+            vy[i] = vhy[i] + ay[i] * hs;
+            vz[i] = vhz[i] + az[i] * hs;
+            u[i] = uh[i] + du[i] * hs;
+        }
+        tnow += dlt;
+        subs++;
+        updates += na;
+        if (Tn == P0) {
+            /* full synchronisation: every particle is active */
+            full++;
+            if (energy) energy[full] = total_energy(n, m, vx, vy, vz, u);
+            if (full == nfull) break;
+            dtmax = block_dtmax(n, dt);
+            tick = dtmax / (double)P0;
+            for (int64_t i = 0; i < n; i++) {
+                int l = level_of(dt[i], dtmax, lmax);
+                if (l < 0) { rc = ORC_EINVAL; goto out; }
+                if (l < lmx[i] - lim) l = (int)(lmx[i] - lim);
+                if (l > lmax) { rc = ORC_EINVAL; goto out; }
+                lev[i] = l;
+                ts[i] = 0;
+                te[i] = P0 >> l;
+            }
+            T = 0;
+        } else {
+            for (int64_t k = 0; k < na; k++) {
+                int64_t i = sel[k];
+                int l = level_of(dt[i], dtmax, lmax);
+                if (l < 0) { rc = ORC_EINVAL; goto out; }
+                int64_t cur = lev[i], nl;
+                if (l > cur) nl = l;
+                else if (l < cur && Tn % (P0 >> (cur - 1)) == 0) nl = cur - 1;
+                else nl = cur;
+                if (nl < lmx[i] - lim) nl = lmx[i] - lim;
+                if (nl > lmax) { rc = ORC_EINVAL; goto out; }
+                lev[i] = nl;
+                ts[i] = Tn;
+                te[i] = Tn + (P0 >> nl);
+            }
+            for (int64_t j = 0; j < n; j++) {
+                /* only inactive particles were marked */
+                if (mark[j] < 0 || lev[j] >= mark[j] - lim) continue;
+                int64_t nl = mark[j] - lim;
+                if (nl > lmax) { rc = ORC_EINVAL; goto out; }
+                int64_t st = P0 >> nl;
+                int64_t tn = (Tn / st + 1) * st;
+                double cut = 0.5 * (double)((te[j] - ts[j]) - (tn - ts[j])) * tick;
+                vhx[j] -= ax[j] * cut;
+                vhy[j] -= ay[j] * cut;
+                vhz[j] -= az[j] * cut;
+                uh[j] -= du[j] * cut;
+                lev[j] = nl;
+                te[j] = tn;
+            }
+            T = Tn;
+        }
+        /* opening kicks of the particles that start a step */
+        for (int64_t k = 0; k < na; k++) {
+            int64_t i = sel[k];
+            double hs = 0.5 * (double)(te[i] - ts[i]) * tick;
+            vhx[i] = vx[i] + ax[i] * hs;
+            vhy[i] = vy[i] + ay[i] * hs;
+            vhz[i] = vz[i] + az[i] * hs;
+            uh[i] = u[i] + du[i] * hs;
+        }
+    }
+    if (levels)
+        for (int64_t i = 0; i < n; i++) levels[i] = (int32_t)lev[i];
+out:
+    if (nsub) *nsub = subs;
+    if (time_out) *time_out = tnow;
+    if (active_total) *active_total = updates;
+    free(buf);
+    free(ib);
+    return rc;
+}
