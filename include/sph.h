@@ -73,7 +73,9 @@ typedef enum {
     SPH_ENONFINITE = -6,    /* a NaN or Inf input or result */
     SPH_EBUDGET = -7,       /* the working set would exceed the HBM budget */
     SPH_ECAP = -8,          /* an output capacity given by the caller is too small */
-    SPH_ESTATE = -9         /* call out of order (e.g. sph_step before upload) */
+    SPH_ESTATE = -9,        /* call out of order (e.g. sph_step before upload) */
+    SPH_ELEVEL = -10        /* block time-steps: a particle needs a level deeper than
+                               block_lmax */
 } sph_status;
 
 enum { SPH_FP64 = 0, SPH_FP32_PAIR = 1 };
@@ -153,6 +155,10 @@ typedef struct {
     double alpha_min;  /* switches: floor of alpha (default 0.1) */
     double alpha_max;  /* switches: ceiling of alpha (default 1) */
     double av_ell;     /* switches: decay constant ell (0: 0.1 MM97, 0.05 CD10) */
+    int32_t block_lmax; /* 0: one global time-step (sph_step); 1..40: hierarchical block
+                           time-steps (sph_substep) with at most this many levels */
+    int32_t block_lim;  /* block time-step limiter: force neighbours at most this many
+                           levels apart (default 2) */
 } sph_params;
 
 /*
@@ -192,6 +198,7 @@ typedef struct {
                              writes the evolved values) */
     double *divv;         /* optional output: velocity divergence */
     double *curlv;        /* optional output: magnitude of the velocity curl */
+    int32_t *level;       /* optional output of sph_download_state: time-step level */
 } sph_particles;
 
 /* Diagnostics of the last evaluation (stateless or resident). */
@@ -221,6 +228,15 @@ typedef struct {
     int32_t force_walk_overflows;   /* of walk_overflows: those of the force loop */
     int64_t dens_list_overflows;    /* particles whose density candidate list outgrew its
                                        capacity in a sweep (swept again at the next Newton step) */
+    /* block time-steps (block_lmax > 0) */
+    int64_t block_full_steps; /* level-0 steps completed since upload */
+    int64_t block_substeps;   /* sub-steps taken since upload */
+    int64_t block_active;     /* active particles of the last sub-step */
+    int64_t block_updates;    /* active particles summed over the sub-steps */
+    double block_time;        /* elapsed time */
+    double block_dt_max;      /* length of the current level-0 step */
+    int32_t block_synchronised; /* 1 when every particle's step has just ended */
+    int32_t pad_;
 } sph_state_stats;
 
 typedef struct sph_ctx sph_ctx;
@@ -329,6 +345,36 @@ sph_status sph_upload_state(sph_ctx *ctx, const sph_particles *ps);
  * NULL it receives the step actually taken when sph_sync next returns.
  */
 sph_status sph_step(sph_ctx *ctx, double dt, double *dt_used);
+
+/*
+ * Hierarchical block time-steps (section 2.1.4) with the predictive and
+ * reactive time-step limiter (section 2.1.5), on the resident state of a
+ * context created with block_lmax > 0 (then sph_step is SPH_ESTATE).  One
+ * level-0 step of length dt_max holds 2^block_lmax ticks; a particle on
+ * level l steps 2^(block_lmax - l) ticks.  At sph_upload_state and at every
+ * full synchronisation dt_max = min_i dt_i 2^k with k the largest integer
+ * keeping dt_max <= max_i dt_i (dt_i the CFL steps), and each particle takes
+ * the smallest level l with dt_max 2^-l <= dt_i.  One call advances to the
+ * next tick at which some particle's step ends:
+ *   every particle drifts with its half-step velocity; every particle is
+ *   predicted to that time (v_half + a (t - t_mid)); the particles whose step
+ *   ends (active) get h, rho and forces from all neighbours (inactive ones
+ *   with their stored h, rho, Omega and predicted v, u) and their closing
+ *   kick;  levels of active particles: any deeper level at once, one level
+ *   shallower only when the time is a multiple of that step, never more
+ *   than block_lim levels shallower than their deepest force neighbour
+ *   (predictive limiter); active particles mark inactive force neighbours
+ *   more than block_lim levels shallower than themselves, which move to
+ *   that level, end their step at its next tick and have their opening kick
+ *   corrected to the shortened step (reactive limiter); opening kicks.
+ * Everything runs on the device (no waiting).  sph_state_info reports the
+ * sub-steps, level-0 steps and the clock; at a synchronisation
+ * (block_synchronised = 1) sph_download_state returns every particle at the
+ * same time; otherwise positions are current and v, u are those of each
+ * particle's last synchronisation.  Not combined with the viscosity
+ * switches, batches or graph capture (SPH_EINVAL / SPH_ESTATE).
+ */
+sph_status sph_substep(sph_ctx *ctx);
 
 /*
  * HIP graph of resident steps.  sph_capture_steps records TWO consecutive

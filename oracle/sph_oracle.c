@@ -805,8 +805,9 @@ int orc_mfv_gradients(const orc_params *p, int64_t n, const double *x, const dou
  *   opening kick of the active particles with their new step.
  * At a full synchronisation the new levels are the fresh ones (with the
  * predictive limiter from this sub-step's neighbour levels; none at the
- * start).  The run stops after nfull level-0 steps, synchronised, before the
- * next opening kick.  energy[k] = sum 1/2 m v^2 + m u at the k-th full
+ * start).  The run stops after nfull level-0 steps, synchronised: x, v, u
+ * are those of the synchronisation, the levels those assigned there for the
+ * next level-0 step.  energy[k] = sum 1/2 m v^2 + m u at the k-th full
  * synchronisation; nsub = sub-steps taken; levels = final levels;
  * time_out = elapsed time; active_total = active particles summed over the
  * sub-steps (the particle updates the scheme made).  Returns ORC_EBOX-like errors of the solves, or
@@ -955,7 +956,6 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
             /* full synchronisation: every particle is active */
             full++;
             if (energy) energy[full] = total_energy(n, m, vx, vy, vz, u);
-            if (full == nfull) break;
             dtmax = block_dtmax(n, dt);
             tick = dtmax / (double)P0;
             for (int64_t i = 0; i < n; i++) {
@@ -1009,6 +1009,7 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
             vhz[i] = vz[i] + az[i] * hs;
             uh[i] = u[i] + du[i] * hs;
         }
+        if (full == nfull && T == 0) break;
     }
     if (levels)
         for (int64_t i = 0; i < n; i++) levels[i] = (int32_t)lev[i];

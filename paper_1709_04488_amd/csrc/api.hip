@@ -41,6 +41,10 @@ constexpr int64_t bytes_per_particle()
     b += 3 * 4;                // s: fp32 offsets
     b += 16 * 8 + 4;           // t: re-sort buffers
     b += 2 * 4;                // leaf starts, leaf of each particle
+    b += 4 + 2 * 8 + 4 * 8 + 3 * 4;   // s: block time-steps (level, step ticks, half-step v, u,
+                                      //    active flag, limiter level and mark)
+    b += 8 * 8 + 4 + 2 * 8;    // t: block re-sort (a, du, rho, Omega, dt, vsig, level, ticks)
+    b += 4;                    // active particles per leaf
     return b;
 }
 
@@ -61,6 +65,10 @@ sph_status check_params(sph_ctx *c, const sph_params *p)
         return fail(c, SPH_EINVAL, "alpha_ac must be finite and >= 0");
     if (p->ac_signal != SPH_AC_WADSLEY && p->ac_signal != SPH_AC_PRICE)
         return fail(c, SPH_EINVAL, "ac_signal must be SPH_AC_WADSLEY or SPH_AC_PRICE");
+    if (p->block_lmax < 0 || p->block_lmax > 40 || p->block_lim < 0)
+        return fail(c, SPH_EINVAL, "need 0 <= block_lmax <= 40 and block_lim >= 0");
+    if (p->block_lmax > 0 && p->av_switch != SPH_AV_NONE)
+        return fail(c, SPH_EINVAL, "block time-steps do not run with a viscosity switch");
     if (p->av_switch != SPH_AV_NONE && p->av_switch != SPH_AV_MM97 && p->av_switch != SPH_AV_CD10)
         return fail(c, SPH_EINVAL, "av_switch must be SPH_AV_NONE, SPH_AV_MM97 or SPH_AV_CD10");
     if (!(p->alpha_min >= 0.0) || !(p->alpha_max >= p->alpha_min) || !std::isfinite(p->alpha_max) ||
@@ -196,6 +204,13 @@ sph_status lay_out(sph_ctx *c, int64_t cap, Take take)
     A_(S.id, cap); A_(T.id, cap);
     A_(S.fx, cap); A_(S.fy, cap); A_(S.fz, cap);
     A_(c->lstart, cap + 1); A_(c->leaf_id, cap);
+    double **bd[] = {&S.vhx, &S.vhy, &S.vhz, &S.uh, &T.ax, &T.ay, &T.az, &T.du, &T.rho,
+                     &T.omega, &T.dt, &T.vsig};
+    for (double **pp : bd) A_(*pp, cap);
+    A_(S.lev, cap); A_(T.lev, cap);
+    A_(S.ts, cap); A_(S.te, cap); A_(T.ts, cap); A_(T.te, cap);
+    A_(S.act, cap); A_(S.lmx, cap); A_(S.mark, cap);
+    A_(c->leaf_act, cap);
     A_(c->nodes, node_count_bound(cap));
     A_(c->hist, hist_words(cap));
 #undef A_
@@ -732,6 +747,8 @@ void sph_default_params(sph_params *p)
     p->alpha_min = 0.1;
     p->alpha_max = 1.0;
     p->av_ell = 0.0;
+    p->block_lmax = 0;
+    p->block_lim = 2;
 }
 
 sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size_t budget)
@@ -757,6 +774,7 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
               hipMalloc((void **)&c->d_work, sizeof(uint32_t) * 64) == hipSuccess &&
               hipMalloc(&c->d_dargs, kArgBytes) == hipSuccess &&
               hipMalloc(&c->d_fargs, kArgBytes) == hipSuccess &&
+              hipMalloc((void **)&c->d_clock, sizeof(BlockClock)) == hipSuccess &&
               hipHostMalloc((void **)&c->h_status, sizeof(int32_t) * kStatusWords) == hipSuccess &&
               hipHostMalloc((void **)&c->h_scal, sizeof(double) * 16) == hipSuccess;
     if (!ok) {
@@ -771,6 +789,7 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
     ok = hipMemsetAsync(c->d_status, 0, sizeof(int32_t) * kStatusWords, c->stream) == hipSuccess &&
          hipMemsetAsync(c->d_scal, 0, sizeof(double) * 16, c->stream) == hipSuccess &&
          hipMemsetAsync(c->d_counts, 0, sizeof(int64_t) * kCountWords, c->stream) == hipSuccess &&
+         hipMemsetAsync(c->d_clock, 0, sizeof(BlockClock), c->stream) == hipSuccess &&
          hipStreamSynchronize(c->stream) == hipSuccess;
     if (!ok) { sph_destroy(c); return SPH_EDEVICE; }
     *out = c;
@@ -794,6 +813,7 @@ sph_status sph_destroy(sph_ctx *c)
     if (c->d_work) (void)hipFree(c->d_work);
     if (c->d_dargs) (void)hipFree(c->d_dargs);
     if (c->d_fargs) (void)hipFree(c->d_fargs);
+    if (c->d_clock) (void)hipFree(c->d_clock);
     if (c->h_status) (void)hipHostFree(c->h_status);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
     delete c;
@@ -927,6 +947,9 @@ sph_status sph_batch_forces(sph_ctx *const *cs, sph_particles *const *ps, int32_
 sph_status sph_batch_step(sph_ctx *const *cs, int32_t count, double dt)
 {
     TRY(check_batch(cs, count));
+    for (int r = 0; r < count; r++)
+        if (cs[r]->p.block_lmax > 0)
+            return fail(cs[r], SPH_ESTATE, "block time-steps advance with sph_substep");
     for (int r = 0; r < count; r++) TRY(step_pre(cs[r], dt));
     TRY(launch_groups(cs, count, [](sph_ctx *const *g, int k) { return density_launch(g, k, 0); }));
     for (int r = 0; r < count; r++) TRY(step_mid(cs[r]));
@@ -970,6 +993,8 @@ sph_status sph_upload_state(sph_ctx *c, const sph_particles *ps)
     TRY(run_forces(c, n));
     TRY(av_rate(c, n, c->s.al));
     TRY(av_cd10(c, n, true));
+    // block time-steps: first levels, steps and opening kicks
+    if (c->p.block_lmax > 0) TRY(block_finish(c, n, true));
     TRY(reduce_dt(c, n));
     TRY(hip_check(c, hipMemsetAsync(c->d_scal + 1, 0, sizeof(double) * 2, c->stream), "reset time"));
     TRY(reduce_diag(c, n));
@@ -982,6 +1007,7 @@ sph_status sph_upload_state(sph_ctx *c, const sph_particles *ps)
 sph_status sph_step(sph_ctx *c, double dt, double *dt_used)
 {
     if (!c) return SPH_EINVAL;
+    if (c->p.block_lmax > 0) return fail(c, SPH_ESTATE, "block time-steps advance with sph_substep");
     TRY(step_pre(c, dt));
     TRY(density_launch(&c, 1, c->n));
     TRY(step_mid(c));
@@ -989,10 +1015,67 @@ sph_status sph_step(sph_ctx *c, double dt, double *dt_used)
     return step_post(c, dt, dt_used);
 }
 
+sph_status sph_substep(sph_ctx *c)
+{
+    if (!c) return SPH_EINVAL;
+    if (!c->resident) return fail(c, SPH_ESTATE, "sph_substep needs sph_upload_state first");
+    if (c->p.block_lmax <= 0) return fail(c, SPH_ESTATE, "the context has no block time-steps");
+    const int64_t n = c->n;
+    Sorted &S = c->s, &T = c->t;
+    // next tick at which steps end; every particle drifts to it
+    TRY(block_next(c, n));
+    // re-sort: everything that persists per particle moves with it
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_begin(c, 2, &e0, &e1);
+    TRY(build_order(c, n, S.x, S.y, S.z));
+    GatherList g{};
+    double **sa[] = {&S.x, &S.y, &S.z, &S.vx, &S.vy, &S.vz, &S.m, &S.u, &S.h, &S.vhx, &S.vhy,
+                     &S.vhz, &S.uh, &S.ax, &S.ay, &S.az, &S.du, &S.rho, &S.omega, &S.dt, &S.vsig};
+    double **ta[] = {&T.x, &T.y, &T.z, &T.vx, &T.vy, &T.vz, &T.m, &T.u, &T.h, &T.vpx, &T.vpy,
+                     &T.vpz, &T.up, &T.ax, &T.ay, &T.az, &T.du, &T.rho, &T.omega, &T.dt, &T.vsig};
+    const int nd = 21;
+    for (int a = 0; a < nd; a++) { g.kind[a] = 0; g.src[a] = *sa[a]; g.dst[a] = *ta[a]; }
+    int k = nd;
+    g.kind[k] = 1; g.src[k] = S.id; g.dst[k] = T.id; k++;
+    g.kind[k] = 1; g.src[k] = S.lev; g.dst[k] = T.lev; k++;
+    g.kind[k] = 0; g.src[k] = S.ts; g.dst[k] = T.ts; k++;
+    g.kind[k] = 0; g.src[k] = S.te; g.dst[k] = T.te; k++;
+    g.count = k;
+    TRY(gather(c, n, g, false));
+    for (int a = 0; a < nd; a++) std::swap(*sa[a], *ta[a]);
+    std::swap(S.id, T.id);
+    std::swap(S.lev, T.lev);
+    std::swap(S.ts, T.ts);
+    std::swap(S.te, T.te);
+    TRY(build_tree(c, n));
+    timer_end(c, 2, e0, e1);
+    // predictors, the active set and its count per leaf
+    TRY(block_predict(c, n));
+    c->f_act = S.act;
+    c->f_block = true;
+    c->f_alpha = nullptr;
+    c->f_div = false;
+    sph_status st = density_prepare(c, n);
+    if (st == SPH_OK) st = density_launch(&c, 1, n);
+    if (st == SPH_OK) st = refresh_hmax(c, n);
+    if (st == SPH_OK) st = force_prep(c, n, S.up, S.vpx, S.vpy, S.vpz);
+    if (st == SPH_OK) st = forces_prepare(c, n);
+    c->f_act = nullptr;
+    c->f_block = false;
+    TRY(st);
+    TRY(forces_launch(&c, 1, n));
+    // closing kicks, levels, limiter, opening kicks, clock
+    TRY(block_finish(c, n, false));
+    TRY(reduce_diag(c, n));
+    c->steps++;
+    return SPH_OK;
+}
+
 sph_status sph_capture_steps(sph_ctx *c, double dt)
 {
     if (!c) return SPH_EINVAL;
     if (!c->resident) return fail(c, SPH_ESTATE, "capture needs a resident state");
+    if (c->p.block_lmax > 0) return fail(c, SPH_ESTATE, "no graph capture of block time-steps");
     if (!c->stream) return fail(c, SPH_EINVAL, "capture needs a non-null stream");
     if (!std::isfinite(dt)) return fail(c, SPH_EINVAL, "dt is not finite");
     drop_graph(c);
@@ -1057,16 +1140,18 @@ sph_status sph_download_state(sph_ctx *c, sph_particles *ps)
     ScatterList sl{};
     const void *src[] = {c->s.x, c->s.y, c->s.z, c->s.vx, c->s.vy, c->s.vz, c->s.u, c->s.h,
                          c->s.rho, c->s.omega, c->s.ax, c->s.ay, c->s.az, c->s.du, c->s.vsig,
-                         c->s.dt, c->s.nngb, c->s.nforce, c->s.al, c->s.divv, c->s.curlv};
+                         c->s.dt, c->s.nngb, c->s.nforce, c->s.al, c->s.divv, c->s.curlv,
+                         c->s.lev};
     void *dst[] = {(void *)ps->x, (void *)ps->y, (void *)ps->z, (void *)ps->vx, (void *)ps->vy,
                    (void *)ps->vz, (void *)ps->u, ps->h, ps->rho, ps->omega, ps->ax, ps->ay,
                    ps->az, ps->dudt, ps->vsig, ps->dt, ps->nngb, ps->nforce,
                    c->res_alpha ? ps->alpha : nullptr,
                    c->p.av_switch != SPH_AV_NONE ? ps->divv : nullptr,
-                   c->p.av_switch != SPH_AV_NONE ? ps->curlv : nullptr};
-    for (int a = 0; a < 21; a++) {
+                   c->p.av_switch != SPH_AV_NONE ? ps->curlv : nullptr,
+                   c->p.block_lmax > 0 ? ps->level : nullptr};
+    for (int a = 0; a < 22; a++) {
         if (!dst[a]) continue;
-        sl.kind[sl.count] = (a == 16 || a == 17) ? 1 : 0;
+        sl.kind[sl.count] = (a == 16 || a == 17 || a == 21) ? 1 : 0;
         sl.src[sl.count] = src[a];
         sl.dst[sl.count] = dst[a];
         sl.count++;
@@ -1111,6 +1196,19 @@ sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
     info->density_walk_overflows = (int32_t)counts[kCntDensOverflows];
     info->force_walk_overflows = (int32_t)counts[kCntForceOverflows];
     info->dens_list_overflows = counts[kCntDensListOverflows];
+    if (c->p.block_lmax > 0 && c->resident) {
+        BlockClock clk{};
+        TRY(hip_check(c, hipMemcpyAsync(&clk, c->d_clock, sizeof(clk), hipMemcpyDeviceToHost,
+                                        c->stream), "copy block clock"));
+        TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+        info->block_full_steps = clk.full;
+        info->block_substeps = clk.nsub;
+        info->block_active = clk.active;
+        info->block_updates = clk.updates;
+        info->block_time = clk.time;
+        info->block_dt_max = clk.dt_max;
+        info->block_synchronised = clk.T == 0 ? 1 : 0;
+    }
     return SPH_OK;
 }
 
@@ -1257,6 +1355,8 @@ sph_status sph_sync(sph_ctx *c)
     if (st[0] & kFlagNotConverged)
         return fail(c, SPH_ENOTCONVERGED, std::to_string(st[1]) +
                                               " smoothing lengths did not converge");
+    if (st[0] & kFlagLevel)
+        return fail(c, SPH_ELEVEL, "a particle needs a time-step level deeper than block_lmax");
     c->err.clear();
     return SPH_OK;
 }

@@ -132,6 +132,16 @@ __device__ inline double wave_max(double v)
     return fmax(fmax(row(0), row(16)), fmax(row(32), row(48)));
 }
 
+template <int K>
+__device__ inline int group_max_int(int v)
+{
+    if constexpr (K >= 2) { const int w = xlane<1>(v); v = w > v ? w : v; }
+    if constexpr (K >= 4) { const int w = xlane<2>(v); v = w > v ? w : v; }
+    if constexpr (K >= 8) { const int w = xlane<4>(v); v = w > v ? w : v; }
+    if constexpr (K >= 16) { const int w = xlane<8>(v); v = w > v ? w : v; }
+    return v;
+}
+
 // Wave-wide sum of small non-negative per-lane counts, wave-uniform.
 __device__ inline int64_t wave_sum_int(int v)
 {
@@ -848,6 +858,9 @@ struct DensArgs {
     double h_rtol;
     double walk_margin;
     int32_t max_iter;
+    // block time-steps: particles that take part (nullptr: all) and their
+    // count per leaf (leaves without any are skipped)
+    const int32_t *active, *leaf_act;
 };
 
 template <int G, int PREC>
@@ -909,11 +922,12 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
         }
         const auto &A = *Ap;
         const int64_t leaf = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
+        if (A.leaf_act && as_const(A.leaf_act)[leaf] == 0) return;   // no active particle
         const Box bx = load_const(&B.req[r]->box);
         const int64_t first = as_const(A.lstart)[leaf];
         const int nhome = (int)(as_const(A.lstart)[leaf + 1] - first);
         const int64_t i = first + p;
-        const bool active = p < nhome;
+        const bool active = p < nhome && (!A.active || as_global(A.active)[i] != 0);
         const int64_t ii = active ? i : first;
         const double hx = as_global(A.x)[ii], hy = as_global(A.y)[ii], hz = as_global(A.z)[ii];
         float hfx = 0.f, hfy = 0.f, hfz = 0.f;
@@ -1201,6 +1215,13 @@ struct ForceArgs {
     const double *alpha_p;
     const double *omega;
     double *divv, *curlv;
+    // block time-steps: the active set (nullptr: all), its count per leaf, and
+    // the limiter: levels, deepest neighbour level (out, active particles),
+    // wake-up marks of inactive neighbours (atomic max), level spread lim
+    const int32_t *active, *leaf_act;
+    const int32_t *lev;
+    int32_t *lmx, *mark;
+    int32_t lim;
 };
 
 // AC: the launch carries artificial conductivity (some set of the batch has
@@ -1245,6 +1266,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         }
         const auto &F = *Fp;
         const int64_t leaf = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
+        if (F.leaf_act && as_const(F.leaf_act)[leaf] == 0) return;   // no active particle
         const Box bx = load_const(&B.req[r]->box);
         const double alpha = F.alpha, beta = F.beta;
         const double *const alpha_p = SW ? F.alpha_p : nullptr;
@@ -1254,8 +1276,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         const int64_t first = as_const(F.lstart)[leaf];
         const int nhome = (int)(as_const(F.lstart)[leaf + 1] - first);
         const int64_t i = first + p;
-        const bool active = p < nhome;
-        const int64_t ii = active ? i : first;
+        const bool active = p < nhome && (!F.active || as_global(F.active)[i] != 0);
+        const int64_t ii = p < nhome ? i : first;
         const double hx = as_global(F.x)[ii], hy = as_global(F.y)[ii], hz = as_global(F.z)[ii];
         float hfx = 0.f, hfy = 0.f, hfz = 0.f;
         if (PREC == SPH_FP32_PAIR) {
@@ -1299,6 +1321,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, vs_max = -INFINITY;
         double dvs = 0.0, cxs = 0.0, cys = 0.0, czs = 0.0;   // div v, curl v sums (SW)
         int cnt = 0, selfs = 0;
+        int lmx_l = 0;                                       // block time-steps
+        const int lev_i = F.lev ? as_global(F.lev)[ii] : 0;
         auto group = [&](const uint32_t *leaves, int ng) {
             __builtin_amdgcn_s_setprio(2);
             stage_group<G, PREC, true>(S, leaves, ng, F.lstart, F.nodes, home, bx, -1.0, F.x, F.y, F.z,
@@ -1448,19 +1472,27 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             // the particle itself is among the hits of its own leaf: it takes
             // no pair terms and is not counted
             const uint32_t self = (uint32_t)i;
+            // block time-steps: the deepest neighbour level, and inactive
+            // neighbours more than lim levels shallower marked to wake up
+            auto limiter = [&](uint32_t j) {
+                if (!F.lev) return;
+                const int lj = as_global(F.lev)[j];
+                lmx_l = lj > lmx_l ? lj : lmx_l;
+                if (lj < lev_i - F.lim && as_global(F.active)[j] == 0) atomicMax(&F.mark[j], lev_i);
+            };
             if (PREC == SPH_FP32_PAIR) {
                 cnt += for_my_bit_pairs<LPP>(w0, w1, q, [&](int sa, int sb) {
                     const JData da = load_j(sa);
                     JData db = da;
                     if (sb >= 0) db = load_j(sb);
-                    if (S.j[sa] != self) pair_terms(sa, da); else selfs++;
+                    if (S.j[sa] != self) { limiter(S.j[sa]); pair_terms(sa, da); } else selfs++;
                     if (sb >= 0) {
-                        if (S.j[sb] != self) pair_terms(sb, db); else selfs++;
+                        if (S.j[sb] != self) { limiter(S.j[sb]); pair_terms(sb, db); } else selfs++;
                     }
                 });
             } else {
                 cnt += for_my_bits<LPP>(w0, w1, q, [&](int sl, int) {
-                    if (S.j[sl] != self) pair_terms(sl, load_j(sl)); else selfs++;
+                    if (S.j[sl] != self) { limiter(S.j[sl]); pair_terms(sl, load_j(sl)); } else selfs++;
                 });
             }
             if (q == 0) {
@@ -1477,6 +1509,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         vs_max = group_max<LPP>(vs_max);
         selfs = group_sum<LPP>(selfs);
         cnt -= selfs;
+        if (F.lev) lmx_l = group_max_int<LPP>(lmx_l);
         if constexpr (SW) {
             dvs = group_sum<LPP>(dvs);
             cxs = group_sum<LPP>(cxs);
@@ -1492,6 +1525,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             F.vsig[i] = vsig;
             F.dt[i] = F.ccfl * hi / vsig;
             F.nforce[i] = cnt;
+            if (F.lmx) F.lmx[i] = lmx_l;
             if (SW && F.divv) {
                 const double orho = as_global(F.omega)[i] * rhoi;
                 F.divv[i] = -dvs / orho;
@@ -1882,6 +1916,8 @@ sph_status density_prepare(sph_ctx *c, int64_t n)
     a.h_rtol = c->p.precision == SPH_FP32_PAIR ? std::max(c->p.h_rtol, 2e-6) : c->p.h_rtol;
     a.walk_margin = 1.1;
     a.max_iter = c->p.h_max_iter;
+    a.active = c->f_act;
+    a.leaf_act = c->f_act ? c->leaf_act : nullptr;
     const void *req[] = {a.nodes, a.x, a.y, a.z, a.m, a.h, a.rho, a.omega, a.nngb, a.status,
                          a.counts, a.tree, a.lstart, a.work, c->d_dargs};
     for (const void *q : req)
@@ -1914,6 +1950,14 @@ sph_status forces_prepare(sph_ctx *c, int64_t n)
     a.ac_price = c->p.ac_signal == SPH_AC_PRICE ? 1 : 0;
     a.alpha_p = c->f_alpha;
     a.omega = c->s.omega;
+    a.active = c->f_act;
+    a.leaf_act = c->f_act ? c->leaf_act : nullptr;
+    if (c->f_block) {
+        a.lev = c->s.lev;
+        a.lmx = c->s.lmx;
+        a.mark = c->s.mark;
+        a.lim = c->p.block_lim;
+    }
     a.divv = c->f_div ? c->s.divv : nullptr;
     a.curlv = c->f_div ? c->s.curlv : nullptr;
     a.count_tests = c->count_tests ? 1 : 0;

@@ -82,6 +82,7 @@ enum : int32_t {
     kFlagNotConverged = 1,
     kFlagNonFinite = 2,
     kFlagStencil = 4,
+    kFlagLevel = 8,     // block time-steps: a level deeper than the timeline allows
 };
 constexpr int kStatusWords = 8;
 
@@ -136,8 +137,31 @@ struct Sorted {
     // (MM97), div v of the previous step (CD10); div v and |curl v| outputs
     double *al = nullptr, *alp = nullptr, *adot = nullptr, *dprev = nullptr;
     double *divv = nullptr, *curlv = nullptr;
+    // block time-steps: level, step start and end (ticks), half-step v and u,
+    // the active flag and the limiter's neighbour level and wake-up mark of
+    // the current sub-step
+    int32_t *lev = nullptr;
+    int64_t *ts = nullptr, *te = nullptr;
+    double *vhx = nullptr, *vhy = nullptr, *vhz = nullptr, *uh = nullptr;
+    int32_t *act = nullptr, *lmx = nullptr, *mark = nullptr;
     // FP32-pair mode
     float *fx = nullptr, *fy = nullptr, *fz = nullptr;
+};
+
+// Device clock of the block time-steps (one level-0 step = 2^lmax ticks).
+struct BlockClock {
+    int64_t T;          // current tick within the level-0 step
+    int64_t Tn;         // tick of the sub-step in progress
+    int64_t full;       // level-0 steps completed
+    int64_t nsub;       // sub-steps taken
+    int64_t active;     // active particles of the last sub-step
+    int64_t updates;    // active particles summed over the sub-steps
+    double tick;        // time per tick of the current level-0 step
+    double tick_next;   // time per tick of the next one (set at a full sync)
+    double time;        // elapsed time
+    double dt_max;      // length of the current level-0 step
+    double dt_max_next; // of the next one (set at a full sync)
+    int64_t pad[5];
 };
 
 struct Timer {
@@ -197,6 +221,8 @@ struct sph_ctx {
     // resident state
     bool resident = false;
     bool res_alpha = false;     // the resident state carries per-particle alpha
+    sph::BlockClock *d_clock = nullptr;   // block time-steps (device)
+    int32_t *leaf_act = nullptr;     // active particles per leaf of the current sub-step
     double *d_scal = nullptr;   // [0] dt_next [1] dt_last [2] time [3] KE [4] TE [5..7] P
                                 // [8] smallest, [9] largest mass of the last density pass
     // device counters, indexed by the kCnt* constants
@@ -215,6 +241,11 @@ struct sph_ctx {
 
     sph::Timer timer;
     bool count_tests = false;   // pair loops also count box and candidate tests
+
+    // per-call active set of the pair loops (block time-steps; nullptr: every
+    // particle) and the force loop's limiter outputs
+    const int32_t *f_act = nullptr;
+    bool f_block = false;
 
     // per-call inputs of the force loop: the sorted per-particle alpha it
     // uses (nullptr: alpha_av for every pair), whether it writes div v and
@@ -242,9 +273,9 @@ sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y,
 // Gather `count` arrays through c->perm: dst[k] = src[perm[k]].
 struct GatherList {
     int32_t count;
-    int32_t kind[24];        // 0: double, 1: uint32, 2: float
-    const void *src[24];
-    void *dst[24];
+    int32_t kind[32];        // 0: 8-byte word, 1: uint32, 2: float
+    const void *src[32];
+    void *dst[32];
 };
 sph_status gather(sph_ctx *c, int64_t n, const GatherList &g, bool identity_src_index);
 // Leaf boxes and tree over c->s.{x,y,z,h}; FP32 offsets when requested.
@@ -278,9 +309,9 @@ sph_status run_neighbours(sph_ctx *c, int64_t n, int32_t mode, int64_t *counts_s
 // scatter sorted arrays back to caller order through c->perm
 struct ScatterList {
     int32_t count;
-    int32_t kind[24];
-    const void *src[24];
-    void *dst[24];
+    int32_t kind[32];
+    const void *src[32];
+    void *dst[32];
 };
 sph_status scatter(sph_ctx *c, int64_t n, const ScatterList &s, const uint32_t *index);
 
@@ -325,6 +356,10 @@ sph_status closing_kick(sph_ctx *c, int64_t n, double dt_host);
 sph_status av_rate(sph_ctx *c, int64_t n, const double *alpha_now);
 sph_status av_cd10(sph_ctx *c, int64_t n, bool first);
 sph_status fill(sph_ctx *c, int64_t n, double *v, double value);
+// block time-steps on the resident state (step.hip)
+sph_status block_next(sph_ctx *c, int64_t n);           // Tn = min te; drift every particle
+sph_status block_predict(sph_ctx *c, int64_t n);        // predictors, active set, leaf counts
+sph_status block_finish(sph_ctx *c, int64_t n, bool init);  // close, levels, limiter, open, clock
 sph_status reduce_dt(sph_ctx *c, int64_t n);
 // smallest and largest sorted mass -> d_scal[8], d_scal[9]
 sph_status reduce_mass_range(sph_ctx *c, int64_t n);

@@ -407,6 +407,345 @@ sph_status kick_drift(sph_ctx *c, int64_t n, double dt_host)
     return hip_check(c, hipGetLastError(), "kick_drift");
 }
 
+// ---- block time-steps (section 2.1.4) and the limiter (section 2.1.5) -----
+//
+// The integer timeline and the rules are those of the oracle: a level-0 step
+// of dt_max holds P0 = 2^lmax ticks; a particle on level l steps 2^(lmax-l)
+// ticks; dt_max = min dt 2^k (k the largest keeping it <= max dt) at every
+// full synchronisation.  Every decision below is integer arithmetic or an
+// exact power-of-two comparison of the CFL steps, so it is taken exactly
+// as the oracle takes it from the same steps.
+namespace {
+
+struct BlockArgs {
+    int64_t n;
+    Box box;
+    int32_t lmax, lim;
+    BlockClock *clk;
+    int32_t *status;
+    double *x, *y, *z;
+    double *vx, *vy, *vz, *u;       // velocities, u at each particle's last synchronisation
+    double *vhx, *vhy, *vhz, *uh;   // after the opening kick
+    double *vpx, *vpy, *vpz, *up;   // predicted to the end of the sub-step
+    const double *ax, *ay, *az, *du, *dt;
+    int32_t *lev;
+    int64_t *ts, *te;
+    int32_t *act, *lmx, *mark;
+    const uint32_t *lstart;
+    const TreeInfo *tree;
+    int32_t *leaf_act;
+    int64_t *part;                  // reduction partials
+};
+
+// smallest level l <= lmax with dt_max 2^-l <= dt, or -1 (exact comparisons)
+__device__ inline int block_level_of(double dt, double dtmax, int lmax)
+{
+    int l = 0;
+    while (l < lmax && ldexp(dtmax, -l) > dt) l++;
+    return ldexp(dtmax, -l) > dt ? -1 : l;
+}
+
+// Tn = min_i te_i (two stages)
+__global__ __launch_bounds__(kRedThreads) void k_block_tn_partial(BlockArgs B)
+{
+    int64_t mn = INT64_MAX;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < B.n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        mn = B.te[k] < mn ? B.te[k] : mn;
+    __shared__ int64_t sh[kRedThreads];
+    sh[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s && sh[threadIdx.x + s] < sh[threadIdx.x])
+            sh[threadIdx.x] = sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) B.part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_block_tn_final(BlockArgs B, int nb)
+{
+    __shared__ int64_t sh[kRedThreads];
+    int64_t mn = INT64_MAX;
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) mn = B.part[b] < mn ? B.part[b] : mn;
+    sh[threadIdx.x] = mn;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s && sh[threadIdx.x + s] < sh[threadIdx.x])
+            sh[threadIdx.x] = sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        B.clk->Tn = sh[0];
+        B.clk->active = 0;
+    }
+}
+
+// every particle drifts with its half-step velocity to the end of the sub-step
+__global__ __launch_bounds__(256) void k_block_drift(BlockArgs B)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= B.n) return;
+    const double dlt = (double)(B.clk->Tn - B.clk->T) * B.clk->tick;
+    double *pos[3] = {B.x, B.y, B.z};
+    const double vel[3] = {B.vhx[k], B.vhy[k], B.vhz[k]};
+    for (int a = 0; a < 3; a++) {
+        double q = pos[a][k] + dlt * vel[a];
+        if (B.box.periodic) {
+            if (q >= B.box.lo[a] + B.box.len[a]) q -= B.box.len[a];
+            else if (q < B.box.lo[a]) q += B.box.len[a];
+        }
+        pos[a][k] = q;
+    }
+}
+
+// predictors at the end of the sub-step, the active set, limiter scratch
+__global__ __launch_bounds__(256) void k_block_predict(BlockArgs B)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= B.n) return;
+    const int64_t Tn = B.clk->Tn;
+    const double dm = ((double)Tn - 0.5 * (double)(B.ts[k] + B.te[k])) * B.clk->tick;
+    B.vpx[k] = B.vhx[k] + B.ax[k] * dm;
+    B.vpy[k] = B.vhy[k] + B.ay[k] * dm;
+    B.vpz[k] = B.vhz[k] + B.az[k] * dm;
+    B.up[k] = B.uh[k] + B.du[k] * dm;
+    B.act[k] = B.te[k] == Tn ? 1 : 0;
+    B.lmx[k] = 0;
+    B.mark[k] = -1;
+}
+
+// active particles per leaf (the pair loops skip leaves without any)
+__global__ __launch_bounds__(256) void k_leaf_active(BlockArgs B)
+{
+    const int64_t L = B.tree->cnt[0];
+    int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int cnt = 0;
+    if (l < L)
+        for (uint32_t i = B.lstart[l]; i < B.lstart[l + 1]; i++) cnt += B.act[i];
+    if (l < L) B.leaf_act[l] = cnt;
+    // the clock's count of active particles
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd((unsigned long long *)&B.clk->active,
+                                                  (unsigned long long)cnt);
+}
+
+// closing kick of the active particles with their new accelerations
+__global__ __launch_bounds__(256) void k_block_close(BlockArgs B)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= B.n || !B.act[k]) return;
+    const double hs = 0.5 * (double)(B.te[k] - B.ts[k]) * B.clk->tick;
+    B.vx[k] = B.vhx[k] + B.ax[k] * hs;
+    B.vy[k] = B.vhy[k] + B.ay[k] * hs;
+    B.vz[k] = B.vhz[k] + B.az[k] * hs;
+    B.u[k] = B.uh[k] + B.du[k] * hs;
+}
+
+// range of the CFL steps (every particle is active at a full synchronisation)
+__global__ __launch_bounds__(kRedThreads) void k_block_dt_partial(BlockArgs B)
+{
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < B.n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        lo = fmin(lo, B.dt[k]);
+        hi = fmax(hi, B.dt[k]);
+    }
+    __shared__ double sl[kRedThreads], sh[kRedThreads];
+    sl[threadIdx.x] = lo;
+    sh[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sl[threadIdx.x] = fmin(sl[threadIdx.x], sl[threadIdx.x + s]);
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *pd = (double *)B.part;
+        pd[2 * blockIdx.x] = sl[0];
+        pd[2 * blockIdx.x + 1] = sh[0];
+    }
+}
+
+// at a full synchronisation (or at the start): dt_max = min dt 2^k, k the
+// largest integer keeping it <= max dt, and its tick length
+__global__ __launch_bounds__(kRedThreads) void k_block_dt_final(BlockArgs B, int nb, bool init)
+{
+    __shared__ double sl[kRedThreads], sh[kRedThreads];
+    const double *pd = (const double *)B.part;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int b = threadIdx.x; b < nb; b += kRedThreads) {
+        lo = fmin(lo, pd[2 * b]);
+        hi = fmax(hi, pd[2 * b + 1]);
+    }
+    sl[threadIdx.x] = lo;
+    sh[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sl[threadIdx.x] = fmin(sl[threadIdx.x], sl[threadIdx.x + s]);
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t P0 = (int64_t)1 << B.lmax;
+        if (init || B.clk->Tn == P0) {
+            int k = 0;
+            while (k < 1000 && ldexp(sl[0], k + 1) <= sh[0]) k++;
+            const double dtm = ldexp(sl[0], k);
+            B.clk->dt_max_next = dtm;
+            B.clk->tick_next = dtm / (double)P0;
+        }
+    }
+}
+
+// new levels and steps of the active particles (fresh at a full
+// synchronisation, else deeper at once or one shallower when synchronised;
+// never shallower than the deepest neighbour minus lim), reactive wake-up of
+// marked inactive particles, opening kicks of the active particles
+__global__ __launch_bounds__(256) void k_block_levels(BlockArgs B, bool init)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= B.n) return;
+    const int64_t P0 = (int64_t)1 << B.lmax;
+    const int64_t Tn = init ? 0 : B.clk->Tn;
+    const bool full = init || Tn == P0;
+    const int lim = B.lim;
+    if (init || B.act[k]) {
+        const double dtm = full ? B.clk->dt_max_next : B.clk->dt_max;
+        int l = block_level_of(B.dt[k], dtm, B.lmax);
+        bool bad = l < 0;
+        int64_t nl;
+        if (full) {
+            nl = l;
+            if (!init && nl < (int64_t)B.lmx[k] - lim) nl = (int64_t)B.lmx[k] - lim;
+        } else {
+            const int64_t cur = B.lev[k];
+            if (l > cur) nl = l;
+            else if (l < cur && Tn % (P0 >> (cur - 1)) == 0) nl = cur - 1;
+            else nl = cur;
+            if (nl < (int64_t)B.lmx[k] - lim) nl = (int64_t)B.lmx[k] - lim;
+        }
+        if (bad || nl > B.lmax) {
+            atomicOr(&B.status[0], kFlagLevel);
+            nl = B.lmax;
+        }
+        const int64_t t0 = full ? 0 : Tn;
+        B.lev[k] = (int32_t)nl;
+        B.ts[k] = t0;
+        B.te[k] = t0 + (P0 >> nl);
+        const double hs = 0.5 * (double)(P0 >> nl) * (full ? B.clk->tick_next : B.clk->tick);
+        B.vhx[k] = B.vx[k] + B.ax[k] * hs;
+        B.vhy[k] = B.vy[k] + B.ay[k] * hs;
+        B.vhz[k] = B.vz[k] + B.az[k] * hs;
+        B.uh[k] = B.u[k] + B.du[k] * hs;
+    } else if (!full && B.mark[k] >= 0 && B.lev[k] < B.mark[k] - lim) {
+        int64_t nl = B.mark[k] - lim;
+        if (nl > B.lmax) {
+            atomicOr(&B.status[0], kFlagLevel);
+            nl = B.lmax;
+        }
+        const int64_t st = P0 >> nl;
+        const int64_t tn = (Tn / st + 1) * st;
+        const double cut = 0.5 * (double)((B.te[k] - B.ts[k]) - (tn - B.ts[k])) * B.clk->tick;
+        B.vhx[k] -= B.ax[k] * cut;
+        B.vhy[k] -= B.ay[k] * cut;
+        B.vhz[k] -= B.az[k] * cut;
+        B.uh[k] -= B.du[k] * cut;
+        B.lev[k] = (int32_t)nl;
+        B.te[k] = tn;
+    }
+}
+
+// the clock moves to the end of the sub-step (one thread)
+__global__ void k_block_advance(BlockArgs B, bool init)
+{
+    BlockClock &C = *B.clk;
+    const int64_t P0 = (int64_t)1 << B.lmax;
+    if (init) {
+        C.T = 0;
+        C.full = 0;
+        C.nsub = 0;
+        C.updates = 0;
+        C.time = 0.0;
+        C.tick = C.tick_next;
+        C.dt_max = C.dt_max_next;
+        return;
+    }
+    C.time += (double)(C.Tn - C.T) * C.tick;
+    C.nsub += 1;
+    C.updates += C.active;
+    if (C.Tn == P0) {
+        C.full += 1;
+        C.T = 0;
+        C.tick = C.tick_next;
+        C.dt_max = C.dt_max_next;
+    } else {
+        C.T = C.Tn;
+    }
+}
+
+BlockArgs block_args(sph_ctx *c, int64_t n)
+{
+    BlockArgs B{};
+    B.n = n;
+    B.box = c->box;
+    B.lmax = c->p.block_lmax;
+    B.lim = c->p.block_lim;
+    B.clk = c->d_clock;
+    B.status = c->d_status;
+    Sorted &S = c->s;
+    B.x = S.x; B.y = S.y; B.z = S.z;
+    B.vx = S.vx; B.vy = S.vy; B.vz = S.vz; B.u = S.u;
+    B.vhx = S.vhx; B.vhy = S.vhy; B.vhz = S.vhz; B.uh = S.uh;
+    B.vpx = S.vpx; B.vpy = S.vpy; B.vpz = S.vpz; B.up = S.up;
+    B.ax = S.ax; B.ay = S.ay; B.az = S.az; B.du = S.du; B.dt = S.dt;
+    B.lev = S.lev; B.ts = S.ts; B.te = S.te;
+    B.act = S.act; B.lmx = S.lmx; B.mark = S.mark;
+    B.lstart = c->lstart;
+    B.tree = c->d_tree;
+    B.leaf_act = c->leaf_act;
+    B.part = (int64_t *)c->d_part;
+    return B;
+}
+
+} // namespace
+
+sph_status block_next(sph_ctx *c, int64_t n)
+{
+    BlockArgs B = block_args(c, n);
+    const int nb = (int)std::min<int64_t>(kRedBlocks / 2, (n + kRedThreads - 1) / kRedThreads);
+    hipLaunchKernelGGL(k_block_tn_partial, dim3(nb), dim3(kRedThreads), 0, c->stream, B);
+    hipLaunchKernelGGL(k_block_tn_final, dim3(1), dim3(kRedThreads), 0, c->stream, B, nb);
+    hipLaunchKernelGGL(k_block_drift, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, B);
+    return hip_check(c, hipGetLastError(), "block_next");
+}
+
+sph_status block_predict(sph_ctx *c, int64_t n)
+{
+    BlockArgs B = block_args(c, n);
+    hipLaunchKernelGGL(k_block_predict, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, B);
+    // leaves: at most n
+    hipLaunchKernelGGL(k_leaf_active, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, B);
+    return hip_check(c, hipGetLastError(), "block_predict");
+}
+
+sph_status block_finish(sph_ctx *c, int64_t n, bool init)
+{
+    BlockArgs B = block_args(c, n);
+    const unsigned g = grid_for(n, 256);
+    if (!init) hipLaunchKernelGGL(k_block_close, dim3(g), dim3(256), 0, c->stream, B);
+    const int nb = (int)std::min<int64_t>(kRedBlocks / 2, (n + kRedThreads - 1) / kRedThreads);
+    hipLaunchKernelGGL(k_block_dt_partial, dim3(nb), dim3(kRedThreads), 0, c->stream, B);
+    hipLaunchKernelGGL(k_block_dt_final, dim3(1), dim3(kRedThreads), 0, c->stream, B, nb, init);
+    hipLaunchKernelGGL(k_block_levels, dim3(g), dim3(256), 0, c->stream, B, init);
+    hipLaunchKernelGGL(k_block_advance, dim3(1), dim3(1), 0, c->stream, B, init);
+    return hip_check(c, hipGetLastError(), "block_finish");
+}
+
 sph_status fill(sph_ctx *c, int64_t n, double *v, double value)
 {
     if (n == 0) return SPH_OK;

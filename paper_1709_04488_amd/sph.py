@@ -18,13 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libsph.so")
 
 SPH_OK, SPH_EINVAL, SPH_ENOMEM, SPH_EDEVICE, SPH_ENOTCONVERGED = 0, -1, -2, -3, -4
 SPH_ESTENCIL, SPH_ENONFINITE, SPH_EBUDGET, SPH_ECAP, SPH_ESTATE = -5, -6, -7, -8, -9
+SPH_ELEVEL = -10
 SPH_FP64, SPH_FP32_PAIR = 0, 1
 SPH_AC_WADSLEY, SPH_AC_PRICE = 0, 1
 SPH_AV_NONE, SPH_AV_MM97, SPH_AV_CD10 = 0, 1, 2
 
 STATUS_NAMES = {0: "SPH_OK", -1: "SPH_EINVAL", -2: "SPH_ENOMEM", -3: "SPH_EDEVICE",
                 -4: "SPH_ENOTCONVERGED", -5: "SPH_ESTENCIL", -6: "SPH_ENONFINITE",
-                -7: "SPH_EBUDGET", -8: "SPH_ECAP", -9: "SPH_ESTATE"}
+                -7: "SPH_EBUDGET", -8: "SPH_ECAP", -9: "SPH_ESTATE", -10: "SPH_ELEVEL"}
 
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream", "sph_set_params",
             "sph_build_cells", "sph_density", "sph_forces", "sph_evaluate", "sph_upload_state",
@@ -34,7 +35,7 @@ EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream",
             "sph_batch_density", "sph_batch_forces", "sph_batch_evaluate", "sph_batch_step",
             "sph_capture_steps",
             "sph_replay_steps", "sph_plan_bytes", "sph_evaluate_noalloc", "sph_noalloc_max_n",
-            "sph_mfv_gradients"]
+            "sph_mfv_gradients", "sph_substep"]
 
 
 class SphError(RuntimeError):
@@ -52,7 +53,8 @@ class _Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("leaf_size", ctypes.c_int32),
                 ("alpha_ac", ctypes.c_double), ("ac_signal", ctypes.c_int32),
                 ("av_switch", ctypes.c_int32), ("alpha_min", ctypes.c_double),
-                ("alpha_max", ctypes.c_double), ("av_ell", ctypes.c_double)]
+                ("alpha_max", ctypes.c_double), ("av_ell", ctypes.c_double),
+                ("block_lmax", ctypes.c_int32), ("block_lim", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -62,7 +64,8 @@ _I = ctypes.POINTER(ctypes.c_int32)
 class _Particles(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in (
         "x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "rho", "omega", "pressure", "cs",
-        "ax", "ay", "az", "dudt", "vsig", "dt", "nngb", "nforce", "alpha", "divv", "curlv")]
+        "ax", "ay", "az", "dudt", "vsig", "dt", "nngb", "nforce", "alpha", "divv", "curlv",
+        "level")]
 
 
 class _MfvSet(ctypes.Structure):
@@ -85,7 +88,11 @@ class _Stats(ctypes.Structure):
                 ("dens_candidate_tests", ctypes.c_int64), ("dens_box_tests", ctypes.c_int64),
                 ("force_candidate_tests", ctypes.c_int64), ("force_box_tests", ctypes.c_int64),
                 ("density_walk_overflows", ctypes.c_int32), ("force_walk_overflows", ctypes.c_int32),
-                ("dens_list_overflows", ctypes.c_int64)]
+                ("dens_list_overflows", ctypes.c_int64),
+                ("block_full_steps", ctypes.c_int64), ("block_substeps", ctypes.c_int64),
+                ("block_active", ctypes.c_int64), ("block_updates", ctypes.c_int64),
+                ("block_time", ctypes.c_double), ("block_dt_max", ctypes.c_double),
+                ("block_synchronised", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 _lib = None
@@ -136,6 +143,7 @@ def load() -> ctypes.CDLL:
         "sph_evaluate_noalloc": (ctypes.c_int, [vp, PS]),
         "sph_noalloc_max_n": (i64, []),
         "sph_mfv_gradients": (ctypes.c_int, [vp, ctypes.POINTER(_MfvSet)]),
+        "sph_substep": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -166,11 +174,14 @@ class Params:
     alpha_min: float = 0.1
     alpha_max: float = 1.0
     av_ell: float = 0.0
+    block_lmax: int = 0
+    block_lim: int = 2
 
     @classmethod
     def from_setup(cls, setup: dict, **kw) -> "Params":
         keys = ("eta", "gamma", "alpha", "beta", "ccfl", "periodic", "lo", "hi", "alpha_ac",
-                "ac_signal", "av_switch", "alpha_min", "alpha_max", "av_ell")
+                "ac_signal", "av_switch", "alpha_min", "alpha_max", "av_ell", "block_lmax",
+                "block_lim")
         return cls(**{k: setup[k] for k in keys if k in setup}, **kw)
 
     def c(self) -> _Params:
@@ -189,13 +200,14 @@ class Params:
         p.av_switch = int(self.av_switch)
         p.alpha_min, p.alpha_max = float(self.alpha_min), float(self.alpha_max)
         p.av_ell = float(self.av_ell)
+        p.block_lmax, p.block_lim = int(self.block_lmax), int(self.block_lim)
         return p
 
 
 FIELDS_F64 = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "h", "rho", "omega", "pressure", "cs",
               "ax", "ay", "az", "dudt", "vsig", "dt")
 # optional arrays (after nngb/nforce in the C struct): only passed when present
-FIELDS_OPT = ("alpha", "divv", "curlv")
+FIELDS_OPT = ("alpha", "divv", "curlv", "level")
 FIELDS_I32 = ("nngb", "nforce")
 
 
@@ -236,11 +248,16 @@ class Particles:
                 continue
             if not v.is_cuda:
                 raise ValueError(f"{k} must be a GPU tensor")
-            want = torch.int32 if k in FIELDS_I32 else torch.float64
+            want = torch.int32 if k in FIELDS_I32 + ("level",) else torch.float64
             if v.dtype != want or not v.is_contiguous() or v.numel() != ps.n:
                 raise ValueError(f"{k} must be a contiguous {want} tensor of {ps.n} elements")
             setattr(ps, k, v.data_ptr())
         return ps
+
+    def with_level(self) -> "Particles":
+        """Also request the time-step levels (sph_download_state)."""
+        self.t["level"] = torch.zeros(self.n, dtype=torch.int32, device=self.t["x"].device)
+        return self
 
     def with_divv(self) -> "Particles":
         """Also request the velocity divergence and curl outputs."""
@@ -361,6 +378,10 @@ class Context:
         ps = p.c()
         self._check(self.lib.sph_upload_state(self.h, ctypes.byref(ps)), "sph_upload_state")
 
+    def substep(self):
+        """One block time-step sub-step (sph_substep)."""
+        self._check(self.lib.sph_substep(self.h), "sph_substep")
+
     def step(self, dt: float = 0.0):
         self._check(self.lib.sph_step(self.h, float(dt), None), "sph_step")
 
@@ -393,7 +414,11 @@ class Context:
                 "force_box_tests": st.force_box_tests,
                 "density_walk_overflows": st.density_walk_overflows,
                 "force_walk_overflows": st.force_walk_overflows,
-                "dens_list_overflows": st.dens_list_overflows}
+                "dens_list_overflows": st.dens_list_overflows,
+                "block_full_steps": st.block_full_steps, "block_substeps": st.block_substeps,
+                "block_active": st.block_active, "block_updates": st.block_updates,
+                "block_time": st.block_time, "block_dt_max": st.block_dt_max,
+                "block_synchronised": st.block_synchronised}
 
     def neighbours(self, p: Particles, mode: int, cap: int = None):
         """CSR lists at the given h -> (offsets int64[n+1], idx int32) on the device."""

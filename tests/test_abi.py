@@ -63,11 +63,11 @@ def test_struct_layouts_match_header():
     from paper_1709_04488_amd import sph
     # ... + alpha_ac, ac_signal, av_switch (filling the old tail padding),
     # alpha_min, alpha_max, av_ell
-    assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4 + 8 + 4 + 4 + 3 * 8
-    # ... + the optional alpha, divv, curlv
-    assert ctypes.sizeof(sph._Particles) == 8 + 24 * 8
+    assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4 + 8 + 4 + 4 + 3 * 8 + 2 * 4
+    # ... + the optional alpha, divv, curlv, level
+    assert ctypes.sizeof(sph._Particles) == 8 + 25 * 8
     # ... + the density and force walk overflows (2 x int32) and the list overflows
-    assert ctypes.sizeof(sph._Stats) == 8 * 8 + 5 * 8 + 8 + 2 * 8 + 5 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(sph._Stats) == 8 * 8 + 5 * 8 + 8 + 2 * 8 + 5 * 8 + 2 * 4 + 8 + 6 * 8 + 8
 
 
 def test_struct_offsets_match_the_c_compiler(tmp_path):
