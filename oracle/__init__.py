@@ -9,7 +9,9 @@ arrays in and out.
 
 Functions and the passages they follow (GANDALF paper, arXiv:1709.04488):
 
-* ``kernel_f/df/W/dWdr/dWdh`` -- M4 cubic spline, R = 2 (section 2).
+* ``kernel_f/df/W/dWdr/dWdh`` -- M4 cubic spline, R = 2 (section 2);
+  ``quintic_f/df`` -- the quintic spline, R = 3 (section 2), chosen for every
+  sum by ``Params.kernel``.
 * ``density``    -- eqs. EQN:SPHRHO, EQN:HRHO, EQN:OMEGA (section 2.1.1).
 * ``eos``        -- ideal gas P = (gamma-1) rho u (below EQN:GRADHMOMEQN).
 * ``forces``     -- eqs. EQN:GRADHMOMEQN, EQN:GRADHENEQN, EQN:MON97ARTVISC,
@@ -74,7 +76,7 @@ def _load():
         build(force=False)
         lib = ctypes.CDLL(_LIB)
         d, i64, i32, vp = ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
-        for name in ("orc_f", "orc_df"):
+        for name in ("orc_f", "orc_df", "orc_quintic_f", "orc_quintic_df"):
             getattr(lib, name).restype = d
             getattr(lib, name).argtypes = [d]
         for name in ("orc_W", "orc_dWdr", "orc_dWdh"):
@@ -113,9 +115,11 @@ class _CParams(ctypes.Structure):
                 ("hi", ctypes.c_double * 3), ("alpha_ac", ctypes.c_double),
                 ("av_switch", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
-                ("av_ell", ctypes.c_double)]
+                ("av_ell", ctypes.c_double), ("kernel", ctypes.c_int32),
+                ("pad2_", ctypes.c_int32)]
 
 AV_NONE, AV_MM97, AV_CD10 = 0, 1, 2
+KERNEL_M4, KERNEL_QUINTIC = 0, 1
 # published decay constants: MM97 tau = h/(0.1 c); CD10 tau = h/(2 0.05 v_sig)
 AV_ELL_DEFAULT = {AV_MM97: 0.1, AV_CD10: 0.05}
 
@@ -142,6 +146,11 @@ class Params:
     alpha_min: float = 0.1
     alpha_max: float = 1.0
     av_ell: float = 0.0         # 0: the switch's published value
+    kernel: int = 0             # KERNEL_M4 (R = 2) or KERNEL_QUINTIC (R = 3)
+
+    def support(self) -> float:
+        """The kernel's support radius in units of h (section 2)."""
+        return 3.0 if self.kernel == KERNEL_QUINTIC else 2.0
 
     def c(self) -> _CParams:
         p = _CParams()
@@ -152,6 +161,7 @@ class Params:
         p.av_switch = int(self.av_switch)
         p.alpha_min, p.alpha_max = float(self.alpha_min), float(self.alpha_max)
         p.av_ell = float(self.av_ell) if self.av_ell > 0.0 else AV_ELL_DEFAULT.get(self.av_switch, 0.0)
+        p.kernel = int(self.kernel)
         for k in range(3):
             p.lo[k] = float(self.lo[k])
             p.hi[k] = float(self.hi[k])
@@ -190,6 +200,15 @@ def kernel_dWdr(r: float, h: float) -> float:
 
 def kernel_dWdh(r: float, h: float) -> float:
     return _load().orc_dWdh(float(r), float(h))
+
+
+def quintic_f(q: float) -> float:
+    """Quintic spline shape (Morris 1996), support R = 3 (section 2)."""
+    return _load().orc_quintic_f(float(q))
+
+
+def quintic_df(q: float) -> float:
+    return _load().orc_quintic_df(float(q))
 
 
 # --- density, EOS, forces -----------------------------------------------------
@@ -426,13 +445,14 @@ def _local_density(params: Params, x, y, z, m, hg, d2, targets, Rs):
     centre whose squared distances are ``d2``.  The solver only evaluates
     smoothing lengths up to max(guess, 2 root); once the support of every such
     h lies inside the sub-set, every sum it formed equals the sum over all N
-    (the kernel vanishes beyond 2h), so the result is the full-set result."""
+    (the kernel vanishes beyond R h), so the result is the full-set result."""
     r_t = np.sqrt(d2[targets])
+    Rk = params.support()
     while True:
         sub = np.nonzero(d2 < Rs * Rs)[0]
         dd = density(params, x[sub], y[sub], z[sub], m[sub], hg[sub],
                      sel=np.searchsorted(sub, targets))
-        need = r_t + 2.0 * np.maximum(hg[targets], 2.0 * dd["h"])
+        need = r_t + Rk * np.maximum(hg[targets], 2.0 * dd["h"])
         if np.all(need < Rs):
             return dd
         Rs = float(np.max(need)) * 1.5
@@ -444,11 +464,12 @@ def sampled_evaluation(params: Params, arrays: dict, sample, force_sample=None,
 
     Density, h, omega, P, c for every particle of ``sample`` (each h is the
     root of its own h-rho relation over all N particles); forces, du/dt,
-    v_sig and dt for ``force_sample`` (default: ``sample``).  Forces on i need
-    h, rho, omega of every j with r_ij < 2 max(h_i, h_j); those j are found by
+    v_sig and dt for ``force_sample`` (default: ``sample``).  With the kernel's
+    support radius Rk (2 for M4, 3 for the quintic), forces on i need h, rho,
+    omega of every j with r_ij < Rk max(h_i, h_j); those j are found by
     growing a radius R around i until every particle inside R has
-    2 h_j <= R, and by also solving exactly every particle whose input guess
-    would reach i with 25 % to spare (2.5 h_guess_j > r_ij).  The guesses
+    Rk h_j <= R, and by also solving exactly every particle whose input guess
+    would reach i with 25 % to spare (1.25 Rk h_guess_j > r_ij).  The guesses
     only choose which particles get an exact root; they never enter a sum.
     This closure assumes that no other particle has a smoothing length larger
     than half its distance to i, which holds for the smooth density fields of
@@ -462,6 +483,7 @@ def sampled_evaluation(params: Params, arrays: dict, sample, force_sample=None,
     sample = np.asarray(sample, dtype=np.int64)
     fsample = sample if force_sample is None else np.asarray(force_sample, dtype=np.int64)
     res = SampledResult(sample=sample, force_sample=fsample)
+    Rk = params.support()
 
     d = density(params, x, y, z, m, hg, sel=sample)
     P, c = eos(params.gamma, d["rho"], u[sample])
@@ -479,15 +501,15 @@ def sampled_evaluation(params: Params, arrays: dict, sample, force_sample=None,
         d2 = _min_image_dist2(params, x, y, z, x[i], y[i], z[i])
         if i not in known:
             di = _local_density(params, x, y, z, m, hg, d2, np.array([i]),
-                                8.0 * float(hg[i]))
+                                4.0 * Rk * float(hg[i]))
             known[i] = (float(di["h"][0]), float(di["rho"][0]), float(di["omega"][0]))
-        R = 2.0 * known[i][0]
-        reach = d2 < (2.5 * hg) ** 2
+        R = Rk * known[i][0]
+        reach = d2 < (1.25 * Rk * hg) ** 2
         for _ in range(64):
             inside = np.nonzero((d2 < R * R) | reach)[0]
             todo = np.array([j for j in inside.tolist() if j not in known], dtype=np.int64)
             if todo.size:
-                Rs = float(np.sqrt(np.max(d2[todo]))) + 8.0 * max(float(np.max(hg[todo])),
+                Rs = float(np.sqrt(np.max(d2[todo]))) + 4.0 * Rk * max(float(np.max(hg[todo])),
                                                                   known[i][0])
                 dd = _local_density(params, x, y, z, m, hg, d2, todo, Rs)
                 for j, hh, rr, oo in zip(todo.tolist(), dd["h"].tolist(), dd["rho"].tolist(),
@@ -495,9 +517,9 @@ def sampled_evaluation(params: Params, arrays: dict, sample, force_sample=None,
                     known[j] = (hh, rr, oo)
             core = np.nonzero(d2 < R * R)[0]
             hmax = max(known[j][0] for j in core.tolist())
-            if 2.0 * hmax <= R:
+            if Rk * hmax <= R:
                 break
-            R = 2.0 * hmax * (1.0 + 1e-7)
+            R = Rk * hmax * (1.0 + 1e-7)
         else:
             raise OracleError(ORC_ENOROOT, "sampled closure")
         hs = np.array([known[j][0] for j in inside.tolist()])

@@ -12,9 +12,10 @@
  * Every sum runs over all particles j = 1..N in index order, with no cells,
  * no trees and no reordering.  The only shortcut is exact: once a bracket
  * [h_lo, h_hi] on the smoothing length is known, particles with
- * r_ij >= 2 h_hi are dropped from the list used by the bisection, because the
- * M4 kernel vanishes identically beyond 2h (compact support R h with R = 2,
- * section 2); adding those zero terms would not change a single bit.
+ * r_ij >= R h_hi are dropped from the list used by the bisection, because the
+ * kernel vanishes identically beyond R h (compact support, R = 2 for the M4
+ * and 3 for the quintic spline, section 2); adding those zero terms would not
+ * change a single bit.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no FMA
  * contraction, so every product and sum is rounded as written).
@@ -29,7 +30,7 @@
 #define ORC_EINVAL -1
 #define ORC_ENOMEM -2
 #define ORC_ENOROOT -4   /* no smoothing length satisfies the h-rho relation */
-#define ORC_EBOX -5      /* periodic: the root needs 2h >= L/2 */
+#define ORC_EBOX -5      /* periodic: the root needs R h >= L/2 */
 #define ORC_ECAP -8      /* neighbour export: caller's capacity too small */
 
 typedef struct {
@@ -48,6 +49,8 @@ typedef struct {
     int32_t pad_;
     double alpha_min, alpha_max; /* floor and ceiling of the per-particle alpha */
     double av_ell;   /* decay constant: tau = h/(ell c) (MM97), h/(2 ell v_sig) (CD10) */
+    int32_t kernel;  /* 0: M4 cubic spline (R = 2), 1: quintic spline (R = 3) */
+    int32_t pad2_;
 } orc_params;
 
 /* ---------------------------------------------------------------------------
@@ -92,6 +95,55 @@ double orc_dWdh(double r, double h)
 {
     double q = r / h;
     return -ORC_SIGMA / (h * h * h * h) * (3.0 * orc_f(q) + q * orc_df(q));
+}
+
+/* ---------------------------------------------------------------------------
+ * Quintic spline (Morris 1996), compact support 3h, the paper's second
+ * kernel (section 2).  In B-spline form with a = (3-q)_+, b = (2-q)_+,
+ * c = (1-q)_+:
+ *   f(q)  = a^5 - 6 b^5 + 15 c^5
+ *   f'(q) = -5 a^4 + 30 b^4 - 75 c^4
+ * and 3D normalisation sigma = 1/(120 pi) (4 pi sigma int_0^3 f q^2 dq = 1).
+ * ------------------------------------------------------------------------- */
+static const double ORC_SIGMA_Q = 0.0026525823848649222; /* 1/(120 pi) */
+
+double orc_quintic_f(double q)
+{
+    double a = q < 3.0 ? 3.0 - q : 0.0, b = q < 2.0 ? 2.0 - q : 0.0, c = q < 1.0 ? 1.0 - q : 0.0;
+    double a2 = a * a, b2 = b * b, c2 = c * c;
+    return a2 * a2 * a - 6.0 * (b2 * b2 * b) + 15.0 * (c2 * c2 * c);
+}
+
+double orc_quintic_df(double q)
+{
+    double a = q < 3.0 ? 3.0 - q : 0.0, b = q < 2.0 ? 2.0 - q : 0.0, c = q < 1.0 ? 1.0 - q : 0.0;
+    double a2 = a * a, b2 = b * b, c2 = c * c;
+    return -5.0 * (a2 * a2) + 30.0 * (b2 * b2) - 75.0 * (c2 * c2);
+}
+
+/* the kernel of the parameters: support R (in units of h), shape, 3D norm */
+static inline double supp(const orc_params *p) { return p->kernel == 1 ? 3.0 : 2.0; }
+static inline double kf(const orc_params *p, double q)
+{
+    return p->kernel == 1 ? orc_quintic_f(q) : orc_f(q);
+}
+static inline double kdf(const orc_params *p, double q)
+{
+    return p->kernel == 1 ? orc_quintic_df(q) : orc_df(q);
+}
+static inline double ksig(const orc_params *p) { return p->kernel == 1 ? ORC_SIGMA_Q : ORC_SIGMA; }
+static inline double kW(const orc_params *p, double r, double h)
+{
+    return ksig(p) / (h * h * h) * kf(p, r / h);
+}
+static inline double kdWdr(const orc_params *p, double r, double h)
+{
+    return ksig(p) / (h * h * h * h) * kdf(p, r / h);
+}
+static inline double kdWdh(const orc_params *p, double r, double h)
+{
+    double q = r / h;
+    return -ksig(p) / (h * h * h * h) * (3.0 * kf(p, q) + q * kdf(p, q));
 }
 
 /* ---------------------------------------------------------------------------
@@ -149,19 +201,19 @@ typedef struct { double r; double m; } orc_nb;
 static double g_full(const orc_params *p, int64_t n, const double *x, const double *y,
                      const double *z, const double *m, int64_t i, double h)
 {
-    double s = 0.0, h2x4 = (2.0 * h) * (2.0 * h);
+    double s = 0.0, h2x4 = (supp(p) * h) * (supp(p) * h);
     for (int64_t j = 0; j < n; j++) {
         double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
-        if (r2 < h2x4) s += m[j] * orc_f(sqrt(r2) / h);
+        if (r2 < h2x4) s += m[j] * kf(p, sqrt(r2) / h);
     }
-    return ORC_SIGMA * s - p->eta * p->eta * p->eta * m[i];
+    return ksig(p) * s - p->eta * p->eta * p->eta * m[i];
 }
 
 static double g_list(const orc_params *p, const orc_nb *nb, int64_t k, double mi, double h)
 {
     double s = 0.0;
-    for (int64_t a = 0; a < k; a++) s += nb[a].m * orc_f(nb[a].r / h);
-    return ORC_SIGMA * s - p->eta * p->eta * p->eta * mi;
+    for (int64_t a = 0; a < k; a++) s += nb[a].m * kf(p, nb[a].r / h);
+    return ksig(p) * s - p->eta * p->eta * p->eta * mi;
 }
 
 /* Solve for one particle; fills h, rho, rho' (= sum m dW/dh), omega, nngb. */
@@ -179,7 +231,7 @@ static int solve_one(const orc_params *p, int64_t n, const double *x, const doub
         while (g_full(p, n, x, y, z, m, i, hi) < 0.0) {
             lo = hi; hi *= 2.0;
             if (++it > 80) return ORC_ENOROOT;
-            if (p->periodic && 4.0 * lo >= min_box_len(p)) return ORC_EBOX;
+            if (p->periodic && 2.0 * supp(p) * lo >= min_box_len(p)) return ORC_EBOX;
         }
     } else {
         hi = hguess; lo = 0.5 * hguess;
@@ -191,7 +243,7 @@ static int solve_one(const orc_params *p, int64_t n, const double *x, const doub
     }
     /* Exact pruning: only j with r_ij < 2 hi can contribute for h <= hi. */
     int64_t k = 0;
-    double lim = (2.0 * hi) * (2.0 * hi);
+    double lim = (supp(p) * hi) * (supp(p) * hi);
     for (int64_t j = 0; j < n; j++) {
         double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
         if (r2 < lim) { nb[k].r = sqrt(r2); nb[k].m = m[j]; k++; }
@@ -203,17 +255,17 @@ static int solve_one(const orc_params *p, int64_t n, const double *x, const doub
         if (g_list(p, nb, k, m[i], mid) < 0.0) lo = mid; else hi = mid;
     }
     double h = lo + 0.5 * (hi - lo);
-    if (p->periodic && 4.0 * h >= min_box_len(p)) return ORC_EBOX;
+    if (p->periodic && 2.0 * supp(p) * h >= min_box_len(p)) return ORC_EBOX;
 
     double rho = 0.0, drho = 0.0;
     int32_t cnt = 0;
-    double h2x4 = (2.0 * h) * (2.0 * h);
+    double h2x4 = (supp(p) * h) * (supp(p) * h);
     for (int64_t j = 0; j < n; j++) {
         double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
         if (r2 < h2x4) {
             double r = sqrt(r2);
-            rho += m[j] * orc_W(r, h);
-            drho += m[j] * orc_dWdh(r, h);
+            rho += m[j] * kW(p, r, h);
+            drho += m[j] * kdWdh(p, r, h);
             if (j != i) cnt++;
         }
     }
@@ -273,13 +325,13 @@ int orc_rho_at(const orc_params *p, int64_t n, const double *x, const double *y,
         int64_t i = sel ? sel[k] : k;
         double h = hsel[k], r0 = 0.0, r1 = 0.0;
         int32_t cnt = 0;
-        double h2x4 = (2.0 * h) * (2.0 * h);
+        double h2x4 = (supp(p) * h) * (supp(p) * h);
         for (int64_t j = 0; j < n; j++) {
             double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
             if (r2 < h2x4) {
                 double r = sqrt(r2);
-                r0 += m[j] * orc_W(r, h);
-                r1 += m[j] * orc_dWdh(r, h);
+                r0 += m[j] * kW(p, r, h);
+                r1 += m[j] * kdWdh(p, r, h);
                 if (j != i) cnt++;
             }
         }
@@ -356,7 +408,7 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
         double Pi = (gam - 1.0) * rho[i] * u[i];
         double ci = sqrt(gam * Pi / rho[i]);
         double Ai = Pi / (omega[i] * rho[i] * rho[i]);
-        double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+        double hi2x4 = (supp(p) * h[i]) * (supp(p) * h[i]);
         double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, sa = 0.0, su = 0.0;
         double vs_max = 2.0 * ci;
         int have_ngb = 0;
@@ -365,7 +417,7 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
         for (int64_t j = 0; j < n; j++) {
             if (j == i) continue;
             double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
-            double hj2x4 = (2.0 * h[j]) * (2.0 * h[j]);
+            double hj2x4 = (supp(p) * h[j]) * (supp(p) * h[j]);
             if (!(r2 < hi2x4 || r2 < hj2x4)) continue;
             cnt++;
             double Pj = (gam - 1.0) * rho[j] * u[j];
@@ -379,8 +431,8 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
             double Aj = Pj / (omega[j] * rho[j] * rho[j]);
             double r = sqrt(r2);
             double ex = dx / r, ey = dy / r, ez = dz / r;
-            double gi = orc_dWdr(r, h[i]);
-            double gj = orc_dWdr(r, h[j]);
+            double gi = kdWdr(p, r, h[i]);
+            double gj = kdWdr(p, r, h[j]);
             double vxij = vx[i] - vx[j], vyij = vy[i] - vy[j], vzij = vz[i] - vz[j];
             double w = (vxij * ex + vyij * ey) + vzij * ez;
             /* pressure term: vector coefficient along rhat */
@@ -496,13 +548,13 @@ int orc_neighbours(const orc_params *p, int64_t n, const double *x, const double
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < nsel; k++) {
         int64_t i = sel ? sel[k] : k;
-        double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+        double hi2x4 = (supp(p) * h[i]) * (supp(p) * h[i]);
         int64_t c = 0;
         for (int64_t j = 0; j < n; j++) {
             if (j == i) continue;
             double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
             int in = r2 < hi2x4;
-            if (mode == 1) in = in || r2 < (2.0 * h[j]) * (2.0 * h[j]);
+            if (mode == 1) in = in || r2 < (supp(p) * h[j]) * (supp(p) * h[j]);
             if (in) c++;
         }
         counts[k] = c;
@@ -518,13 +570,13 @@ int orc_neighbours(const orc_params *p, int64_t n, const double *x, const double
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < nsel; k++) {
         int64_t i = sel ? sel[k] : k;
-        double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+        double hi2x4 = (supp(p) * h[i]) * (supp(p) * h[i]);
         int64_t c = off[k];
         for (int64_t j = 0; j < n; j++) {
             if (j == i) continue;
             double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
             int in = r2 < hi2x4;
-            if (mode == 1) in = in || r2 < (2.0 * h[j]) * (2.0 * h[j]);
+            if (mode == 1) in = in || r2 < (supp(p) * h[j]) * (supp(p) * h[j]);
             if (in) idx[c++] = (int32_t)j;
         }
     }
@@ -717,13 +769,13 @@ int orc_mfv_gradients(const orc_params *p, int64_t n, const double *x, const dou
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < nsel; k++) {
         int64_t i = sel ? sel[k] : k;
-        double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+        double hi2x4 = (supp(p) * h[i]) * (supp(p) * h[i]);
         double E[3][3] = {{0}}, B[3][3];
         for (int64_t j = 0; j < n; j++) {
             double dx, dy, dz, r2 = pair_r2(p, x, y, z, i, j, &dx, &dy, &dz);
             if (!(r2 < hi2x4)) continue;
             double d[3] = {-dx, -dy, -dz};   /* r_j - r_i */
-            double psi = orc_W(sqrt(r2), h[i]) / ndens[i];
+            double psi = kW(p, sqrt(r2), h[i]) / ndens[i];
             for (int a = 0; a < 3; a++)
                 for (int b = 0; b < 3; b++) E[a][b] += d[a] * d[b] * psi;
         }
@@ -745,12 +797,12 @@ int orc_mfv_gradients(const orc_params *p, int64_t n, const double *x, const dou
             double r = sqrt(r2);
             double psit[3];
             if (!sph) {
-                double psi = orc_W(r, h[i]) / ndens[i];
+                double psi = kW(p, r, h[i]) / ndens[i];
                 for (int a = 0; a < 3; a++)
                     psit[a] = (B[a][0] * d[0] + B[a][1] * d[1] + B[a][2] * d[2]) * psi;
             } else {
                 /* V_i grad_i W = (1/n_i) dW/dr (r_i - r_j)/r */
-                double g = orc_dWdr(r, h[i]) / ndens[i] / r;
+                double g = kdWdr(p, r, h[i]) / ndens[i] / r;
                 for (int a = 0; a < 3; a++) psit[a] = -d[a] * g;
             }
             for (int q = 0; q < nfields; q++) {
@@ -929,12 +981,12 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
         /* limiter information over the force neighbours of the active particles */
         for (int64_t k = 0; k < na; k++) {
             int64_t i = sel[k];
-            double hi2x4 = (2.0 * h[i]) * (2.0 * h[i]);
+            double hi2x4 = (supp(p) * h[i]) * (supp(p) * h[i]);
             int64_t mx = 0;
             for (int64_t j = 0; j < n; j++) {
                 if (j == i) continue;
                 double ddx, ddy, ddz, r2 = pair_r2(p, x, y, z, i, j, &ddx, &ddy, &ddz);
-                if (!(r2 < hi2x4 || r2 < (2.0 * h[j]) * (2.0 * h[j]))) continue;
+                if (!(r2 < hi2x4 || r2 < (supp(p) * h[j]) * (supp(p) * h[j]))) continue;
                 if (lev[j] > mx) mx = lev[j];
                 if (te[j] != Tn && lev[j] < lev[i] - lim && lev[i] > mark[j]) mark[j] = lev[i];
             }
