@@ -21,7 +21,12 @@
  *                        and the CFL time-step (eq. EQN:SPH_DT)
  *   time integration  -- kick-drift-kick leapfrog (eqs. EQN:LFKDK1/EQN:LFKDK2)
  *
- * Kernel: M4 cubic spline, support 2h (section 2).
+ * Kernel (section 2 names two, selected by sph_params.kernel): the M4 cubic
+ * spline, support R h with R = 2, W = (1/pi) h^-3 f(r/h),
+ *   f(q) = (2-q)_+^3 / 4 - (1-q)_+^3;
+ * or the quintic spline (Morris 1996), R = 3, W = (1/(120 pi)) h^-3 f(r/h),
+ *   f(q) = (3-q)_+^5 - 6 (2-q)_+^5 + 15 (1-q)_+^5.
+ * "R h" below is that support radius.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -69,7 +74,7 @@ typedef enum {
     SPH_ENOMEM = -2,        /* device allocation failed */
     SPH_EDEVICE = -3,       /* a HIP runtime call failed */
     SPH_ENOTCONVERGED = -4, /* some h_i did not reach h_rtol in h_max_iter steps */
-    SPH_ESTENCIL = -5,      /* periodic box: some 2 h_i >= L/2 (minimum image ambiguous) */
+    SPH_ESTENCIL = -5,      /* periodic box: some R h_i >= L/2 (minimum image ambiguous) */
     SPH_ENONFINITE = -6,    /* a NaN or Inf input or result */
     SPH_EBUDGET = -7,       /* the working set would exceed the HBM budget */
     SPH_ECAP = -8,          /* an output capacity given by the caller is too small */
@@ -85,6 +90,9 @@ enum { SPH_AC_WADSLEY = 0, SPH_AC_PRICE = 1 };
 
 /* artificial-viscosity switch (section 2.1.1 names both) */
 enum { SPH_AV_NONE = 0, SPH_AV_MM97 = 1, SPH_AV_CD10 = 2 };
+
+/* smoothing kernel (section 2): M4 cubic spline (R = 2) or quintic spline (R = 3) */
+enum { SPH_KERNEL_M4 = 0, SPH_KERNEL_QUINTIC = 1 };
 
 /*
  * Method parameters.  Defaults (sph_default_params): eta = 1.2 (section
@@ -159,6 +167,8 @@ typedef struct {
                            time-steps (sph_substep) with at most this many levels */
     int32_t block_lim;  /* block time-step limiter: force neighbours at most this many
                            levels apart (default 2) */
+    int32_t kernel;     /* SPH_KERNEL_M4 (default, R = 2) or SPH_KERNEL_QUINTIC (R = 3) */
+    int32_t pad_;       /* zero */
 } sph_params;
 
 /*
@@ -192,7 +202,7 @@ typedef struct {
     double *dudt;         /* du/dt */
     double *vsig;         /* max signal speed over force neighbours */
     double *dt;           /* per-particle CFL step */
-    int32_t *nngb;        /* density neighbours j != i with r_ij < 2 h_i */
+    int32_t *nngb;        /* density neighbours j != i with r_ij < R h_i */
     int32_t *nforce;      /* force neighbours j != i with r_ij < 2 max(h_i, h_j) */
     double *alpha;        /* optional: per-particle alpha_AV (input; sph_download_state
                              writes the evolved values) */
@@ -420,7 +430,7 @@ typedef struct {
     const double *x, *y, *z;
     double *h;
     double *ndens;            /* n_i */
-    int32_t *nngb;            /* neighbours j != i with r_ij < 2 h_i */
+    int32_t *nngb;            /* neighbours j != i with r_ij < R h_i */
     double *B[6];             /* E^-1: xx, xy, xz, yy, yz, zz */
     double *cond;             /* |E|_F |E^-1|_F / 3 */
     int32_t nfields;          /* 0..4 */
@@ -432,8 +442,8 @@ sph_status sph_mfv_gradients(sph_ctx *ctx, sph_mfv_set *s);
 
 /*
  * Neighbour lists, for tests and export, at the given h (no h solve):
- *   mode 0: j != i with r_ij^2 < (2 h_i)^2        (density neighbours)
- *   mode 1: j != i with r_ij^2 < (2 h_i)^2 or r_ij^2 < (2 h_j)^2  (force)
+ *   mode 0: j != i with r_ij^2 < (R h_i)^2        (density neighbours)
+ *   mode 1: j != i with r_ij^2 < (R h_i)^2 or r_ij^2 < (R h_j)^2  (force)
  * r_ij^2 is formed exactly as (dx*dx + dy*dy) + dz*dz with the minimum image
  * per axis and no fused multiply-add.  offsets: device int64[n+1], idx:
  * device int32[cap]; the lists of particle i are idx[offsets[i] ..

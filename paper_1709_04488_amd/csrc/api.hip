@@ -65,6 +65,8 @@ sph_status check_params(sph_ctx *c, const sph_params *p)
         return fail(c, SPH_EINVAL, "alpha_ac must be finite and >= 0");
     if (p->ac_signal != SPH_AC_WADSLEY && p->ac_signal != SPH_AC_PRICE)
         return fail(c, SPH_EINVAL, "ac_signal must be SPH_AC_WADSLEY or SPH_AC_PRICE");
+    if (p->kernel != SPH_KERNEL_M4 && p->kernel != SPH_KERNEL_QUINTIC)
+        return fail(c, SPH_EINVAL, "kernel must be SPH_KERNEL_M4 or SPH_KERNEL_QUINTIC");
     if (p->block_lmax < 0 || p->block_lmax > 40 || p->block_lim < 0)
         return fail(c, SPH_EINVAL, "need 0 <= block_lmax <= 40 and block_lim >= 0");
     if (p->block_lmax > 0 && p->av_switch != SPH_AV_NONE)
@@ -153,7 +155,7 @@ sph_status alloc(sph_ctx *c, T **ptr, int64_t count)
 // request) does not reallocate.
 static sph_status ensure_cache(sph_ctx *c)
 {
-    const int64_t bytes = cache_bytes(c->p.leaf_size, pair_grid(c->ncap));
+    const int64_t bytes = cache_bytes(c->p.leaf_size, c->p.kernel, pair_grid(c->ncap));
     if (c->cache && c->cache_size >= bytes) return SPH_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
@@ -227,7 +229,8 @@ sph_status ensure_capacity(sph_ctx *c, int64_t n)
     if (n <= c->ncap && node_count_bound(n) <= c->node_cap) return ensure_cache(c);
     int64_t cap = std::max<int64_t>(n, 1024);
     int64_t need = bytes_per_particle() * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
-                   4 * hist_words(cap) + 4096 + cache_bytes(c->p.leaf_size, pair_grid(cap));
+                   4 * hist_words(cap) + 4096 +
+                   cache_bytes(c->p.leaf_size, c->p.kernel, pair_grid(cap));
     if (c->budget && (size_t)need > c->budget)
         return fail(c, SPH_EBUDGET, "working set of " + std::to_string(need) +
                                         " bytes exceeds the HBM budget of " +
@@ -480,8 +483,8 @@ sph_status step_post(sph_ctx *c, double dt, double *dt_used)
     return SPH_OK;
 }
 
-// Run the pair launches of a batch: group the sets by (precision, leaf size)
-// and launch each group in chunks of kMaxBatch.
+// Run the pair launches of a batch: group the sets by (precision, leaf size,
+// smoothing kernel) and launch each group in chunks of kMaxBatch.
 template <class Launch>
 sph_status launch_groups(sph_ctx *const *cs, int count, Launch launch)
 {
@@ -492,7 +495,8 @@ sph_status launch_groups(sph_ctx *const *cs, int count, Launch launch)
         grp.clear();
         for (int b = a; b < count; b++) {
             if (done[b] || cs[b]->n == 0) continue;
-            if (cs[b]->p.precision == cs[a]->p.precision && cs[b]->p.leaf_size == cs[a]->p.leaf_size) {
+            if (cs[b]->p.precision == cs[a]->p.precision && cs[b]->p.leaf_size == cs[a]->p.leaf_size &&
+                cs[b]->p.kernel == cs[a]->p.kernel) {
                 grp.push_back(cs[b]);
                 done[b] = true;
             }
@@ -601,7 +605,8 @@ sph_status evaluate_post(sph_ctx *c, const sph_particles *ps)
 // device allocation, free or stream synchronisation.  The array holds the
 // buffers of kStaticMaxN particles; the pair kernels' persistent grid is
 // capped by the candidate-list slices that fit (kStaticListBlocks at leaf
-// size 32, more at smaller leaves).  Every call on one device shares that
+// size 32 with the M4 kernel; more at smaller leaves, a third as many with
+// the quintic's longer lists).  Every call on one device shares that
 // device's copy: calls that overlap on a device race.
 constexpr int64_t kStaticMaxN = 32768;
 constexpr int64_t kStaticListBlocks = 256;
@@ -621,7 +626,7 @@ constexpr int64_t static_node_bound(int64_t n)
 constexpr int64_t kStaticBytes =
     kStaticMaxN * bytes_per_particle() + static_node_bound(kStaticMaxN) * (int64_t)sizeof(Node) +
     4 * (256 * ((kStaticMaxN + 4095) / 4096) + 256) + 80 * 256 +
-    kStaticListBlocks * 2 * (int64_t)kCacheEntriesPerParticle * 32 * (int64_t)sizeof(double);
+    kStaticListBlocks * 2 * (int64_t)Kern<SPH_KERNEL_M4>::list * 32 * (int64_t)sizeof(double);
 
 static __device__ __align__(256) unsigned char scratch[kStaticBytes];
 
@@ -714,7 +719,7 @@ sph_status carve_static(sph_ctx *c, unsigned char *base)
     if (s != SPH_OK) return s;
     // the candidate lists take the rest, whole per-block slices at this leaf size
     const int64_t at = (used + 255) & ~(int64_t)255;
-    const int64_t per = cache_bytes(c->p.leaf_size, 1);
+    const int64_t per = cache_bytes(c->p.leaf_size, c->p.kernel, 1);
     const int64_t blocks = std::min<int64_t>((kStaticBytes - at) / per, kMaxPairBlocks) / kXcds * kXcds;
     if (blocks < kXcds) return fail(c, SPH_ENOMEM, "static scratch holds no candidate lists");
     c->cache = (double *)(base + at);
@@ -1375,7 +1380,7 @@ size_t sph_plan_bytes(const sph_params *p, int64_t n)
     const int64_t cap = std::max<int64_t>(n, 1024);
     return (size_t)(bytes_per_particle() * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
                     256 * 4 * ceil_div(cap, kRsTile) + 4096 + 3 * kArgBytes +
-                    cache_bytes(p->leaf_size, pair_grid(cap)));
+                    cache_bytes(p->leaf_size, p->kernel, pair_grid(cap)));
 }
 
 sph_status sph_enable_kernel_timing(sph_ctx *c, int32_t enable)

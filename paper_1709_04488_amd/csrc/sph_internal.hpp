@@ -11,10 +11,33 @@
 
 namespace sph {
 
-// M4 cubic spline in B-spline form: f(q) = (2-q)_+^3 / 4 - (1-q)_+^3, which
-// equals 1 - 3/2 q^2 + 3/4 q^3 on [0,1) and (2-q)^3/4 on [1,2); 3D
-// normalisation 1/pi.
-constexpr double kSigma = 0.31830988618379067154;
+// Smoothing kernels (section 2), W(r, h) = sigma h^-3 f(r/h) with compact
+// support R h:
+//   M4 cubic spline, R = 2, sigma = 1/pi, in B-spline form
+//     f(q) = (2-q)_+^3 / 4 - (1-q)_+^3
+//   (1 - 3/2 q^2 + 3/4 q^3 on [0,1), (2-q)^3/4 on [1,2));
+//   quintic spline (Morris 1996), R = 3, sigma = 1/(120 pi),
+//     f(q) = (3-q)_+^5 - 6 (2-q)_+^5 + 15 (1-q)_+^5.
+// list: density-loop candidate-list entries per particle (below).
+template <int K>
+struct Kern;
+template <>
+struct Kern<SPH_KERNEL_M4> {
+    static constexpr double R = 2.0;
+    static constexpr double sigma = 0.31830988618379067154;
+    static constexpr int list = 160;
+};
+template <>
+struct Kern<SPH_KERNEL_QUINTIC> {
+    static constexpr double R = 3.0;
+    static constexpr double sigma = 0.0026525823848649222;
+    static constexpr int list = 480;
+};
+inline double kern_support(int k) { return k == SPH_KERNEL_QUINTIC ? 3.0 : 2.0; }
+inline int kern_list(int k)
+{
+    return k == SPH_KERNEL_QUINTIC ? Kern<SPH_KERNEL_QUINTIC>::list : Kern<SPH_KERNEL_M4>::list;
+}
 
 constexpr int kWave = 64;
 constexpr int kMaxLevels = 16;   // tree levels above the leaves (8-ary)
@@ -37,15 +60,16 @@ inline unsigned pair_grid(int64_t n)
     return (unsigned)blocks;
 }
 
-// Density-loop candidate lists: up to 160 entries per home particle, each an
-// FP64 r^2 and an FP64 mass, for the candidates within 2 Rc, Rc = kCacheGrow h
-// (capped by the walk radius), so that Newton steps within that bound reuse
-// them.  A block holds the lists of one leaf's G particles.
+// Density-loop candidate lists: up to Kern<K>::list entries per home
+// particle (160 for the M4, whose sphere of radius 2 Rc holds ~90 neighbours
+// at eta = 1.2; 480 for the quintic's ~300 within 3 Rc), each an FP64 r^2 and
+// an FP64 mass, for the candidates within R Rc, Rc = kCacheGrow h (capped by
+// the walk radius), so that Newton steps within that bound reuse them.  A
+// block holds the lists of one leaf's G particles.
 constexpr double kCacheGrow = 1.15;
-constexpr int kCacheEntriesPerParticle = 160;
-inline int64_t cache_bytes(int G, int64_t blocks)
+inline int64_t cache_bytes(int G, int kernel, int64_t blocks)
 {
-    return blocks * 2 * (int64_t)kCacheEntriesPerParticle * G * (int64_t)sizeof(double);
+    return blocks * 2 * (int64_t)kern_list(kernel) * G * (int64_t)sizeof(double);
 }
 
 // Tree node: bounding box of the particles below it and their largest h.

@@ -22,6 +22,7 @@ SPH_ELEVEL = -10
 SPH_FP64, SPH_FP32_PAIR = 0, 1
 SPH_AC_WADSLEY, SPH_AC_PRICE = 0, 1
 SPH_AV_NONE, SPH_AV_MM97, SPH_AV_CD10 = 0, 1, 2
+SPH_KERNEL_M4, SPH_KERNEL_QUINTIC = 0, 1
 
 STATUS_NAMES = {0: "SPH_OK", -1: "SPH_EINVAL", -2: "SPH_ENOMEM", -3: "SPH_EDEVICE",
                 -4: "SPH_ENOTCONVERGED", -5: "SPH_ESTENCIL", -6: "SPH_ENONFINITE",
@@ -54,7 +55,8 @@ class _Params(ctypes.Structure):
                 ("alpha_ac", ctypes.c_double), ("ac_signal", ctypes.c_int32),
                 ("av_switch", ctypes.c_int32), ("alpha_min", ctypes.c_double),
                 ("alpha_max", ctypes.c_double), ("av_ell", ctypes.c_double),
-                ("block_lmax", ctypes.c_int32), ("block_lim", ctypes.c_int32)]
+                ("block_lmax", ctypes.c_int32), ("block_lim", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -176,12 +178,13 @@ class Params:
     av_ell: float = 0.0
     block_lmax: int = 0
     block_lim: int = 2
+    kernel: int = SPH_KERNEL_M4
 
     @classmethod
     def from_setup(cls, setup: dict, **kw) -> "Params":
         keys = ("eta", "gamma", "alpha", "beta", "ccfl", "periodic", "lo", "hi", "alpha_ac",
                 "ac_signal", "av_switch", "alpha_min", "alpha_max", "av_ell", "block_lmax",
-                "block_lim")
+                "block_lim", "kernel")
         return cls(**{k: setup[k] for k in keys if k in setup}, **kw)
 
     def c(self) -> _Params:
@@ -201,6 +204,7 @@ class Params:
         p.alpha_min, p.alpha_max = float(self.alpha_min), float(self.alpha_max)
         p.av_ell = float(self.av_ell)
         p.block_lmax, p.block_lim = int(self.block_lmax), int(self.block_lim)
+        p.kernel = int(self.kernel)
         return p
 
 
