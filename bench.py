@@ -31,6 +31,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -49,8 +50,23 @@ METRIC = "neighbour interactions/s (density+force) FP64 vs FP32; p50/p99 request
 #     9 + 9, v_ij and v.rhat 8, pressure term 4, du/dt term 3, signal speed 3,
 #     max 1, accumulation 7 -> 56; viscosity on approaching pairs +15, about
 #     half of all pairs for random velocities -> 64 on average
+#   the quintic kernel's shape costs 16 flops for f and 5 more for f' (the
+#     M4's 8 and 3): +10 per density pair, +14 per force pair (f' at h_i and h_j)
+#   artificial conductivity: u_i - u_j from c^2 4, signal speed 1 (Wadsley) or
+#     7 (Price), term and accumulation 5 -> +10 or +16 per force pair
 DENS_FLOPS_PER_PAIR_ITER = 26
 FORCE_FLOPS_PER_PAIR = 64
+
+
+def flops_per_pair(setup: dict) -> tuple:
+    """(density flops per pair and iteration, force flops per pair) of a run."""
+    quintic = int(setup.get("kernel", 0)) == 1
+    d = DENS_FLOPS_PER_PAIR_ITER + (10 if quintic else 0)
+    f = FORCE_FLOPS_PER_PAIR + (14 if quintic else 0)
+    if float(setup.get("alpha_ac", 0.0)) > 0.0:
+        f += 16 if int(setup.get("ac_signal", 0)) == 1 else 10
+    return d, f
+
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}   # MI355X vector FP64 / FP32 (FMA = 2)
 PAPER_H_RTOL = 0.01                           # h-rho iteration tolerance the paper quotes
 
@@ -68,13 +84,15 @@ def workload(name: str):
     raise ValueError(name)
 
 
-def run_gpu(w, precision: int, steps: int, warmup: int, leaf: int, warm_start: bool = False,
+def run_gpu(w, precision: int, steps: int, warmup: int, leaf, warm_start: bool = False,
             h_rtol: float = None, count_tests: bool = True, over: dict = None):
+    """leaf: a leaf size, or an autotuner launch shape {"leaf", "stage", "claim"}."""
     import torch
-    from paper_1709_04488_amd import sph
+    from paper_1709_04488_amd import sph, tune
 
+    shape = leaf if isinstance(leaf, dict) else {"leaf": int(leaf), "stage": "full", "claim": 1}
     params = sph.Params.from_setup({**w.setup, **(over or {})}, precision=precision,
-                                   leaf_size=leaf)
+                                   **tune.params_kw(shape))
     if h_rtol is not None:
         params.h_rtol = h_rtol
     ctx = sph.Context(params)
@@ -112,7 +130,9 @@ def run_gpu(w, precision: int, steps: int, warmup: int, leaf: int, warm_start: b
             info[k] = diag[k]
     ms = (t1 - t0) * 1e3 / steps
     inter = info["n_dens_pairs"] + info["n_force_pairs"]
+    fd, ff = flops_per_pair({**w.setup, **(over or {})})
     res = {"ms_per_step": ms, "interactions": inter, "value": inter / (ms * 1e-3), "info": info,
+           "flops_per_pair": {"density_per_iteration": fd, "force": ff},
            "kernel_ms": {k: (v[0] / max(v[1], 1)) for k, v in kt.items()},
            "kernel_launches": {k: v[1] for k, v in kt.items()},
            "device_bytes": ctx.device_bytes()}
@@ -124,17 +144,24 @@ def _profile_record(tag: str):
     """The committed rocprofv3 record of this workload, precision and leaf size
     (profiles/traffic.json), or None when there is none or the pair-loop
     source has changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_1709_04488_amd", "csrc", "pairs.hip")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(tag)
     if not rec:
         return None
-    if rec.get("pairs_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if rec.get("pairs_source_sha256") != pairs_source_sha256():
         return None
     return rec
+
+
+def pairs_source_sha256() -> str:
+    """Digest of the pair kernels' source (kernel code and argument blocks)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pairs.hpp", "pairs_args.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1709_04488_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(tag: str, kernel: str):
@@ -158,14 +185,16 @@ def prof_tag(args, prec: str):
     """Key of the committed counter runs that match this invocation: workload,
     precision, leaf size and, when on, the artificial conductivity."""
     ac = f"_ac{args.alpha_ac:g}{args.ac_signal}" if args.alpha_ac > 0.0 else ""
-    return f"{args.config}_{prec}_g{args.leaf_used[prec]}{ac}"
+    return f"{args.config}_{prec}_g{args.leaf_used[prec]['leaf']}{ac}"
 
 
 def roofline(res, prec: str, tag: str = None, phase: str = "cold"):
     info = res["info"]
     km = res["kernel_ms"]
-    dens_flops = info["dens_pair_evals"] * DENS_FLOPS_PER_PAIR_ITER
-    force_flops = info["force_pair_evals"] * FORCE_FLOPS_PER_PAIR
+    fpp = res.get("flops_per_pair", {"density_per_iteration": DENS_FLOPS_PER_PAIR_ITER,
+                                     "force": FORCE_FLOPS_PER_PAIR})
+    dens_flops = info["dens_pair_evals"] * fpp["density_per_iteration"]
+    force_flops = info["force_pair_evals"] * fpp["force"]
     cand = {"density": (dens_flops, km["density"]), "force": (force_flops, km["force"])}
     name = max(cand, key=lambda k: cand[k][1])
     flops, t_ms = cand[name]
@@ -217,21 +246,134 @@ def largest_leg(args):
     from paper_1709_04488_amd import workloads as W
     w = W.config2()
     print(f"# largest: {w.name} N={w.n}", file=sys.stderr, flush=True)
-    tuned = tune.LeafTuner().measure(w.arrays, w.setup, sph.SPH_FP32_PAIR)
+    tuned = tune.LaunchTuner().measure(w.arrays, w.setup, sph.SPH_FP32_PAIR)
     g = tuned["leaf"]
-    r = run_gpu(w, sph.SPH_FP32_PAIR, max(args.steps // 2, 5), args.warmup, g,
+    r = run_gpu(w, sph.SPH_FP32_PAIR, max(args.steps // 2, 5), args.warmup, tuned,
                 count_tests=False)
     print(f"# largest fp32: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     tag = f"c2_fp32_g{g}"
     return {"workload": f"{w.name}: N={w.n}, isolated Plummer sphere (a = 0.05, cut at r = 1), "
                         "FP32-pair, cold h start from the input guess",
             "n": w.n, "leaf_size": g, "steps": max(args.steps // 2, 5),
+            "launch_shape": {k: tuned[k] for k in ("leaf", "stage", "claim")},
             "value": r["value"], "unit": "interactions/s", "ms_per_step": r["ms_per_step"],
             "interactions_per_step": r["interactions"],
             "nr_iter_mean": r["info"]["nr_iter_total"] / w.n,
             "roofline": roofline(r, "fp32", tag=tag),
             "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()},
             "autotuner": tuned}
+
+
+def _resident(w, params, steps: int, warmup: int, substeps: bool = False, nfull: int = 1):
+    """Resident integration: `steps` sph_step calls (or, with substeps, block
+    sub-steps until `nfull` more level-0 steps are done) after `warmup`
+    untimed ones.  Returns (ms per call, calls, pairs per call, state info)."""
+    import torch
+    from paper_1709_04488_amd import sph
+    ctx = sph.Context(params)
+    ctx.upload_state(sph.Particles.from_host(w.arrays))
+    for _ in range(warmup):
+        ctx.step(0.0) if not substeps else ctx.substep()
+    ctx.sync()
+    i0 = ctx.state_info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    calls = 0
+    if substeps:
+        target = i0["block_full_steps"] + nfull
+        while ctx.state_info()["block_full_steps"] < target and calls < 100000:
+            ctx.substep()
+            calls += 1
+    else:
+        for _ in range(steps):
+            ctx.step(0.0)
+            calls += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    info = ctx.state_info()
+    ctx.close()
+    return (t1 - t0) * 1e3 / max(calls, 1), calls, info, i0
+
+
+def rows_legs(args, w, shape):
+    """The method's other rows on the same set in FP64: the quintic kernel
+    (density + forces, with its roofline), resident steps with the Cullen &
+    Dehnen viscosity switch next to plain global steps, hierarchical block
+    time-steps over one level-0 step, and the MFV geometry."""
+    import torch
+    from paper_1709_04488_amd import sph, tune
+    out = {}
+    steps = max(args.steps // 4, 3)
+    r = run_gpu(w, sph.SPH_FP64, steps, 1, shape, count_tests=False,
+                over={"kernel": sph.SPH_KERNEL_QUINTIC})
+    out["quintic_fp64"] = {
+        "workload": "the same set with the quintic kernel (R = 3), FP64, cold h start",
+        "value": r["value"], "unit": "interactions/s", "ms_per_step": r["ms_per_step"],
+        "interactions_per_step": r["interactions"],
+        "density_neighbours_mean": r["info"]["n_dens_pairs"] / w.n,
+        "roofline": roofline(r, "fp64"),
+        "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()}}
+    print(f"# quintic fp64: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    kw = tune.params_kw(shape)
+    glob_ms, n, info, _ = _resident(w, sph.Params.from_setup(w.setup, **kw), steps, 1)
+    sw_ms, _, sw_info, _ = _resident(
+        w, sph.Params.from_setup({**w.setup, "av_switch": sph.SPH_AV_CD10}, **kw), steps, 1)
+    out["resident_steps_fp64"] = {
+        "workload": "resident kick-drift-kick steps of the same set (sort, tree, density, "
+                    "forces, kicks and drift each step), FP64",
+        "global_ms_per_step": glob_ms,
+        "cd10_switch_ms_per_step": sw_ms,
+        "interactions_per_step": (info["n_dens_pairs"] + info["n_force_pairs"]),
+        "value_global": (info["n_dens_pairs"] + info["n_force_pairs"]) / (glob_ms * 1e-3),
+        "value_cd10": (sw_info["n_dens_pairs"] + sw_info["n_force_pairs"]) / (sw_ms * 1e-3),
+        "unit": "interactions/s"}
+    print(f"# resident: global {glob_ms:.3f} ms/step, CD10 {sw_ms:.3f} ms/step",
+          file=sys.stderr, flush=True)
+    bp = sph.Params.from_setup({**w.setup, "block_lmax": 20, "block_lim": 2}, **kw)
+    blk_ms, calls, binfo, b0 = _resident(w, bp, 0, 0, substeps=True, nfull=1)
+    dt_max = binfo["block_time"] - b0["block_time"]
+    updates = binfo["block_updates"] - b0["block_updates"]
+    subs = binfo["block_substeps"] - b0["block_substeps"]
+    # global steps over the same time take the smallest time-step every step
+    g_steps = dt_max / max(info["dt_next"], 1e-300)
+    out["block_timesteps_fp64"] = {
+        "workload": "one level-0 step of hierarchical block time-steps (levels down to "
+                    "dt_max/2^20, limiter 2 levels) of the same set, FP64, from the "
+                    "uploaded state",
+        "substeps": subs, "levels_deepest": int(round(math.log2(max(subs, 1)))),
+        "particle_updates": updates, "updates_per_substep_mean": updates / max(subs, 1),
+        "ms_per_level0_step": blk_ms * calls, "ms_per_substep": blk_ms,
+        "particle_updates_per_s": updates / (blk_ms * calls * 1e-3),
+        "global_steps_for_same_time": g_steps,
+        "global_ms_for_same_time": g_steps * glob_ms,
+        "speedup_vs_global_steps": (g_steps * glob_ms) / (blk_ms * calls)}
+    print(f"# block: {subs} sub-steps, {blk_ms * calls:.1f} ms per level-0 step",
+          file=sys.stderr, flush=True)
+    x, y, z, h0 = (torch.as_tensor(w.arrays[k], dtype=torch.float64, device="cuda")
+                   for k in ("x", "y", "z", "h"))
+    fields = [torch.as_tensor(w.arrays[k], dtype=torch.float64, device="cuda")
+              for k in ("vx", "vy", "vz", "u")]
+    with sph.Context(sph.Params.from_setup({**w.setup, "eta": 1.0}, **kw)) as ctx:
+        h = h0.clone()
+        ctx.mfv_gradients(x, y, z, h, fields)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            h.copy_(h0)
+            o = ctx.mfv_gradients(x, y, z, h, fields)
+        torch.cuda.synchronize()
+        mfv_ms = (time.perf_counter() - t0) * 1e3 / steps
+        ctx.sync()
+        nngb = float(o["nngb"].double().mean())
+    out["mfv_fp64"] = {
+        "workload": "MFV geometry of the same positions (number-density h solve with "
+                    "eta = 1, E, B = E^-1, condition number, gradients of v and u), FP64",
+        "ms_per_call": mfv_ms, "neighbours_mean": nngb,
+        "pairs_per_s": nngb * w.n / (mfv_ms * 1e-3)}
+    print(f"# mfv: {mfv_ms:.3f} ms/call", file=sys.stderr, flush=True)
+    return out
 
 
 def serving_legs(args):
@@ -304,6 +446,8 @@ def main():
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the 4,194,304-particle Plummer leg (FP32-pair)")
     ap.add_argument("--no-serving", action="store_true", help="skip the two served workloads")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the quintic, viscosity-switch, block time-step and MFV legs")
     ap.add_argument("--serve-steps", type=int, default=200,
                     help="KDK steps per served integration request")
     args = ap.parse_args()
@@ -341,13 +485,13 @@ def main():
         if args.precision not in (name, "both"):
             continue
         if args.leaf == "auto":
-            tuned[name] = tune.LeafTuner().measure(w.arrays, w.setup, prec)
-            leaf[name] = tuned[name]["leaf"]
-            print(f"# autotuner {name}: leaf {leaf[name]} "
+            tuned[name] = tune.LaunchTuner().measure(w.arrays, w.setup, prec)
+            leaf[name] = {k: tuned[name][k] for k in ("leaf", "stage", "claim")}
+            print(f"# autotuner {name}: {tune.shape_key(leaf[name])} "
                   f"({', '.join(f'{g}: {s * 1e3:.1f} ms' for g, s in tuned[name]['seconds'].items())})",
                   file=sys.stderr, flush=True)
         else:
-            leaf[name] = int(args.leaf)
+            leaf[name] = {"leaf": int(args.leaf), "stage": "full", "claim": 1}
     args.leaf_used = leaf
     results = {}
     if args.precision in ("fp64", "both"):
@@ -361,9 +505,11 @@ def main():
         # (section 2.1.1); a throughput mode, never parity-checked
         results["fp64_paper_tol"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, leaf["fp64"],
                                             h_rtol=PAPER_H_RTOL)
-        # with artificial conductivity, the paper's default signal speed
-        results["fp64_ac"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, leaf["fp64"],
-                                     over={"alpha_ac": 1.0, "ac_signal": sph.SPH_AC_WADSLEY})
+        # with artificial conductivity, the paper's default signal speed (when
+        # the main run does not already carry it)
+        if args.alpha_ac == 0.0:
+            results["fp64_ac"] = run_gpu(w, sph.SPH_FP64, args.steps, args.warmup, leaf["fp64"],
+                                         over={"alpha_ac": 1.0, "ac_signal": sph.SPH_AC_WADSLEY})
     if args.precision in ("fp32", "both"):
         results["fp32"] = run_gpu(w, sph.SPH_FP32_PAIR, args.steps, args.warmup, leaf["fp32"],
                                   count_tests=not args.main_only)
@@ -392,7 +538,8 @@ def main():
                                   if args.alpha_ac > 0.0 else "")
                                + f"{'FP64' if head_key == 'fp64' else 'FP32-pair'}, "
                                "cold h start from the input guess",
-                   "n": w.n, "leaf_size": leaf[prec_name],
+                   "n": w.n, "leaf_size": leaf[prec_name]["leaf"],
+                   "launch_shape": leaf[prec_name],
                    "leaf_choice": "autotuner" if args.leaf == "auto" else "fixed",
                    "interactions_per_step": head["interactions"]},
         "roofline": roofline(head, prec_name, tag=prof_tag(args, prec_name)),
@@ -436,7 +583,8 @@ def main():
     if "fp32" in results and head_key != "fp32":
         r = results["fp32"]
         out["fp32_pair"] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
-                            "leaf_size": leaf["fp32"],
+                            "leaf_size": leaf["fp32"]["leaf"],
+                            "launch_shape": leaf["fp32"],
                             "speedup_vs_fp64": r["value"] / head["value"],
                             "roofline": roofline(r, "fp32", tag=prof_tag(args, "fp32")),
                             "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()}}
@@ -444,6 +592,8 @@ def main():
         out["autotuner"] = tuned
     if not args.main_only and not args.no_largest and args.config != "c2":
         out["largest_fp32_pair"] = largest_leg(args)
+    if not args.main_only and not args.no_rows and "fp64" in leaf:
+        out["other_rows"] = rows_legs(args, w, leaf["fp64"])
     if not args.main_only and not args.no_serving:
         out["serving"] = serving_legs(args)
     if not args.no_cpu_baseline:

@@ -168,6 +168,16 @@ typedef struct {
     int32_t block_lim;  /* block time-step limiter: force neighbours at most this many
                            levels apart (default 2) */
     int32_t kernel;     /* SPH_KERNEL_M4 (default, R = 2) or SPH_KERNEL_QUINTIC (R = 3) */
+    /* Launch shape of the density and force loops (the autotuner's knobs
+     * besides leaf_size; neither changes what is computed):
+     *   stage_leaves: candidate leaves staged in LDS per step of a sweep,
+     *     1..128/leaf_size (0: all 128/leaf_size the LDS tile holds).  The
+     *     density results do not depend on it; the force sums may change in
+     *     their last bits (the split of a particle's terms over its lanes).
+     *   claim_leaves: home leaves a wavefront claims per atomic claim of the
+     *     persistent loop, 1..64 (0: 1); results do not depend on it. */
+    int32_t stage_leaves;
+    int32_t claim_leaves;
     int32_t pad_;       /* zero */
 } sph_params;
 

@@ -67,6 +67,10 @@ sph_status check_params(sph_ctx *c, const sph_params *p)
         return fail(c, SPH_EINVAL, "ac_signal must be SPH_AC_WADSLEY or SPH_AC_PRICE");
     if (p->kernel != SPH_KERNEL_M4 && p->kernel != SPH_KERNEL_QUINTIC)
         return fail(c, SPH_EINVAL, "kernel must be SPH_KERNEL_M4 or SPH_KERNEL_QUINTIC");
+    if (p->stage_leaves < 0 || p->stage_leaves > 2 * kWave / p->leaf_size)
+        return fail(c, SPH_EINVAL, "stage_leaves must be 0..128/leaf_size");
+    if (p->claim_leaves < 0 || p->claim_leaves > 64)
+        return fail(c, SPH_EINVAL, "claim_leaves must be 0..64");
     if (p->block_lmax < 0 || p->block_lmax > 40 || p->block_lim < 0)
         return fail(c, SPH_EINVAL, "need 0 <= block_lmax <= 40 and block_lim >= 0");
     if (p->block_lmax > 0 && p->av_switch != SPH_AV_NONE)
@@ -484,7 +488,8 @@ sph_status step_post(sph_ctx *c, double dt, double *dt_used)
 }
 
 // Run the pair launches of a batch: group the sets by (precision, leaf size,
-// smoothing kernel) and launch each group in chunks of kMaxBatch.
+// smoothing kernel, launch shape) and launch each group in chunks of
+// kMaxBatch.
 template <class Launch>
 sph_status launch_groups(sph_ctx *const *cs, int count, Launch launch)
 {
@@ -496,7 +501,9 @@ sph_status launch_groups(sph_ctx *const *cs, int count, Launch launch)
         for (int b = a; b < count; b++) {
             if (done[b] || cs[b]->n == 0) continue;
             if (cs[b]->p.precision == cs[a]->p.precision && cs[b]->p.leaf_size == cs[a]->p.leaf_size &&
-                cs[b]->p.kernel == cs[a]->p.kernel) {
+                cs[b]->p.kernel == cs[a]->p.kernel &&
+                cs[b]->p.stage_leaves == cs[a]->p.stage_leaves &&
+                cs[b]->p.claim_leaves == cs[a]->p.claim_leaves) {
                 grp.push_back(cs[b]);
                 done[b] = true;
             }

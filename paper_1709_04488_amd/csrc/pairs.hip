@@ -167,7 +167,8 @@ sph_status forces_prepare(sph_ctx *c, int64_t n)
 }
 
 // One persistent launch over the prepared sets cs[0..count) (same stream,
-// same precision, leaf size and smoothing kernel, count <= kMaxBatch).
+// same precision, leaf size, smoothing kernel and launch shape, count <=
+// kMaxBatch).
 sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax)
 {
     if (count <= 0) return SPH_OK;
@@ -177,6 +178,8 @@ sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax)
     TRY_(zero_batch_counts(cs, count, kCntDensListOverflows, 1));
     Batch<DensArgs> B{};
     B.nreq = count;
+    B.claim = c->p.claim_leaves > 0 ? c->p.claim_leaves : 1;
+    B.stage = c->p.stage_leaves;
     B.work = c->d_work;
     int64_t leaves_bound = 0;
     for (int r = 0; r < count; r++) {
@@ -215,6 +218,8 @@ sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax)
     TRY_(zero_batch_counts(cs, count, kCntForceFirst, kCntForceWords));
     Batch<ForceArgs> B{};
     B.nreq = count;
+    B.claim = c->p.claim_leaves > 0 ? c->p.claim_leaves : 1;
+    B.stage = c->p.stage_leaves;
     B.work = c->d_work;
     int64_t leaves_bound = 0;
     for (int r = 0; r < count; r++) {

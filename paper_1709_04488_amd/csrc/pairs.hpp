@@ -169,10 +169,12 @@ __device__ inline int wave_max_int(int v)
 // over the 8 XCDs, so block b runs on XCD b % 8; each XCD first claims leaves
 // from its own contiguous eighth of the leaf range (neighbouring leaves then
 // share that XCD's L2), then helps the others.  Claims go through one atomic
-// counter per eighth; every leaf is processed by exactly one wave, so results
-// do not depend on which wave took it.
+// counter per eighth, `claim` consecutive leaves at a time; every leaf is
+// processed by exactly one wave, so results do not depend on which wave took
+// it.
 template <class Fn>
-__device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work, Fn fn)
+__device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work, int claim,
+                                          Fn fn)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t per = (L + kXcds - 1) / kXcds;
@@ -183,14 +185,15 @@ __device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work
         const int64_t end = beg + per < L ? beg + per : L;
         if (beg >= end) continue;
         for (;;) {
-            uint32_t claim = 0;
-            if (lane == 0) claim = atomicAdd(&work[x], 1u);
+            uint32_t c = 0;
+            if (lane == 0) c = atomicAdd(&work[x], 1u);
             // wave-uniform from here on (scalar registers): the leaf's argument
             // block, node and particle range are then loaded once per wave
-            claim = (uint32_t)__builtin_amdgcn_readlane((int)claim, 0);
-            const int64_t leaf = beg + (int64_t)claim;
-            if (leaf >= end) break;
-            fn(leaf);
+            c = (uint32_t)__builtin_amdgcn_readlane((int)c, 0);
+            const int64_t leaf0 = beg + (int64_t)c * claim;
+            if (leaf0 >= end) break;
+            const int64_t leaf1 = leaf0 + claim < end ? leaf0 + claim : end;
+            for (int64_t leaf = leaf0; leaf < leaf1; leaf++) fn(leaf);
         }
     }
 }
@@ -412,15 +415,17 @@ __device__ WalkResult walk(const TreeInfo &T, const Node *nodes, Test test, Walk
     return walk_result(wb, cur, ncur, 0);
 }
 
-// Visit the candidate leaves in groups of at most NL: fn(leaves, count) with
-// a wave-uniform count.  After a truncated walk the leaves under each
-// returned node are tested 64 at a time and the passing ones grouped.
+// Visit the candidate leaves in groups of at most `depth` (<= NL, the LDS
+// tile): fn(leaves, count) with a wave-uniform count.  After a truncated walk
+// the leaves under each returned node are tested 64 at a time and the
+// passing ones grouped.
 template <int NL, class Test, class Fn>
 __device__ int64_t for_each_leaf_group(const TreeInfo &T, const Node *nodes, const WalkResult &wr,
-                                       Test test, WalkBuf &wb, Fn fn)
+                                       Test test, WalkBuf &wb, Fn fn, int depth = NL)
 {
+    const int D = depth >= 1 && depth <= NL ? depth : NL;
     if (wr.lev == 0) {
-        for (int t0 = 0; t0 < wr.n; t0 += NL) fn(wr.list + t0, wr.n - t0 < NL ? wr.n - t0 : NL);
+        for (int t0 = 0; t0 < wr.n; t0 += D) fn(wr.list + t0, wr.n - t0 < D ? wr.n - t0 : D);
         return wr.n;
     }
     const int lane = threadIdx.x & (kWave - 1);
@@ -439,7 +444,7 @@ __device__ int64_t for_each_leaf_group(const TreeInfo &T, const Node *nodes, con
             if (pass) wb.tmp[__popcll(mask & lt)] = (uint32_t)c;
             wave_lds_sync();
             const int cnt = (int)__popcll(mask);
-            for (int t0 = 0; t0 < cnt; t0 += NL) fn(wb.tmp + t0, cnt - t0 < NL ? cnt - t0 : NL);
+            for (int t0 = 0; t0 < cnt; t0 += D) fn(wb.tmp + t0, cnt - t0 < D ? cnt - t0 : D);
             wave_lds_sync();
             tested += b1 - b < kWave ? b1 - b : kWave;
         }
@@ -895,7 +900,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
         evals = walks = visits = overflows = nr_total = tests = boxes = list_over = 0;
         iter_max = 0;
     };
-    for_each_home_leaf(pre[B.nreq], B.work, [&](int64_t gleaf) {
+    for_each_home_leaf(pre[B.nreq], B.work, B.claim, [&](int64_t gleaf) {
         // the request and its argument block are wave-uniform (scalar registers)
         const int r = __builtin_amdgcn_readfirstlane(find_req(pre, B.nreq, gleaf));
         if (r != cur) {
@@ -1059,7 +1064,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                     }
                     wave_lds_sync();
                 };
-                visits += for_each_leaf_group<NL>(T, A.nodes, wr, make_test(hcov), wb, group);
+                visits += for_each_leaf_group<NL>(T, A.nodes, wr, make_test(hcov), wb, group,
+                                                  B.stage);
                 count = base;
                 cached = !conv && count <= KP;
                 list_over += (int64_t)__popcll(__ballot(!conv && q == 0 && count > KP));
@@ -1207,7 +1213,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         }
         pairs_total = overflows = tests = boxes = 0;
     };
-    for_each_home_leaf(pre[B.nreq], B.work, [&](int64_t gleaf) {
+    for_each_home_leaf(pre[B.nreq], B.work, B.claim, [&](int64_t gleaf) {
         const int r = __builtin_amdgcn_readfirstlane(find_req(pre, B.nreq, gleaf));
         if (r != cur) {
             flush_counts();
@@ -1453,7 +1459,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             }
             wave_lds_sync();
         };
-        for_each_leaf_group<NL>(T, F.nodes, wr, test, wb, group);
+        for_each_leaf_group<NL>(T, F.nodes, wr, test, wb, group, B.stage);
         axi = group_sum<LPP>(axi);
         ayi = group_sum<LPP>(ayi);
         azi = group_sum<LPP>(azi);
@@ -1514,7 +1520,7 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
     const Box &bx = N.box;
     const int32_t mode = N.mode;
     int64_t overflows = 0;
-    for_each_home_leaf(T.cnt[0], N.work, [&](int64_t leaf) {
+    for_each_home_leaf(T.cnt[0], N.work, 1, [&](int64_t leaf) {
         const int64_t first = N.lstart[leaf];
         const int nhome = (int)(N.lstart[leaf + 1] - first);
         const int64_t i = first + p;
@@ -1624,7 +1630,7 @@ __global__ __launch_bounds__(kWave) void k_mfv(MfvArgs M)
     const Box &bx = M.box;
     const int nf = M.nf;
     int64_t overflows = 0;
-    for_each_home_leaf(T.cnt[0], M.work, [&](int64_t leaf) {
+    for_each_home_leaf(T.cnt[0], M.work, 1, [&](int64_t leaf) {
         const int64_t first = M.lstart[leaf];
         const int nhome = (int)(M.lstart[leaf + 1] - first);
         const int64_t i = first + p;

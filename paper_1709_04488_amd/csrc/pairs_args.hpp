@@ -13,6 +13,8 @@ namespace sph {
 template <class Args>
 struct Batch {
     int32_t nreq;
+    int32_t claim;   // home leaves per claim of the persistent loop (>= 1)
+    int32_t stage;   // candidate leaves per staged group (1..128/G)
     uint32_t *work;
     double *cache;   // density loop: per-block candidate cache (nullptr: none)
     const Args *req[kMaxBatch];

@@ -345,6 +345,13 @@ class GpuExecutor:
             self.pool = None
 
     def params(self, req: Request):
+        # a launch-shape tuner gives leaf size, stage depth and claim size;
+        # a plain function gives the leaf size only
+        shape_of = getattr(self.leaf_for, "shape", None)
+        if shape_of is not None:
+            from .tune import params_kw
+            return self.sph.Params.from_setup(req.setup, precision=req.precision,
+                                              **params_kw(shape_of(req)))
         return self.sph.Params.from_setup(req.setup, precision=req.precision,
                                           leaf_size=self.leaf_for(req))
 
@@ -585,8 +592,8 @@ def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200
     integrations of `steps` KDK steps each.  Every request class is tuned
     before the timed runs when leaf is "auto"."""
     if leaf == "auto":
-        from .tune import LeafTuner
-        leaf_for = LeafTuner(path=tune_table)
+        from .tune import LaunchTuner
+        leaf_for = LaunchTuner(path=tune_table)
     else:
         g = int(leaf)
         leaf_for = lambda req: g  # noqa: E731

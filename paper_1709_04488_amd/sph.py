@@ -56,7 +56,8 @@ class _Params(ctypes.Structure):
                 ("av_switch", ctypes.c_int32), ("alpha_min", ctypes.c_double),
                 ("alpha_max", ctypes.c_double), ("av_ell", ctypes.c_double),
                 ("block_lmax", ctypes.c_int32), ("block_lim", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("stage_leaves", ctypes.c_int32),
+                ("claim_leaves", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -179,6 +180,8 @@ class Params:
     block_lmax: int = 0
     block_lim: int = 2
     kernel: int = SPH_KERNEL_M4
+    stage_leaves: int = 0       # launch shape: candidate leaves per LDS stage (0: 128/leaf)
+    claim_leaves: int = 0       # launch shape: home leaves per claim (0: 1)
 
     @classmethod
     def from_setup(cls, setup: dict, **kw) -> "Params":
@@ -205,6 +208,7 @@ class Params:
         p.av_ell = float(self.av_ell)
         p.block_lmax, p.block_lim = int(self.block_lmax), int(self.block_lim)
         p.kernel = int(self.kernel)
+        p.stage_leaves, p.claim_leaves = int(self.stage_leaves), int(self.claim_leaves)
         return p
 
 

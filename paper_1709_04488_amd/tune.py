@@ -1,19 +1,30 @@
-"""Autotuner for the pair-loop launch shape.
+"""Autotuner for the pair loops' launch shape.
 
-The knob is the leaf size G (8, 16 or 32 particles).  It fixes the whole
-mapping of a pair loop onto the GPU: one wavefront per leaf of G home
-particles, 64/G lanes per home particle, and 64/G candidate leaves (64
-candidate particles) staged in LDS per step of the sweep.  Smaller leaves
-give tighter candidate sets but more tree walks per particle; which wins
-depends on N, on the precision of the pair arithmetic and on how clustered
-the set is, so the tuner measures instead of guessing.
+Three separate choices of how the density and force loops map onto the GPU
+(sph_params fields):
 
+* leaf size G (8, 16 or 32 particles) -- the cell size.  One wavefront per
+  leaf of G home particles with 64/G lanes each; smaller leaves give tighter
+  candidate sets but more tree walks per particle.
+* LDS stage depth (stage_leaves) -- candidate leaves staged in LDS per step
+  of a sweep: the whole tile (128/G leaves) or half of it.  A shallower stage
+  runs more, smaller test-and-flush rounds with denser hit masks; a deeper
+  one fewer rounds.
+* claim size (claim_leaves) -- home leaves a wavefront takes per atomic claim
+  of the persistent loop (1 or 4): the wavefront-to-cell mapping.  Larger
+  claims give a wave a run of neighbouring leaves (shared candidates in L2,
+  fewer atomics) at the price of a coarser load balance at the end.
+
+Which combination wins depends on N, the precision of the pair arithmetic
+and how clustered the set is, so the tuner measures instead of guessing.
 Requests are grouped into classes by (kind, precision, periodic, log2 N
-rounded).  The first request of a class is timed at every leaf size (one
-untimed call, then the best of `reps` timed calls, each a full density +
-force evaluation on a private stream) and the fastest leaf size is kept for
-the class; later requests of the class reuse it without measuring.  The
-table can be saved to and loaded from a JSON file so a server starts tuned.
+rounded).  The first request of a class is timed by coordinate descent: every
+leaf size at the default stage and claim, then the other stage depths at the
+best leaf size, then the other claim sizes at the best (leaf, stage); each
+timing is one untimed call and the best of `reps` timed calls of a full
+density + force evaluation on a private stream.  Later requests of the class
+reuse the choice without measuring.  The table can be saved to and loaded
+from a JSON file so a server starts tuned.
 """
 from __future__ import annotations
 
@@ -23,6 +34,8 @@ import os
 import time
 
 LEAF_SIZES = (8, 16, 32)
+STAGES = ("full", "half")
+CLAIMS = (1, 4)
 
 
 def request_class(kind: str, precision: int, periodic: bool, n: int) -> str:
@@ -31,27 +44,58 @@ def request_class(kind: str, precision: int, periodic: bool, n: int) -> str:
     return f"{kind}/p{int(precision)}/{'per' if periodic else 'open'}/n2^{b}"
 
 
-class LeafTuner:
-    """Leaf size per request class, measured on the first request of each class.
+def stage_leaves(leaf: int, stage: str) -> int:
+    """sph_params.stage_leaves of a stage depth: 0 (the whole 128/G tile) or
+    half of it."""
+    if stage == "full":
+        return 0
+    if stage == "half":
+        return max(1, 64 // int(leaf))
+    raise ValueError(f"unknown stage depth {stage!r}")
 
-    `timer(arrays, setup, precision, leaf) -> seconds` times one evaluation;
-    the default runs the HIP path (density + forces) on the GPU.  Tests pass a
-    synthetic timer."""
 
-    def __init__(self, sizes=LEAF_SIZES, reps: int = 2, path: str = None, timer=None):
+def shape_key(shape: dict) -> str:
+    return f"g{shape['leaf']}/{shape['stage']}/c{shape['claim']}"
+
+
+def params_kw(shape: dict) -> dict:
+    """sph.Params keyword arguments of a launch shape."""
+    return {"leaf_size": int(shape["leaf"]),
+            "stage_leaves": stage_leaves(shape["leaf"], shape["stage"]),
+            "claim_leaves": int(shape["claim"])}
+
+
+class LaunchTuner:
+    """Launch shape per request class, measured on the first request of each
+    class.
+
+    `timer(arrays, setup, precision, shape) -> seconds` times one evaluation
+    with shape = {"leaf": G, "stage": "full"|"half", "claim": C}; the default
+    runs the HIP path (density + forces) on the GPU.  Tests pass a synthetic
+    timer.  Calling the tuner on a request returns its leaf size (what memory
+    planning needs); shape(req) returns the whole choice."""
+
+    def __init__(self, sizes=LEAF_SIZES, stages=STAGES, claims=CLAIMS, reps: int = 2,
+                 path: str = None, timer=None):
         self.sizes = tuple(int(s) for s in sizes)
+        self.stages = tuple(stages)
+        self.claims = tuple(int(c) for c in claims)
         self.reps = int(reps)
         self.path = path
         self.timer = timer or _gpu_timer(self.reps)
-        self.table = {}          # class -> {"leaf": G, "seconds": {G: s}}
+        self.table = {}          # class -> {"leaf", "stage", "claim", "seconds": {shape: s}}
         if path and os.path.exists(path):
             self.load(path)
 
     # --- table ------------------------------------------------------------
+    def _valid(self, v: dict) -> bool:
+        return (v.get("leaf") in self.sizes and v.get("stage") in self.stages
+                and v.get("claim") in self.claims)
+
     def load(self, path: str):
         with open(path) as f:
             data = json.load(f)
-        self.table.update({k: v for k, v in data.items() if v.get("leaf") in self.sizes})
+        self.table.update({k: v for k, v in data.items() if self._valid(v)})
 
     def save(self, path: str = None):
         path = path or self.path
@@ -63,30 +107,46 @@ class LeafTuner:
     def key(self, req) -> str:
         return request_class(req.kind, req.precision, bool(req.setup.get("periodic", True)), req.n)
 
-    def choose(self, req) -> int:
+    def shape(self, req) -> dict:
         k = self.key(req)
         if k not in self.table:
             self.table[k] = self.measure(req.arrays, req.setup, req.precision)
             self.save()
-        return int(self.table[k]["leaf"])
+        e = self.table[k]
+        return {"leaf": int(e["leaf"]), "stage": e["stage"], "claim": int(e["claim"])}
+
+    def choose(self, req) -> int:
+        return self.shape(req)["leaf"]
 
     __call__ = choose
 
     def measure(self, arrays, setup, precision: int) -> dict:
         secs = {}
-        for g in self.sizes:
-            secs[g] = float(self.timer(arrays, setup, precision, g))
-        best = min(secs, key=lambda g: (secs[g], g))
-        return {"leaf": int(best), "seconds": {str(g): s for g, s in secs.items()}}
+
+        def t(shape):
+            k = shape_key(shape)
+            if k not in secs:
+                secs[k] = float(self.timer(arrays, setup, precision, dict(shape)))
+            return secs[k]
+
+        def best(cands):
+            # ties go to the earlier candidate (smaller leaf, full stage, claim 1)
+            return min(cands, key=lambda s: t(s))
+
+        base = {"stage": self.stages[0], "claim": self.claims[0]}
+        cur = best([{**base, "leaf": g} for g in self.sizes])
+        cur = best([{**cur, "stage": s} for s in self.stages])
+        cur = best([{**cur, "claim": c} for c in self.claims])
+        return {**cur, "seconds": secs}
 
 
 def _gpu_timer(reps: int):
-    def run(arrays, setup, precision, leaf):
+    def run(arrays, setup, precision, shape):
         import torch
 
         from . import sph
         stream = torch.cuda.Stream()
-        params = sph.Params.from_setup(setup, precision=precision, leaf_size=leaf)
+        params = sph.Params.from_setup(setup, precision=precision, **params_kw(shape))
         with torch.cuda.stream(stream):
             ctx = sph.Context(params, stream=stream)
             p = sph.Particles.from_host(arrays)
@@ -110,7 +170,7 @@ def main(argv=None):
     import argparse
 
     from . import workloads as W
-    ap = argparse.ArgumentParser(description="tune the leaf size on named workloads")
+    ap = argparse.ArgumentParser(description="tune the pair loops' launch shape on named workloads")
     ap.add_argument("--workload", default="c1", help="c0, c1, c2 or c1s<n_side>")
     ap.add_argument("--precision", type=int, default=None, help="0 FP64, 1 FP32-pair (default both)")
     ap.add_argument("--out", default=None, help="JSON table to update")
@@ -119,7 +179,7 @@ def main(argv=None):
     name = args.workload
     w = {"c0": W.config0, "c1": W.config1, "c2": W.config2}.get(name)
     w = w() if w else W.config1(n_side=int(name[3:]))
-    tuner = LeafTuner(reps=args.reps, path=args.out)
+    tuner = LaunchTuner(reps=args.reps, path=args.out)
     precs = (0, 1) if args.precision is None else (args.precision,)
     out = {}
     for p in precs:

@@ -63,7 +63,7 @@ def test_struct_layouts_match_header():
     from paper_1709_04488_amd import sph
     # ... + alpha_ac, ac_signal, av_switch (filling the old tail padding),
     # alpha_min, alpha_max, av_ell
-    assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4 + 8 + 4 + 4 + 3 * 8 + 2 * 4 + 2 * 4
+    assert ctypes.sizeof(sph._Params) == 6 * 8 + 2 * 4 + 6 * 8 + 2 * 4 + 8 + 4 + 4 + 3 * 8 + 2 * 4 + 4 * 4
     # ... + the optional alpha, divv, curlv, level
     assert ctypes.sizeof(sph._Particles) == 8 + 25 * 8
     # ... + the density and force walk overflows (2 x int32) and the list overflows

@@ -42,30 +42,41 @@ def test_roofline_uses_the_longest_pair_loop():
     assert b.roofline(res, "fp32")["kernel"] == "force"
 
 
-def _tree(tmp_path, pairs_text):
+PAIR_SOURCES = ("pairs.hpp", "pairs_args.hpp")
+
+
+def _sources():
+    return {f: open(os.path.join(ROOT, "paper_1709_04488_amd", "csrc", f), "rb").read()
+            for f in PAIR_SOURCES}
+
+
+def _tree(tmp_path, texts):
     d = tmp_path / "tree"
     (d / "profiles").mkdir(parents=True)
     (d / "paper_1709_04488_amd" / "csrc").mkdir(parents=True)
     shutil.copy(os.path.join(ROOT, "profiles", "traffic.json"), d / "profiles" / "traffic.json")
-    (d / "paper_1709_04488_amd" / "csrc" / "pairs.hip").write_bytes(pairs_text)
+    for f, t in texts.items():
+        (d / "paper_1709_04488_amd" / "csrc" / f).write_bytes(t)
     return str(d)
 
 
 def test_counter_records_follow_the_pair_loop_source(tmp_path):
     b = _bench()
     recs = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    src = open(os.path.join(ROOT, "paper_1709_04488_amd", "csrc", "pairs.hip"), "rb").read()
+    src = _sources()
+    digest = hashlib.sha256(b"".join(src[f] for f in PAIR_SOURCES)).hexdigest()
     tag = next(iter(recs))
     want = recs[tag]["bytes_per_launch"]["density_cold"]
-    # a tree whose pairs.hip is the one the record names: quoted
-    if recs[tag]["pairs_source_sha256"] == hashlib.sha256(src).hexdigest():
+    # a tree whose pair-kernel sources are the ones the record names: quoted
+    if recs[tag]["pairs_source_sha256"] == digest:
         b.ROOT = _tree(tmp_path / "same", src)
         assert b.measured_traffic(tag, "density_cold") == int(round(want["read"] + want["written"]))
         assert b.measured_valu_insts(tag, "density_cold") is not None
-    # any edit, a comment included: dropped
-    b.ROOT = _tree(tmp_path / "edited", src + b"\n// edited\n")
-    assert b.measured_traffic(tag, "density_cold") is None
-    assert b.measured_valu_insts(tag, "density_cold") is None
+    # any edit of either file, a comment included: dropped
+    for f in PAIR_SOURCES:
+        b.ROOT = _tree(tmp_path / ("edited_" + f), {**src, f: src[f] + b"\n// edited\n"})
+        assert b.measured_traffic(tag, "density_cold") is None
+        assert b.measured_valu_insts(tag, "density_cold") is None
     # unknown workload, precision or leaf size: nothing
     b.ROOT = _tree(tmp_path / "none", src)
     assert b.measured_traffic("c9_fp64_g16", "density_cold") is None
@@ -75,8 +86,18 @@ def test_counter_record_key_names_workload_precision_leaf_and_conductivity():
     import argparse
     b = _bench()
     a = argparse.Namespace(config="c1", alpha_ac=0.0, ac_signal="wadsley",
-                           leaf_used={"fp64": 16, "fp32": 32})
+                           leaf_used={"fp64": {"leaf": 16, "stage": "full", "claim": 1},
+                                      "fp32": {"leaf": 32, "stage": "half", "claim": 4}})
     assert b.prof_tag(a, "fp64") == "c1_fp64_g16"
     assert b.prof_tag(a, "fp32") == "c1_fp32_g32"
     a.alpha_ac = 1.0
     assert b.prof_tag(a, "fp64") == "c1_fp64_g16_ac1wadsley"
+
+
+def test_flops_per_pair_counts_the_kernel_and_conductivity():
+    b = _bench()
+    assert b.flops_per_pair({}) == (b.DENS_FLOPS_PER_PAIR_ITER, b.FORCE_FLOPS_PER_PAIR)
+    assert b.flops_per_pair({"kernel": 1}) == (36, 78)
+    assert b.flops_per_pair({"alpha_ac": 1.0, "ac_signal": 0}) == (26, 74)
+    assert b.flops_per_pair({"alpha_ac": 1.0, "ac_signal": 1, "kernel": 1}) == (36, 94)
+    assert b.flops_per_pair({"alpha_ac": 0.0, "ac_signal": 1}) == (26, 64)
