@@ -381,10 +381,10 @@ def serving_legs(args):
     throughput with p50/p99 latency from arrival to results in host memory."""
     from paper_1709_04488_amd import serve
     t0 = time.perf_counter()
-    ev = serve.run_served("evaluate", requests=512, slots=8, mode="streams", load=0.8)
+    ev = serve.run_served("evaluate", requests=512, slots=4, mode="streams", load=0.8)
     print(f"# served evaluate: {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    it = serve.run_served("integrate", requests=64, steps=args.serve_steps, slots=8,
+    it = serve.run_served("integrate", requests=64, steps=args.serve_steps, slots=4,
                           mode="streams")
     print(f"# served integrate: {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     keep = ("requests", "completed", "errors", "makespan_s", "throughput_interactions_per_s",
@@ -393,7 +393,7 @@ def serving_legs(args):
         "evaluate_512": {
             "workload": "512 evaluation requests, jittered-lattice boxes, N log-uniform in "
                         "[1e3, 2e5] snapped to n^3, FP64 or FP32-pair with probability 1/2, "
-                        "HBM budget 1 GiB, 8 slots, one stream each",
+                        "HBM budget 1 GiB, 4 slots (one per hardware queue), one stream each",
             "budget_bytes": ev["budget_bytes"],
             "saturated_all_at_t0": {k: ev["saturated"][k] for k in keep},
             "poisson_arrivals_per_s": ev["arrival_rate_per_s"],
@@ -402,7 +402,7 @@ def serving_legs(args):
             "workload": f"64 integration requests, blob-in-lattice boxes, N log-uniform in "
                         f"[1e4, 1e6] snapped to n^3, {args.serve_steps} KDK steps each, "
                         "FP32-pair pair terms, FP64 state, resident, graph replay, "
-                        "HBM budget 16 GiB, 8 slots",
+                        "HBM budget 16 GiB, 4 slots",
             "budget_bytes": it["budget_bytes"],
             "steps_total": it["steps_total"],
             "result": {k: it["result"][k] for k in keep},

@@ -845,7 +845,6 @@ sph_status sph_set_params(sph_ctx *c, const sph_params *p)
 {
     if (!c) return SPH_EINVAL;
     TRY(check_params(c, p));
-    bool regrow = p->leaf_size < c->p.leaf_size;
     if (c->graph_exec || c->graph) {
         // captured steps carry the old parameters (argument blocks and kernel
         // variants): let any replay in flight finish, then drop them
@@ -854,8 +853,10 @@ sph_status sph_set_params(sph_ctx *c, const sph_params *p)
     }
     c->p = *p;
     set_box(c);
+    // the buffers are sized by the particle capacity alone (the node bound
+    // holds for any leaf size; the candidate lists grow on next use if the
+    // new leaf size or kernel needs more), so nothing is reallocated here
     c->built = false;
-    if (regrow) c->node_cap = 0;   // force a re-plan of the tree storage on next use
     return SPH_OK;
 }
 

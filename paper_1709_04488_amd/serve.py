@@ -583,7 +583,7 @@ def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=
 
 
 def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200,
-               budget_gib: float = None, slots: int = 8, mode: str = "streams",
+               budget_gib: float = None, slots: int = 4, mode: str = "streams",
                load: float = 0.8, max_side: int = None, leaf="auto", tune_table: str = None,
                threads: bool = True, progress: bool = True) -> dict:
     """Serve one of the two workloads and summarise it.  evaluate: a closed
@@ -641,7 +641,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--budget-gib", type=float, default=None,
                     help="HBM budget (default 1 GiB for evaluate, 16 GiB for integrate)")
-    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--mode", choices=["streams", "batched"], default="streams")
     ap.add_argument("--load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured saturated capacity")
