@@ -198,6 +198,19 @@ __device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work
     }
 }
 
+// Status of a wave's particles: when any lane raises `cond`, set `flag` in
+// status[0] and add the number of such lanes to status[word], one atomic
+// each per wave (a set whose particles all fail then costs one atomic per
+// leaf, not one per particle).  Called by every lane of the wave.
+__device__ inline void report(int32_t *status, bool cond, int32_t flag, int word)
+{
+    const int cnt = (int)__popcll(__ballot(cond));
+    if (cnt && (threadIdx.x & (kWave - 1)) == 0) {
+        atomicOr(&status[0], flag);
+        atomicAdd(&status[word], cnt);
+    }
+}
+
 // Copy the device tree description into LDS once per block.
 __device__ inline void load_tree(const TreeInfo *__restrict__ src, TreeInfo &dst)
 {
@@ -1149,27 +1162,22 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 if (wr.lev) overflows++;
             }
         }
+        bool bad = false, slow = false, wide = false;
         if (active && q == 0) {
             A.h[i] = h_out;
             A.rho[i] = rho_out;
             A.omega[i] = om_out;
             A.nngb[i] = n_out;
-            bool bad = !isfinite(h_out) || !isfinite(rho_out) || !isfinite(om_out) || !(rho_out > 0.0);
-            if (bad) {
-                atomicOr(&A.status[0], kFlagNonFinite);
-                atomicAdd(&A.status[2], 1);
-            } else if (!conv) {
-                atomicOr(&A.status[0], kFlagNotConverged);
-                atomicAdd(&A.status[1], 1);
-            }
+            bad = !isfinite(h_out) || !isfinite(rho_out) || !isfinite(om_out) || !(rho_out > 0.0);
+            slow = !bad && !conv;
             if (bx.periodic) {
-                double Lmin = fmin(fmin(bx.len[0], bx.len[1]), bx.len[2]);
-                if (!(2.0 * RK * h_out < Lmin)) {
-                    atomicOr(&A.status[0], kFlagStencil);
-                    atomicAdd(&A.status[3], 1);
-                }
+                const double Lmin = fmin(fmin(bx.len[0], bx.len[1]), bx.len[2]);
+                wide = !(2.0 * RK * h_out < Lmin);
             }
         }
+        report(A.status, bad, kFlagNonFinite, 2);
+        report(A.status, slow, kFlagNotConverged, 1);
+        report(A.status, wide, kFlagStencil, 3);
         iter_max = iter > iter_max ? iter : iter_max;
         evals += wave_sum_int(evals_leaf);
         wave_lds_sync();   // the home table is rewritten for the next leaf
@@ -1474,6 +1482,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             cys = group_sum<LPP>(cys);
             czs = group_sum<LPP>(czs);
         }
+        bool bad = false;
         if (active && q == 0) {
             const double vsig = cnt > 0 ? vs_max : 2.0 * ci;
             F.ax[i] = axi;
@@ -1489,12 +1498,10 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                 F.divv[i] = -dvs / orho;
                 F.curlv[i] = sqrt((cxs * cxs + cys * cys) + czs * czs) / orho;
             }
-            if (!isfinite(axi) || !isfinite(ayi) || !isfinite(azi) || !isfinite(dui) ||
-                !isfinite(vsig)) {
-                atomicOr(&F.status[0], kFlagNonFinite);
-                atomicAdd(&F.status[2], 1);
-            }
+            bad = !isfinite(axi) || !isfinite(ayi) || !isfinite(azi) || !isfinite(dui) ||
+                  !isfinite(vsig);
         }
+        report(F.status, bad, kFlagNonFinite, 2);
         pairs_total += wave_sum_int((q == 0 && active) ? cnt : 0);
         wave_lds_sync();   // the home table is rewritten for the next leaf
     });
