@@ -183,9 +183,11 @@ def measured_valu_insts(tag: str, kernel: str):
 
 def prof_tag(args, prec: str):
     """Key of the committed counter runs that match this invocation: workload,
-    precision, leaf size and, when on, the artificial conductivity."""
+    precision, leaf size and, when on, the artificial conductivity and the
+    quintic kernel."""
     ac = f"_ac{args.alpha_ac:g}{args.ac_signal}" if args.alpha_ac > 0.0 else ""
-    return f"{args.config}_{prec}_g{args.leaf_used[prec]['leaf']}{ac}"
+    kern = "_quintic" if getattr(args, "kernel", "m4") == "quintic" else ""
+    return f"{args.config}_{prec}_g{args.leaf_used[prec]['leaf']}{ac}{kern}"
 
 
 def roofline(res, prec: str, tag: str = None, phase: str = "cold"):
@@ -443,6 +445,8 @@ def main():
     ap.add_argument("--alpha-ac", type=float, default=0.0,
                     help="artificial conductivity strength for every run (default 0: none)")
     ap.add_argument("--ac-signal", default="wadsley", choices=["wadsley", "price"])
+    ap.add_argument("--kernel", default="m4", choices=["m4", "quintic"],
+                    help="smoothing kernel of every leg (default M4, the paper's headline)")
     ap.add_argument("--no-largest", action="store_true",
                     help="skip the 4,194,304-particle Plummer leg (FP32-pair)")
     ap.add_argument("--no-serving", action="store_true", help="skip the two served workloads")
@@ -474,6 +478,9 @@ def main():
         from paper_1709_04488_amd import workloads as W
         w = W.Workload(w.name, w.arrays, {**w.setup, "alpha_ac": args.alpha_ac,
                                           "ac_signal": 0 if args.ac_signal == "wadsley" else 1})
+    if args.kernel == "quintic":
+        from paper_1709_04488_amd import workloads as W
+        w = W.Workload(w.name, w.arrays, {**w.setup, "kernel": 1})
     gen_s = time.perf_counter() - t_gen
     print(f"# workload {w.name} N={w.n} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
@@ -533,7 +540,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: N={w.n}, "
                                + ("periodic unit box" if w.setup["periodic"] else "isolated")
-                               + f", eta={w.setup['eta']}, M4, alpha_AV=1, beta_AV=2, "
+                               + f", eta={w.setup['eta']}, "
+                               + ("quintic" if args.kernel == "quintic" else "M4")
+                               + ", alpha_AV=1, beta_AV=2, "
                                + (f"alpha_AC={args.alpha_ac:g} ({args.ac_signal}), "
                                   if args.alpha_ac > 0.0 else "")
                                + f"{'FP64' if head_key == 'fp64' else 'FP32-pair'}, "
