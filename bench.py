@@ -314,7 +314,7 @@ def rows_legs(args, w, shape):
         "value": r["value"], "unit": "interactions/s", "ms_per_step": r["ms_per_step"],
         "interactions_per_step": r["interactions"],
         "density_neighbours_mean": r["info"]["n_dens_pairs"] / w.n,
-        "roofline": roofline(r, "fp64"),
+        "roofline": roofline(r, "fp64", tag=f"{args.config}_fp64_g{shape['leaf']}_quintic"),
         "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()}}
     print(f"# quintic fp64: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     kw = tune.params_kw(shape)
