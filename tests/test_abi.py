@@ -56,6 +56,20 @@ def test_default_params_match_paper_values():
     assert d["leaf_size"] in (8, 16, 32)
     # no conductivity unless asked for; the paper's default signal speed
     assert d["alpha_ac"] == 0.0 and d["ac_signal"] == sph.SPH_AC_WADSLEY
+    # M4 kernel, global time-steps, the full LDS stage and one leaf per claim
+    assert d["kernel"] == sph.SPH_KERNEL_M4 and d["block_lmax"] == 0
+    assert d["stage_leaves"] == 0 and d["claim_leaves"] == 0
+
+
+def test_python_defaults_equal_the_library_defaults():
+    from paper_1709_04488_amd import sph
+    sph.load()
+    d = sph.default_params_from_library()
+    c = sph.Params().c()
+    for f, _ in sph._Params._fields_:
+        v = getattr(c, f)
+        v = tuple(v) if f in ("box_lo", "box_hi") else v
+        assert v == d[f], f
 
 
 def test_struct_layouts_match_header():
