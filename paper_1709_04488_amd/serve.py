@@ -335,6 +335,7 @@ class GpuExecutor:
         # run without the interpreter lock); each slot's context is used by
         # one thread at a time
         self.pool = None
+        self.inflight = set()   # worker-thread futures not yet finished
         if threads and mode == "streams":
             from concurrent.futures import ThreadPoolExecutor
             self.pool = ThreadPoolExecutor(max_workers=max_slots)
@@ -448,8 +449,10 @@ class GpuExecutor:
 
     def start(self, items):
         if self.pool is not None:
-            return [{"req": req, "future": self.pool.submit(self._serve_one, req, self.slots[sidx])}
-                    for req, sidx in items]
+            hs = [{"req": req, "future": self.pool.submit(self._serve_one, req, self.slots[sidx])}
+                  for req, sidx in items]
+            self.inflight.update(h["future"] for h in hs)
+            return hs
         torch = self.torch
         handles = [None] * len(items)
         batch = []
@@ -475,6 +478,7 @@ class GpuExecutor:
 
     def finish(self, h):
         if "future" in h:
+            self.inflight.discard(h["future"])
             return h["future"].result()
         return self._finish(h)
 
@@ -510,6 +514,15 @@ class GpuExecutor:
             sl.ctx = None
 
     def wait(self, clock, next_arrival: float):
+        """Until a running request completes or the next one arrives.  With
+        worker threads the wait wakes on the first completion itself;
+        otherwise the device events are polled every 0.2 ms."""
+        if self.inflight:
+            from concurrent.futures import FIRST_COMPLETED
+            from concurrent.futures import wait as wait_futures
+            t = next_arrival - clock.now() if math.isfinite(next_arrival) else 0.05
+            wait_futures(self.inflight, timeout=max(0.0, min(t, 0.05)), return_when=FIRST_COMPLETED)
+            return
         time.sleep(0.0002)
 
 
