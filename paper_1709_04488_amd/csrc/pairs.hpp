@@ -1,21 +1,24 @@
-// Pair loops: density + Newton-Raphson h solve, hydro forces, neighbour export.
+// Pair loops: density + Newton-Raphson h solve, hydro forces, neighbour
+// export, MFV geometry.
 //
 // Work decomposition (the GPU analogue of the paper's per-leaf-cell neighbour
 // gathering, section 4.2, with a leaf as the unit of work as in its OpenMP
 // loop, section 5.2.1): one wavefront per home leaf of at most G sorted
 // particles, 64/G lanes per particle.  The wave walks the box tree to collect
 // the leaves that can hold neighbours of its particles into an LDS list.
-// Candidate leaves are then handled 64/G at a time (64 candidate particles):
+// Candidate leaves are then handled 128/G at a time (128 candidate slots):
 //   stage  -- one coalesced load per field brings their positions into LDS;
-//   test   -- every lane tests its share of the staged candidates against its
-//             particle and records each hit as a one-byte slot index in its
-//             own LDS hit buffer (no pair arithmetic yet);
-//   flush  -- every lane evaluates the pair terms of its recorded hits.
-// The test is cheap and runs for every candidate; the expensive pair terms
-// run only for hits, with the lanes compacted (a wave-wide branch on "any
-// lane hit" would otherwise execute them for almost every candidate).  Each
-// output is accumulated by its own lanes in a fixed order, so results are
-// deterministic and need no atomics.
+//   test   -- each (home particle, staged leaf) combination is first judged
+//             by the distance from the particle to the leaf's box; the
+//             passing ones are dealt out over the 64 lanes, which test their
+//             candidates and set hit bits in a per-particle 128-bit mask
+//             (no pair arithmetic yet);
+//   flush  -- each particle's lanes evaluate the pair terms of its hits.
+// The test is cheap and runs for every candidate of a passing combination;
+// the expensive pair terms run only for hits, with the lanes compacted (a
+// wave-wide branch on "any lane hit" would otherwise execute them for almost
+// every candidate).  Each output is accumulated by its own lanes in a fixed
+// order, so results are deterministic and need no atomics.
 //
 // This header holds the kernels, templated on the smoothing kernel; it is
 // compiled by pairs_m4.hip and pairs_quintic.hip only.

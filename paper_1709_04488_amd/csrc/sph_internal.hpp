@@ -312,7 +312,7 @@ sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted, const doubl
 sph_status iota(sph_ctx *c, int64_t n, uint32_t *v);
 int64_t node_count_bound(int64_t n);
 
-// ---- pairs.hip ---------------------------------------------------------------
+// ---- pairs.hip (dispatch) and pairs.hpp (kernels) -------------------------
 sph_status run_density(sph_ctx *c, int64_t n);
 sph_status run_forces(sph_ctx *c, int64_t n);
 // batched pair loops: prepare writes each set's argument block on its
