@@ -45,6 +45,7 @@ constexpr int64_t bytes_per_particle()
                                       //    active flag, limiter level and mark)
     b += 8 * 8 + 4 + 2 * 8;    // t: block re-sort (a, du, rho, Omega, dt, vsig, level, ticks)
     b += 4;                    // active particles per leaf
+    b += 4;                    // active leaves (the list; the tile counts are counted apart)
     return b;
 }
 
@@ -217,6 +218,9 @@ sph_status lay_out(sph_ctx *c, int64_t cap, Take take)
     A_(S.ts, cap); A_(S.te, cap); A_(T.ts, cap); A_(T.te, cap);
     A_(S.act, cap); A_(S.lmx, cap); A_(S.mark, cap);
     A_(c->leaf_act, cap);
+    A_(c->act_list, cap);
+    A_(c->act_tile, act_tiles(cap));
+    A_(c->act_cnt, 1);
     A_(c->nodes, node_count_bound(cap));
     A_(c->hist, hist_words(cap));
 #undef A_
@@ -629,10 +633,10 @@ constexpr int64_t static_node_bound(int64_t n)
     return tot;
 }
 // the static array: every buffer of lay_out at capacity kStaticMaxN (256-byte
-// aligned slices: 80 buffers at most), and the candidate lists
+// aligned slices: 96 buffers at most), and the candidate lists
 constexpr int64_t kStaticBytes =
     kStaticMaxN * bytes_per_particle() + static_node_bound(kStaticMaxN) * (int64_t)sizeof(Node) +
-    4 * (256 * ((kStaticMaxN + 4095) / 4096) + 256) + 80 * 256 +
+    4 * (256 * ((kStaticMaxN + 4095) / 4096) + 256) + 4 * (act_tiles(kStaticMaxN) + 1) + 96 * 256 +
     kStaticListBlocks * 2 * (int64_t)Kern<SPH_KERNEL_M4>::list * 32 * (int64_t)sizeof(double);
 
 static __device__ __align__(256) unsigned char scratch[kStaticBytes];

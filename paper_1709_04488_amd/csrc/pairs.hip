@@ -110,6 +110,8 @@ sph_status density_prepare(sph_ctx *c, int64_t n)
     a.max_iter = c->p.h_max_iter;
     a.active = c->f_act;
     a.leaf_act = c->f_act ? c->leaf_act : nullptr;
+    a.leaf_list = c->f_act ? c->act_list : nullptr;
+    a.leaf_count = c->f_act ? c->act_cnt : nullptr;
     const void *req[] = {a.nodes, a.x, a.y, a.z, a.m, a.h, a.rho, a.omega, a.nngb, a.status,
                          a.counts, a.tree, a.lstart, a.work, c->d_dargs};
     for (const void *q : req)
@@ -144,6 +146,8 @@ sph_status forces_prepare(sph_ctx *c, int64_t n)
     a.omega = c->s.omega;
     a.active = c->f_act;
     a.leaf_act = c->f_act ? c->leaf_act : nullptr;
+    a.leaf_list = c->f_act ? c->act_list : nullptr;
+    a.leaf_count = c->f_act ? c->act_cnt : nullptr;
     if (c->f_block) {
         a.lev = c->s.lev;
         a.lmx = c->s.lmx;

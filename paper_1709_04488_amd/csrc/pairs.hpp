@@ -845,7 +845,8 @@ __device__ inline void batch_prefix(const Batch<Args> &B, uint32_t *pre)
         uint32_t acc = 0;
         pre[0] = 0;
         for (int r = 0; r < B.nreq; r++) {
-            acc += (uint32_t)B.req[r]->tree->cnt[0];
+            const uint32_t *lc = B.req[r]->leaf_count;
+            acc += lc ? *lc : (uint32_t)B.req[r]->tree->cnt[0];
             pre[r + 1] = acc;
         }
     }
@@ -926,7 +927,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             load_tree(Ap->tree, T);
         }
         const auto &A = *Ap;
-        const int64_t leaf = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
+        const int64_t li = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
+        const int64_t leaf = A.leaf_list ? (int64_t)as_const(A.leaf_list)[li] : li;
         if (A.leaf_act && as_const(A.leaf_act)[leaf] == 0) return;   // no active particle
         const Box bx = load_const(&B.req[r]->box);
         const int64_t first = as_const(A.lstart)[leaf];
@@ -1233,7 +1235,8 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
             load_tree(Fp->tree, T);
         }
         const auto &F = *Fp;
-        const int64_t leaf = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
+        const int64_t li = gleaf - (int64_t)__builtin_amdgcn_readfirstlane(pre[r]);
+        const int64_t leaf = F.leaf_list ? (int64_t)as_const(F.leaf_list)[li] : li;
         if (F.leaf_act && as_const(F.leaf_act)[leaf] == 0) return;   // no active particle
         const Box bx = load_const(&B.req[r]->box);
         const double alpha = F.alpha, beta = F.beta;

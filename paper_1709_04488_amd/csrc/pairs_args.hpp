@@ -40,8 +40,10 @@ struct DensArgs {
     double walk_margin;
     int32_t max_iter;
     // block time-steps: particles that take part (nullptr: all) and their
-    // count per leaf (leaves without any are skipped)
+    // count per leaf (leaves without any are skipped); the home leaves are
+    // then leaf_list[0 .. *leaf_count) (nullptr: every leaf)
     const int32_t *active, *leaf_act;
+    const uint32_t *leaf_list, *leaf_count;
 };
 
 struct ForceArgs {
@@ -69,10 +71,12 @@ struct ForceArgs {
     const double *alpha_p;
     const double *omega;
     double *divv, *curlv;
-    // block time-steps: the active set (nullptr: all), its count per leaf, and
-    // the limiter: levels, deepest neighbour level (out, active particles),
+    // block time-steps: the active set (nullptr: all), its count per leaf, the
+    // home leaves leaf_list[0 .. *leaf_count) (nullptr: every leaf), and the
+    // limiter: levels, deepest neighbour level (out, active particles),
     // wake-up marks of inactive neighbours (atomic max), level spread lim
     const int32_t *active, *leaf_act;
+    const uint32_t *leaf_list, *leaf_count;
     const int32_t *lev;
     int32_t *lmx, *mark;
     int32_t lim;

@@ -52,6 +52,11 @@ constexpr int kArgBytes = 1024;  // device argument block of one pair-kernel lau
 // multiple of the XCD count.  Each block owns a slice of the density loop's
 // candidate-list scratch, so the cap also bounds that scratch.
 constexpr int64_t kMaxPairBlocks = 256 * 16;
+
+// Active-leaf compaction of block time-steps: leaves per block, and the
+// per-block counts (one more than the blocks, for the bound of n leaves)
+constexpr int kActTile = 1024;
+constexpr int64_t act_tiles(int64_t cap) { return (cap + kActTile - 1) / kActTile + 1; }
 inline unsigned pair_grid(int64_t n)
 {
     int64_t blocks = (n + 7) / 8;
@@ -247,6 +252,10 @@ struct sph_ctx {
     bool res_alpha = false;     // the resident state carries per-particle alpha
     sph::BlockClock *d_clock = nullptr;   // block time-steps (device)
     int32_t *leaf_act = nullptr;     // active particles per leaf of the current sub-step
+    // the leaves with an active particle, in leaf order, and their number (on
+    // the device): the home leaves of the pair loops in a sub-step; per-tile
+    // counts, then offsets, of the compaction that lists them
+    uint32_t *act_list = nullptr, *act_tile = nullptr, *act_cnt = nullptr;
     double *d_scal = nullptr;   // [0] dt_next [1] dt_last [2] time [3] KE [4] TE [5..7] P
                                 // [8] smallest, [9] largest mass of the last density pass
     // device counters, indexed by the kCnt* constants

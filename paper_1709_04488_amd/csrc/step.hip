@@ -530,6 +530,76 @@ __global__ __launch_bounds__(256) void k_leaf_active(BlockArgs B)
                                                   (unsigned long long)cnt);
 }
 
+// The leaves with an active particle, in leaf order: a count per tile of
+// kActTile leaves, one block turning the counts into offsets (and the total),
+// then every tile writing its active leaves at its offset, ranked by ballots
+// within the waves and by the waves' counts across the block.
+__global__ __launch_bounds__(256) void k_act_count(BlockArgs B, uint32_t *__restrict__ tile)
+{
+    const int64_t L = B.tree->cnt[0];
+    const int64_t base = blockIdx.x * (int64_t)kActTile;
+    int c = 0;
+    for (int k = threadIdx.x; k < kActTile; k += 256) {
+        const int64_t l = base + k;
+        c += (l < L && B.leaf_act[l] != 0) ? 1 : 0;
+    }
+    __shared__ int part[4];
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) tile[blockIdx.x] = (uint32_t)(part[0] + part[1] + part[2] + part[3]);
+}
+
+__global__ __launch_bounds__(1024) void k_act_scan(BlockArgs B, uint32_t *__restrict__ tile,
+                                                    uint32_t *__restrict__ total)
+{
+    const int64_t L = B.tree->cnt[0];
+    const int64_t tiles = (L + kActTile - 1) / kActTile;
+    __shared__ uint32_t sh[1024];
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < tiles; b0 += 1024) {
+        const int64_t b = b0 + threadIdx.x;
+        const uint32_t v = b < tiles ? tile[b] : 0u;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const uint32_t t = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (b < tiles) tile[b] = carry + sh[threadIdx.x] - v;   // exclusive offset
+        carry += sh[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void k_act_scatter(BlockArgs B, const uint32_t *__restrict__ tile,
+                                                     uint32_t *__restrict__ list)
+{
+    const int64_t L = B.tree->cnt[0];
+    const int64_t base = blockIdx.x * (int64_t)kActTile;
+    if (base >= L) return;   // the whole block: no tile of the tree's leaves
+    __shared__ uint32_t wsum[4];
+    uint32_t off = tile[blockIdx.x];
+    for (int r = 0; r < kActTile / 256; r++) {
+        const int64_t l = base + r * 256 + threadIdx.x;
+        const bool a = l < L && B.leaf_act[l] != 0;
+        const uint64_t m = __ballot(a);
+        const int w = threadIdx.x >> 6;
+        const uint32_t rank = (uint32_t)__popcll(m & __lanemask_lt());
+        if ((threadIdx.x & 63) == 0) wsum[w] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = 0;
+        for (int k = 0; k < w; k++) before += wsum[k];
+        if (a) list[off + before + rank] = (uint32_t)l;
+        const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+        off += tot;
+    }
+}
+
 // closing kick of the active particles with their new accelerations
 __global__ __launch_bounds__(256) void k_block_close(BlockArgs B)
 {
@@ -730,6 +800,12 @@ sph_status block_predict(sph_ctx *c, int64_t n)
     hipLaunchKernelGGL(k_block_predict, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, B);
     // leaves: at most n
     hipLaunchKernelGGL(k_leaf_active, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, B);
+    // the pair loops' home leaves: those with an active particle
+    const unsigned tiles = (unsigned)((n + kActTile - 1) / kActTile);
+    hipLaunchKernelGGL(k_act_count, dim3(tiles), dim3(256), 0, c->stream, B, c->act_tile);
+    hipLaunchKernelGGL(k_act_scan, dim3(1), dim3(1024), 0, c->stream, B, c->act_tile, c->act_cnt);
+    hipLaunchKernelGGL(k_act_scatter, dim3(tiles), dim3(256), 0, c->stream, B, c->act_tile,
+                       c->act_list);
     return hip_check(c, hipGetLastError(), "block_predict");
 }
 
