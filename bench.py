@@ -314,6 +314,8 @@ def rows_legs(args, w, shape):
         "value": r["value"], "unit": "interactions/s", "ms_per_step": r["ms_per_step"],
         "interactions_per_step": r["interactions"],
         "density_neighbours_mean": r["info"]["n_dens_pairs"] / w.n,
+        "nr_iter_mean": r["info"]["nr_iter_total"] / w.n,
+        "density_list_overflows": r["info"]["dens_list_overflows"],
         "roofline": roofline(r, "fp64", tag=f"{args.config}_fp64_g{shape['leaf']}_quintic"),
         "kernel_ms": {k: round(v, 4) for k, v in r["kernel_ms"].items()}}
     print(f"# quintic fp64: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
@@ -554,6 +556,7 @@ def main():
         "roofline": roofline(head, prec_name, tag=prof_tag(args, prec_name)),
         "nr_iter_max": head["info"]["nr_iter_max"],
         "walk_overflows": head["info"]["walk_overflows"],
+        "density_list_overflows": head["info"]["dens_list_overflows"],
         "dens_leaf_visits": head["info"]["dens_leaf_visits"],
         "dens_walks": head["info"]["dens_walks"],
         "density_pair_evals": head["info"]["dens_pair_evals"],
