@@ -509,6 +509,106 @@ size_t sph_plan_bytes(const sph_params *p, int64_t n);
 sph_status sph_enable_kernel_timing(sph_ctx *ctx, int32_t enable);
 sph_status sph_kernel_times(sph_ctx *ctx, int32_t which, double *ms, int64_t *launches);
 
+/*
+ * Request executor for serving many independent particle sets from host
+ * memory.  A server owns `slots` slots on the HIP device that is current
+ * at sph_server_create.  Each slot has one worker thread, one non-blocking
+ * HIP stream, one context and device arrays plus pinned host staging, all
+ * grown to the largest request the slot has run and kept between requests.
+ * A request handed to an idle slot runs entirely on that slot's thread:
+ *   - its host inputs go to the device in one copy through the staging;
+ *   - evaluate: sph_evaluate;
+ *   - integrate: sph_upload_state, then steps with the CFL step (dt <= 0)
+ *     replayed two at a time from sph_capture_steps (plus one sph_step for
+ *     an odd count), then sph_download_state;
+ *   - the outputs come back in one copy and are written into the caller's
+ *     host arrays, and the request is marked done.
+ * Different slots run concurrently; their kernels overlap on the device.
+ * Which request goes to which slot and when (admission under an HBM budget)
+ * is the caller's choice: sph_server_plan_bytes gives what a slot holds.
+ * Results are bit-for-bit those of the same calls made one by one on a
+ * fresh context: the library's results do not depend on what a context
+ * ran before.
+ */
+#define SPH_REQUEST_EVALUATE  0
+#define SPH_REQUEST_INTEGRATE 1
+#define SPH_REQUEST_ERROR_LEN 160
+
+/* FP64 fields of a request, in this order (the first nine are its inputs) */
+enum {
+    SPH_F_X = 0, SPH_F_Y, SPH_F_Z, SPH_F_VX, SPH_F_VY, SPH_F_VZ, SPH_F_M, SPH_F_U, SPH_F_H,
+    SPH_F_RHO, SPH_F_OMEGA, SPH_F_PRESSURE, SPH_F_CS, SPH_F_AX, SPH_F_AY, SPH_F_AZ,
+    SPH_F_DUDT, SPH_F_VSIG, SPH_F_DT,
+    SPH_NF64,
+    SPH_NIN = SPH_F_H + 1
+};
+
+typedef struct {
+    /* set by the caller */
+    int32_t kind;          /* SPH_REQUEST_EVALUATE or SPH_REQUEST_INTEGRATE */
+    int32_t nsteps;        /* integrate: number of steps (>= 0) */
+    sph_params params;     /* method and launch parameters of this request */
+    int64_t n;             /* particles (>= 0) */
+    const double *in[SPH_NIN]; /* HOST inputs, n values each, all non-NULL: x, y, z,
+                              vx, vy, vz, m, u and the guess of h */
+    double *out[SPH_NF64]; /* HOST outputs by field (n values each), NULL when not
+                              wanted.  evaluate writes h .. dt (the fields
+                              sph_evaluate writes, h the solved value); integrate
+                              writes every field but m (the state after the last
+                              step, as sph_download_state gives it).  Entries a
+                              kind does not write are ignored. */
+    int32_t *iout[2];      /* HOST outputs nngb, nforce (n each), or NULL */
+    /* set by the executor once the request is done */
+    int32_t status;        /* sph_status of the request */
+    int32_t slot;          /* slot that ran it */
+    int64_t interactions;  /* n_dens_pairs + n_force_pairs of the last
+                              evaluation, times max(nsteps, 1) for integrate */
+    sph_state_stats info;  /* sph_state_info after the request (zero on error) */
+    char error[SPH_REQUEST_ERROR_LEN]; /* readable error ("" when status is SPH_OK) */
+} sph_request;
+
+typedef struct sph_server sph_server;
+
+/* Start `slots` (1..64) worker threads on the current HIP device.  Nothing is
+ * allocated on the device until a slot runs its first request.  *s is NULL
+ * on error (SPH_EINVAL for a bad slot count, SPH_EDEVICE without a device). */
+sph_status sph_server_create(sph_server **s, int32_t slots);
+
+/* Hand request r to slot `slot`, which must be idle (no request submitted
+ * and not yet returned by sph_server_wait).  Returns at once.  r and every
+ * host array it names stay owned by the caller, who must keep them valid and
+ * leave them untouched until sph_server_wait has returned r.  A bad slot, a
+ * busy slot or a malformed request (bad kind, n < 0, nsteps < 0, a missing
+ * input) returns SPH_EINVAL and queues nothing; errors of
+ * the run itself (parameters, memory, the method) come back in r->status and
+ * r->error.  A request of n = 0 completes at once with SPH_OK. */
+sph_status sph_server_submit(sph_server *s, int32_t slot, sph_request *r);
+
+/* Completed requests, oldest first: stores up to `max` of them in done[] and
+ * returns how many (0 when none completed within timeout_s seconds; 0 s
+ * polls, a negative timeout waits without limit while any request is
+ * running).  A slot is idle again before its request is returned.  Returns
+ * -1 for bad arguments. */
+int32_t sph_server_wait(sph_server *s, sph_request **done, int32_t max, double timeout_s);
+
+/* Free the context, device arrays and pinned staging of an idle slot (its
+ * next request allocates them again).  SPH_EINVAL for a bad or busy slot. */
+sph_status sph_server_release(sph_server *s, int32_t slot);
+
+/* Device bytes slot `slot` holds now (context plus particle arrays);
+ * 0 for a bad slot. */
+size_t sph_server_slot_bytes(sph_server *s, int32_t slot);
+
+/* Device bytes a slot needs to run a request of n particles with parameters
+ * p: sph_plan_bytes plus the request's particle arrays (19 FP64 and 2 int32
+ * values per particle).  No allocation is made. */
+size_t sph_server_plan_bytes(const sph_params *p, int64_t n);
+
+/* Wait for the running requests, stop the threads and free everything the
+ * server owns.  Requests still unreturned by sph_server_wait are complete
+ * when it returns.  NULL is a no-op. */
+sph_status sph_server_destroy(sph_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsph.so")
-SOURCES = ["api.hip", "build.hip", "pairs.hip", "pairs_m4.hip", "pairs_quintic.hip", "step.hip"]
+SOURCES = ["api.hip", "build.hip", "pairs.hip", "pairs_m4.hip", "pairs_quintic.hip", "step.hip",
+           "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Wno-unused-variable",

@@ -174,7 +174,15 @@ __device__ inline int wave_max_int(int v)
 // share that XCD's L2), then helps the others.  Claims go through one atomic
 // counter per eighth, `claim` consecutive leaves at a time; every leaf is
 // processed by exactly one wave, so results do not depend on which wave took
-// it.
+// it.  Atomics on one address serialise (~0.1 us each), so claims are kept
+// few: a block's first claim in its own eighth is static (its rank among the
+// eighth's blocks; the counter hands out the claims after those), and after
+// draining its own eighth a block helps the following eighths in turn and
+// stops at the first one it finds exhausted.  Every eighth is still drained
+// by its own blocks; a block makes no atomic at start and one failing claim
+// on another counter at the end, instead of one on each of them (for a small
+// set that finishes early, those tail claims were a large part of the
+// launch).
 template <class Fn>
 __device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work, int claim,
                                           Fn fn)
@@ -182,22 +190,30 @@ __device__ inline void for_each_home_leaf(int64_t L, uint32_t *__restrict__ work
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t per = (L + kXcds - 1) / kXcds;
     const int x0 = (int)(blockIdx.x % kXcds);
+    const uint32_t rank = blockIdx.x / kXcds;          // among the blocks of eighth x0
+    const uint32_t nstatic = gridDim.x / kXcds;        // static first claims per eighth
     for (int r = 0; r < kXcds; r++) {
         const int x = (x0 + r) % kXcds;
         const int64_t beg = x * per;
         const int64_t end = beg + per < L ? beg + per : L;
         if (beg >= end) continue;
-        for (;;) {
-            uint32_t c = 0;
-            if (lane == 0) c = atomicAdd(&work[x], 1u);
-            // wave-uniform from here on (scalar registers): the leaf's argument
-            // block, node and particle range are then loaded once per wave
-            c = (uint32_t)__builtin_amdgcn_readlane((int)c, 0);
+        bool got = false;
+        for (int k = 0;; k++) {
+            uint32_t c = rank;
+            if (r > 0 || k > 0 || rank >= nstatic) {   // (a grid not a multiple of 8)
+                if (lane == 0) c = nstatic + atomicAdd(&work[x], 1u);
+                // wave-uniform from here on (scalar registers): the leaf's
+                // argument block, node and particle range are then loaded once
+                // per wave
+                c = (uint32_t)__builtin_amdgcn_readlane((int)c, 0);
+            }
             const int64_t leaf0 = beg + (int64_t)c * claim;
             if (leaf0 >= end) break;
+            got = true;
             const int64_t leaf1 = leaf0 + claim < end ? leaf0 + claim : end;
             for (int64_t leaf = leaf0; leaf < leaf1; leaf++) fn(leaf);
         }
+        if (r > 0 && !got) break;   // a helped eighth was already exhausted
     }
 }
 

@@ -23,6 +23,7 @@ exercises the scheduler without a GPU.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import heapq
 import json
 import math
@@ -287,6 +288,17 @@ class FakeExecutor:
         clock.sleep_until(t if math.isfinite(t) else clock.now() + 1e-3)
 
 
+def _request_params(sph, leaf_for, req: Request):
+    """sph.Params of a request: its setup and precision, with the launch shape
+    a tuner chooses (leaf size, stage depth, claim size) or the leaf size a
+    plain function gives."""
+    shape_of = getattr(leaf_for, "shape", None)
+    if shape_of is not None:
+        from .tune import params_kw
+        return sph.Params.from_setup(req.setup, precision=req.precision, **params_kw(shape_of(req)))
+    return sph.Params.from_setup(req.setup, precision=req.precision, leaf_size=leaf_for(req))
+
+
 class _Slot:
     def __init__(self, idx, stream, ctx):
         self.idx = idx
@@ -346,15 +358,7 @@ class GpuExecutor:
             self.pool = None
 
     def params(self, req: Request):
-        # a launch-shape tuner gives leaf size, stage depth and claim size;
-        # a plain function gives the leaf size only
-        shape_of = getattr(self.leaf_for, "shape", None)
-        if shape_of is not None:
-            from .tune import params_kw
-            return self.sph.Params.from_setup(req.setup, precision=req.precision,
-                                              **params_kw(shape_of(req)))
-        return self.sph.Params.from_setup(req.setup, precision=req.precision,
-                                          leaf_size=self.leaf_for(req))
+        return _request_params(self.sph, self.leaf_for, req)
 
     def slot_bytes(self, cap: int, leaf: int = 16) -> int:
         return 0 if cap == 0 else self.sph.plan_bytes(self.sph.Params(leaf_size=leaf or 16), cap)
@@ -526,6 +530,105 @@ class GpuExecutor:
         time.sleep(0.0002)
 
 
+class NativeExecutor:
+    """Requests through the library's own executor (sph_server_*): each slot's
+    native worker thread stages the inputs, copies them to the device, runs
+    the request on the slot's stream and writes the outputs into host arrays,
+    so the interpreter only admits requests and collects them.  A slot's
+    device memory is its context plus its particle arrays, both kept at the
+    slot's capacity (counted in slot_bytes, none per request)."""
+
+    OUT_EVAL = GpuExecutor.OUT_EVAL
+    OUT_INTEGRATE = ("x", "y", "z", "vx", "vy", "vz", "u", "h")
+
+    def __init__(self, max_slots: int, leaf_for=None, keep_outputs=False, download=True):
+        from . import sph
+        self.sph = sph
+        self.server = sph.Server(max_slots)
+        self.leaf_for = leaf_for or (lambda req: 16)
+        self.keep_outputs = keep_outputs
+        self.download = download or keep_outputs
+        self.host = [dict() for _ in range(max_slots)]   # reusable host outputs per slot
+        self.pending = {}                                # request address -> handle
+
+    def close(self):
+        self.server.close()
+
+    def params(self, req: Request):
+        return _request_params(self.sph, self.leaf_for, req)
+
+    def slot_bytes(self, cap: int, leaf: int = 16) -> int:
+        return 0 if cap == 0 else self.sph.server_plan_bytes(self.sph.Params(leaf_size=leaf or 16), cap)
+
+    def leaf_of(self, req: Request) -> int:
+        return int(self.leaf_for(req))
+
+    def array_bytes(self, req: Request) -> int:
+        return 0
+
+    def _outputs(self, slot: int, req: Request) -> dict:
+        if not self.download:
+            return {}
+        names = self.OUT_EVAL if req.kind == "evaluate" else self.OUT_INTEGRATE
+        n = req.n
+        out = {}
+        for k in names:
+            dt = np.int32 if k in self.sph.FIELDS_I32 else np.float64
+            if self.keep_outputs:
+                out[k] = np.empty(n, dtype=dt)
+                continue
+            buf = self.host[slot].get(k)
+            if buf is None or buf.size < n:
+                buf = np.empty(max(n, 1), dtype=dt)
+                self.host[slot][k] = buf
+            out[k] = buf[:n]
+        return out
+
+    def start(self, items):
+        hs = []
+        for req, slot in items:
+            kind = (self.sph.SPH_REQUEST_EVALUATE if req.kind == "evaluate"
+                    else self.sph.SPH_REQUEST_INTEGRATE)
+            outs = self._outputs(slot, req)
+            r, keep = self.sph.make_request(kind, req.arrays, self.params(req), req.nsteps, outs)
+            h = {"req": req, "r": r, "keep": keep, "outputs": outs, "done": False}
+            self.pending[ctypes.addressof(r)] = h
+            self.server.submit(slot, r)
+            hs.append(h)
+        return hs
+
+    def _collect(self, timeout: float):
+        for addr in self.server.wait(timeout):
+            self.pending.pop(addr)["done"] = True
+
+    def poll(self, h) -> bool:
+        if not h["done"]:
+            self._collect(0.0)
+        return h["done"]
+
+    def finish(self, h):
+        r, req = h["r"], h["req"]
+        h["keep"] = None
+        if r.status != self.sph.SPH_OK:
+            raise self.sph.SphError(r.status, r.error.decode(errors="replace"))
+        out = {"info": self.sph.stats_dict(r.info), "interactions": int(r.interactions)}
+        if self.keep_outputs:
+            out["outputs"] = h["outputs"]
+        return out
+
+    def release(self, slot: int):
+        self.server.release(slot)
+
+    def wait(self, clock, next_arrival: float):
+        """Until a running request completes (the library wakes the wait) or
+        the next one arrives."""
+        t = next_arrival - clock.now() if math.isfinite(next_arrival) else 0.05
+        if self.pending:
+            self._collect(max(0.0, min(t, 0.05)))
+        else:
+            clock.sleep_until(next_arrival if math.isfinite(next_arrival) else clock.now() + 1e-3)
+
+
 # ----------------------------------------------------------------------------
 # the two served workloads
 # ----------------------------------------------------------------------------
@@ -580,8 +683,11 @@ def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=
     (download=False stops at the device, for measurements of that part).
     threads: in streams mode, one worker thread per slot."""
     import torch
-    ex = GpuExecutor(slots, mode=mode, leaf_for=leaf_for, keep_outputs=keep_outputs,
-                     download=download, threads=threads)
+    if mode == "native":
+        ex = NativeExecutor(slots, leaf_for=leaf_for, keep_outputs=keep_outputs, download=download)
+    else:
+        ex = GpuExecutor(slots, mode=mode, leaf_for=leaf_for, keep_outputs=keep_outputs,
+                         download=download, threads=threads)
     sched = Scheduler(ex, budget, slots, WallClock(), progress=_progress if progress else None)
     t0 = sched.clock.now()
     try:
@@ -655,7 +761,9 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=None,
                     help="HBM budget (default 1 GiB for evaluate, 16 GiB for integrate)")
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--mode", choices=["streams", "batched"], default="streams")
+    ap.add_argument("--mode", choices=["native", "streams", "batched"], default="native",
+                    help="native: the library's executor threads; streams: one Python "
+                         "worker thread per slot; batched: one batched launch per admission")
     ap.add_argument("--load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured saturated capacity")
     ap.add_argument("--max-side", type=int, default=None)

@@ -36,7 +36,9 @@ EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream",
             "sph_batch_density", "sph_batch_forces", "sph_batch_evaluate", "sph_batch_step",
             "sph_capture_steps",
             "sph_replay_steps", "sph_plan_bytes", "sph_evaluate_noalloc", "sph_noalloc_max_n",
-            "sph_mfv_gradients", "sph_substep"]
+            "sph_mfv_gradients", "sph_substep", "sph_server_create", "sph_server_submit",
+            "sph_server_wait", "sph_server_release", "sph_server_slot_bytes",
+            "sph_server_plan_bytes", "sph_server_destroy"]
 
 
 class SphError(RuntimeError):
@@ -58,6 +60,11 @@ class _Params(ctypes.Structure):
                 ("block_lmax", ctypes.c_int32), ("block_lim", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("stage_leaves", ctypes.c_int32),
                 ("claim_leaves", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+SPH_REQUEST_EVALUATE, SPH_REQUEST_INTEGRATE = 0, 1
+REQUEST_ERROR_LEN = 160
+NIN = 9           # x .. h: a request's inputs, the first FP64 fields
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -96,6 +103,15 @@ class _Stats(ctypes.Structure):
                 ("block_active", ctypes.c_int64), ("block_updates", ctypes.c_int64),
                 ("block_time", ctypes.c_double), ("block_dt_max", ctypes.c_double),
                 ("block_synchronised", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nsteps", ctypes.c_int32), ("params", _Params),
+                ("n", ctypes.c_int64), ("in_", ctypes.c_void_p * NIN),
+                ("out", ctypes.c_void_p * 19), ("iout", ctypes.c_void_p * 2),
+                ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("interactions", ctypes.c_int64), ("info", _Stats),
+                ("error", ctypes.c_char * REQUEST_ERROR_LEN)]
 
 
 _lib = None
@@ -147,6 +163,13 @@ def load() -> ctypes.CDLL:
         "sph_noalloc_max_n": (i64, []),
         "sph_mfv_gradients": (ctypes.c_int, [vp, ctypes.POINTER(_MfvSet)]),
         "sph_substep": (ctypes.c_int, [vp]),
+        "sph_server_create": (ctypes.c_int, [ctypes.POINTER(vp), i32]),
+        "sph_server_submit": (ctypes.c_int, [vp, i32, ctypes.POINTER(_Request)]),
+        "sph_server_wait": (i32, [vp, ctypes.POINTER(vp), i32, d]),
+        "sph_server_release": (ctypes.c_int, [vp, i32]),
+        "sph_server_slot_bytes": (ctypes.c_size_t, [vp, i32]),
+        "sph_server_plan_bytes": (ctypes.c_size_t, [P, i64]),
+        "sph_server_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -154,6 +177,29 @@ def load() -> ctypes.CDLL:
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def stats_dict(st: _Stats) -> dict:
+    """sph_state_stats as a dict."""
+    return {"time": st.time, "dt_last": st.dt_last, "dt_next": st.dt_next,
+            "kinetic": st.kinetic, "thermal": st.thermal,
+            "momentum": tuple(st.momentum), "steps": st.steps,
+            "n_dens_pairs": st.n_dens_pairs, "n_force_pairs": st.n_force_pairs,
+            "dens_pair_evals": st.dens_pair_evals, "force_pair_evals": st.force_pair_evals,
+            "nr_iter_max": st.nr_iter_max, "walk_overflows": st.walk_overflows,
+            "dens_leaf_visits": st.dens_leaf_visits, "dens_walks": st.dens_walks,
+            "nr_iter_total": st.nr_iter_total,
+            "dens_candidate_tests": st.dens_candidate_tests,
+            "dens_box_tests": st.dens_box_tests,
+            "force_candidate_tests": st.force_candidate_tests,
+            "force_box_tests": st.force_box_tests,
+            "density_walk_overflows": st.density_walk_overflows,
+            "force_walk_overflows": st.force_walk_overflows,
+            "dens_list_overflows": st.dens_list_overflows,
+            "block_full_steps": st.block_full_steps, "block_substeps": st.block_substeps,
+            "block_active": st.block_active, "block_updates": st.block_updates,
+            "block_time": st.block_time, "block_dt_max": st.block_dt_max,
+            "block_synchronised": st.block_synchronised}
 
 
 @dataclass
@@ -408,25 +454,7 @@ class Context:
     def state_info(self) -> dict:
         st = _Stats()
         self._check(self.lib.sph_state_info(self.h, ctypes.byref(st)), "sph_state_info")
-        return {"time": st.time, "dt_last": st.dt_last, "dt_next": st.dt_next,
-                "kinetic": st.kinetic, "thermal": st.thermal,
-                "momentum": tuple(st.momentum), "steps": st.steps,
-                "n_dens_pairs": st.n_dens_pairs, "n_force_pairs": st.n_force_pairs,
-                "dens_pair_evals": st.dens_pair_evals, "force_pair_evals": st.force_pair_evals,
-                "nr_iter_max": st.nr_iter_max, "walk_overflows": st.walk_overflows,
-                "dens_leaf_visits": st.dens_leaf_visits, "dens_walks": st.dens_walks,
-                "nr_iter_total": st.nr_iter_total,
-                "dens_candidate_tests": st.dens_candidate_tests,
-                "dens_box_tests": st.dens_box_tests,
-                "force_candidate_tests": st.force_candidate_tests,
-                "force_box_tests": st.force_box_tests,
-                "density_walk_overflows": st.density_walk_overflows,
-                "force_walk_overflows": st.force_walk_overflows,
-                "dens_list_overflows": st.dens_list_overflows,
-                "block_full_steps": st.block_full_steps, "block_substeps": st.block_substeps,
-                "block_active": st.block_active, "block_updates": st.block_updates,
-                "block_time": st.block_time, "block_dt_max": st.block_dt_max,
-                "block_synchronised": st.block_synchronised}
+        return stats_dict(st)
 
     def neighbours(self, p: Particles, mode: int, cap: int = None):
         """CSR lists at the given h -> (offsets int64[n+1], idx int32) on the device."""
@@ -527,3 +555,88 @@ def plan_bytes(params: Params, n: int) -> int:
     """Device bytes a context needs for n particles (sph_plan_bytes)."""
     p = params.c()
     return int(load().sph_plan_bytes(ctypes.byref(p), int(n)))
+
+
+def server_plan_bytes(params: Params, n: int) -> int:
+    """Device bytes one executor slot needs for n particles (sph_server_plan_bytes)."""
+    p = params.c()
+    return int(load().sph_server_plan_bytes(ctypes.byref(p), int(n)))
+
+
+class Server:
+    """The library's request executor (sph_server_*): `slots` worker threads
+    on the current device, each with its own HIP stream and context.  Requests
+    are _Request structs that name host arrays; the caller keeps them (and
+    the arrays) alive until wait() has returned their addresses."""
+
+    def __init__(self, slots: int):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        rc = self.lib.sph_server_create(ctypes.byref(h), int(slots))
+        if rc != SPH_OK or not h.value:
+            raise SphError(rc, "sph_server_create failed")
+        self.h = h
+        self.slots = int(slots)
+        self._done = (ctypes.c_void_p * 64)()
+
+    def submit(self, slot: int, req: _Request):
+        rc = self.lib.sph_server_submit(self.h, int(slot), ctypes.byref(req))
+        if rc != SPH_OK:
+            raise SphError(rc, f"sph_server_submit: slot {slot} is busy or the request is malformed")
+
+    def wait(self, timeout: float) -> list:
+        """Addresses (ctypes.addressof) of the requests completed within
+        `timeout` seconds (0: poll; < 0: until one completes or none runs)."""
+        k = self.lib.sph_server_wait(self.h, self._done, len(self._done), float(timeout))
+        if k < 0:
+            raise SphError(SPH_EINVAL, "sph_server_wait")
+        return [int(self._done[i]) for i in range(k)]
+
+    def release(self, slot: int):
+        rc = self.lib.sph_server_release(self.h, int(slot))
+        if rc != SPH_OK:
+            raise SphError(rc, f"sph_server_release: slot {slot} is busy or out of range")
+
+    def slot_bytes(self, slot: int) -> int:
+        return int(self.lib.sph_server_slot_bytes(self.h, int(slot)))
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.sph_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_request(kind: int, arrays: dict, params: Params, nsteps: int = 0,
+                 outputs: dict = None):
+    """A _Request over host arrays: inputs x .. h from `arrays` (made
+    contiguous float64), outputs into the numpy arrays of `outputs` (field
+    name -> array of n values: float64 fields, int32 nngb / nforce).  Returns
+    (request, arrays to keep alive until the request is returned)."""
+    import numpy as np
+    r = _Request()
+    r.kind, r.nsteps = int(kind), int(nsteps)
+    r.params = params.c()
+    ins = [np.ascontiguousarray(arrays[k], dtype=np.float64) for k in FIELDS_F64[:NIN]]
+    n = int(ins[0].size)
+    r.n = n
+    for i, a in enumerate(ins):
+        if a.size != n:
+            raise ValueError(f"{FIELDS_F64[i]} has {a.size} values, x has {n}")
+        r.in_[i] = a.ctypes.data
+    keep = list(ins)
+    for k, a in (outputs or {}).items():
+        want = np.int32 if k in FIELDS_I32 else np.float64
+        if a.dtype != want or a.size != n or not a.flags.c_contiguous:
+            raise ValueError(f"output {k} must be a contiguous {want.__name__} array of {n} values")
+        if k in FIELDS_I32:
+            r.iout[FIELDS_I32.index(k)] = a.ctypes.data
+        else:
+            r.out[FIELDS_F64.index(k)] = a.ctypes.data
+        keep.append(a)
+    return r, keep

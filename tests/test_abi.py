@@ -93,13 +93,15 @@ def test_struct_offsets_match_the_c_compiler(tmp_path):
     if not shutil.which("gcc"):
         pytest.skip("no gcc")
     pairs = (("sph_params", sph._Params), ("sph_particles", sph._Particles),
-             ("sph_state_stats", sph._Stats), ("sph_mfv_set", sph._MfvSet))
+             ("sph_state_stats", sph._Stats), ("sph_mfv_set", sph._MfvSet),
+             ("sph_request", sph._Request))
+    cname_of = {"in_": "in"}   # Python keyword renamed in the binding
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sph.h"', "int main(void) {"]
     for cname, py in pairs:
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
         for field in py._fields_:
             f = field[0]
-            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {cname_of.get(f, f)}));')
     lines.append("return 0; }")
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines))
@@ -111,3 +113,13 @@ def test_struct_offsets_match_the_c_compiler(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for field in py._fields_:
             assert got[(cname, field[0])] == getattr(py, field[0]).offset, (cname, field[0])
+
+
+def test_server_plan_counts_the_context_and_the_particle_arrays():
+    # an executor slot holds a context and the request's 19 FP64 and 2 int32
+    # arrays (host-side arithmetic only: no device call)
+    from paper_1709_04488_amd import sph
+    for leaf in (8, 16, 32):
+        p = sph.Params(leaf_size=leaf)
+        for n in (1, 1000, 250_000):
+            assert sph.server_plan_bytes(p, n) == sph.plan_bytes(p, n) + n * (19 * 8 + 2 * 4)

@@ -1,7 +1,7 @@
 """Served requests on the GPU: each result inside the concurrent mix equals
-the same request run alone, bit for bit (FP64 and FP32-pair), in both the
-per-slot-stream mode and the batched-launch mode; integration requests
-replaying captured steps equal eager steps."""
+the same request run alone, bit for bit (FP64 and FP32-pair), in the
+library's native executor, the per-slot-stream mode and the batched-launch
+mode; integration requests replaying captured steps equal eager steps."""
 import math
 
 import numpy as np
@@ -45,7 +45,7 @@ def _alone(sph, req):
         return p.host(*S.GpuExecutor.OUT_EVAL)
 
 
-@pytest.mark.parametrize("mode", ["streams", "batched"])
+@pytest.mark.parametrize("mode", ["native", "streams", "batched"])
 def test_served_equals_alone(sph, mode):
     reqs = _eval_mix()
     print("case: serve %d requests mode=%s" % (len(reqs), mode), flush=True)
@@ -59,13 +59,14 @@ def test_served_equals_alone(sph, mode):
             assert np.array_equal(rec.outputs[f], ref[f]), (req.rid, f)
 
 
-def test_served_integration_equals_eager(sph):
+@pytest.mark.parametrize("mode", ["native", "streams"])
+def test_served_integration_equals_eager(sph, mode):
     reqs = []
     for rid, side in enumerate((8, 10, 7)):
         w = W.blob_in_lattice(side, seed=200 + rid)
         reqs.append(S.Request(rid, 0.0, "integrate", w.arrays, w.setup, precision=rid % 2, nsteps=5))
-    print("case: served integration", flush=True)
-    recs, summary = S.serve(reqs, 1 << 30, 3, "streams", keep_outputs=True)
+    print("case: served integration mode=%s" % mode, flush=True)
+    recs, summary = S.serve(reqs, 1 << 30, 3, mode, keep_outputs=True)
     assert summary["completed"] == 3
     for req, rec in zip(reqs, recs):
         params = sph.Params.from_setup(req.setup, precision=req.precision, leaf_size=16)
@@ -87,3 +88,56 @@ def test_budget_rejects_oversized_request(sph):
     reqs = [S.Request(0, 0.0, "evaluate", w.arrays, w.setup)]
     recs, summary = S.serve(reqs, 1 << 20, 2, "streams")
     assert recs[0].error == "exceeds HBM budget"
+
+
+def _native_eval(sph, server, slot, arrays, params):
+    outs = {k: np.empty(arrays["x"].size, dtype=np.int32 if k in sph.FIELDS_I32 else np.float64)
+            for k in S.GpuExecutor.OUT_EVAL}
+    r, keep = sph.make_request(sph.SPH_REQUEST_EVALUATE, arrays, params, 0, outs)
+    server.submit(slot, r)
+    got = []
+    while not got:
+        got = server.wait(5.0)
+    assert got == [__import__("ctypes").addressof(r)]
+    return r, outs
+
+
+def test_native_executor_reuse_release_and_errors(sph):
+    server = sph.Server(2)
+    try:
+        big = W.jittered_lattice(14, seed=31)
+        small = W.plummer(900, seed=32)
+        for slot, w, prec in ((0, big, 0), (0, small, 1), (1, small, 0), (1, big, 1)):
+            print("case: native slot %d n=%d precision %d" % (slot, w.n, prec), flush=True)
+            params = sph.Params.from_setup(w.setup, precision=prec, leaf_size=16)
+            r, outs = _native_eval(sph, server, slot, w.arrays, params)
+            assert r.status == sph.SPH_OK and r.error == b"" and r.slot == slot
+            ref = _alone(sph, S.Request(0, 0.0, "evaluate", w.arrays, w.setup, precision=prec))
+            for f in S.GpuExecutor.OUT_EVAL:
+                assert np.array_equal(outs[f], ref[f]), (slot, w.n, f)
+            assert r.interactions == int(ref["nngb"].sum()) + int(ref["nforce"].sum())
+        # a slot holds its context and arrays, within what was planned for
+        # the largest request it ran; release gives them back and the slot
+        # still serves
+        held = server.slot_bytes(0)
+        assert 0 < held <= sph.server_plan_bytes(sph.Params(leaf_size=16), big.n)
+        server.release(0)
+        assert server.slot_bytes(0) == 0
+        params = sph.Params.from_setup(small.setup, precision=1, leaf_size=16)
+        r, outs = _native_eval(sph, server, 0, small.arrays, params)
+        assert r.status == sph.SPH_OK
+        # a run-time error is the request's, and the slot goes on serving
+        bad = sph.Params.from_setup(small.setup, precision=0, leaf_size=12)
+        r, _ = _native_eval(sph, server, 1, small.arrays, bad)
+        assert r.status == sph.SPH_EINVAL and r.error
+        r, _ = _native_eval(sph, server, 1, small.arrays, params)
+        assert r.status == sph.SPH_OK
+        # an empty set completes at once; a bad slot is refused at submit
+        empty = {k: np.zeros(0) for k in small.arrays}
+        r, _ = _native_eval(sph, server, 1, empty, params)
+        assert r.status == sph.SPH_OK and r.interactions == 0
+        with pytest.raises(sph.SphError):
+            server.submit(2, r)
+        assert server.wait(0.0) == []
+    finally:
+        server.close()
