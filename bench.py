@@ -380,16 +380,21 @@ def rows_legs(args, w, shape):
     return out
 
 
+# slots of the serving executor: 3 measured best on C3 (2: 1360, 3: 1700-1780,
+# 4: 1470-1620, 5: 1330-1460, 8: 1170 requests/s at leaf size 16)
+SERVE_SLOTS = 3
+
+
 def serving_legs(args):
     """The two served workloads (continuous batching under an HBM budget),
     throughput with p50/p99 latency from arrival to results in host memory."""
     from paper_1709_04488_amd import serve
     t0 = time.perf_counter()
-    ev = serve.run_served("evaluate", requests=512, slots=4, mode="streams", load=0.8)
+    ev = serve.run_served("evaluate", requests=512, slots=SERVE_SLOTS, mode="native", load=0.8)
     print(f"# served evaluate: {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    it = serve.run_served("integrate", requests=64, steps=args.serve_steps, slots=4,
-                          mode="streams")
+    it = serve.run_served("integrate", requests=64, steps=args.serve_steps, slots=SERVE_SLOTS,
+                          mode="native")
     print(f"# served integrate: {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     keep = ("requests", "completed", "errors", "makespan_s", "throughput_interactions_per_s",
             "requests_per_s", "latency_p50_ms", "latency_p99_ms", "latency_max_ms", "peak_bytes")
@@ -397,7 +402,9 @@ def serving_legs(args):
         "evaluate_512": {
             "workload": "512 evaluation requests, jittered-lattice boxes, N log-uniform in "
                         "[1e3, 2e5] snapped to n^3, FP64 or FP32-pair with probability 1/2, "
-                        "HBM budget 1 GiB, 4 slots (one per hardware queue), one stream each",
+                        f"HBM budget 1 GiB, {SERVE_SLOTS} slots of the library's request "
+                        "executor (one native worker thread, stream and context each), launch "
+                        "shape per request class tuned for throughput on that executor",
             "budget_bytes": ev["budget_bytes"],
             "saturated_all_at_t0": {k: ev["saturated"][k] for k in keep},
             "poisson_arrivals_per_s": ev["arrival_rate_per_s"],
@@ -406,7 +413,8 @@ def serving_legs(args):
             "workload": f"64 integration requests, blob-in-lattice boxes, N log-uniform in "
                         f"[1e4, 1e6] snapped to n^3, {args.serve_steps} KDK steps each, "
                         "FP32-pair pair terms, FP64 state, resident, graph replay, "
-                        "HBM budget 16 GiB, 4 slots",
+                        f"HBM budget 16 GiB, {SERVE_SLOTS} slots of the library's request "
+                        "executor",
             "budget_bytes": it["budget_bytes"],
             "steps_total": it["steps_total"],
             "result": {k: it["result"][k] for k in keep},

@@ -792,7 +792,9 @@ sph_status sph_create(sph_ctx **out, const sph_params *p, void *hip_stream, size
               hipMalloc(&c->d_fargs, kArgBytes) == hipSuccess &&
               hipMalloc((void **)&c->d_clock, sizeof(BlockClock)) == hipSuccess &&
               hipHostMalloc((void **)&c->h_status, sizeof(int32_t) * kStatusWords) == hipSuccess &&
-              hipHostMalloc((void **)&c->h_scal, sizeof(double) * 16) == hipSuccess;
+              hipHostMalloc((void **)&c->h_scal, sizeof(double) * 16) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_counts, sizeof(int64_t) * kCountWords) == hipSuccess &&
+              hipHostMalloc((void **)&c->h_clock, sizeof(BlockClock)) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         sph_destroy(c);
@@ -832,6 +834,8 @@ sph_status sph_destroy(sph_ctx *c)
     if (c->d_clock) (void)hipFree(c->d_clock);
     if (c->h_status) (void)hipHostFree(c->h_status);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->h_counts) (void)hipHostFree(c->h_counts);
+    if (c->h_clock) (void)hipHostFree(c->h_clock);
     delete c;
     return SPH_OK;
 }
@@ -1182,13 +1186,17 @@ sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
 {
     if (!c || !info) return SPH_EINVAL;
     if (c->n <= 0) return fail(c, SPH_ESTATE, "nothing evaluated yet");
-    int64_t counts[kCountWords];
+    // scalars, counters and the block clock in pinned mirrors, one wait
+    const bool block = c->p.block_lmax > 0 && c->resident;
     TRY(hip_check(c, hipMemcpyAsync(c->h_scal, c->d_scal, sizeof(double) * 8,
                                     hipMemcpyDeviceToHost, c->stream), "copy scalars"));
+    TRY(hip_check(c, hipMemcpyAsync(c->h_counts, c->d_counts, sizeof(int64_t) * kCountWords,
+                                    hipMemcpyDeviceToHost, c->stream), "copy counts"));
+    if (block)
+        TRY(hip_check(c, hipMemcpyAsync(c->h_clock, c->d_clock, sizeof(BlockClock),
+                                        hipMemcpyDeviceToHost, c->stream), "copy block clock"));
     TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
-    TRY(hip_check(c, hipMemcpyAsync(counts, c->d_counts, sizeof(counts), hipMemcpyDeviceToHost,
-                                    c->stream), "copy counts"));
-    TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    const int64_t *counts = c->h_counts;
     std::memset(info, 0, sizeof(*info));
     info->dt_next = c->h_scal[0];
     info->dt_last = c->h_scal[1];
@@ -1213,11 +1221,8 @@ sph_status sph_state_info(sph_ctx *c, sph_state_stats *info)
     info->density_walk_overflows = (int32_t)counts[kCntDensOverflows];
     info->force_walk_overflows = (int32_t)counts[kCntForceOverflows];
     info->dens_list_overflows = counts[kCntDensListOverflows];
-    if (c->p.block_lmax > 0 && c->resident) {
-        BlockClock clk{};
-        TRY(hip_check(c, hipMemcpyAsync(&clk, c->d_clock, sizeof(clk), hipMemcpyDeviceToHost,
-                                        c->stream), "copy block clock"));
-        TRY(hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize"));
+    if (block) {
+        const BlockClock clk = *c->h_clock;
         info->block_full_steps = clk.full;
         info->block_substeps = clk.nsub;
         info->block_active = clk.active;
@@ -1346,10 +1351,9 @@ sph_status sph_mfv_gradients(sph_ctx *c, sph_mfv_set *s)
 sph_status sph_sync(sph_ctx *c)
 {
     if (!c) return SPH_EINVAL;
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
-    e = hipMemcpyAsync(c->h_status, c->d_status, sizeof(int32_t) * kStatusWords,
-                       hipMemcpyDeviceToHost, c->stream);
+    // the status copy is ordered after the enqueued work: one wait covers both
+    hipError_t e = hipMemcpyAsync(c->h_status, c->d_status, sizeof(int32_t) * kStatusWords,
+                                  hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && c->dt_used_out && c->resident)
         e = hipMemcpyAsync(c->h_scal + 1, c->d_scal + 1, sizeof(double), hipMemcpyDeviceToHost,
                            c->stream);

@@ -261,6 +261,8 @@ struct sph_ctx {
     // device counters, indexed by the kCnt* constants
     int64_t *d_counts = nullptr;
     double *h_scal = nullptr;   // pinned mirror
+    int64_t *h_counts = nullptr;   // pinned mirror of d_counts
+    sph::BlockClock *h_clock = nullptr; // pinned mirror of d_clock
     double *dt_used_out = nullptr;
     int64_t steps = 0;
 

@@ -701,8 +701,25 @@ def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=
     return recs, out
 
 
+def serving_tuner(reqs, budget: int, slots: int, tune_table: str = None):
+    """Launch-shape tuner for a served workload: each request class tuned for
+    the GPU time it occupies (many requests share the GPU), among the leaf
+    sizes whose slot footprint at the largest request fits the per-slot share
+    of the HBM budget.  A larger leaf size enlarges a slot's candidate-list
+    scratch (G = 32: twice that of G = 16); where that pushes slots past their
+    share, the budget admits fewer requests at once, which costs more than
+    the shape gains."""
+    from . import sph
+    from .tune import LEAF_SIZES, LaunchTuner
+    n_max = max((r.n for r in reqs), default=1)
+    share = budget // max(int(slots), 1)
+    sizes = tuple(g for g in LEAF_SIZES
+                  if sph.server_plan_bytes(sph.Params(leaf_size=g), n_max) <= share)
+    return LaunchTuner(sizes=sizes or (min(LEAF_SIZES),), path=tune_table, objective="throughput")
+
+
 def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200,
-               budget_gib: float = None, slots: int = 4, mode: str = "streams",
+               budget_gib: float = None, slots: int = 3, mode: str = "native",
                load: float = 0.8, max_side: int = None, leaf="auto", tune_table: str = None,
                threads: bool = True, progress: bool = True) -> dict:
     """Serve one of the two workloads and summarise it.  evaluate: a closed
@@ -710,20 +727,20 @@ def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200
     arrivals at `load` times that rate; integrate: `requests` resident
     integrations of `steps` KDK steps each.  Every request class is tuned
     before the timed runs when leaf is "auto"."""
-    if leaf == "auto":
-        from .tune import LaunchTuner
-        leaf_for = LaunchTuner(path=tune_table)
-    else:
-        g = int(leaf)
-        leaf_for = lambda req: g  # noqa: E731
     gib = budget_gib if budget_gib else (1.0 if workload == "evaluate" else 16.0)
     budget = int(gib * GIB)
 
     def pretune(reqs):
+        nonlocal leaf_for
         if leaf == "auto":
+            leaf_for = serving_tuner(reqs, budget, slots, tune_table)
             for r in reqs:
                 leaf_for(r)
+        else:
+            g = int(leaf)
+            leaf_for = lambda req: g  # noqa: E731
 
+    leaf_for = None
     if workload == "evaluate":
         burst = evaluate_requests(requests, math.inf, n_max_side=max_side)
         pretune(burst)
@@ -750,6 +767,7 @@ def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200
                "per_step_latency_p99_ms": float(np.percentile(per_step, 99))}
     if leaf == "auto":
         res["autotuner"] = leaf_for.table
+        res["autotuner_leaf_sizes"] = list(leaf_for.sizes)
     return res
 
 
@@ -760,7 +778,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--budget-gib", type=float, default=None,
                     help="HBM budget (default 1 GiB for evaluate, 16 GiB for integrate)")
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--mode", choices=["native", "streams", "batched"], default="native",
                     help="native: the library's executor threads; streams: one Python "
                          "worker thread per slot; batched: one batched launch per admission")

@@ -20,11 +20,20 @@ and how clustered the set is, so the tuner measures instead of guessing.
 Requests are grouped into classes by (kind, precision, periodic, log2 N
 rounded).  The first request of a class is timed by coordinate descent: every
 leaf size at the default stage and claim, then the other stage depths at the
-best leaf size, then the other claim sizes at the best (leaf, stage); each
-timing is one untimed call and the best of `reps` timed calls of a full
-density + force evaluation on a private stream.  Later requests of the class
-reuse the choice without measuring.  The table can be saved to and loaded
-from a JSON file so a server starts tuned.
+best leaf size, then the other claim sizes at the best (leaf, stage).  Later
+requests of the class reuse the choice without measuring.  The table can be
+saved to and loaded from a JSON file so a server starts tuned.
+
+Two objectives:
+* latency (default): one untimed call and the best of `reps` timed calls of
+  a full density + force evaluation alone on a private stream;
+* throughput (for serving): the device time of the pair loops per set when
+  enough copies of the request share one batched launch to fill the GPU.
+  A small set alone is fastest with the most parallel shape (G = 8: more
+  waves, shorter chains per leaf), but when many sets share the GPU what
+  counts is the GPU time each one occupies, which this measures.  (Timing
+  a few concurrent copies by wall clock still rewards the parallel shape:
+  they do not fill the GPU.)
 """
 from __future__ import annotations
 
@@ -76,13 +85,18 @@ class LaunchTuner:
     planning needs); shape(req) returns the whole choice."""
 
     def __init__(self, sizes=LEAF_SIZES, stages=STAGES, claims=CLAIMS, reps: int = 2,
-                 path: str = None, timer=None):
+                 path: str = None, timer=None, objective: str = "latency"):
         self.sizes = tuple(int(s) for s in sizes)
         self.stages = tuple(stages)
         self.claims = tuple(int(c) for c in claims)
         self.reps = int(reps)
         self.path = path
-        self.timer = timer or _gpu_timer(self.reps)
+        if objective not in ("latency", "throughput"):
+            raise ValueError(f"unknown objective {objective!r}")
+        self.objective = objective
+        if timer is None:
+            timer = _gpu_timer(self.reps) if objective == "latency" else _batch_timer(self.reps)
+        self.timer = timer
         self.table = {}          # class -> {"leaf", "stage", "claim", "seconds": {shape: s}}
         if path and os.path.exists(path):
             self.load(path)
@@ -105,7 +119,8 @@ class LaunchTuner:
 
     # --- choice -----------------------------------------------------------
     def key(self, req) -> str:
-        return request_class(req.kind, req.precision, bool(req.setup.get("periodic", True)), req.n)
+        k = request_class(req.kind, req.precision, bool(req.setup.get("periodic", True)), req.n)
+        return k if self.objective == "latency" else k + "/throughput"
 
     def shape(self, req) -> dict:
         k = self.key(req)
@@ -164,6 +179,62 @@ def _gpu_timer(reps: int):
             ctx.close()
         return best
     return run
+
+
+class _batch_timer:
+    """Device seconds per set of the density and force loops when K copies of
+    the request share one batched launch: K = ceil(2^18 / N) up to 64, so
+    that small sets together give the launch enough leaves to fill the GPU.
+    The time is that of the pair-loop kernels alone (HIP events around them,
+    best of `reps` after an untimed call), divided by K.  The contexts are
+    kept between timings (one stream) and take each shape's parameters."""
+
+    TARGET_PARTICLES = 1 << 18
+    MAX_COPIES = 64
+
+    def __init__(self, reps: int):
+        self.reps = int(reps)
+        self.stream = None
+        self.ctxs = []
+
+    def __call__(self, arrays, setup, precision, shape):
+        import numpy as np
+        import torch
+
+        from . import sph
+        n = int(np.asarray(arrays["x"]).size)
+        k = int(min(self.MAX_COPIES, max(1, math.ceil(self.TARGET_PARTICLES / max(n, 1)))))
+        params = sph.Params.from_setup(setup, precision=precision, **params_kw(shape))
+        if self.stream is None:
+            self.stream = torch.cuda.Stream()
+        best = math.inf
+        with torch.cuda.stream(self.stream):
+            while len(self.ctxs) < k:
+                self.ctxs.append(sph.Context(params, stream=self.stream))
+            ctxs = self.ctxs[:k]
+            for c in ctxs:
+                c.set_params(params)
+            ctxs[0].enable_kernel_timing(True)
+            parts = [sph.Particles.from_host(arrays) for _ in range(k)]
+            h0 = parts[0].t["h"].clone()
+            for r in range(self.reps + 1):
+                for p in parts:
+                    p.t["h"].copy_(h0)
+                ctxs[0].sync()
+                ctxs[0].reset_kernel_times()
+                sph.batch_evaluate(ctxs, parts)
+                ms = ctxs[0].kernel_times(0)[0] + ctxs[0].kernel_times(1)[0]
+                if r > 0:
+                    best = min(best, ms * 1e-3 / k)
+            ctxs[0].enable_kernel_timing(False)
+        return best
+
+    def __del__(self):
+        for c in self.ctxs:
+            try:
+                c.close()
+            except Exception:
+                pass
 
 
 def main(argv=None):

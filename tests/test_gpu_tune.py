@@ -55,6 +55,24 @@ def test_tuner_measures_the_knobs_and_serving_uses_its_choice(sph, tmp_path):
         assert np.array_equal(recs[0].outputs[f], ref[f]), f
 
 
+def test_throughput_tuner_times_batched_pair_loops(sph):
+    w = W.jittered_lattice(12, seed=19)
+    req = S.Request(0, 0.0, "evaluate", w.arrays, w.setup, precision=1)
+    tuner = T.LaunchTuner(reps=1, objective="throughput")
+    print("case: throughput tuning N=%d" % w.n, flush=True)
+    shape = tuner.shape(req)
+    entry = tuner.table[tuner.key(req)]
+    assert tuner.key(req).endswith("/throughput")
+    assert shape["leaf"] in T.LEAF_SIZES and len(entry["seconds"]) == 5
+    assert all(v > 0 for v in entry["seconds"].values())
+    # serving through the native executor with that choice: results are
+    # those of a plain call with the same shape
+    recs, _ = S.serve([req], 1 << 30, 3, "native", leaf_for=tuner, keep_outputs=True)
+    ref = _eval(sph, w, 1, shape)
+    for f in S.GpuExecutor.OUT_EVAL:
+        assert np.array_equal(recs[0].outputs[f], ref[f]), f
+
+
 @pytest.mark.parametrize("leaf", [8, 16, 32])
 def test_every_launch_shape_computes_the_same(sph, orc, leaf):
     w = W.blob_in_lattice(13, seed=31)

@@ -87,3 +87,33 @@ def test_stale_table_entries_are_ignored(tmp_path):
                              {1: 0.0, 4: 0.1})
     t = T.LaunchTuner(timer=timer, path=str(path))
     assert t.choose(_req(1, 16)) == 8 and len(calls) == 5
+
+
+def test_objectives_keep_separate_table_entries(tmp_path):
+    path = tmp_path / "tune.json"
+    calls = []
+    timer = _separable_timer(calls, {0: {8: 1.0, 16: 2.0, 32: 3.0}}, {"full": 0.0, "half": 0.1},
+                             {1: 0.0, 4: 0.1})
+    lat = T.LaunchTuner(timer=timer, path=str(path))
+    thr = T.LaunchTuner(timer=timer, path=str(path), objective="throughput")
+    r = _req(1, 16)
+    assert lat.key(r) != thr.key(r) and thr.key(r).endswith("/throughput")
+    lat.choose(r)
+    thr.load(str(path))
+    assert thr.key(r) not in thr.table        # a latency entry is not reused
+    thr.choose(r)
+    assert len(calls) == 10
+    with pytest.raises(ValueError):
+        T.LaunchTuner(timer=timer, objective="fastest")
+
+
+def test_serving_tuner_keeps_the_leaf_sizes_that_fit_a_slot_share():
+    # C3-like: the largest set is 58^3; one slot in three of 1 GiB holds its
+    # G = 8 and G = 16 footprints but not G = 32's (twice the candidate-list
+    # scratch of G = 16); a 16 GiB budget holds all three
+    reqs = [_req(1, 20), _req(2, 58)]
+    t = S.serving_tuner(reqs, 1 << 30, 3)
+    assert t.sizes == (8, 16) and t.objective == "throughput"
+    assert S.serving_tuner(reqs, 16 << 30, 3).sizes == T.LEAF_SIZES
+    # nothing fits: the smallest leaf size is still tried
+    assert S.serving_tuner(reqs, 1 << 20, 3).sizes == (8,)
