@@ -512,17 +512,20 @@ sph_status sph_kernel_times(sph_ctx *ctx, int32_t which, double *ms, int64_t *la
 /*
  * Request executor for serving many independent particle sets from host
  * memory.  A server owns `slots` slots on the HIP device that is current
- * at sph_server_create.  Each slot has one worker thread, one non-blocking
- * HIP stream, one context and device arrays plus pinned host staging, all
- * grown to the largest request the slot has run and kept between requests.
- * A request handed to an idle slot runs entirely on that slot's thread:
+ * at sph_server_create, driven by `threads` native worker threads (slot k by
+ * thread k mod threads).  Each slot has one non-blocking HIP stream, one
+ * context and device arrays plus pinned host staging, all grown to the
+ * largest request the slot has run and kept between requests.  A request
+ * handed to an idle slot is carried by the slot's thread:
  *   - its host inputs go to the device in one copy through the staging;
  *   - evaluate: sph_evaluate;
  *   - integrate: sph_upload_state, then steps with the CFL step (dt <= 0)
  *     replayed two at a time from sph_capture_steps (plus one sph_step for
  *     an odd count), then sph_download_state;
- *   - the outputs come back in one copy and are written into the caller's
- *     host arrays, and the request is marked done.
+ *   - the copies of its outputs back are enqueued, and the thread goes on to
+ *     its other slots; once the slot's stream has drained, the outputs are
+ *     written into the caller's host arrays and the request is marked done.
+ * So one thread keeps several requests in flight while it stages the next.
  * Different slots run concurrently; their kernels overlap on the device.
  * Which request goes to which slot and when (admission under an HBM budget)
  * is the caller's choice: sph_server_plan_bytes gives what a slot holds.
@@ -564,15 +567,20 @@ typedef struct {
     int64_t interactions;  /* n_dens_pairs + n_force_pairs of the last
                               evaluation, times max(nsteps, 1) for integrate */
     sph_state_stats info;  /* sph_state_info after the request (zero on error) */
+    double host_seconds[4];/* staging the inputs and enqueueing the work (the
+                              slot thread's time), then in flight on the device
+                              until the thread saw it done, then reading the
+                              status and writing the outputs (the thread's time) */
     char error[SPH_REQUEST_ERROR_LEN]; /* readable error ("" when status is SPH_OK) */
 } sph_request;
 
 typedef struct sph_server sph_server;
 
-/* Start `slots` (1..64) worker threads on the current HIP device.  Nothing is
+/* `slots` (1..64) slots on the current HIP device, driven by `threads`
+ * (1..slots; 0 = one per slot) worker threads, started here.  Nothing is
  * allocated on the device until a slot runs its first request.  *s is NULL
- * on error (SPH_EINVAL for a bad slot count, SPH_EDEVICE without a device). */
-sph_status sph_server_create(sph_server **s, int32_t slots);
+ * on error (SPH_EINVAL for a bad count, SPH_EDEVICE without a device). */
+sph_status sph_server_create(sph_server **s, int32_t slots, int32_t threads);
 
 /* Hand request r to slot `slot`, which must be idle (no request submitted
  * and not yet returned by sph_server_wait).  Returns at once.  r and every

@@ -21,6 +21,7 @@ constexpr int kRsThreads = 256;
 constexpr int kRsItems = 16;
 constexpr int kRsTile = kRsThreads * kRsItems;   // 4096 keys per tile
 constexpr int kMortonBits = 16;                  // per axis: 48-bit keys, 6 passes
+constexpr int64_t kRsRawTiles = 64;              // scatter forms its own offsets up to here
 
 __device__ inline void wave_lds_sync()
 {
@@ -176,14 +177,19 @@ __global__ __launch_bounds__(256) void k_rs_digit_scan(uint32_t *__restrict__ hi
 // Stable scatter.  Wave w of the block owns keys [tile + w*1024, +1024) and
 // walks them in 16 rounds of 64 in index order; equal digits within a round
 // are ranked with 8 ballots, across rounds with per-wave LDS counters, and
-// across waves by an exclusive prefix of those counters.
+// across waves by an exclusive prefix of those counters.  raw = 0: offs holds
+// k_rs_digit_scan's per-digit scans over the tiles and totals the digit
+// totals; raw = 1 (few tiles): offs holds k_rs_hist's counts as they are and
+// each block forms both itself (one thread per digit summing that digit's
+// counts over the tiles), which saves the scan's launch.
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint64_t *__restrict__ kin,
                                                            const uint32_t *__restrict__ vin,
                                                            uint64_t *__restrict__ kout,
                                                            uint32_t *__restrict__ vout, int shift,
                                                            const uint32_t *__restrict__ offs,
                                                            int64_t ntiles,
-                                                           const uint32_t *__restrict__ totals)
+                                                           const uint32_t *__restrict__ totals,
+                                                           int raw)
 {
     __shared__ uint32_t wcnt[kRsThreads / kWave][256];
     __shared__ uint32_t dbase[256];
@@ -194,10 +200,25 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
     const int w = threadIdx.x / kWave;
     for (int k = threadIdx.x; k < (kRsThreads / kWave) * 256; k += kRsThreads)
         (&wcnt[0][0])[k] = 0;
-    // first position of each digit: exclusive scan of the digit totals
+    // this digit's keys in the tiles before this one, and in all tiles
     static_assert(kRsThreads == 256, "one thread per digit");
+    uint32_t before_tile, digit_total;
+    if (raw) {
+        const uint32_t *h = offs + (int64_t)threadIdx.x * ntiles;
+        before_tile = 0u;
+        digit_total = 0u;
+        for (int64_t t = 0; t < ntiles; t++) {
+            const uint32_t v = h[t];
+            before_tile += t < (int64_t)blockIdx.x ? v : 0u;
+            digit_total += v;
+        }
+    } else {
+        before_tile = offs[threadIdx.x * ntiles + blockIdx.x];
+        digit_total = totals[threadIdx.x];
+    }
+    // first position of each digit: exclusive scan of the digit totals
     {
-        const uint32_t v = totals[threadIdx.x];
+        const uint32_t v = digit_total;
         const uint32_t incl = block_scan_256(v, dbase);
         __syncthreads();
         dbase[threadIdx.x] = incl - v;
@@ -255,7 +276,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
     __syncthreads();
     // slot i of the tile goes to (global start of its digit's run in this tile)
     // + (i - tile start of that run); dbase + offs >= tbase, so no wrap
-    dbase[threadIdx.x] += offs[threadIdx.x * ntiles + blockIdx.x] - tbase[threadIdx.x];
+    dbase[threadIdx.x] += before_tile - tbase[threadIdx.x];
     __syncthreads();
     const int64_t left = n - blockIdx.x * (int64_t)kRsTile;   // >= 1
     const int tile_n = left < kRsTile ? (int)left : kRsTile;
@@ -664,16 +685,20 @@ sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y, 
                        c->d_box, kMortonBits, c->keys[0], c->vals[0]);
     int64_t ntiles = ceil_div(n, kRsTile);
     int passes = (3 * kMortonBits + 7) / 8;
+    // up to kRsRawTiles tiles the scatter blocks form the digit offsets from
+    // the raw counts themselves (one launch fewer per pass)
+    const int raw = ntiles <= kRsRawTiles ? 1 : 0;
     int cur = 0;
     for (int ps = 0; ps < passes; ps++) {
         int shift = 8 * ps;
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(kRsThreads), 0, c->stream, n,
                            c->keys[cur], shift, c->hist, ntiles);
-        hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(256), 0, c->stream, c->hist, ntiles,
-                           c->hist + 256 * ntiles);
+        if (!raw)
+            hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(256), 0, c->stream, c->hist, ntiles,
+                               c->hist + 256 * ntiles);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(kRsThreads), 0, c->stream, n,
                            c->keys[cur], c->vals[cur], c->keys[cur ^ 1], c->vals[cur ^ 1], shift,
-                           c->hist, ntiles, c->hist + 256 * ntiles);
+                           c->hist, ntiles, c->hist + 256 * ntiles, raw);
         cur ^= 1;
     }
     c->perm = c->vals[cur];
@@ -691,14 +716,20 @@ sph_status gather(sph_ctx *c, int64_t n, const GatherList &g, bool identity_src_
     return hip_check(c, hipGetLastError(), "gather");
 }
 
-// nodes above the leaves, merged level by level
+// nodes above the leaves, merged level by level.  A grid-wide level is
+// launched only where its children can outnumber what the one-block kernel
+// takes (kSmallLevel): level l has at most ceil(n / 8^(l-1)) children (a leaf
+// holds at least one particle), and a launch with fewer would return at once,
+// so small sets skip those launches.
 static void upper_levels(sph_ctx *c, int64_t n)
 {
-    int64_t bound = n;
+    int64_t children = n;
     for (int l = 1; l <= kBigLevels; l++) {
-        bound = ceil_div(bound, 8);
-        hipLaunchKernelGGL(k_tree_level_big, dim3(grid_for(bound, 256)), dim3(256), 0, c->stream,
-                           c->d_tree, c->nodes, l);
+        const int64_t parents = ceil_div(children, 8);
+        if (children > kSmallLevel)
+            hipLaunchKernelGGL(k_tree_level_big, dim3(grid_for(parents, 256)), dim3(256), 0,
+                               c->stream, c->d_tree, c->nodes, l);
+        children = parents;
     }
     hipLaunchKernelGGL(k_tree_level_small, dim3(1), dim3(1024), 0, c->stream, c->d_tree, c->nodes);
 }

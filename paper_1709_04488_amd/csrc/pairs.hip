@@ -49,44 +49,24 @@ inline void fill_common(sph_ctx *c, int64_t n, Args &a)
 
 namespace {
 
+// A set's pair-loop prologue in one launch: its argument block, its counters
+// of that loop and its claim counters zeroed.  Stream order puts it after the
+// set's previous pair loop and before the next launch that reads them (a
+// batched launch claims through its first set's counters).
 template <class Args>
-__global__ void k_store_args(Args a, Args *dst)
+__global__ void k_prologue(Args a, Args *dst, int64_t *__restrict__ counts, int first, int nwords,
+                           int first2, int nwords2, uint32_t *__restrict__ work)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = a;
-}
-
-struct CountsBatch {
-    int32_t n;
-    int32_t first, count;
-    int64_t *p[kMaxBatch];
-};
-
-__global__ void k_zero_counts_batch(CountsBatch cb)
-{
-    for (int r = blockIdx.x; r < cb.n; r += gridDim.x)
-        if ((int)threadIdx.x < cb.count) cb.p[r][cb.first + threadIdx.x] = 0;
-}
-
-__global__ void k_zero_work_one(uint32_t *__restrict__ w)
-{
-    if (threadIdx.x < kXcds) w[threadIdx.x] = 0u;
+    const int t = threadIdx.x;
+    if (t == 0) *dst = a;
+    if (t < nwords) counts[first + t] = 0;
+    if (t < nwords2) counts[first2 + t] = 0;
+    if (t < kXcds) work[t] = 0u;
 }
 
 static_assert(sizeof(DensArgs) <= kArgBytes, "density argument block too large");
 static_assert(sizeof(ForceArgs) <= kArgBytes, "force argument block too large");
-
-sph_status zero_batch_counts(sph_ctx *const *cs, int count, int first, int nwords)
-{
-    CountsBatch cb{};
-    cb.n = count;
-    cb.first = first;
-    cb.count = nwords;
-    for (int r = 0; r < count; r++) cb.p[r] = cs[r]->d_counts;
-    hipLaunchKernelGGL(k_zero_counts_batch, dim3((unsigned)std::min(count, 64)), dim3(64), 0,
-                       cs[0]->stream, cb);
-    hipLaunchKernelGGL(k_zero_work_one, dim3(1), dim3(64), 0, cs[0]->stream, cs[0]->d_work);
-    return hip_check(cs[0], hipGetLastError(), "zero batch counters");
-}
+static_assert(kCntDensWords <= 64 && kCntForceWords <= 64, "prologue zeroes one word per lane");
 
 } // namespace
 
@@ -120,8 +100,9 @@ sph_status density_prepare(sph_ctx *c, int64_t n)
         return fail(c, SPH_EINVAL, "density: offsets not allocated");
     if (c->tree_n != n || n <= 0) return fail(c, SPH_ESTATE, "density: tree not built");
     TRY_(reduce_mass_range(c, n));
-    hipLaunchKernelGGL(k_store_args<DensArgs>, dim3(1), dim3(64), 0, c->stream, a,
-                       (DensArgs *)c->d_dargs);
+    hipLaunchKernelGGL(k_prologue<DensArgs>, dim3(1), dim3(64), 0, c->stream, a,
+                       (DensArgs *)c->d_dargs, c->d_counts, (int)kCntDensFirst, (int)kCntDensWords,
+                       (int)kCntDensListOverflows, 1, c->d_work);
     return hip_check(c, hipGetLastError(), "density arguments");
 }
 
@@ -165,8 +146,9 @@ sph_status forces_prepare(sph_ctx *c, int64_t n)
     if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
         return fail(c, SPH_EINVAL, "forces: offsets not allocated");
     if (c->tree_n != n || n <= 0) return fail(c, SPH_ESTATE, "forces: tree not built");
-    hipLaunchKernelGGL(k_store_args<ForceArgs>, dim3(1), dim3(64), 0, c->stream, a,
-                       (ForceArgs *)c->d_fargs);
+    hipLaunchKernelGGL(k_prologue<ForceArgs>, dim3(1), dim3(64), 0, c->stream, a,
+                       (ForceArgs *)c->d_fargs, c->d_counts, (int)kCntForceFirst,
+                       (int)kCntForceWords, 0, 0, c->d_work);
     return hip_check(c, hipGetLastError(), "force arguments");
 }
 
@@ -178,8 +160,6 @@ sph_status density_launch(sph_ctx *const *cs, int count, int64_t nmax)
     if (count <= 0) return SPH_OK;
     sph_ctx *c = cs[0];
     if (count > kMaxBatch) return fail(c, SPH_EINVAL, "batch larger than kMaxBatch");
-    TRY_(zero_batch_counts(cs, count, kCntDensFirst, kCntDensWords));
-    TRY_(zero_batch_counts(cs, count, kCntDensListOverflows, 1));
     Batch<DensArgs> B{};
     B.nreq = count;
     B.claim = c->p.claim_leaves > 0 ? c->p.claim_leaves : 1;
@@ -219,7 +199,6 @@ sph_status forces_launch(sph_ctx *const *cs, int count, int64_t nmax)
     if (count <= 0) return SPH_OK;
     sph_ctx *c = cs[0];
     if (count > kMaxBatch) return fail(c, SPH_EINVAL, "batch larger than kMaxBatch");
-    TRY_(zero_batch_counts(cs, count, kCntForceFirst, kCntForceWords));
     Batch<ForceArgs> B{};
     B.nreq = count;
     B.claim = c->p.claim_leaves > 0 ? c->p.claim_leaves : 1;

@@ -1,14 +1,18 @@
-// Request executor for serving: one worker thread, one HIP stream and one
-// context per slot.  Every HIP call a slot makes (its context, its device
-// arrays, its pinned staging, its stream) happens on that slot's own thread;
-// the caller's threads only hand requests over and collect them.
+// Request executor for serving: slots of one HIP stream and one context
+// each, driven by a few native worker threads.  Every HIP call a slot makes
+// (its context, its device arrays, its pinned staging, its stream) happens on
+// the worker thread that owns the slot; the caller's threads only hand
+// requests over and collect them.
 //
-// A slot's worker takes a request, stages its nine input arrays into pinned
-// memory, copies them to the device in one transfer, runs the request through
-// the public entry points (sph_evaluate, or sph_upload_state + captured steps +
-// sph_download_state), brings the wanted outputs back in one transfer, writes
-// them into the caller's arrays and marks the slot idle before the request is
-// published as done.
+// A worker owns slots k, k + T, k + 2T, ... (T threads).  For each request
+// handed to one of them it stages the nine input arrays into the slot's
+// pinned memory, copies them to the device in one transfer and enqueues the
+// request (sph_evaluate, or sph_upload_state + captured steps +
+// sph_download_state) and the copies of its outputs back, then goes on to its
+// other slots.  When a slot's stream reports the work done, the worker reads
+// the status and counters, writes the outputs into the caller's arrays and
+// marks the slot idle before publishing the request as done.  So a thread
+// keeps several requests in flight on the GPU while it stages the next.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,17 +37,20 @@ constexpr int kMaxSlots = 64;
 // device bytes per particle of a slot's arrays: every FP64 field and both counts
 constexpr size_t kArrayBytesPerParticle = SPH_NF64 * sizeof(double) + kI32 * sizeof(int32_t);
 
+struct Worker;
+
 struct Slot {
     int idx = 0;
-    std::thread th;
-    // guarded by mu
-    std::mutex mu;
-    std::condition_variable cv;
-    sph_request *job = nullptr;  // handed over, not yet taken by the worker
+    Worker *w = nullptr;
+    // guarded by w->mu
+    sph_request *job = nullptr;  // handed over, not yet started
     bool busy = false;           // from submit until the request is published
     bool release = false;        // the caller asks the worker to free its buffers
-    bool quit = false;
     // owned by the worker thread
+    sph_request *run = nullptr;  // enqueued on the stream, not yet finished
+    bool eval = false;           // the running request's kind
+    int lo = 0, hi = -1;         // rows of the outputs copied back
+    std::chrono::steady_clock::time_point t_enqueued;
     hipStream_t stream = nullptr;
     hipError_t stream_err = hipSuccess;
     sph_ctx *ctx = nullptr;
@@ -55,11 +62,23 @@ struct Slot {
     std::atomic<size_t> bytes{0};
 };
 
+struct Worker {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<Slot *> slots;
+    bool quit = false;
+};
+
+// a worker with a request in flight looks at its streams this often
+constexpr auto kPoll = std::chrono::microseconds(20);
+
 }  // namespace
 
 struct sph_server {
     int device = 0;
     std::vector<std::unique_ptr<Slot>> slots;
+    std::vector<std::unique_ptr<Worker>> workers;
     std::mutex mu;               // guards done and running
     std::condition_variable cv;
     std::deque<sph_request *> done;
@@ -162,24 +181,36 @@ sph_particles device_view(double *base, int64_t n)
     return d;
 }
 
-// One request on the slot's stream; returns the request's status.
-sph_status run(Slot &s, sph_request *r)
+double seconds_since(std::chrono::steady_clock::time_point &t)
+{
+    const auto now = std::chrono::steady_clock::now();
+    const double d = std::chrono::duration<double>(now - t).count();
+    t = now;
+    return d;
+}
+
+// Stage and enqueue request r on slot s.  Returns true when the request is
+// in flight; false when it is already complete (n = 0 or an error, with
+// r->status set).
+bool start(Slot &s, sph_request *r)
 {
     const int64_t n = r->n;
     if (n == 0) {               // nothing to compute, nothing allocated
         set_error(r, SPH_OK, "");
-        return SPH_OK;
+        return false;
     }
-    sph_status st = prepare(s, r);
-    if (st != SPH_OK) return st;
+    auto t = std::chrono::steady_clock::now();
+    if (prepare(s, r) != SPH_OK) return false;
     const size_t row = (size_t)n * sizeof(double);
     for (int k = 0; k < SPH_NIN; k++) std::memcpy(s.pin + (size_t)k * n, r->in[k], row);
+    r->host_seconds[0] = seconds_since(t);
     hipError_t e = hipMemcpyAsync(s.dev, s.pin, SPH_NIN * row, hipMemcpyHostToDevice, s.stream);
-    if (e != hipSuccess) return hip_fail(r, e, "input copy");
+    if (e != hipSuccess) { hip_fail(r, e, "input copy"); return false; }
     sph_particles d = device_view(s.dev, n);
 
-    const bool eval = r->kind == SPH_REQUEST_EVALUATE;
-    if (eval) {
+    s.eval = r->kind == SPH_REQUEST_EVALUATE;
+    sph_status st;
+    if (s.eval) {
         st = sph_evaluate(s.ctx, &d);
     } else {
         st = sph_upload_state(s.ctx, &d);
@@ -194,108 +225,173 @@ sph_status run(Slot &s, sph_request *r)
         for (; st == SPH_OK && left > 0; left--) st = sph_step(s.ctx, 0.0, nullptr);
         if (st == SPH_OK) st = sph_download_state(s.ctx, &d);
     }
-    if (st == SPH_OK) st = sph_sync(s.ctx);
     if (st != SPH_OK) {
         set_error(r, st, sph_last_error(s.ctx));
         (void)sph_sync(s.ctx);   // clear the sticky status for the slot's next request
-        return st;
+        return false;
     }
-
     // the wanted outputs: one copy of the rows from the first to the last wanted
-    int lo = SPH_NF64, hi = -1;
+    s.lo = SPH_NF64;
+    s.hi = -1;
     for (int k = 0; k < SPH_NF64; k++) {
-        const bool written = eval ? k >= SPH_F_H : k != SPH_F_M;
-        if (written && r->out[k]) { lo = std::min(lo, k); hi = std::max(hi, k); }
+        const bool written = s.eval ? k >= SPH_F_H : k != SPH_F_M;
+        if (written && r->out[k]) { s.lo = std::min(s.lo, k); s.hi = std::max(s.hi, k); }
     }
-    const bool counts = r->iout[0] || r->iout[1];
-    if (hi >= 0) {
-        e = hipMemcpyAsync(s.pin + (size_t)lo * n, d.x + (size_t)lo * n, (size_t)(hi - lo + 1) * row,
+    if (s.hi >= 0) {
+        e = hipMemcpyAsync(s.pin + (size_t)s.lo * n, d.x + (size_t)s.lo * n,
+                           (size_t)(s.hi - s.lo + 1) * row, hipMemcpyDeviceToHost, s.stream);
+        if (e != hipSuccess) { hip_fail(r, e, "output copy"); return false; }
+    }
+    if (r->iout[0] || r->iout[1]) {
+        e = hipMemcpyAsync(s.pin + (size_t)SPH_NF64 * n, d.nngb, (size_t)kI32 * n * sizeof(int32_t),
                            hipMemcpyDeviceToHost, s.stream);
-        if (e != hipSuccess) return hip_fail(r, e, "output copy");
+        if (e != hipSuccess) { hip_fail(r, e, "count copy"); return false; }
     }
-    int32_t *ipin = reinterpret_cast<int32_t *>(s.pin + (size_t)SPH_NF64 * n);
-    if (counts) {
-        e = hipMemcpyAsync(ipin, d.nngb, (size_t)kI32 * n * sizeof(int32_t), hipMemcpyDeviceToHost,
-                           s.stream);
-        if (e != hipSuccess) return hip_fail(r, e, "count copy");
+    r->host_seconds[1] = seconds_since(t);
+    s.t_enqueued = t;
+    return true;
+}
+
+// The request in flight on slot s, whose stream has drained: its status,
+// counters and outputs.
+void finish(Slot &s, sph_request *r)
+{
+    auto t = std::chrono::steady_clock::now();
+    r->host_seconds[2] = std::chrono::duration<double>(t - s.t_enqueued).count();
+    const int64_t n = r->n;
+    sph_status st = sph_sync(s.ctx);
+    if (st != SPH_OK) {
+        set_error(r, st, sph_last_error(s.ctx));
+        (void)sph_sync(s.ctx);
+        return;
     }
-    // sph_state_info waits for the stream, so the copies above are complete
     st = sph_state_info(s.ctx, &r->info);
     if (st != SPH_OK) {
         set_error(r, st, sph_last_error(s.ctx));
-        return st;
+        return;
     }
-    for (int k = lo; k <= hi; k++)
-        if (r->out[k] && (eval ? k >= SPH_F_H : k != SPH_F_M))
+    const size_t row = (size_t)n * sizeof(double);
+    for (int k = s.lo; k <= s.hi; k++)
+        if (r->out[k] && (s.eval ? k >= SPH_F_H : k != SPH_F_M))
             std::memcpy(r->out[k], s.pin + (size_t)k * n, row);
+    const int32_t *ipin = reinterpret_cast<const int32_t *>(s.pin + (size_t)SPH_NF64 * n);
     for (int k = 0; k < kI32; k++)
         if (r->iout[k]) std::memcpy(r->iout[k], ipin + (size_t)k * n, n * sizeof(int32_t));
+    r->host_seconds[3] = seconds_since(t);
     const int64_t pairs = r->info.n_dens_pairs + r->info.n_force_pairs;
-    r->interactions = eval ? pairs : pairs * std::max<int64_t>(r->nsteps, 1);
+    r->interactions = s.eval ? pairs : pairs * std::max<int64_t>(r->nsteps, 1);
     set_error(r, SPH_OK, "");
-    return SPH_OK;
 }
 
-void worker(sph_server *S, Slot *s)
+// Mark the slot idle, then hand the request to the waiters (the worker's lock
+// is held on entry and on return, not while the server's is taken).
+void publish(sph_server *S, Slot &s, sph_request *r, std::unique_lock<std::mutex> &lk)
+{
+    s.busy = false;
+    lk.unlock();
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->done.push_back(r);
+        S->running--;
+    }
+    S->cv.notify_all();
+    lk.lock();
+}
+
+void worker(sph_server *S, Worker *W)
 {
     (void)hipSetDevice(S->device);
-    s->stream_err = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (s->stream_err != hipSuccess) s->stream = nullptr;
+    for (Slot *s : W->slots) {
+        s->stream_err = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (s->stream_err != hipSuccess) s->stream = nullptr;
+    }
+    std::unique_lock<std::mutex> lk(W->mu);
     for (;;) {
-        sph_request *r = nullptr;
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            s->cv.wait(lk, [&] { return s->job || s->release || s->quit; });
+        bool did = false, running = false, waiting = false;
+        for (Slot *s : W->slots) {
             if (s->release) {
+                lk.unlock();
                 free_buffers(*s);
+                lk.lock();
                 s->release = false;
                 s->busy = false;
-                lk.unlock();
-                s->cv.notify_all();
-                continue;
+                W->cv.notify_all();
+                did = true;
             }
-            if (!s->job) break;   // quit with nothing handed over
-            r = s->job;
-            s->job = nullptr;
+            if (s->job) {
+                sph_request *r = s->job;
+                s->job = nullptr;
+                lk.unlock();
+                std::memset(&r->info, 0, sizeof(r->info));
+                std::memset(r->host_seconds, 0, sizeof(r->host_seconds));
+                r->interactions = 0;
+                r->slot = s->idx;
+                const bool flying = start(*s, r);
+                lk.lock();
+                if (flying) s->run = r;
+                else publish(S, *s, r, lk);
+                did = true;
+            }
         }
-        std::memset(&r->info, 0, sizeof(r->info));
-        r->interactions = 0;
-        r->slot = s->idx;
-        (void)run(*s, r);
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->busy = false;
+        for (Slot *s : W->slots) {
+            if (!s->run) continue;
+            lk.unlock();
+            const bool ready = hipStreamQuery(s->stream) != hipErrorNotReady;
+            if (ready) finish(*s, s->run);
+            lk.lock();
+            if (ready) {
+                sph_request *r = s->run;
+                s->run = nullptr;
+                publish(S, *s, r, lk);
+                did = true;
+            } else {
+                running = true;
+            }
         }
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->done.push_back(r);
-            S->running--;
+        for (Slot *s : W->slots) waiting = waiting || s->job || s->release;
+        if (did || waiting) continue;
+        if (running) {
+            W->cv.wait_for(lk, kPoll);
+        } else {
+            if (W->quit) break;
+            W->cv.wait(lk, [&] {
+                bool any = W->quit;
+                for (Slot *s : W->slots) any = any || s->job || s->release;
+                return any;
+            });
         }
-        S->cv.notify_all();
     }
-    free_buffers(*s);
-    if (s->stream) (void)hipStreamDestroy(s->stream);
-    s->stream = nullptr;
+    lk.unlock();
+    for (Slot *s : W->slots) {
+        free_buffers(*s);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+        s->stream = nullptr;
+    }
 }
 
 }  // namespace
 
 extern "C" {
 
-sph_status sph_server_create(sph_server **out, int32_t slots)
+sph_status sph_server_create(sph_server **out, int32_t slots, int32_t threads)
 {
     if (!out) return SPH_EINVAL;
     *out = nullptr;
-    if (slots < 1 || slots > kMaxSlots) return SPH_EINVAL;
+    if (slots < 1 || slots > kMaxSlots || threads < 0 || threads > slots) return SPH_EINVAL;
+    if (threads == 0) threads = slots;
     int device = 0;
     if (hipGetDevice(&device) != hipSuccess) return SPH_EDEVICE;
     auto *S = new sph_server;
     S->device = device;
+    for (int k = 0; k < threads; k++) S->workers.emplace_back(new Worker);
     for (int k = 0; k < slots; k++) {
         S->slots.emplace_back(new Slot);
-        S->slots.back()->idx = k;
+        Slot *s = S->slots.back().get();
+        s->idx = k;
+        s->w = S->workers[k % threads].get();
+        s->w->slots.push_back(s);
     }
-    for (auto &sl : S->slots) sl->th = std::thread(worker, S, sl.get());
+    for (auto &w : S->workers) w->th = std::thread(worker, S, w.get());
     *out = S;
     return SPH_OK;
 }
@@ -309,9 +405,10 @@ sph_status sph_server_submit(sph_server *S, int32_t slot, sph_request *r)
         for (int k = 0; k < SPH_NIN; k++)
             if (!r->in[k]) return SPH_EINVAL;
     Slot &s = *S->slots[slot];
+    Worker &W = *s.w;
     {
-        std::lock_guard<std::mutex> lk(s.mu);
-        if (s.busy || s.quit) return SPH_EINVAL;
+        std::lock_guard<std::mutex> lk(W.mu);
+        if (s.busy || W.quit) return SPH_EINVAL;
         s.busy = true;
         s.job = r;
         r->status = SPH_OK;
@@ -319,7 +416,7 @@ sph_status sph_server_submit(sph_server *S, int32_t slot, sph_request *r)
         std::lock_guard<std::mutex> lk2(S->mu);
         S->running++;
     }
-    s.cv.notify_all();
+    W.cv.notify_all();
     return SPH_OK;
 }
 
@@ -344,12 +441,13 @@ sph_status sph_server_release(sph_server *S, int32_t slot)
 {
     if (!S || slot < 0 || slot >= (int32_t)S->slots.size()) return SPH_EINVAL;
     Slot &s = *S->slots[slot];
-    std::unique_lock<std::mutex> lk(s.mu);
-    if (s.busy || s.quit) return SPH_EINVAL;
+    Worker &W = *s.w;
+    std::unique_lock<std::mutex> lk(W.mu);
+    if (s.busy || W.quit) return SPH_EINVAL;
     s.busy = true;
     s.release = true;
-    s.cv.notify_all();
-    s.cv.wait(lk, [&] { return !s.busy; });
+    W.cv.notify_all();
+    W.cv.wait(lk, [&] { return !s.busy; });
     return SPH_OK;
 }
 
@@ -368,15 +466,15 @@ size_t sph_server_plan_bytes(const sph_params *p, int64_t n)
 sph_status sph_server_destroy(sph_server *S)
 {
     if (!S) return SPH_OK;
-    for (auto &sl : S->slots) {
+    for (auto &w : S->workers) {
         {
-            std::lock_guard<std::mutex> lk(sl->mu);
-            sl->quit = true;
+            std::lock_guard<std::mutex> lk(w->mu);
+            w->quit = true;
         }
-        sl->cv.notify_all();
+        w->cv.notify_all();
     }
-    for (auto &sl : S->slots)
-        if (sl->th.joinable()) sl->th.join();
+    for (auto &w : S->workers)
+        if (w->th.joinable()) w->th.join();
     delete S;
     return SPH_OK;
 }

@@ -65,6 +65,7 @@ class Record:
     error: str = ""
     outputs: dict = field(default_factory=dict)
     info: dict = field(default_factory=dict)
+    host_seconds: tuple = ()       # native executor: the slot thread's time, by phase
 
     @property
     def latency(self) -> float:
@@ -211,6 +212,7 @@ class Scheduler:
                     rec.outputs = out.get("outputs", {})
                     rec.interactions = int(out.get("interactions", 0))
                     rec.info = out.get("info", {})
+                    rec.host_seconds = tuple(out.get("host_seconds", ()))
                 except Exception as e:  # reported per request, the server keeps going
                     rec.error = str(e)
                 rec.done = self.clock.now()
@@ -234,7 +236,18 @@ def summarize(recs, makespan: float) -> dict:
             "requests_per_s": len(ok) / makespan if makespan > 0 else 0.0,
             "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
             "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "latency_max_ms": float(lat.max() * 1e3)}
+            "latency_max_ms": float(lat.max() * 1e3),
+            **_host_phases(ok)}
+
+
+def _host_phases(recs) -> dict:
+    """Native executor: the slot threads' summed time per phase of a request."""
+    hs = [r.host_seconds for r in recs if r.host_seconds]
+    if not hs:
+        return {}
+    tot = np.sum(np.array(hs), axis=0)
+    return {"slot_thread_seconds": dict(zip(("stage_inputs", "enqueue", "in_flight",
+                                             "write_outputs"), map(float, tot)))}
 
 
 # ----------------------------------------------------------------------------
@@ -541,10 +554,11 @@ class NativeExecutor:
     OUT_EVAL = GpuExecutor.OUT_EVAL
     OUT_INTEGRATE = ("x", "y", "z", "vx", "vy", "vz", "u", "h")
 
-    def __init__(self, max_slots: int, leaf_for=None, keep_outputs=False, download=True):
+    def __init__(self, max_slots: int, leaf_for=None, keep_outputs=False, download=True,
+                 threads: int = 0):
         from . import sph
         self.sph = sph
-        self.server = sph.Server(max_slots)
+        self.server = sph.Server(max_slots, threads)
         self.leaf_for = leaf_for or (lambda req: 16)
         self.keep_outputs = keep_outputs
         self.download = download or keep_outputs
@@ -611,7 +625,8 @@ class NativeExecutor:
         h["keep"] = None
         if r.status != self.sph.SPH_OK:
             raise self.sph.SphError(r.status, r.error.decode(errors="replace"))
-        out = {"info": self.sph.stats_dict(r.info), "interactions": int(r.interactions)}
+        out = {"info": self.sph.stats_dict(r.info), "interactions": int(r.interactions),
+               "host_seconds": tuple(r.host_seconds)}
         if self.keep_outputs:
             out["outputs"] = h["outputs"]
         return out
@@ -678,13 +693,15 @@ def _progress(done: int, total: int):
 
 
 def serve(reqs, budget: int, slots: int, mode: str, leaf_for=None, keep_outputs=False,
-          progress=False, download=True, threads=True):
+          progress=False, download=True, threads=True, native_threads: int = 0):
     """Serve `reqs`; a request completes when its results are in host memory
     (download=False stops at the device, for measurements of that part).
-    threads: in streams mode, one worker thread per slot."""
+    threads: in streams mode, one worker thread per slot; native_threads: the
+    native executor's worker threads (0: one per slot)."""
     import torch
     if mode == "native":
-        ex = NativeExecutor(slots, leaf_for=leaf_for, keep_outputs=keep_outputs, download=download)
+        ex = NativeExecutor(slots, leaf_for=leaf_for, keep_outputs=keep_outputs, download=download,
+                            threads=native_threads)
     else:
         ex = GpuExecutor(slots, mode=mode, leaf_for=leaf_for, keep_outputs=keep_outputs,
                          download=download, threads=threads)

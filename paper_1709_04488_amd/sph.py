@@ -111,6 +111,7 @@ class _Request(ctypes.Structure):
                 ("out", ctypes.c_void_p * 19), ("iout", ctypes.c_void_p * 2),
                 ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
                 ("interactions", ctypes.c_int64), ("info", _Stats),
+                ("host_seconds", ctypes.c_double * 4),
                 ("error", ctypes.c_char * REQUEST_ERROR_LEN)]
 
 
@@ -163,7 +164,7 @@ def load() -> ctypes.CDLL:
         "sph_noalloc_max_n": (i64, []),
         "sph_mfv_gradients": (ctypes.c_int, [vp, ctypes.POINTER(_MfvSet)]),
         "sph_substep": (ctypes.c_int, [vp]),
-        "sph_server_create": (ctypes.c_int, [ctypes.POINTER(vp), i32]),
+        "sph_server_create": (ctypes.c_int, [ctypes.POINTER(vp), i32, i32]),
         "sph_server_submit": (ctypes.c_int, [vp, i32, ctypes.POINTER(_Request)]),
         "sph_server_wait": (i32, [vp, ctypes.POINTER(vp), i32, d]),
         "sph_server_release": (ctypes.c_int, [vp, i32]),
@@ -564,15 +565,16 @@ def server_plan_bytes(params: Params, n: int) -> int:
 
 
 class Server:
-    """The library's request executor (sph_server_*): `slots` worker threads
-    on the current device, each with its own HIP stream and context.  Requests
-    are _Request structs that name host arrays; the caller keeps them (and
-    the arrays) alive until wait() has returned their addresses."""
+    """The library's request executor (sph_server_*): `slots` slots on the
+    current device, each with its own HIP stream and context, driven by
+    `threads` native worker threads (0: one per slot).  Requests are _Request
+    structs that name host arrays; the caller keeps them (and the arrays)
+    alive until wait() has returned their addresses."""
 
-    def __init__(self, slots: int):
+    def __init__(self, slots: int, threads: int = 0):
         self.lib = load()
         h = ctypes.c_void_p()
-        rc = self.lib.sph_server_create(ctypes.byref(h), int(slots))
+        rc = self.lib.sph_server_create(ctypes.byref(h), int(slots), int(threads))
         if rc != SPH_OK or not h.value:
             raise SphError(rc, "sph_server_create failed")
         self.h = h

@@ -59,6 +59,21 @@ def test_served_equals_alone(sph, mode):
             assert np.array_equal(rec.outputs[f], ref[f]), (req.rid, f)
 
 
+def test_native_threads_driving_several_slots_each(sph):
+    # 4 slots on 2 native threads: each thread keeps two requests in flight
+    reqs = _eval_mix()
+    print("case: native executor, 4 slots on 2 threads", flush=True)
+    recs, summary = S.serve(reqs, 256 << 20, 4, "native", keep_outputs=True, native_threads=2)
+    assert summary["completed"] == len(reqs)
+    for req, rec in zip(reqs, recs):
+        assert not rec.error, rec.error
+        ref = _alone(sph, req)
+        for f in S.GpuExecutor.OUT_EVAL:
+            assert np.array_equal(rec.outputs[f], ref[f]), (req.rid, f)
+    with pytest.raises(sph.SphError):
+        sph.Server(2, 3)          # more threads than slots
+
+
 @pytest.mark.parametrize("mode", ["native", "streams"])
 def test_served_integration_equals_eager(sph, mode):
     reqs = []
