@@ -896,9 +896,24 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
     __shared__ TreeInfo T;
     __shared__ Stage<G, PREC> S;
     __shared__ uint32_t pre[kMaxBatch + 1];
+    // Per home particle, the Newton iteration's bracket and the results of its
+    // latest evaluation.  Every lane of a particle computes the same values;
+    // kept in registers they were spilled to scratch and reloaded at every
+    // step (the loop is register-bound at 4 waves per SIMD), so they live in
+    // LDS where the per-wave budget (10 KB at 16 waves per CU) has room: FP64
+    // up to G = 16 and FP32-pair.  Each lane of the particle writes the same
+    // value and reads its own wave's writes (LDS operations of a wave are
+    // performed in order).
+    constexpr bool NR_LDS = PREC == SPH_FP32_PAIR || G <= 16;
+    __shared__ double nr_mem[NR_LDS ? 5 * G : 1];
     batch_prefix(B, pre);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
+    double *const nr_lo = nr_mem + (NR_LDS ? 0 * G + p : 0);
+    double *const nr_hi = nr_mem + (NR_LDS ? 1 * G + p : 0);
+    double *const nr_h = nr_mem + (NR_LDS ? 2 * G + p : 0);
+    double *const nr_rho = nr_mem + (NR_LDS ? 3 * G + p : 0);
+    double *const nr_om = nr_mem + (NR_LDS ? 4 * G + p : 0);
     // Candidate lists of this block: for every home particle up to KP entries
     // (r^2, and m unless all masses are equal) of the candidates within R Rc
     // of it, in the order a sweep meets them.  Entry e of particle p sits in
@@ -964,9 +979,16 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
         const bool equal_m = mu == as_const(A.mrange)[1];
         const Node home = load_const(A.nodes + leaf);
         double h = as_global((const double *)A.h)[ii];
-        double lo_b = 0.0, hi_b = INFINITY;
+        double lo_b = 0.0, hi_b = INFINITY;          // registers unless NR_LDS
         bool conv = !active;
         double h_out = h, rho_out = 0.0, om_out = 1.0;
+        if constexpr (NR_LDS) {
+            *nr_lo = 0.0;
+            *nr_hi = INFINITY;
+            *nr_h = h;
+            *nr_rho = 0.0;
+            *nr_om = 1.0;
+        }
         int n_out = 0;
         if (q == 0) {
             S.hx[p] = hx;
@@ -1148,9 +1170,15 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 const double hs = h * cbrt(A.eta3 * mi / (SIG * s0));
                 const double om = -s2 / (3.0 * s0);
                 const double fp = 1.0 - (hs * hinv) * (1.0 - om);
-                h_out = h;
-                rho_out = SIG * s0 * hinv * hinv * hinv;
-                om_out = om;
+                if constexpr (NR_LDS) {
+                    *nr_h = h;
+                    *nr_rho = SIG * s0 * hinv * hinv * hinv;
+                    *nr_om = om;
+                } else {
+                    h_out = h;
+                    rho_out = SIG * s0 * hinv * hinv * hinv;
+                    om_out = om;
+                }
                 n_out = cnt;
                 // the Newton step decides convergence before any safeguard: h and rho
                 // are final once the step would change h by at most h_rtol h and rho
@@ -1161,13 +1189,21 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 if (g == 0.0 || fabs(step) * sens <= A.h_rtol * h) {
                     conv = true;
                 } else {
-                    if (g < 0.0) lo_b = fmax(lo_b, h); else hi_b = fmin(hi_b, h);
+                    double lo = NR_LDS ? *nr_lo : lo_b, hi = NR_LDS ? *nr_hi : hi_b;
+                    if (g < 0.0) lo = fmax(lo, h); else hi = fmin(hi, h);
                     double hn = fp > 0.0 ? h - step : (g < 0.0 ? 2.0 * h : 0.5 * h);
                     hn = fmin(fmax(hn, 0.5 * h), 2.0 * h);
                     // outside the bracket of known signs: bisect it
-                    if (!(hn > lo_b && hn < hi_b)) hn = hi_b < INFINITY ? 0.5 * (lo_b + hi_b) : 2.0 * h;
+                    if (!(hn > lo && hn < hi)) hn = hi < INFINITY ? 0.5 * (lo + hi) : 2.0 * h;
                     if (!(hn == hn)) conv = true;
                     else h = hn;
+                    if constexpr (NR_LDS) {
+                        *nr_lo = lo;
+                        *nr_hi = hi;
+                    } else {
+                        lo_b = lo;
+                        hi_b = hi;
+                    }
                 }
             }
             if (cached && !(h <= Rc)) cached = false;
@@ -1184,6 +1220,11 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
             }
         }
         bool bad = false, slow = false, wide = false;
+        if constexpr (NR_LDS) {
+            h_out = *nr_h;
+            rho_out = *nr_rho;
+            om_out = *nr_om;
+        }
         if (active && q == 0) {
             A.h[i] = h_out;
             A.rho[i] = rho_out;
