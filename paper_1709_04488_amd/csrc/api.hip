@@ -26,8 +26,6 @@ sph_status hip_check(sph_ctx *c, hipError_t e, const char *what)
 
 namespace {
 
-constexpr int kRsTile = 4096;
-
 // per-particle device bytes of everything sized by the capacity
 constexpr int64_t bytes_per_particle()
 {
@@ -49,8 +47,6 @@ constexpr int64_t bytes_per_particle()
     return b;
 }
 
-// radix-sort tile counts per digit plus the 256 digit totals
-int64_t hist_words(int64_t cap) { return 256 * ceil_div(cap, kRsTile) + 256; }
 
 sph_status check_params(sph_ctx *c, const sph_params *p)
 {
@@ -636,7 +632,7 @@ constexpr int64_t static_node_bound(int64_t n)
 // aligned slices: 96 buffers at most), and the candidate lists
 constexpr int64_t kStaticBytes =
     kStaticMaxN * bytes_per_particle() + static_node_bound(kStaticMaxN) * (int64_t)sizeof(Node) +
-    4 * (256 * ((kStaticMaxN + 4095) / 4096) + 256) + 4 * (act_tiles(kStaticMaxN) + 1) + 96 * 256 +
+    4 * hist_words(kStaticMaxN) + 4 * (act_tiles(kStaticMaxN) + 1) + 96 * 256 +
     kStaticListBlocks * 2 * (int64_t)Kern<SPH_KERNEL_M4>::list * 32 * (int64_t)sizeof(double);
 
 static __device__ __align__(256) unsigned char scratch[kStaticBytes];
@@ -1395,7 +1391,7 @@ size_t sph_plan_bytes(const sph_params *p, int64_t n)
     if (!p || n < 0) return 0;
     const int64_t cap = std::max<int64_t>(n, 1024);
     return (size_t)(bytes_per_particle() * cap + node_count_bound(cap) * (int64_t)sizeof(Node) +
-                    256 * 4 * ceil_div(cap, kRsTile) + 4096 + 3 * kArgBytes +
+                    4 * hist_words(cap) + 4096 + 3 * kArgBytes +
                     cache_bytes(p->leaf_size, p->kernel, pair_grid(cap)));
 }
 

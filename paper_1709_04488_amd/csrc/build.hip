@@ -18,10 +18,9 @@ namespace {
 
 constexpr int kBoxThreads = 256;
 constexpr int kRsThreads = 256;
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kRsThreads * kRsItems;   // 4096 keys per tile
 constexpr int kMortonBits = 16;                  // per axis: 48-bit keys, 6 passes
-constexpr int64_t kRsRawTiles = 64;              // scatter forms its own offsets up to here
+static_assert(kRsTile == kRsThreads * kRsItems && kRsTileSmall == kRsThreads * kRsItemsSmall,
+              "radix tiles are 256 threads wide");
 
 __device__ inline void wave_lds_sync()
 {
@@ -137,15 +136,17 @@ __device__ inline uint32_t block_scan_256(uint32_t v, uint32_t *sh)
     return sh[t];
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(int64_t n, const uint64_t *__restrict__ keys,
                                                         int shift, uint32_t *__restrict__ hist,
                                                         int64_t ntiles)
 {
+    constexpr int64_t TILE = (int64_t)kRsThreads * ITEMS;
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = blockIdx.x * (int64_t)kRsTile;
-    for (int it = 0; it < kRsItems; it++) {
+    int64_t base = blockIdx.x * TILE;
+    for (int it = 0; it < ITEMS; it++) {
         int64_t k = base + it * kRsThreads + threadIdx.x;
         if (k < n) atomicAdd(&cnt[(keys[k] >> shift) & 255u], 1u);
     }
@@ -174,14 +175,15 @@ __global__ __launch_bounds__(256) void k_rs_digit_scan(uint32_t *__restrict__ hi
     if (threadIdx.x == 0) totals[blockIdx.x] = run;
 }
 
-// Stable scatter.  Wave w of the block owns keys [tile + w*1024, +1024) and
-// walks them in 16 rounds of 64 in index order; equal digits within a round
+// Stable scatter.  Wave w of the block owns keys [tile + w*64*ITEMS, +64*ITEMS)
+// and walks them in ITEMS rounds of 64 in index order; equal digits within a round
 // are ranked with 8 ballots, across rounds with per-wave LDS counters, and
 // across waves by an exclusive prefix of those counters.  raw = 0: offs holds
 // k_rs_digit_scan's per-digit scans over the tiles and totals the digit
 // totals; raw = 1 (few tiles): offs holds k_rs_hist's counts as they are and
 // each block forms both itself (one thread per digit summing that digit's
 // counts over the tiles), which saves the scan's launch.
+template <int ITEMS>
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint64_t *__restrict__ kin,
                                                            const uint32_t *__restrict__ vin,
                                                            uint64_t *__restrict__ kout,
@@ -194,8 +196,9 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
     __shared__ uint32_t wcnt[kRsThreads / kWave][256];
     __shared__ uint32_t dbase[256];
     __shared__ uint32_t tbase[256];            // first slot of each digit in the tile
-    __shared__ uint64_t skey[kRsTile];         // the tile in digit order
-    __shared__ uint32_t sval[kRsTile];
+    constexpr int TILE = kRsThreads * ITEMS;
+    __shared__ uint64_t skey[TILE];            // the tile in digit order
+    __shared__ uint32_t sval[TILE];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
     for (int k = threadIdx.x; k < (kRsThreads / kWave) * 256; k += kRsThreads)
@@ -225,11 +228,11 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
     }
     __syncthreads();
     const uint64_t lt = __lanemask_lt();
-    const int64_t base = blockIdx.x * (int64_t)kRsTile + w * (kRsItems * kWave);
-    uint64_t key[kRsItems];
-    uint32_t val[kRsItems];
-    uint32_t rank[kRsItems];
-    for (int r = 0; r < kRsItems; r++) {
+    const int64_t base = blockIdx.x * (int64_t)TILE + w * (ITEMS * kWave);
+    uint64_t key[ITEMS];
+    uint32_t val[ITEMS];
+    uint32_t rank[ITEMS];
+    for (int r = 0; r < ITEMS; r++) {
         int64_t k = base + r * kWave + lane;
         bool valid = k < n;
         key[r] = valid ? kin[k] : 0ull;
@@ -264,7 +267,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
     }
     __syncthreads();
     // stage the tile in digit order (stable: wave, then item, then lane)
-    for (int r = 0; r < kRsItems; r++) {
+    for (int r = 0; r < ITEMS; r++) {
         int64_t k = base + r * kWave + lane;
         if (k < n) {
             uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
@@ -278,8 +281,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t n, const uint
     // + (i - tile start of that run); dbase + offs >= tbase, so no wrap
     dbase[threadIdx.x] += before_tile - tbase[threadIdx.x];
     __syncthreads();
-    const int64_t left = n - blockIdx.x * (int64_t)kRsTile;   // >= 1
-    const int tile_n = left < kRsTile ? (int)left : kRsTile;
+    const int64_t left = n - blockIdx.x * (int64_t)TILE;   // >= 1
+    const int tile_n = left < TILE ? (int)left : TILE;
     for (int i = threadIdx.x; i < tile_n; i += kRsThreads) {
         const uint64_t kk = skey[i];
         const uint32_t d = (uint32_t)(kk >> shift) & 255u;
@@ -683,22 +686,35 @@ sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y, 
     }
     hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, x, y, z,
                        c->d_box, kMortonBits, c->keys[0], c->vals[0]);
-    int64_t ntiles = ceil_div(n, kRsTile);
-    int passes = (3 * kMortonBits + 7) / 8;
-    // up to kRsRawTiles tiles the scatter blocks form the digit offsets from
-    // the raw counts themselves (one launch fewer per pass)
+    // small sets: tiles of 1024 keys (more, shorter blocks); up to
+    // kRsRawTiles tiles the scatter blocks form the digit offsets from the raw
+    // counts themselves (one launch fewer per pass).  A stable sort's result
+    // does not depend on the tiling.
+    const bool small = rs_use_small(n);
+    const int64_t ntiles = small ? rs_small_tiles(n) : ceil_div(n, kRsTile);
+    if (256 * ntiles + 256 > c->hist_cap) return fail(c, SPH_ENOMEM, "radix count capacity");
+    const int passes = (3 * kMortonBits + 7) / 8;
     const int raw = ntiles <= kRsRawTiles ? 1 : 0;
     int cur = 0;
     for (int ps = 0; ps < passes; ps++) {
         int shift = 8 * ps;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(kRsThreads), 0, c->stream, n,
-                           c->keys[cur], shift, c->hist, ntiles);
+        if (small)
+            hipLaunchKernelGGL(k_rs_hist<kRsItemsSmall>, dim3((unsigned)ntiles), dim3(kRsThreads), 0,
+                               c->stream, n, c->keys[cur], shift, c->hist, ntiles);
+        else
+            hipLaunchKernelGGL(k_rs_hist<kRsItems>, dim3((unsigned)ntiles), dim3(kRsThreads), 0,
+                               c->stream, n, c->keys[cur], shift, c->hist, ntiles);
         if (!raw)
             hipLaunchKernelGGL(k_rs_digit_scan, dim3(256), dim3(256), 0, c->stream, c->hist, ntiles,
                                c->hist + 256 * ntiles);
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(kRsThreads), 0, c->stream, n,
-                           c->keys[cur], c->vals[cur], c->keys[cur ^ 1], c->vals[cur ^ 1], shift,
-                           c->hist, ntiles, c->hist + 256 * ntiles, raw);
+        if (small)
+            hipLaunchKernelGGL(k_rs_scatter<kRsItemsSmall>, dim3((unsigned)ntiles), dim3(kRsThreads),
+                               0, c->stream, n, c->keys[cur], c->vals[cur], c->keys[cur ^ 1],
+                               c->vals[cur ^ 1], shift, c->hist, ntiles, c->hist + 256 * ntiles, raw);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<kRsItems>, dim3((unsigned)ntiles), dim3(kRsThreads), 0,
+                               c->stream, n, c->keys[cur], c->vals[cur], c->keys[cur ^ 1],
+                               c->vals[cur ^ 1], shift, c->hist, ntiles, c->hist + 256 * ntiles, raw);
         cur ^= 1;
     }
     c->perm = c->vals[cur];

@@ -55,6 +55,24 @@ constexpr int64_t kMaxPairBlocks = 256 * 16;
 
 // Active-leaf compaction of block time-steps: leaves per block, and the
 // per-block counts (one more than the blocks, for the bound of n leaves)
+// Radix sort tiles: 4096 keys (256 threads x 16) per block; sets of at most
+// kRsRawTiles small tiles of 1024 keys (256 x 4) sort with those instead (four
+// times the blocks and a quarter of each block's chain), and up to kRsRawTiles
+// tiles the scatter forms the digit offsets from the raw counts.  The counts
+// take 256 words per tile plus 256 digit totals.
+constexpr int kRsItems = 16, kRsItemsSmall = 4;
+constexpr int64_t kRsTile = 256 * kRsItems, kRsTileSmall = 256 * kRsItemsSmall;
+constexpr int64_t kRsRawTiles = 64;
+constexpr int64_t rs_small_tiles(int64_t n) { return (n + kRsTileSmall - 1) / kRsTileSmall; }
+constexpr bool rs_use_small(int64_t n) { return rs_small_tiles(n) <= kRsRawTiles; }
+constexpr int64_t hist_words(int64_t cap)
+{
+    // the larger of the two tilings any n <= cap can use
+    const int64_t big = (cap + kRsTile - 1) / kRsTile;
+    const int64_t small = rs_small_tiles(cap) < kRsRawTiles ? rs_small_tiles(cap) : kRsRawTiles;
+    return 256 * (big > small ? big : small) + 256;
+}
+
 constexpr int kActTile = 1024;
 constexpr int64_t act_tiles(int64_t cap) { return (cap + kActTile - 1) / kActTile + 1; }
 inline unsigned pair_grid(int64_t n)

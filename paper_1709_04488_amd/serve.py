@@ -738,12 +738,15 @@ def serving_tuner(reqs, budget: int, slots: int, tune_table: str = None):
 def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200,
                budget_gib: float = None, slots: int = 3, mode: str = "native",
                load: float = 0.8, max_side: int = None, leaf="auto", tune_table: str = None,
-               threads: bool = True, progress: bool = True) -> dict:
+               threads: bool = True, progress: bool = True, saturated_only: bool = False,
+               repeat: int = 1) -> dict:
     """Serve one of the two workloads and summarise it.  evaluate: a closed
     burst (every request at t = 0) gives the saturated capacity, then Poisson
-    arrivals at `load` times that rate; integrate: `requests` resident
-    integrations of `steps` KDK steps each.  Every request class is tuned
-    before the timed runs when leaf is "auto"."""
+    arrivals at `load` times that rate (saturated_only: the burst alone);
+    integrate: `requests` resident integrations of `steps` KDK steps each.
+    Every request class is tuned before the timed runs when leaf is "auto".
+    repeat: serve the burst that many times, 0.2 s apart (the last pass is
+    reported; a trace can tell the passes apart by the pause)."""
     gib = budget_gib if budget_gib else (1.0 if workload == "evaluate" else 16.0)
     budget = int(gib * GIB)
 
@@ -761,15 +764,19 @@ def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200
     if workload == "evaluate":
         burst = evaluate_requests(requests, math.inf, n_max_side=max_side)
         pretune(burst)
-        _, closed = serve(burst, budget, slots, mode, leaf_for=leaf_for, progress=progress,
-                          threads=threads)
-        rate = load * closed["requests_per_s"]
-        reqs = evaluate_requests(requests, rate, n_max_side=max_side)
-        _, opened = serve(reqs, budget, slots, mode, leaf_for=leaf_for, progress=progress,
-                          threads=threads)
+        for k in range(max(int(repeat), 1)):
+            if k:
+                time.sleep(0.2)
+            _, closed = serve(burst, budget, slots, mode, leaf_for=leaf_for, progress=progress,
+                              threads=threads)
         res = {"workload": "evaluate", "mode": mode, "slots": slots, "leaf": leaf,
-               "budget_bytes": budget, "saturated": closed, "arrival_rate_per_s": rate,
-               "poisson": opened}
+               "budget_bytes": budget, "saturated": closed}
+        if not saturated_only:
+            rate = load * closed["requests_per_s"]
+            reqs = evaluate_requests(requests, rate, n_max_side=max_side)
+            _, opened = serve(reqs, budget, slots, mode, leaf_for=leaf_for, progress=progress,
+                              threads=threads)
+            res.update({"arrival_rate_per_s": rate, "poisson": opened})
     else:
         reqs = integrate_requests(requests, steps, n_max_side=max_side)
         pretune(reqs)
@@ -807,10 +814,15 @@ def main(argv=None):
     ap.add_argument("--tune-table", default=None, help="JSON table of the autotuner to load and update")
     ap.add_argument("--no-threads", action="store_true",
                     help="streams mode: drive every slot from the main thread")
+    ap.add_argument("--saturated-only", action="store_true",
+                    help="evaluate: serve the closed burst only (no Poisson pass)")
+    ap.add_argument("--repeat", type=int, default=1,
+                    help="evaluate: serve the burst this many times, 0.2 s apart")
     args = ap.parse_args(argv)
     res = run_served(args.workload, args.requests, args.steps, args.budget_gib, args.slots,
                      args.mode, args.load, args.max_side, args.leaf, args.tune_table,
-                     threads=not args.no_threads)
+                     threads=not args.no_threads, saturated_only=args.saturated_only,
+                     repeat=args.repeat)
     print(json.dumps(res), flush=True)
 
 
