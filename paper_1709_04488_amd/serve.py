@@ -606,8 +606,13 @@ class NativeExecutor:
             outs = self._outputs(slot, req)
             r, keep = self.sph.make_request(kind, req.arrays, self.params(req), req.nsteps, outs)
             h = {"req": req, "r": r, "keep": keep, "outputs": outs, "done": False}
-            self.pending[ctypes.addressof(r)] = h
-            self.server.submit(slot, r)
+            addr = ctypes.addressof(r)
+            self.pending[addr] = h
+            try:
+                self.server.submit(slot, r)
+            except Exception:
+                del self.pending[addr]
+                raise
             hs.append(h)
         return hs
 
