@@ -531,7 +531,9 @@ sph_status sph_kernel_times(sph_ctx *ctx, int32_t which, double *ms, int64_t *la
  * is the caller's choice: sph_server_plan_bytes gives what a slot holds.
  * Results are bit-for-bit those of the same calls made one by one on a
  * fresh context: the library's results do not depend on what a context
- * ran before.
+ * ran before.  A request computes nothing of its own: its work is that of
+ * the entry points it runs (density and forces of section 2.1.1, the
+ * time-step of section 2.1.4, the kick-drift-kick steps of section 2.1.3).
  */
 #define SPH_REQUEST_EVALUATE  0
 #define SPH_REQUEST_INTEGRATE 1
