@@ -33,6 +33,7 @@ constexpr int64_t bytes_per_particle()
     b += 2 * 8 + 2 * 4;        // sort keys / values, ping-pong
     b += 17 * 8 + 2 * 4 + 4;   // s: doubles, nngb/nforce, id
     b += (int64_t)sizeof(ForceRec);   // s: force records
+    b += (int64_t)sizeof(ForceRec32); // s: their single-precision copies
     b += 4 * 8;                // s: predictor arrays
     b += 6 * 8;                // s: viscosity switches (alpha, predictor, rate, div v of
                                //    the last step, div v, |curl v|)
@@ -203,6 +204,7 @@ sph_status lay_out(sph_ctx *c, int64_t cap, Take take)
                      &T.vpx, &T.vpy, &T.vpz, &T.up, &T.al, &T.alp, &T.dprev};
     for (double **pp : sd) A_(*pp, cap);
     A_(S.frec, cap);
+    A_(S.frec32, cap);
     A_(S.nngb, cap); A_(S.nforce, cap);
     A_(S.id, cap); A_(T.id, cap);
     A_(S.fx, cap); A_(S.fy, cap); A_(S.fz, cap);

@@ -634,7 +634,8 @@ __global__ __launch_bounds__(256) void k_force_prep(int64_t n, double gamma,
                                                     const double *__restrict__ vx,
                                                     const double *__restrict__ vy,
                                                     const double *__restrict__ vz,
-                                                    ForceRec *__restrict__ rec)
+                                                    ForceRec *__restrict__ rec,
+                                                    ForceRec32 *__restrict__ rec32)
 {
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -650,6 +651,18 @@ __global__ __launch_bounds__(256) void k_force_prep(int64_t n, double gamma,
     f.A = P / (omega[k] * r * r);
     f.rho = r;
     rec[k] = f;
+    if (rec32) {
+        ForceRec32 g;
+        g.c = (float)f.c;
+        g.hinv = (float)f.hinv;
+        g.vx = (float)f.vx;
+        g.vy = (float)f.vy;
+        g.vz = (float)f.vz;
+        g.m = (float)f.m;
+        g.A = (float)f.A;
+        g.rho = (float)f.rho;
+        rec32[k] = g;
+    }
 }
 
 } // namespace
@@ -802,7 +815,7 @@ sph_status force_prep(sph_ctx *c, int64_t n, const double *u_sorted, const doubl
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_force_prep, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n,
                        c->p.gamma, c->s.rho, c->s.omega, u_sorted, c->s.h, c->s.m, vx, vy, vz,
-                       c->s.frec);
+                       c->s.frec, c->p.precision == SPH_FP32_PAIR ? c->s.frec32 : nullptr);
     return hip_check(c, hipGetLastError(), "force_prep");
 }
 

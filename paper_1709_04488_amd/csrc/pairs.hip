@@ -113,6 +113,7 @@ sph_status forces_prepare(sph_ctx *c, int64_t n)
     a.x = c->s.x; a.y = c->s.y; a.z = c->s.z;
     a.h = c->s.h;
     a.rec = c->s.frec;
+    a.rec32 = c->p.precision == SPH_FP32_PAIR ? c->s.frec32 : nullptr;
     a.fx = c->s.fx; a.fy = c->s.fy; a.fz = c->s.fz;
     a.ax = c->s.ax; a.ay = c->s.ay; a.az = c->s.az; a.du = c->s.du;
     a.vsig = c->s.vsig; a.dt = c->s.dt; a.nforce = c->s.nforce;
@@ -143,7 +144,7 @@ sph_status forces_prepare(sph_ctx *c, int64_t n)
                          c->d_fargs};
     for (const void *q : req)
         if (!q) return fail(c, SPH_EINVAL, "forces: internal buffer not allocated");
-    if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz))
+    if (c->p.precision == SPH_FP32_PAIR && (!a.fx || !a.fy || !a.fz || !a.rec32))
         return fail(c, SPH_EINVAL, "forces: offsets not allocated");
     if (c->tree_n != n || n <= 0) return fail(c, SPH_ESTATE, "forces: tree not built");
     hipLaunchKernelGGL(k_prologue<ForceArgs>, dim3(1), dim3(64), 0, c->stream, a,

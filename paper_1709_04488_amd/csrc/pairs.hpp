@@ -1323,6 +1323,9 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
         const double gfi = SIG * (hinvi * hinvi) * (hinvi * hinvi);
         const float hinvif = (float)hinvi;
         const float gfif = (float)SIG * (hinvif * hinvif) * (hinvif * hinvif);
+        // FP32-pair: the home particle's values as its single-precision record holds them
+        const float vxif = (float)vxi, vyif = (float)vyi, vzif = (float)vzi;
+        const float Aif = (float)Ai, cif = (float)ci, rhoif = (float)rhoi;
         const Node home = load_const(F.nodes + leaf);
         if (q == 0) {
             S.hx[p] = hx;
@@ -1378,8 +1381,12 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                 F.count_tests != 0, boxes, tests);
             const uint64_t w0 = S.mask[p][0], w1 = S.mask[p][1];
             // the record of a neighbour that the pair terms read (one line)
-            using JData = ForceRec;
-            auto load_j = [&](int sl) { return load_global(F.rec + S.j[sl]); };
+            // FP32-pair: the neighbours' single-precision records (32 bytes)
+            using JData = std::conditional_t<PREC == SPH_FP64, ForceRec, ForceRec32>;
+            auto load_j = [&](int sl) {
+                if constexpr (PREC == SPH_FP64) return load_global(F.rec + S.j[sl]);
+                else return load_global(F.rec32 + S.j[sl]);
+            };
             auto pair_terms = [&](int sl, const JData &d) {
                 double dx, dy, dz, r2;
                 // FP64: home position from LDS, as in the density flush
@@ -1388,14 +1395,14 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                                     hfx, hfy, hfz, sl, dx, dy, dz, r2);
                 const double cj = d.c;
                 if (r2 == 0.0) {
-                    vs_max = fmax(vs_max, PREC == SPH_FP64 ? ci + cj : (double)((float)ci + (float)cj));
+                    vs_max = fmax(vs_max, PREC == SPH_FP64 ? ci + cj : (double)(cif + (float)cj));
                     return;
                 }
                 // the pair's viscosity strength: (alpha_i + alpha_j)/2 with
                 // per-particle values, alpha_AV otherwise
                 const double aij = (SW && alpha_p) ? 0.5 * (alpha_i + as_global(alpha_p)[S.j[sl]])
                                                    : alpha;
-                if (PREC == SPH_FP64) {
+                if constexpr (PREC == SPH_FP64) {
                     const double rinv = rsqrt_nr(r2);
                     const double rr = r2 * rinv;
                     const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
@@ -1445,7 +1452,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     const float rinv = __builtin_amdgcn_rsqf((float)r2);
                     const float rr = (float)r2 * rinv;
                     const float ex = fdx * rinv, ey = fdy * rinv, ez = fdz * rinv;
-                    const float hinvj = (float)d.hinv;
+                    const float hinvj = d.hinv;
                     // own and other kernel factors formed by the same float
                     // expression, so the (j, i) pair sees exactly the values of
                     // the (i, j) pair
@@ -1455,28 +1462,28 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     kern<K>(rr * hinvj, fj, dfj);
                     float gi, gj, gsum;
                     sym_grads(gfif, dfi, gfjf, dfj, gi, gj, gsum);
-                    const float w = ((float)(vxi - d.vx) * ex + (float)(vyi - d.vy) * ey) +
-                                    (float)(vzi - d.vz) * ez;
-                    const float mj = (float)d.m;
-                    const float Aif = (float)Ai;
-                    const float cif = (float)ci, cjf = (float)cj;
-                    float cvec = -mj * sym_dot2(Aif, gi, (float)d.A, gj);
+                    const float w = ((vxif - d.vx) * ex + (vyif - d.vy) * ey) + (vzif - d.vz) * ez;
+                    const float mj = d.m;
+                    const float cjf = d.c;
+                    float cvec = -mj * sym_dot2(Aif, gi, d.A, gj);
                     float cdu = Aif * mj * gi * w;
                     const float wneg = fminf(w, 0.0f);
                     const float vs = (cif + cjf) - (float)beta * wneg;
                     vs_max = fmax(vs_max, (double)vs);
-                    const float rbinv = __builtin_amdgcn_rcpf(0.5f * ((float)rhoi + (float)d.rho));
+                    const float rbinv = __builtin_amdgcn_rcpf(0.5f * (rhoif + d.rho));
                     const float visc = (mj * rbinv) * (float)aij * vs * wneg;
                     const float gbar = 0.5f * gsum;
                     cvec += visc * gbar;
                     cdu -= visc * 0.5f * wneg * gbar;
                     if constexpr (AC) {
-                        // differences of u and P formed in double precision
-                        const double c2i = ci * ci, c2j = cj * cj;
+                        // differences of u and P formed in double precision from
+                        // the single-precision values both sides of the pair see
+                        const double c2i = (double)cif * cif, c2j = (double)cjf * cjf;
                         const float du_ij = (float)((c2i - c2j) * u_per_c2);
                         const float vc =
                             ac_price
-                                ? sqrtf((float)(fabs(rhoi * c2i - d.rho * c2j) * inv_gamma) * rbinv)
+                                ? sqrtf((float)(fabs((double)rhoif * c2i - (double)d.rho * c2j) *
+                                                inv_gamma) * rbinv)
                                 : fabsf(w);
                         cdu += (mj * rbinv) * (float)alpha_ac * vc * du_ij * gbar;
                     }
@@ -1485,8 +1492,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_forces(B
                     azi += (double)(cvec * ez);
                     dui += (double)cdu;
                     if constexpr (SW) {
-                        const float vxij = (float)(vxi - d.vx), vyij = (float)(vyi - d.vy);
-                        const float vzij = (float)(vzi - d.vz);
+                        const float vxij = vxif - d.vx, vyij = vyif - d.vy, vzij = vzif - d.vz;
                         dvs += (double)(mj * w * gi);
                         cxs += (double)(mj * gi * (vyij * ez - vzij * ey));
                         cys += (double)(mj * gi * (vzij * ex - vxij * ez));

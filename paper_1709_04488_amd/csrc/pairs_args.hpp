@@ -55,6 +55,7 @@ struct ForceArgs {
     const Node *nodes;
     const double *x, *y, *z, *h;
     const ForceRec *rec;
+    const ForceRec32 *rec32;   // FP32-pair: the single-precision records
     const float *fx, *fy, *fz;
     double *ax, *ay, *az, *du, *vsig, *dt;
     int32_t *nforce;

@@ -166,6 +166,14 @@ struct alignas(64) ForceRec {
     double c, hinv, vx, vy, vz, m, A, rho;
 };
 
+// FP32-pair mode: the same record rounded to single precision (32 bytes), so
+// the force loop's pair terms read half the bytes and convert nothing.  The
+// home particle's values are rounded the same way, so the (j, i) pair sees
+// exactly the values of the (i, j) pair.
+struct alignas(32) ForceRec32 {
+    float c, hinv, vx, vy, vz, m, A, rho;
+};
+
 // Arrays in sorted (Morton) order.  FP32-pair mode adds float offsets from the
 // centre of each particle's leaf.
 struct Sorted {
@@ -174,6 +182,7 @@ struct Sorted {
     double *m = nullptr, *u = nullptr, *h = nullptr;
     double *rho = nullptr, *omega = nullptr;
     ForceRec *frec = nullptr;                  // force record
+    ForceRec32 *frec32 = nullptr;              // its single-precision copy (FP32-pair)
     double *ax = nullptr, *ay = nullptr, *az = nullptr, *du = nullptr;
     double *vsig = nullptr, *dt = nullptr;
     int32_t *nngb = nullptr, *nforce = nullptr;
