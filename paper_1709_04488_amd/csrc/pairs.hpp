@@ -922,8 +922,12 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
     // steps read them back, summing them in the same order: a step from the
     // list gives the bits of a sweep.  The particle itself is marked (mass or,
     // with equal masses, r^2 = 0 stored negated) to keep it out of the count.
-    double *const cr2 = B.cache + (size_t)blockIdx.x * (2 * ROWS * kWave);
-    double *const cm = cr2 + ROWS * kWave;
+    // FP32-pair forms every r^2 in single precision, so its list holds them
+    // as floats (half the bytes, the same values); FP64 lists hold doubles.
+    using ListR2 = std::conditional_t<PREC == SPH_FP64, double, float>;
+    double *const cslice = B.cache + (size_t)blockIdx.x * (2 * ROWS * kWave);
+    ListR2 *const cr2 = reinterpret_cast<ListR2 *>(cslice);
+    double *const cm = cslice + ROWS * kWave;
     int64_t evals = 0, walks = 0, visits = 0, overflows = 0, nr_total = 0, tests = 0, boxes = 0;
     int64_t list_over = 0;
     int iter_max = 0;
@@ -1106,7 +1110,7 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                             if (PREC == SPH_FP64 || !equal_m) mw = S.c.w[sl];
                             if (pos < KP) {
                                 const int at = (pos / LPP) * kWave + lane;
-                                cr2[at] = r2;
+                                cr2[at] = (ListR2)r2;
                                 if (!equal_m) cm[at] = mw;
                             }
                             accumulate(r2, mw);
@@ -1136,14 +1140,14 @@ __global__ __launch_bounds__(kWave, pair_waves_per_simd<PREC>()) void k_density(
                 constexpr int kRowBatch = 4;
                 static_assert(ROWS % kRowBatch == 0, "list rows come in whole batches");
                 const int rows = wave_max_int(conv ? 0 : (count + LPP - 1) / LPP);
-                const double *__restrict__ lr2 = cr2 + lane;
+                const ListR2 *__restrict__ lr2 = cr2 + lane;
                 const double *__restrict__ lm = cm + lane;
                 const int lim = conv ? 0 : count;   // entries of this particle still iterating
                 for (int r0 = 0; r0 < rows; r0 += kRowBatch) {
                     double r2b[kRowBatch], mwb[kRowBatch];
 #pragma unroll
                     for (int b = 0; b < kRowBatch; b++) {
-                        r2b[b] = lr2[(r0 + b) * kWave];
+                        r2b[b] = (double)lr2[(r0 + b) * kWave];
                         mwb[b] = equal_m ? 0.0 : lm[(r0 + b) * kWave];
                     }
 #pragma unroll
