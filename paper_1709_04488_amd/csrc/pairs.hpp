@@ -1691,12 +1691,15 @@ __global__ __launch_bounds__(kWave) void k_neighbours(NgbArgs N, int pass)
 //   gs = sum_j (f_j - f_i) grad_i W(r_ij, h_i), the SPH gradient n_i^-1 gs
 //        used when cond(E) = |E|_F |B|_F / 3 exceeds 100.
 // One wave per home leaf, LPP lanes per particle taking every LPP-th slot
-// of each candidate leaf (the direct loop of the neighbour export: this is
-// not the hot path), sums reduced over the particle's lanes.  The sums of the
-// SPH fallback are taken in a second pass over the same pairs, only in waves
-// where some particle's E is ill-conditioned (rare), so the first pass holds
-// fewer live sums; at 4 waves per SIMD (a few spills) the C1 geometry call
-// measured 13.1 ms against 15.0 ms for the single pass unbounded (2 waves).
+// of each candidate leaf, sums reduced over the particle's lanes.  The
+// candidate leaves are staged in LDS 64 slots at a time (positions, fields,
+// per-leaf shift), so each candidate is loaded once per wave rather than by
+// every home particle.  The sums of the SPH fallback are taken in a second
+// pass over the same pairs, only in waves where some particle's E is
+// ill-conditioned (rare), so the first pass holds fewer live sums.  Measured
+// on the C1 geometry call: 15.0 ms for one pass from global memory
+// (unbounded, 2 waves per SIMD), 13.1 ms with the two passes at 4 waves,
+// 10.6 ms staged (11.5 ms staged at 3 waves).
 // ---------------------------------------------------------------------------
 
 template <int G, int K>
@@ -1704,10 +1707,15 @@ __global__ __launch_bounds__(kWave, 4) void k_mfv(MfvArgs M)
 {
     constexpr double RK = Kern<K>::R;
     constexpr int LPP = kWave / G;
-    constexpr int PER = G / LPP;
+    // candidates staged in LDS one slot per lane (MNL leaves at a time): each
+    // is loaded once per wave instead of once per home particle
+    constexpr int MS = kWave, MNL = MS / G;
     __shared__ WalkBuf wb;
     __shared__ uint32_t spare[kFront];
     __shared__ TreeInfo T;
+    __shared__ double st_x[MS], st_y[MS], st_z[MS], st_f[kMfvFields][MS];
+    __shared__ double st_s[MNL][3];
+    __shared__ int32_t st_pp[MNL], st_jn[MNL];
     load_tree(M.tree, T);
     const int lane = threadIdx.x;
     const int p = lane / LPP, q = lane % LPP;
@@ -1735,53 +1743,72 @@ __global__ __launch_bounds__(kWave, 4) void k_mfv(MfvArgs M)
         const WalkResult wr = walk(T, M.nodes, test, wb, spare);
         if (wr.lev) overflows++;
         // The pairs (i, j) with 0 < r_ij < R h_i, candidate leaf by candidate
-        // leaf: fn(d, psi, gw, j) with d = r_j - r_i, psi = psi_j(r_i) and
-        // gw = -(dW/dr) / r (grad_i W = gw d).  Every use visits them in the
-        // same order.
+        // leaf, each leaf's slots q, q + LPP, ... on lane q of the particle:
+        // fn(d, psi, gw, s) with d = r_j - r_i, psi = psi_j(r_i),
+        // gw = -(dW/dr) / r (grad_i W = gw d) and s the staged slot of j.
+        // Every use visits them in the same order.
         auto for_pairs = [&](auto fn) {
             auto group = [&](const uint32_t *leaves, int count) {
-                for (int c0 = 0; c0 < count; c0++) {
-                    const int64_t c = leaves[c0];
-                    const Node cand = M.nodes[c];
-                    const Shift sh = leaf_shift(home, cand, bx, RK * home.hmax);
-                    const int64_t j0 = M.lstart[c];
-                    const int jn = (int)(M.lstart[c + 1] - j0);
+                {
+                    const int k = lane / G, slot = lane % G;
+                    if (k < count) {
+                        const uint32_t c = leaves[k];
+                        const int64_t j0 = M.lstart[c];
+                        const int jn = (int)(M.lstart[c + 1] - j0);
+                        if (slot < jn) {
+                            const int64_t j = j0 + slot;
+                            st_x[lane] = M.x[j];
+                            st_y[lane] = M.y[j];
+                            st_z[lane] = M.z[j];
 #pragma unroll
-                    for (int t = 0; t < PER; t++) {
-                        const int jj = q + LPP * t;
-                        if (jj >= jn) continue;
-                        const int64_t j = j0 + jj;
-                        double dx = xi - M.x[j], dy = yi - M.y[j], dz = zi - M.z[j];
-                        if (sh.per_pair) {
-                            dx = min_image(dx, bx.len[0], bx.half[0]);
-                            dy = min_image(dy, bx.len[1], bx.half[1]);
-                            dz = min_image(dz, bx.len[2], bx.half[2]);
-                        } else {
-                            dx += sh.s[0];
-                            dy += sh.s[1];
-                            dz += sh.s[2];
+                            for (int f = 0; f < kMfvFields; f++)
+                                if (f < nf) st_f[f][lane] = M.f[f][j];
                         }
-                        const double r2 = exact_r2(dx, dy, dz);
-                        if (!(active && r2 < hi2x4 && r2 > 0.0)) continue;
-                        const double d[3] = {-dx, -dy, -dz};   // r_j - r_i
-                        const double r = sqrt(r2);
-                        double fk, dfk;
-                        kern<K>(r * hinv, fk, dfk);
-                        const double psi = wf * fk * ninv;
-                        // grad_i W = dW/dr (r_i - r_j) / r = -(dW/dr / r) d
-                        const double gw = -(wf * hinv * dfk) / r;
-                        fn(d, psi, gw, j);
+                        if (slot == 0) {
+                            const Shift sh = leaf_shift(home, M.nodes[c], bx, RK * home.hmax);
+                            for (int a = 0; a < 3; a++) st_s[k][a] = sh.s[a];
+                            st_pp[k] = sh.per_pair ? 1 : 0;
+                            st_jn[k] = jn;
+                        }
                     }
                 }
+                wave_lds_sync();
+#pragma unroll 1
+                for (int t = 0; t < MS / LPP; t++) {
+                    const int s = q + LPP * t;
+                    const int k = s / G;
+                    if (k >= count || s % G >= st_jn[k]) continue;
+                    double dx = xi - st_x[s], dy = yi - st_y[s], dz = zi - st_z[s];
+                    if (st_pp[k]) {
+                        dx = min_image(dx, bx.len[0], bx.half[0]);
+                        dy = min_image(dy, bx.len[1], bx.half[1]);
+                        dz = min_image(dz, bx.len[2], bx.half[2]);
+                    } else {
+                        dx += st_s[k][0];
+                        dy += st_s[k][1];
+                        dz += st_s[k][2];
+                    }
+                    const double r2 = exact_r2(dx, dy, dz);
+                    if (!(active && r2 < hi2x4 && r2 > 0.0)) continue;
+                    const double d[3] = {-dx, -dy, -dz};   // r_j - r_i
+                    const double r = sqrt(r2);
+                    double fk, dfk;
+                    kern<K>(r * hinv, fk, dfk);
+                    const double psi = wf * fk * ninv;
+                    // grad_i W = dW/dr (r_i - r_j) / r = -(dW/dr / r) d
+                    const double gw = -(wf * hinv * dfk) / r;
+                    fn(d, psi, gw, s);
+                }
+                wave_lds_sync();   // the slots are restaged for the next group
             };
-            for_each_leaf_group<kWave>(T, M.nodes, wr, test, wb, group);
+            for_each_leaf_group<MNL>(T, M.nodes, wr, test, wb, group);
         };
         // first pass: E and the least-squares sums
         double E[6] = {0, 0, 0, 0, 0, 0};
         double g[3 * kMfvFields];
 #pragma unroll
         for (int k = 0; k < 3 * kMfvFields; k++) g[k] = 0.0;
-        for_pairs([&](const double *d, double psi, double gw, int64_t j) {
+        for_pairs([&](const double *d, double psi, double gw, int sl) {
             E[0] += d[0] * d[0] * psi;
             E[1] += d[0] * d[1] * psi;
             E[2] += d[0] * d[2] * psi;
@@ -1791,7 +1818,7 @@ __global__ __launch_bounds__(kWave, 4) void k_mfv(MfvArgs M)
 #pragma unroll
             for (int k = 0; k < kMfvFields; k++) {
                 if (k >= nf) break;
-                const double df = M.f[k][j] - fi[k];
+                const double df = st_f[k][sl] - fi[k];
 #pragma unroll
                 for (int a = 0; a < 3; a++) g[3 * k + a] += df * d[a] * psi;
             }
@@ -1823,11 +1850,11 @@ __global__ __launch_bounds__(kWave, 4) void k_mfv(MfvArgs M)
 #pragma unroll
         for (int k = 0; k < 3 * kMfvFields; k++) gs[k] = 0.0;
         if (__ballot(active && sph) != 0ull) {
-            for_pairs([&](const double *d, double psi, double gw, int64_t j) {
+            for_pairs([&](const double *d, double psi, double gw, int sl) {
 #pragma unroll
                 for (int k = 0; k < kMfvFields; k++) {
                     if (k >= nf) break;
-                    const double df = M.f[k][j] - fi[k];
+                    const double df = st_f[k][sl] - fi[k];
 #pragma unroll
                     for (int a = 0; a < 3; a++) gs[3 * k + a] += df * gw * d[a];
                 }
