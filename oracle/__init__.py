@@ -101,7 +101,7 @@ def _load():
         lib.orc_mfv_gradients.restype = ctypes.c_int
         lib.orc_mfv_gradients.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, i64, vp, vp, vp, vp]
         lib.orc_kdk_block.restype = ctypes.c_int
-        lib.orc_kdk_block.argtypes = [vp, i64] + [vp] * 9 + [i32, i32, i32, vp, vp, vp, vp, vp]
+        lib.orc_kdk_block.argtypes = [vp, i64] + [vp] * 9 + [i32, i32, i32, vp, vp, vp, vp, vp, vp]
         lib.orc_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -344,16 +344,20 @@ def kdk(params: Params, x, y, z, vx, vy, vz, m, u, h_guess, nsteps: int, dt_fixe
 
 
 def kdk_block(params: Params, x, y, z, vx, vy, vz, m, u, h_guess, nfull: int, lmax: int = 20,
-              lim: int = 2):
+              lim: int = 2, alpha=None):
     """Block time-step KDK over nfull level-0 steps.  Returns (state dict,
     energy[nfull+1] at the full synchronisations, sub-steps, levels, time);
     the state dict also holds "updates", the active particles summed over
-    the sub-steps."""
+    the sub-steps.  With an AV switch, alpha holds the initial per-particle
+    strengths (default alpha_max) and the state dict the final ones (key
+    "alpha")."""
     lib = _load()
     st = {k: _f64(a).copy() for k, a in zip(("x", "y", "z", "vx", "vy", "vz", "u", "h"),
                                            (x, y, z, vx, vy, vz, u, h_guess))}
     m = _f64(m)
     n = m.size
+    if params.av_switch:
+        st["alpha"] = _f64(alpha if alpha is not None else np.full(n, params.alpha_max)).copy()
     energy = np.empty(nfull + 1)
     nsub = ctypes.c_int64(0)
     tout = ctypes.c_double(0.0)
@@ -363,7 +367,8 @@ def kdk_block(params: Params, x, y, z, vx, vy, vz, m, u, h_guess, nfull: int, lm
     rc = lib.orc_kdk_block(ctypes.byref(cp), n, _ptr(st["x"]), _ptr(st["y"]), _ptr(st["z"]),
                            _ptr(st["vx"]), _ptr(st["vy"]), _ptr(st["vz"]), _ptr(m), _ptr(st["u"]),
                            _ptr(st["h"]), int(lmax), int(lim), int(nfull), _ptr(energy),
-                           ctypes.byref(nsub), _ptr(lev), ctypes.byref(tout), ctypes.byref(upd))
+                           ctypes.byref(nsub), _ptr(lev), ctypes.byref(tout), ctypes.byref(upd),
+                           _ptr(st.get("alpha")))
     if rc != ORC_OK:
         raise OracleError(rc, "kdk_block")
     st["updates"] = int(upd.value)

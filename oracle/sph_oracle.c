@@ -864,6 +864,19 @@ int orc_mfv_gradients(const orc_params *p, int64_t n, const double *x, const dou
  * time_out = elapsed time; active_total = active particles summed over the
  * sub-steps (the particle updates the scheme made).  Returns ORC_EBOX-like errors of the solves, or
  * ORC_EINVAL if a particle needs a level beyond lmax.
+ *
+ * Viscosity switches (p->av_switch; alpha in/out as in orc_kdk, required
+ * with a switch, ignored without one) follow each particle's own steps:
+ *   MM97: alpha is integrated like u.  d alpha/dt comes from each force
+ *   evaluation of the particle (from its predicted alpha, div v, c and h);
+ *   alpha is opened, predicted to T' (the forces see the predicted alpha of
+ *   every particle, active or not), closed, and its opening kick corrected
+ *   by the reactive limiter exactly as u is.
+ *   CD10: after the forces of a sub-step, each active particle's alpha is
+ *   updated with its own step length (t_end - t_start) tick and the rate
+ *   of div v since its previous evaluation; the forces see every
+ *   particle's current alpha (that of the start of an active particle's
+ *   step).  At the start, div v of the first evaluation is the previous one.
  * ------------------------------------------------------------------------- */
 static double block_dtmax(int64_t n, const double *dt)
 {
@@ -887,11 +900,13 @@ static int level_of(double dt, double dtmax, int lmax)
 int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *z, double *vx,
                   double *vy, double *vz, const double *m, double *u, double *h, int32_t lmax,
                   int32_t lim, int32_t nfull, double *energy, int64_t *nsub, int32_t *levels,
-                  double *time_out, int64_t *active_total)
+                  double *time_out, int64_t *active_total, double *alpha)
 {
     if (n <= 0 || lmax < 0 || lmax > 40 || lim < 0 || nfull < 0) return ORC_EINVAL;
+    const int sw = p->av_switch;
+    if (sw && !alpha) return ORC_EINVAL;
     size_t N = (size_t)n;
-    double *buf = (double *)malloc(sizeof(double) * N * 30);
+    double *buf = (double *)malloc(sizeof(double) * N * 31);
     int64_t *ib = (int64_t *)malloc(sizeof(int64_t) * N * 6);
     if (!buf || !ib) { free(buf); free(ib); return ORC_ENOMEM; }
     double *vhx = buf, *vhy = buf + N, *vhz = buf + 2 * N, *uh = buf + 3 * N, *ax = buf + 4 * N,
@@ -903,6 +918,12 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
     int64_t *ts = ib, *te = ib + N, *lev = ib + 2 * N, *lmx = ib + 3 * N, *mark = ib + 4 * N,
             *sel = ib + 5 * N;
     int32_t *cnt = (int32_t *)t9;
+    /* switch state: alpha after the opening kick, predicted alpha and its
+     * rate (MM97); div v of the previous evaluation (CD10); div v and curl v
+     * of the selection */
+    double *alh = buf + 25 * N, *alp = buf + 26 * N, *adot = buf + 27 * N, *dprev = buf + 28 * N,
+           *dvs = buf + 29 * N, *cvs = buf + 30 * N;
+    const double cfac = p->gamma * (p->gamma - 1.0);
     const int64_t P0 = (int64_t)1 << lmax;
     double Lb[3];
     for (int k = 0; k < 3; k++) Lb[k] = p->hi[k] - p->lo[k];
@@ -915,8 +936,13 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
     if (rc != ORC_OK) goto out;
     memcpy(h, hn, sizeof(double) * N);
     rc = orc_forces(p, n, x, y, z, vx, vy, vz, m, u, h, rho, omega, n, NULL, ax, ay, az, du, t2,
-                    dt, t3, t4, cnt, NULL, NULL, NULL);
+                    dt, t3, t4, cnt, sw ? alpha : NULL, sw ? dvs : NULL, sw ? cvs : NULL);
     if (rc != ORC_OK) goto out;
+    for (int64_t i = 0; sw && i < n; i++) {
+        double c = sqrt(cfac * u[i]);
+        if (sw == 1) orc_mm97_rate(p, 1, &alpha[i], &dvs[i], &c, &h[i], &adot[i]);
+        else dprev[i] = dvs[i];
+    }
     double dtmax = block_dtmax(n, dt);
     for (int64_t i = 0; i < n; i++) {
         int l = level_of(dt[i], dtmax, lmax);
@@ -936,6 +962,7 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
         vhy[i] = vy[i] + ay[i] * hs;
         vhz[i] = vz[i] + az[i] * hs;
         uh[i] = u[i] + du[i] * hs;
+        if (sw == 1) alh[i] = alpha[i] + adot[i] * hs;
     }
     while (full < nfull) {
         int64_t Tn = te[0];
@@ -958,6 +985,7 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
             vpy[i] = vhy[i] + ay[i] * dm;
             vpz[i] = vhz[i] + az[i] * dm;
             up[i] = uh[i] + du[i] * dm;
+            if (sw == 1) alp[i] = alh[i] + adot[i] * dm;
             if (te[i] == Tn) sel[na++] = i;
             lmx[i] = 0;
             mark[i] = -1;
@@ -972,11 +1000,22 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
             omega[i] = t4[k];
         }
         rc = orc_forces(p, n, x, y, z, vpx, vpy, vpz, m, up, h, rho, omega, na, sel, t1, t2, t3,
-                        t4, t5, t6, t7, t8, cnt, NULL, NULL, NULL);
+                        t4, t5, t6, t7, t8, cnt, sw == 1 ? alp : (sw == 2 ? alpha : NULL),
+                        sw ? dvs : NULL, sw ? cvs : NULL);
         if (rc != ORC_OK) goto out;
         for (int64_t k = 0; k < na; k++) {
             int64_t i = sel[k];
             ax[i] = t1[k]; ay[i] = t2[k]; az[i] = t3[k]; du[i] = t4[k]; dt[i] = t6[k];
+            /* the switch from this evaluation (c from the predicted u the
+             * forces used; the step that ends now for CD10) */
+            double c = sqrt(cfac * up[i]);
+            if (sw == 1) orc_mm97_rate(p, 1, &alp[i], &dvs[k], &c, &h[i], &adot[i]);
+            if (sw == 2) {
+                double dti = (double)(te[i] - ts[i]) * tick;
+                orc_cd10_update(p, 1, dti, &alpha[i], &dvs[k], &dprev[i], &cvs[k], &t5[k], &c,
+                                &h[i]);
+                dprev[i] = dvs[k];
+            }
         }
         /* limiter information over the force neighbours of the active particles */
         for (int64_t k = 0; k < na; k++) {
@@ -1000,6 +1039,7 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
             vy[i] = vhy[i] + ay[i] * hs;
             vz[i] = vhz[i] + az[i] * hs;
             u[i] = uh[i] + du[i] * hs;
+            if (sw == 1) alpha[i] = alh[i] + adot[i] * hs;
         }
         tnow += dlt;
         subs++;
@@ -1047,6 +1087,7 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
                 vhy[j] -= ay[j] * cut;
                 vhz[j] -= az[j] * cut;
                 uh[j] -= du[j] * cut;
+                if (sw == 1) alh[j] -= adot[j] * cut;
                 lev[j] = nl;
                 te[j] = tn;
             }
@@ -1060,6 +1101,7 @@ int orc_kdk_block(const orc_params *p, int64_t n, double *x, double *y, double *
             vhy[i] = vy[i] + ay[i] * hs;
             vhz[i] = vz[i] + az[i] * hs;
             uh[i] = u[i] + du[i] * hs;
+            if (sw == 1) alh[i] = alpha[i] + adot[i] * hs;
         }
         if (full == nfull && T == 0) break;
     }
