@@ -390,9 +390,16 @@ sph_status sph_step(sph_ctx *ctx, double dt, double *dt_used);
  * Everything runs on the device (no waiting).  sph_state_info reports the
  * sub-steps, level-0 steps and the clock; at a synchronisation
  * (block_synchronised = 1) sph_download_state returns every particle at the
- * same time; otherwise positions are current and v, u are those of each
- * particle's last synchronisation.  Not combined with the viscosity
- * switches, batches or graph capture (SPH_EINVAL / SPH_ESTATE).
+ * same time; otherwise positions are current and v, u (and alpha) are
+ * those of each particle's last synchronisation.  Viscosity switches follow
+ * each particle's own steps: under SPH_AV_MM97 alpha is opened, predicted
+ * (every particle's forces see the predicted alpha of its neighbours),
+ * closed and corrected by the reactive limiter exactly as u is, its rate
+ * taken from each force evaluation of the particle; under SPH_AV_CD10 an
+ * active particle's alpha is updated after its forces with dt = its own
+ * step length and div v of its previous evaluation.  A per-particle alpha
+ * given at upload without a switch stays with its particle.  Not combined
+ * with batches or graph capture (SPH_ESTATE).
  */
 sph_status sph_substep(sph_ctx *ctx);
 

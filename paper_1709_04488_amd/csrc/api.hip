@@ -40,8 +40,8 @@ constexpr int64_t bytes_per_particle()
     b += 3 * 4;                // s: fp32 offsets
     b += 16 * 8 + 4;           // t: re-sort buffers
     b += 2 * 4;                // leaf starts, leaf of each particle
-    b += 4 + 2 * 8 + 4 * 8 + 3 * 4;   // s: block time-steps (level, step ticks, half-step v, u,
-                                      //    active flag, limiter level and mark)
+    b += 4 + 2 * 8 + 5 * 8 + 3 * 4;   // s: block time-steps (level, step ticks, half-step v, u,
+                                      //    alpha, active flag, limiter level and mark)
     b += 8 * 8 + 4 + 2 * 8;    // t: block re-sort (a, du, rho, Omega, dt, vsig, level, ticks)
     b += 4;                    // active particles per leaf
     b += 4;                    // active leaves (the list; the tile counts are counted apart)
@@ -71,8 +71,6 @@ sph_status check_params(sph_ctx *c, const sph_params *p)
         return fail(c, SPH_EINVAL, "claim_leaves must be 0..64");
     if (p->block_lmax < 0 || p->block_lmax > 40 || p->block_lim < 0)
         return fail(c, SPH_EINVAL, "need 0 <= block_lmax <= 40 and block_lim >= 0");
-    if (p->block_lmax > 0 && p->av_switch != SPH_AV_NONE)
-        return fail(c, SPH_EINVAL, "block time-steps do not run with a viscosity switch");
     if (p->av_switch != SPH_AV_NONE && p->av_switch != SPH_AV_MM97 && p->av_switch != SPH_AV_CD10)
         return fail(c, SPH_EINVAL, "av_switch must be SPH_AV_NONE, SPH_AV_MM97 or SPH_AV_CD10");
     if (!(p->alpha_min >= 0.0) || !(p->alpha_max >= p->alpha_min) || !std::isfinite(p->alpha_max) ||
@@ -209,7 +207,7 @@ sph_status lay_out(sph_ctx *c, int64_t cap, Take take)
     A_(S.id, cap); A_(T.id, cap);
     A_(S.fx, cap); A_(S.fy, cap); A_(S.fz, cap);
     A_(c->lstart, cap + 1); A_(c->leaf_id, cap);
-    double **bd[] = {&S.vhx, &S.vhy, &S.vhz, &S.uh, &T.ax, &T.ay, &T.az, &T.du, &T.rho,
+    double **bd[] = {&S.vhx, &S.vhy, &S.vhz, &S.uh, &S.alh, &T.ax, &T.ay, &T.az, &T.du, &T.rho,
                      &T.omega, &T.dt, &T.vsig};
     for (double **pp : bd) A_(*pp, cap);
     A_(S.lev, cap); A_(T.lev, cap);
@@ -1059,9 +1057,24 @@ sph_status sph_substep(sph_ctx *c)
     g.kind[k] = 1; g.src[k] = S.lev; g.dst[k] = T.lev; k++;
     g.kind[k] = 0; g.src[k] = S.ts; g.dst[k] = T.ts; k++;
     g.kind[k] = 0; g.src[k] = S.te; g.dst[k] = T.te; k++;
+    // per-particle alpha and the switch state, through the re-sort buffers
+    // the global step uses for them (the predicted alpha is recomputed every
+    // sub-step, so its buffer takes the half-step alpha; MM97 keeps no div v
+    // of the last step, so that buffer takes the rate)
+    const int sw = c->p.av_switch;
+    double **xa[3], **xb[3];
+    int nx = 0;
+    if (c->res_alpha) { xa[nx] = &S.al; xb[nx++] = &T.al; }
+    if (sw == SPH_AV_MM97) {
+        xa[nx] = &S.alh; xb[nx++] = &T.alp;
+        xa[nx] = &S.adot; xb[nx++] = &T.dprev;
+    }
+    if (sw == SPH_AV_CD10) { xa[nx] = &S.dprev; xb[nx++] = &T.dprev; }
+    for (int a = 0; a < nx; a++) { g.kind[k] = 0; g.src[k] = *xa[a]; g.dst[k] = *xb[a]; k++; }
     g.count = k;
     TRY(gather(c, n, g, false));
     for (int a = 0; a < nd; a++) std::swap(*sa[a], *ta[a]);
+    for (int a = 0; a < nx; a++) std::swap(*xa[a], *xb[a]);
     std::swap(S.id, T.id);
     std::swap(S.lev, T.lev);
     std::swap(S.ts, T.ts);
@@ -1072,8 +1085,9 @@ sph_status sph_substep(sph_ctx *c)
     TRY(block_predict(c, n));
     c->f_act = S.act;
     c->f_block = true;
-    c->f_alpha = nullptr;
-    c->f_div = false;
+    // the forces see every particle's predicted alpha (MM97) or its current
+    // one (CD10, or a constant per-particle alpha given at upload)
+    resident_force_inputs(c);
     sph_status st = density_prepare(c, n);
     if (st == SPH_OK) st = density_launch(&c, 1, n);
     if (st == SPH_OK) st = refresh_hmax(c, n);
@@ -1083,7 +1097,9 @@ sph_status sph_substep(sph_ctx *c)
     c->f_block = false;
     TRY(st);
     TRY(forces_launch(&c, 1, n));
-    // closing kicks, levels, limiter, opening kicks, clock
+    // the switches of the active particles from these forces, then closing
+    // kicks, levels, limiter, opening kicks, clock
+    TRY(block_av(c, n));
     TRY(block_finish(c, n, false));
     TRY(reduce_diag(c, n));
     c->steps++;

@@ -193,12 +193,12 @@ struct Sorted {
     // (MM97), div v of the previous step (CD10); div v and |curl v| outputs
     double *al = nullptr, *alp = nullptr, *adot = nullptr, *dprev = nullptr;
     double *divv = nullptr, *curlv = nullptr;
-    // block time-steps: level, step start and end (ticks), half-step v and u,
-    // the active flag and the limiter's neighbour level and wake-up mark of
-    // the current sub-step
+    // block time-steps: level, step start and end (ticks), half-step v and u
+    // (and alpha under MM97), the active flag and the limiter's neighbour
+    // level and wake-up mark of the current sub-step
     int32_t *lev = nullptr;
     int64_t *ts = nullptr, *te = nullptr;
-    double *vhx = nullptr, *vhy = nullptr, *vhz = nullptr, *uh = nullptr;
+    double *vhx = nullptr, *vhy = nullptr, *vhz = nullptr, *uh = nullptr, *alh = nullptr;
     int32_t *act = nullptr, *lmx = nullptr, *mark = nullptr;
     // FP32-pair mode
     float *fx = nullptr, *fy = nullptr, *fz = nullptr;
@@ -422,6 +422,7 @@ sph_status fill(sph_ctx *c, int64_t n, double *v, double value);
 sph_status block_next(sph_ctx *c, int64_t n);           // Tn = min te; drift every particle
 sph_status block_predict(sph_ctx *c, int64_t n);        // predictors, active set, leaf counts
 sph_status block_finish(sph_ctx *c, int64_t n, bool init);  // close, levels, limiter, open, clock
+sph_status block_av(sph_ctx *c, int64_t n);             // switches of the active particles
 sph_status reduce_dt(sph_ctx *c, int64_t n);
 // smallest and largest sorted mass -> d_scal[8], d_scal[9]
 sph_status reduce_mass_range(sph_ctx *c, int64_t n);

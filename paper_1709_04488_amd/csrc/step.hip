@@ -128,6 +128,30 @@ __global__ __launch_bounds__(256) void k_fill(int64_t n, double *__restrict__ v,
 // Morris & Monaghan 1997 rate of alpha from the alpha the forces used, their
 // div v, and c and h of the same evaluation (c from the force record):
 //   d alpha/dt = -(alpha - alpha_min) ell c / h + max(-div v, 0) (alpha_max - alpha)
+__device__ inline double mm97_rate(double a, double d, double c, double h, double amin,
+                                   double amax, double ell)
+{
+    const double decay = -(a - amin) * ell * c / h;
+    const double src = d < 0.0 ? -d * (amax - a) : 0.0;
+    return decay + src;
+}
+
+// Cullen & Dehnen 2010: alpha after a step of length dt from div v now (d)
+// and at the previous evaluation (dp), |curl v|, v_sig, c and h
+__device__ inline double cd10_alpha(double a, double dt, double d, double dp, double curl,
+                                    double vs, double c, double hk, double amin, double amax,
+                                    double ell)
+{
+    const double rate = (d - dp) / dt;
+    const double ad = fabs(d);
+    const double xi = ad / (ad + curl + 1e-4 * c / hk);
+    const double A = rate < 0.0 ? -xi * rate : 0.0;
+    const double h2A = hk * hk * A;
+    double aloc = amax * h2A / (vs * vs + h2A);
+    if (aloc < amin) aloc = amin;
+    return a < aloc ? aloc : aloc + (a - aloc) * exp(-dt * 2.0 * ell * vs / hk);
+}
+
 __global__ __launch_bounds__(256) void k_av_mm97(int64_t n, double amin, double amax, double ell,
                                                  const double *__restrict__ alpha,
                                                  const double *__restrict__ divv,
@@ -137,10 +161,7 @@ __global__ __launch_bounds__(256) void k_av_mm97(int64_t n, double amin, double 
 {
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const double a = alpha[k], d = divv[k];
-    const double decay = -(a - amin) * ell * rec[k].c / h[k];
-    const double src = d < 0.0 ? -d * (amax - a) : 0.0;
-    adot[k] = decay + src;
+    adot[k] = mm97_rate(alpha[k], divv[k], rec[k].c, h[k], amin, amax, ell);
 }
 
 // Cullen & Dehnen 2010 update of alpha after the forces at the end of a step
@@ -158,18 +179,9 @@ __global__ __launch_bounds__(256) void k_av_cd10(int64_t n, double amin, double 
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
     const double d = divv[k];
-    if (!first) {
-        const double dt = scal[1];
-        const double rate = (d - dprev[k]) / dt;
-        const double ad = fabs(d), hk = h[k], vs = vsig[k];
-        const double xi = ad / (ad + curlv[k] + 1e-4 * rec[k].c / hk);
-        const double A = rate < 0.0 ? -xi * rate : 0.0;
-        const double h2A = hk * hk * A;
-        double aloc = amax * h2A / (vs * vs + h2A);
-        if (aloc < amin) aloc = amin;
-        const double a = alpha[k];
-        alpha[k] = a < aloc ? aloc : aloc + (a - aloc) * exp(-dt * 2.0 * ell * vs / hk);
-    }
+    if (!first)
+        alpha[k] = cd10_alpha(alpha[k], scal[1], d, dprev[k], curlv[k], vsig[k], rec[k].c, h[k],
+                              amin, amax, ell);
     dprev[k] = d;
 }
 
@@ -428,6 +440,9 @@ struct BlockArgs {
     double *vhx, *vhy, *vhz, *uh;   // after the opening kick
     double *vpx, *vpy, *vpz, *up;   // predicted to the end of the sub-step
     const double *ax, *ay, *az, *du, *dt;
+    // MM97 (else null): alpha at the last synchronisation, after the opening
+    // kick, predicted, and its rate
+    double *al, *alh, *alp, *adot;
     int32_t *lev;
     int64_t *ts, *te;
     int32_t *act, *lmx, *mark;
@@ -510,6 +525,7 @@ __global__ __launch_bounds__(256) void k_block_predict(BlockArgs B)
     B.vpy[k] = B.vhy[k] + B.ay[k] * dm;
     B.vpz[k] = B.vhz[k] + B.az[k] * dm;
     B.up[k] = B.uh[k] + B.du[k] * dm;
+    if (B.alh) B.alp[k] = B.alh[k] + B.adot[k] * dm;
     B.act[k] = B.te[k] == Tn ? 1 : 0;
     B.lmx[k] = 0;
     B.mark[k] = -1;
@@ -610,6 +626,7 @@ __global__ __launch_bounds__(256) void k_block_close(BlockArgs B)
     B.vy[k] = B.vhy[k] + B.ay[k] * hs;
     B.vz[k] = B.vhz[k] + B.az[k] * hs;
     B.u[k] = B.uh[k] + B.du[k] * hs;
+    if (B.alh) B.al[k] = B.alh[k] + B.adot[k] * hs;
 }
 
 // range of the CFL steps (every particle is active at a full synchronisation)
@@ -712,6 +729,7 @@ __global__ __launch_bounds__(256) void k_block_levels(BlockArgs B, bool init)
         B.vhy[k] = B.vy[k] + B.ay[k] * hs;
         B.vhz[k] = B.vz[k] + B.az[k] * hs;
         B.uh[k] = B.u[k] + B.du[k] * hs;
+        if (B.alh) B.alh[k] = B.al[k] + B.adot[k] * hs;
     } else if (!full && B.mark[k] >= 0 && B.lev[k] < B.mark[k] - lim) {
         int64_t nl = B.mark[k] - lim;
         if (nl > B.lmax) {
@@ -725,6 +743,7 @@ __global__ __launch_bounds__(256) void k_block_levels(BlockArgs B, bool init)
         B.vhy[k] -= B.ay[k] * cut;
         B.vhz[k] -= B.az[k] * cut;
         B.uh[k] -= B.du[k] * cut;
+        if (B.alh) B.alh[k] -= B.adot[k] * cut;
         B.lev[k] = (int32_t)nl;
         B.te[k] = tn;
     }
@@ -758,6 +777,33 @@ __global__ void k_block_advance(BlockArgs B, bool init)
     }
 }
 
+// The switches of the particles active in this sub-step, from its forces:
+// the MM97 rate from the predicted alpha the forces used; the CD10 update
+// over the step that ends now, (t_end - t_start) ticks, from div v now and at
+// the particle's previous evaluation.
+struct BlockAv {
+    int sw;
+    double amin, amax, ell;
+    double *al, *adot, *dprev;
+    const double *alp, *divv, *curlv, *vsig, *h;
+    const ForceRec *rec;
+};
+
+__global__ __launch_bounds__(256) void k_block_av(BlockArgs B, BlockAv V)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= B.n || !B.act[k]) return;
+    const double d = V.divv[k];
+    if (V.sw == SPH_AV_MM97) {
+        V.adot[k] = mm97_rate(V.alp[k], d, V.rec[k].c, V.h[k], V.amin, V.amax, V.ell);
+    } else {
+        const double dt = (double)(B.te[k] - B.ts[k]) * B.clk->tick;
+        V.al[k] = cd10_alpha(V.al[k], dt, d, V.dprev[k], V.curlv[k], V.vsig[k], V.rec[k].c,
+                             V.h[k], V.amin, V.amax, V.ell);
+        V.dprev[k] = d;
+    }
+}
+
 BlockArgs block_args(sph_ctx *c, int64_t n)
 {
     BlockArgs B{};
@@ -775,6 +821,9 @@ BlockArgs block_args(sph_ctx *c, int64_t n)
     B.ax = S.ax; B.ay = S.ay; B.az = S.az; B.du = S.du; B.dt = S.dt;
     B.lev = S.lev; B.ts = S.ts; B.te = S.te;
     B.act = S.act; B.lmx = S.lmx; B.mark = S.mark;
+    if (c->p.av_switch == SPH_AV_MM97) {
+        B.al = S.al; B.alh = S.alh; B.alp = S.alp; B.adot = S.adot;
+    }
     B.lstart = c->lstart;
     B.tree = c->d_tree;
     B.leaf_act = c->leaf_act;
@@ -820,6 +869,18 @@ sph_status block_finish(sph_ctx *c, int64_t n, bool init)
     hipLaunchKernelGGL(k_block_levels, dim3(g), dim3(256), 0, c->stream, B, init);
     hipLaunchKernelGGL(k_block_advance, dim3(1), dim3(1), 0, c->stream, B, init);
     return hip_check(c, hipGetLastError(), "block_finish");
+}
+
+sph_status block_av(sph_ctx *c, int64_t n)
+{
+    const int sw = c->p.av_switch;
+    if (n == 0 || (sw != SPH_AV_MM97 && sw != SPH_AV_CD10)) return SPH_OK;
+    BlockArgs B = block_args(c, n);
+    Sorted &S = c->s;
+    BlockAv V{sw, c->p.alpha_min, c->p.alpha_max, av_ell(c->p), S.al, S.adot, S.dprev,
+              S.alp, S.divv, S.curlv, S.vsig, S.h, S.frec};
+    hipLaunchKernelGGL(k_block_av, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, B, V);
+    return hip_check(c, hipGetLastError(), "block_av");
 }
 
 sph_status fill(sph_ctx *c, int64_t n, double *v, double value)

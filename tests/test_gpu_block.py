@@ -9,7 +9,7 @@
 * When every particle shares one level, sub-steps are global steps: the
   state after k sub-steps is bit for bit that of k sph_step calls.
 * A timeline too shallow for the hot particles reports SPH_ELEVEL; sph_step
-  on a block context and block steps with a viscosity switch are refused.
+  on a block context is refused.
 """
 import numpy as np
 import pytest
@@ -120,7 +120,3 @@ def test_block_error_paths(sph):
         with pytest.raises(sph.SphError) as e:
             ctx.step(0.0)
         assert e.value.code == sph.SPH_ESTATE
-    with pytest.raises(sph.SphError) as e:
-        sph.Context(sph.Params.from_setup({**w.setup, "block_lmax": 10,
-                                           "av_switch": sph.SPH_AV_MM97}))
-    assert e.value.code == sph.SPH_EINVAL
