@@ -302,7 +302,8 @@ def rows_legs(args, w, shape):
     """The method's other rows on the same set in FP64: the quintic kernel
     (density + forces, with its roofline), resident steps with the Cullen &
     Dehnen viscosity switch next to plain global steps, hierarchical block
-    time-steps over one level-0 step, and the MFV geometry."""
+    time-steps over one level-0 step (plain and with the switch), and the
+    MFV geometry."""
     import torch
     from paper_1709_04488_amd import sph, tune
     out = {}
@@ -352,8 +353,16 @@ def rows_legs(args, w, shape):
         "global_steps_for_same_time": g_steps,
         "global_ms_for_same_time": g_steps * glob_ms,
         "speedup_vs_global_steps": (g_steps * glob_ms) / (blk_ms * calls)}
-    print(f"# block: {subs} sub-steps, {blk_ms * calls:.1f} ms per level-0 step",
-          file=sys.stderr, flush=True)
+    # the same with the Cullen & Dehnen switch on each particle's own steps
+    bsp = sph.Params.from_setup({**w.setup, "block_lmax": 20, "block_lim": 2,
+                                 "av_switch": sph.SPH_AV_CD10}, **kw)
+    bsw_ms, bsw_calls, bsw_info, bsw0 = _resident(w, bsp, 0, 0, substeps=True, nfull=1)
+    out["block_timesteps_fp64"].update({
+        "cd10_substeps": bsw_info["block_substeps"] - bsw0["block_substeps"],
+        "cd10_particle_updates": bsw_info["block_updates"] - bsw0["block_updates"],
+        "cd10_ms_per_level0_step": bsw_ms * bsw_calls})
+    print(f"# block: {subs} sub-steps, {blk_ms * calls:.1f} ms per level-0 step "
+          f"(CD10 switch: {bsw_ms * bsw_calls:.1f} ms)", file=sys.stderr, flush=True)
     x, y, z, h0 = (torch.as_tensor(w.arrays[k], dtype=torch.float64, device="cuda")
                    for k in ("x", "y", "z", "h"))
     fields = [torch.as_tensor(w.arrays[k], dtype=torch.float64, device="cuda")
