@@ -13,6 +13,8 @@
   sub-step sends particles one level deeper: the oracle's own particle
   updates change under 1e-13 position noise there, and not with the
   jitter.)
+* FP32-pair mode, without a switch and with each: levels, sub-steps and
+  particle updates identical to the FP64 oracle's, state within 1e-4.
 * Every particle on one level: sub-steps with a switch are global steps
   with it, bit for bit (x, v, u, h, alpha).
 * A per-particle alpha without a switch moves with the particles through
@@ -53,8 +55,9 @@ def _alpha(n, seed):
     return np.random.default_rng(seed).uniform(0.1, 1.0, n)
 
 
-def _run_block(sph, arrays, setup, nfull, alpha=None, lmax=20, lim=2):
-    params = sph.Params.from_setup({**setup, "block_lmax": lmax, "block_lim": lim})
+def _run_block(sph, arrays, setup, nfull, alpha=None, lmax=20, lim=2, precision=0):
+    params = sph.Params.from_setup({**setup, "block_lmax": lmax, "block_lim": lim},
+                                   precision=precision)
     extra = {} if alpha is None else {"alpha": alpha}
     with sph.Context(params) as ctx:
         ctx.upload_state(sph.Particles.from_host({**arrays, **extra}))
@@ -101,6 +104,28 @@ def test_block_switch_matches_oracle(sph, orc, switch):
     assert np.array_equal(out["level"], lev)
     assert info["block_time"] == pytest.approx(t, rel=1e-12)
     _compare(out, st, ("vx", "vy", "vz", "u", "h", "alpha"), 1e-8, f"block {switch}")
+
+
+@pytest.mark.parametrize("switch", ["none", "mm97", "cd10"])
+def test_fp32_block_steps_match_oracle(sph, orc, switch):
+    w = _hot_lattice()
+    a = w.arrays
+    setup = dict(w.setup)
+    al0 = None
+    if switch != "none":
+        setup.update(av_switch=_sw(sph, switch), alpha_min=0.1, alpha_max=1.0)
+        al0 = _alpha(w.n, 63)
+    nfull = 2
+    st, energy, nsub, lev, t = orc.kdk_block(orc.Params(**setup), a["x"], a["y"], a["z"], a["vx"],
+                                             a["vy"], a["vz"], a["m"], a["u"], a["h"], nfull,
+                                             alpha=al0)
+    print(f"case: fp32 block {switch} N={w.n} oracle sub-steps {nsub}", flush=True)
+    out, info = _run_block(sph, a, setup, nfull, alpha=al0, precision=1)
+    assert info["block_substeps"] == nsub
+    assert info["block_updates"] == st["updates"]
+    assert np.array_equal(out["level"], lev)
+    keys = ("vx", "vy", "vz", "u", "h") + (("alpha",) if al0 is not None else ())
+    _compare(out, st, keys, 1e-4, f"fp32 block {switch}")
 
 
 def _hot_slab(nx=32, ny=8, u_hot=17.6, jitter=0.05, seed=71):
