@@ -13,6 +13,8 @@
   sub-step sends particles one level deeper: the oracle's own particle
   updates change under 1e-13 position noise there, and not with the
   jitter.)
+* Artificial conductivity (alpha_AC = 1, both signal speeds) with the CD10
+  switch under block time-steps: levels exact, state within 1e-8.
 * FP32-pair mode, without a switch and with each: levels, sub-steps and
   particle updates identical to the FP64 oracle's, state within 1e-4.
 * Every particle on one level: sub-steps with a switch are global steps
@@ -104,6 +106,27 @@ def test_block_switch_matches_oracle(sph, orc, switch):
     assert np.array_equal(out["level"], lev)
     assert info["block_time"] == pytest.approx(t, rel=1e-12)
     _compare(out, st, ("vx", "vy", "vz", "u", "h", "alpha"), 1e-8, f"block {switch}")
+
+
+@pytest.mark.parametrize("signal", [0, 1])
+def test_block_conductivity_and_switch_match_oracle(sph, orc, signal):
+    w = _hot_lattice(seed=5)
+    a = w.arrays
+    u = a["u"] * np.random.default_rng(64).uniform(0.5, 2.0, w.n)   # spread for the conductivity
+    a = {**a, "u": u}
+    setup = {**w.setup, "alpha_ac": 1.0, "ac_signal": signal, "av_switch": _sw(sph, "cd10"),
+             "alpha_min": 0.1, "alpha_max": 1.0}
+    al0 = _alpha(w.n, 65)
+    st, energy, nsub, lev, t = orc.kdk_block(orc.Params(**setup), a["x"], a["y"], a["z"], a["vx"],
+                                             a["vy"], a["vz"], a["m"], a["u"], a["h"], 2,
+                                             alpha=al0)
+    assert lev.max() >= 2
+    print(f"case: block conductivity signal={signal} + cd10 N={w.n} sub-steps {nsub}", flush=True)
+    out, info = _run_block(sph, a, setup, 2, alpha=al0)
+    assert info["block_substeps"] == nsub
+    assert info["block_updates"] == st["updates"]
+    assert np.array_equal(out["level"], lev)
+    _compare(out, st, ("vx", "vy", "vz", "u", "h", "alpha"), 1e-8, f"block ac{signal}")
 
 
 @pytest.mark.parametrize("switch", ["none", "mm97", "cd10"])
