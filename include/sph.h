@@ -398,8 +398,8 @@ sph_status sph_step(sph_ctx *ctx, double dt, double *dt_used);
  * taken from each force evaluation of the particle; under SPH_AV_CD10 an
  * active particle's alpha is updated after its forces with dt = its own
  * step length and div v of its previous evaluation.  A per-particle alpha
- * given at upload without a switch stays with its particle.  Not combined
- * with batches or graph capture (SPH_ESTATE).
+ * given at upload without a switch stays with its particle.  Many states
+ * advance together with sph_batch_substep; no graph capture (SPH_ESTATE).
  */
 sph_status sph_substep(sph_ctx *ctx);
 
@@ -488,6 +488,11 @@ sph_status sph_batch_forces(sph_ctx *const *ctx, sph_particles *const *ps, int32
 sph_status sph_batch_evaluate(sph_ctx *const *ctx, sph_particles *const *ps, int32_t count);
 /* One sph_step of each resident state, pair loops batched as above. */
 sph_status sph_batch_step(sph_ctx *const *ctx, int32_t count, double dt);
+/* One sph_substep of each block time-step state (each on its own clock),
+ * pair loops batched as above; each set's state afterwards is bit-for-bit
+ * that of sph_substep on it alone.  SPH_ESTATE, before anything is
+ * enqueued, if a context holds no resident state or has block_lmax = 0. */
+sph_status sph_batch_substep(sph_ctx *const *ctx, int32_t count);
 
 /* Wait for the context's stream; return and clear the sticky device status. */
 sph_status sph_sync(sph_ctx *ctx);

@@ -1032,9 +1032,13 @@ sph_status sph_step(sph_ctx *c, double dt, double *dt_used)
     return step_post(c, dt, dt_used);
 }
 
-sph_status sph_substep(sph_ctx *c)
+// Block sub-step in three phases around the two pair launches (so that a
+// batch can launch the pair loops of many sets together).
+// First: the next tick at which steps end, drift, re-sort, tree, predictors,
+// the active set, the density arguments.  The block flags stay set until
+// substep_mid (or clear_block_flags on an error in between).
+static sph_status substep_pre(sph_ctx *c)
 {
-    if (!c) return SPH_EINVAL;
     if (!c->resident) return fail(c, SPH_ESTATE, "sph_substep needs sph_upload_state first");
     if (c->p.block_lmax <= 0) return fail(c, SPH_ESTATE, "the context has no block time-steps");
     const int64_t n = c->n;
@@ -1088,21 +1092,76 @@ sph_status sph_substep(sph_ctx *c)
     // the forces see every particle's predicted alpha (MM97) or its current
     // one (CD10, or a constant per-particle alpha given at upload)
     resident_force_inputs(c);
-    sph_status st = density_prepare(c, n);
-    if (st == SPH_OK) st = density_launch(&c, 1, n);
-    if (st == SPH_OK) st = refresh_hmax(c, n);
-    if (st == SPH_OK) st = force_prep(c, n, S.up, S.vpx, S.vpy, S.vpz);
-    if (st == SPH_OK) st = forces_prepare(c, n);
+    return density_prepare(c, n);
+}
+
+static void clear_block_flags(sph_ctx *c)
+{
     c->f_act = nullptr;
     c->f_block = false;
-    TRY(st);
-    TRY(forces_launch(&c, 1, n));
-    // the switches of the active particles from these forces, then closing
-    // kicks, levels, limiter, opening kicks, clock
+}
+
+// Second: after the density loop, the force arguments of the active set.
+static sph_status substep_mid(sph_ctx *c)
+{
+    const int64_t n = c->n;
+    Sorted &S = c->s;
+    sph_status st = refresh_hmax(c, n);
+    if (st == SPH_OK) st = force_prep(c, n, S.up, S.vpx, S.vpy, S.vpz);
+    if (st == SPH_OK) st = forces_prepare(c, n);
+    clear_block_flags(c);
+    return st;
+}
+
+// Third: after the force loop, the switches of the active particles, then
+// closing kicks, levels, limiter, opening kicks, clock.
+static sph_status substep_post(sph_ctx *c)
+{
+    const int64_t n = c->n;
     TRY(block_av(c, n));
     TRY(block_finish(c, n, false));
     TRY(reduce_diag(c, n));
     c->steps++;
+    return SPH_OK;
+}
+
+sph_status sph_substep(sph_ctx *c)
+{
+    if (!c) return SPH_EINVAL;
+    sph_status st = substep_pre(c);
+    if (st == SPH_OK) st = density_launch(&c, 1, c->n);
+    if (st != SPH_OK) {
+        clear_block_flags(c);
+        return st;
+    }
+    TRY(substep_mid(c));
+    TRY(forces_launch(&c, 1, c->n));
+    return substep_post(c);
+}
+
+sph_status sph_batch_substep(sph_ctx *const *cs, int32_t count)
+{
+    TRY(check_batch(cs, count));
+    // every context is checked before any is advanced
+    for (int r = 0; r < count; r++) {
+        if (!cs[r]->resident) return fail(cs[r], SPH_ESTATE, "sph_substep needs sph_upload_state first");
+        if (cs[r]->p.block_lmax <= 0)
+            return fail(cs[r], SPH_ESTATE, "the context has no block time-steps");
+    }
+    sph_status st = SPH_OK;
+    for (int r = 0; r < count && st == SPH_OK; r++) st = substep_pre(cs[r]);
+    if (st == SPH_OK)
+        st = launch_groups(cs, count,
+                           [](sph_ctx *const *g, int k) { return density_launch(g, k, 0); });
+    if (st != SPH_OK) {
+        for (int r = 0; r < count; r++) clear_block_flags(cs[r]);
+        return st;
+    }
+    for (int r = 0; r < count && st == SPH_OK; r++) st = substep_mid(cs[r]);
+    for (int r = 0; r < count; r++) clear_block_flags(cs[r]);
+    TRY(st);
+    TRY(launch_groups(cs, count, [](sph_ctx *const *g, int k) { return forces_launch(g, k, 0); }));
+    for (int r = 0; r < count; r++) TRY(substep_post(cs[r]));
     return SPH_OK;
 }
 

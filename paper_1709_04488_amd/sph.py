@@ -34,6 +34,7 @@ EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_set_stream",
             "sph_download_state", "sph_state_info", "sph_neighbours", "sph_sync",
             "sph_last_error", "sph_device_bytes", "sph_enable_kernel_timing", "sph_kernel_times",
             "sph_batch_density", "sph_batch_forces", "sph_batch_evaluate", "sph_batch_step",
+            "sph_batch_substep",
             "sph_capture_steps",
             "sph_replay_steps", "sph_plan_bytes", "sph_evaluate_noalloc", "sph_noalloc_max_n",
             "sph_mfv_gradients", "sph_substep", "sph_server_create", "sph_server_submit",
@@ -157,6 +158,7 @@ def load() -> ctypes.CDLL:
         "sph_batch_forces": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(PS), i32]),
         "sph_batch_evaluate": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(PS), i32]),
         "sph_batch_step": (ctypes.c_int, [ctypes.POINTER(vp), i32, d]),
+        "sph_batch_substep": (ctypes.c_int, [ctypes.POINTER(vp), i32]),
         "sph_capture_steps": (ctypes.c_int, [vp, d]),
         "sph_replay_steps": (ctypes.c_int, [vp]),
         "sph_plan_bytes": (ctypes.c_size_t, [P, i64]),
@@ -550,6 +552,14 @@ def batch_step(ctxs, dt: float = 0.0):
     n = len(ctxs)
     hs = (ctypes.c_void_p * n)(*[c.h.value for c in ctxs])
     _batch_check(ctxs, lib.sph_batch_step(hs, n, float(dt)), "sph_batch_step")
+
+
+def batch_substep(ctxs):
+    """One block sub-step of each state, pair loops batched (sph_batch_substep)."""
+    lib = load()
+    n = len(ctxs)
+    hs = (ctypes.c_void_p * n)(*[c.h.value for c in ctxs])
+    _batch_check(ctxs, lib.sph_batch_substep(hs, n), "sph_batch_substep")
 
 
 def plan_bytes(params: Params, n: int) -> int:

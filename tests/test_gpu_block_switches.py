@@ -214,3 +214,62 @@ def test_block_per_particle_alpha_moves_with_particles(sph):
     assert i0["block_substeps"] == i1["block_substeps"]
     for k in ("x", "y", "z", "vx", "vy", "vz", "u", "h", "level"):
         assert np.array_equal(plain[k], same[k]), k
+
+
+def test_batch_substep_equals_single_substeps(sph):
+    """Block states of different sizes, switches and precisions, each on its
+    own clock, advanced together by sph_batch_substep: after every call each
+    set is bit for bit where sph_substep alone takes it."""
+    hot = _hot_lattice()
+    blob = W.blob_in_lattice(9, seed=66)
+    mix = [(hot.arrays, hot.setup, 0, None),
+           (blob.arrays, {**blob.setup, "av_switch": sph.SPH_AV_CD10}, 0, _alpha(blob.n, 67)),
+           (_hot_lattice(side=7, seed=8).arrays, {**hot.setup, "av_switch": sph.SPH_AV_MM97}, 0,
+            _alpha(343, 68)),
+           (hot.arrays, hot.setup, 1, None)]
+    nsub = 12
+    fields = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "rho", "ax", "level")
+
+    def params(setup, prec):
+        return sph.Params.from_setup({**setup, "block_lmax": 20, "block_lim": 2}, precision=prec)
+
+    def parts(arrays, al):
+        return sph.Particles.from_host({**arrays, **({} if al is None else {"alpha": al})})
+
+    print(f"case: batched block sub-steps of {len(mix)} sets", flush=True)
+    single = []
+    for arrays, setup, prec, al in mix:
+        with sph.Context(params(setup, prec)) as ctx:
+            ctx.upload_state(parts(arrays, al))
+            for _ in range(nsub):
+                ctx.substep()
+            q = parts(arrays, al).with_level()
+            ctx.download_state(q)
+            ctx.sync()
+            single.append((q.host(), ctx.state_info()))
+    stream = torch.cuda.current_stream()
+    ctxs = [sph.Context(params(setup, prec), stream=stream) for _, setup, prec, _ in mix]
+    for c, (arrays, _, _, al) in zip(ctxs, mix):
+        c.upload_state(parts(arrays, al))
+    for _ in range(nsub):
+        sph.batch_substep(ctxs)
+    for k, (c, (arrays, _, _, al), (ref, rinfo)) in enumerate(zip(ctxs, mix, single)):
+        q = parts(arrays, al).with_level()
+        c.download_state(q)
+        c.sync()
+        out, info = q.host(), c.state_info()
+        assert info["block_substeps"] == rinfo["block_substeps"] == nsub, k
+        assert info["block_updates"] == rinfo["block_updates"], k
+        assert info["block_time"] == rinfo["block_time"], k
+        for f in fields + (("alpha",) if al is not None else ()):
+            assert np.array_equal(out[f], ref[f]), (k, f)
+    # a context without block time-steps is refused before anything runs
+    flat = sph.Context(sph.Params.from_setup(hot.setup), stream=stream)
+    flat.upload_state(sph.Particles.from_host(hot.arrays))
+    before = ctxs[0].state_info()["block_substeps"]
+    with pytest.raises(sph.SphError) as e:
+        sph.batch_substep([ctxs[0], flat])
+    assert e.value.code == sph.SPH_ESTATE
+    assert ctxs[0].state_info()["block_substeps"] == before
+    for c in ctxs + [flat]:
+        c.close()
