@@ -563,7 +563,12 @@ enum {
 typedef struct {
     /* set by the caller */
     int32_t kind;          /* SPH_REQUEST_EVALUATE or SPH_REQUEST_INTEGRATE */
-    int32_t nsteps;        /* integrate: number of steps (>= 0) */
+    int32_t nsteps;        /* integrate: number of steps (>= 0); with
+                              params.block_lmax > 0, level-0 steps of block
+                              time-steps (sph_substep until that many full
+                              synchronisations, one sub-step in flight at a
+                              time: the slot's thread reads the device clock
+                              between them without blocking other slots) */
     sph_params params;     /* method and launch parameters of this request */
     int64_t n;             /* particles (>= 0) */
     const double *in[SPH_NIN]; /* HOST inputs, n values each, all non-NULL: x, y, z,
@@ -579,7 +584,9 @@ typedef struct {
     int32_t status;        /* sph_status of the request */
     int32_t slot;          /* slot that ran it */
     int64_t interactions;  /* n_dens_pairs + n_force_pairs of the last
-                              evaluation, times max(nsteps, 1) for integrate */
+                              evaluation, times max(nsteps, 1) for integrate;
+                              with block time-steps the pairs of the active
+                              particles summed over the sub-steps */
     sph_state_stats info;  /* sph_state_info after the request (zero on error) */
     double host_seconds[4];/* staging the inputs and enqueueing the work (the
                               slot thread's time), then in flight on the device

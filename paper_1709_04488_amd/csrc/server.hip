@@ -49,6 +49,8 @@ struct Slot {
     // owned by the worker thread
     sph_request *run = nullptr;  // enqueued on the stream, not yet finished
     bool eval = false;           // the running request's kind
+    bool block = false;          // block time-steps: a sub-step is in flight
+    int64_t block_pairs = 0;     // pairs of the sub-steps so far
     int lo = 0, hi = -1;         // rows of the outputs copied back
     std::chrono::steady_clock::time_point t_enqueued;
     hipStream_t stream = nullptr;
@@ -192,6 +194,8 @@ double seconds_since(std::chrono::steady_clock::time_point &t)
 // Stage and enqueue request r on slot s.  Returns true when the request is
 // in flight; false when it is already complete (n = 0 or an error, with
 // r->status set).
+bool enqueue_outputs(Slot &s, sph_request *r, const sph_particles &d);
+
 bool start(Slot &s, sph_request *r)
 {
     const int64_t n = r->n;
@@ -209,16 +213,27 @@ bool start(Slot &s, sph_request *r)
     sph_particles d = device_view(s.dev, n);
 
     s.eval = r->kind == SPH_REQUEST_EVALUATE;
+    s.block = false;
+    s.block_pairs = 0;
     sph_status st;
     if (s.eval) {
         st = sph_evaluate(s.ctx, &d);
+    } else if (r->params.block_lmax > 0) {
+        // block time-steps: one sub-step at a time; the worker reads the
+        // device clock whenever the stream drains (advance) and enqueues the
+        // next sub-step, or the download once nsteps level-0 steps are done
+        st = sph_upload_state(s.ctx, &d);
+        if (st == SPH_OK && r->nsteps > 0) {
+            st = sph_substep(s.ctx);
+            s.block = st == SPH_OK;
+        }
+        if (st == SPH_OK && !s.block) st = sph_download_state(s.ctx, &d);
     } else {
         st = sph_upload_state(s.ctx, &d);
         // two steps per replay of a captured graph, then one eager step for an
-        // odd count; block time-steps are not captured and step eagerly
-        const bool graph = r->params.block_lmax == 0 && r->nsteps >= 2;
+        // odd count
         int32_t left = r->nsteps;
-        if (st == SPH_OK && graph) {
+        if (st == SPH_OK && left >= 2) {
             st = sph_capture_steps(s.ctx, 0.0);
             for (; st == SPH_OK && left >= 2; left -= 2) st = sph_replay_steps(s.ctx);
         }
@@ -230,6 +245,19 @@ bool start(Slot &s, sph_request *r)
         (void)sph_sync(s.ctx);   // clear the sticky status for the slot's next request
         return false;
     }
+    if (!s.block && !enqueue_outputs(s, r, d)) return false;
+    r->host_seconds[1] = seconds_since(t);
+    s.t_enqueued = t;
+    return true;
+}
+
+// The copies of the wanted outputs to the pinned staging (after the
+// evaluation or the download on the slot's stream).
+bool enqueue_outputs(Slot &s, sph_request *r, const sph_particles &d)
+{
+    const int64_t n = r->n;
+    const size_t row = (size_t)n * sizeof(double);
+    hipError_t e;
     // the wanted outputs: one copy of the rows from the first to the last wanted
     s.lo = SPH_NF64;
     s.hi = -1;
@@ -247,9 +275,31 @@ bool start(Slot &s, sph_request *r)
                            hipMemcpyDeviceToHost, s.stream);
         if (e != hipSuccess) { hip_fail(r, e, "count copy"); return false; }
     }
-    r->host_seconds[1] = seconds_since(t);
-    s.t_enqueued = t;
     return true;
+}
+
+// A block request whose sub-step has drained: count its pairs, then enqueue
+// the next sub-step, or the download and output copies once the clock has
+// completed nsteps level-0 steps.  false: the request failed (error set).
+bool advance(Slot &s, sph_request *r)
+{
+    sph_state_stats info;
+    sph_status st = sph_state_info(s.ctx, &info);   // the stream is idle: no wait
+    if (st == SPH_OK) {
+        s.block_pairs += info.n_dens_pairs + info.n_force_pairs;
+        if (info.block_full_steps < r->nsteps) {
+            st = sph_substep(s.ctx);
+            if (st == SPH_OK) return true;
+        } else {
+            s.block = false;
+            sph_particles d = device_view(s.dev, r->n);
+            st = sph_download_state(s.ctx, &d);
+            if (st == SPH_OK) return enqueue_outputs(s, r, d);
+        }
+    }
+    set_error(r, st, sph_last_error(s.ctx));
+    (void)sph_sync(s.ctx);
+    return false;
 }
 
 // The request in flight on slot s, whose stream has drained: its status,
@@ -279,7 +329,11 @@ void finish(Slot &s, sph_request *r)
         if (r->iout[k]) std::memcpy(r->iout[k], ipin + (size_t)k * n, n * sizeof(int32_t));
     r->host_seconds[3] = seconds_since(t);
     const int64_t pairs = r->info.n_dens_pairs + r->info.n_force_pairs;
-    r->interactions = s.eval ? pairs : pairs * std::max<int64_t>(r->nsteps, 1);
+    // block time-steps: the pairs of all sub-steps (active particles only)
+    r->interactions = s.eval ? pairs
+                      : (r->params.block_lmax > 0 && r->nsteps > 0)
+                          ? s.block_pairs
+                          : pairs * std::max<int64_t>(r->nsteps, 1);
     set_error(r, SPH_OK, "");
 }
 
@@ -336,8 +390,17 @@ void worker(sph_server *S, Worker *W)
         for (Slot *s : W->slots) {
             if (!s->run) continue;
             lk.unlock();
-            const bool ready = hipStreamQuery(s->stream) != hipErrorNotReady;
-            if (ready) finish(*s, s->run);
+            const bool drained = hipStreamQuery(s->stream) != hipErrorNotReady;
+            bool ready = false;
+            if (drained && s->block) {
+                // a block sub-step has finished: the next one (or the
+                // download) is in flight again, or the request failed (its
+                // error set; nothing to finish)
+                ready = !advance(*s, s->run);
+            } else if (drained) {
+                finish(*s, s->run);
+                ready = true;
+            }
             lk.lock();
             if (ready) {
                 sph_request *r = s->run;

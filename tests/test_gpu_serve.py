@@ -156,3 +156,55 @@ def test_native_executor_reuse_release_and_errors(sph):
         assert server.wait(0.0) == []
     finally:
         server.close()
+
+
+def test_native_block_integration_equals_direct_substeps(sph):
+    """Integration requests with block time-steps (nsteps level-0 steps,
+    sub-step by sub-step on the slot's own stream) give the state of a
+    direct upload + sph_substep loop bit for bit, on two slots at once; the
+    interactions are the sub-steps' pairs."""
+    import ctypes
+    hot = W.jittered_lattice(8, seed=3)
+    u = hot.arrays["u"].copy()
+    u[:2] *= 200.0
+    cases = [({**hot.arrays, "u": u}, {**hot.setup, "av_switch": sph.SPH_AV_CD10}, 0, 2),
+             (W.blob_in_lattice(9, seed=70).arrays, W.blob_in_lattice(9, seed=70).setup, 1, 1)]
+    fields = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "rho", "ax", "dudt")
+    server = sph.Server(2)
+    try:
+        reqs = []
+        for slot, (arrays, setup, prec, nfull) in enumerate(cases):
+            params = sph.Params.from_setup({**setup, "block_lmax": 20, "block_lim": 2},
+                                           precision=prec)
+            outs = {k: np.empty(arrays["x"].size) for k in fields}
+            r, keep = sph.make_request(sph.SPH_REQUEST_INTEGRATE, arrays, params, nfull, outs)
+            print(f"case: native block integration slot {slot} n={arrays['x'].size}", flush=True)
+            server.submit(slot, r)
+            reqs.append((r, keep, outs, params, arrays, nfull))
+        pending = {ctypes.addressof(r) for r, *_ in reqs}
+        for _ in range(200):
+            for a in server.wait(5.0):
+                pending.discard(a)
+            if not pending:
+                break
+        assert not pending
+        for r, keep, outs, params, arrays, nfull in reqs:
+            assert r.status == sph.SPH_OK, r.error
+            with sph.Context(params) as ctx:
+                ctx.upload_state(sph.Particles.from_host(arrays))
+                pairs = 0
+                while ctx.state_info()["block_full_steps"] < nfull:
+                    ctx.substep()
+                    i = ctx.state_info()
+                    pairs += i["n_dens_pairs"] + i["n_force_pairs"]
+                q = sph.Particles.from_host(arrays)
+                ctx.download_state(q)
+                ctx.sync()
+                ref, info = q.host(), ctx.state_info()
+            assert r.info.block_full_steps == nfull == info["block_full_steps"]
+            assert r.info.block_substeps == info["block_substeps"] > nfull
+            assert r.interactions == pairs
+            for f in fields:
+                assert np.array_equal(outs[f], ref[f]), f
+    finally:
+        server.close()
