@@ -449,6 +449,15 @@ class GpuExecutor:
         with torch.cuda.stream(slot.stream):
             if req.kind == "evaluate":
                 ctx.evaluate(p)
+            elif ctx.params.block_lmax > 0:
+                # block time-steps: sub-steps until nsteps level-0 steps are
+                # done (the clock is read between them), their pairs summed
+                ctx.upload_state(p)
+                h["block_pairs"] = 0
+                while ctx.state_info()["block_full_steps"] < req.nsteps:
+                    ctx.substep()
+                    i = ctx.state_info()
+                    h["block_pairs"] += i["n_dens_pairs"] + i["n_force_pairs"]
             else:
                 ctx.upload_state(p)
                 ctx.capture_steps(0.0)
@@ -513,7 +522,8 @@ class GpuExecutor:
                 if self.keep_outputs:
                     out["outputs"] = {k: v.copy() for k, v in res.items()}
         else:
-            out["interactions"] = (info["n_dens_pairs"] + info["n_force_pairs"]) * max(req.nsteps, 1)
+            out["interactions"] = (h["block_pairs"] if "block_pairs" in h and req.nsteps > 0 else
+                                   (info["n_dens_pairs"] + info["n_force_pairs"]) * max(req.nsteps, 1))
             q = self._zeros(req.n, h["slot"].stream)
             ctx.download_state(q)
             ctx.sync()

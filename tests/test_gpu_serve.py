@@ -208,3 +208,36 @@ def test_native_block_integration_equals_direct_substeps(sph):
                 assert np.array_equal(outs[f], ref[f]), f
     finally:
         server.close()
+
+
+@pytest.mark.parametrize("mode", ["native", "streams"])
+def test_served_block_integration_equals_eager(sph, mode):
+    """Integration requests with block time-steps (one with the MM97 switch)
+    through the scheduler: nsteps level-0 steps each, the state of a direct
+    sub-step loop bit for bit, on either executor."""
+    reqs = []
+    for rid, side in enumerate((8, 9)):
+        w = W.blob_in_lattice(side, seed=210 + rid)
+        setup = {**w.setup, "block_lmax": 20, "block_lim": 2,
+                 **({"av_switch": sph.SPH_AV_MM97} if rid else {})}
+        reqs.append(S.Request(rid, 0.0, "integrate", w.arrays, setup, precision=rid % 2, nsteps=1))
+    print("case: served block integration mode=%s" % mode, flush=True)
+    recs, summary = S.serve(reqs, 1 << 30, 2, mode, keep_outputs=True)
+    assert summary["completed"] == 2
+    for req, rec in zip(reqs, recs):
+        assert not rec.error, rec.error
+        params = sph.Params.from_setup(req.setup, precision=req.precision, leaf_size=16)
+        with sph.Context(params) as ctx:
+            ctx.upload_state(sph.Particles.from_host(req.arrays))
+            pairs = 0
+            while ctx.state_info()["block_full_steps"] < req.nsteps:
+                ctx.substep()
+                i = ctx.state_info()
+                pairs += i["n_dens_pairs"] + i["n_force_pairs"]
+            q = sph.Particles.from_host(req.arrays)
+            ctx.download_state(q)
+            ctx.sync()
+            ref = q.host()
+        assert rec.info["block_full_steps"] == req.nsteps and rec.interactions == pairs
+        for f in ("x", "y", "z", "vx", "vy", "vz", "u", "h"):
+            assert np.array_equal(rec.outputs[f], ref[f]), (req.rid, f)
