@@ -284,7 +284,10 @@ bool enqueue_outputs(Slot &s, sph_request *r, const sph_particles &d)
 bool advance(Slot &s, sph_request *r)
 {
     sph_state_stats info;
-    sph_status st = sph_state_info(s.ctx, &info);   // the stream is idle: no wait
+    // the stream is idle, so neither call waits; a status the device raised
+    // in the sub-step (e.g. a level beyond block_lmax) ends the request now
+    sph_status st = sph_sync(s.ctx);
+    if (st == SPH_OK) st = sph_state_info(s.ctx, &info);
     if (st == SPH_OK) {
         s.block_pairs += info.n_dens_pairs + info.n_force_pairs;
         if (info.block_full_steps < r->nsteps) {

@@ -241,3 +241,30 @@ def test_served_block_integration_equals_eager(sph, mode):
         assert rec.info["block_full_steps"] == req.nsteps and rec.interactions == pairs
         for f in ("x", "y", "z", "vx", "vy", "vz", "u", "h"):
             assert np.array_equal(rec.outputs[f], ref[f]), (req.rid, f)
+
+
+def test_native_block_request_error_then_next(sph):
+    """A block integration request whose timeline is too shallow for its hot
+    particles (block_lmax 1) ends with SPH_ELEVEL at its first sub-step; the
+    slot then serves the next request normally."""
+    import ctypes
+    w = W.jittered_lattice(8, seed=3)
+    u = w.arrays["u"].copy()
+    u[:2] *= 1000.0
+    arrays = {**w.arrays, "u": u}
+    server = sph.Server(1)
+    try:
+        for lmax, want in ((1, sph.SPH_ELEVEL), (20, sph.SPH_OK)):
+            params = sph.Params.from_setup({**w.setup, "block_lmax": lmax})
+            outs = {"x": np.empty(w.n)}
+            r, keep = sph.make_request(sph.SPH_REQUEST_INTEGRATE, arrays, params, 1, outs)
+            print(f"case: native block request block_lmax={lmax}", flush=True)
+            server.submit(0, r)
+            got = []
+            while not got:
+                got = server.wait(5.0)
+            assert got == [ctypes.addressof(r)]
+            assert r.status == want, (lmax, r.status, r.error)
+            assert bool(r.error) == (want != sph.SPH_OK)
+    finally:
+        server.close()
