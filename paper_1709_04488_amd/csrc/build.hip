@@ -18,7 +18,15 @@ namespace {
 
 constexpr int kBoxThreads = 256;
 constexpr int kRsThreads = 256;
-constexpr int kMortonBits = 16;                  // per axis: 48-bit keys, 6 passes
+// Bits per axis of the Morton key, by set size: at least 64 cells per mean
+// particle spacing along an axis (particles sharing a cell keep their input
+// order: the sort is stable), rounded up to what a number of 8-bit passes
+// holds: 10 bits (4 passes) up to 2^12 particles, 13 (5 passes) up to 2^21,
+// else 16 (6 passes).  The sort and the segment rule use the same count.
+constexpr int key_bits(int64_t n)
+{
+    return n <= (int64_t(1) << 12) ? 10 : (n <= (int64_t(1) << 21) ? 13 : 16);
+}
 static_assert(kRsTile == kRsThreads * kRsItems && kRsTileSmall == kRsThreads * kRsItemsSmall,
               "radix tiles are 256 threads wide");
 
@@ -697,8 +705,9 @@ sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y, 
                            c->d_part);
         hipLaunchKernelGGL(k_box_final, dim3(1), dim3(64), 0, c->stream, nb, c->d_part, c->d_box);
     }
+    const int bits = key_bits(n);
     hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, x, y, z,
-                       c->d_box, kMortonBits, c->keys[0], c->vals[0]);
+                       c->d_box, bits, c->keys[0], c->vals[0]);
     // small sets: tiles of 1024 keys (more, shorter blocks); up to
     // kRsRawTiles tiles the scatter blocks form the digit offsets from the raw
     // counts themselves (one launch fewer per pass).  A stable sort's result
@@ -706,7 +715,7 @@ sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y, 
     const bool small = rs_use_small(n);
     const int64_t ntiles = small ? rs_small_tiles(n) : ceil_div(n, kRsTile);
     if (256 * ntiles + 256 > c->hist_cap) return fail(c, SPH_ENOMEM, "radix count capacity");
-    const int passes = (3 * kMortonBits + 7) / 8;
+    const int passes = (3 * bits + 7) / 8;
     const int raw = ntiles <= kRsRawTiles ? 1 : 0;
     int cur = 0;
     for (int ps = 0; ps < passes; ps++) {
@@ -776,7 +785,7 @@ sph_status build_tree(sph_ctx *c, int64_t n)
     uint32_t *tmax = c->hist, *tcnt = c->hist + ntile;
     uint32_t *flag = c->scratch_u32;
     hipLaunchKernelGGL(k_seg_tiles, dim3((unsigned)ntile), dim3(kScanThreads), 0, c->stream, n,
-                       c->skeys, c->s.h, c->d_box, kMortonBits, flag, tmax);
+                       c->skeys, c->s.h, c->d_box, key_bits(n), flag, tmax);
     hipLaunchKernelGGL((k_scan_tiles<true>), dim3(1), dim3(1024), 0, c->stream, tmax, ntile);
     hipLaunchKernelGGL(k_seg_apply, dim3((unsigned)ntile), dim3(kScanThreads), 0, c->stream, n, G,
                        flag, tmax, tcnt);
