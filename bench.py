@@ -396,7 +396,8 @@ SERVE_SLOTS = 3
 
 def serving_legs(args):
     """The two served workloads (continuous batching under an HBM budget),
-    throughput with p50/p99 latency from arrival to results in host memory."""
+    throughput with p50/p99 latency from arrival to results in host memory,
+    and the integration workload again on block time-steps."""
     from paper_1709_04488_amd import serve
     t0 = time.perf_counter()
     ev = serve.run_served("evaluate", requests=512, slots=SERVE_SLOTS, mode="native", load=0.8)
@@ -405,6 +406,11 @@ def serving_legs(args):
     it = serve.run_served("integrate", requests=64, steps=args.serve_steps, slots=SERVE_SLOTS,
                           mode="native")
     print(f"# served integrate: {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    bl = serve.run_served("integrate", requests=64, steps=2, slots=SERVE_SLOTS, mode="native",
+                          block=True)
+    print(f"# served block integrate: {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+          flush=True)
     keep = ("requests", "completed", "errors", "makespan_s", "throughput_interactions_per_s",
             "requests_per_s", "latency_p50_ms", "latency_p99_ms", "latency_max_ms", "peak_bytes")
     return {
@@ -429,6 +435,18 @@ def serving_legs(args):
             "result": {k: it["result"][k] for k in keep},
             "per_step_latency_p50_ms": it["per_step_latency_p50_ms"],
             "per_step_latency_p99_ms": it["per_step_latency_p99_ms"]},
+        "integrate_block_64": {
+            "workload": "the same 64 sets on hierarchical block time-steps (levels down to "
+                        "2^-20 of the level-0 step, limiter 2 levels), 2 level-0 steps each, "
+                        "one sub-step in flight per slot, FP32-pair pair terms, FP64 state, "
+                        f"HBM budget 16 GiB, {SERVE_SLOTS} slots of the library's request "
+                        "executor; interactions = the active particles' pairs summed over "
+                        "the sub-steps",
+            "result": {k: bl["result"][k] for k in keep},
+            "substeps_total": bl["substeps_total"],
+            "particles_total": bl["particles_total"],
+            "particle_updates_total": bl["particle_updates_total"],
+            "particle_updates_per_s": bl["particle_updates_per_s"]},
     }
 
 

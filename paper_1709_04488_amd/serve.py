@@ -683,9 +683,11 @@ def evaluate_requests(count: int, rate: float, seed: int = 3, n_max_side: int = 
 
 
 def integrate_requests(count: int, nsteps: int, rate: float = math.inf, seed: int = 4,
-                       n_max_side: int = None, precision: int = 1):
+                       n_max_side: int = None, precision: int = 1, block: bool = False):
     """Served integration: blob-in-lattice boxes, N log-uniform in [1e4, 1e6]
-    snapped to n^3, FP32-pair pair arithmetic with FP64 state."""
+    snapped to n^3, FP32-pair pair arithmetic with FP64 state.  block: every
+    request on hierarchical block time-steps (levels down to 2^-20 of the
+    level-0 step, limiter 2 levels), nsteps then counting level-0 steps."""
     from . import workloads as W
     spec = W.config4_requests(count, seed=seed)
     rng = np.random.default_rng(seed + 7)
@@ -697,7 +699,8 @@ def integrate_requests(count: int, nsteps: int, rate: float = math.inf, seed: in
         w = W.blob_in_lattice(side, seed=wseed)
         if math.isfinite(rate):
             t += rng.exponential(1.0 / rate)
-        reqs.append(Request(rid, t if math.isfinite(rate) else 0.0, "integrate", w.arrays, w.setup,
+        setup = {**w.setup, "block_lmax": 20, "block_lim": 2} if block else w.setup
+        reqs.append(Request(rid, t if math.isfinite(rate) else 0.0, "integrate", w.arrays, setup,
                             precision=precision, nsteps=nsteps))
     return reqs
 
@@ -754,11 +757,12 @@ def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200
                budget_gib: float = None, slots: int = 3, mode: str = "native",
                load: float = 0.8, max_side: int = None, leaf="auto", tune_table: str = None,
                threads: bool = True, progress: bool = True, saturated_only: bool = False,
-               repeat: int = 1) -> dict:
+               repeat: int = 1, block: bool = False) -> dict:
     """Serve one of the two workloads and summarise it.  evaluate: a closed
     burst (every request at t = 0) gives the saturated capacity, then Poisson
     arrivals at `load` times that rate (saturated_only: the burst alone);
-    integrate: `requests` resident integrations of `steps` KDK steps each.
+    integrate: `requests` resident integrations of `steps` KDK steps each
+    (block: `steps` level-0 steps of block time-steps each).
     Every request class is tuned before the timed runs when leaf is "auto".
     repeat: serve the burst that many times, 0.2 s apart (the last pass is
     reported; a trace can tell the passes apart by the pause)."""
@@ -793,17 +797,25 @@ def run_served(workload: str = "evaluate", requests: int = 512, steps: int = 200
                               threads=threads)
             res.update({"arrival_rate_per_s": rate, "poisson": opened})
     else:
-        reqs = integrate_requests(requests, steps, n_max_side=max_side)
+        reqs = integrate_requests(requests, steps, n_max_side=max_side, block=block)
         pretune(reqs)
         recs, out = serve(reqs, budget, slots, mode, leaf_for=leaf_for, progress=progress,
                           threads=threads)
-        nsteps = sum(r.info.get("steps", 0) for r in recs if not r.error)
-        per_step = [r.latency / max(steps, 1) * 1e3 for r in recs if not r.error] or [0.0]
+        ok = [r for r in recs if not r.error]
+        nsteps = sum(r.info.get("steps", 0) for r in ok)
+        per_step = [r.latency / max(steps, 1) * 1e3 for r in ok] or [0.0]
         res = {"workload": "integrate", "mode": mode, "slots": slots, "leaf": leaf,
                "budget_bytes": budget, "steps_per_request": steps, "result": out,
                "steps_total": nsteps,
                "per_step_latency_p50_ms": float(np.percentile(per_step, 50)),
                "per_step_latency_p99_ms": float(np.percentile(per_step, 99))}
+        if block:
+            upd = sum(r.info.get("block_updates", 0) for r in ok)
+            res.update({"block_time_steps": True,
+                        "substeps_total": sum(r.info.get("block_substeps", 0) for r in ok),
+                        "particle_updates_total": upd,
+                        "particles_total": sum(r.n for r in ok),
+                        "particle_updates_per_s": upd / max(out["makespan_s"], 1e-12)})
     if leaf == "auto":
         res["autotuner"] = leaf_for.table
         res["autotuner_leaf_sizes"] = list(leaf_for.sizes)
@@ -824,6 +836,8 @@ def main(argv=None):
     ap.add_argument("--load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured saturated capacity")
     ap.add_argument("--max-side", type=int, default=None)
+    ap.add_argument("--block", action="store_true",
+                    help="integrate on block time-steps (--steps then counts level-0 steps)")
     ap.add_argument("--leaf", default="auto",
                     help="leaf size 8, 16 or 32, or auto: the autotuner picks per request class")
     ap.add_argument("--tune-table", default=None, help="JSON table of the autotuner to load and update")
@@ -837,7 +851,7 @@ def main(argv=None):
     res = run_served(args.workload, args.requests, args.steps, args.budget_gib, args.slots,
                      args.mode, args.load, args.max_side, args.leaf, args.tune_table,
                      threads=not args.no_threads, saturated_only=args.saturated_only,
-                     repeat=args.repeat)
+                     repeat=args.repeat, block=args.block)
     print(json.dumps(res), flush=True)
 
 
