@@ -96,3 +96,17 @@ def test_idle_slot_capacity_is_released_when_it_blocks_admission():
     assert recs[2].admitted == pytest.approx(5.0)
     assert ex.released, "idle capacity was never released"
     assert sched.peak_bytes <= budget
+
+
+def test_block_integration_requests_carry_the_timeline():
+    """integrate_requests(block=True): the same sets, each on block time-steps
+    (block_lmax 20, limiter 2), nsteps counting level-0 steps; the global
+    variant leaves the setups untouched."""
+    from paper_1709_04488_amd import serve as S
+    glob = S.integrate_requests(4, 3, n_max_side=6)
+    blk = S.integrate_requests(4, 3, n_max_side=6, block=True)
+    for g, b in zip(glob, blk):
+        assert "block_lmax" not in g.setup
+        assert b.setup["block_lmax"] == 20 and b.setup["block_lim"] == 2
+        assert b.nsteps == g.nsteps == 3 and b.kind == g.kind == "integrate"
+        assert all(np.array_equal(b.arrays[k], g.arrays[k]) for k in g.arrays)
