@@ -467,6 +467,31 @@ class GpuExecutor:
                     ctx.step(0.0)
         h["event"].record(slot.stream)
 
+    def _block_batch(self, hs):
+        """Block integration requests admitted together (batched mode, one
+        shared stream): every state advances by sph_batch_substep, each on its
+        own clock, its pair loops launched with the others'; a state leaves the
+        batch once its level-0 steps are done."""
+        torch = self.torch
+        with torch.cuda.stream(self.shared):
+            for h in hs:
+                h["ctx"].upload_state(h["p"])
+                h["block_pairs"] = 0
+            live = [h for h in hs if h["req"].nsteps > 0]
+            while live:
+                self.sph.batch_substep([h["ctx"] for h in live])
+                nxt = []
+                for h in live:
+                    i = h["ctx"].state_info()
+                    h["block_pairs"] += i["n_dens_pairs"] + i["n_force_pairs"]
+                    if i["block_full_steps"] < h["req"].nsteps:
+                        nxt.append(h)
+                live = nxt
+            ev = torch.cuda.Event()
+            ev.record(self.shared)
+        for h in hs:
+            h["event"] = ev
+
     def _serve_one(self, req: Request, slot: _Slot) -> dict:
         """A worker thread's whole request: upload, kernels, results on the host."""
         h = self._prepare(req, slot)
@@ -482,13 +507,18 @@ class GpuExecutor:
         torch = self.torch
         handles = [None] * len(items)
         batch = []
+        blocks = []
         for k, (req, sidx) in enumerate(items):
             h = self._prepare(req, self.slots[sidx])
             if req.kind == "evaluate" and self.mode == "batched":
                 batch.append(h)
+            elif self.mode == "batched" and h["ctx"].params.block_lmax > 0:
+                blocks.append(h)
             else:
                 self._launch(h)
             handles[k] = h
+        if blocks:
+            self._block_batch(blocks)
         if batch:
             self.sph.batch_evaluate([h["ctx"] for h in batch], [h["p"] for h in batch])
             ev = torch.cuda.Event()

@@ -210,11 +210,12 @@ def test_native_block_integration_equals_direct_substeps(sph):
         server.close()
 
 
-@pytest.mark.parametrize("mode", ["native", "streams"])
+@pytest.mark.parametrize("mode", ["native", "streams", "batched"])
 def test_served_block_integration_equals_eager(sph, mode):
     """Integration requests with block time-steps (one with the MM97 switch)
     through the scheduler: nsteps level-0 steps each, the state of a direct
-    sub-step loop bit for bit, on either executor."""
+    sub-step loop bit for bit, on every executor (batched: the states admitted
+    together advance by batched sub-steps)."""
     reqs = []
     for rid, side in enumerate((8, 9)):
         w = W.blob_in_lattice(side, seed=210 + rid)
