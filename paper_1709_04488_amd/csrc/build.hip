@@ -37,15 +37,6 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ void k_box_fixed(double *box, double l0, double l1, double l2, double h0, double h1,
-                            double h2)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        box[0] = l0; box[1] = l1; box[2] = l2;
-        box[3] = h0; box[4] = h1; box[5] = h2;
-    }
-}
-
 __global__ __launch_bounds__(kBoxThreads) void k_box_partial(int64_t n, const double *__restrict__ x,
                                                              const double *__restrict__ y,
                                                              const double *__restrict__ z,
@@ -101,20 +92,35 @@ __device__ inline uint64_t spread3(uint64_t v)
     return v;
 }
 
+// Keys in the box stored at `box` (the bounding box a reduction wrote there),
+// or, with fb.fixed (periodic sets), in the given box, which the first thread
+// also stores at `box` for the kernels after this one (one launch fewer).
+struct FixedBox {
+    int fixed;
+    double lo[3], hi[3];
+};
+
 __global__ __launch_bounds__(256) void k_keys(int64_t n, const double *__restrict__ x,
                                               const double *__restrict__ y,
-                                              const double *__restrict__ z,
-                                              const double *__restrict__ box, int bits,
+                                              const double *__restrict__ z, double *box,
+                                              FixedBox fb, int bits,
                                               uint64_t *__restrict__ keys,
                                               uint32_t *__restrict__ vals)
 {
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
-    double ext = fmax(fmax(box[3] - box[0], box[4] - box[1]), box[5] - box[2]);
+    double b[6];
+    for (int a = 0; a < 3; a++) {
+        b[a] = fb.fixed ? fb.lo[a] : box[a];
+        b[3 + a] = fb.fixed ? fb.hi[a] : box[3 + a];
+    }
+    if (fb.fixed && k == 0)
+        for (int a = 0; a < 6; a++) box[a] = b[a];
+    double ext = fmax(fmax(b[3] - b[0], b[4] - b[1]), b[5] - b[2]);
     double cells = (double)(1u << bits);
     double scale = ext > 0.0 ? cells / ext : 0.0;
     double top = cells - 1.0;
-    double q[3] = {(x[k] - box[0]) * scale, (y[k] - box[1]) * scale, (z[k] - box[2]) * scale};
+    double q[3] = {(x[k] - b[0]) * scale, (y[k] - b[1]) * scale, (z[k] - b[2]) * scale};
     uint64_t key = 0;
     for (int a = 0; a < 3; a++) {
         double c = floor(q[a]);
@@ -696,9 +702,11 @@ sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y, 
 {
     if (n == 0) return SPH_OK;
     const sph_params &p = c->p;
+    FixedBox fb{};
     if (p.periodic) {
-        hipLaunchKernelGGL(k_box_fixed, dim3(1), dim3(64), 0, c->stream, c->d_box, p.box_lo[0],
-                           p.box_lo[1], p.box_lo[2], p.box_hi[0], p.box_hi[1], p.box_hi[2]);
+        // k_keys takes the box by value and stores it for the later kernels
+        fb.fixed = 1;
+        for (int a = 0; a < 3; a++) { fb.lo[a] = p.box_lo[a]; fb.hi[a] = p.box_hi[a]; }
     } else {
         int nb = (int)std::min<int64_t>(1024, ceil_div(n, kBoxThreads));
         hipLaunchKernelGGL(k_box_partial, dim3(nb), dim3(kBoxThreads), 0, c->stream, n, x, y, z,
@@ -707,7 +715,7 @@ sph_status build_order(sph_ctx *c, int64_t n, const double *x, const double *y, 
     }
     const int bits = key_bits(n);
     hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, x, y, z,
-                       c->d_box, bits, c->keys[0], c->vals[0]);
+                       c->d_box, fb, bits, c->keys[0], c->vals[0]);
     // small sets: tiles of 1024 keys (more, shorter blocks); up to
     // kRsRawTiles tiles the scatter blocks form the digit offsets from the raw
     // counts themselves (one launch fewer per pass).  A stable sort's result
