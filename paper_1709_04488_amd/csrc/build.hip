@@ -317,12 +317,6 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t *__res
     copy_listed(g, src, k);
 }
 
-__global__ void k_copy_u32(int64_t n, const uint32_t *__restrict__ a, uint32_t *__restrict__ b)
-{
-    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k < n) b[k] = a[k];
-}
-
 __global__ void k_iota(int64_t n, uint32_t *__restrict__ v)
 {
     int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -396,9 +390,11 @@ __global__ __launch_bounds__(kScanThreads) void k_seg_tiles(int64_t n, const uin
     if (threadIdx.x == kScanThreads - 1) tmax[blockIdx.x] = r;
 }
 
-// exclusive scan over the tile values, one block (max or sum)
+// exclusive scan over the tile values, one block (max or sum); copy (when not
+// null) receives the values as they were
 template <bool MAX>
-__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ a, int64_t ntile)
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ a, int64_t ntile,
+                                                     uint32_t *__restrict__ copy)
 {
     __shared__ uint32_t sums[1024];
     const int t = threadIdx.x;
@@ -417,6 +413,7 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t *__restrict__ a, i
     uint32_t run = t > 0 ? sums[t - 1] : 0u;
     for (int64_t k = s0; k < s1; k++) {
         uint32_t v = a[k];
+        if (copy) copy[k] = v;
         a[k] = run;
         run = MAX ? (v > run ? v : run) : run + v;
     }
@@ -794,13 +791,14 @@ sph_status build_tree(sph_ctx *c, int64_t n)
     uint32_t *flag = c->scratch_u32;
     hipLaunchKernelGGL(k_seg_tiles, dim3((unsigned)ntile), dim3(kScanThreads), 0, c->stream, n,
                        c->skeys, c->s.h, c->d_box, key_bits(n), flag, tmax);
-    hipLaunchKernelGGL((k_scan_tiles<true>), dim3(1), dim3(1024), 0, c->stream, tmax, ntile);
+    hipLaunchKernelGGL((k_scan_tiles<true>), dim3(1), dim3(1024), 0, c->stream, tmax, ntile,
+                       (uint32_t *)nullptr);
     hipLaunchKernelGGL(k_seg_apply, dim3((unsigned)ntile), dim3(kScanThreads), 0, c->stream, n, G,
                        flag, tmax, tcnt);
-    // tcnt -> exclusive offsets in place; keep the counts for the total in tmax
-    hipLaunchKernelGGL(k_copy_u32, dim3((unsigned)ceil_div(ntile, 256)), dim3(256), 0, c->stream,
-                       ntile, tcnt, tmax);
-    hipLaunchKernelGGL((k_scan_tiles<false>), dim3(1), dim3(1024), 0, c->stream, tcnt, ntile);
+    // tcnt -> exclusive offsets in place; the counts themselves go to tmax
+    // for the total
+    hipLaunchKernelGGL((k_scan_tiles<false>), dim3(1), dim3(1024), 0, c->stream, tcnt, ntile,
+                       tmax);
     hipLaunchKernelGGL(k_tree_info, dim3(1), dim3(64), 0, c->stream, n, G, tcnt, tmax, ntile,
                        c->d_tree);
     hipLaunchKernelGGL(k_leaf_ids, dim3((unsigned)ntile), dim3(kScanThreads), 0, c->stream, n,
